@@ -1,0 +1,153 @@
+/*
+ * Reference CPU oracle for ragged-row spiking networks with e-prop, DEEP R and
+ * topographic-map rewiring (Knight, Senk, Nowotny et al., "A flexible framework
+ * for structural plasticity in GPU-accelerated sparse spiking neural networks").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is a deliberately plain, slow,
+ * single-threaded fp64 re-statement of the paper's method.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or helper with the HIP library, and never
+ * includes anything from it.
+ *
+ * Conventions
+ *   - Floating point state is double.  Weights handed in from a float32 device
+ *     snapshot are widened exactly; decisions that the method takes on weights
+ *     (sign mismatch, w < g_theta) are taken in float32, the precision the
+ *     weights are stored in.
+ *   - Ragged rows (paper, Sec. 2.1 and Fig. 1): len[n_pre], and for slot k of
+ *     row i the flat index i*cap + k into ind / w / m / v / G.  Per-batch
+ *     synapse traces are stored per slot: eps[(i*cap + k)*B + b].
+ *   - Bitfields (paper, Sec. 2.1.2, Fig. 2 and Sec. 2.1.3, Fig. 3): one section
+ *     of ceil(n_post/32) 32-bit words per presynaptic row; bit j%32 of word
+ *     j/32 stands for target j.
+ *   - Random draws: Philox4x64-10 (Salmon et al., SC'11), key = (seed,
+ *     tag | proj<<8), counter = (c0, c1, c2, c3).  A 32-bit draw is the top
+ *     half of output word 0; an integer below n is (u32*n)>>32; a Bernoulli
+ *     trial with probability p succeeds when u32 < floor(p*2^32) (computed in
+ *     double; p >= 1 always succeeds).
+ */
+#ifndef RAGSNN_ORACLE_H
+#define RAGSNN_ORACLE_H
+#include <stdint.h>
+
+/* Random stream tags (key word 1 = tag | proj << 8). */
+enum {
+    ORC_TAG_CONN = 1,    /* connectivity Bernoulli trial, counter (0, i, j, 0) */
+    ORC_TAG_WINIT = 2,   /* initial weight normal draw,   counter (0, i, j, 0) */
+    ORC_TAG_SIGN = 3,    /* DEEP R sign bit,              counter (0, i, j, 0) */
+    ORC_TAG_DR_ROW = 4,  /* DEEP R activation -> row,     counter (step, a, round, 0) */
+    ORC_TAG_DR_TGT = 5,  /* DEEP R new target,            counter (step, r, k, try) */
+    ORC_TAG_TP_ROW = 6,  /* topomap attempt -> row,       counter (step, a, 0, 0) */
+    ORC_TAG_TP_TGT = 7,  /* topomap candidate target,     counter (step, r, q, try) */
+    ORC_TAG_TP_ELIM = 8, /* topomap elimination draw,     counter (step, r, s, 0) */
+    ORC_TAG_TP_FORM = 9  /* topomap formation draw,       counter (step, r, j, 0) */
+};
+
+/* Draws per (row, activation) before the bounded fallback scan takes over. */
+#define ORC_MAX_TRIES 64
+/* Distribution rounds before the deterministic fallback assignment. */
+#define ORC_MAX_ROUNDS 64
+
+/* ---- counter-based generator --------------------------------------------- */
+void orc_philox4x64_10(uint64_t key0, uint64_t key1, const uint64_t ctr[4], uint64_t out[4]);
+uint32_t orc_u32(uint64_t seed, uint32_t tag, uint32_t proj, uint64_t c0, uint64_t c1,
+                 uint64_t c2, uint64_t c3);
+uint32_t orc_below(uint32_t u, uint32_t n);
+uint64_t orc_threshold(double p);
+double orc_normal(uint64_t seed, uint32_t tag, uint32_t proj, uint64_t c0, uint64_t c1,
+                  uint64_t c2, uint64_t c3);
+
+/* ---- one ragged projection ----------------------------------------------- */
+typedef struct orc_proj {
+    int32_t n_pre, n_post, cap;
+    int32_t recurrent; /* 1: targets may not equal the row index (no autapses) */
+    int32_t proj_id;   /* random stream id */
+    int32_t *len;      /* [n_pre] */
+    int32_t *ind;      /* [n_pre*cap] */
+    double *w, *m, *v, *G; /* [n_pre*cap]; m, v, G may be NULL when not trained */
+    double *eps, *ebar;    /* [n_pre*cap*B]; eps NULL for LIF, both NULL untrained */
+    uint32_t *conn, *sign; /* [n_pre*words] or NULL */
+    int32_t words;         /* ceil(n_post/32) */
+} orc_proj;
+
+/* ---- e-prop classifier (input -> LIF/ALIF recurrent -> leaky readout) ---- */
+typedef struct orc_net {
+    int32_t n_in, n_rec, n_out, batch;
+    int32_t alif;           /* 0: LIF (beta = rho = 0) */
+    double alpha, rho, v_thr, beta;
+    orc_proj *in, *rec;
+    double *v, *a;          /* [B][n_rec] */
+    double *y;              /* [B][n_out] */
+    double *xbar;           /* [B][n_in]   input spike trace  */
+    double *zbar;           /* [B][n_rec]  recurrent spike trace */
+    double *Wout, *bout;    /* [n_out][n_rec], [n_out] */
+    double *Gout, *Gb;      /* [n_out][n_rec], [n_out] accumulated over b and t */
+    double *Mout, *Vout, *Mb, *Vb; /* Adam moments of the readout */
+    /* per-step outputs, overwritten by every step */
+    double *psi, *L;        /* [B][n_rec] */
+    uint8_t *z;             /* [B][n_rec] spikes emitted this step */
+    double *delta;          /* [B][n_out] pi - onehot(label) */
+} orc_net;
+
+/* Build: fixed-probability rows (paper, classifier model section).  Row i
+ * connects to j (ascending) when the CONN draw passes p; j == i is skipped for
+ * recurrent projections.  With ind == NULL only len[] is filled.  Weights are
+ * sigma * N(0,1).  Returns the largest row length. */
+int32_t orc_fixed_prob_rows(uint64_t seed, orc_proj *P, double p, double sigma);
+/* Build: pairwise-Bernoulli rows with Gaussian distance-dependent probability
+ * on an L x L torus (paper, topographic-map model, Tab. B / Tab. G). */
+int32_t orc_gauss_rows(uint64_t seed, orc_proj *P, int32_t L, double p_form, double sigma,
+                       double g_init);
+/* Dense readout init, W[k][j] = sigma * N(0,1). */
+void orc_dense_init(uint64_t seed, int32_t proj_id, int32_t rows, int32_t cols, double sigma,
+                    double *W);
+/* DEEP R bitfield init (paper, Sec. 2.1.2, Fig. 2A). */
+void orc_deepr_init_bits(uint64_t seed, orc_proj *P);
+
+/* One timestep of the e-prop network for every batch instance.  x_off has B+1
+ * entries delimiting each instance's input spike list in x_idx.  When z_force
+ * is not NULL it replaces the spikes the oracle would emit ([B][n_rec]).
+ * learn = 0 skips eligibility and gradients. */
+void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
+                    const int32_t *labels, const uint8_t *z_force, int32_t learn);
+/* Spikes the network would emit from its current state, without stepping. */
+void orc_eprop_spikes(const orc_net *N, uint8_t *z_out, double *margin_out);
+/* Reset neuron, readout and trace state at a sample boundary. */
+void orc_eprop_reset(orc_net *N);
+
+/* Parameter update: gradient averaged over the batch, L1 term for DEEP R
+ * projections, then Adam (Kingma & Ba) with update counter k >= 1. */
+void orc_adam_update(orc_net *N, int32_t k, double lr, double b1, double b2, double eps,
+                     double l1, int32_t deepr_mask);
+
+/* DEEP R rewiring of one projection (paper, Sec. 2.1.2): elimination of
+ * sign-mismatched synapses, then formation of the same number elsewhere.
+ * stats[0] = eliminated, stats[1] = formed. */
+void orc_deepr_rewire(uint64_t seed, orc_proj *P, int32_t batch, uint64_t step,
+                      int32_t *dormant, int32_t *stats);
+
+/* Topographic-map rewiring (paper, Sec. 2.1.3, Fig. 3, Tab. B and G). */
+typedef struct orc_topo_params {
+    int32_t L;             /* sheet side; pre and post sheets are L x L */
+    int32_t n_attempts;
+    double p_form, sigma_form, g_theta, p_elim_dep, p_elim_pot, g_new;
+} orc_topo_params;
+/* Draw source; the default uses Philox, tests may script the outcomes. */
+typedef struct orc_topo_draws {
+    uint32_t (*attempt_row)(void *ctx, int32_t a);
+    uint32_t (*target)(void *ctx, int32_t r, int32_t q, int32_t try_);
+    uint32_t (*elim_u32)(void *ctx, int32_t r, int32_t s);
+    uint32_t (*form_u32)(void *ctx, int32_t r, int32_t j);
+    void *ctx;
+} orc_topo_draws;
+/* stats[0] = eliminated, [1] = formed, [2] = blocked (row full), [3] = attempts.
+ * bits is the attempt bitfield ([n_pre*words]) and must be all zero on entry;
+ * it is all zero again on return. */
+void orc_topo_rewire_with(orc_proj *P, const orc_topo_params *tp, const orc_topo_draws *d,
+                          uint32_t *bits, int32_t *stats);
+void orc_topo_rewire(uint64_t seed, orc_proj *P, const orc_topo_params *tp, uint64_t step,
+                     uint32_t *bits, int32_t *stats);
+/* Squared torus distance between node i of one sheet and node j of the other. */
+int32_t orc_torus_d2(int32_t L, int32_t i, int32_t j);
+
+#endif
