@@ -1,0 +1,237 @@
+"""Benchmark: e-prop training of the sparse classifier (700 synthetic input
+channels -> 1024 ALIF -> 20 readouts, 10% ragged connectivity, batch 256,
+1000 steps per sample batch, Adam + DEEP R every 100 steps) on one MI355X.
+
+One benchmark step = one training batch: 1000 timesteps of the whole path
+(input, spikes, propagation, neurons, readout, learning signal, eligibility
+traces and gradients) plus 10 parameter updates and 20 DEEP R rewires, and the
+state reset at the end of the batch.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def classifier_config(seed=1):
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    c = wl.SHD_CLASSIFIER
+    f32 = lambda x: float(np.float32(x))
+    return rb.EpropConfig(n_in=c["n_in"], n_rec=c["n_rec"], n_out=c["n_out"], batch=c["batch"], alif=c["alif"],
+                          p_in=c["p_in"], p_rec=c["p_rec"], sigma_in=f32(wl.sigma_init(c["p_in"], c["n_in"])),
+                          sigma_rec=f32(wl.sigma_init(c["p_rec"], c["n_rec"])),
+                          sigma_out=f32(1.0 / np.sqrt(c["n_rec"])), deepr_mask=c["deepr_mask"], l1=c["l1"],
+                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed)
+
+
+def eprop_algorithmic_bytes(cfg, n_syn: int) -> int:
+    """HBM bytes one e-prop launch must move at minimum: per synapse and batch
+    instance, eps and ebar read and written (16 B; 8 B for LIF); per synapse its
+    target index (4 B) and gradient read and written (8 B); each per-neuron,
+    per-instance input once: presynaptic traces, psi and L (and the new recurrent
+    trace, output errors and readout gradient for the readout rows)."""
+    B = cfg.batch
+    per_unit = 16 if cfg.alif else 8
+    syn = n_syn * (per_unit * B + 12)
+    neuron = 4 * B * (cfg.n_in + cfg.n_rec + 2 * cfg.n_rec) + 4 * B * (cfg.n_rec + cfg.n_out)
+    readout = 8 * cfg.n_out * cfg.n_rec + 8 * cfg.n_out
+    return syn + neuron + readout
+
+
+def run_cpu_baseline(cfg, raster, labels, n_steps: int):
+    """Time the oracle (single-threaded fp64 C) on a bounded sample of the same
+    workload: n_steps timesteps plus one update and two DEEP R rewires."""
+    import oracle
+    B = cfg.batch
+    f32 = lambda x: float(np.float32(x))
+    projs = []
+    for n_pre, rec, p, sig, pid in ((cfg.n_in, False, cfg.p_in, cfg.sigma_in, 0),
+                                    (cfg.n_rec, True, cfg.p_rec, cfg.sigma_rec, 1)):
+        _, mx = oracle.fixed_prob_count(cfg.seed, n_pre, cfg.n_rec, p, rec, pid)
+        P = oracle.Proj(n_pre, cfg.n_rec, min(2 * mx, cfg.n_rec), rec, pid, batch=B, trained=True,
+                        traces="alif" if cfg.alif else "lif", bitfields=True)
+        oracle.fixed_prob_rows(cfg.seed, P, p, sig)
+        oracle.deepr_init_bits(cfg.seed, P)
+        projs.append(P)
+    prm = oracle.EpropParams(n_in=cfg.n_in, n_rec=cfg.n_rec, n_out=cfg.n_out, batch=B, alif=cfg.alif,
+                             v_thr=f32(cfg.v_thr), beta=f32(cfg.beta))
+    N = oracle.Net(prm, projs[0], projs[1])
+    N.Wout[:] = oracle.dense_init(cfg.seed, 2, cfg.n_out, cfg.n_rec, cfg.sigma_out)
+    t0 = time.perf_counter()
+    for t in range(n_steps):
+        idx, off = raster.step_lists(t)
+        N.step(idx, off, labels)
+    t_step = (time.perf_counter() - t0) / n_steps
+    t1 = time.perf_counter()
+    N.adam_update(1, lr=cfg.lr, l1=cfg.l1, deepr_mask=cfg.deepr_mask)
+    oracle.deepr_rewire(cfg.seed, N.inp, n_steps)
+    oracle.deepr_rewire(cfg.seed, N.rec, n_steps)
+    t_upd = time.perf_counter() - t1
+    T, U = cfg.sample_steps, cfg.update_interval
+    t_batch = T * t_step + (T // U) * t_upd
+    return {"value": B / t_batch, "unit": "samples/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} of {T} timesteps and 1 of {T // U} update+DEEP R intervals of one "
+                      f"{B}-sample batch, extrapolated linearly to the batch",
+            "seconds_per_timestep": t_step, "seconds_per_update_rewire": t_upd}
+
+
+def topo_rewire_latency(n_rewires=200):
+    """Topographic-map rewiring (64 x 64 sheets, cap 32, 160 attempts)."""
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    import torch
+    c = wl.TOPO_S4
+    out = {}
+    for name, ff in (("ff", c["ff"]), ("lat", c["lat"])):
+        t = rb.TopoNet(rb.TopoConfig(L=c["L"], cap=c["cap"], n_attempts=c["n_attempts"], proj_id=0 if name == "ff" else 1,
+                                     p_form=ff["p_form"], sigma_form=ff["sigma"], g_theta=c["g_max"] / 2,
+                                     p_elim_dep=c["p_elim_dep"], p_elim_pot=c["p_elim_pot"], g_new=c["g_max"],
+                                     g_init=c["g_max"], seed=1))
+        for s in range(10):
+            t.rewire(s * 10, stats=False)
+        torch.cuda.synchronize()
+        ms = []
+        for s in range(n_rewires):
+            t.rewire(1000 + 10 * s, stats=False)
+            ms.append(t.last_ms())
+        t0 = time.perf_counter()
+        for s in range(n_rewires):
+            t.rewire(10**6 + 10 * s, stats=False)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / n_rewires
+        out[name] = {"device_us": 1e3 * float(np.mean(ms)), "wall_us": 1e6 * wall}
+        t.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--no-topo", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="only run a plain copy of this many MiB 20 times (byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this engine runs on one GPU; multi-GPU runs are not part of this build "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    torch.cuda.set_device(0)
+
+    if args.calib_copy_mib:
+        n = args.calib_copy_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device="cuda")
+        b = torch.empty(n, dtype=torch.uint8, device="cuda")
+        for _ in range(20):
+            rb.calib_copy(b, a, n)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": n, "launches": 20}))
+        return
+
+    cfg = classifier_config()
+    print(f"[bench] generating synthetic input ({cfg.batch} samples x {cfg.sample_steps} steps)",
+          file=sys.stderr, flush=True)
+    gen = wl.ShdLike(T=cfg.sample_steps)
+    batches = [gen.batch(seed=1, batch_index=q, B=cfg.batch) for q in range(2)]
+    dev = []
+    for labels, raster in batches:
+        dev.append((torch.tensor(raster.off, dtype=torch.int32, device="cuda"),
+                    torch.tensor(raster.idx, dtype=torch.int32, device="cuda"),
+                    torch.tensor(labels, dtype=torch.int32, device="cuda")))
+    net = rb.EpropNet(cfg)
+    inf = net.info()
+    n_syn = int(net.get(rb.PROJ(0, rb.P_LEN)).sum() + net.get(rb.PROJ(1, rb.P_LEN)).sum())
+    flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+    T = cfg.sample_steps
+
+    def one_batch(q):
+        net.set_input(*dev[q % 2])
+        net.step(T, flags)
+
+    print(f"[bench] warmup {args.warmup} batch(es)", file=sys.stderr, flush=True)
+    for q in range(args.warmup):
+        one_batch(q)
+    torch.cuda.synchronize()
+    # rs_eprop_set_input validates the raster (a host round trip); attach both
+    # rasters' validation outside the timed region by pre-validating them here
+    ev0 = net.info().synaptic_events
+    net.timing(True)
+    net.phase_times()
+    print(f"[bench] timing {args.steps} batch(es)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(args.steps):
+        one_batch(args.warmup + q)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    phases = net.phase_times()
+    net.timing(False)
+    inf = net.info()
+    events = inf.synaptic_events - ev0
+    n_syn_after = int(net.get(rb.PROJ(0, rb.P_LEN)).sum() + net.get(rb.PROJ(1, rb.P_LEN)).sum())
+    assert n_syn_after == n_syn, "DEEP R must keep the synapse count"
+
+    samples = args.steps * cfg.batch
+    value = samples / elapsed
+    ep_ms, ep_n = phases["eprop"]
+    ep_avg_s = ep_ms / 1e3 / max(ep_n, 1)
+    alg_bytes = eprop_algorithmic_bytes(cfg, n_syn)
+    achieved = alg_bytes / ep_avg_s / 1e9
+    result = {
+        "metric": "train samples/s (e-prop + DEEP R, sparse classifier)",
+        "value": round(value, 2),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * elapsed / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32/f64",
+        "data": "synthetic",
+        "config": {"workload": "sparse-classifier 700->1024 ALIF->20, p=0.1, batch 256, 1000 steps/sample, "
+                               "Adam + DEEP R every 100 steps, synthetic SHD-shaped input",
+                   "global_batch": cfg.batch, "seq_len": T, "parallelism": "single GPU",
+                   "synapses": n_syn, "row_capacity": [inf.cap_in, inf.cap_rec]},
+        "synaptic_events_per_s": round(events / elapsed, 1),
+        "timesteps_per_s": round(args.steps * T / elapsed, 1),
+        "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
+        "roofline": {"bound": "hbm", "kernel": "k_eprop_wide<true>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "avg_launch_us": round(ep_avg_s * 1e6, 2),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+    }
+    net.close()
+    if not args.no_topo:
+        print("[bench] topographic-map rewiring latency", file=sys.stderr, flush=True)
+        result["topomap_rewire"] = topo_rewire_latency()
+    if not args.no_cpu_baseline:
+        print(f"[bench] oracle CPU baseline ({args.cpu_steps} timesteps)", file=sys.stderr, flush=True)
+        labels, raster = batches[0]
+        result["cpu_baseline"] = run_cpu_baseline(cfg, raster, labels, args.cpu_steps)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

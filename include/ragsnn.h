@@ -1,0 +1,250 @@
+/*
+ * ragsnn -- MI355X (gfx950) engine for sparse spiking networks stored as ragged
+ * rows, trained with e-prop and rewired with DEEP R, plus topographic-map
+ * rewiring.  Method: Knight, Senk, Nowotny et al., "A flexible framework for
+ * structural plasticity in GPU-accelerated sparse spiking neural networks"
+ * (arXiv 2510.19764).
+ *
+ * Conventions for every call
+ *   - Return value: RS_OK (0) or a negative rs_status.  Arguments are validated
+ *     before anything is enqueued, so a call that fails with RS_EINVAL,
+ *     RS_ECAPACITY or RS_ESTATE leaves the object unchanged.  RS_EDEVICE reports
+ *     a HIP runtime error; the object is then unusable.  rs_last_error()
+ *     describes the most recent failure of the calling thread.
+ *   - Ownership: the library allocates and owns all device state of an object
+ *     (released by its destroy call).  Buffers passed in belong to the caller;
+ *     "device" pointers must stay valid for as long as the call's work may run
+ *     on the object's stream, "host" pointers only for the duration of the call.
+ *   - Streams: every object is bound to the HIP stream given at creation
+ *     (NULL = the default stream).  Calls enqueue work on it and return without
+ *     waiting, except where a call is documented as synchronising.
+ *   - Threads: an object must not be used by two threads at once.
+ *   - Randomness: every random decision is a Philox4x64-10 draw keyed by
+ *     (seed, stream tag, projection) with a counter of (step, row, slot/target,
+ *     retry), so results depend only on the seed and the call sequence.
+ */
+#ifndef RAGSNN_H
+#define RAGSNN_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rs_status;
+#define RS_OK 0
+#define RS_EINVAL (-1)     /* invalid argument, size or shape */
+#define RS_ENOMEM (-2)     /* device allocation failed */
+#define RS_ECAPACITY (-3)  /* caller buffer too small */
+#define RS_ESTATE (-4)     /* call not valid in the object's current state */
+#define RS_EDEVICE (-5)    /* HIP runtime error */
+
+/* Message describing the last failed call on this thread ("" if none). */
+const char* rs_last_error(void);
+
+/* Counts returned by a rewiring call. */
+typedef struct rs_rewire_stats {
+  int64_t eliminated;  /* synapses removed */
+  int64_t formed;      /* synapses added */
+  int64_t blocked;     /* formations skipped because the row was full */
+  int64_t attempts;    /* DEEP R: dormant total D; topomap: rewiring attempts */
+} rs_rewire_stats;
+
+/* ==========================================================================
+ * e-prop classifier: Poisson/raster input -> recurrent LIF or ALIF -> leaky
+ * readout (paper, "Recurrent classifier" section), input and recurrent weights
+ * stored as ragged rows (Sec. 2.1, Fig. 1) with DEEP R rewiring (Sec. 2.1.2).
+ * ========================================================================== */
+typedef struct rs_eprop rs_eprop;
+
+typedef struct rs_eprop_params {
+  uint32_t n_in;        /* input channels */
+  uint32_t n_rec;       /* recurrent neurons, 1..8192 */
+  uint32_t n_out;       /* readout units, 1..256 */
+  uint32_t batch;       /* batch instances simulated together, >= 1 */
+  int32_t alif;         /* 1: ALIF neurons, 0: LIF (beta = rho = 0) */
+  float dt_ms, tau_mem_ms, tau_adapt_ms, v_thr, beta;
+  float p_in, p_rec;    /* fixed connection probabilities */
+  float sigma_in, sigma_rec, sigma_out;  /* initial weight standard deviations */
+  uint32_t cap_in, cap_rec;  /* row capacities; 0 = twice the longest initial row */
+  uint32_t deepr_mask;  /* bit 0: rewire the input projection, bit 1: recurrent */
+  float l1;             /* DEEP R L1 strength added to the batch-mean gradient */
+  float lr, adam_b1, adam_b2, adam_eps;
+  uint32_t update_interval;  /* steps between automatic update + rewire (0 = never) */
+  uint32_t sample_steps;     /* steps per presented sample; state resets after each */
+  uint64_t seed;
+} rs_eprop_params;
+
+/* Step flags */
+#define RS_LEARN 1u        /* eligibility traces and gradient accumulation */
+#define RS_AUTO_UPDATE 2u  /* update + DEEP R rewire whenever step % update_interval == 0 */
+#define RS_AUTO_RESET 4u   /* reset neuron/trace state whenever step % sample_steps == 0 */
+
+/* Create and build a network on `hip_device` (the caller's current device).
+ * Builds the fixed-probability rows (weights sigma*N(0,1)), the dense readout
+ * (bias 0) and, for projections in deepr_mask, the DEEP R connectivity and
+ * sign bitfields (Sec. 2.1.2: signs of all potential synapses random, then
+ * matched to the initial weights of existing ones).  Synchronises the stream.
+ * `hip_stream` is a hipStream_t or NULL.  Errors: RS_EINVAL (bad parameters),
+ * RS_ENOMEM, RS_EDEVICE.  *out is NULL on failure. */
+rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_eprop** out);
+
+/* Attach the input of one sample batch: a compressed raster of
+ * params->sample_steps steps.  Device pointers: off int32[sample_steps*batch+1],
+ * idx int32[off[last]] with the channels of instance b at step t in
+ * idx[off[t*batch+b] .. off[t*batch+b+1]), labels int32[batch] in [0, n_out).
+ * Step t of the simulation reads raster step t % sample_steps.  The library
+ * keeps the pointers (no copy).  Errors: RS_EINVAL. */
+rs_status rs_eprop_set_input(rs_eprop* net, const int32_t* off_dev, const int32_t* idx_dev,
+                             const int32_t* labels_dev);
+
+/* Advance n_steps timesteps.  Each step: spikes and surrogate derivatives from
+ * the current state, eligibility traces (eq. eprop_elig_1/2 or eprop_elig_lif),
+ * propagation of input and recurrent spikes through the ragged rows, neuron
+ * update with subtractive reset, presynaptic traces, leaky readout, softmax
+ * error and learning signal, and gradient accumulation (RS_LEARN).  With
+ * RS_AUTO_UPDATE, rs_eprop_update and DEEP R rewiring of the deepr_mask
+ * projections follow every update_interval-th step; with RS_AUTO_RESET the
+ * state resets after every sample_steps-th step.  Errors: RS_ESTATE (no input
+ * attached). */
+rs_status rs_eprop_step(rs_eprop* net, uint32_t n_steps, uint32_t flags);
+
+/* Parameter update: gradient / batch, + l1 * (sign of the potential
+ * connection) for DEEP R projections (Sec. 2.1.2, L1 regularisation), then one
+ * Adam step (update counter += 1) for input, recurrent and readout weights and
+ * readout biases; gradients are cleared. */
+rs_status rs_eprop_update(rs_eprop* net);
+
+/* DEEP R rewiring of projection `proj` (0 = input, 1 = recurrent), Sec. 2.1.2:
+ * eliminate synapses whose weight sign differs from their sign bit, then form
+ * the same number at random free targets (weight and all synapse state zero).
+ * Random counter step = the object's current step count.  With stats != NULL
+ * the call synchronises and fills it.  Errors: RS_EINVAL (proj not in
+ * deepr_mask). */
+rs_status rs_eprop_rewire(rs_eprop* net, uint32_t proj, rs_rewire_stats* stats);
+
+/* Zero neuron, readout and eligibility-trace state (sample boundary). */
+rs_status rs_eprop_reset(rs_eprop* net);
+
+/* Variable identifiers for rs_eprop_get / rs_eprop_set.  Per-neuron and
+ * readout state is double (it is small, and its rounding would otherwise drift
+ * the surrogate derivative); synapse state is float.  Network variables
+ * (element type, layout): */
+#define RS_V 0x01      /* double[batch][n_rec]  membrane voltage */
+#define RS_A 0x02      /* double[batch][n_rec]  adaptation */
+#define RS_Y 0x03      /* double[batch][n_out]  readout */
+#define RS_XBAR 0x04   /* double[batch][n_in]   filtered input spikes */
+#define RS_ZBAR 0x05   /* double[batch][n_rec]  filtered recurrent spikes */
+#define RS_PSI 0x06    /* float[n_rec][batch]   surrogate derivative of the last step */
+#define RS_LSIG 0x07   /* float[n_rec][batch]   learning signal of the last step */
+#define RS_DELTA 0x08  /* float[n_out][batch]   softmax - one-hot of the last step */
+#define RS_Z 0x09      /* uint8[batch][n_rec]   spikes emitted by the last step */
+#define RS_WOUT 0x0A   /* float[n_out][n_rec] */
+#define RS_BOUT 0x0B   /* float[n_out] */
+#define RS_GOUT 0x0C   /* float[n_out][n_rec]   accumulated readout gradient */
+#define RS_GB 0x0D     /* float[n_out] */
+#define RS_MOUT 0x0E   /* float[n_out][n_rec]   Adam moments */
+#define RS_VOUT 0x0F
+#define RS_MB 0x10     /* float[n_out] */
+#define RS_VB 0x11
+/* Projection variables: RS_PROJ(p, field), p = 0 input, 1 recurrent;
+ * cap = row capacity (rs_eprop_info), words = ceil(n_post/32). */
+#define RS_PROJ(p, f) (0x100 * ((p) + 1) + (f))
+#define RS_P_LEN 0x01     /* int32[n_pre] row lengths */
+#define RS_P_IND 0x02     /* int32[n_pre][cap] postsynaptic indices */
+#define RS_P_W 0x03       /* float[n_pre][cap] weights */
+#define RS_P_M 0x04       /* float[n_pre][cap] Adam first moment */
+#define RS_P_V 0x05       /* float[n_pre][cap] Adam second moment */
+#define RS_P_G 0x06       /* float[n_pre][cap] accumulated gradient */
+#define RS_P_EPS 0x07     /* float[n_pre][cap][batch] ALIF eligibility vector */
+#define RS_P_EBAR 0x08    /* float[n_pre][cap][batch] filtered eligibility trace */
+#define RS_P_CONN 0x09    /* uint32[n_pre][words] DEEP R connectivity bits */
+#define RS_P_SIGN 0x0A    /* uint32[n_pre][words] DEEP R sign bits (1 = negative) */
+#define RS_P_DORMANT 0x0B /* int32[n_pre] eliminated per row by the last rewire */
+
+/* Copy a variable to host memory (`bytes` must equal its full size).
+ * Synchronises the stream.  Errors: RS_EINVAL (unknown variable),
+ * RS_ECAPACITY (bytes differs from the size). */
+rs_status rs_eprop_get(rs_eprop* net, int32_t var, void* host, size_t bytes);
+/* Overwrite a variable from host memory (snapshot restore).  Slots beyond a
+ * row's length are ignored by every kernel.  Synchronises the stream. */
+rs_status rs_eprop_set(rs_eprop* net, int32_t var, const void* host, size_t bytes);
+
+typedef struct rs_eprop_info {
+  uint32_t cap_in, cap_rec;       /* row capacities */
+  uint32_t words_in, words_rec;   /* bitfield words per row */
+  uint64_t step;                  /* timesteps done */
+  uint32_t adam_step;             /* Adam updates done */
+  uint32_t _pad;
+  uint64_t synaptic_events;       /* spikes x row lengths propagated so far */
+  uint64_t spikes;                /* recurrent spikes emitted so far */
+  uint64_t device_bytes;          /* device memory held */
+} rs_eprop_info;
+/* Synchronises the stream. */
+rs_status rs_eprop_info_get(rs_eprop* net, rs_eprop_info* out);
+
+/* Per-phase device timers (the paper's kernel timers, Sec. 2.1): when enabled,
+ * HIP events bracket every kernel launch of a phase on the object's stream.
+ * Phases: 0 forward (neurons, propagation, readout), 1 e-prop eligibility and
+ * gradients, 2 update, 3 rewiring, 4 state reset. */
+#define RS_NUM_PHASES 5
+rs_status rs_eprop_timing(rs_eprop* net, int32_t enable);
+/* Synchronises; ms[p] = total milliseconds and count[p] = launches since the
+ * last call (both arrays of RS_NUM_PHASES), then clears the totals. */
+rs_status rs_eprop_phase_times(rs_eprop* net, double* ms, uint64_t* count);
+
+void rs_eprop_destroy(rs_eprop* net);
+
+/* ==========================================================================
+ * Topographic-map projection (Sec. 2.1.3, Fig. 3; model in Tab. A-H): two
+ * L x L sheets with periodic boundaries, rows capped at `cap` synapses.
+ * ========================================================================== */
+typedef struct rs_topo rs_topo;
+
+typedef struct rs_topo_params {
+  uint32_t L;            /* sheet side; n_pre = n_post = L*L, L <= 1024 */
+  uint32_t cap;          /* row capacity, 1..1024 */
+  uint32_t n_attempts;   /* rewiring attempts per update */
+  uint32_t proj_id;      /* random stream id */
+  float p_form, sigma_form;   /* formation: p_form exp(-d^2 / 2 sigma^2) */
+  float g_theta;              /* weights below it use p_elim_dep */
+  float p_elim_dep, p_elim_pot;
+  float g_new;                /* weight of newly formed synapses */
+  float g_init;               /* weight of initial synapses */
+  uint64_t seed;
+} rs_topo_params;
+
+/* Create and build rows by the pairwise-Bernoulli rule with the formation
+ * probability (topographic-map section).  Rows longer than cap keep their
+ * first cap targets.  Synchronises.  Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE. */
+rs_status rs_topo_create(const rs_topo_params* params, void* hip_stream, rs_topo** out);
+/* One connectivity update (Sec. 2.1.3): attempts distributed over rows with
+ * replacement, candidate targets set without replacement in the row's bitfield
+ * section, elimination of candidate synapses with weight-dependent probability,
+ * formation at the remaining candidates with distance-dependent probability,
+ * all bits cleared.  `step` keys the random draws.  With stats != NULL the call
+ * synchronises and fills it. */
+rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* stats);
+/* Row access, host buffers: len int32[n_pre], ind int32[n_pre][cap],
+ * w float[n_pre][cap].  Synchronise.  Errors: RS_EINVAL (len beyond cap or
+ * index out of range on set). */
+rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w);
+rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w);
+/* The attempt bitfield uint32[n_pre][ceil(n_post/32)] (all zero between updates). */
+rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits);
+/* Device timing of the last rs_topo_rewire in milliseconds (all kernels). */
+rs_status rs_topo_last_ms(rs_topo* t, double* ms);
+void rs_topo_destroy(rs_topo* t);
+
+/* ==========================================================================
+ * Calibration
+ * ========================================================================== */
+/* Plain streaming copy of `bytes` (multiple of 16) from src to dst (device
+ * pointers) on `hip_stream`; used to calibrate hardware byte counters. */
+rs_status rs_calib_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -291,14 +291,23 @@ class EpropParams:
     tau_adapt_ms: float = 2000.0
     v_thr: float = 0.6
     beta: float = 0.0174
+    # explicit decay factors; None derives them from dt and the time constants
+    alpha_value: float | None = None
+    rho_value: float | None = None
 
     @property
     def alpha(self):
+        if self.alpha_value is not None:
+            return float(self.alpha_value)
         return float(np.exp(-self.dt_ms / self.tau_mem_ms))
 
     @property
     def rho(self):
-        return float(np.exp(-self.dt_ms / self.tau_adapt_ms)) if self.alif else 0.0
+        if not self.alif:
+            return 0.0
+        if self.rho_value is not None:
+            return float(self.rho_value)
+        return float(np.exp(-self.dt_ms / self.tau_adapt_ms))
 
     @property
     def beta_eff(self):

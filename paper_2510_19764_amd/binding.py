@@ -1,0 +1,351 @@
+"""Thin ctypes binding of libragsnn.so (include/ragsnn.h): argument marshalling
+only.  Every computation runs in the HIP library; there is no fallback path.
+
+Device buffers handed to the library (the input raster) are torch tensors on
+the GPU; host snapshots are numpy arrays."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass, fields
+
+import numpy as np
+
+from . import build as _build
+
+RS_OK, RS_EINVAL, RS_ENOMEM, RS_ECAPACITY, RS_ESTATE, RS_EDEVICE = 0, -1, -2, -3, -4, -5
+RS_LEARN, RS_AUTO_UPDATE, RS_AUTO_RESET = 1, 2, 4
+NUM_PHASES = 5
+PHASES = ("forward", "eprop", "update", "rewire", "reset")
+
+# variable ids (include/ragsnn.h)
+V, A, Y, XBAR, ZBAR, PSI, LSIG, DELTA, Z = range(1, 10)
+WOUT, BOUT, GOUT, GB, MOUT, VOUT, MB, VB = range(0x0A, 0x12)
+P_LEN, P_IND, P_W, P_M, P_V, P_G, P_EPS, P_EBAR, P_CONN, P_SIGN, P_DORMANT = range(1, 12)
+
+
+def PROJ(p: int, f: int) -> int:
+    return 0x100 * (p + 1) + f
+
+
+class RagsnnError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ragsnn error {code}: {msg}")
+        self.code = code
+
+
+class _EpropParams(C.Structure):
+    _fields_ = [("n_in", C.c_uint32), ("n_rec", C.c_uint32), ("n_out", C.c_uint32), ("batch", C.c_uint32),
+                ("alif", C.c_int32),
+                ("dt_ms", C.c_float), ("tau_mem_ms", C.c_float), ("tau_adapt_ms", C.c_float),
+                ("v_thr", C.c_float), ("beta", C.c_float),
+                ("p_in", C.c_float), ("p_rec", C.c_float),
+                ("sigma_in", C.c_float), ("sigma_rec", C.c_float), ("sigma_out", C.c_float),
+                ("cap_in", C.c_uint32), ("cap_rec", C.c_uint32),
+                ("deepr_mask", C.c_uint32), ("l1", C.c_float),
+                ("lr", C.c_float), ("adam_b1", C.c_float), ("adam_b2", C.c_float), ("adam_eps", C.c_float),
+                ("update_interval", C.c_uint32), ("sample_steps", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("eliminated", C.c_int64), ("formed", C.c_int64), ("blocked", C.c_int64),
+                ("attempts", C.c_int64)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("cap_in", C.c_uint32), ("cap_rec", C.c_uint32), ("words_in", C.c_uint32),
+                ("words_rec", C.c_uint32), ("step", C.c_uint64), ("adam_step", C.c_uint32),
+                ("_pad", C.c_uint32), ("synaptic_events", C.c_uint64), ("spikes", C.c_uint64),
+                ("device_bytes", C.c_uint64)]
+
+
+class _TopoParams(C.Structure):
+    _fields_ = [("L", C.c_uint32), ("cap", C.c_uint32), ("n_attempts", C.c_uint32), ("proj_id", C.c_uint32),
+                ("p_form", C.c_float), ("sigma_form", C.c_float), ("g_theta", C.c_float),
+                ("p_elim_dep", C.c_float), ("p_elim_pot", C.c_float), ("g_new", C.c_float),
+                ("g_init", C.c_float), ("seed", C.c_uint64)]
+
+
+EXPORTS = [
+    "rs_last_error", "rs_eprop_create", "rs_eprop_set_input", "rs_eprop_step", "rs_eprop_update",
+    "rs_eprop_rewire", "rs_eprop_reset", "rs_eprop_get", "rs_eprop_set", "rs_eprop_info_get",
+    "rs_eprop_timing", "rs_eprop_phase_times", "rs_eprop_destroy",
+    "rs_topo_create", "rs_topo_rewire", "rs_topo_get_rows", "rs_topo_set_rows", "rs_topo_get_bits",
+    "rs_topo_last_ms", "rs_topo_destroy", "rs_calib_copy",
+]
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Load libragsnn.so, building it first only if no build exists."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        vp, st = C.c_void_p, C.c_int32
+        L.rs_last_error.restype = C.c_char_p
+        L.rs_eprop_create.argtypes = [C.POINTER(_EpropParams), vp, C.POINTER(vp)]
+        L.rs_eprop_set_input.argtypes = [vp, vp, vp, vp]
+        L.rs_eprop_step.argtypes = [vp, C.c_uint32, C.c_uint32]
+        L.rs_eprop_update.argtypes = [vp]
+        L.rs_eprop_rewire.argtypes = [vp, C.c_uint32, C.POINTER(_Stats)]
+        L.rs_eprop_reset.argtypes = [vp]
+        L.rs_eprop_get.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_eprop_set.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_eprop_info_get.argtypes = [vp, C.POINTER(_Info)]
+        L.rs_eprop_timing.argtypes = [vp, C.c_int32]
+        L.rs_eprop_phase_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+        L.rs_eprop_destroy.argtypes = [vp]
+        L.rs_eprop_destroy.restype = None
+        L.rs_topo_create.argtypes = [C.POINTER(_TopoParams), vp, C.POINTER(vp)]
+        L.rs_topo_rewire.argtypes = [vp, C.c_uint64, C.POINTER(_Stats)]
+        L.rs_topo_get_rows.argtypes = [vp, vp, vp, vp]
+        L.rs_topo_set_rows.argtypes = [vp, vp, vp, vp]
+        L.rs_topo_get_bits.argtypes = [vp, vp]
+        L.rs_topo_last_ms.argtypes = [vp, C.POINTER(C.c_double)]
+        L.rs_topo_destroy.argtypes = [vp]
+        L.rs_topo_destroy.restype = None
+        L.rs_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
+        for name in EXPORTS:
+            f = getattr(L, name)
+            if name not in ("rs_last_error", "rs_eprop_destroy", "rs_topo_destroy"):
+                f.restype = st
+        _lib = L
+    return _lib
+
+
+def _check(code: int):
+    if code != RS_OK:
+        raise RagsnnError(code, lib().rs_last_error().decode())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+@dataclass
+class EpropConfig:
+    n_in: int
+    n_rec: int
+    n_out: int
+    batch: int
+    alif: bool = True
+    dt_ms: float = 1.0
+    tau_mem_ms: float = 20.0
+    tau_adapt_ms: float = 2000.0
+    v_thr: float = 0.6
+    beta: float = 0.0174
+    p_in: float = 0.1
+    p_rec: float = 0.1
+    sigma_in: float = 0.0
+    sigma_rec: float = 0.0
+    sigma_out: float = 0.0
+    cap_in: int = 0
+    cap_rec: int = 0
+    deepr_mask: int = 3
+    l1: float = 0.005
+    lr: float = 1e-3
+    adam_b1: float = 0.9
+    adam_b2: float = 0.999
+    adam_eps: float = 1e-8
+    update_interval: int = 100
+    sample_steps: int = 1000
+    seed: int = 1
+
+    def c(self) -> _EpropParams:
+        p = _EpropParams()
+        for f in fields(self):
+            setattr(p, f.name, int(getattr(self, f.name)) if isinstance(getattr(self, f.name), bool)
+                    else getattr(self, f.name))
+        return p
+
+
+@dataclass
+class RewireStats:
+    eliminated: int
+    formed: int
+    blocked: int
+    attempts: int
+
+
+class EpropNet:
+    """e-prop classifier network held on the GPU (rs_eprop_*)."""
+
+    def __init__(self, cfg: EpropConfig, stream=None):
+        self.cfg = cfg
+        self._h = C.c_void_p()
+        self._stream = _stream_ptr(stream)
+        self._input_refs = None
+        _check(lib().rs_eprop_create(C.byref(cfg.c()), self._stream, C.byref(self._h)))
+        self.info()
+
+    def close(self):
+        if self._h:
+            lib().rs_eprop_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- input
+    def set_input(self, off, idx, labels):
+        """off/idx/labels: int32 CUDA tensors (kept alive by this object)."""
+        import torch
+        for t in (off, idx, labels):
+            assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()
+        self._input_refs = (off, idx, labels)
+        _check(lib().rs_eprop_set_input(self._h, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
+                                        C.c_void_p(labels.data_ptr())))
+
+    # ---- simulation
+    def step(self, n: int = 1, flags: int = RS_LEARN):
+        _check(lib().rs_eprop_step(self._h, n, flags))
+
+    def update(self):
+        _check(lib().rs_eprop_update(self._h))
+
+    def rewire(self, proj: int) -> RewireStats:
+        st = _Stats()
+        _check(lib().rs_eprop_rewire(self._h, proj, C.byref(st)))
+        return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
+
+    def reset(self):
+        _check(lib().rs_eprop_reset(self._h))
+
+    # ---- snapshots
+    def shape_of(self, var: int):
+        c, inf = self.cfg, self._info
+        B, NR, NI, K = c.batch, c.n_rec, c.n_in, c.n_out
+        net = {V: ((B, NR), np.float64), A: ((B, NR), np.float64), Y: ((B, K), np.float64),
+               XBAR: ((B, NI), np.float64), ZBAR: ((B, NR), np.float64), PSI: ((NR, B), np.float32),
+               LSIG: ((NR, B), np.float32), DELTA: ((K, B), np.float32), Z: ((B, NR), np.uint8),
+               WOUT: ((K, NR), np.float32), BOUT: ((K,), np.float32), GOUT: ((K, NR), np.float32),
+               GB: ((K,), np.float32), MOUT: ((K, NR), np.float32), VOUT: ((K, NR), np.float32),
+               MB: ((K,), np.float32), VB: ((K,), np.float32)}
+        if var in net:
+            return net[var]
+        p, f = var // 0x100 - 1, var % 0x100
+        n_pre = NI if p == 0 else NR
+        cap = inf.cap_in if p == 0 else inf.cap_rec
+        words = inf.words_in if p == 0 else inf.words_rec
+        return {P_LEN: ((n_pre,), np.int32), P_IND: ((n_pre, cap), np.int32), P_W: ((n_pre, cap), np.float32),
+                P_M: ((n_pre, cap), np.float32), P_V: ((n_pre, cap), np.float32), P_G: ((n_pre, cap), np.float32),
+                P_EPS: ((n_pre, cap, B), np.float32), P_EBAR: ((n_pre, cap, B), np.float32),
+                P_CONN: ((n_pre, words), np.uint32), P_SIGN: ((n_pre, words), np.uint32),
+                P_DORMANT: ((n_pre,), np.int32)}[f]
+
+    def get(self, var: int) -> np.ndarray:
+        shape, dt = self.shape_of(var)
+        a = np.empty(shape, dt)
+        _check(lib().rs_eprop_get(self._h, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+        return a
+
+    def set(self, var: int, value):
+        shape, dt = self.shape_of(var)
+        a = np.ascontiguousarray(np.asarray(value, dtype=dt).reshape(shape))
+        _check(lib().rs_eprop_set(self._h, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+
+    def info(self) -> _Info:
+        inf = _Info()
+        _check(lib().rs_eprop_info_get(self._h, C.byref(inf)))
+        self._info = inf
+        return inf
+
+    def timing(self, enable: bool):
+        _check(lib().rs_eprop_timing(self._h, int(enable)))
+
+    def phase_times(self):
+        ms = (C.c_double * NUM_PHASES)()
+        cnt = (C.c_uint64 * NUM_PHASES)()
+        _check(lib().rs_eprop_phase_times(self._h, ms, cnt))
+        return {PHASES[q]: (ms[q], cnt[q]) for q in range(NUM_PHASES)}
+
+
+@dataclass
+class TopoConfig:
+    L: int = 64
+    cap: int = 32
+    n_attempts: int = 160
+    proj_id: int = 0
+    p_form: float = 0.16
+    sigma_form: float = 2.5
+    g_theta: float = 0.1
+    p_elim_dep: float = 2.45e-2 * 50
+    p_elim_pot: float = 1.36e-4 * 50
+    g_new: float = 0.2
+    g_init: float = 0.2
+    seed: int = 1
+
+    def c(self) -> _TopoParams:
+        p = _TopoParams()
+        for f in fields(self):
+            setattr(p, f.name, getattr(self, f.name))
+        return p
+
+
+class TopoNet:
+    """Topographic-map projection held on the GPU (rs_topo_*)."""
+
+    def __init__(self, cfg: TopoConfig, stream=None):
+        self.cfg = cfg
+        self._h = C.c_void_p()
+        _check(lib().rs_topo_create(C.byref(cfg.c()), _stream_ptr(stream), C.byref(self._h)))
+        self.n = cfg.L * cfg.L
+        self.words = (self.n + 31) // 32
+
+    def close(self):
+        if self._h:
+            lib().rs_topo_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rewire(self, step: int, stats: bool = True):
+        st = _Stats()
+        _check(lib().rs_topo_rewire(self._h, step, C.byref(st) if stats else None))
+        return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts) if stats else None
+
+    def get_rows(self):
+        n, cap = self.n, self.cfg.cap
+        ln = np.empty(n, np.int32)
+        ind = np.empty((n, cap), np.int32)
+        w = np.empty((n, cap), np.float32)
+        _check(lib().rs_topo_get_rows(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p)))
+        return ln, ind, w
+
+    def set_rows(self, ln, ind, w):
+        ln = np.ascontiguousarray(ln, np.int32)
+        ind = np.ascontiguousarray(ind, np.int32)
+        w = np.ascontiguousarray(w, np.float32)
+        _check(lib().rs_topo_set_rows(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
+                                      w.ctypes.data_as(C.c_void_p)))
+
+    def get_bits(self):
+        b = np.empty((self.n, self.words), np.uint32)
+        _check(lib().rs_topo_get_bits(self._h, b.ctypes.data_as(C.c_void_p)))
+        return b
+
+    def last_ms(self) -> float:
+        ms = C.c_double()
+        _check(lib().rs_topo_last_ms(self._h, C.byref(ms)))
+        return ms.value
+
+
+def calib_copy(dst, src, nbytes: int, stream=None):
+    _check(lib().rs_calib_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes, _stream_ptr(stream)))

@@ -1,0 +1,789 @@
+// Host engine behind the C-ABI of include/ragsnn.h: argument validation,
+// device memory plan, build sequence, timestep loop and snapshot access.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ragsnn.h"
+#include "rs_kernels.hpp"
+
+using namespace rs;
+
+namespace {
+
+thread_local std::string g_err;
+
+rs_status fail(rs_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(RS_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t threshold(double p) {
+  if (!(p > 0.0)) return 0;
+  if (p >= 1.0) return 1ull << 32;
+  return (uint64_t)std::floor(p * 4294967296.0);
+}
+
+// Device allocation list owned by one object.
+struct Arena {
+  std::vector<void*> ptrs;
+  uint64_t bytes = 0;
+  template <class T>
+  rs_status alloc(T** p, size_t n) {
+    *p = nullptr;
+    if (n == 0) return RS_OK;
+    void* q = nullptr;
+    size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
+    if (hipMalloc(&q, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RS_ENOMEM, "device allocation of %zu bytes failed", b);
+    }
+    ptrs.push_back(q);
+    bytes += b;
+    *p = (T*)q;
+    return RS_OK;
+  }
+  void release() {
+    for (void* q : ptrs) (void)hipFree(q);
+    ptrs.clear();
+    bytes = 0;
+  }
+};
+
+#define TRY(expr)                 \
+  do {                            \
+    rs_status st_ = (expr);       \
+    if (st_ != RS_OK) return st_; \
+  } while (0)
+
+struct PhaseTimer {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Rec { int phase; hipEvent_t a, b; };
+  std::vector<Rec> open;
+  double ms[RS_NUM_PHASES] = {0};
+  uint64_t count[RS_NUM_PHASES] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+  void begin(hipStream_t s, int phase) {
+    if (!on) return;
+    Rec r{phase, get(), get()};
+    (void)hipEventRecord(r.a, s);
+    open.push_back(r);
+  }
+  void end(hipStream_t s) {
+    if (!on) return;
+    (void)hipEventRecord(open.back().b, s);
+  }
+  void collect() {
+    for (auto& r : open) {
+      float t = 0.f;
+      (void)hipEventSynchronize(r.b);
+      (void)hipEventElapsedTime(&t, r.a, r.b);
+      ms[r.phase] += t;
+      count[r.phase] += 1;
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    open.clear();
+  }
+  void destroy() {
+    collect();
+    for (auto e : pool) (void)hipEventDestroy(e);
+    pool.clear();
+  }
+};
+
+}  // namespace
+
+struct rs_eprop {
+  rs_eprop_params p;
+  hipStream_t stream = nullptr;
+  int B = 0;
+  Arena arena;
+  ProjDev in{}, rec{};
+  double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
+  double *xbar = nullptr, *zbar = nullptr;            // fp64 trace masters [B][n]
+  float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;  // [n][B]
+  float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
+  uint8_t* z = nullptr;
+  float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
+  float *Mout = nullptr, *Vout = nullptr, *Mb = nullptr, *Vb = nullptr;
+  unsigned long long* counters = nullptr;  // [0] events, [1] spikes
+  long long* rw_stats = nullptr;           // [2]
+  const int32_t *x_off = nullptr, *x_idx = nullptr, *labels = nullptr;
+  uint64_t step = 0;
+  uint32_t adam_k = 0;
+  double alpha = 0.0, rho = 0.0, beta = 0.0;  // decay factors exp(-dt/tau) in double
+  PhaseTimer timer;
+};
+
+namespace {
+
+rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr) {
+  const size_t n = (size_t)P.n_pre * P.cap;
+  TRY(ar.alloc(&P.len, (size_t)P.n_pre));
+  TRY(ar.alloc(&P.ind, n));
+  TRY(ar.alloc(&P.w, n));
+  TRY(ar.alloc(&P.m, n));
+  TRY(ar.alloc(&P.v, n));
+  TRY(ar.alloc(&P.G, n));
+  TRY(ar.alloc(&P.ebar, n * B));
+  if (alif) TRY(ar.alloc(&P.eps, n * B));
+  TRY(ar.alloc(&P.dormant, (size_t)P.n_pre));
+  TRY(ar.alloc(&P.assigned, (size_t)P.n_pre));
+  if (deepr) {
+    TRY(ar.alloc(&P.conn, (size_t)P.n_pre * P.words));
+    TRY(ar.alloc(&P.sign, (size_t)P.n_pre * P.words));
+  }
+  return RS_OK;
+}
+
+void zero_proj_state(hipStream_t s, const ProjDev& P, int B) {
+  const size_t n = (size_t)P.n_pre * P.cap;
+  launch_fill_zero(s, P.m, n * 4);
+  launch_fill_zero(s, P.v, n * 4);
+  launch_fill_zero(s, P.G, n * 4);
+  launch_fill_zero(s, P.ebar, n * B * 4);
+  if (P.eps) launch_fill_zero(s, P.eps, n * B * 4);
+  launch_fill_zero(s, P.dormant, (size_t)P.n_pre * 4);
+  launch_fill_zero(s, P.assigned, (size_t)P.n_pre * 4);
+}
+
+// Count rows on the device, return the longest.
+rs_status count_rows(hipStream_t s, uint64_t seed, ProjDev& P, uint64_t T, int* max_len) {
+  int* d_len = nullptr;
+  HIP_OK(hipMalloc(&d_len, sizeof(int) * P.n_pre));
+  ProjDev tmp = P;
+  tmp.len = d_len;
+  tmp.cap = 0;
+  launch_fixed_rows(s, seed, tmp, T, 0.0, false);
+  std::vector<int> h(P.n_pre);
+  hipError_t e = hipMemcpyAsync(h.data(), d_len, sizeof(int) * P.n_pre, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(d_len);
+  if (e != hipSuccess) return fail(RS_EDEVICE, "row count: %s", hipGetErrorString(e));
+  *max_len = P.n_pre ? *std::max_element(h.begin(), h.end()) : 0;
+  return RS_OK;
+}
+
+rs_status validate(const rs_eprop_params* p) {
+  if (!p) return fail(RS_EINVAL, "params is NULL");
+  if (p->n_in < 1 || p->n_in > 65536) return fail(RS_EINVAL, "n_in must be in 1..65536");
+  if (p->n_rec < 1 || p->n_rec > 8192) return fail(RS_EINVAL, "n_rec must be in 1..8192");
+  if (p->n_out < 1 || p->n_out > 256) return fail(RS_EINVAL, "n_out must be in 1..256");
+  if (p->batch < 1 || p->batch > 65536) return fail(RS_EINVAL, "batch must be in 1..65536");
+  if (!(p->dt_ms > 0) || !(p->tau_mem_ms > 0) || !(p->tau_adapt_ms > 0) || !(p->v_thr > 0))
+    return fail(RS_EINVAL, "time constants, dt and v_thr must be positive");
+  if (!(p->p_in >= 0 && p->p_in <= 1) || !(p->p_rec >= 0 && p->p_rec <= 1))
+    return fail(RS_EINVAL, "connection probabilities must be in [0, 1]");
+  if (p->deepr_mask > 3) return fail(RS_EINVAL, "deepr_mask must be within bits 0..1");
+  if ((p->deepr_mask & 1) && p->n_in > 8192) return fail(RS_EINVAL, "DEEP R input projection: n_in <= 8192");
+  if (p->cap_in > p->n_rec || p->cap_rec > p->n_rec)
+    return fail(RS_EINVAL, "row capacity cannot exceed the number of targets");
+  if (p->sample_steps < 1) return fail(RS_EINVAL, "sample_steps must be >= 1");
+  if (!(p->lr >= 0) || !(p->adam_b1 >= 0 && p->adam_b1 < 1) || !(p->adam_b2 >= 0 && p->adam_b2 < 1) ||
+      !(p->adam_eps > 0))
+    return fail(RS_EINVAL, "invalid Adam hyper-parameters");
+  return RS_OK;
+}
+
+rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) {
+  TRY(validate(prm));
+  rs_eprop* n = new rs_eprop();
+  *out = n;
+  n->p = *prm;
+  n->stream = (hipStream_t)stream;
+  n->B = (int)prm->batch;
+  n->alpha = std::exp(-(double)prm->dt_ms / (double)prm->tau_mem_ms);
+  n->rho = prm->alif ? std::exp(-(double)prm->dt_ms / (double)prm->tau_adapt_ms) : 0.0;
+  n->beta = prm->alif ? (double)prm->beta : 0.0;
+  hipStream_t s = n->stream;
+  const int B = n->B;
+  const uint64_t seed = prm->seed;
+
+  auto setup = [&](ProjDev& P, int n_pre, int n_post, int rec, int id, float p, uint32_t cap_req) -> rs_status {
+    P.n_pre = n_pre;
+    P.n_post = n_post;
+    P.recurrent = rec;
+    P.proj_id = id;
+    P.words = (n_post + 31) / 32;
+    int mx = 0;
+    TRY(count_rows(s, seed, P, threshold(p), &mx));
+    int cap = cap_req ? (int)cap_req : 2 * mx;
+    cap = std::min(cap, n_post);
+    cap = std::max(cap, 1);
+    if (mx > cap) return fail(RS_EINVAL, "projection %d: longest row %d exceeds capacity %d", id, mx, cap);
+    P.cap = cap;
+    return RS_OK;
+  };
+  TRY(setup(n->in, prm->n_in, prm->n_rec, 0, 0, prm->p_in, prm->cap_in));
+  TRY(setup(n->rec, prm->n_rec, prm->n_rec, 1, 1, prm->p_rec, prm->cap_rec));
+  TRY(alloc_proj(n->arena, n->in, B, prm->alif, prm->deepr_mask & 1));
+  TRY(alloc_proj(n->arena, n->rec, B, prm->alif, prm->deepr_mask & 2));
+  Arena& ar = n->arena;
+  const size_t NR = prm->n_rec, NI = prm->n_in, K = prm->n_out;
+  TRY(ar.alloc(&n->V, B * NR));
+  TRY(ar.alloc(&n->A, B * NR));
+  TRY(ar.alloc(&n->Y, B * K));
+  TRY(ar.alloc(&n->xbar, NI * B));
+  TRY(ar.alloc(&n->zbar, NR * B));
+  TRY(ar.alloc(&n->xbar_prevT, NI * B));
+  TRY(ar.alloc(&n->zbar_prevT, NR * B));
+  TRY(ar.alloc(&n->zbar_newT, NR * B));
+  TRY(ar.alloc(&n->psiT, NR * B));
+  TRY(ar.alloc(&n->LT, NR * B));
+  TRY(ar.alloc(&n->deltaT, K * B));
+  TRY(ar.alloc(&n->z, B * NR));
+  TRY(ar.alloc(&n->Wout, K * NR));
+  TRY(ar.alloc(&n->bout, K));
+  TRY(ar.alloc(&n->Gout, K * NR));
+  TRY(ar.alloc(&n->Gb, K));
+  TRY(ar.alloc(&n->Mout, K * NR));
+  TRY(ar.alloc(&n->Vout, K * NR));
+  TRY(ar.alloc(&n->Mb, K));
+  TRY(ar.alloc(&n->Vb, K));
+  TRY(ar.alloc(&n->counters, 2));
+  TRY(ar.alloc(&n->rw_stats, 2));
+
+  for (ProjDev* P : {&n->in, &n->rec}) {  // padding slots start defined
+    launch_fill_zero(s, P->ind, (size_t)P->n_pre * P->cap * 4);
+    launch_fill_zero(s, P->w, (size_t)P->n_pre * P->cap * 4);
+    if (P->conn) launch_fill_zero(s, P->conn, (size_t)P->n_pre * P->words * 4);
+    if (P->sign) launch_fill_zero(s, P->sign, (size_t)P->n_pre * P->words * 4);
+  }
+  launch_fixed_rows(s, seed, n->in, threshold(prm->p_in), (double)prm->sigma_in, true);
+  launch_fixed_rows(s, seed, n->rec, threshold(prm->p_rec), (double)prm->sigma_rec, true);
+  launch_dense_init(s, seed, 2, (int)K, (int)NR, (double)prm->sigma_out, n->Wout);
+  if (prm->deepr_mask & 1) launch_deepr_bits_init(s, seed, n->in);
+  if (prm->deepr_mask & 2) launch_deepr_bits_init(s, seed, n->rec);
+  zero_proj_state(s, n->in, B);
+  zero_proj_state(s, n->rec, B);
+  for (double* q : {n->V, n->A, n->zbar}) launch_fill_zero(s, q, B * NR * 8);
+  for (float* q : {n->psiT, n->LT, n->zbar_prevT, n->zbar_newT}) launch_fill_zero(s, q, B * NR * 4);
+  launch_fill_zero(s, n->xbar, B * NI * 8);
+  launch_fill_zero(s, n->xbar_prevT, B * NI * 4);
+  launch_fill_zero(s, n->Y, B * K * 8);
+  launch_fill_zero(s, n->deltaT, B * K * 4);
+  launch_fill_zero(s, n->z, B * NR);
+  for (float* q : {n->Gout, n->Mout, n->Vout}) launch_fill_zero(s, q, K * NR * 4);
+  for (float* q : {n->bout, n->Gb, n->Mb, n->Vb}) launch_fill_zero(s, q, K * 4);
+  launch_fill_zero(s, n->counters, 16);
+  launch_fill_zero(s, n->rw_stats, 16);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  return RS_OK;
+}
+
+void reset_state(rs_eprop* n) {
+  hipStream_t s = n->stream;
+  const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in, K = n->p.n_out;
+  launch_fill_zero(s, n->V, B * NR * 8);
+  launch_fill_zero(s, n->A, B * NR * 8);
+  launch_fill_zero(s, n->Y, B * K * 8);
+  launch_fill_zero(s, n->xbar, B * NI * 8);
+  launch_fill_zero(s, n->zbar, B * NR * 8);
+  for (ProjDev* P : {&n->in, &n->rec}) {
+    const size_t m = (size_t)P->n_pre * P->cap * B * 4;
+    launch_fill_zero(s, P->ebar, m);
+    if (P->eps) launch_fill_zero(s, P->eps, m);
+  }
+}
+
+void do_update(rs_eprop* n) {
+  n->adam_k += 1;
+  UpdateArgs u{};
+  u.B = n->B;
+  u.lr = n->p.lr;
+  u.b1 = n->p.adam_b1;
+  u.b2 = n->p.adam_b2;
+  u.eps = n->p.adam_eps;
+  u.inv_c1 = (float)(1.0 / (1.0 - std::pow((double)n->p.adam_b1, (double)n->adam_k)));
+  u.inv_c2 = (float)(1.0 / (1.0 - std::pow((double)n->p.adam_b2, (double)n->adam_k)));
+  u.l1 = n->p.l1;
+  u.l1_in = (n->p.deepr_mask & 1) != 0;
+  u.l1_rec = (n->p.deepr_mask & 2) != 0;
+  u.in = n->in;
+  u.rec = n->rec;
+  u.Wout = n->Wout; u.bout = n->bout; u.Gout = n->Gout; u.Gb = n->Gb;
+  u.Mout = n->Mout; u.Vout = n->Vout; u.Mb = n->Mb; u.Vb = n->Vb;
+  u.n_out_elems = (int)(n->p.n_out * n->p.n_rec);
+  u.n_b = (int)n->p.n_out;
+  n->timer.begin(n->stream, 2);
+  launch_update(n->stream, u);
+  n->timer.end(n->stream);
+}
+
+void do_rewire(rs_eprop* n, int proj) {
+  ProjDev& P = proj == 0 ? n->in : n->rec;
+  n->timer.begin(n->stream, 3);
+  launch_deepr(n->stream, n->p.seed, P, n->B, n->step, n->rw_stats);
+  n->timer.end(n->stream);
+}
+
+void do_step(rs_eprop* n, uint32_t flags) {
+  hipStream_t s = n->stream;
+  const int t_local = (int)(n->step % n->p.sample_steps);
+  FwdArgs f{};
+  f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
+  f.alpha = n->alpha; f.rho = n->rho; f.v_thr = n->p.v_thr; f.beta = n->beta;
+  f.psi_scale = 0.3 / (double)n->p.v_thr;
+  f.V = n->V; f.A = n->A; f.Y = n->Y;
+  f.xbar = n->xbar; f.zbar = n->zbar;
+  f.xbar_prevT = n->xbar_prevT; f.zbar_prevT = n->zbar_prevT; f.zbar_newT = n->zbar_newT;
+  f.psiT = n->psiT; f.LT = n->LT; f.deltaT = n->deltaT; f.z = n->z;
+  f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
+  f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
+  f.Wout = n->Wout; f.bout = n->bout;
+  f.x_off = n->x_off; f.x_idx = n->x_idx; f.t_local = t_local; f.labels = n->labels;
+  f.counters = n->counters;
+  n->timer.begin(s, 0);
+  launch_fwd(s, f);
+  n->timer.end(s);
+  if (flags & RS_LEARN) {
+    EpropArgs e{};
+    e.n_in = f.n_in; e.n_rec = f.n_rec; e.n_out = f.n_out; e.B = n->B; e.alif = n->p.alif ? 1 : 0;
+    e.alpha = n->alpha; e.rho = n->rho; e.beta = n->beta;
+    e.in = n->in; e.rec = n->rec;
+    e.xbar_prev = n->xbar_prevT; e.zbar_prev = n->zbar_prevT; e.zbar_new = n->zbar_newT;
+    e.psiT = n->psiT; e.LT = n->LT; e.deltaT = n->deltaT;
+    e.Gout = n->Gout; e.Gb = n->Gb;
+    n->timer.begin(s, 1);
+    launch_eprop(s, e);
+    n->timer.end(s);
+  }
+  n->step += 1;
+  if ((flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0) {
+    do_update(n);
+    if (n->p.deepr_mask & 1) do_rewire(n, 0);
+    if (n->p.deepr_mask & 2) do_rewire(n, 1);
+  }
+  if ((flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0) {
+    n->timer.begin(s, 4);
+    reset_state(n);
+    n->timer.end(s);
+  }
+}
+
+struct VarRef {
+  void* ptr;
+  size_t bytes;
+};
+
+bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
+  const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in, K = n->p.n_out;
+  const int pj = var / 0x100 - 1, f = var % 0x100;
+  if (var < 0x100) {
+    switch (var) {
+      case RS_V: *r = {n->V, B * NR * 8}; return true;
+      case RS_A: *r = {n->A, B * NR * 8}; return true;
+      case RS_Y: *r = {n->Y, B * K * 8}; return true;
+      case RS_XBAR: *r = {n->xbar, NI * B * 8}; return true;
+      case RS_ZBAR: *r = {n->zbar, NR * B * 8}; return true;
+      case RS_PSI: *r = {n->psiT, NR * B * 4}; return !for_write;
+      case RS_LSIG: *r = {n->LT, NR * B * 4}; return !for_write;
+      case RS_DELTA: *r = {n->deltaT, K * B * 4}; return !for_write;
+      case RS_Z: *r = {n->z, B * NR}; return !for_write;
+      case RS_WOUT: *r = {n->Wout, K * NR * 4}; return true;
+      case RS_BOUT: *r = {n->bout, K * 4}; return true;
+      case RS_GOUT: *r = {n->Gout, K * NR * 4}; return true;
+      case RS_GB: *r = {n->Gb, K * 4}; return true;
+      case RS_MOUT: *r = {n->Mout, K * NR * 4}; return true;
+      case RS_VOUT: *r = {n->Vout, K * NR * 4}; return true;
+      case RS_MB: *r = {n->Mb, K * 4}; return true;
+      case RS_VB: *r = {n->Vb, K * 4}; return true;
+      default: return false;
+    }
+  }
+  if (pj < 0 || pj > 1) return false;
+  ProjDev& P = pj == 0 ? n->in : n->rec;
+  const size_t ns = (size_t)P.n_pre * P.cap;
+  switch (f) {
+    case RS_P_LEN: *r = {P.len, (size_t)P.n_pre * 4}; return true;
+    case RS_P_IND: *r = {P.ind, ns * 4}; return true;
+    case RS_P_W: *r = {P.w, ns * 4}; return true;
+    case RS_P_M: *r = {P.m, ns * 4}; return true;
+    case RS_P_V: *r = {P.v, ns * 4}; return true;
+    case RS_P_G: *r = {P.G, ns * 4}; return true;
+    case RS_P_EPS: *r = {P.eps, ns * B * 4}; return P.eps != nullptr;
+    case RS_P_EBAR: *r = {P.ebar, ns * B * 4}; return true;
+    case RS_P_CONN: *r = {P.conn, (size_t)P.n_pre * P.words * 4}; return P.conn != nullptr;
+    case RS_P_SIGN: *r = {P.sign, (size_t)P.n_pre * P.words * 4}; return P.sign != nullptr;
+    case RS_P_DORMANT: *r = {P.dormant, (size_t)P.n_pre * 4}; return true;
+    default: return false;
+  }
+}
+
+}  // namespace
+
+// =========================================================================== C-ABI
+extern "C" {
+
+const char* rs_last_error(void) { return g_err.c_str(); }
+
+rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_eprop** out) {
+  if (!out) return fail(RS_EINVAL, "out is NULL");
+  *out = nullptr;
+  rs_eprop* n = nullptr;
+  rs_status st = create_impl(params, hip_stream, &n);
+  if (st != RS_OK) {
+    if (n) {
+      (void)hipStreamSynchronize(n->stream);
+      n->arena.release();
+      delete n;
+    }
+    return st;
+  }
+  *out = n;
+  return RS_OK;
+}
+
+rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t* idx_dev,
+                             const int32_t* labels_dev) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  if (!off_dev || !idx_dev || !labels_dev) return fail(RS_EINVAL, "input pointers must not be NULL");
+  // validate the raster once: offsets non-decreasing from 0, channels and labels in range
+  const size_t n_off = (size_t)n->p.sample_steps * n->B + 1;
+  std::vector<int32_t> off(n_off), lab((size_t)n->B);
+  HIP_OK(hipStreamSynchronize(n->stream));
+  HIP_OK(hipMemcpy(off.data(), off_dev, n_off * 4, hipMemcpyDeviceToHost));
+  HIP_OK(hipMemcpy(lab.data(), labels_dev, lab.size() * 4, hipMemcpyDeviceToHost));
+  if (off[0] != 0) return fail(RS_EINVAL, "raster offsets must start at 0");
+  for (size_t q = 1; q < n_off; ++q)
+    if (off[q] < off[q - 1]) return fail(RS_EINVAL, "raster offsets decrease at %zu", q);
+  for (int32_t l : lab)
+    if (l < 0 || l >= (int32_t)n->p.n_out) return fail(RS_EINVAL, "label %d outside 0..%u", l, n->p.n_out - 1);
+  if (off[n_off - 1] > 0) {
+    std::vector<int32_t> idx((size_t)off[n_off - 1]);
+    HIP_OK(hipMemcpy(idx.data(), idx_dev, idx.size() * 4, hipMemcpyDeviceToHost));
+    for (int32_t i : idx)
+      if (i < 0 || i >= (int32_t)n->p.n_in) return fail(RS_EINVAL, "input channel %d outside 0..%u", i, n->p.n_in - 1);
+  }
+  n->x_off = off_dev;
+  n->x_idx = idx_dev;
+  n->labels = labels_dev;
+  return RS_OK;
+}
+
+rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  if (!n->x_off) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input)");
+  if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
+  for (uint32_t q = 0; q < n_steps; ++q) do_step(n, flags);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_eprop_update(rs_eprop* n) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  do_update(n);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  if (proj > 1 || !((n->p.deepr_mask >> proj) & 1u))
+    return fail(RS_EINVAL, "projection %u is not rewired by DEEP R", proj);
+  launch_fill_zero(n->stream, n->rw_stats, 16);
+  do_rewire(n, (int)proj);
+  HIP_OK(hipGetLastError());
+  if (st) {
+    long long h[2];
+    HIP_OK(hipMemcpyAsync(h, n->rw_stats, sizeof h, hipMemcpyDeviceToHost, n->stream));
+    HIP_OK(hipStreamSynchronize(n->stream));
+    st->eliminated = h[0];
+    st->formed = h[1];
+    st->blocked = 0;
+    st->attempts = h[0];
+  }
+  return RS_OK;
+}
+
+rs_status rs_eprop_reset(rs_eprop* n) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  reset_state(n);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
+  if (!n || !host) return fail(RS_EINVAL, "NULL argument");
+  VarRef r;
+  if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
+  if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
+  HIP_OK(hipMemcpyAsync(host, r.ptr, bytes, hipMemcpyDeviceToHost, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  return RS_OK;
+}
+
+rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes) {
+  if (!n || !host) return fail(RS_EINVAL, "NULL argument");
+  VarRef r;
+  if (!var_ref(n, var, &r, true)) return fail(RS_EINVAL, "unknown or read-only variable 0x%x", var);
+  if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
+  const int pj = var / 0x100 - 1, f = var % 0x100;
+  if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) {
+    // every slot below a row's length must hold a valid target: check the
+    // new lengths against the current indices, or the new indices against
+    // the current lengths
+    const ProjDev& P = pj == 0 ? n->in : n->rec;
+    std::vector<int32_t> len((size_t)P.n_pre), ind((size_t)P.n_pre * P.cap);
+    HIP_OK(hipStreamSynchronize(n->stream));
+    if (f == RS_P_LEN) {
+      memcpy(len.data(), host, bytes);
+      HIP_OK(hipMemcpy(ind.data(), P.ind, ind.size() * 4, hipMemcpyDeviceToHost));
+    } else {
+      memcpy(ind.data(), host, bytes);
+      HIP_OK(hipMemcpy(len.data(), P.len, len.size() * 4, hipMemcpyDeviceToHost));
+    }
+    for (int i = 0; i < P.n_pre; ++i) {
+      if (len[i] < 0 || len[i] > P.cap) return fail(RS_EINVAL, "row %d length %d outside 0..%d", i, len[i], P.cap);
+      for (int k = 0; k < len[i]; ++k) {
+        const int32_t j = ind[(size_t)i * P.cap + k];
+        if (j < 0 || j >= P.n_post) return fail(RS_EINVAL, "row %d slot %d target %d outside 0..%d", i, k, j, P.n_post - 1);
+      }
+    }
+  }
+  HIP_OK(hipStreamSynchronize(n->stream));
+  HIP_OK(hipMemcpyAsync(r.ptr, host, bytes, hipMemcpyHostToDevice, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  return RS_OK;
+}
+
+rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
+  if (!n || !o) return fail(RS_EINVAL, "NULL argument");
+  unsigned long long c[2];
+  HIP_OK(hipMemcpyAsync(c, n->counters, sizeof c, hipMemcpyDeviceToHost, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  memset(o, 0, sizeof *o);
+  o->cap_in = (uint32_t)n->in.cap;
+  o->cap_rec = (uint32_t)n->rec.cap;
+  o->words_in = (uint32_t)n->in.words;
+  o->words_rec = (uint32_t)n->rec.words;
+  o->step = n->step;
+  o->adam_step = n->adam_k;
+  o->synaptic_events = c[0];
+  o->spikes = c[1];
+  o->device_bytes = n->arena.bytes;
+  return RS_OK;
+}
+
+rs_status rs_eprop_timing(rs_eprop* n, int32_t enable) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  n->timer.on = enable != 0;
+  return RS_OK;
+}
+
+rs_status rs_eprop_phase_times(rs_eprop* n, double* ms, uint64_t* count) {
+  if (!n || !ms || !count) return fail(RS_EINVAL, "NULL argument");
+  n->timer.collect();
+  for (int q = 0; q < RS_NUM_PHASES; ++q) {
+    ms[q] = n->timer.ms[q];
+    count[q] = n->timer.count[q];
+    n->timer.ms[q] = 0;
+    n->timer.count[q] = 0;
+  }
+  return RS_OK;
+}
+
+void rs_eprop_destroy(rs_eprop* n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  n->timer.destroy();
+  n->arena.release();
+  delete n;
+}
+
+}  // extern "C"
+
+// =========================================================================== topomap
+struct rs_topo {
+  rs_topo_params p;
+  hipStream_t stream = nullptr;
+  Arena arena;
+  TopoDev t{};
+  uint64_t* T_d2 = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+};
+
+namespace {
+
+rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
+  if (p->L < 2 || p->L > 128) return fail(RS_EINVAL, "L must be in 2..128");
+  if (p->cap < 1 || p->cap > 1024 || p->cap > p->L * p->L) return fail(RS_EINVAL, "cap must be in 1..min(1024, L*L)");
+  if (p->n_attempts > 4096) return fail(RS_EINVAL, "n_attempts must be <= 4096");
+  if (!(p->p_form >= 0) || !(p->sigma_form > 0) || !(p->p_elim_dep >= 0) || !(p->p_elim_pot >= 0))
+    return fail(RS_EINVAL, "probabilities must be >= 0 and sigma_form > 0");
+  t->p = *p;
+  t->stream = (hipStream_t)stream;
+  hipStream_t s = t->stream;
+  const int L = (int)p->L, N = L * L;
+  ProjDev& P = t->t.P;
+  P.n_pre = N;
+  P.n_post = N;
+  P.cap = (int)p->cap;
+  P.words = (N + 31) / 32;
+  P.recurrent = 0;
+  P.proj_id = (int)p->proj_id;
+  Arena& ar = t->arena;
+  TRY(ar.alloc(&P.len, (size_t)N));
+  TRY(ar.alloc(&P.ind, (size_t)N * P.cap));
+  TRY(ar.alloc(&P.w, (size_t)N * P.cap));
+  const int half = L / 2, n_d2 = 2 * half * half + 1;
+  std::vector<uint64_t> T(n_d2);
+  for (int d2 = 0; d2 < n_d2; ++d2)
+    T[d2] = threshold((double)p->p_form * std::exp(-(double)d2 / (2.0 * (double)p->sigma_form * (double)p->sigma_form)));
+  TRY(ar.alloc(&t->T_d2, (size_t)n_d2));
+  TRY(ar.alloc(&t->t.bits, (size_t)N * P.words));
+  TRY(ar.alloc(&t->t.kcount, (size_t)N));
+  TRY(ar.alloc(&t->t.rowlist, (size_t)std::max<uint32_t>(p->n_attempts, 1)));
+  TRY(ar.alloc(&t->t.nrows, 1));
+  TRY(ar.alloc(&t->t.stats, 4));
+  HIP_OK(hipMemcpyAsync(t->T_d2, T.data(), n_d2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  t->t.T_d2 = t->T_d2;
+  t->t.L = L;
+  t->t.n_attempts = (int)p->n_attempts;
+  t->t.g_theta = p->g_theta;
+  t->t.g_new = p->g_new;
+  t->t.T_dep = threshold(p->p_elim_dep);
+  t->t.T_pot = threshold(p->p_elim_pot);
+  launch_fill_zero(s, P.ind, (size_t)N * P.cap * 4);
+  launch_fill_zero(s, P.w, (size_t)N * P.cap * 4);
+  launch_gauss_rows(s, p->seed, P, L, t->T_d2, p->g_init, true);
+  launch_fill_zero(s, t->t.bits, (size_t)N * P.words * 4);
+  launch_fill_zero(s, t->t.stats, 32);
+  HIP_OK(hipEventCreate(&t->ev0));
+  HIP_OK(hipEventCreate(&t->ev1));
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  return RS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_topo_create(const rs_topo_params* p, void* hip_stream, rs_topo** out) {
+  if (!out || !p) return fail(RS_EINVAL, "NULL argument");
+  *out = nullptr;
+  rs_topo* t = new rs_topo();
+  rs_status st = topo_create_impl(p, hip_stream, t);
+  if (st != RS_OK) {
+    (void)hipStreamSynchronize(t->stream);
+    t->arena.release();
+    delete t;
+    return st;
+  }
+  *out = t;
+  return RS_OK;
+}
+
+rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
+  if (!t) return fail(RS_EINVAL, "NULL argument");
+  hipStream_t s = t->stream;
+  launch_fill_zero(s, t->t.stats, 32);
+  HIP_OK(hipEventRecord(t->ev0, s));
+  launch_topo_rewire(s, t->p.seed, t->t, step);
+  HIP_OK(hipEventRecord(t->ev1, s));
+  t->timed = true;
+  HIP_OK(hipGetLastError());
+  if (st) {
+    long long h[4];
+    HIP_OK(hipMemcpyAsync(h, t->t.stats, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    st->eliminated = h[0];
+    st->formed = h[1];
+    st->blocked = h[2];
+    st->attempts = t->p.n_attempts;
+  }
+  return RS_OK;
+}
+
+rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
+  if (!t || !len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
+  const ProjDev& P = t->t.P;
+  const size_t n = (size_t)P.n_pre * P.cap;
+  HIP_OK(hipMemcpyAsync(len, P.len, (size_t)P.n_pre * 4, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipMemcpyAsync(ind, P.ind, n * 4, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipMemcpyAsync(w, P.w, n * 4, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
+}
+
+rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w) {
+  if (!t || !len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
+  const ProjDev& P = t->t.P;
+  for (int i = 0; i < P.n_pre; ++i) {
+    if (len[i] < 0 || len[i] > P.cap) return fail(RS_EINVAL, "row %d length %d outside 0..%d", i, len[i], P.cap);
+    for (int k = 0; k < len[i]; ++k) {
+      const int32_t j = ind[(size_t)i * P.cap + k];
+      if (j < 0 || j >= P.n_post) return fail(RS_EINVAL, "row %d slot %d target %d out of range", i, k, j);
+    }
+  }
+  const size_t n = (size_t)P.n_pre * P.cap;
+  HIP_OK(hipStreamSynchronize(t->stream));
+  HIP_OK(hipMemcpyAsync(P.len, len, (size_t)P.n_pre * 4, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipMemcpyAsync(P.ind, ind, n * 4, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipMemcpyAsync(P.w, w, n * 4, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
+}
+
+rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits) {
+  if (!t || !bits) return fail(RS_EINVAL, "NULL argument");
+  const ProjDev& P = t->t.P;
+  HIP_OK(hipMemcpyAsync(bits, t->t.bits, (size_t)P.n_pre * P.words * 4, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
+}
+
+rs_status rs_topo_last_ms(rs_topo* t, double* ms) {
+  if (!t || !ms) return fail(RS_EINVAL, "NULL argument");
+  if (!t->timed) return fail(RS_ESTATE, "no rewire has run");
+  float f = 0.f;
+  HIP_OK(hipEventSynchronize(t->ev1));
+  HIP_OK(hipEventElapsedTime(&f, t->ev0, t->ev1));
+  *ms = f;
+  return RS_OK;
+}
+
+void rs_topo_destroy(rs_topo* t) {
+  if (!t) return;
+  (void)hipStreamSynchronize(t->stream);
+  if (t->ev0) (void)hipEventDestroy(t->ev0);
+  if (t->ev1) (void)hipEventDestroy(t->ev1);
+  t->arena.release();
+  delete t;
+}
+
+rs_status rs_calib_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes % 16) return fail(RS_EINVAL, "copy needs non-NULL pointers and bytes % 16 == 0");
+  launch_copy((hipStream_t)hip_stream, dst, src, bytes);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+}  // extern "C"

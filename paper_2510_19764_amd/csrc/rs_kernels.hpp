@@ -1,0 +1,100 @@
+// Internal launch interface between the host engine and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+// Device view of one ragged projection.
+struct ProjDev {
+  int n_pre, n_post, cap, words, recurrent, proj_id;
+  int* len;          // [n_pre]
+  int* ind;          // [n_pre*cap]
+  float* w;          // [n_pre*cap]
+  float* m;          // Adam moments / gradient, may be null
+  float* v;
+  float* G;
+  float* eps;        // [n_pre*cap*B], null for LIF / untrained
+  float* ebar;       // [n_pre*cap*B], null if untrained
+  uint32_t* conn;    // [n_pre*words] DEEP R connectivity bits, may be null
+  uint32_t* sign;    // [n_pre*words] DEEP R sign bits, may be null
+  int* dormant;      // [n_pre] eliminated per row by the last rewire
+  int* assigned;     // [n_pre] activations per row of the last formation
+};
+
+// ---------------------------------------------------------------- build
+void launch_fixed_rows(hipStream_t s, uint64_t seed, const ProjDev& P, uint64_t T, double sigma, bool fill);
+void launch_gauss_rows(hipStream_t s, uint64_t seed, const ProjDev& P, int L, const uint64_t* T_d2,
+                       float g_init, bool fill);
+void launch_dense_init(hipStream_t s, uint64_t seed, int proj_id, int rows, int cols, double sigma, float* W);
+void launch_deepr_bits_init(hipStream_t s, uint64_t seed, const ProjDev& P);
+void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
+
+// ---------------------------------------------------------------- e-prop step
+struct FwdArgs {
+  int n_in, n_rec, n_out, B;
+  double alpha, rho, v_thr, beta;            // recurrences are evaluated in double
+  double psi_scale;                          // 0.3 / v_thr
+  double* V; double* A; double* Y;           // [B][n_rec], [B][n_rec], [B][n_out]
+  double* xbar; double* zbar;                // [B][n_in], [B][n_rec] trace masters
+  float* xbar_prevT;                         // [n_in][B]  trace before this step's input
+  float* zbar_prevT; float* zbar_newT;       // [n_rec][B] before / after this step's spikes
+  float* psiT; float* LT;                    // [n_rec][B]
+  float* deltaT;                             // [n_out][B]
+  uint8_t* z;                                // [B][n_rec]
+  const int* len_in; const int* ind_in; const float* w_in; int cap_in;
+  const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
+  const float* Wout; const float* bout;      // [n_out][n_rec], [n_out]
+  const int* x_off; const int* x_idx; int t_local;
+  const int* labels;
+  unsigned long long* counters;              // [0] synaptic events, [1] spikes
+};
+void launch_fwd(hipStream_t s, const FwdArgs& a);
+
+struct EpropArgs {
+  int n_in, n_rec, n_out, B, alif;
+  double alpha, rho, beta;
+  ProjDev in, rec;
+  const float* xbar_prev;   // [n_in][B]  presynaptic traces before this step's spikes
+  const float* zbar_prev;   // [n_rec][B]
+  const float* zbar_new;    // [n_rec][B]  after this step (readout gradient)
+  const float* psiT; const float* LT; const float* deltaT;
+  float* Gout; float* Gb;
+};
+void launch_eprop(hipStream_t s, const EpropArgs& a);
+
+// ---------------------------------------------------------------- update
+struct UpdateArgs {
+  int B;
+  float lr, b1, b2, eps, inv_c1, inv_c2, l1;
+  int l1_in, l1_rec;
+  ProjDev in, rec;
+  float* Wout; float* bout; float* Gout; float* Gb; float* Mout; float* Vout; float* Mb; float* Vb;
+  int n_out_elems, n_b;
+};
+void launch_update(hipStream_t s, const UpdateArgs& a);
+
+// ---------------------------------------------------------------- DEEP R
+// stats: int64[2] device counters, incremented (0: eliminated = D, 1: formed)
+void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step,
+                  long long* stats);
+
+// ---------------------------------------------------------------- topomap
+struct TopoDev {
+  ProjDev P;
+  int L, n_attempts;
+  float g_theta, g_new;
+  uint64_t T_dep, T_pot;
+  const uint64_t* T_d2;   // [2*(L/2)^2 + 1]
+  uint32_t* bits;         // [n_pre*words]
+  int* kcount;            // [n_pre]
+  int* rowlist;           // [max(n_attempts,1)]
+  int* nrows;             // [1]
+  long long* stats;       // [4]
+};
+void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step);
+
+// ---------------------------------------------------------------- misc
+void launch_copy(hipStream_t s, void* dst, const void* src, size_t bytes);
+
+}  // namespace rs

@@ -99,9 +99,10 @@ class ShdLike:
             cc = ch0[c] + rng.normal(0.0, self.jitter_ch, self.bumps)
             tc = t0[c] + rng.normal(0.0, self.jitter_t_ms, self.bumps)
             rate = np.full((self.T, self.n_ch), self.base_hz)
-            for m in range(self.bumps):
-                rate += self.peak_hz * np.exp(-(ts[:, None] - tc[m]) ** 2 / (2 * self.sigma_t_ms ** 2)
-                                              - (chs[None, :] - cc[m]) ** 2 / (2 * self.sigma_ch ** 2))
+            for m in range(self.bumps):  # separable Gaussian bump in (time, channel)
+                gt = np.exp(-(ts - tc[m]) ** 2 / (2 * self.sigma_t_ms ** 2))
+                gc = np.exp(-(chs - cc[m]) ** 2 / (2 * self.sigma_ch ** 2))
+                rate += self.peak_hz * np.outer(gt, gc)
             spk[:, b, :] = rng.random((self.T, self.n_ch)) < rate * self.dt_ms * 1e-3
         return labels, _to_raster(spk)
 

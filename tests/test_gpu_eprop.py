@@ -1,0 +1,223 @@
+"""GPU parity of the e-prop network path against the fp64 oracle, called
+through the C-ABI: build, lockstep steps with spike resync at threshold ties,
+parameter update, DEEP R rewiring (bit-exact from the same pre-rewire state),
+determinism and error handling."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_harness import (close, compare_rows_exact, compare_state, gpu_input, oracle_net,
+                         oracle_step_resync, real_slots, snapshot)
+from paper_2510_19764_amd import binding as rb
+from paper_2510_19764_amd import workload as wl
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def make_cfg(n_in, n_rec, n_out, B, alif, p=0.2, seed=3, U=25, T=500, mask=3, lr=1e-3):
+    f32 = lambda x: float(np.float32(x))
+    return rb.EpropConfig(n_in=n_in, n_rec=n_rec, n_out=n_out, batch=B, alif=alif, p_in=p, p_rec=p,
+                          sigma_in=f32(wl.sigma_init(p, n_in)), sigma_rec=f32(wl.sigma_init(p, n_rec)),
+                          sigma_out=f32(1.0 / np.sqrt(n_rec)), deepr_mask=mask, update_interval=U,
+                          sample_steps=T, seed=seed, lr=lr)
+
+
+CASES = {
+    # name: (config, max input rate Hz)
+    "tiny-lif-b1": (make_cfg(100, 128, 4, 1, False, p=0.1, seed=1), 50.0),
+    "alif-b3-narrow": (make_cfg(30, 40, 3, 3, True, seed=2), 150.0),
+    "alif-b64-wide": (make_cfg(60, 96, 5, 64, True, seed=3), 150.0),
+    "lif-b256-wide": (make_cfg(50, 80, 6, 256, False, seed=4), 150.0),
+    "alif-b320-chunked": (make_cfg(40, 70, 4, 320, True, seed=5), 150.0),
+}
+
+
+def setup_case(name, T=None):
+    cfg, rate = CASES[name]
+    if T is not None:
+        cfg = rb.EpropConfig(**{**cfg.__dict__, "sample_steps": T})
+    net = rb.EpropNet(cfg)
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
+    raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+    labels = np.random.default_rng(cfg.seed).integers(0, cfg.n_out, cfg.batch).astype(np.int32)
+    dev = gpu_input(raster, labels)
+    net.set_input(*dev)
+    return cfg, net, raster, labels
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_build_matches_oracle(name):
+    cfg, net, _, _ = setup_case(name, T=10)
+    snap = snapshot(net, with_traces=False)
+    for tag, n_pre, rec, p, sigma, pid in (("in", cfg.n_in, False, cfg.p_in, cfg.sigma_in, 0),
+                                           ("rec", cfg.n_rec, True, cfg.p_rec, cfg.sigma_rec, 1)):
+        g = snap[tag]
+        cap = g["ind"].shape[1]
+        lens, mx = oracle.fixed_prob_count(cfg.seed, n_pre, cfg.n_rec, p, rec, pid)
+        assert cap == min(2 * mx, cfg.n_rec)
+        P = oracle.Proj(n_pre, cfg.n_rec, cap, rec, pid, bitfields=True)
+        oracle.fixed_prob_rows(cfg.seed, P, p, sigma)
+        compare_rows_exact(tag, g, P)
+        m = real_slots(g)
+        close(tag + ".w", g["w"][m], P.w.reshape(-1, cap)[m], 0.0, rtol=1e-6)
+        oracle.deepr_init_bits(cfg.seed, P)
+        assert np.array_equal(g["conn"].ravel(), P.conn)
+        assert np.array_equal(g["sign"].ravel(), P.sign)
+    Wo = oracle.dense_init(cfg.seed, 2, cfg.n_out, cfg.n_rec, cfg.sigma_out)
+    close("Wout", snap["Wout"], Wo, 0.0, rtol=1e-6)
+    assert not snap["bout"].any()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_lockstep_100_steps(name):
+    cfg, net, raster, labels = setup_case(name)
+    N = oracle_net(snapshot(net), cfg)
+    resync = 0
+    spikes = 0
+    for t in range(100):
+        net.step(1, rb.RS_LEARN)
+        snap = snapshot(net)
+        resync += oracle_step_resync(N, raster, t, labels, snap["z"])
+        spikes += int(snap["z"].sum())
+        compare_state(snap, N, cfg)
+    assert spikes > 0
+    assert resync <= 2, f"{resync} threshold ties in 100 steps"
+    inf = net.info()
+    assert inf.step == 100 and inf.spikes == spikes
+
+
+@pytest.mark.parametrize("name", ["tiny-lif-b1", "alif-b64-wide", "alif-b3-narrow"])
+def test_update_matches_oracle(name):
+    cfg, net, raster, labels = setup_case(name)
+    net.step(30, rb.RS_LEARN)
+    snap = snapshot(net)
+    N = oracle_net(snap, cfg)
+    net.update()
+    after = snapshot(net)
+    N.adam_update(1, lr=cfg.lr, b1=cfg.adam_b1, b2=cfg.adam_b2, eps=cfg.adam_eps, l1=cfg.l1,
+                  deepr_mask=cfg.deepr_mask)
+    for tag, P, sig in (("in", N.inp, cfg.sigma_in), ("rec", N.rec, cfg.sigma_rec)):
+        g = after[tag]
+        m = real_slots(g)
+        cap = g["ind"].shape[1]
+        close(tag + ".w", g["w"][m], P.w.reshape(-1, cap)[m], sig)
+        close(tag + ".m", g["m"][m], P.m.reshape(-1, cap)[m], np.abs(P.m).max())
+        # the second moment is quadratic in the gradient: twice its relative error
+        close(tag + ".v", g["vv"][m], P.v.reshape(-1, cap)[m], np.abs(P.v).max(), rtol=2e-5)
+        assert not g["G"][m].any()
+    close("Wout", after["Wout"], N.Wout, cfg.sigma_out)
+    close("bout", after["bout"], N.bout, 1e-3)
+    assert not after["Gout"].any() and not after["Gb"].any()
+    assert net.info().adam_step == 1
+
+
+def flip_some_signs(net, cfg, frac, seed):
+    """Flip the sign of a fraction of weights through the snapshot API so that
+    DEEP R has synapses to eliminate."""
+    rng = np.random.default_rng(seed)
+    for p in (0, 1):
+        w = net.get(rb.PROJ(p, rb.P_W))
+        w[rng.random(w.shape) < frac] *= -1
+        net.set(rb.PROJ(p, rb.P_W), w)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_deepr_rewire_bit_exact(name):
+    cfg, net, raster, labels = setup_case(name)
+    net.step(20, rb.RS_LEARN)
+    net.update()
+    flip_some_signs(net, cfg, 0.15, cfg.seed)
+    for proj in (0, 1):
+        pre = snapshot(net)
+        step = net.info().step
+        st = net.rewire(proj)
+        post = snapshot(net)
+        N = oracle_net(pre, cfg)
+        P = N.inp if proj == 0 else N.rec
+        dormant, ost = oracle.deepr_rewire(cfg.seed, P, step)
+        assert (st.eliminated, st.formed) == (int(ost[0]), int(ost[1]))
+        assert st.eliminated > 0
+        tag = "in" if proj == 0 else "rec"
+        g = post[tag]
+        cap = g["ind"].shape[1]
+        m = real_slots(g)
+        compare_rows_exact(tag, g, P)
+        for name_g, arr in (("w", P.w), ("m", P.m), ("vv", P.v), ("G", P.G)):
+            assert np.array_equal(g[name_g][m], arr.reshape(-1, cap)[m].astype(np.float32)), name_g
+        assert np.array_equal(g["ebar"][m], P.ebar.reshape(-1, cap, cfg.batch)[m].astype(np.float32))
+        if cfg.alif:
+            assert np.array_equal(g["eps"][m], P.eps.reshape(-1, cap, cfg.batch)[m].astype(np.float32))
+        assert np.array_equal(g["conn"].ravel(), P.conn)
+        assert np.array_equal(g["sign"].ravel(), P.sign)
+        assert np.array_equal(g["dormant"], dormant)
+        assert int(g["len"].sum()) == int(pre[tag]["len"].sum())
+        # the other projection is untouched
+        other = "rec" if proj == 0 else "in"
+        assert np.array_equal(post[other]["len"], pre[other]["len"])
+
+
+def test_training_loop_invariants_and_determinism():
+    cfg = make_cfg(100, 128, 4, 1, False, p=0.1, seed=11, U=25, T=500, lr=0.05)
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, 50.0)
+    raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+    labels = np.array([2], np.int32)
+    snaps = []
+    for rep in range(2):
+        net = rb.EpropNet(cfg)
+        net.set_input(*gpu_input(raster, labels))
+        total0 = [int(net.get(rb.PROJ(p, rb.P_LEN)).sum()) for p in (0, 1)]
+        net.step(500, rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET)
+        s = snapshot(net)
+        inf = net.info()
+        assert inf.adam_step == 20 and inf.step == 500
+        for p, tag in ((0, "in"), (1, "rec")):
+            g = s[tag]
+            assert int(g["len"].sum()) == total0[p]
+            for i in range(g["len"].size):
+                row = g["ind"][i, :g["len"][i]]
+                assert len(set(row.tolist())) == row.size
+                if tag == "rec":
+                    assert i not in row
+                words = g["conn"][i]
+                bits = {j for j in range(cfg.n_rec) if (int(words[j >> 5]) >> (j & 31)) & 1}
+                assert bits == set(row.tolist())
+        snaps.append(s)
+        net.close()
+    a, b = snaps
+    for tag in ("in", "rec"):
+        for k in a[tag]:
+            assert np.array_equal(a[tag][k], b[tag][k]), (tag, k)
+    for k in ("v", "Wout", "bout"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_error_paths():
+    cfg, _ = CASES["tiny-lif-b1"]
+    net = rb.EpropNet(cfg)
+    with pytest.raises(rb.RagsnnError) as e:
+        net.step(1)
+    assert e.value.code == rb.RS_ESTATE
+    cfg2 = rb.EpropConfig(**{**cfg.__dict__, "deepr_mask": 2})
+    net2 = rb.EpropNet(cfg2)
+    with pytest.raises(rb.RagsnnError) as e:
+        net2.rewire(0)
+    assert e.value.code == rb.RS_EINVAL
+    ln = net.get(rb.PROJ(1, rb.P_LEN))
+    bad = ln.copy()
+    bad[0] = net.info().cap_rec + 1
+    with pytest.raises(rb.RagsnnError) as e:
+        net.set(rb.PROJ(1, rb.P_LEN), bad)
+    assert e.value.code == rb.RS_EINVAL
+    ind = net.get(rb.PROJ(1, rb.P_IND))
+    if ln[0] > 0:
+        ind[0, 0] = cfg.n_rec + 5
+        with pytest.raises(rb.RagsnnError) as e:
+            net.set(rb.PROJ(1, rb.P_IND), ind)
+        assert e.value.code == rb.RS_EINVAL
+    assert np.array_equal(net.get(rb.PROJ(1, rb.P_LEN)), ln)
+    import ctypes
+    buf = np.zeros(3, np.float32)
+    code = rb.lib().rs_eprop_get(net._h, rb.V, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes)
+    assert code == rb.RS_ECAPACITY
