@@ -125,8 +125,13 @@ struct rs_eprop {
   ProjDev in{}, rec{};
   double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
   double *xbar = nullptr, *zbar = nullptr;            // fp64 trace masters [B][n]
-  float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;  // [n][B]
-  float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
+  // Per-step hand-off from the forward kernel to the e-prop kernel, double
+  // buffered by step parity so that forward(t+1) overlaps e-prop(t).
+  float *xbar_prevT[2] = {}, *zbar_prevT[2] = {}, *zbar_newT[2] = {};  // [n][B]
+  float *psiT[2] = {}, *LT[2] = {}, *deltaT[2] = {};
+  hipStream_t side = nullptr;                         // e-prop / update / rewire stream
+  hipEvent_t ev_fwd[2] = {}, ev_ep[2] = {}, ev_join = nullptr, ev_back = nullptr;
+  bool ep_pending[2] = {false, false};
   uint8_t* z = nullptr;
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
   float *Mout = nullptr, *Vout = nullptr, *Mb = nullptr, *Vb = nullptr;
@@ -249,12 +254,21 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  TRY(ar.alloc(&n->xbar_prevT, NI * B));
-  TRY(ar.alloc(&n->zbar_prevT, NR * B));
-  TRY(ar.alloc(&n->zbar_newT, NR * B));
-  TRY(ar.alloc(&n->psiT, NR * B));
-  TRY(ar.alloc(&n->LT, NR * B));
-  TRY(ar.alloc(&n->deltaT, K * B));
+  for (int q = 0; q < 2; ++q) {
+    TRY(ar.alloc(&n->xbar_prevT[q], NI * B));
+    TRY(ar.alloc(&n->zbar_prevT[q], NR * B));
+    TRY(ar.alloc(&n->zbar_newT[q], NR * B));
+    TRY(ar.alloc(&n->psiT[q], NR * B));
+    TRY(ar.alloc(&n->LT[q], NR * B));
+    TRY(ar.alloc(&n->deltaT[q], K * B));
+  }
+  HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
+  for (int q = 0; q < 2; ++q) {
+    HIP_OK(hipEventCreateWithFlags(&n->ev_fwd[q], hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
+  }
+  HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_back, hipEventDisableTiming));
   TRY(ar.alloc(&n->z, B * NR));
   TRY(ar.alloc(&n->Wout, K * NR));
   TRY(ar.alloc(&n->bout, K));
@@ -281,11 +295,13 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   zero_proj_state(s, n->in, B);
   zero_proj_state(s, n->rec, B);
   for (double* q : {n->V, n->A, n->zbar}) launch_fill_zero(s, q, B * NR * 8);
-  for (float* q : {n->psiT, n->LT, n->zbar_prevT, n->zbar_newT}) launch_fill_zero(s, q, B * NR * 4);
+  for (int b = 0; b < 2; ++b) {
+    for (float* q : {n->psiT[b], n->LT[b], n->zbar_prevT[b], n->zbar_newT[b]}) launch_fill_zero(s, q, B * NR * 4);
+    launch_fill_zero(s, n->xbar_prevT[b], B * NI * 4);
+    launch_fill_zero(s, n->deltaT[b], B * K * 4);
+  }
   launch_fill_zero(s, n->xbar, B * NI * 8);
-  launch_fill_zero(s, n->xbar_prevT, B * NI * 4);
   launch_fill_zero(s, n->Y, B * K * 8);
-  launch_fill_zero(s, n->deltaT, B * K * 4);
   launch_fill_zero(s, n->z, B * NR);
   for (float* q : {n->Gout, n->Mout, n->Vout}) launch_fill_zero(s, q, K * NR * 4);
   for (float* q : {n->bout, n->Gb, n->Mb, n->Vb}) launch_fill_zero(s, q, K * 4);
@@ -296,8 +312,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   return RS_OK;
 }
 
-void reset_state(rs_eprop* n) {
-  hipStream_t s = n->stream;
+void reset_state(rs_eprop* n, hipStream_t s) {
   const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in, K = n->p.n_out;
   launch_fill_zero(s, n->V, B * NR * 8);
   launch_fill_zero(s, n->A, B * NR * 8);
@@ -311,7 +326,7 @@ void reset_state(rs_eprop* n) {
   }
 }
 
-void do_update(rs_eprop* n) {
+void do_update(rs_eprop* n, hipStream_t s) {
   n->adam_k += 1;
   UpdateArgs u{};
   u.B = n->B;
@@ -330,29 +345,36 @@ void do_update(rs_eprop* n) {
   u.Mout = n->Mout; u.Vout = n->Vout; u.Mb = n->Mb; u.Vb = n->Vb;
   u.n_out_elems = (int)(n->p.n_out * n->p.n_rec);
   u.n_b = (int)n->p.n_out;
-  n->timer.begin(n->stream, 2);
-  launch_update(n->stream, u);
-  n->timer.end(n->stream);
+  n->timer.begin(s, 2);
+  launch_update(s, u);
+  n->timer.end(s);
 }
 
-void do_rewire(rs_eprop* n, int proj) {
+void do_rewire(rs_eprop* n, int proj, hipStream_t s) {
   ProjDev& P = proj == 0 ? n->in : n->rec;
-  n->timer.begin(n->stream, 3);
-  launch_deepr(n->stream, n->p.seed, P, n->B, n->step, n->rw_stats);
-  n->timer.end(n->stream);
+  n->timer.begin(s, 3);
+  launch_deepr(s, n->p.seed, P, n->B, n->step, n->rw_stats);
+  n->timer.end(s);
 }
 
+// One timestep.  The forward kernel runs on the caller's stream, the e-prop
+// kernel on the side stream; buffer set q = step parity carries the hand-off.
 void do_step(rs_eprop* n, uint32_t flags) {
-  hipStream_t s = n->stream;
+  hipStream_t s = n->stream, e = n->side;
   const int t_local = (int)(n->step % n->p.sample_steps);
+  const int q = (int)(n->step & 1);
+  if (n->ep_pending[q]) {  // e-prop two steps back still reads set q
+    (void)hipStreamWaitEvent(s, n->ev_ep[q], 0);
+    n->ep_pending[q] = false;
+  }
   FwdArgs f{};
   f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
   f.alpha = n->alpha; f.rho = n->rho; f.v_thr = n->p.v_thr; f.beta = n->beta;
   f.psi_scale = 0.3 / (double)n->p.v_thr;
   f.V = n->V; f.A = n->A; f.Y = n->Y;
   f.xbar = n->xbar; f.zbar = n->zbar;
-  f.xbar_prevT = n->xbar_prevT; f.zbar_prevT = n->zbar_prevT; f.zbar_newT = n->zbar_newT;
-  f.psiT = n->psiT; f.LT = n->LT; f.deltaT = n->deltaT; f.z = n->z;
+  f.xbar_prevT = n->xbar_prevT[q]; f.zbar_prevT = n->zbar_prevT[q]; f.zbar_newT = n->zbar_newT[q];
+  f.psiT = n->psiT[q]; f.LT = n->LT[q]; f.deltaT = n->deltaT[q]; f.z = n->z;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
   f.Wout = n->Wout; f.bout = n->bout;
@@ -361,28 +383,40 @@ void do_step(rs_eprop* n, uint32_t flags) {
   n->timer.begin(s, 0);
   launch_fwd(s, f);
   n->timer.end(s);
+  (void)hipEventRecord(n->ev_fwd[q], s);
   if (flags & RS_LEARN) {
-    EpropArgs e{};
-    e.n_in = f.n_in; e.n_rec = f.n_rec; e.n_out = f.n_out; e.B = n->B; e.alif = n->p.alif ? 1 : 0;
-    e.alpha = n->alpha; e.rho = n->rho; e.beta = n->beta;
-    e.in = n->in; e.rec = n->rec;
-    e.xbar_prev = n->xbar_prevT; e.zbar_prev = n->zbar_prevT; e.zbar_new = n->zbar_newT;
-    e.psiT = n->psiT; e.LT = n->LT; e.deltaT = n->deltaT;
-    e.Gout = n->Gout; e.Gb = n->Gb;
-    n->timer.begin(s, 1);
-    launch_eprop(s, e);
-    n->timer.end(s);
+    EpropArgs a{};
+    a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B; a.alif = n->p.alif ? 1 : 0;
+    a.alpha = n->alpha; a.rho = n->rho; a.beta = n->beta;
+    a.in = n->in; a.rec = n->rec;
+    a.xbar_prev = n->xbar_prevT[q]; a.zbar_prev = n->zbar_prevT[q]; a.zbar_new = n->zbar_newT[q];
+    a.psiT = n->psiT[q]; a.LT = n->LT[q]; a.deltaT = n->deltaT[q];
+    a.Gout = n->Gout; a.Gb = n->Gb;
+    (void)hipStreamWaitEvent(e, n->ev_fwd[q], 0);
+    n->timer.begin(e, 1);
+    launch_eprop(e, a);
+    n->timer.end(e);
+    (void)hipEventRecord(n->ev_ep[q], e);
+    n->ep_pending[q] = true;
   }
   n->step += 1;
-  if ((flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0) {
-    do_update(n);
-    if (n->p.deepr_mask & 1) do_rewire(n, 0);
-    if (n->p.deepr_mask & 2) do_rewire(n, 1);
-  }
-  if ((flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0) {
-    n->timer.begin(s, 4);
-    reset_state(n);
-    n->timer.end(s);
+  const bool upd = (flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0;
+  const bool rst = (flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0;
+  if (upd || rst) {
+    // after this step's forward (and e-prop, queued first on the side stream)
+    (void)hipStreamWaitEvent(e, n->ev_fwd[q], 0);
+    if (upd) {
+      do_update(n, e);
+      if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
+      if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
+    }
+    if (rst) {
+      n->timer.begin(e, 4);
+      reset_state(n, e);
+      n->timer.end(e);
+    }
+    (void)hipEventRecord(n->ev_back, e);
+    (void)hipStreamWaitEvent(s, n->ev_back, 0);
   }
 }
 
@@ -393,6 +427,7 @@ struct VarRef {
 
 bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
   const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in, K = n->p.n_out;
+  const int last = (int)((n->step + 1) & 1);  // buffer set written by the last step
   const int pj = var / 0x100 - 1, f = var % 0x100;
   if (var < 0x100) {
     switch (var) {
@@ -401,9 +436,9 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_Y: *r = {n->Y, B * K * 8}; return true;
       case RS_XBAR: *r = {n->xbar, NI * B * 8}; return true;
       case RS_ZBAR: *r = {n->zbar, NR * B * 8}; return true;
-      case RS_PSI: *r = {n->psiT, NR * B * 4}; return !for_write;
-      case RS_LSIG: *r = {n->LT, NR * B * 4}; return !for_write;
-      case RS_DELTA: *r = {n->deltaT, K * B * 4}; return !for_write;
+      case RS_PSI: *r = {n->psiT[last], NR * B * 4}; return !for_write;
+      case RS_LSIG: *r = {n->LT[last], NR * B * 4}; return !for_write;
+      case RS_DELTA: *r = {n->deltaT[last], K * B * 4}; return !for_write;
       case RS_Z: *r = {n->z, B * NR}; return !for_write;
       case RS_WOUT: *r = {n->Wout, K * NR * 4}; return true;
       case RS_BOUT: *r = {n->bout, K * 4}; return true;
@@ -448,11 +483,7 @@ rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_ep
   rs_eprop* n = nullptr;
   rs_status st = create_impl(params, hip_stream, &n);
   if (st != RS_OK) {
-    if (n) {
-      (void)hipStreamSynchronize(n->stream);
-      n->arena.release();
-      delete n;
-    }
+    if (n) rs_eprop_destroy(n);
     return st;
   }
   *out = n;
@@ -490,14 +521,18 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
   if (!n->x_off) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input)");
   if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
+  HIP_OK(hipEventRecord(n->ev_join, n->stream));  // side stream follows earlier caller work
+  HIP_OK(hipStreamWaitEvent(n->side, n->ev_join, 0));
   for (uint32_t q = 0; q < n_steps; ++q) do_step(n, flags);
+  HIP_OK(hipEventRecord(n->ev_back, n->side));     // caller's stream covers all of it
+  HIP_OK(hipStreamWaitEvent(n->stream, n->ev_back, 0));
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
 
 rs_status rs_eprop_update(rs_eprop* n) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
-  do_update(n);
+  do_update(n, n->stream);
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
@@ -507,7 +542,7 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
   if (proj > 1 || !((n->p.deepr_mask >> proj) & 1u))
     return fail(RS_EINVAL, "projection %u is not rewired by DEEP R", proj);
   launch_fill_zero(n->stream, n->rw_stats, 16);
-  do_rewire(n, (int)proj);
+  do_rewire(n, (int)proj, n->stream);
   HIP_OK(hipGetLastError());
   if (st) {
     long long h[2];
@@ -523,7 +558,7 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
 
 rs_status rs_eprop_reset(rs_eprop* n) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
-  reset_state(n);
+  reset_state(n, n->stream);
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
@@ -611,7 +646,11 @@ rs_status rs_eprop_phase_times(rs_eprop* n, double* ms, uint64_t* count) {
 void rs_eprop_destroy(rs_eprop* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->stream);
+  if (n->side) (void)hipStreamSynchronize(n->side);
   n->timer.destroy();
+  for (hipEvent_t ev : {n->ev_fwd[0], n->ev_fwd[1], n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back})
+    if (ev) (void)hipEventDestroy(ev);
+  if (n->side) (void)hipStreamDestroy(n->side);
   n->arena.release();
   delete n;
 }

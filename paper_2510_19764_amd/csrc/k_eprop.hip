@@ -239,6 +239,26 @@ __device__ __forceinline__ float synapse_update(const EpropArgs& a, const float*
   return (L.x * eb.x + L.y * eb.y) + (L.z * eb.z + L.w * eb.w);
 }
 
+// One eligibility step for four batch instances held by a lane; returns the
+// lane's part of sum_b L ebar.
+template <bool ALIF>
+__device__ __forceinline__ float trace_step(const EpropArgs& a, f4 psi, f4 L, f4 p, f4 eb0, f4 ep0,
+                                            float* __restrict__ ebar_out, float* __restrict__ eps_out) {
+  const d4 dpsi = __builtin_convertvector(psi, d4), dp = __builtin_convertvector(p, d4);
+  d4 e;
+  if (ALIF) {
+    const d4 ep = __builtin_convertvector(ep0, d4);
+    e = dpsi * (dp - a.beta * ep);
+    const d4 ep1 = dpsi * dp + (a.rho - dpsi * a.beta) * ep;
+    __builtin_nontemporal_store(__builtin_convertvector(ep1, f4), (f4*)eps_out);
+  } else {
+    e = dpsi * dp;
+  }
+  const f4 eb = __builtin_convertvector(a.alpha * __builtin_convertvector(eb0, d4) + e, f4);
+  __builtin_nontemporal_store(eb, (f4*)ebar_out);
+  return (L.x * eb.x + L.y * eb.y) + (L.z * eb.z + L.w * eb.w);
+}
+
 __device__ __forceinline__ void readout_grad_wave(const EpropArgs& a, int j, int lane) {
   const int B = a.B, nb4 = B / 4;
   if (j < a.n_rec) {
@@ -285,14 +305,58 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_wide(EpropArgs a) {
   const int B = a.B, nb4 = B / 4;
   const int64_t base = (int64_t)i * cap;
   if (nb4 <= WAVE) {
+    // Wave wv owns slots k = wv + 4q.  Per chunk of 64 such slots, lane q holds
+    // the target index and gradient of slot wv + 4(64c + q); synapses are then
+    // processed two at a time with every load issued before any arithmetic.
     const bool act = lane < nb4;
-    const f4 p = act ? *(const f4*)&pre[(int64_t)i * B + 4 * lane] : f4{0.f, 0.f, 0.f, 0.f};
-    for (int k = wv; k < n; k += EP_WAVES) {
-      const int64_t s = base + k;
-      const int j = ind[s];
-      float g = act ? synapse_update<ALIF>(a, a.psiT, a.LT, eps, ebar, s, j, lane, p) : 0.0f;
-      g = wave_sum(g);
-      if (lane == 0) G[s] += g;
+    const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    const f4 p = act ? *(const f4*)&pre[(int64_t)i * B + 4 * lane] : zero4;
+    for (int c0 = 0; wv + 4 * c0 < n; c0 += WAVE) {
+      const int kl = wv + 4 * (c0 + lane);
+      const bool own = kl < n;
+      const int my_j = own ? ind[base + kl] : 0;
+      float my_g = own ? G[base + kl] : 0.0f;
+      const int cnt = min(WAVE, (n - wv - 4 * c0 + 3) / 4);
+      int q = 0;
+      for (; q + 1 < cnt; q += 2) {
+        const int j0 = __builtin_amdgcn_readlane(my_j, q), j1 = __builtin_amdgcn_readlane(my_j, q + 1);
+        const int64_t s0 = base + wv + 4 * (c0 + q), s1 = s0 + 4;
+        float g0 = 0.f, g1 = 0.f;
+        if (act) {
+          const f4 psi0 = *(const f4*)&a.psiT[(int64_t)j0 * B + 4 * lane];
+          const f4 L0 = *(const f4*)&a.LT[(int64_t)j0 * B + 4 * lane];
+          const f4 psi1 = *(const f4*)&a.psiT[(int64_t)j1 * B + 4 * lane];
+          const f4 L1 = *(const f4*)&a.LT[(int64_t)j1 * B + 4 * lane];
+          const f4 eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + 4 * lane]);
+          const f4 eb1 = __builtin_nontemporal_load((const f4*)&ebar[s1 * B + 4 * lane]);
+          f4 ep0 = zero4, ep1 = zero4;
+          if (ALIF) {
+            ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + 4 * lane]);
+            ep1 = __builtin_nontemporal_load((const f4*)&eps[s1 * B + 4 * lane]);
+          }
+          g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0, &ebar[s0 * B + 4 * lane], &eps[s0 * B + 4 * lane]);
+          g1 = trace_step<ALIF>(a, psi1, L1, p, eb1, ep1, &ebar[s1 * B + 4 * lane], &eps[s1 * B + 4 * lane]);
+        }
+        g0 = wave_sum(g0);
+        g1 = wave_sum(g1);
+        my_g += (lane == q) ? g0 : ((lane == q + 1) ? g1 : 0.0f);
+      }
+      if (q < cnt) {
+        const int j0 = __builtin_amdgcn_readlane(my_j, q);
+        const int64_t s0 = base + wv + 4 * (c0 + q);
+        float g0 = 0.f;
+        if (act) {
+          const f4 psi0 = *(const f4*)&a.psiT[(int64_t)j0 * B + 4 * lane];
+          const f4 L0 = *(const f4*)&a.LT[(int64_t)j0 * B + 4 * lane];
+          const f4 eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + 4 * lane]);
+          f4 ep0 = zero4;
+          if (ALIF) ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + 4 * lane]);
+          g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0, &ebar[s0 * B + 4 * lane], &eps[s0 * B + 4 * lane]);
+        }
+        g0 = wave_sum(g0);
+        my_g += (lane == q) ? g0 : 0.0f;
+      }
+      if (own) G[base + kl] = my_g;
     }
   } else {
     for (int k = wv; k < n; k += EP_WAVES) {
