@@ -44,7 +44,8 @@ class _EpropParams(C.Structure):
                 ("cap_in", C.c_uint32), ("cap_rec", C.c_uint32),
                 ("deepr_mask", C.c_uint32), ("l1", C.c_float),
                 ("lr", C.c_float), ("adam_b1", C.c_float), ("adam_b2", C.c_float), ("adam_eps", C.c_float),
-                ("update_interval", C.c_uint32), ("sample_steps", C.c_uint32), ("seed", C.c_uint64)]
+                ("update_interval", C.c_uint32), ("sample_steps", C.c_uint32), ("seed", C.c_uint64),
+                ("trace_block", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class _Stats(C.Structure):
@@ -159,6 +160,7 @@ class EpropConfig:
     update_interval: int = 100
     sample_steps: int = 1000
     seed: int = 1
+    trace_block: int = 0
 
     def c(self) -> _EpropParams:
         p = _EpropParams()

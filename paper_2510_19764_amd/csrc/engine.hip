@@ -125,12 +125,18 @@ struct rs_eprop {
   ProjDev in{}, rec{};
   double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
   double *xbar = nullptr, *zbar = nullptr;            // fp64 trace masters [B][n]
-  // Per-step hand-off from the forward kernel to the e-prop kernel, double
-  // buffered by step parity so that forward(t+1) overlaps e-prop(t).
-  float *xbar_prevT[2] = {}, *zbar_prevT[2] = {}, *zbar_newT[2] = {};  // [n][B]
-  float *psiT[2] = {}, *LT[2] = {}, *deltaT[2] = {};
+  // Hand-off from the forward kernel to the e-prop kernel: a ring of 2K step
+  // slots laid out [n][2K][B].  Steps are grouped in blocks of K; the forward
+  // pass fills one half while the e-prop launch of the previous block reads
+  // the other.
+  float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;
+  float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
+  int K = 8, nslot = 16;
+  int blk_half = 0, blk_n = 0, last_slot = 0;
+  uint64_t blk_t0 = 0;
+  bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
-  hipEvent_t ev_fwd[2] = {}, ev_ep[2] = {}, ev_join = nullptr, ev_back = nullptr;
+  hipEvent_t ev_fwd = nullptr, ev_ep[2] = {}, ev_join = nullptr, ev_back = nullptr;
   bool ep_pending[2] = {false, false};
   uint8_t* z = nullptr;
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
@@ -161,6 +167,11 @@ rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr) {
   if (deepr) {
     TRY(ar.alloc(&P.conn, (size_t)P.n_pre * P.words));
     TRY(ar.alloc(&P.sign, (size_t)P.n_pre * P.words));
+  }
+  if (B % 4 == 0 && B >= 64 && B <= 256) {
+    TRY(ar.alloc(&P.perm, n));
+    TRY(ar.alloc(&P.oct_off, (size_t)P.n_pre * 9));
+    P.oct_size = (P.n_post + 7) / 8;
   }
   return RS_OK;
 }
@@ -195,7 +206,7 @@ rs_status count_rows(hipStream_t s, uint64_t seed, ProjDev& P, uint64_t T, int* 
 
 rs_status validate(const rs_eprop_params* p) {
   if (!p) return fail(RS_EINVAL, "params is NULL");
-  if (p->n_in < 1 || p->n_in > 65536) return fail(RS_EINVAL, "n_in must be in 1..65536");
+  if (p->n_in < 1 || p->n_in > 8192) return fail(RS_EINVAL, "n_in must be in 1..8192");
   if (p->n_rec < 1 || p->n_rec > 8192) return fail(RS_EINVAL, "n_rec must be in 1..8192");
   if (p->n_out < 1 || p->n_out > 256) return fail(RS_EINVAL, "n_out must be in 1..256");
   if (p->batch < 1 || p->batch > 65536) return fail(RS_EINVAL, "batch must be in 1..65536");
@@ -208,6 +219,8 @@ rs_status validate(const rs_eprop_params* p) {
   if (p->cap_in > p->n_rec || p->cap_rec > p->n_rec)
     return fail(RS_EINVAL, "row capacity cannot exceed the number of targets");
   if (p->sample_steps < 1) return fail(RS_EINVAL, "sample_steps must be >= 1");
+  if (p->trace_block > 32) return fail(RS_EINVAL, "trace_block must be in 0..32");
+  if (p->reserved != 0) return fail(RS_EINVAL, "reserved must be 0");
   if (!(p->lr >= 0) || !(p->adam_b1 >= 0 && p->adam_b1 < 1) || !(p->adam_b2 >= 0 && p->adam_b2 < 1) ||
       !(p->adam_eps > 0))
     return fail(RS_EINVAL, "invalid Adam hyper-parameters");
@@ -254,19 +267,18 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  for (int q = 0; q < 2; ++q) {
-    TRY(ar.alloc(&n->xbar_prevT[q], NI * B));
-    TRY(ar.alloc(&n->zbar_prevT[q], NR * B));
-    TRY(ar.alloc(&n->zbar_newT[q], NR * B));
-    TRY(ar.alloc(&n->psiT[q], NR * B));
-    TRY(ar.alloc(&n->LT[q], NR * B));
-    TRY(ar.alloc(&n->deltaT[q], K * B));
-  }
+  n->K = prm->trace_block ? (int)prm->trace_block : 8;
+  n->nslot = 2 * n->K;
+  const size_t NS = (size_t)n->nslot;
+  TRY(ar.alloc(&n->xbar_prevT, NI * NS * B));
+  TRY(ar.alloc(&n->zbar_prevT, NR * NS * B));
+  TRY(ar.alloc(&n->zbar_newT, NR * NS * B));
+  TRY(ar.alloc(&n->psiT, NR * NS * B));
+  TRY(ar.alloc(&n->LT, NR * NS * B));
+  TRY(ar.alloc(&n->deltaT, K * NS * B));
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
-  for (int q = 0; q < 2; ++q) {
-    HIP_OK(hipEventCreateWithFlags(&n->ev_fwd[q], hipEventDisableTiming));
-    HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
-  }
+  HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
+  for (int q = 0; q < 2; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_back, hipEventDisableTiming));
   TRY(ar.alloc(&n->z, B * NR));
@@ -292,14 +304,14 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   launch_dense_init(s, seed, 2, (int)K, (int)NR, (double)prm->sigma_out, n->Wout);
   if (prm->deepr_mask & 1) launch_deepr_bits_init(s, seed, n->in);
   if (prm->deepr_mask & 2) launch_deepr_bits_init(s, seed, n->rec);
+  launch_octant_perm(s, n->in);
+  launch_octant_perm(s, n->rec);
   zero_proj_state(s, n->in, B);
   zero_proj_state(s, n->rec, B);
   for (double* q : {n->V, n->A, n->zbar}) launch_fill_zero(s, q, B * NR * 8);
-  for (int b = 0; b < 2; ++b) {
-    for (float* q : {n->psiT[b], n->LT[b], n->zbar_prevT[b], n->zbar_newT[b]}) launch_fill_zero(s, q, B * NR * 4);
-    launch_fill_zero(s, n->xbar_prevT[b], B * NI * 4);
-    launch_fill_zero(s, n->deltaT[b], B * K * 4);
-  }
+  for (float* q : {n->psiT, n->LT, n->zbar_prevT, n->zbar_newT}) launch_fill_zero(s, q, B * NR * NS * 4);
+  launch_fill_zero(s, n->xbar_prevT, B * NI * NS * 4);
+  launch_fill_zero(s, n->deltaT, B * K * NS * 4);
   launch_fill_zero(s, n->xbar, B * NI * 8);
   launch_fill_zero(s, n->Y, B * K * 8);
   launch_fill_zero(s, n->z, B * NR);
@@ -354,18 +366,22 @@ void do_rewire(rs_eprop* n, int proj, hipStream_t s) {
   ProjDev& P = proj == 0 ? n->in : n->rec;
   n->timer.begin(s, 3);
   launch_deepr(s, n->p.seed, P, n->B, n->step, n->rw_stats);
+  launch_octant_perm(s, P);
   n->timer.end(s);
 }
 
-// One timestep.  The forward kernel runs on the caller's stream, the e-prop
-// kernel on the side stream; buffer set q = step parity carries the hand-off.
-void do_step(rs_eprop* n, uint32_t flags) {
+// Run the open block (steps accumulated since the last flush): one forward
+// launch for all its steps on the caller's stream, writing ring half
+// blk_half, then the e-prop launch on the side stream.  The forward pass of
+// the next block (other half) overlaps this e-prop launch; a half is reused
+// only after the e-prop launch that read it has finished.
+void flush_block(rs_eprop* n) {
+  if (n->blk_n == 0) return;
   hipStream_t s = n->stream, e = n->side;
-  const int t_local = (int)(n->step % n->p.sample_steps);
-  const int q = (int)(n->step & 1);
-  if (n->ep_pending[q]) {  // e-prop two steps back still reads set q
-    (void)hipStreamWaitEvent(s, n->ev_ep[q], 0);
-    n->ep_pending[q] = false;
+  const int h = n->blk_half;
+  if (n->ep_pending[h]) {
+    (void)hipStreamWaitEvent(s, n->ev_ep[h], 0);
+    n->ep_pending[h] = false;
   }
   FwdArgs f{};
   f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
@@ -373,38 +389,62 @@ void do_step(rs_eprop* n, uint32_t flags) {
   f.psi_scale = 0.3 / (double)n->p.v_thr;
   f.V = n->V; f.A = n->A; f.Y = n->Y;
   f.xbar = n->xbar; f.zbar = n->zbar;
-  f.xbar_prevT = n->xbar_prevT[q]; f.zbar_prevT = n->zbar_prevT[q]; f.zbar_newT = n->zbar_newT[q];
-  f.psiT = n->psiT[q]; f.LT = n->LT[q]; f.deltaT = n->deltaT[q]; f.z = n->z;
+  f.xbar_prevT = n->xbar_prevT; f.zbar_prevT = n->zbar_prevT; f.zbar_newT = n->zbar_newT;
+  f.psiT = n->psiT; f.LT = n->LT; f.deltaT = n->deltaT; f.z = n->z;
+  f.slot = h * n->K; f.nslot = n->nslot;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
   f.Wout = n->Wout; f.bout = n->bout;
-  f.x_off = n->x_off; f.x_idx = n->x_idx; f.t_local = t_local; f.labels = n->labels;
+  f.x_off = n->x_off; f.x_idx = n->x_idx;
+  f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
+  f.labels = n->labels;
   f.counters = n->counters;
   n->timer.begin(s, 0);
   launch_fwd(s, f);
   n->timer.end(s);
-  (void)hipEventRecord(n->ev_fwd[q], s);
-  if (flags & RS_LEARN) {
+  n->last_slot = h * n->K + n->blk_n - 1;
+  (void)hipEventRecord(n->ev_fwd, s);
+  (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
+  if (n->blk_learn) {
     EpropArgs a{};
-    a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B; a.alif = n->p.alif ? 1 : 0;
-    a.alpha = n->alpha; a.rho = n->rho; a.beta = n->beta;
+    a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B;
+    a.alif = n->p.alif ? 1 : 0;
+    a.alpha = (float)n->alpha; a.rho = (float)n->rho; a.beta = (float)n->beta;
+    a.one_m_rho = (float)(1.0 - n->rho);
     a.in = n->in; a.rec = n->rec;
-    a.xbar_prev = n->xbar_prevT[q]; a.zbar_prev = n->zbar_prevT[q]; a.zbar_new = n->zbar_newT[q];
-    a.psiT = n->psiT[q]; a.LT = n->LT[q]; a.deltaT = n->deltaT[q];
+    a.xbar_prev = n->xbar_prevT; a.zbar_prev = n->zbar_prevT; a.zbar_new = n->zbar_newT;
+    a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
+    a.slot0 = h * n->K; a.nsteps = n->blk_n; a.nslot = n->nslot;
     a.Gout = n->Gout; a.Gb = n->Gb;
-    (void)hipStreamWaitEvent(e, n->ev_fwd[q], 0);
     n->timer.begin(e, 1);
     launch_eprop(e, a);
     n->timer.end(e);
-    (void)hipEventRecord(n->ev_ep[q], e);
-    n->ep_pending[q] = true;
+    (void)hipEventRecord(n->ev_ep[h], e);
+    n->ep_pending[h] = true;
   }
+  n->blk_half ^= 1;
+  n->blk_n = 0;
+}
+
+// One timestep joins the open block; a full block, an update/rewire or a
+// sample boundary runs it.
+void do_step(rs_eprop* n, uint32_t flags) {
+  hipStream_t s = n->stream, e = n->side;
+  const bool learn = (flags & RS_LEARN) != 0;
+  if (n->blk_n > 0 && learn != n->blk_learn) flush_block(n);
+  if (n->blk_n == 0) {
+    n->blk_learn = learn;
+    n->blk_t0 = n->step;
+  }
+  n->blk_n += 1;
   n->step += 1;
+  if (n->blk_n == n->K) flush_block(n);
   const bool upd = (flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0;
   const bool rst = (flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0;
   if (upd || rst) {
-    // after this step's forward (and e-prop, queued first on the side stream)
-    (void)hipStreamWaitEvent(e, n->ev_fwd[q], 0);
+    flush_block(n);
+    (void)hipEventRecord(n->ev_fwd, s);  // side stream after the last forward launch
+    (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
     if (upd) {
       do_update(n, e);
       if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
@@ -423,11 +463,12 @@ void do_step(rs_eprop* n, uint32_t flags) {
 struct VarRef {
   void* ptr;
   size_t bytes;
+  size_t rows = 0, pitch = 0;  // strided ring slot: rows of bytes/rows, pitch apart
 };
 
 bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
   const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in, K = n->p.n_out;
-  const int last = (int)((n->step + 1) & 1);  // buffer set written by the last step
+  const size_t slot_off = (size_t)n->last_slot * B * 4, pitch = (size_t)n->nslot * B * 4;
   const int pj = var / 0x100 - 1, f = var % 0x100;
   if (var < 0x100) {
     switch (var) {
@@ -436,9 +477,9 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_Y: *r = {n->Y, B * K * 8}; return true;
       case RS_XBAR: *r = {n->xbar, NI * B * 8}; return true;
       case RS_ZBAR: *r = {n->zbar, NR * B * 8}; return true;
-      case RS_PSI: *r = {n->psiT[last], NR * B * 4}; return !for_write;
-      case RS_LSIG: *r = {n->LT[last], NR * B * 4}; return !for_write;
-      case RS_DELTA: *r = {n->deltaT[last], K * B * 4}; return !for_write;
+      case RS_PSI: *r = {(char*)n->psiT + slot_off, NR * B * 4, NR, pitch}; return !for_write;
+      case RS_LSIG: *r = {(char*)n->LT + slot_off, NR * B * 4, NR, pitch}; return !for_write;
+      case RS_DELTA: *r = {(char*)n->deltaT + slot_off, K * B * 4, K, pitch}; return !for_write;
       case RS_Z: *r = {n->z, B * NR}; return !for_write;
       case RS_WOUT: *r = {n->Wout, K * NR * 4}; return true;
       case RS_BOUT: *r = {n->bout, K * 4}; return true;
@@ -524,6 +565,7 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   HIP_OK(hipEventRecord(n->ev_join, n->stream));  // side stream follows earlier caller work
   HIP_OK(hipStreamWaitEvent(n->side, n->ev_join, 0));
   for (uint32_t q = 0; q < n_steps; ++q) do_step(n, flags);
+  flush_block(n);
   HIP_OK(hipEventRecord(n->ev_back, n->side));     // caller's stream covers all of it
   HIP_OK(hipStreamWaitEvent(n->stream, n->ev_back, 0));
   HIP_OK(hipGetLastError());
@@ -568,7 +610,12 @@ rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
   VarRef r;
   if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
-  HIP_OK(hipMemcpyAsync(host, r.ptr, bytes, hipMemcpyDeviceToHost, n->stream));
+  if (r.rows) {
+    const size_t w = bytes / r.rows;
+    HIP_OK(hipMemcpy2DAsync(host, w, r.ptr, r.pitch, w, r.rows, hipMemcpyDeviceToHost, n->stream));
+  } else {
+    HIP_OK(hipMemcpyAsync(host, r.ptr, bytes, hipMemcpyDeviceToHost, n->stream));
+  }
   HIP_OK(hipStreamSynchronize(n->stream));
   return RS_OK;
 }
@@ -603,6 +650,7 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
   }
   HIP_OK(hipStreamSynchronize(n->stream));
   HIP_OK(hipMemcpyAsync(r.ptr, host, bytes, hipMemcpyHostToDevice, n->stream));
+  if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) launch_octant_perm(n->stream, pj == 0 ? n->in : n->rec);
   HIP_OK(hipStreamSynchronize(n->stream));
   return RS_OK;
 }
@@ -648,7 +696,7 @@ void rs_eprop_destroy(rs_eprop* n) {
   (void)hipStreamSynchronize(n->stream);
   if (n->side) (void)hipStreamSynchronize(n->side);
   n->timer.destroy();
-  for (hipEvent_t ev : {n->ev_fwd[0], n->ev_fwd[1], n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back})
+  for (hipEvent_t ev : {n->ev_fwd, n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back})
     if (ev) (void)hipEventDestroy(ev);
   if (n->side) (void)hipStreamDestroy(n->side);
   n->arena.release();

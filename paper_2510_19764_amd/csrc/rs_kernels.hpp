@@ -20,6 +20,12 @@ struct ProjDev {
   uint32_t* sign;    // [n_pre*words] DEEP R sign bits, may be null
   int* dormant;      // [n_pre] eliminated per row by the last rewire
   int* assigned;     // [n_pre] activations per row of the last formation
+  // Target-octant view for the e-prop kernel: perm[i*cap + q] lists the row's
+  // slots grouped by target octant (j / oct_size), octant o occupying
+  // q in [oct_off[i*9+o], oct_off[i*9+o+1]).  Rebuilt whenever rows change.
+  int* perm;         // [n_pre*cap], may be null
+  int* oct_off;      // [n_pre*9]
+  int oct_size;
 };
 
 // ---------------------------------------------------------------- build
@@ -37,31 +43,41 @@ struct FwdArgs {
   double psi_scale;                          // 0.3 / v_thr
   double* V; double* A; double* Y;           // [B][n_rec], [B][n_rec], [B][n_out]
   double* xbar; double* zbar;                // [B][n_in], [B][n_rec] trace masters
-  float* xbar_prevT;                         // [n_in][B]  trace before this step's input
-  float* zbar_prevT; float* zbar_newT;       // [n_rec][B] before / after this step's spikes
-  float* psiT; float* LT;                    // [n_rec][B]
-  float* deltaT;                             // [n_out][B]
+  // hand-off ring [n][nslot][B]; this step writes slot `slot`
+  float* xbar_prevT;                         // n = n_in: trace before this step's input
+  float* zbar_prevT; float* zbar_newT;       // n = n_rec: before / after this step's spikes
+  float* psiT; float* LT;                    // n = n_rec
+  float* deltaT;                             // n = n_out
+  int slot, nslot;
   uint8_t* z;                                // [B][n_rec]
   const int* len_in; const int* ind_in; const float* w_in; int cap_in;
   const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
   const float* Wout; const float* bout;      // [n_out][n_rec], [n_out]
-  const int* x_off; const int* x_idx; int t_local;
+  const int* x_off; const int* x_idx;
+  int t0, sample_steps, nsteps;              // steps t0 .. t0+nsteps-1 (raster step t % sample_steps)
+  int wout_lds;                              // 1: stage W_out in LDS for the block
+  int xcap;                                  // LDS capacity for the block's input spike lists
   const int* labels;
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
 };
+// One launch runs `nsteps` consecutive steps; step tau writes ring slot slot + tau.
 void launch_fwd(hipStream_t s, const FwdArgs& a);
 
 struct EpropArgs {
   int n_in, n_rec, n_out, B, alif;
-  double alpha, rho, beta;
+  float alpha, rho, beta;   // eligibility arithmetic is float; state is float
+  float one_m_rho;          // 1 - rho, so the slow eps decay carries no rounding bias
   ProjDev in, rec;
-  const float* xbar_prev;   // [n_in][B]  presynaptic traces before this step's spikes
-  const float* zbar_prev;   // [n_rec][B]
-  const float* zbar_new;    // [n_rec][B]  after this step (readout gradient)
+  // hand-off ring [n][nslot][B]; this launch applies steps slot0 .. slot0+nsteps-1
+  const float* xbar_prev;   // n_in: presynaptic traces before each step's spikes
+  const float* zbar_prev;   // n_rec
+  const float* zbar_new;    // n_rec: after each step (readout gradient)
   const float* psiT; const float* LT; const float* deltaT;
+  int slot0, nsteps, nslot;
   float* Gout; float* Gb;
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+void launch_octant_perm(hipStream_t s, const ProjDev& P);
 
 // ---------------------------------------------------------------- update
 struct UpdateArgs {

@@ -221,3 +221,53 @@ def test_error_paths():
     buf = np.zeros(3, np.float32)
     code = rb.lib().rs_eprop_get(net._h, rb.V, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes)
     assert code == rb.RS_ECAPACITY
+
+
+@pytest.mark.parametrize("name", ["alif-b64-wide", "lif-b256-wide", "alif-b3-narrow", "alif-b320-chunked"])
+def test_trace_block_length_is_bit_invariant(name):
+    """Applying eligibility updates in blocks of K steps gives bit-identical
+    state for every K, across update/rewire boundaries and uneven step calls."""
+    base, rate = CASES[name]
+    snaps = {}
+    for K in (1, 3, 8):
+        cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": K, "update_interval": 25})
+        net = rb.EpropNet(cfg)
+        rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
+        raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+        labels = np.random.default_rng(cfg.seed).integers(0, cfg.n_out, cfg.batch).astype(np.int32)
+        net.set_input(*gpu_input(raster, labels))
+        flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+        for n in (7, 1, 30, 13, 9):   # 60 steps in uneven calls
+            net.step(n, flags)
+        snaps[K] = snapshot(net)
+        net.close()
+    ref = snaps[1]
+    for K in (3, 8):
+        s = snaps[K]
+        for k in ("v", "a", "y", "xbar", "zbar", "psiT", "LT", "deltaT", "z", "Wout", "bout", "Gout", "Gb"):
+            assert np.array_equal(s[k], ref[k]), (K, k)
+        for tag in ("in", "rec"):
+            for k in ref[tag]:
+                assert np.array_equal(s[tag][k], ref[tag][k]), (K, tag, k)
+
+
+@pytest.mark.parametrize("name", ["alif-b64-wide", "lif-b256-wide"])
+def test_lockstep_in_blocks_of_8(name):
+    base, rate = CASES[name]
+    cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": 8})
+    net = rb.EpropNet(cfg)
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
+    raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+    labels = np.random.default_rng(cfg.seed).integers(0, cfg.n_out, cfg.batch).astype(np.int32)
+    net.set_input(*gpu_input(raster, labels))
+    N = oracle_net(snapshot(net), cfg)
+    t = 0
+    for blk in range(12):
+        net.step(8, rb.RS_LEARN)
+        for _ in range(8):
+            idx, off = raster.step_lists(t)
+            N.step(idx, off, labels)
+            t += 1
+        snap = snapshot(net)
+        assert np.array_equal(snap["z"], N.z), f"spikes differ in block {blk}"
+        compare_state(snap, N, cfg)
