@@ -75,7 +75,7 @@ typedef struct rs_eprop_params {
   uint32_t sample_steps;     /* steps per presented sample; state resets after each */
   uint64_t seed;
   uint32_t trace_block;      /* steps whose eligibility updates one launch applies
-                                together, 1..32 (0 = 8); results do not depend on it */
+                                together, 1..32 (0 = 16); results do not depend on it */
   uint32_t reserved;         /* must be 0 */
 } rs_eprop_params;
 
@@ -95,11 +95,14 @@ rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_ep
 
 /* Attach the input of one sample batch: a compressed raster of
  * params->sample_steps steps.  Device pointers: off int32[sample_steps*batch+1],
- * idx int32[off[last]] with the channels of instance b at step t in
+ * idx int32[n_idx] with the channels of instance b at step t in
  * idx[off[t*batch+b] .. off[t*batch+b+1]), labels int32[batch] in [0, n_out).
  * Step t of the simulation reads raster step t % sample_steps.  The library
- * keeps the pointers (no copy).  Errors: RS_EINVAL. */
-rs_status rs_eprop_set_input(rs_eprop* net, const int32_t* off_dev, const int32_t* idx_dev,
+ * keeps the pointers (no copy, no host round trip).  Any content is memory
+ * safe: offsets are clamped to [0, n_idx], channels outside [0, n_in) are
+ * ignored and a label outside [0, n_out) gives an all-zero target.
+ * Errors: RS_EINVAL (NULL pointer). */
+rs_status rs_eprop_set_input(rs_eprop* net, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
                              const int32_t* labels_dev);
 
 /* Advance n_steps timesteps.  Each step: spikes and surrogate derivatives from
@@ -187,12 +190,13 @@ typedef struct rs_eprop_info {
 /* Synchronises the stream. */
 rs_status rs_eprop_info_get(rs_eprop* net, rs_eprop_info* out);
 
-/* Per-phase device timers (the paper's kernel timers, Sec. 2.1): when enabled,
- * HIP events bracket every kernel launch of a phase on the object's stream.
- * Phases: 0 forward (neurons, propagation, readout), 1 e-prop eligibility and
- * gradients, 2 update, 3 rewiring, 4 state reset. */
+/* Per-phase device timers (the paper's kernel timers, Sec. 2.1): HIP events
+ * bracket every kernel launch of the phases selected by `phase_mask` (bit p
+ * for phase p; 0 switches timing off).  Phases: 0 forward (neurons,
+ * propagation, readout), 1 e-prop eligibility and gradients, 2 update,
+ * 3 rewiring, 4 state reset. */
 #define RS_NUM_PHASES 5
-rs_status rs_eprop_timing(rs_eprop* net, int32_t enable);
+rs_status rs_eprop_timing(rs_eprop* net, int32_t phase_mask);
 /* Synchronises; ms[p] = total milliseconds and count[p] = launches since the
  * last call (both arrays of RS_NUM_PHASES), then clears the totals. */
 rs_status rs_eprop_phase_times(rs_eprop* net, double* ms, uint64_t* count);

@@ -92,7 +92,7 @@ def lib():
         vp, st = C.c_void_p, C.c_int32
         L.rs_last_error.restype = C.c_char_p
         L.rs_eprop_create.argtypes = [C.POINTER(_EpropParams), vp, C.POINTER(vp)]
-        L.rs_eprop_set_input.argtypes = [vp, vp, vp, vp]
+        L.rs_eprop_set_input.argtypes = [vp, vp, vp, C.c_size_t, vp]
         L.rs_eprop_step.argtypes = [vp, C.c_uint32, C.c_uint32]
         L.rs_eprop_update.argtypes = [vp]
         L.rs_eprop_rewire.argtypes = [vp, C.c_uint32, C.POINTER(_Stats)]
@@ -208,7 +208,7 @@ class EpropNet:
             assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()
         self._input_refs = (off, idx, labels)
         _check(lib().rs_eprop_set_input(self._h, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
-                                        C.c_void_p(labels.data_ptr())))
+                                        idx.numel(), C.c_void_p(labels.data_ptr())))
 
     # ---- simulation
     def step(self, n: int = 1, flags: int = RS_LEARN):
@@ -264,8 +264,10 @@ class EpropNet:
         self._info = inf
         return inf
 
-    def timing(self, enable: bool):
-        _check(lib().rs_eprop_timing(self._h, int(enable)))
+    def timing(self, enable=True):
+        """enable: True (all phases), False, or a bit mask of phases to time."""
+        mask = (1 << NUM_PHASES) - 1 if enable is True else (0 if enable is False else int(enable))
+        _check(lib().rs_eprop_timing(self._h, mask))
 
     def phase_times(self):
         ms = (C.c_double * NUM_PHASES)()

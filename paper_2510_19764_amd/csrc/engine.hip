@@ -74,7 +74,7 @@ struct Arena {
   } while (0)
 
 struct PhaseTimer {
-  bool on = false;
+  int mask = 0;  // phases being timed
   std::vector<hipEvent_t> pool;
   struct Rec { int phase; hipEvent_t a, b; };
   std::vector<Rec> open;
@@ -86,15 +86,18 @@ struct PhaseTimer {
     (void)hipEventCreate(&e);
     return e;
   }
+  bool armed = false;  // the last begin() recorded an event
   void begin(hipStream_t s, int phase) {
-    if (!on) return;
+    armed = (mask >> phase) & 1;
+    if (!armed) return;
     Rec r{phase, get(), get()};
     (void)hipEventRecord(r.a, s);
     open.push_back(r);
   }
   void end(hipStream_t s) {
-    if (!on) return;
+    if (!armed) return;
     (void)hipEventRecord(open.back().b, s);
+    armed = false;
   }
   void collect() {
     for (auto& r : open) {
@@ -144,6 +147,7 @@ struct rs_eprop {
   unsigned long long* counters = nullptr;  // [0] events, [1] spikes
   long long* rw_stats = nullptr;           // [2]
   const int32_t *x_off = nullptr, *x_idx = nullptr, *labels = nullptr;
+  long long n_idx = 0;
   uint64_t step = 0;
   uint32_t adam_k = 0;
   double alpha = 0.0, rho = 0.0, beta = 0.0;  // decay factors exp(-dt/tau) in double
@@ -267,7 +271,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  n->K = prm->trace_block ? (int)prm->trace_block : 8;
+  n->K = prm->trace_block ? (int)prm->trace_block : 16;
   n->nslot = 2 * n->K;
   const size_t NS = (size_t)n->nslot;
   TRY(ar.alloc(&n->xbar_prevT, NI * NS * B));
@@ -395,7 +399,7 @@ void flush_block(rs_eprop* n) {
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
   f.Wout = n->Wout; f.bout = n->bout;
-  f.x_off = n->x_off; f.x_idx = n->x_idx;
+  f.x_off = n->x_off; f.x_idx = n->x_idx; f.n_idx = n->n_idx;
   f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
   f.labels = n->labels;
   f.counters = n->counters;
@@ -531,29 +535,14 @@ rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_ep
   return RS_OK;
 }
 
-rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t* idx_dev,
+rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
                              const int32_t* labels_dev) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
   if (!off_dev || !idx_dev || !labels_dev) return fail(RS_EINVAL, "input pointers must not be NULL");
-  // validate the raster once: offsets non-decreasing from 0, channels and labels in range
-  const size_t n_off = (size_t)n->p.sample_steps * n->B + 1;
-  std::vector<int32_t> off(n_off), lab((size_t)n->B);
-  HIP_OK(hipStreamSynchronize(n->stream));
-  HIP_OK(hipMemcpy(off.data(), off_dev, n_off * 4, hipMemcpyDeviceToHost));
-  HIP_OK(hipMemcpy(lab.data(), labels_dev, lab.size() * 4, hipMemcpyDeviceToHost));
-  if (off[0] != 0) return fail(RS_EINVAL, "raster offsets must start at 0");
-  for (size_t q = 1; q < n_off; ++q)
-    if (off[q] < off[q - 1]) return fail(RS_EINVAL, "raster offsets decrease at %zu", q);
-  for (int32_t l : lab)
-    if (l < 0 || l >= (int32_t)n->p.n_out) return fail(RS_EINVAL, "label %d outside 0..%u", l, n->p.n_out - 1);
-  if (off[n_off - 1] > 0) {
-    std::vector<int32_t> idx((size_t)off[n_off - 1]);
-    HIP_OK(hipMemcpy(idx.data(), idx_dev, idx.size() * 4, hipMemcpyDeviceToHost));
-    for (int32_t i : idx)
-      if (i < 0 || i >= (int32_t)n->p.n_in) return fail(RS_EINVAL, "input channel %d outside 0..%u", i, n->p.n_in - 1);
-  }
+  if (n_idx > (size_t)INT32_MAX) return fail(RS_EINVAL, "index array larger than 2^31 entries");
   n->x_off = off_dev;
   n->x_idx = idx_dev;
+  n->n_idx = (long long)n_idx;
   n->labels = labels_dev;
   return RS_OK;
 }
@@ -673,9 +662,10 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   return RS_OK;
 }
 
-rs_status rs_eprop_timing(rs_eprop* n, int32_t enable) {
+rs_status rs_eprop_timing(rs_eprop* n, int32_t phase_mask) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
-  n->timer.on = enable != 0;
+  if (phase_mask < 0 || phase_mask >= (1 << RS_NUM_PHASES)) return fail(RS_EINVAL, "phase_mask out of range");
+  n->timer.mask = phase_mask;
   return RS_OK;
 }
 

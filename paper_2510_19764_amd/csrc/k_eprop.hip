@@ -89,7 +89,8 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   const int xwords = (a.n_in + 31) >> 5;
   __shared__ int s_wave[FWD_NT / WAVE];
   __shared__ unsigned long long s_events;
-  __shared__ int s_xsrc[33];
+  __shared__ int s_xsrc[33], s_xcnt[33];
+  __shared__ int s_xstaged;
 
   const int b = blockIdx.x, tid = threadIdx.x, B = a.B;
   const int lane = lane_id(), wv = tid / WAVE;
@@ -107,24 +108,27 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   if (tid <= a.nsteps) {
     const int tau = tid < a.nsteps ? tid : a.nsteps - 1;
     const int xq = ((a.t0 + tau) % a.sample_steps) * B + b;
-    s_xsrc[tid] = tid < a.nsteps ? a.x_off[xq] : 0;
-    xpos[tid] = tid < a.nsteps ? a.x_off[xq + 1] - a.x_off[xq] : 0;  // counts for now
+    // clamp the caller's offsets into the index array
+    const long long lo = min(max((long long)a.x_off[xq], 0ll), a.n_idx);
+    const long long hi = min(max((long long)a.x_off[xq + 1], lo), a.n_idx);
+    s_xsrc[tid] = tid < a.nsteps ? (int)lo : 0;
+    s_xcnt[tid] = tid < a.nsteps ? (int)(hi - lo) : 0;
   }
   __syncthreads();
-  if (tid == 0) {  // counts -> starts
-    int run = 0;
+  if (tid == 0) {  // starts of each step's list in xbuf, staged only if all fit
+    long long run = 0;
     for (int t = 0; t < a.nsteps; ++t) {
-      const int c = xpos[t];
-      xpos[t] = run;
-      run += c;
+      xpos[t] = (int)min(run, (long long)a.xcap);
+      run += s_xcnt[t];
     }
-    xpos[a.nsteps] = run;
+    xpos[a.nsteps] = (int)min(run, (long long)a.xcap);
+    s_xstaged = run <= (long long)a.xcap;
   }
   __syncthreads();
-  const bool xstaged = xpos[a.nsteps] <= a.xcap;
+  const bool xstaged = s_xstaged != 0;
   if (xstaged) {
     for (int t = wv; t < a.nsteps; t += FWD_NT / WAVE) {
-      const int n = xpos[t + 1] - xpos[t];
+      const int n = s_xcnt[t];
       for (int l = lane; l < n; l += WAVE) xbuf[xpos[t] + l] = a.x_idx[s_xsrc[t] + l];
     }
   }
@@ -175,7 +179,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     spikes += (unsigned long long)nz;
 
     // ---- input spikes of (t, b)
-    const int nx = xpos[tau + 1] - xpos[tau];
+    const int nx = s_xcnt[tau];
     const int* xs = xstaged ? xbuf + xpos[tau] : a.x_idx + s_xsrc[tau];
     for (int q = tid; q < nx; q += FWD_NT) {
       const int i = xs[q];
@@ -527,12 +531,12 @@ __global__ void __launch_bounds__(WAVE) k_eprop_oct(EpropArgs a) {
   float* __restrict__ G = P.G;
   float* __restrict__ eps = P.eps;
   float* __restrict__ ebar = P.ebar;
-  const float* __restrict__ pre = from_in ? a.xbar_prev : a.zbar_prev;
   const int B = a.B, nb4 = B / 4, T = a.nsteps;
   const int64_t base = (int64_t)i * cap;
   const bool act = lane < nb4;
-  const int lo = 4 * lane;
+  const int lo = act ? 4 * lane : 0;  // inactive lanes read instance 0, never store
   const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  const float* __restrict__ pre = (from_in ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0) + lo;
   for (int c0 = q0; c0 < q1; c0 += WAVE) {
     const bool own = c0 + lane < q1;
     const int my_s = own ? perm[base + c0 + lane] : 0;
@@ -545,30 +549,33 @@ __global__ void __launch_bounds__(WAVE) k_eprop_oct(EpropArgs a) {
       const int j1 = two ? __builtin_amdgcn_readlane(my_j, q + 1) : j0;
       const int64_t s0 = base + __builtin_amdgcn_readlane(my_s, q);
       const int64_t s1 = two ? base + __builtin_amdgcn_readlane(my_s, q + 1) : s0;
-      f4 eb0 = zero4, eb1 = zero4, ep0 = zero4, ep1 = zero4;
-      if (act) {
-        eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + lo]);
-        if (two) eb1 = __builtin_nontemporal_load((const f4*)&ebar[s1 * B + lo]);
-        if (ALIF) {
-          ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + lo]);
-          if (two) ep1 = __builtin_nontemporal_load((const f4*)&eps[s1 * B + lo]);
-        }
+      const float* __restrict__ psi0p = a.psiT + ring(a, j0, 0) + lo;
+      const float* __restrict__ L0p = a.LT + ring(a, j0, 0) + lo;
+      const float* __restrict__ psi1p = a.psiT + ring(a, j1, 0) + lo;
+      const float* __restrict__ L1p = a.LT + ring(a, j1, 0) + lo;
+      f4 eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + lo]);
+      f4 eb1 = __builtin_nontemporal_load((const f4*)&ebar[s1 * B + lo]);
+      f4 ep0 = zero4, ep1 = zero4;
+      if (ALIF) {
+        ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + lo]);
+        ep1 = __builtin_nontemporal_load((const f4*)&eps[s1 * B + lo]);
       }
+      // software pipeline over the block's steps: step tau+1's inputs are in
+      // flight while step tau is computed
+      f4 p = *(const f4*)pre, psi0 = *(const f4*)psi0p, L0 = *(const f4*)L0p;
+      f4 psi1 = *(const f4*)psi1p, L1 = *(const f4*)L1p;
       for (int tau = 0; tau < T; ++tau) {
-        float g0 = 0.f, g1 = 0.f;
-        if (act) {
-          const f4 p = *(const f4*)&pre[ring(a, i, tau) + lo];
-          const f4 psi0 = *(const f4*)&a.psiT[ring(a, j0, tau) + lo];
-          const f4 L0 = *(const f4*)&a.LT[ring(a, j0, tau) + lo];
-          const f4 psi1 = *(const f4*)&a.psiT[ring(a, j1, tau) + lo];
-          const f4 L1 = *(const f4*)&a.LT[ring(a, j1, tau) + lo];
-          g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0);
-          g1 = trace_step<ALIF>(a, psi1, L1, p, eb1, ep1);
-        }
+        const int nx = (tau + 1 < T ? tau + 1 : tau) * B;
+        const f4 pn = *(const f4*)(pre + nx), psi0n = *(const f4*)(psi0p + nx), L0n = *(const f4*)(L0p + nx);
+        const f4 psi1n = *(const f4*)(psi1p + nx), L1n = *(const f4*)(L1p + nx);
+        float g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0);
+        float g1 = trace_step<ALIF>(a, psi1, L1, p, eb1, ep1);
+        if (!act) { g0 = 0.f; g1 = 0.f; }
         g0 = wave_sum(g0);
         g1 = wave_sum(g1);
         if (lane == q) my_g += g0;
         if (two && lane == q + 1) my_g += g1;
+        p = pn; psi0 = psi0n; L0 = L0n; psi1 = psi1n; L1 = L1n;
       }
       if (act) {
         __builtin_nontemporal_store(eb0, (f4*)&ebar[s0 * B + lo]);

@@ -53,7 +53,7 @@ struct FwdArgs {
   const int* len_in; const int* ind_in; const float* w_in; int cap_in;
   const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
   const float* Wout; const float* bout;      // [n_out][n_rec], [n_out]
-  const int* x_off; const int* x_idx;
+  const int* x_off; const int* x_idx; long long n_idx;
   int t0, sample_steps, nsteps;              // steps t0 .. t0+nsteps-1 (raster step t % sample_steps)
   int wout_lds;                              // 1: stage W_out in LDS for the block
   int xcap;                                  // LDS capacity for the block's input spike lists

@@ -271,3 +271,21 @@ def test_lockstep_in_blocks_of_8(name):
         snap = snapshot(net)
         assert np.array_equal(snap["z"], N.z), f"spikes differ in block {blk}"
         compare_state(snap, N, cfg)
+
+
+def test_malformed_raster_is_memory_safe():
+    """Offsets are clamped to the index array and out-of-range channels and
+    labels are ignored by the kernels: a garbage raster cannot fault."""
+    cfg, rate = CASES["alif-b64-wide"]
+    cfg = rb.EpropConfig(**{**cfg.__dict__, "sample_steps": 20, "trace_block": 8})
+    net = rb.EpropNet(cfg)
+    rng = np.random.default_rng(0)
+    n_off = cfg.sample_steps * cfg.batch + 1
+    off = rng.integers(-50, 400, n_off).astype(np.int32)            # unsorted, negative, too large
+    idx = rng.integers(-5, cfg.n_in + 5, 300).astype(np.int32)       # some channels out of range
+    labels = rng.integers(-2, cfg.n_out + 2, cfg.batch).astype(np.int32)
+    dev = (torch.tensor(off, device="cuda"), torch.tensor(idx, device="cuda"), torch.tensor(labels, device="cuda"))
+    net.set_input(*dev)
+    net.step(20, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
+    s = snapshot(net, with_traces=True)
+    assert np.isfinite(s["v"]).all() and np.isfinite(s["rec"]["ebar"]).all()
