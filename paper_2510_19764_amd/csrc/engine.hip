@@ -134,6 +134,8 @@ struct rs_eprop {
   // the other.
   float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;
   float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
+  // the forward kernel's coalesced staging of one block, [tau][B][n]
+  float *stg[6] = {};
   int K = 8, nslot = 16;
   int blk_half = 0, blk_n = 0, last_slot = 0;
   uint64_t blk_t0 = 0;
@@ -280,6 +282,11 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->psiT, NR * NS * B));
   TRY(ar.alloc(&n->LT, NR * NS * B));
   TRY(ar.alloc(&n->deltaT, K * NS * B));
+  {
+    const size_t KB = (size_t)n->K * B;
+    const size_t dims[6] = {NI, NR, NR, NR, NR, K};  // xbar_prev, zbar_prev, zbar_new, psi, L, delta
+    for (int q = 0; q < 6; ++q) TRY(ar.alloc(&n->stg[q], KB * dims[q]));
+  }
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
   for (int q = 0; q < 2; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
@@ -393,9 +400,8 @@ void flush_block(rs_eprop* n) {
   f.psi_scale = 0.3 / (double)n->p.v_thr;
   f.V = n->V; f.A = n->A; f.Y = n->Y;
   f.xbar = n->xbar; f.zbar = n->zbar;
-  f.xbar_prevT = n->xbar_prevT; f.zbar_prevT = n->zbar_prevT; f.zbar_newT = n->zbar_newT;
-  f.psiT = n->psiT; f.LT = n->LT; f.deltaT = n->deltaT; f.z = n->z;
-  f.slot = h * n->K; f.nslot = n->nslot;
+  f.xbar_prev = n->stg[0]; f.zbar_prev = n->stg[1]; f.zbar_new = n->stg[2];
+  f.psi = n->stg[3]; f.L = n->stg[4]; f.delta = n->stg[5]; f.z = n->z;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
   f.Wout = n->Wout; f.bout = n->bout;
@@ -405,6 +411,12 @@ void flush_block(rs_eprop* n) {
   f.counters = n->counters;
   n->timer.begin(s, 0);
   launch_fwd(s, f);
+  HandoffArrays ho{};
+  float* dst[6] = {n->xbar_prevT, n->zbar_prevT, n->zbar_newT, n->psiT, n->LT, n->deltaT};
+  const int dims[6] = {(int)n->p.n_in, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec,
+                       (int)n->p.n_out};
+  for (int q = 0; q < 6; ++q) { ho.src[q] = n->stg[q]; ho.dst[q] = dst[q]; ho.n[q] = dims[q]; }
+  launch_handoff_transpose(s, ho, n->B, n->blk_n, h * n->K, n->nslot);
   n->timer.end(s);
   n->last_slot = h * n->K + n->blk_n - 1;
   (void)hipEventRecord(n->ev_fwd, s);

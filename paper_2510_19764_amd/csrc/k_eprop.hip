@@ -154,7 +154,6 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   __syncthreads();
 
   for (int tau = 0; tau < a.nsteps; ++tau) {
-    const int slot = a.slot + tau;
     for (int q = tid; q < xwords; q += FWD_NT) xflags[q] = 0u;
     // ---- spikes, surrogate derivative, ordered compaction of the spike list
     int nz = 0;
@@ -167,7 +166,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
         const double thr = a.v_thr + a.beta * ar[it];
         z = vr[it] >= thr;
         const double h = 1.0 - fabs(vr[it] - thr) / a.v_thr;
-        a.psiT[((int64_t)j * a.nslot + slot) * B + b] = (float)(a.psi_scale * fmax(h, 0.0));
+        a.psi[((int64_t)tau * B + b) * a.n_rec + j] = (float)(a.psi_scale * fmax(h, 0.0));
         acc[j] = 0ll;
       }
       zr[it] = z;
@@ -218,10 +217,10 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
         const double zf = zr[it] ? 1.0 : 0.0;
         vr[it] = a.alpha * (vr[it] - zf * a.v_thr) + I;
         ar[it] = a.rho * ar[it] + zf;
-        const int64_t q = ((int64_t)j * a.nslot + slot) * B + b;
-        a.zbar_prevT[q] = (float)zbr[it];
+        const int64_t q = ((int64_t)tau * B + b) * a.n_rec + j;
+        a.zbar_prev[q] = (float)zbr[it];
         zbr[it] = a.alpha * zbr[it] + zf;
-        a.zbar_newT[q] = (float)zbr[it];
+        a.zbar_new[q] = (float)zbr[it];
       }
     }
 #pragma unroll
@@ -230,7 +229,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       const int i = it * FWD_NT + tid;
       if (i < a.n_in) {
         const double x = ((xflags[i >> 5] >> (i & 31)) & 1u) ? 1.0 : 0.0;
-        a.xbar_prevT[((int64_t)i * a.nslot + slot) * B + b] = (float)xbr[it];
+        a.xbar_prev[((int64_t)tau * B + b) * a.n_in + i] = (float)xbr[it];
         xbr[it] = a.alpha * xbr[it] + x;
       }
     }
@@ -260,7 +259,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       for (int k = lane; k < a.n_out; k += WAVE) {
         const float d = expf(ylds[k] - m) / den - (k == label ? 1.0f : 0.0f);
         dlds[k] = d;
-        a.deltaT[((int64_t)k * a.nslot + slot) * B + b] = d;
+        a.delta[((int64_t)tau * B + b) * a.n_out + k] = d;
       }
     }
     __syncthreads();
@@ -273,7 +272,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       if (j < a.n_rec) {
         float l = 0.0f;
         for (int k = 0; k < a.n_out; ++k) l += wout[(int64_t)k * a.n_rec + j] * dlds[k];
-        a.LT[((int64_t)j * a.nslot + slot) * B + b] = l;
+        a.L[((int64_t)tau * B + b) * a.n_rec + j] = l;
       }
     }
     __syncthreads();  // LDS (acc, zlist, xflags, dlds) is reused by the next step
@@ -503,6 +502,36 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_wide(EpropArgs a) {
       if (lane == 0) G[s] = gsum;
     }
   }
+}
+
+// Hand-off transpose: [tau][B][n] -> [n][nslot][B] through a 64 x 64 LDS tile
+// (both sides coalesced).  blockIdx.z = array * nsteps + tau.
+__global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B, int nsteps, int slot0,
+                                                           int nslot) {
+  __shared__ float tile[64][65];
+  const int arr = blockIdx.z / nsteps, tau = blockIdx.z % nsteps;
+  const int n = h.n[arr];
+  const int n0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+  if (n0 >= n || b0 >= B) return;
+  const float* src = h.src[arr] + (int64_t)tau * B * n;
+  float* dst = h.dst[arr];
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  for (int r = ty; r < 64; r += 4) {
+    const int b = b0 + r, j = n0 + tx;
+    tile[r][tx] = (b < B && j < n) ? src[(int64_t)b * n + j] : 0.0f;
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += 4) {
+    const int j = n0 + r, b = b0 + tx;
+    if (j < n && b < B) dst[((int64_t)j * nslot + slot0 + tau) * B + b] = tile[tx][r];
+  }
+}
+
+void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot) {
+  int nmax = 0;
+  for (int q = 0; q < 6; ++q) nmax = max(nmax, h.n[q]);
+  dim3 grid((nmax + 63) / 64, (B + 63) / 64, 6 * nsteps);
+  hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B, nsteps, slot0, nslot);
 }
 
 // XCD-aware form (B % 4 == 0, 64 <= B <= 256): workgroup w = row*8 + o takes

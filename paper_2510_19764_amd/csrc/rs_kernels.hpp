@@ -43,12 +43,11 @@ struct FwdArgs {
   double psi_scale;                          // 0.3 / v_thr
   double* V; double* A; double* Y;           // [B][n_rec], [B][n_rec], [B][n_out]
   double* xbar; double* zbar;                // [B][n_in], [B][n_rec] trace masters
-  // hand-off ring [n][nslot][B]; this step writes slot `slot`
-  float* xbar_prevT;                         // n = n_in: trace before this step's input
-  float* zbar_prevT; float* zbar_newT;       // n = n_rec: before / after this step's spikes
-  float* psiT; float* LT;                    // n = n_rec
-  float* deltaT;                             // n = n_out
-  int slot, nslot;
+  // hand-off of step tau, instance-major staging [tau][B][n] (coalesced writes):
+  float* xbar_prev;                          // n = n_in: trace before this step's input
+  float* zbar_prev; float* zbar_new;         // n = n_rec: before / after this step's spikes
+  float* psi; float* L;                      // n = n_rec
+  float* delta;                              // n = n_out
   uint8_t* z;                                // [B][n_rec]
   const int* len_in; const int* ind_in; const float* w_in; int cap_in;
   const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
@@ -60,8 +59,17 @@ struct FwdArgs {
   const int* labels;
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
 };
-// One launch runs `nsteps` consecutive steps; step tau writes ring slot slot + tau.
+// One launch runs `nsteps` consecutive steps into the staging buffers.
 void launch_fwd(hipStream_t s, const FwdArgs& a);
+
+// Move the staged hand-off of `nsteps` steps ([tau][B][n] for each of the six
+// arrays) into the e-prop ring ([n][nslot][B], slots slot0 + tau).
+struct HandoffArrays {
+  const float* src[6];
+  float* dst[6];
+  int n[6];
+};
+void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot);
 
 struct EpropArgs {
   int n_in, n_rec, n_out, B, alif;
