@@ -41,14 +41,15 @@ def classifier_config(seed=1, trace_block=16):
 def eprop_algorithmic_bytes(cfg, n_syn: int, n_launch: int, n_steps: int) -> int:
     """HBM bytes the e-prop launches must move at minimum over n_steps steps in
     n_launch launches.  Per launch and synapse: eps and ebar of every batch
-    instance read and written once (16 B per instance; 8 B for LIF), target
-    index (4 B) and gradient read and written (8 B), and the readout gradient.
+    instance read and written once (16 B per instance; 8 B for LIF), its
+    column-view entry (8 B) and gradient read and written (8 B), and the
+    readout gradient.
     Per step: each per-neuron, per-instance input read once (presynaptic
     traces before the step, psi, L, the recurrent trace after the step) and
     the output errors."""
     B = cfg.batch
     per_unit = 16 if cfg.alif else 8
-    per_launch = n_syn * (per_unit * B + 12) + 8 * cfg.n_out * cfg.n_rec + 8 * cfg.n_out
+    per_launch = n_syn * (per_unit * B + 16) + 8 * cfg.n_out * cfg.n_rec + 8 * cfg.n_out
     per_step = 4 * B * (cfg.n_in + 4 * cfg.n_rec + cfg.n_out)
     return n_launch * per_launch + n_steps * per_step
 
@@ -220,7 +221,7 @@ def main():
         "synaptic_events_per_s": round(events / elapsed, 1),
         "timesteps_per_s": round(args.steps * T / elapsed, 1),
         "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
-        "roofline": {"bound": "hbm", "kernel": "k_eprop_oct<true>", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_eprop_col<true>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
                      "trace_block": inf_k,

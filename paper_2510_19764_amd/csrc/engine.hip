@@ -126,6 +126,7 @@ struct rs_eprop {
   int B = 0;
   Arena arena;
   ProjDev in{}, rec{};
+  ColumnView cv{};                                    // target-major view of both projections
   double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
   double *xbar = nullptr, *zbar = nullptr;            // fp64 trace masters [B][n]
   // Hand-off from the forward kernel to the e-prop kernel: a ring of 2K step
@@ -173,11 +174,6 @@ rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr) {
   if (deepr) {
     TRY(ar.alloc(&P.conn, (size_t)P.n_pre * P.words));
     TRY(ar.alloc(&P.sign, (size_t)P.n_pre * P.words));
-  }
-  if (B % 4 == 0 && B >= 64 && B <= 256) {
-    TRY(ar.alloc(&P.perm, n));
-    TRY(ar.alloc(&P.oct_off, (size_t)P.n_pre * 9));
-    P.oct_size = (P.n_post + 7) / 8;
   }
   return RS_OK;
 }
@@ -302,6 +298,9 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Mb, K));
   TRY(ar.alloc(&n->Vb, K));
   TRY(ar.alloc(&n->counters, 2));
+  TRY(ar.alloc(&n->cv.cnt, NR * 8));
+  TRY(ar.alloc(&n->cv.off, NR * 8 + 1));
+  TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
   TRY(ar.alloc(&n->rw_stats, 2));
 
   for (ProjDev* P : {&n->in, &n->rec}) {  // padding slots start defined
@@ -315,8 +314,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   launch_dense_init(s, seed, 2, (int)K, (int)NR, (double)prm->sigma_out, n->Wout);
   if (prm->deepr_mask & 1) launch_deepr_bits_init(s, seed, n->in);
   if (prm->deepr_mask & 2) launch_deepr_bits_init(s, seed, n->rec);
-  launch_octant_perm(s, n->in);
-  launch_octant_perm(s, n->rec);
+  launch_columns(s, n->in, n->rec, n->cv);
   zero_proj_state(s, n->in, B);
   zero_proj_state(s, n->rec, B);
   for (double* q : {n->V, n->A, n->zbar}) launch_fill_zero(s, q, B * NR * 8);
@@ -373,11 +371,18 @@ void do_update(rs_eprop* n, hipStream_t s) {
   n->timer.end(s);
 }
 
+// The column view follows the rows after every rewire or restore; it is timed
+// with the rewire phase.
+void rebuild_columns(rs_eprop* n, hipStream_t s) {
+  n->timer.begin(s, 3);
+  launch_columns(s, n->in, n->rec, n->cv);
+  n->timer.end(s);
+}
+
 void do_rewire(rs_eprop* n, int proj, hipStream_t s) {
   ProjDev& P = proj == 0 ? n->in : n->rec;
   n->timer.begin(s, 3);
   launch_deepr(s, n->p.seed, P, n->B, n->step, n->rw_stats);
-  launch_octant_perm(s, P);
   n->timer.end(s);
 }
 
@@ -432,6 +437,7 @@ void flush_block(rs_eprop* n) {
     a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
     a.slot0 = h * n->K; a.nsteps = n->blk_n; a.nslot = n->nslot;
     a.Gout = n->Gout; a.Gb = n->Gb;
+    a.col_off = n->cv.off; a.col = n->cv.col;
     n->timer.begin(e, 1);
     launch_eprop(e, a);
     n->timer.end(e);
@@ -465,6 +471,7 @@ void do_step(rs_eprop* n, uint32_t flags) {
       do_update(n, e);
       if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
       if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
+      if (n->p.deepr_mask) rebuild_columns(n, e);
     }
     if (rst) {
       n->timer.begin(e, 4);
@@ -586,6 +593,7 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
     return fail(RS_EINVAL, "projection %u is not rewired by DEEP R", proj);
   launch_fill_zero(n->stream, n->rw_stats, 16);
   do_rewire(n, (int)proj, n->stream);
+  rebuild_columns(n, n->stream);
   HIP_OK(hipGetLastError());
   if (st) {
     long long h[2];
@@ -651,7 +659,7 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
   }
   HIP_OK(hipStreamSynchronize(n->stream));
   HIP_OK(hipMemcpyAsync(r.ptr, host, bytes, hipMemcpyHostToDevice, n->stream));
-  if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) launch_octant_perm(n->stream, pj == 0 ? n->in : n->rec);
+  if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) rebuild_columns(n, n->stream);
   HIP_OK(hipStreamSynchronize(n->stream));
   return RS_OK;
 }

@@ -10,7 +10,7 @@
 //   Input currents are accumulated as 64-bit fixed point (2^-36 resolution) so
 //   the sum does not depend on the order of the LDS atomics.
 // k_eprop_*: per-synapse eligibility traces over every batch instance and the
-//   batch-summed gradient G_ji += sum_b L_j ebar_ji; workgroups past the rows
+//   batch-summed gradient G_ji += sum_b L_j ebar_ji; the last workgroups
 //   accumulate the readout delta rule.  State is laid out batch-innermost
 //   ([slot][B], [neuron][B]) so a wave reads 64 consecutive instances.
 #include "rs_device.hpp"
@@ -343,165 +343,212 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
 // Eligibility traces and gradients over a block of steps.
 // The forward pass does not depend on the traces, so it runs ahead and leaves
 // psi, L and the presynaptic traces of every step in a ring of slots; one
-// launch then applies `nsteps` steps per synapse while its eps/ebar stay in
+// launch then applies up to COL_TB steps per synapse while its eps/ebar stay in
 // registers: the trace stream crosses HBM once per block instead of once per
-// step.  Each step rounds eps/ebar to float and adds its batch sum to G in
-// step order, so the result is bit-identical for every block length.
-// Wide form (B % 4 == 0, B >= 64): a 256-thread workgroup owns one presynaptic
-// row, wave w the slots w, w+4, ...; each lane carries four consecutive batch
-// instances, so every access of eps, ebar, psi, L and the presynaptic trace is
-// a contiguous 1 KB wave access.
+// step.  Each step rounds eps/ebar to float, so they are bit-identical for
+// every block length; the gradient is summed over the block's steps per lane
+// before the batch reduction, so G depends on the block length only through
+// float rounding.
 constexpr int EP_NT = 256;
-constexpr int EP_WAVES = EP_NT / WAVE;
-
-// One eligibility step for the four instances a lane holds (eq. eprop_elig_1/2,
-// eprop_elig_lif); returns the lane's part of sum_b L ebar.  The eps update
-// eps' = psi p + (rho - psi beta) eps is evaluated as
-// eps + (psi p - ((1 - rho) + psi beta) eps): rho is within 5e-4 of one, and a
-// float rho would shift its 2000-step decay by a systematic 3e-8 per step,
-// whereas 1 - rho in float is accurate to 3e-8 of itself.
-template <bool ALIF>
-__device__ __forceinline__ float trace_step(const EpropArgs& a, f4 psi, f4 L, f4 p, f4& eb, f4& ep) {
-  f4 e;
-  if (ALIF) {
-    e = psi * (p - a.beta * ep);
-    const f4 k = psi * a.beta + a.one_m_rho;
-    ep = ep + (psi * p - k * ep);
-  } else {
-    e = psi * p;
-  }
-  eb = a.alpha * eb + e;
-  return (L.x * eb.x + L.y * eb.y) + (L.z * eb.z + L.w * eb.w);
-}
+constexpr int COL_TB = 16;  // steps per launch of the column kernel
+constexpr int COL_OCT = 8;  // source octants, one per XCD
 
 __device__ __forceinline__ int64_t ring(const EpropArgs& a, int n, int tau) {
   return ((int64_t)n * a.nslot + a.slot0 + tau) * a.B;
 }
 
-__device__ __forceinline__ void readout_grad_wave(const EpropArgs& a, int j, int lane) {
-  const int nb4 = a.B / 4;
-  for (int tau = 0; tau < a.nsteps; ++tau) {
-    if (j < a.n_rec) {
-      for (int k = 0; k < a.n_out; ++k) {
-        float g = 0.0f;
-        for (int c = lane; c < nb4; c += WAVE) {
-          const f4 z = *(const f4*)&a.zbar_new[ring(a, j, tau) + 4 * c];
-          const f4 d = *(const f4*)&a.deltaT[ring(a, k, tau) + 4 * c];
-          g += (d.x * z.x + d.y * z.y) + (d.z * z.z + d.w * z.w);
+// Readout delta rule over the launch's steps (recurrent classifier section):
+// wave j < n_rec adds sum_t sum_b delta_k z_j to Gout[k][j] for every output
+// k, wave n_rec the bias gradient sum_t sum_b delta_k.
+__device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane) {
+  if (j > a.n_rec) return;
+  const int B = a.B, T = a.nsteps;
+  const bool wt = j < a.n_rec;
+  for (int k = 0; k < a.n_out; ++k) {
+    float g = 0.0f;
+    for (int t = 0; t < T; ++t) {
+      const float* __restrict__ d = a.deltaT + ring(a, k, t);
+      const float* __restrict__ z = a.zbar_new + ring(a, wt ? j : 0, t);
+      if (B % 4 == 0) {
+        for (int c = lane; c < B / 4; c += WAVE) {
+          const f4 d4 = *(const f4*)&d[4 * c];
+          if (wt) {
+            const f4 z4 = *(const f4*)&z[4 * c];
+            g += (d4.x * z4.x + d4.y * z4.y) + (d4.z * z4.z + d4.w * z4.w);
+          } else {
+            g += (d4.x + d4.y) + (d4.z + d4.w);
+          }
         }
-        g = wave_sum(g);
-        if (lane == 0) a.Gout[(int64_t)k * a.n_rec + j] += g;
+      } else {
+        for (int b = lane; b < B; b += WAVE) g += wt ? d[b] * z[b] : d[b];
       }
-    } else if (j == a.n_rec) {
-      for (int k = 0; k < a.n_out; ++k) {
-        float g = 0.0f;
-        for (int c = lane; c < nb4; c += WAVE) {
-          const f4 d = *(const f4*)&a.deltaT[ring(a, k, tau) + 4 * c];
-          g += (d.x + d.y) + (d.z + d.w);
-        }
-        g = wave_sum(g);
-        if (lane == 0) a.Gb[k] += g;
-      }
+    }
+    g = wave_sum(g);
+    if (lane == 0) {
+      if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
+      else a.Gb[k] += g;
     }
   }
 }
 
+// Target-major form (B >= 32).  Workgroup g = j*8 + o owns target neuron j
+// and the synapses onto it from rows r with r % 8 == o (r = i for input rows,
+// n_in + i for recurrent rows).  Workgroups are handed to the 8 XCDs
+// round-robin, so XCD o only gathers the presynaptic traces of its own eighth
+// of the rows.  Wave w takes 64-instance chunks w, w + nw, ... with one
+// instance per lane; psi_j, L_j and the eps decay factor of the block's steps
+// sit in registers, so each synapse step costs one gathered float (the
+// presynaptic trace) and six float operations (ALIF):
+//   u = psi p,  d = u - ((1 - rho) + psi beta) eps,  e = d + (1 - rho) eps,
+//   eps' = eps + d,  ebar' = alpha ebar + e,  g += L ebar'
+// which is e = psi (p - beta eps) and eps' = psi p + (rho - psi beta) eps of
+// eq. eprop_elig_1/2 (eprop_elig_lif without eps).  rho is within 5e-4 of one:
+// carrying 1 - rho instead of a float rho keeps the slow eps decay free of a
+// systematic 3e-8 per step.  Lane sums over the steps are reduced per synapse
+// with DPP, per wave in chunk order and across waves in wave order, so the
+// result does not depend on scheduling or on the order of the column list.
 template <bool ALIF>
-__global__ void __launch_bounds__(EP_NT) k_eprop_wide(EpropArgs a) {
-  const int row = blockIdx.x, wv = threadIdx.x / WAVE, lane = lane_id();
-  const int n_rows = a.n_in + a.n_rec;
-  if (row >= n_rows) {
-    readout_grad_wave(a, (row - n_rows) * EP_WAVES + wv, lane);
+__global__ void __launch_bounds__(EP_NT) k_eprop_col(EpropArgs a) {
+  __shared__ float gpart[EP_NT / WAVE][WAVE];
+  const int wv = threadIdx.x / WAVE, lane = lane_id();
+  const int nw = blockDim.x / WAVE;
+  const int ncol = a.n_rec * COL_OCT;
+  const int wg = blockIdx.x;
+  if (wg >= ncol) {
+    readout_grad(a, (wg - ncol) * nw + wv, lane);
     return;
   }
-  const bool from_in = row < a.n_in;
-  const int i = from_in ? row : row - a.n_in;
-  const int cap = from_in ? a.in.cap : a.rec.cap;
-  const int n = from_in ? a.in.len[i] : a.rec.len[i];
-  const int* __restrict__ ind = from_in ? a.in.ind : a.rec.ind;
-  float* __restrict__ G = from_in ? a.in.G : a.rec.G;
-  float* __restrict__ eps = from_in ? a.in.eps : a.rec.eps;
-  float* __restrict__ ebar = from_in ? a.in.ebar : a.rec.ebar;
-  const float* __restrict__ pre = from_in ? a.xbar_prev : a.zbar_prev;
-  const int B = a.B, nb4 = B / 4, T = a.nsteps;
-  const int64_t base = (int64_t)i * cap;
-  const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
-  if (nb4 <= WAVE) {
-    // lane q of wave wv holds the target index and gradient of slot
-    // wv + 4(c0 + q); synapses go two at a time, every load issued up front
-    const bool act = lane < nb4;
-    const int lo = 4 * lane;
-    for (int c0 = 0; wv + 4 * c0 < n; c0 += WAVE) {
-      const int kl = wv + 4 * (c0 + lane);
-      const bool own = kl < n;
-      const int my_j = own ? ind[base + kl] : 0;
-      float my_g = own ? G[base + kl] : 0.0f;
-      const int cnt = min(WAVE, (n - wv - 4 * c0 + 3) / 4);
-      for (int q = 0; q < cnt; q += 2) {
-        const bool two = q + 1 < cnt;
-        const int j0 = __builtin_amdgcn_readlane(my_j, q);
-        const int j1 = two ? __builtin_amdgcn_readlane(my_j, q + 1) : j0;
-        const int64_t s0 = base + wv + 4 * (c0 + q), s1 = two ? s0 + 4 : s0;
-        f4 eb0 = zero4, eb1 = zero4, ep0 = zero4, ep1 = zero4;
-        if (act) {
-          eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + lo]);
-          if (two) eb1 = __builtin_nontemporal_load((const f4*)&ebar[s1 * B + lo]);
-          if (ALIF) {
-            ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + lo]);
-            if (two) ep1 = __builtin_nontemporal_load((const f4*)&eps[s1 * B + lo]);
+  const int j = wg / COL_OCT;
+  const int q0 = a.col_off[wg], q1 = a.col_off[wg + 1];
+  const int B = a.B, T = a.nsteps, n_ic = (B + WAVE - 1) / WAVE;
+  const float alpha = a.alpha, omr = a.one_m_rho, beta = a.beta;
+  for (int sc = q0; sc < q1; sc += WAVE) {  // uniform over the workgroup
+    const int ns = min(WAVE, q1 - sc);
+    float my_g = 0.0f;  // lane k: this wave's part of the gradient of entry sc + k
+    for (int ic = wv; ic < n_ic; ic += nw) {
+      const int b = ic * WAVE + lane;
+      const bool act = b < B;
+      const int bb = act ? b : 0;  // idle lanes read instance 0 and never store
+      float psi[COL_TB], L[COL_TB], c[COL_TB];
+      const float* __restrict__ pj = a.psiT + ring(a, j, 0) + bb;
+      const float* __restrict__ lj = a.LT + ring(a, j, 0) + bb;
+#pragma unroll
+      for (int t = 0; t < COL_TB; ++t) {
+        const int tt = t < T ? t : T - 1;  // loads stay inside the block
+        psi[t] = pj[(int64_t)tt * B];
+        L[t] = act ? lj[(int64_t)tt * B] : 0.0f;
+        c[t] = ALIF ? fmaf(psi[t], beta, omr) : 0.0f;
+      }
+      for (int k = 0; k < ns; ++k) {
+        const int2 ent = a.col[sc + k];
+        const bool fin = ent.x < a.n_in;
+        const int i = fin ? ent.x : ent.x - a.n_in;
+        const float* __restrict__ pre = (fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0) + bb;
+        const int64_t rec = (int64_t)ent.y * B + bb;
+        float* __restrict__ ebp = (fin ? a.in.ebar : a.rec.ebar) + rec;
+        float* __restrict__ epp = ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : nullptr;
+        float p[COL_TB];
+#pragma unroll
+        for (int t = 0; t < COL_TB; ++t) p[t] = pre[(int64_t)(t < T ? t : T - 1) * B];
+        float eb = __builtin_nontemporal_load(ebp);
+        float ep = ALIF ? __builtin_nontemporal_load(epp) : 0.0f;
+        float g = 0.0f;
+#pragma unroll
+        for (int t = 0; t < COL_TB; ++t) {
+          if (t < T) {
+            const float u = psi[t] * p[t];
+            if (ALIF) {
+              const float d = fmaf(-c[t], ep, u);
+              const float e = fmaf(omr, ep, d);
+              ep = ep + d;
+              eb = fmaf(alpha, eb, e);
+            } else {
+              eb = fmaf(alpha, eb, u);
+            }
+            g = fmaf(L[t], eb, g);
           }
-        }
-        for (int tau = 0; tau < T; ++tau) {
-          float g0 = 0.f, g1 = 0.f;
-          if (act) {
-            const f4 p = *(const f4*)&pre[ring(a, i, tau) + lo];
-            const f4 psi0 = *(const f4*)&a.psiT[ring(a, j0, tau) + lo];
-            const f4 L0 = *(const f4*)&a.LT[ring(a, j0, tau) + lo];
-            const f4 psi1 = *(const f4*)&a.psiT[ring(a, j1, tau) + lo];
-            const f4 L1 = *(const f4*)&a.LT[ring(a, j1, tau) + lo];
-            g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0);
-            g1 = trace_step<ALIF>(a, psi1, L1, p, eb1, ep1);
-          }
-          g0 = wave_sum(g0);
-          g1 = wave_sum(g1);
-          if (lane == q) my_g += g0;
-          if (two && lane == q + 1) my_g += g1;
         }
         if (act) {
-          __builtin_nontemporal_store(eb0, (f4*)&ebar[s0 * B + lo]);
-          if (ALIF) __builtin_nontemporal_store(ep0, (f4*)&eps[s0 * B + lo]);
-          if (two) {
-            __builtin_nontemporal_store(eb1, (f4*)&ebar[s1 * B + lo]);
-            if (ALIF) __builtin_nontemporal_store(ep1, (f4*)&eps[s1 * B + lo]);
-          }
+          __builtin_nontemporal_store(eb, ebp);
+          if (ALIF) __builtin_nontemporal_store(ep, epp);
         }
+        const float gs = wave_sum(g);
+        if (lane == k) my_g += gs;
       }
-      if (own) G[base + kl] = my_g;
     }
-  } else {
-    // more than 256 instances: lanes loop over 256-instance chunks
-    for (int k = wv; k < n; k += EP_WAVES) {
-      const int64_t s = base + k;
-      const int j = ind[s];
-      float gsum = G[s];
-      float gstep[32];
-      for (int tau = 0; tau < T; ++tau) gstep[tau] = 0.0f;
-      for (int c = lane; c < nb4; c += WAVE) {
-        f4 eb = __builtin_nontemporal_load((const f4*)&ebar[s * B + 4 * c]);
-        f4 ep = ALIF ? __builtin_nontemporal_load((const f4*)&eps[s * B + 4 * c]) : zero4;
-        for (int tau = 0; tau < T; ++tau) {
-          const f4 p = *(const f4*)&pre[ring(a, i, tau) + 4 * c];
-          const f4 psi = *(const f4*)&a.psiT[ring(a, j, tau) + 4 * c];
-          const f4 L = *(const f4*)&a.LT[ring(a, j, tau) + 4 * c];
-          gstep[tau] += trace_step<ALIF>(a, psi, L, p, eb, ep);
-        }
-        __builtin_nontemporal_store(eb, (f4*)&ebar[s * B + 4 * c]);
-        if (ALIF) __builtin_nontemporal_store(ep, (f4*)&eps[s * B + 4 * c]);
-      }
-      for (int tau = 0; tau < T; ++tau) gsum += wave_sum(gstep[tau]);
-      if (lane == 0) G[s] = gsum;
+    gpart[wv][lane] = my_g;
+    __syncthreads();
+    if ((int)threadIdx.x < ns) {
+      const int2 ent = a.col[sc + threadIdx.x];
+      float gsum = 0.0f;
+      for (int w = 0; w < nw; ++w) gsum += gpart[w][threadIdx.x];
+      float* G = ent.x < a.n_in ? a.in.G : a.rec.G;
+      G[ent.y] += gsum;
     }
+    __syncthreads();
   }
+}
+
+// Column view of both projections for k_eprop_col: entries
+// col[col_off[j*8+o] .. col_off[j*8+o+1]) are (r, slot) of every synapse of a
+// row r with r % 8 == o onto target j.  Rebuilt whenever rows change; the
+// order inside a list is arbitrary.
+__global__ void __launch_bounds__(WAVE) k_col_count(ProjDev in, ProjDev rec, int* cnt) {
+  const int r = blockIdx.x;
+  const bool fin = r < in.n_pre;
+  const ProjDev& P = fin ? in : rec;
+  const int i = fin ? r : r - in.n_pre;
+  const int n = P.len[i];
+  const int64_t base = (int64_t)i * P.cap;
+  for (int k = lane_id(); k < n; k += WAVE) atomicAdd(&cnt[P.ind[base + k] * COL_OCT + (r & 7)], 1);
+}
+
+// Exclusive scan of n counts (one workgroup): off[0..n]; cnt becomes the fill
+// cursor (= off).
+__global__ void __launch_bounds__(1024) k_col_scan(int* cnt, int* off, int n) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (n + 1023) / 1024;
+  const int lo = min(t * per, n), hi = min(lo + per, n);
+  int s = 0;
+  for (int q = lo; q < hi; ++q) s += cnt[q];
+  part[t] = s;
+  __syncthreads();
+  for (int d = 1; d < 1024; d <<= 1) {  // inclusive Hillis-Steele scan
+    const int v = t >= d ? part[t - d] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = t ? part[t - 1] : 0;
+  for (int q = lo; q < hi; ++q) {
+    const int c = cnt[q];
+    off[q] = run;
+    cnt[q] = run;
+    run += c;
+  }
+  if (t == 1023) off[n] = part[1023];
+}
+
+__global__ void __launch_bounds__(WAVE) k_col_fill(ProjDev in, ProjDev rec, int* cur, int2* col) {
+  const int r = blockIdx.x;
+  const bool fin = r < in.n_pre;
+  const ProjDev& P = fin ? in : rec;
+  const int i = fin ? r : r - in.n_pre;
+  const int n = P.len[i];
+  const int64_t base = (int64_t)i * P.cap;
+  for (int k = lane_id(); k < n; k += WAVE) {
+    const int pos = atomicAdd(&cur[P.ind[base + k] * COL_OCT + (r & 7)], 1);
+    col[pos] = make_int2(r, (int)(base + k));
+  }
+}
+
+void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const ColumnView& cv) {
+  const int n = rec.n_post * COL_OCT;
+  launch_fill_zero(s, cv.cnt, (size_t)n * 4);
+  hipLaunchKernelGGL(k_col_count, dim3(in.n_pre + rec.n_pre), dim3(WAVE), 0, s, in, rec, cv.cnt);
+  hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, s, cv.cnt, cv.off, n);
+  hipLaunchKernelGGL(k_col_fill, dim3(in.n_pre + rec.n_pre), dim3(WAVE), 0, s, in, rec, cv.cnt, cv.col);
 }
 
 // Hand-off transpose: [tau][B][n] -> [n][nslot][B] through a 64 x 64 LDS tile
@@ -534,134 +581,7 @@ void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int 
   hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B, nsteps, slot0, nslot);
 }
 
-// XCD-aware form (B % 4 == 0, 64 <= B <= 256): workgroup w = row*8 + o takes
-// the row's synapses whose target lies in octant o.  Workgroups are handed to
-// the 8 XCDs round-robin, so each XCD's L2 only ever holds psi and L of its own
-// eighth of the targets.  One wave per workgroup; same arithmetic and order as
-// the row form.
-template <bool ALIF>
-__global__ void __launch_bounds__(WAVE) k_eprop_oct(EpropArgs a) {
-  const int lane = lane_id();
-  const int n_rows = a.n_in + a.n_rec;
-  const int wg = blockIdx.x;
-  if (wg >= n_rows * 8) {
-    readout_grad_wave(a, wg - n_rows * 8, lane);
-    return;
-  }
-  const int row = wg >> 3, oct = wg & 7;
-  const bool from_in = row < a.n_in;
-  const ProjDev& P = from_in ? a.in : a.rec;
-  const int i = from_in ? row : row - a.n_in;
-  const int cap = P.cap;
-  const int q0 = P.oct_off[i * 9 + oct], q1 = P.oct_off[i * 9 + oct + 1];
-  if (q1 <= q0) return;
-  const int* __restrict__ ind = P.ind;
-  const int* __restrict__ perm = P.perm;
-  float* __restrict__ G = P.G;
-  float* __restrict__ eps = P.eps;
-  float* __restrict__ ebar = P.ebar;
-  const int B = a.B, nb4 = B / 4, T = a.nsteps;
-  const int64_t base = (int64_t)i * cap;
-  const bool act = lane < nb4;
-  const int lo = act ? 4 * lane : 0;  // inactive lanes read instance 0, never store
-  const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
-  const float* __restrict__ pre = (from_in ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0) + lo;
-  for (int c0 = q0; c0 < q1; c0 += WAVE) {
-    const bool own = c0 + lane < q1;
-    const int my_s = own ? perm[base + c0 + lane] : 0;
-    const int my_j = own ? ind[base + my_s] : 0;
-    float my_g = own ? G[base + my_s] : 0.0f;
-    const int cnt = min(WAVE, q1 - c0);
-    for (int q = 0; q < cnt; q += 2) {
-      const bool two = q + 1 < cnt;
-      const int j0 = __builtin_amdgcn_readlane(my_j, q);
-      const int j1 = two ? __builtin_amdgcn_readlane(my_j, q + 1) : j0;
-      const int64_t s0 = base + __builtin_amdgcn_readlane(my_s, q);
-      const int64_t s1 = two ? base + __builtin_amdgcn_readlane(my_s, q + 1) : s0;
-      const float* __restrict__ psi0p = a.psiT + ring(a, j0, 0) + lo;
-      const float* __restrict__ L0p = a.LT + ring(a, j0, 0) + lo;
-      const float* __restrict__ psi1p = a.psiT + ring(a, j1, 0) + lo;
-      const float* __restrict__ L1p = a.LT + ring(a, j1, 0) + lo;
-      f4 eb0 = __builtin_nontemporal_load((const f4*)&ebar[s0 * B + lo]);
-      f4 eb1 = __builtin_nontemporal_load((const f4*)&ebar[s1 * B + lo]);
-      f4 ep0 = zero4, ep1 = zero4;
-      if (ALIF) {
-        ep0 = __builtin_nontemporal_load((const f4*)&eps[s0 * B + lo]);
-        ep1 = __builtin_nontemporal_load((const f4*)&eps[s1 * B + lo]);
-      }
-      // software pipeline over the block's steps: step tau+1's inputs are in
-      // flight while step tau is computed
-      f4 p = *(const f4*)pre, psi0 = *(const f4*)psi0p, L0 = *(const f4*)L0p;
-      f4 psi1 = *(const f4*)psi1p, L1 = *(const f4*)L1p;
-      for (int tau = 0; tau < T; ++tau) {
-        const int nx = (tau + 1 < T ? tau + 1 : tau) * B;
-        const f4 pn = *(const f4*)(pre + nx), psi0n = *(const f4*)(psi0p + nx), L0n = *(const f4*)(L0p + nx);
-        const f4 psi1n = *(const f4*)(psi1p + nx), L1n = *(const f4*)(L1p + nx);
-        float g0 = trace_step<ALIF>(a, psi0, L0, p, eb0, ep0);
-        float g1 = trace_step<ALIF>(a, psi1, L1, p, eb1, ep1);
-        if (!act) { g0 = 0.f; g1 = 0.f; }
-        g0 = wave_sum(g0);
-        g1 = wave_sum(g1);
-        if (lane == q) my_g += g0;
-        if (two && lane == q + 1) my_g += g1;
-        p = pn; psi0 = psi0n; L0 = L0n; psi1 = psi1n; L1 = L1n;
-      }
-      if (act) {
-        __builtin_nontemporal_store(eb0, (f4*)&ebar[s0 * B + lo]);
-        if (ALIF) __builtin_nontemporal_store(ep0, (f4*)&eps[s0 * B + lo]);
-        if (two) {
-          __builtin_nontemporal_store(eb1, (f4*)&ebar[s1 * B + lo]);
-          if (ALIF) __builtin_nontemporal_store(ep1, (f4*)&eps[s1 * B + lo]);
-        }
-      }
-    }
-    if (own) G[base + my_s] = my_g;
-  }
-}
-
-// Octant permutation of every row: one wave per row, stable counting sort of
-// the row's slots by target octant.
-__global__ void __launch_bounds__(WAVE) k_octant_perm(ProjDev P) {
-  __shared__ int cnt[9];
-  const int i = blockIdx.x, lane = lane_id();
-  const int n = P.len[i];
-  const int64_t base = (int64_t)i * P.cap;
-  if (lane < 9) cnt[lane] = 0;
-  __syncthreads();
-  int run[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // per-octant running offset (uniform)
-  // first pass: octant sizes
-  for (int c = 0; c < n; c += WAVE) {
-    const int k = c + lane;
-    const int o = k < n ? min(P.ind[base + k] / P.oct_size, 7) : 8;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) run[b] += __popcll(ballot(o == b));
-  }
-  int off[9];
-  off[0] = 0;
-#pragma unroll
-  for (int b = 0; b < 8; ++b) off[b + 1] = off[b] + run[b];
-  if (lane < 9) P.oct_off[i * 9 + lane] = off[lane];
-  // second pass: stable placement
-#pragma unroll
-  for (int b = 0; b < 8; ++b) run[b] = off[b];
-  for (int c = 0; c < n; c += WAVE) {
-    const int k = c + lane;
-    const int o = k < n ? min(P.ind[base + k] / P.oct_size, 7) : 8;
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t m = ballot(o == b);
-      if (o == b) P.perm[base + run[b] + __popcll(m & lanemask_lt())] = k;
-      run[b] += __popcll(m);
-    }
-  }
-}
-
-void launch_octant_perm(hipStream_t s, const ProjDev& P) {
-  if (!P.perm) return;
-  hipLaunchKernelGGL(k_octant_perm, dim3(P.n_pre), dim3(WAVE), 0, s, P);
-}
-
-// Narrow form (any B): threads over a row's synapses, each looping over steps
+// Narrow form (B < 32): threads over a row's synapses, each looping over steps
 // and instances; used for small batches such as single-instance learning.
 template <bool ALIF>
 __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
@@ -724,18 +644,21 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   }
 }
 
+
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
-  const int n_rows = a.n_in + a.n_rec;
   if (a.nsteps <= 0) return;
-  if (a.B % 4 == 0 && a.B >= 64 && a.B <= 256 && a.in.perm && a.rec.perm) {
-    const int blocks = n_rows * 8 + a.n_rec + 1;
-    if (a.alif) hipLaunchKernelGGL(k_eprop_oct<true>, dim3(blocks), dim3(WAVE), 0, s, a);
-    else hipLaunchKernelGGL(k_eprop_oct<false>, dim3(blocks), dim3(WAVE), 0, s, a);
-  } else if (a.B % 4 == 0 && a.B >= 64) {
-    const int extra = (a.n_rec + 1 + EP_WAVES - 1) / EP_WAVES;
-    if (a.alif) hipLaunchKernelGGL(k_eprop_wide<true>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);
-    else hipLaunchKernelGGL(k_eprop_wide<false>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);
+  if (a.B >= 32 && a.col && a.col_off) {
+    const int nw = min(EP_NT / WAVE, (a.B + WAVE - 1) / WAVE);
+    const int blocks = a.n_rec * COL_OCT + (a.n_rec + 1 + nw - 1) / nw;
+    for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
+      EpropArgs p = a;
+      p.slot0 = a.slot0 + t0;
+      p.nsteps = min(COL_TB, a.nsteps - t0);
+      if (a.alif) hipLaunchKernelGGL(k_eprop_col<true>, dim3(blocks), dim3(nw * WAVE), 0, s, p);
+      else hipLaunchKernelGGL(k_eprop_col<false>, dim3(blocks), dim3(nw * WAVE), 0, s, p);
+    }
   } else {
+    const int n_rows = a.n_in + a.n_rec;
     const int extra = (a.n_rec + 1 + EP_NT - 1) / EP_NT;
     if (a.alif) hipLaunchKernelGGL(k_eprop_narrow<true>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);
     else hipLaunchKernelGGL(k_eprop_narrow<false>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);

@@ -20,12 +20,17 @@ struct ProjDev {
   uint32_t* sign;    // [n_pre*words] DEEP R sign bits, may be null
   int* dormant;      // [n_pre] eliminated per row by the last rewire
   int* assigned;     // [n_pre] activations per row of the last formation
-  // Target-octant view for the e-prop kernel: perm[i*cap + q] lists the row's
-  // slots grouped by target octant (j / oct_size), octant o occupying
-  // q in [oct_off[i*9+o], oct_off[i*9+o+1]).  Rebuilt whenever rows change.
-  int* perm;         // [n_pre*cap], may be null
-  int* oct_off;      // [n_pre*9]
-  int oct_size;
+};
+
+// Column view of the two projections onto the recurrent layer, for the
+// target-major e-prop kernel: col[off[j*8+o] .. off[j*8+o+1]) holds (r, slot)
+// of every synapse onto target j from a row r with r % 8 == o, where
+// r = i for input rows and n_in + i for recurrent rows.  Rebuilt whenever
+// rows change.
+struct ColumnView {
+  int* cnt;          // [n_rec*8] counts, then the fill cursor
+  int* off;          // [n_rec*8 + 1]
+  int2* col;         // [n_in*cap_in + n_rec*cap_rec]
 };
 
 // ---------------------------------------------------------------- build
@@ -83,9 +88,10 @@ struct EpropArgs {
   const float* psiT; const float* LT; const float* deltaT;
   int slot0, nsteps, nslot;
   float* Gout; float* Gb;
+  const int* col_off; const int2* col;   // ColumnView (B >= 32)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
-void launch_octant_perm(hipStream_t s, const ProjDev& P);
+void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const ColumnView& cv);
 
 // ---------------------------------------------------------------- update
 struct UpdateArgs {

@@ -28,9 +28,9 @@ CASES = {
     # name: (config, max input rate Hz)
     "tiny-lif-b1": (make_cfg(100, 128, 4, 1, False, p=0.1, seed=1), 50.0),
     "alif-b3-narrow": (make_cfg(30, 40, 3, 3, True, seed=2), 150.0),
-    "alif-b64-wide": (make_cfg(60, 96, 5, 64, True, seed=3), 150.0),
-    "lif-b256-wide": (make_cfg(50, 80, 6, 256, False, seed=4), 150.0),
-    "alif-b320-chunked": (make_cfg(40, 70, 4, 320, True, seed=5), 150.0),
+    "alif-b64-col": (make_cfg(60, 96, 5, 64, True, seed=3), 150.0),
+    "lif-b256-col": (make_cfg(50, 80, 6, 256, False, seed=4), 150.0),
+    "alif-b320-col": (make_cfg(40, 70, 4, 320, True, seed=5), 150.0),
 }
 
 
@@ -88,7 +88,7 @@ def test_lockstep_100_steps(name):
     assert inf.step == 100 and inf.spikes == spikes
 
 
-@pytest.mark.parametrize("name", ["tiny-lif-b1", "alif-b64-wide", "alif-b3-narrow"])
+@pytest.mark.parametrize("name", ["tiny-lif-b1", "alif-b64-col", "alif-b3-narrow"])
 def test_update_matches_oracle(name):
     cfg, net, raster, labels = setup_case(name)
     net.step(30, rb.RS_LEARN)
@@ -158,20 +158,21 @@ def test_deepr_rewire_bit_exact(name):
         assert np.array_equal(post[other]["len"], pre[other]["len"])
 
 
-def test_training_loop_invariants_and_determinism():
-    cfg = make_cfg(100, 128, 4, 1, False, p=0.1, seed=11, U=25, T=500, lr=0.05)
+@pytest.mark.parametrize("B,alif,steps", [(1, False, 500), (64, True, 200)])
+def test_training_loop_invariants_and_determinism(B, alif, steps):
+    cfg = make_cfg(100, 128, 4, B, alif, p=0.1, seed=11, U=25, T=500, lr=0.05)
     rates = wl.poisson_rates(cfg.seed, cfg.n_in, 50.0)
     raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
-    labels = np.array([2], np.int32)
+    labels = (np.arange(B) % cfg.n_out).astype(np.int32)
     snaps = []
     for rep in range(2):
         net = rb.EpropNet(cfg)
         net.set_input(*gpu_input(raster, labels))
         total0 = [int(net.get(rb.PROJ(p, rb.P_LEN)).sum()) for p in (0, 1)]
-        net.step(500, rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET)
+        net.step(steps, rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET)
         s = snapshot(net)
         inf = net.info()
-        assert inf.adam_step == 20 and inf.step == 500
+        assert inf.adam_step == steps // 25 and inf.step == steps
         for p, tag in ((0, "in"), (1, "rec")):
             g = s[tag]
             assert int(g["len"].sum()) == total0[p]
@@ -223,35 +224,67 @@ def test_error_paths():
     assert code == rb.RS_ECAPACITY
 
 
-@pytest.mark.parametrize("name", ["alif-b64-wide", "lif-b256-wide", "alif-b3-narrow", "alif-b320-chunked"])
-def test_trace_block_length_is_bit_invariant(name):
+@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col", "alif-b3-narrow", "alif-b320-col"])
+def test_trace_block_length_invariance(name):
     """Applying eligibility updates in blocks of K steps gives bit-identical
-    state for every K, across update/rewire boundaries and uneven step calls."""
+    neuron state, traces and eps/ebar for every K, over uneven step calls.  The
+    gradient is summed per lane over a block's steps before the batch
+    reduction, so G may differ by float rounding only."""
     base, rate = CASES[name]
     snaps = {}
-    for K in (1, 3, 8):
-        cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": K, "update_interval": 25})
+    for K in (1, 3, 8, 16):
+        cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": K})
         net = rb.EpropNet(cfg)
         rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
         raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
         labels = np.random.default_rng(cfg.seed).integers(0, cfg.n_out, cfg.batch).astype(np.int32)
         net.set_input(*gpu_input(raster, labels))
-        flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
         for n in (7, 1, 30, 13, 9):   # 60 steps in uneven calls
-            net.step(n, flags)
+            net.step(n, rb.RS_LEARN)
         snaps[K] = snapshot(net)
         net.close()
     ref = snaps[1]
-    for K in (3, 8):
+    for K in (3, 8, 16):
         s = snaps[K]
-        for k in ("v", "a", "y", "xbar", "zbar", "psiT", "LT", "deltaT", "z", "Wout", "bout", "Gout", "Gb"):
+        for k in ("v", "a", "y", "xbar", "zbar", "psiT", "LT", "deltaT", "z", "Wout", "bout"):
             assert np.array_equal(s[k], ref[k]), (K, k)
+        for k in ("Gout", "Gb"):
+            tol = 1e-6 * max(float(np.abs(ref[k]).max()), 1e-30)
+            assert np.abs(s[k] - ref[k]).max() <= tol, (K, k)
         for tag in ("in", "rec"):
             for k in ref[tag]:
-                assert np.array_equal(s[tag][k], ref[tag][k]), (K, tag, k)
+                if k == "G":
+                    tol = 1e-6 * max(float(np.abs(ref[tag][k]).max()), 1e-30)
+                    assert np.abs(s[tag][k] - ref[tag][k]).max() <= tol, (K, tag, k)
+                else:
+                    assert np.array_equal(s[tag][k], ref[tag][k]), (K, tag, k)
 
 
-@pytest.mark.parametrize("name", ["alif-b64-wide", "lif-b256-wide"])
+@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col"])
+def test_partial_blocks_match_oracle(name):
+    """Each step call ends its open block: uneven calls with K = 16 give
+    blocks of 7, 16 + 2, 13 and 16 + 6 steps, each matching the oracle."""
+    base, rate = CASES[name]
+    cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": 16})
+    net = rb.EpropNet(cfg)
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
+    raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+    labels = np.random.default_rng(cfg.seed).integers(0, cfg.n_out, cfg.batch).astype(np.int32)
+    net.set_input(*gpu_input(raster, labels))
+    N = oracle_net(snapshot(net), cfg)
+    t = 0
+    for n in (7, 18, 13, 22):
+        net.step(n, rb.RS_LEARN)
+        for _ in range(n):
+            idx, off = raster.step_lists(t)
+            N.step(idx, off, labels)
+            t += 1
+        snap = snapshot(net)
+        assert np.array_equal(snap["z"], N.z), f"spikes differ after step {t}"
+        compare_state(snap, N, cfg)
+
+
+@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col"])
 def test_lockstep_in_blocks_of_8(name):
     base, rate = CASES[name]
     cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": 8})
@@ -276,7 +309,7 @@ def test_lockstep_in_blocks_of_8(name):
 def test_malformed_raster_is_memory_safe():
     """Offsets are clamped to the index array and out-of-range channels and
     labels are ignored by the kernels: a garbage raster cannot fault."""
-    cfg, rate = CASES["alif-b64-wide"]
+    cfg, rate = CASES["alif-b64-col"]
     cfg = rb.EpropConfig(**{**cfg.__dict__, "sample_steps": 20, "trace_block": 8})
     net = rb.EpropNet(cfg)
     rng = np.random.default_rng(0)
@@ -289,3 +322,58 @@ def test_malformed_raster_is_memory_safe():
     net.step(20, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
     s = snapshot(net, with_traces=True)
     assert np.isfinite(s["v"]).all() and np.isfinite(s["rec"]["ebar"]).all()
+
+
+@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col", "alif-b320-col"])
+def test_lockstep_after_rewire(name):
+    """DEEP R moves and creates synapses; the following steps still match the
+    oracle, so the e-prop kernel's view of the rows follows every rewire."""
+    cfg, net, raster, labels = setup_case(name)
+    net.step(20, rb.RS_LEARN)
+    net.update()
+    flip_some_signs(net, cfg, 0.15, cfg.seed)
+    assert net.rewire(0).eliminated > 0 and net.rewire(1).eliminated > 0
+    N = oracle_net(snapshot(net), cfg)
+    resync = 0
+    for t in range(20, 40):
+        net.step(1, rb.RS_LEARN)
+        snap = snapshot(net)
+        resync += oracle_step_resync(N, raster, t, labels, snap["z"])
+        compare_state(snap, N, cfg)
+    assert resync <= 2
+
+
+@pytest.mark.parametrize("name", ["alif-b64-col", "alif-b3-narrow"])
+def test_slot_order_is_irrelevant(name):
+    """Restoring rows with every row's slots reversed (all per-synapse arrays
+    permuted alike) gives bit-identical results after 20 learning steps:
+    propagation sums in fixed point and every synapse's trace and gradient
+    are computed on their own."""
+    nets = []
+    for rev in (False, True):
+        cfg, net, raster, labels = setup_case(name)
+        net.step(10, rb.RS_LEARN)
+        if rev:
+            for p in (0, 1):
+                n = net.get(rb.PROJ(p, rb.P_LEN))
+                fields = [rb.P_IND, rb.P_W, rb.P_M, rb.P_V, rb.P_G, rb.P_EBAR] + ([rb.P_EPS] if cfg.alif else [])
+                for f in fields:
+                    a = net.get(rb.PROJ(p, f))
+                    for i in range(n.size):
+                        a[i, :n[i]] = a[i, :n[i]][::-1].copy()
+                    net.set(rb.PROJ(p, f), a)
+        net.step(20, rb.RS_LEARN)
+        nets.append((net, snapshot(net)))
+    (_, a), (_, b) = nets
+    for k in ("v", "a", "y", "z", "Gout", "Gb"):
+        assert np.array_equal(a[k], b[k]), k
+    for tag in ("in", "rec"):
+        n = a[tag]["len"]
+        for k in ("ind", "w", "G", "ebar") + (("eps",) if "eps" in a[tag] else ()):
+            x, y = a[tag][k], b[tag][k].copy()
+            for i in range(n.size):
+                y[i, :n[i]] = y[i, :n[i]][::-1].copy()
+            m = real_slots(a[tag])
+            assert np.array_equal(x[m], y[m]), (tag, k)
+    for net, _ in nets:
+        net.close()
