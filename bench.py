@@ -221,7 +221,7 @@ def main():
         "synaptic_events_per_s": round(events / elapsed, 1),
         "timesteps_per_s": round(args.steps * T / elapsed, 1),
         "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
-        "roofline": {"bound": "hbm", "kernel": "k_eprop_col<true>", "achieved": round(achieved, 1),
+        "roofline": {"bound": "hbm", "kernel": "k_eprop_wl<true>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
                      "trace_block": inf_k,

@@ -350,37 +350,93 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
 // before the batch reduction, so G depends on the block length only through
 // float rounding.
 constexpr int EP_NT = 256;
-constexpr int COL_TB = 16;  // steps per launch of the column kernel
+constexpr int COL_TB = 16;  // steps per launch of the target-major kernel
 constexpr int COL_OCT = 8;  // source octants, one per XCD
 
 __device__ __forceinline__ int64_t ring(const EpropArgs& a, int n, int tau) {
   return ((int64_t)n * a.nslot + a.slot0 + tau) * a.B;
 }
 
+// Raw buffer access: a 128-bit resource (base, byte size) in scalar registers
+// plus a 32-bit per-lane byte offset and a uniform byte offset, so a load
+// costs no vector address arithmetic.  Offsets at or past the size read zero
+// and drop stores; every offset used here is in range by construction.
+constexpr int BUF_FLAGS = 0x00020000;  // 32-bit data format (gfx9 family)
+constexpr int BUF_NT = 2;              // non-temporal
+// The base and size are wave-uniform; readfirstlane states it to the compiler.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  const uint64_t v = (uint64_t)base;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  void* u = (void*)(((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_make_buffer_rsrc(u, 0, (int)__builtin_amdgcn_readfirstlane(bytes), BUF_FLAGS);
+}
+template <int AUX = 0>
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, AUX));
+}
+template <int AUX = 0>
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, 0, AUX);
+}
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 buf_ld4(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+}
+template <int AUX>
+__device__ __forceinline__ f4 buf_ld4x(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  return __builtin_bit_cast(f4, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, AUX));
+}
+template <int AUX>
+__device__ __forceinline__ void buf_st4(f4 v, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(v4u, v), r, (int)voff, 0, AUX);
+}
+
+
 // Readout delta rule over the launch's steps (recurrent classifier section):
 // wave j < n_rec adds sum_t sum_b delta_k z_j to Gout[k][j] for every output
-// k, wave n_rec the bias gradient sum_t sum_b delta_k.
+// k, wave n_rec the bias gradient sum_t sum_b delta_k.  Steps are read four at
+// a time with independent loads, so a wave waits once per group, not per step.
 __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane) {
   if (j > a.n_rec) return;
   const int B = a.B, T = a.nsteps;
   const bool wt = j < a.n_rec;
+  const uint32_t step_bytes = (uint32_t)B * 4u, blk = (uint32_t)T * step_bytes;
+  const auto rz = buf_rsrc(a.zbar_new + ring(a, wt ? j : 0, 0), blk);
   for (int k = 0; k < a.n_out; ++k) {
+    const auto rd = buf_rsrc(a.deltaT + ring(a, k, 0), blk);
     float g = 0.0f;
-    for (int t = 0; t < T; ++t) {
-      const float* __restrict__ d = a.deltaT + ring(a, k, t);
-      const float* __restrict__ z = a.zbar_new + ring(a, wt ? j : 0, t);
-      if (B % 4 == 0) {
-        for (int c = lane; c < B / 4; c += WAVE) {
-          const f4 d4 = *(const f4*)&d[4 * c];
-          if (wt) {
-            const f4 z4 = *(const f4*)&z[4 * c];
-            g += (d4.x * z4.x + d4.y * z4.y) + (d4.z * z4.z + d4.w * z4.w);
-          } else {
-            g += (d4.x + d4.y) + (d4.z + d4.w);
+    if (B % 4 == 0) {
+      for (int c = 4 * lane; c < B; c += 4 * WAVE) {
+        const uint32_t off = (uint32_t)c * 4u;
+        for (int t0 = 0; t0 < T; t0 += 4) {
+          f4 d[4], z[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t so = (uint32_t)min(t0 + u, T - 1) * step_bytes;
+            d[u] = buf_ld4(rd, off, so);
+            z[u] = wt ? buf_ld4(rz, off, so) : f4{1.f, 1.f, 1.f, 1.f};
           }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (t0 + u < T) g += (d[u].x * z[u].x + d[u].y * z[u].y) + (d[u].z * z[u].z + d[u].w * z[u].w);
         }
-      } else {
-        for (int b = lane; b < B; b += WAVE) g += wt ? d[b] * z[b] : d[b];
+      }
+    } else {
+      for (int c = lane; c < B; c += WAVE) {
+        const uint32_t off = (uint32_t)c * 4u;
+        for (int t0 = 0; t0 < T; t0 += 4) {
+          float d[4], z[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const uint32_t so = (uint32_t)min(t0 + u, T - 1) * step_bytes;
+            d[u] = buf_ld(rd, off, so);
+            z[u] = wt ? buf_ld(rz, off, so) : 1.0f;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (t0 + u < T) g = fmaf(d[u], z[u], g);
+        }
       }
     }
     g = wave_sum(g);
@@ -391,105 +447,156 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
   }
 }
 
-// Target-major form (B >= 32).  Workgroup g = j*8 + o owns target neuron j
-// and the synapses onto it from rows r with r % 8 == o (r = i for input rows,
-// n_in + i for recurrent rows).  Workgroups are handed to the 8 XCDs
-// round-robin, so XCD o only gathers the presynaptic traces of its own eighth
-// of the rows.  Wave w takes 64-instance chunks w, w + nw, ... with one
-// instance per lane; psi_j, L_j and the eps decay factor of the block's steps
-// sit in registers, so each synapse step costs one gathered float (the
-// presynaptic trace) and six float operations (ALIF):
-//   u = psi p,  d = u - ((1 - rho) + psi beta) eps,  e = d + (1 - rho) eps,
+// Workgroups of an e-prop launch: the readout waves come first (they form a
+// long dependent chain per wave and would otherwise trail the launch), padded
+// to a multiple of 8 so that workgroup n_ro + 8j + o still lands on XCD o.
+__host__ __device__ inline int readout_groups(int n_rec, int nw) {
+  return ((n_rec + 1 + nw - 1) / nw + 7) & ~7;
+}
+
+// Target-major form (B % 4 == 0).  Workgroup n_ro + 8j + o owns target
+// neuron j and the synapses onto it from rows r with r % 8 == o (r = i for
+// input rows, n_in + i for recurrent rows).  Workgroups are dealt to the 8 XCDs
+// in turn, so XCD o only gathers the presynaptic traces of its own eighth of
+// the rows, which fits its L2.  Every lane holds four consecutive instances,
+// so one wave covers 256 instances of a synapse with 16-byte accesses; wave w
+// takes synapses w, w + 4, ... of the list.  psi_j and L_j of the block's
+// steps for the current 256-instance chunk are staged once in LDS (32 KB) and
+// shared by the workgroup's waves, so a synapse step costs one gathered
+// presynaptic trace and seven float operations per instance (ALIF):
+//   x = psi p,  c = (1 - rho) + psi beta,  d = x - c eps,  e = d + (1 - rho) eps,
 //   eps' = eps + d,  ebar' = alpha ebar + e,  g += L ebar'
 // which is e = psi (p - beta eps) and eps' = psi p + (rho - psi beta) eps of
 // eq. eprop_elig_1/2 (eprop_elig_lif without eps).  rho is within 5e-4 of one:
 // carrying 1 - rho instead of a float rho keeps the slow eps decay free of a
-// systematic 3e-8 per step.  Lane sums over the steps are reduced per synapse
-// with DPP, per wave in chunk order and across waves in wave order, so the
-// result does not depend on scheduling or on the order of the column list.
+// systematic 3e-8 per step.  The gradient is summed per lane over the steps
+// and its four instances, reduced once per synapse and chunk, and added to G
+// in chunk order by the one wave that owns the synapse, so the result does
+// not depend on scheduling or on the order of the column list.
+constexpr int WL_CH = 4 * WAVE;  // instances per chunk
+
 template <bool ALIF>
-__global__ void __launch_bounds__(EP_NT) k_eprop_col(EpropArgs a) {
-  __shared__ float gpart[EP_NT / WAVE][WAVE];
-  const int wv = threadIdx.x / WAVE, lane = lane_id();
+__global__ void __launch_bounds__(EP_NT) k_eprop_wl(EpropArgs a) {
+  __shared__ f4 s_psi[COL_TB][WAVE], s_L[COL_TB][WAVE];
+  const int wv = wave_id(), lane = lane_id();
   const int nw = blockDim.x / WAVE;
-  const int ncol = a.n_rec * COL_OCT;
-  const int wg = blockIdx.x;
-  if (wg >= ncol) {
-    readout_grad(a, (wg - ncol) * nw + wv, lane);
+  const int n_ro = readout_groups(a.n_rec, nw);
+  if ((int)blockIdx.x < n_ro) {
+    readout_grad(a, blockIdx.x * nw + wv, lane);
     return;
   }
+  const int wg = blockIdx.x - n_ro;
   const int j = wg / COL_OCT;
   const int q0 = a.col_off[wg], q1 = a.col_off[wg + 1];
-  const int B = a.B, T = a.nsteps, n_ic = (B + WAVE - 1) / WAVE;
+  if (q1 <= q0) return;
+  const int B = a.B, T = a.nsteps;
+  const int n_ch = (B + WL_CH - 1) / WL_CH;
+  const uint32_t step_bytes = (uint32_t)B * 4u, blk_bytes = (uint32_t)T * step_bytes;
   const float alpha = a.alpha, omr = a.one_m_rho, beta = a.beta;
-  for (int sc = q0; sc < q1; sc += WAVE) {  // uniform over the workgroup
-    const int ns = min(WAVE, q1 - sc);
-    float my_g = 0.0f;  // lane k: this wave's part of the gradient of entry sc + k
-    for (int ic = wv; ic < n_ic; ic += nw) {
-      const int b = ic * WAVE + lane;
-      const bool act = b < B;
-      const int bb = act ? b : 0;  // idle lanes read instance 0 and never store
-      float psi[COL_TB], L[COL_TB], c[COL_TB];
-      const float* __restrict__ pj = a.psiT + ring(a, j, 0) + bb;
-      const float* __restrict__ lj = a.LT + ring(a, j, 0) + bb;
+  const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < n_ch; ++m) {
+    const int b0 = m * WL_CH + 4 * lane;
+    const bool act = b0 < B;
+    const uint32_t off = (uint32_t)(act ? b0 : 0) * 4u;  // idle lanes read instance 0, never store
+    __syncthreads();  // the previous chunk's psi/L are no longer read
+    {
+      const auto rp = buf_rsrc(a.psiT + ring(a, j, 0), blk_bytes);
+      const auto rl = buf_rsrc(a.LT + ring(a, j, 0), blk_bytes);
+      for (int t = wv; t < COL_TB; t += nw) {
+        const uint32_t st = (uint32_t)(t < T ? t : T - 1) * step_bytes;
+        s_psi[t][lane] = buf_ld4(rp, off, st);
+        s_L[t][lane] = act && t < T ? buf_ld4(rl, off, st) : zero4;
+      }
+    }
+    __syncthreads();
+    // Synapses of this wave: q = q0 + wv, q + nw, ...  The next synapse's
+    // records are loaded during step group 1 and its first four presynaptic
+    // steps during group 3 of the current one.
+    struct Cur {
+      __amdgpu_buffer_rsrc_t pre, eb, ep;
+      int2 ent;
+    };
+    auto decode = [&](int q) {
+      Cur c;
+      c.ent = a.col[q];
+      const bool fin = c.ent.x < a.n_in;
+      const int i = fin ? c.ent.x : c.ent.x - a.n_in;
+      c.pre = buf_rsrc((fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0), blk_bytes);
+      const int64_t rec = (int64_t)c.ent.y * B;
+      c.eb = buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
+      c.ep = buf_rsrc(ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : a.in.ebar, step_bytes);
+      return c;
+    };
+    auto st_off = [&](int t) { return (uint32_t)(t < T ? t : T - 1) * step_bytes; };
+    int q = q0 + wv;
+    Cur nx{};
+    f4 eb_n = zero4, ep_n = zero4, p_n[4];
+    if (q < q1) {
+      nx = decode(q);
+      eb_n = buf_ld4x<BUF_NT>(nx.eb, off);
+      if (ALIF) ep_n = buf_ld4x<BUF_NT>(nx.ep, off);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) p_n[t] = buf_ld4(nx.pre, off, st_off(t));
+    }
+    for (; q < q1; q += nw) {
+      // the empty asm statements keep the compiler from hoisting every load
+      // (and the loop-invariant LDS reads) ahead: registers, hence occupancy
+      __asm__ volatile("" ::: "memory");
+      const Cur cu = nx;
+      const bool more = q + nw < q1;
+      f4 eb = eb_n, ep = ep_n;
+      f4 p[COL_TB];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) p[t] = p_n[t];
+      f4 g = zero4;
 #pragma unroll
       for (int t = 0; t < COL_TB; ++t) {
-        const int tt = t < T ? t : T - 1;  // loads stay inside the block
-        psi[t] = pj[(int64_t)tt * B];
-        L[t] = act ? lj[(int64_t)tt * B] : 0.0f;
-        c[t] = ALIF ? fmaf(psi[t], beta, omr) : 0.0f;
-      }
-      for (int k = 0; k < ns; ++k) {
-        const int2 ent = a.col[sc + k];
-        const bool fin = ent.x < a.n_in;
-        const int i = fin ? ent.x : ent.x - a.n_in;
-        const float* __restrict__ pre = (fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0) + bb;
-        const int64_t rec = (int64_t)ent.y * B + bb;
-        float* __restrict__ ebp = (fin ? a.in.ebar : a.rec.ebar) + rec;
-        float* __restrict__ epp = ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : nullptr;
-        float p[COL_TB];
+        if (t % 4 == 0) {
+          __asm__ volatile("" ::: "memory");
+          if (t + 4 < COL_TB) {
 #pragma unroll
-        for (int t = 0; t < COL_TB; ++t) p[t] = pre[(int64_t)(t < T ? t : T - 1) * B];
-        float eb = __builtin_nontemporal_load(ebp);
-        float ep = ALIF ? __builtin_nontemporal_load(epp) : 0.0f;
-        float g = 0.0f;
+            for (int u = t + 4; u < t + 8; ++u) p[u] = buf_ld4(cu.pre, off, st_off(u));
+          }
+          if (t == 4 && more) {
+            nx = decode(q + nw);
+            eb_n = buf_ld4x<BUF_NT>(nx.eb, off);
+            if (ALIF) ep_n = buf_ld4x<BUF_NT>(nx.ep, off);
+          }
+          if (t == 12 && more) {
 #pragma unroll
-        for (int t = 0; t < COL_TB; ++t) {
-          if (t < T) {
-            const float u = psi[t] * p[t];
-            if (ALIF) {
-              const float d = fmaf(-c[t], ep, u);
-              const float e = fmaf(omr, ep, d);
-              ep = ep + d;
-              eb = fmaf(alpha, eb, e);
-            } else {
-              eb = fmaf(alpha, eb, u);
-            }
-            g = fmaf(L[t], eb, g);
+            for (int u = 0; u < 4; ++u) p_n[u] = buf_ld4(nx.pre, off, st_off(u));
           }
         }
-        if (act) {
-          __builtin_nontemporal_store(eb, ebp);
-          if (ALIF) __builtin_nontemporal_store(ep, epp);
+        if (t < T) {
+          const f4 psi = s_psi[t][lane], L = s_L[t][lane];
+          const f4 x = psi * p[t];
+          if (ALIF) {
+            const f4 c = psi * beta + omr;
+            const f4 d = x - c * ep;
+            const f4 e = d + omr * ep;
+            ep = ep + d;
+            eb = alpha * eb + e;
+          } else {
+            eb = alpha * eb + x;
+          }
+          g = g + L * eb;
         }
-        const float gs = wave_sum(g);
-        if (lane == k) my_g += gs;
+      }
+      const bool fin = cu.ent.x < a.n_in;
+      if (act) {
+        buf_st4<BUF_NT>(eb, cu.eb, off);
+        if (ALIF) buf_st4<BUF_NT>(ep, cu.ep, off);
+      }
+      const float gs = wave_sum((g.x + g.y) + (g.z + g.w));
+      if (lane == 0) {
+        float* G = fin ? a.in.G : a.rec.G;
+        G[cu.ent.y] += gs;
       }
     }
-    gpart[wv][lane] = my_g;
-    __syncthreads();
-    if ((int)threadIdx.x < ns) {
-      const int2 ent = a.col[sc + threadIdx.x];
-      float gsum = 0.0f;
-      for (int w = 0; w < nw; ++w) gsum += gpart[w][threadIdx.x];
-      float* G = ent.x < a.n_in ? a.in.G : a.rec.G;
-      G[ent.y] += gsum;
-    }
-    __syncthreads();
   }
 }
 
-// Column view of both projections for k_eprop_col: entries
+// Column view of both projections for k_eprop_wl: entries
 // col[col_off[j*8+o] .. col_off[j*8+o+1]) are (r, slot) of every synapse of a
 // row r with r % 8 == o onto target j.  Rebuilt whenever rows change; the
 // order inside a list is arbitrary.
@@ -647,15 +754,15 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
 
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
-  if (a.B >= 32 && a.col && a.col_off) {
-    const int nw = min(EP_NT / WAVE, (a.B + WAVE - 1) / WAVE);
-    const int blocks = a.n_rec * COL_OCT + (a.n_rec + 1 + nw - 1) / nw;
+  if (a.B % 4 == 0 && a.col && a.col_off) {
+    const int nw = EP_NT / WAVE;
+    const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_OCT;
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;
       p.slot0 = a.slot0 + t0;
       p.nsteps = min(COL_TB, a.nsteps - t0);
-      if (a.alif) hipLaunchKernelGGL(k_eprop_col<true>, dim3(blocks), dim3(nw * WAVE), 0, s, p);
-      else hipLaunchKernelGGL(k_eprop_col<false>, dim3(blocks), dim3(nw * WAVE), 0, s, p);
+      if (a.alif) hipLaunchKernelGGL(k_eprop_wl<true>, dim3(blocks), dim3(EP_NT), 0, s, p);
+      else hipLaunchKernelGGL(k_eprop_wl<false>, dim3(blocks), dim3(EP_NT), 0, s, p);
     }
   } else {
     const int n_rows = a.n_in + a.n_rec;

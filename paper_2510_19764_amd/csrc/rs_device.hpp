@@ -90,6 +90,10 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   int l = lane_id();
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
+
+// Index of the calling wave in its workgroup, as a wave-uniform value.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)); }
+
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ bool get_bit(const uint32_t* bits, int words, int row, int j) {

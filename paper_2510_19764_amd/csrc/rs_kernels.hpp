@@ -88,7 +88,7 @@ struct EpropArgs {
   const float* psiT; const float* LT; const float* deltaT;
   int slot0, nsteps, nslot;
   float* Gout; float* Gb;
-  const int* col_off; const int2* col;   // ColumnView (B >= 32)
+  const int* col_off; const int2* col;   // ColumnView (B % 4 == 0)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
 void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const ColumnView& cv);

@@ -31,6 +31,7 @@ CASES = {
     "alif-b64-col": (make_cfg(60, 96, 5, 64, True, seed=3), 150.0),
     "lif-b256-col": (make_cfg(50, 80, 6, 256, False, seed=4), 150.0),
     "alif-b320-col": (make_cfg(40, 70, 4, 320, True, seed=5), 150.0),
+    "alif-b33-narrow": (make_cfg(36, 50, 3, 33, True, seed=6), 150.0),
 }
 
 
