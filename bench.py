@@ -54,6 +54,22 @@ def eprop_algorithmic_bytes(cfg, n_syn: int, n_launch: int, n_steps: int) -> int
     return n_launch * per_launch + n_steps * per_step
 
 
+def recorded_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (calibrated against a plain copy), or None when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "eprop_wl_classifier_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if rec.get("kernel") != kernel or hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return int(rec["hbm_bytes_per_dispatch"])
+
+
 def run_cpu_baseline(cfg, raster, labels, n_steps: int):
     """Time the oracle (single-threaded fp64 C) on a bounded sample of the same
     workload: n_steps timesteps plus one update and two DEEP R rewires."""
@@ -223,7 +239,8 @@ def main():
         "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
         "roofline": {"bound": "hbm", "kernel": "k_eprop_wl<true>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
+                     "traffic": recorded_traffic("k_eprop_wl<true>"),
+                     "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
                      "trace_block": inf_k,
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(ep_n, 1))},
     }
