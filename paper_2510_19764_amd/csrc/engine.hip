@@ -136,7 +136,8 @@ struct rs_eprop {
   float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;
   float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
   // the forward kernel's coalesced staging of one block, [tau][B][n]
-  float *stg[6] = {};
+  float *stg[HANDOFF_ARRAYS] = {};
+  float *u_stg = nullptr;                             // readout drive [2 halves][K][B][n_out]
   int K = 8, nslot = 16;
   int blk_half = 0, blk_n = 0, last_slot = 0;
   uint64_t blk_t0 = 0;
@@ -280,8 +281,9 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->deltaT, K * NS * B));
   {
     const size_t KB = (size_t)n->K * B;
-    const size_t dims[6] = {NI, NR, NR, NR, NR, K};  // xbar_prev, zbar_prev, zbar_new, psi, L, delta
-    for (int q = 0; q < 6; ++q) TRY(ar.alloc(&n->stg[q], KB * dims[q]));
+    const size_t dims[HANDOFF_ARRAYS] = {NI, NR, NR, NR};  // xbar_prev, zbar_prev, zbar_new, psi
+    for (int q = 0; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], KB * dims[q]));
+    TRY(ar.alloc(&n->u_stg, 2 * KB * K));
   }
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
@@ -403,29 +405,40 @@ void flush_block(rs_eprop* n) {
   f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
   f.alpha = n->alpha; f.rho = n->rho; f.v_thr = n->p.v_thr; f.beta = n->beta;
   f.psi_scale = 0.3 / (double)n->p.v_thr;
-  f.V = n->V; f.A = n->A; f.Y = n->Y;
+  f.V = n->V; f.A = n->A;
   f.xbar = n->xbar; f.zbar = n->zbar;
   f.xbar_prev = n->stg[0]; f.zbar_prev = n->stg[1]; f.zbar_new = n->stg[2];
-  f.psi = n->stg[3]; f.L = n->stg[4]; f.delta = n->stg[5]; f.z = n->z;
+  f.psi = n->stg[3]; f.z = n->z;
+  // the readout drive goes to the block's half, read on the side stream
+  f.u = n->u_stg + (size_t)h * n->K * n->B * n->p.n_out;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
-  f.Wout = n->Wout; f.bout = n->bout;
+  f.Wout = n->Wout;
   f.x_off = n->x_off; f.x_idx = n->x_idx; f.n_idx = n->n_idx;
   f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
-  f.labels = n->labels;
   f.counters = n->counters;
   n->timer.begin(s, 0);
   launch_fwd(s, f);
   HandoffArrays ho{};
-  float* dst[6] = {n->xbar_prevT, n->zbar_prevT, n->zbar_newT, n->psiT, n->LT, n->deltaT};
-  const int dims[6] = {(int)n->p.n_in, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec,
-                       (int)n->p.n_out};
-  for (int q = 0; q < 6; ++q) { ho.src[q] = n->stg[q]; ho.dst[q] = dst[q]; ho.n[q] = dims[q]; }
+  float* dst[HANDOFF_ARRAYS] = {n->xbar_prevT, n->zbar_prevT, n->zbar_newT, n->psiT};
+  const int dims[HANDOFF_ARRAYS] = {(int)n->p.n_in, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec};
+  for (int q = 0; q < HANDOFF_ARRAYS; ++q) { ho.src[q] = n->stg[q]; ho.dst[q] = dst[q]; ho.n[q] = dims[q]; }
   launch_handoff_transpose(s, ho, n->B, n->blk_n, h * n->K, n->nslot);
   n->timer.end(s);
   n->last_slot = h * n->K + n->blk_n - 1;
   (void)hipEventRecord(n->ev_fwd, s);
   (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
+  // readout state, softmax error and (when learning) the learning signal of
+  // the block, on the side stream ahead of its e-prop launch
+  ReadoutArgs ro{};
+  ro.n_rec = f.n_rec; ro.n_out = f.n_out; ro.B = n->B; ro.nsteps = n->blk_n;
+  ro.slot0 = h * n->K; ro.nslot = n->nslot;
+  ro.alpha = n->alpha;
+  ro.u = f.u; ro.Y = n->Y; ro.Wout = n->Wout; ro.bout = n->bout; ro.labels = n->labels;
+  ro.deltaT = n->deltaT; ro.LT = n->LT;
+  n->timer.begin(e, 0);
+  launch_readout(e, ro, n->blk_learn);
+  n->timer.end(e);
   if (n->blk_learn) {
     EpropArgs a{};
     a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B;
@@ -441,9 +454,10 @@ void flush_block(rs_eprop* n) {
     n->timer.begin(e, 1);
     launch_eprop(e, a);
     n->timer.end(e);
-    (void)hipEventRecord(n->ev_ep[h], e);
-    n->ep_pending[h] = true;
   }
+  // the next forward launch into this half waits for everything above
+  (void)hipEventRecord(n->ev_ep[h], e);
+  n->ep_pending[h] = true;
   n->blk_half ^= 1;
   n->blk_n = 0;
 }

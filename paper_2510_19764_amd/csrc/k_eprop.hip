@@ -1,18 +1,21 @@
 // Per-timestep kernels of the e-prop classifier (paper, recurrent classifier
 // section; eligibility traces eq. eprop_elig_1/2 and eprop_elig_lif).
 //
-// k_fwd: one workgroup per batch instance b.  Spikes and surrogate derivatives
-//   from the state at the start of the step, ordered spike compaction with
-//   ballots, propagation of input and recurrent spikes through the ragged rows
-//   (one wave per spiking row, lanes over its slots, accumulation into LDS),
-//   neuron update with subtractive reset, presynaptic traces, leaky readout,
-//   softmax error and learning signal L_j = sum_k W_out[k][j] delta_k.
+// k_fwd: one workgroup per batch instance b runs a block of steps.  Spikes and
+//   surrogate derivatives from the state at the start of the step, ordered
+//   spike compaction with ballots, propagation of input and recurrent spikes
+//   through the ragged rows (one wave per spiking row, lanes over its slots,
+//   accumulation into LDS), neuron update with subtractive reset, presynaptic
+//   traces, and the readout drive u_k = sum_j W_out[k][j] z_j of the step.
 //   Input currents are accumulated as 64-bit fixed point (2^-36 resolution) so
 //   the sum does not depend on the order of the LDS atomics.
+// k_readout / k_learning_signal: leaky readout, softmax error and learning
+//   signal L_j = sum_k W_out[k][j] delta_k for the whole block, off the
+//   forward kernel's sequential path.
 // k_eprop_*: per-synapse eligibility traces over every batch instance and the
-//   batch-summed gradient G_ji += sum_b L_j ebar_ji; the last workgroups
+//   batch-summed gradient G_ji += sum_b L_j ebar_ji; further workgroups
 //   accumulate the readout delta rule.  State is laid out batch-innermost
-//   ([slot][B], [neuron][B]) so a wave reads 64 consecutive instances.
+//   ([slot][B], [neuron][B]) so a wave reads consecutive instances.
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -21,9 +24,13 @@ namespace rs {
 constexpr int FWD_NT = 1024;
 constexpr int FWD_MAX_ITEMS = 8;  // n_rec <= FWD_NT * FWD_MAX_ITEMS
 
+// Ordered position of a flagged thread among the workgroup's flagged threads,
+// and their total.  s_wave alternates between two buffers on consecutive calls
+// so that no trailing barrier is needed: a buffer is written again only after
+// the intervening call's barrier.
 __device__ __forceinline__ int block_scan_flag_fwd(bool f, int* s_wave, int* total) {
   uint64_t m = ballot(f);
-  int lane = lane_id(), w = threadIdx.x / WAVE;
+  int lane = lane_id(), w = wave_id();
   constexpr int nw = FWD_NT / WAVE;
   int pre = __popcll(m & lanemask_lt());
   if (lane == 0) s_wave[w] = __popcll(m);
@@ -35,7 +42,6 @@ __device__ __forceinline__ int block_scan_flag_fwd(bool f, int* s_wave, int* tot
     base += (i < w) ? c : 0;
     tot += c;
   }
-  __syncthreads();
   *total = tot;
   return base + pre;
 }
@@ -44,13 +50,12 @@ __device__ __forceinline__ int block_scan_flag_fwd(bool f, int* s_wave, int* tot
 //   acc      int64[n_rec]        fixed-point input current of the step
 //   zlist    int[n_rec]          ordered spike list of the step
 //   len_in   int[n_in], len_rec int[n_rec]   row lengths, staged per launch
-//   xflags   u32[ceil(n_in/32)]  input spikes of the step as bits
+//   xflags   u32[2][ceil(n_in/32)] input spikes of the step as bits, by step parity
 //   xpos     int[33]             start of each step's input list in xbuf
 //   xbuf     int[xcap]           the launch's input spike lists
-//   yst      double[n_out], ylds/dlds float[n_out]
 //   wout     float[n_out*n_rec]  readout weights (when wout_lds)
 struct FwdLds {
-  size_t acc, zlist, len_in, len_rec, xflags, xpos, xbuf, yst, ylds, dlds, wout, total;
+  size_t acc, zlist, len_in, len_rec, xflags, xpos, xbuf, wout, total;
 };
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
 __host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out, int xcap, int wout_lds) {
@@ -60,16 +65,15 @@ __host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out,
   L.zlist = o; o = align16(o + (size_t)n_rec * 4);
   L.len_in = o; o = align16(o + (size_t)n_in * 4);
   L.len_rec = o; o = align16(o + (size_t)n_rec * 4);
-  L.xflags = o; o = align16(o + (size_t)((n_in + 31) / 32) * 4);
+  L.xflags = o; o = align16(o + (size_t)((n_in + 31) / 32) * 8);
   L.xpos = o; o = align16(o + 33 * 4);
   L.xbuf = o; o = align16(o + (size_t)xcap * 4);
-  L.yst = o; o = align16(o + (size_t)n_out * 8);
-  L.ylds = o; o = align16(o + (size_t)n_out * 4);
-  L.dlds = o; o = align16(o + (size_t)n_out * 4);
   L.wout = o; o = align16(o + (wout_lds ? (size_t)n_out * n_rec * 4 : 0));
   L.total = o;
   return L;
 }
+
+constexpr int PROP_U = 4;  // slots per lane loaded ahead of the LDS atomics
 
 template <int ITEMS>
 __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
@@ -79,21 +83,18 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   int* zlist = (int*)(smem + lay.zlist);
   int* len_in = (int*)(smem + lay.len_in);
   int* len_rec = (int*)(smem + lay.len_rec);
-  uint32_t* xflags = (uint32_t*)(smem + lay.xflags);
+  uint32_t* xflags2 = (uint32_t*)(smem + lay.xflags);
   int* xpos = (int*)(smem + lay.xpos);
   int* xbuf = (int*)(smem + lay.xbuf);
-  double* yst = (double*)(smem + lay.yst);
-  float* ylds = (float*)(smem + lay.ylds);
-  float* dlds = (float*)(smem + lay.dlds);
   const float* wout = a.wout_lds ? (const float*)(smem + lay.wout) : a.Wout;
   const int xwords = (a.n_in + 31) >> 5;
-  __shared__ int s_wave[FWD_NT / WAVE];
+  __shared__ int s_wave[2][FWD_NT / WAVE];
   __shared__ unsigned long long s_events;
   __shared__ int s_xsrc[33], s_xcnt[33];
   __shared__ int s_xstaged;
 
   const int b = blockIdx.x, tid = threadIdx.x, B = a.B;
-  const int lane = lane_id(), wv = tid / WAVE;
+  const int lane = lane_id(), wv = wave_id();
   const int items = (a.n_rec + FWD_NT - 1) / FWD_NT;
   const int xitems = (a.n_in + FWD_NT - 1) / FWD_NT;
 
@@ -114,6 +115,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     s_xsrc[tid] = tid < a.nsteps ? (int)lo : 0;
     s_xcnt[tid] = tid < a.nsteps ? (int)(hi - lo) : 0;
   }
+  for (int q = tid; q < 2 * xwords; q += FWD_NT) xflags2[q] = 0u;
   __syncthreads();
   if (tid == 0) {  // starts of each step's list in xbuf, staged only if all fit
     long long run = 0;
@@ -133,7 +135,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     }
   }
 
-  // neuron, trace and readout state of this instance stays on chip for the block
+  // neuron and trace state of this instance stays on chip for the block
   double vr[ITEMS], ar[ITEMS], zbr[ITEMS], xbr[ITEMS];
   bool zr[ITEMS];
 #pragma unroll
@@ -147,16 +149,27 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     xbr[it] = (it < xitems && i < a.n_in) ? a.xbar[(int64_t)b * a.n_in + i] : 0.0;
     zr[it] = false;
   }
-  for (int k = tid; k < a.n_out; k += FWD_NT) yst[k] = a.Y[(int64_t)b * a.n_out + k];
   if (tid == 0) s_events = 0ull;
   unsigned long long spikes = 0ull;
-  const int label = a.labels[b];
+  int scan_buf = 0;
   __syncthreads();
 
+  // Barriers per step: the scan's, one before propagation and one before the
+  // neuron update.  Nothing needs one at the end of a step: each thread
+  // clears only the acc entries it read itself, the input bits alternate
+  // between two buffers (a buffer is cleared after the next scan's barrier),
+  // and zlist is rewritten only after the next scan's barrier.
   for (int tau = 0; tau < a.nsteps; ++tau) {
-    for (int q = tid; q < xwords; q += FWD_NT) xflags[q] = 0u;
+    uint32_t* xflags = xflags2 + (tau & 1) * xwords;
     // ---- spikes, surrogate derivative, ordered compaction of the spike list
     int nz = 0;
+    const int nx = s_xcnt[tau];
+    const int* xs = xstaged ? xbuf + xpos[tau] : a.x_idx + s_xsrc[tau];
+    // input spikes of (t, b) as bits, published by the scan's barrier
+    for (int q = tid; q < nx; q += FWD_NT) {
+      const int i = xs[q];
+      if ((unsigned)i < (unsigned)a.n_in) atomicOr(&xflags[i >> 5], 1u << (i & 31));
+    }
 #pragma unroll
     for (int it = 0; it < ITEMS; ++it) {
       if (it >= items) break;
@@ -171,41 +184,58 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       }
       zr[it] = z;
       int tot;
-      const int off = block_scan_flag_fwd(z, s_wave, &tot);
+      const int off = block_scan_flag_fwd(z, s_wave[scan_buf], &tot);
+      scan_buf ^= 1;
       if (z) zlist[nz + off] = j;
       nz += tot;
     }
     spikes += (unsigned long long)nz;
+    __syncthreads();  // zlist, acc and xflags complete
+    // the other parity's bits were last read in the previous step's update,
+    // before this step's scan barrier, and are next set after this step's
+    // update barrier
+    for (int q = tid; q < xwords; q += FWD_NT) xflags2[((tau + 1) & 1) * xwords + q] = 0u;
 
-    // ---- input spikes of (t, b)
-    const int nx = s_xcnt[tau];
-    const int* xs = xstaged ? xbuf + xpos[tau] : a.x_idx + s_xsrc[tau];
-    for (int q = tid; q < nx; q += FWD_NT) {
-      const int i = xs[q];
-      if ((unsigned)i < (unsigned)a.n_in) atomicOr(&xflags[i >> 5], 1u << (i & 31));
-    }
-    __syncthreads();
-
-    // ---- propagation: one wave per spiking row, lanes over the row's slots
+    // ---- propagation: one wave per spiking row, lanes over the row's slots;
+    // up to PROP_U slots per lane are loaded before any LDS atomic, so a row
+    // of up to 256 slots costs one memory latency
     unsigned long long ev = 0ull;
     for (int r = wv; r < nx + nz; r += FWD_NT / WAVE) {
       const bool from_in = r < nx;
       const int i = from_in ? xs[r] : zlist[r - nx];
-      if (from_in && (unsigned)i >= (unsigned)a.n_in) continue;  // rejected at set_input; never read
+      if (from_in && (unsigned)i >= (unsigned)a.n_in) continue;  // out-of-range channel: ignored
       const int* ind = from_in ? a.ind_in : a.ind_rec;
       const float* w = from_in ? a.w_in : a.w_rec;
       const int cap = from_in ? a.cap_in : a.cap_rec;
       const int n = from_in ? len_in[i] : len_rec[i];
       const int64_t base = (int64_t)i * cap;
       ev += (unsigned long long)n;
-      for (int k = lane; k < n; k += WAVE) {
-        const int j = ind[base + k];
-        const long long q = __double2ll_rn((double)w[base + k] * FIX_SCALE);
-        atomicAdd((unsigned long long*)&acc[j], (unsigned long long)q);
+      for (int c0 = 0; c0 < n; c0 += PROP_U * WAVE) {
+        int jj[PROP_U];
+        float ww[PROP_U];
+#pragma unroll
+        for (int u = 0; u < PROP_U; ++u) {
+          const int k = c0 + u * WAVE + lane;
+          jj[u] = k < n ? ind[base + k] : -1;
+          ww[u] = k < n ? w[base + k] : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < PROP_U; ++u)
+          if (jj[u] >= 0)
+            atomicAdd((unsigned long long*)&acc[jj[u]], (unsigned long long)__double2ll_rn((double)ww[u] * FIX_SCALE));
       }
     }
     if (lane == 0 && ev) atomicAdd(&s_events, ev);
-    __syncthreads();
+
+    // ---- readout drive u_k = sum_j W_out[k][j] z_j: one wave per output unit
+    for (int k = wv; k < a.n_out; k += FWD_NT / WAVE) {
+      float s = 0.0f;
+      const float* wk = wout + (int64_t)k * a.n_rec;
+      for (int l = lane; l < nz; l += WAVE) s += wk[zlist[l]];
+      s = wave_sum(s);
+      if (lane == 0) a.u[((int64_t)tau * B + b) * a.n_out + k] = s;
+    }
+    __syncthreads();  // acc complete
 
     // ---- neuron update, traces
 #pragma unroll
@@ -228,54 +258,12 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       if (it >= xitems) break;
       const int i = it * FWD_NT + tid;
       if (i < a.n_in) {
-        const double x = ((xflags[i >> 5] >> (i & 31)) & 1u) ? 1.0 : 0.0;
+        const uint32_t wd = xflags[i >> 5];
+        const double x = ((wd >> (i & 31)) & 1u) ? 1.0 : 0.0;
         a.xbar_prev[((int64_t)tau * B + b) * a.n_in + i] = (float)xbr[it];
         xbr[it] = a.alpha * xbr[it] + x;
       }
     }
-
-    // ---- leaky readout: one wave per output unit over the spike list
-    for (int k = wv; k < a.n_out; k += FWD_NT / WAVE) {
-      float s = 0.0f;
-      const float* wk = wout + (int64_t)k * a.n_rec;
-      for (int l = lane; l < nz; l += WAVE) s += wk[zlist[l]];
-      s = wave_sum(s);
-      if (lane == 0) {
-        const double y = a.alpha * yst[k] + (double)s + (double)a.bout[k];
-        yst[k] = y;
-        ylds[k] = (float)y;
-      }
-    }
-    __syncthreads();
-
-    // ---- softmax and output error (wave 0)
-    if (wv == 0) {
-      float m = -INFINITY;
-      for (int k = lane; k < a.n_out; k += WAVE) m = fmaxf(m, ylds[k]);
-      m = wave_max(m);
-      float den = 0.0f;
-      for (int k = lane; k < a.n_out; k += WAVE) den += expf(ylds[k] - m);
-      den = wave_sum(den);
-      for (int k = lane; k < a.n_out; k += WAVE) {
-        const float d = expf(ylds[k] - m) / den - (k == label ? 1.0f : 0.0f);
-        dlds[k] = d;
-        a.delta[((int64_t)tau * B + b) * a.n_out + k] = d;
-      }
-    }
-    __syncthreads();
-
-    // ---- learning signal through B = W_out^T
-#pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      if (it >= items) break;
-      const int j = it * FWD_NT + tid;
-      if (j < a.n_rec) {
-        float l = 0.0f;
-        for (int k = 0; k < a.n_out; ++k) l += wout[(int64_t)k * a.n_rec + j] * dlds[k];
-        a.L[((int64_t)tau * B + b) * a.n_rec + j] = l;
-      }
-    }
-    __syncthreads();  // LDS (acc, zlist, xflags, dlds) is reused by the next step
   }
 
   // ---- write back the state and the last step's spikes
@@ -297,7 +285,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     const int i = it * FWD_NT + tid;
     if (i < a.n_in) a.xbar[(int64_t)b * a.n_in + i] = xbr[it];
   }
-  for (int k = tid; k < a.n_out; k += FWD_NT) a.Y[(int64_t)b * a.n_out + k] = yst[k];
+  __syncthreads();
   if (tid == 0) {
     atomicAdd(&a.counters[0], s_events);
     atomicAdd(&a.counters[1], spikes);
@@ -337,6 +325,101 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
   else if (need <= 2) hipLaunchKernelGGL(k_fwd<2>, dim3(a.B), dim3(FWD_NT), sm, s, a);
   else if (need <= 4) hipLaunchKernelGGL(k_fwd<4>, dim3(a.B), dim3(FWD_NT), sm, s, a);
   else hipLaunchKernelGGL(k_fwd<8>, dim3(a.B), dim3(FWD_NT), sm, s, a);
+}
+
+// Leaky readout and softmax error over a block (recurrent classifier
+// section): one wave per instance b, lane k (and k + 64, ...) carrying output
+// k through the block's steps,
+//   y_k <- alpha y_k + u_k + b_k   (double),   delta_k = softmax(y)_k - [k == label_b],
+// with the softmax maximum and denominator reduced across the wave.  delta
+// goes into the ring [k][slot][b].  Labels outside 0..n_out-1 contribute no
+// target term.
+constexpr int RO_KMAX = 4;  // n_out <= 4 * WAVE
+__global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) {
+  const int b = blockIdx.x * 4 + wave_id(), lane = lane_id();
+  if (b >= a.B) return;
+  const int label = a.labels[b];
+  double y[RO_KMAX];
+  float bias[RO_KMAX];
+#pragma unroll
+  for (int q = 0; q < RO_KMAX; ++q) {
+    const int k = q * WAVE + lane;
+    y[q] = k < a.n_out ? a.Y[(int64_t)b * a.n_out + k] : 0.0;
+    bias[q] = k < a.n_out ? a.bout[k] : 0.0f;
+  }
+  for (int tau = 0; tau < a.nsteps; ++tau) {
+    const float* u = a.u + ((int64_t)tau * a.B + b) * a.n_out;
+    float m = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < RO_KMAX; ++q) {
+      const int k = q * WAVE + lane;
+      if (k < a.n_out) {
+        y[q] = a.alpha * y[q] + (double)u[k] + (double)bias[q];
+        m = fmaxf(m, (float)y[q]);
+      }
+    }
+    m = wave_max(m);
+    float den = 0.0f;
+#pragma unroll
+    for (int q = 0; q < RO_KMAX; ++q)
+      if (q * WAVE + lane < a.n_out) den += expf((float)y[q] - m);
+    den = wave_sum(den);
+#pragma unroll
+    for (int q = 0; q < RO_KMAX; ++q) {
+      const int k = q * WAVE + lane;
+      if (k < a.n_out) {
+        const float d = expf((float)y[q] - m) / den - (k == label ? 1.0f : 0.0f);
+        a.deltaT[((int64_t)k * a.nslot + a.slot0 + tau) * a.B + b] = d;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < RO_KMAX; ++q) {
+    const int k = q * WAVE + lane;
+    if (k < a.n_out) a.Y[(int64_t)b * a.n_out + k] = y[q];
+  }
+}
+
+// Learning signal L_j = sum_k W_out[k][j] delta_k (recurrent classifier
+// section), written straight into the ring [j][slot][b]: lanes over
+// instances, each thread 16 consecutive neurons of a 64-neuron tile whose
+// readout weights are staged in LDS.  blockIdx = (neuron tile, instance tile,
+// step).
+__global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
+  __shared__ float w[64][65];  // [k in chunk][j in tile]
+  const int j0 = blockIdx.x * 64, b = blockIdx.y * 64 + lane_id(), tau = blockIdx.z;
+  const int jq = wave_id() * 16;  // this wave's 16 neurons of the tile
+  const bool act = b < a.B;
+  float acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
+  for (int k0 = 0; k0 < a.n_out; k0 += 64) {
+    const int kn = min(64, a.n_out - k0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int kk = e / 64, jj = e % 64;
+      w[kk][jj] = (kk < kn && j0 + jj < a.n_rec) ? a.Wout[(int64_t)(k0 + kk) * a.n_rec + j0 + jj] : 0.0f;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kn; ++kk) {
+      const float d = act ? a.deltaT[((int64_t)(k0 + kk) * a.nslot + a.slot0 + tau) * a.B + b] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = fmaf(w[kk][jq + q], d, acc[q]);
+    }
+  }
+  if (!act) return;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int j = j0 + jq + q;
+    if (j < a.n_rec) a.LT[((int64_t)j * a.nslot + a.slot0 + tau) * a.B + b] = acc[q];
+  }
+}
+
+void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal) {
+  if (a.nsteps <= 0) return;
+  hipLaunchKernelGGL(k_readout, dim3((a.B + 3) / 4), dim3(256), 0, s, a);
+  if (learning_signal)
+    hipLaunchKernelGGL(k_learning_signal, dim3((a.n_rec + 63) / 64, (a.B + 63) / 64, a.nsteps), dim3(256), 0, s, a);
 }
 
 // ---------------------------------------------------------------------------
@@ -463,23 +546,65 @@ __host__ __device__ inline int readout_groups(int n_rec, int nw) {
 // takes synapses w, w + 4, ... of the list.  psi_j and L_j of the block's
 // steps for the current 256-instance chunk are staged once in LDS (32 KB) and
 // shared by the workgroup's waves, so a synapse step costs one gathered
-// presynaptic trace and seven float operations per instance (ALIF):
-//   x = psi p,  c = (1 - rho) + psi beta,  d = x - c eps,  e = d + (1 - rho) eps,
-//   eps' = eps + d,  ebar' = alpha ebar + e,  g += L ebar'
-// which is e = psi (p - beta eps) and eps' = psi p + (rho - psi beta) eps of
-// eq. eprop_elig_1/2 (eprop_elig_lif without eps).  rho is within 5e-4 of one:
-// carrying 1 - rho instead of a float rho keeps the slow eps decay free of a
+// presynaptic trace and six float operations per instance (ALIF):
+//   e = psi (p - beta eps),  d = e - (1 - rho) eps,  eps' = eps + d,
+//   ebar' = alpha ebar + e,  g += L ebar'
+// which is eq. eprop_elig_1/2 (eprop_elig_lif without eps), with
+// eps' = psi p + (rho - psi beta) eps.  rho is within 5e-4 of one: carrying
+// 1 - rho instead of a float rho keeps the slow eps decay free of a
 // systematic 3e-8 per step.  The gradient is summed per lane over the steps
 // and its four instances, reduced once per synapse and chunk, and added to G
 // in chunk order by the one wave that owns the synapse, so the result does
 // not depend on scheduling or on the order of the column list.
-constexpr int WL_CH = 4 * WAVE;  // instances per chunk
+constexpr int WL_CH = 4 * WAVE;  // instances per LDS chunk
+constexpr int WL_IPL = 4;  // instances per lane (2 doubles the waves and measured slower)
 
-template <bool ALIF>
-__global__ void __launch_bounds__(EP_NT) k_eprop_wl(EpropArgs a) {
-  __shared__ f4 s_psi[COL_TB][WAVE], s_L[COL_TB][WAVE];
+// IPL instances per lane (2 or 4); NH = 4 / IPL wave groups split a chunk's
+// 256 instances, so a workgroup has 4 * NH waves and wave w works on half
+// w / 4 of the chunk and on synapses w % 4, w % 4 + 4, ...
+template <int IPL> struct VecT;
+template <> struct VecT<2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecT<4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type buf_ldv(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  typedef typename VecT<IPL>::type V;
+  if constexpr (IPL == 4)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type buf_ldv_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef typename VecT<IPL>::type V;
+  if constexpr (IPL == 4)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, BUF_NT));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, BUF_NT));
+}
+template <int IPL>
+__device__ __forceinline__ void buf_stv_nt(typename VecT<IPL>::type v, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef unsigned U __attribute__((ext_vector_type(IPL)));
+  if constexpr (IPL == 4)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
+}
+template <int IPL>
+__device__ __forceinline__ float hsum(typename VecT<IPL>::type v) {
+  if constexpr (IPL == 4) return (v.x + v.y) + (v.z + v.w);
+  else return v.x + v.y;
+}
+
+template <bool ALIF, int IPL>
+__global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
+  typedef typename VecT<IPL>::type V;
+  constexpr int NH = 4 / IPL;
+  constexpr int LPC = WL_CH / IPL;  // lanes across a chunk: 64 * NH vectors per step
+  __shared__ V s_psi[COL_TB][LPC], s_L[COL_TB][LPC];
+  __shared__ float gpart[NH][WAVE];
   const int wv = wave_id(), lane = lane_id();
-  const int nw = blockDim.x / WAVE;
+  const int nw = blockDim.x / WAVE;  // 4 * NH
   const int n_ro = readout_groups(a.n_rec, nw);
   if ((int)blockIdx.x < n_ro) {
     readout_grad(a, blockIdx.x * nw + wv, lane);
@@ -489,108 +614,94 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_wl(EpropArgs a) {
   const int j = wg / COL_OCT;
   const int q0 = a.col_off[wg], q1 = a.col_off[wg + 1];
   if (q1 <= q0) return;
+  const int half = wv / 4, sub = wv % 4;
   const int B = a.B, T = a.nsteps;
   const int n_ch = (B + WL_CH - 1) / WL_CH;
   const uint32_t step_bytes = (uint32_t)B * 4u, blk_bytes = (uint32_t)T * step_bytes;
   const float alpha = a.alpha, omr = a.one_m_rho, beta = a.beta;
-  const f4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  V zero;
+#pragma unroll
+  for (int e = 0; e < IPL; ++e) zero[e] = 0.0f;
+  auto st_off = [&](int t) { return (uint32_t)(t < T ? t : T - 1) * step_bytes; };
   for (int m = 0; m < n_ch; ++m) {
-    const int b0 = m * WL_CH + 4 * lane;
+    const int lv = half * WAVE + lane;  // this lane's vector within the chunk
+    const int b0 = m * WL_CH + IPL * lv;
     const bool act = b0 < B;
     const uint32_t off = (uint32_t)(act ? b0 : 0) * 4u;  // idle lanes read instance 0, never store
     __syncthreads();  // the previous chunk's psi/L are no longer read
     {
       const auto rp = buf_rsrc(a.psiT + ring(a, j, 0), blk_bytes);
       const auto rl = buf_rsrc(a.LT + ring(a, j, 0), blk_bytes);
-      for (int t = wv; t < COL_TB; t += nw) {
-        const uint32_t st = (uint32_t)(t < T ? t : T - 1) * step_bytes;
-        s_psi[t][lane] = buf_ld4(rp, off, st);
-        s_L[t][lane] = act && t < T ? buf_ld4(rl, off, st) : zero4;
+      for (int t = sub; t < COL_TB; t += 4) {
+        s_psi[t][lv] = buf_ldv<IPL>(rp, off, st_off(t));
+        s_L[t][lv] = act && t < T ? buf_ldv<IPL>(rl, off, st_off(t)) : zero;
       }
     }
     __syncthreads();
-    // Synapses of this wave: q = q0 + wv, q + nw, ...  The next synapse's
-    // records are loaded during step group 1 and its first four presynaptic
-    // steps during group 3 of the current one.
-    struct Cur {
-      __amdgpu_buffer_rsrc_t pre, eb, ep;
-      int2 ent;
-    };
-    auto decode = [&](int q) {
-      Cur c;
-      c.ent = a.col[q];
-      const bool fin = c.ent.x < a.n_in;
-      const int i = fin ? c.ent.x : c.ent.x - a.n_in;
-      c.pre = buf_rsrc((fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0), blk_bytes);
-      const int64_t rec = (int64_t)c.ent.y * B;
-      c.eb = buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
-      c.ep = buf_rsrc(ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : a.in.ebar, step_bytes);
-      return c;
-    };
-    auto st_off = [&](int t) { return (uint32_t)(t < T ? t : T - 1) * step_bytes; };
-    int q = q0 + wv;
-    Cur nx{};
-    f4 eb_n = zero4, ep_n = zero4, p_n[4];
-    if (q < q1) {
-      nx = decode(q);
-      eb_n = buf_ld4x<BUF_NT>(nx.eb, off);
-      if (ALIF) ep_n = buf_ld4x<BUF_NT>(nx.ep, off);
+    for (int sc = q0; sc < q1; sc += WAVE) {  // chunks of 64 list entries
+      const int ns = min(WAVE, q1 - sc);
+      for (int k = sub; k < ns; k += 4) {
+        // keeps the per-step LDS reads and the trace loads inside their
+        // groups (hoisted, they would cost registers, hence occupancy)
+        __asm__ volatile("" ::: "memory");
+        const int2 ent = a.col[sc + k];
+        const bool fin = ent.x < a.n_in;
+        const int i = fin ? ent.x : ent.x - a.n_in;
+        const auto rpre = buf_rsrc((fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0), blk_bytes);
+        const int64_t rec = (int64_t)ent.y * B;
+        const auto reb = buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
+        const auto rep = buf_rsrc(ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : a.in.ebar, step_bytes);
+        V eb = buf_ldv_nt<IPL>(reb, off);
+        V ep = ALIF ? buf_ldv_nt<IPL>(rep, off) : zero;
+        // presynaptic traces in groups of four steps, each group loaded while
+        // the previous one is computed
+        V p[COL_TB];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) p_n[t] = buf_ld4(nx.pre, off, st_off(t));
-    }
-    for (; q < q1; q += nw) {
-      // the empty asm statements keep the compiler from hoisting every load
-      // (and the loop-invariant LDS reads) ahead: registers, hence occupancy
-      __asm__ volatile("" ::: "memory");
-      const Cur cu = nx;
-      const bool more = q + nw < q1;
-      f4 eb = eb_n, ep = ep_n;
-      f4 p[COL_TB];
+        for (int t = 0; t < 4; ++t) p[t] = buf_ldv<IPL>(rpre, off, st_off(t));
+        V g = zero;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) p[t] = p_n[t];
-      f4 g = zero4;
+        for (int t = 0; t < COL_TB; ++t) {
+          if (t % 4 == 0) {
+            __asm__ volatile("" ::: "memory");
+            if (t + 4 < COL_TB) {
 #pragma unroll
-      for (int t = 0; t < COL_TB; ++t) {
-        if (t % 4 == 0) {
-          __asm__ volatile("" ::: "memory");
-          if (t + 4 < COL_TB) {
-#pragma unroll
-            for (int u = t + 4; u < t + 8; ++u) p[u] = buf_ld4(cu.pre, off, st_off(u));
+              for (int u = t + 4; u < t + 8; ++u) p[u] = buf_ldv<IPL>(rpre, off, st_off(u));
+            }
           }
-          if (t == 4 && more) {
-            nx = decode(q + nw);
-            eb_n = buf_ld4x<BUF_NT>(nx.eb, off);
-            if (ALIF) ep_n = buf_ld4x<BUF_NT>(nx.ep, off);
-          }
-          if (t == 12 && more) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) p_n[u] = buf_ld4(nx.pre, off, st_off(u));
+          if (t < T) {
+            const V psi = s_psi[t][lv], L = s_L[t][lv];
+            if (ALIF) {
+              const V e = psi * (p[t] - beta * ep);
+              const V d = e - omr * ep;
+              ep = ep + d;
+              eb = alpha * eb + e;
+            } else {
+              eb = alpha * eb + psi * p[t];
+            }
+            g = g + L * eb;
           }
         }
-        if (t < T) {
-          const f4 psi = s_psi[t][lane], L = s_L[t][lane];
-          const f4 x = psi * p[t];
-          if (ALIF) {
-            const f4 c = psi * beta + omr;
-            const f4 d = x - c * ep;
-            const f4 e = d + omr * ep;
-            ep = ep + d;
-            eb = alpha * eb + e;
-          } else {
-            eb = alpha * eb + x;
-          }
-          g = g + L * eb;
+        if (act) {
+          buf_stv_nt<IPL>(eb, reb, off);
+          if (ALIF) buf_stv_nt<IPL>(ep, rep, off);
+        }
+        const float gs = wave_sum(hsum<IPL>(g));
+        if (NH == 1) {
+          if (lane == 0) (fin ? a.in.G : a.rec.G)[ent.y] += gs;
+        } else if (lane == 0) {
+          gpart[half][k] = gs;
         }
       }
-      const bool fin = cu.ent.x < a.n_in;
-      if (act) {
-        buf_st4<BUF_NT>(eb, cu.eb, off);
-        if (ALIF) buf_st4<BUF_NT>(ep, cu.ep, off);
-      }
-      const float gs = wave_sum((g.x + g.y) + (g.z + g.w));
-      if (lane == 0) {
-        float* G = fin ? a.in.G : a.rec.G;
-        G[cu.ent.y] += gs;
+      if (NH > 1) {  // halves of each synapse, added in half order
+        __syncthreads();
+        if ((int)threadIdx.x < ns) {
+          const int2 ent = a.col[sc + threadIdx.x];
+          float gsum = 0.0f;
+#pragma unroll
+          for (int h = 0; h < NH; ++h) gsum += gpart[h][threadIdx.x];
+          (ent.x < a.n_in ? a.in.G : a.rec.G)[ent.y] += gsum;
+        }
+        __syncthreads();
       }
     }
   }
@@ -683,8 +794,8 @@ __global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int 
 
 void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot) {
   int nmax = 0;
-  for (int q = 0; q < 6; ++q) nmax = max(nmax, h.n[q]);
-  dim3 grid((nmax + 63) / 64, (B + 63) / 64, 6 * nsteps);
+  for (int q = 0; q < HANDOFF_ARRAYS; ++q) nmax = max(nmax, h.n[q]);
+  dim3 grid((nmax + 63) / 64, (B + 63) / 64, HANDOFF_ARRAYS * nsteps);
   hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B, nsteps, slot0, nslot);
 }
 
@@ -755,14 +866,16 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
   if (a.B % 4 == 0 && a.col && a.col_off) {
-    const int nw = EP_NT / WAVE;
+    const int nw = 4 * (4 / WL_IPL);
     const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_OCT;
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;
       p.slot0 = a.slot0 + t0;
       p.nsteps = min(COL_TB, a.nsteps - t0);
-      if (a.alif) hipLaunchKernelGGL(k_eprop_wl<true>, dim3(blocks), dim3(EP_NT), 0, s, p);
-      else hipLaunchKernelGGL(k_eprop_wl<false>, dim3(blocks), dim3(EP_NT), 0, s, p);
+      // the step count stays a runtime value: fixed at 16, the compiler
+      // schedules for registers beyond the occupancy the LDS allows
+      if (a.alif) hipLaunchKernelGGL((k_eprop_wl<true, WL_IPL>), dim3(blocks), dim3(nw * WAVE), 0, s, p);
+      else hipLaunchKernelGGL((k_eprop_wl<false, WL_IPL>), dim3(blocks), dim3(nw * WAVE), 0, s, p);
     }
   } else {
     const int n_rows = a.n_in + a.n_rec;

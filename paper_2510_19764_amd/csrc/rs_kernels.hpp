@@ -46,33 +46,46 @@ struct FwdArgs {
   int n_in, n_rec, n_out, B;
   double alpha, rho, v_thr, beta;            // recurrences are evaluated in double
   double psi_scale;                          // 0.3 / v_thr
-  double* V; double* A; double* Y;           // [B][n_rec], [B][n_rec], [B][n_out]
+  double* V; double* A;                      // [B][n_rec]
   double* xbar; double* zbar;                // [B][n_in], [B][n_rec] trace masters
   // hand-off of step tau, instance-major staging [tau][B][n] (coalesced writes):
   float* xbar_prev;                          // n = n_in: trace before this step's input
   float* zbar_prev; float* zbar_new;         // n = n_rec: before / after this step's spikes
-  float* psi; float* L;                      // n = n_rec
-  float* delta;                              // n = n_out
+  float* psi;                                // n = n_rec
+  float* u;                                  // n = n_out: readout drive sum_j W_out[k][j] z_j
   uint8_t* z;                                // [B][n_rec]
   const int* len_in; const int* ind_in; const float* w_in; int cap_in;
   const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
-  const float* Wout; const float* bout;      // [n_out][n_rec], [n_out]
+  const float* Wout;                         // [n_out][n_rec]
   const int* x_off; const int* x_idx; long long n_idx;
   int t0, sample_steps, nsteps;              // steps t0 .. t0+nsteps-1 (raster step t % sample_steps)
   int wout_lds;                              // 1: stage W_out in LDS for the block
   int xcap;                                  // LDS capacity for the block's input spike lists
-  const int* labels;
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
 };
 // One launch runs `nsteps` consecutive steps into the staging buffers.
 void launch_fwd(hipStream_t s, const FwdArgs& a);
 
-// Move the staged hand-off of `nsteps` steps ([tau][B][n] for each of the six
-// arrays) into the e-prop ring ([n][nslot][B], slots slot0 + tau).
+// Readout over a block: y, softmax error delta into the ring, and (if asked)
+// the learning signal L = W_out^T delta into the ring.
+struct ReadoutArgs {
+  int n_rec, n_out, B, nsteps, slot0, nslot;
+  double alpha;
+  const float* u;                            // staging [tau][B][n_out]
+  double* Y;                                 // [B][n_out] readout state
+  const float* Wout; const float* bout;      // [n_out][n_rec], [n_out]
+  const int* labels;                         // [B]
+  float* deltaT; float* LT;                  // rings [n_out][nslot][B], [n_rec][nslot][B]
+};
+void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal);
+
+// Move the staged hand-off of `nsteps` steps ([tau][B][n] for each array) into
+// the e-prop ring ([n][nslot][B], slots slot0 + tau).
+constexpr int HANDOFF_ARRAYS = 4;  // xbar_prev, zbar_prev, zbar_new, psi
 struct HandoffArrays {
-  const float* src[6];
-  float* dst[6];
-  int n[6];
+  const float* src[HANDOFF_ARRAYS];
+  float* dst[HANDOFF_ARRAYS];
+  int n[HANDOFF_ARRAYS];
 };
 void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot);
 
