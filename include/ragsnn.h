@@ -133,15 +133,17 @@ rs_status rs_eprop_rewire(rs_eprop* net, uint32_t proj, rs_rewire_stats* stats);
 /* Zero neuron, readout and eligibility-trace state (sample boundary). */
 rs_status rs_eprop_reset(rs_eprop* net);
 
-/* Variable identifiers for rs_eprop_get / rs_eprop_set.  Per-neuron and
- * readout state is double (it is small, and its rounding would otherwise drift
- * the surrogate derivative); synapse state is float.  Network variables
- * (element type, layout): */
+/* Variable identifiers for rs_eprop_get / rs_eprop_set.  Membrane, adaptation
+ * and readout state is double (it is small, and its rounding would otherwise
+ * drift the surrogate derivative); the presynaptic traces are float, updated
+ * as F <- fma(alpha, F, spike) so that the e-prop kernels can rebuild every
+ * step's value exactly from a block's start value and spike bits; synapse
+ * state is float.  Network variables (element type, layout): */
 #define RS_V 0x01      /* double[batch][n_rec]  membrane voltage */
 #define RS_A 0x02      /* double[batch][n_rec]  adaptation */
 #define RS_Y 0x03      /* double[batch][n_out]  readout */
-#define RS_XBAR 0x04   /* double[batch][n_in]   filtered input spikes */
-#define RS_ZBAR 0x05   /* double[batch][n_rec]  filtered recurrent spikes */
+#define RS_XBAR 0x04   /* float[batch][n_in]    filtered input spikes */
+#define RS_ZBAR 0x05   /* float[batch][n_rec]   filtered recurrent spikes */
 #define RS_PSI 0x06    /* float[n_rec][batch]   surrogate derivative of the last step */
 #define RS_LSIG 0x07   /* float[n_rec][batch]   learning signal of the last step */
 #define RS_DELTA 0x08  /* float[n_out][batch]   softmax - one-hot of the last step */

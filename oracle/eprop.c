@@ -148,9 +148,9 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         }
         /* 5. presynaptic traces */
         for (int32_t i = 0; i < NI; ++i)
-            N->xbar[(int64_t)b * NI + i] = N->alpha * N->xbar[(int64_t)b * NI + i] + x[i];
+            N->xbar[(int64_t)b * NI + i] = N->alpha_trace * N->xbar[(int64_t)b * NI + i] + x[i];
         for (int32_t j = 0; j < NR; ++j)
-            N->zbar[(int64_t)b * NR + j] = N->alpha * N->zbar[(int64_t)b * NR + j] + zb[j];
+            N->zbar[(int64_t)b * NR + j] = N->alpha_trace * N->zbar[(int64_t)b * NR + j] + zb[j];
         /* 6. leaky readout, softmax, output error */
         double *yb = N->y + (int64_t)b * K;
         double ymax = -INFINITY;

@@ -75,6 +75,8 @@ typedef struct orc_net {
     int32_t n_in, n_rec, n_out, batch;
     int32_t alif;           /* 0: LIF (beta = rho = 0) */
     double alpha, rho, v_thr, beta;
+    double alpha_trace;     /* decay of the presynaptic traces xbar, zbar (equals
+                               alpha unless a test passes a rounded value) */
     orc_proj *in, *rec;
     double *v, *a;          /* [B][n_rec] */
     double *y;              /* [B][n_out] */

@@ -230,7 +230,7 @@ class EpropNet:
         c, inf = self.cfg, self._info
         B, NR, NI, K = c.batch, c.n_rec, c.n_in, c.n_out
         net = {V: ((B, NR), np.float64), A: ((B, NR), np.float64), Y: ((B, K), np.float64),
-               XBAR: ((B, NI), np.float64), ZBAR: ((B, NR), np.float64), PSI: ((NR, B), np.float32),
+               XBAR: ((B, NI), np.float32), ZBAR: ((B, NR), np.float32), PSI: ((NR, B), np.float32),
                LSIG: ((NR, B), np.float32), DELTA: ((K, B), np.float32), Z: ((B, NR), np.uint8),
                WOUT: ((K, NR), np.float32), BOUT: ((K,), np.float32), GOUT: ((K, NR), np.float32),
                GB: ((K,), np.float32), MOUT: ((K, NR), np.float32), VOUT: ((K, NR), np.float32),

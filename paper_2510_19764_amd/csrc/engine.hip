@@ -128,15 +128,17 @@ struct rs_eprop {
   ProjDev in{}, rec{};
   ColumnView cv{};                                    // target-major view of both projections
   double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
-  double *xbar = nullptr, *zbar = nullptr;            // fp64 trace masters [B][n]
+  float *xbar = nullptr, *zbar = nullptr;             // presynaptic traces [B][n]
   // Hand-off from the forward kernel to the e-prop kernel: a ring of 2K step
   // slots laid out [n][2K][B].  Steps are grouped in blocks of K; the forward
   // pass fills one half while the e-prop launch of the previous block reads
   // the other.
-  float *xbar_prevT = nullptr, *zbar_prevT = nullptr, *zbar_newT = nullptr;
   float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
+  // per block half: traces at the block start and the block's spike bits, [2][n][B]
+  float *x0T = nullptr, *z0T = nullptr;
+  uint32_t *xbitsT = nullptr, *zbitsT = nullptr;
   // the forward kernel's coalesced staging of one block, [tau][B][n]
-  float *stg[HANDOFF_ARRAYS] = {};
+  uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [K][B][NR]; x0, z0, xbits, zbits [B][n]
   float *u_stg = nullptr;                             // readout drive [2 halves][K][B][n_out]
   int K = 8, nslot = 16;
   int blk_half = 0, blk_n = 0, last_slot = 0;
@@ -270,19 +272,21 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
+  TRY(ar.alloc(&n->x0T, 2 * NI * B));
+  TRY(ar.alloc(&n->z0T, 2 * NR * B));
+  TRY(ar.alloc(&n->xbitsT, 2 * NI * B));
+  TRY(ar.alloc(&n->zbitsT, 2 * NR * B));
   n->K = prm->trace_block ? (int)prm->trace_block : 16;
   n->nslot = 2 * n->K;
   const size_t NS = (size_t)n->nslot;
-  TRY(ar.alloc(&n->xbar_prevT, NI * NS * B));
-  TRY(ar.alloc(&n->zbar_prevT, NR * NS * B));
-  TRY(ar.alloc(&n->zbar_newT, NR * NS * B));
   TRY(ar.alloc(&n->psiT, NR * NS * B));
   TRY(ar.alloc(&n->LT, NR * NS * B));
   TRY(ar.alloc(&n->deltaT, K * NS * B));
   {
     const size_t KB = (size_t)n->K * B;
-    const size_t dims[HANDOFF_ARRAYS] = {NI, NR, NR, NR};  // xbar_prev, zbar_prev, zbar_new, psi
-    for (int q = 0; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], KB * dims[q]));
+    TRY(ar.alloc(&n->stg[0], KB * NR));                   // psi
+    const size_t dims[HANDOFF_ARRAYS] = {NR, NI, NR, NI, NR};  // psi, x0, z0, xbits, zbits
+    for (int q = 1; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], (size_t)B * dims[q]));
     TRY(ar.alloc(&n->u_stg, 2 * KB * K));
   }
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
@@ -319,11 +323,15 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   launch_columns(s, n->in, n->rec, n->cv);
   zero_proj_state(s, n->in, B);
   zero_proj_state(s, n->rec, B);
-  for (double* q : {n->V, n->A, n->zbar}) launch_fill_zero(s, q, B * NR * 8);
-  for (float* q : {n->psiT, n->LT, n->zbar_prevT, n->zbar_newT}) launch_fill_zero(s, q, B * NR * NS * 4);
-  launch_fill_zero(s, n->xbar_prevT, B * NI * NS * 4);
+  for (double* q : {n->V, n->A}) launch_fill_zero(s, q, B * NR * 8);
+  launch_fill_zero(s, n->zbar, B * NR * 4);
+  for (float* q : {n->psiT, n->LT}) launch_fill_zero(s, q, B * NR * NS * 4);
+  launch_fill_zero(s, n->x0T, 2 * B * NI * 4);
+  launch_fill_zero(s, n->z0T, 2 * B * NR * 4);
+  launch_fill_zero(s, n->xbitsT, 2 * B * NI * 4);
+  launch_fill_zero(s, n->zbitsT, 2 * B * NR * 4);
   launch_fill_zero(s, n->deltaT, B * K * NS * 4);
-  launch_fill_zero(s, n->xbar, B * NI * 8);
+  launch_fill_zero(s, n->xbar, B * NI * 4);
   launch_fill_zero(s, n->Y, B * K * 8);
   launch_fill_zero(s, n->z, B * NR);
   for (float* q : {n->Gout, n->Mout, n->Vout}) launch_fill_zero(s, q, K * NR * 4);
@@ -340,8 +348,8 @@ void reset_state(rs_eprop* n, hipStream_t s) {
   launch_fill_zero(s, n->V, B * NR * 8);
   launch_fill_zero(s, n->A, B * NR * 8);
   launch_fill_zero(s, n->Y, B * K * 8);
-  launch_fill_zero(s, n->xbar, B * NI * 8);
-  launch_fill_zero(s, n->zbar, B * NR * 8);
+  launch_fill_zero(s, n->xbar, B * NI * 4);
+  launch_fill_zero(s, n->zbar, B * NR * 4);
   for (ProjDev* P : {&n->in, &n->rec}) {
     const size_t m = (size_t)P->n_pre * P->cap * B * 4;
     launch_fill_zero(s, P->ebar, m);
@@ -405,10 +413,11 @@ void flush_block(rs_eprop* n) {
   f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
   f.alpha = n->alpha; f.rho = n->rho; f.v_thr = n->p.v_thr; f.beta = n->beta;
   f.psi_scale = 0.3 / (double)n->p.v_thr;
+  f.alpha_f = (float)n->alpha;
   f.V = n->V; f.A = n->A;
   f.xbar = n->xbar; f.zbar = n->zbar;
-  f.xbar_prev = n->stg[0]; f.zbar_prev = n->stg[1]; f.zbar_new = n->stg[2];
-  f.psi = n->stg[3]; f.z = n->z;
+  f.psi = (float*)n->stg[0]; f.x0 = (float*)n->stg[1]; f.z0 = (float*)n->stg[2];
+  f.xbits = n->stg[3]; f.zbits = n->stg[4]; f.z = n->z;
   // the readout drive goes to the block's half, read on the side stream
   f.u = n->u_stg + (size_t)h * n->K * n->B * n->p.n_out;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
@@ -420,10 +429,20 @@ void flush_block(rs_eprop* n) {
   n->timer.begin(s, 0);
   launch_fwd(s, f);
   HandoffArrays ho{};
-  float* dst[HANDOFF_ARRAYS] = {n->xbar_prevT, n->zbar_prevT, n->zbar_newT, n->psiT};
-  const int dims[HANDOFF_ARRAYS] = {(int)n->p.n_in, (int)n->p.n_rec, (int)n->p.n_rec, (int)n->p.n_rec};
-  for (int q = 0; q < HANDOFF_ARRAYS; ++q) { ho.src[q] = n->stg[q]; ho.dst[q] = dst[q]; ho.n[q] = dims[q]; }
-  launch_handoff_transpose(s, ho, n->B, n->blk_n, h * n->K, n->nslot);
+  const size_t NI = n->p.n_in, NR = n->p.n_rec, B = n->B;
+  uint32_t* dst[HANDOFF_ARRAYS] = {(uint32_t*)n->psiT, (uint32_t*)(n->x0T + h * NI * B),
+                                   (uint32_t*)(n->z0T + h * NR * B), n->xbitsT + h * NI * B,
+                                   n->zbitsT + h * NR * B};
+  const int dims[HANDOFF_ARRAYS] = {(int)NR, (int)NI, (int)NR, (int)NI, (int)NR};
+  for (int q = 0; q < HANDOFF_ARRAYS; ++q) {
+    ho.src[q] = n->stg[q];
+    ho.dst[q] = dst[q];
+    ho.n[q] = dims[q];
+    ho.steps[q] = q == 0 ? n->blk_n : 1;  // psi per step into the ring, the rest once per block
+    ho.slot0[q] = q == 0 ? h * n->K : 0;
+    ho.nslot[q] = q == 0 ? n->nslot : 1;
+  }
+  launch_handoff_transpose(s, ho, n->B);
   n->timer.end(s);
   n->last_slot = h * n->K + n->blk_n - 1;
   (void)hipEventRecord(n->ev_fwd, s);
@@ -446,7 +465,9 @@ void flush_block(rs_eprop* n) {
     a.alpha = (float)n->alpha; a.rho = (float)n->rho; a.beta = (float)n->beta;
     a.one_m_rho = (float)(1.0 - n->rho);
     a.in = n->in; a.rec = n->rec;
-    a.xbar_prev = n->xbar_prevT; a.zbar_prev = n->zbar_prevT; a.zbar_new = n->zbar_newT;
+    a.x0 = n->x0T + h * NI * B; a.z0 = n->z0T + h * NR * B;
+    a.xbits = n->xbitsT + h * NI * B; a.zbits = n->zbitsT + h * NR * B;
+    a.tofs = 0;
     a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
     a.slot0 = h * n->K; a.nsteps = n->blk_n; a.nslot = n->nslot;
     a.Gout = n->Gout; a.Gb = n->Gb;
@@ -512,8 +533,8 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_V: *r = {n->V, B * NR * 8}; return true;
       case RS_A: *r = {n->A, B * NR * 8}; return true;
       case RS_Y: *r = {n->Y, B * K * 8}; return true;
-      case RS_XBAR: *r = {n->xbar, NI * B * 8}; return true;
-      case RS_ZBAR: *r = {n->zbar, NR * B * 8}; return true;
+      case RS_XBAR: *r = {n->xbar, NI * B * 4}; return true;
+      case RS_ZBAR: *r = {n->zbar, NR * B * 4}; return true;
       case RS_PSI: *r = {(char*)n->psiT + slot_off, NR * B * 4, NR, pitch}; return !for_write;
       case RS_LSIG: *r = {(char*)n->LT + slot_off, NR * B * 4, NR, pitch}; return !for_write;
       case RS_DELTA: *r = {(char*)n->deltaT + slot_off, K * B * 4, K, pitch}; return !for_write;

@@ -6,7 +6,9 @@
 //   spike compaction with ballots, propagation of input and recurrent spikes
 //   through the ragged rows (one wave per spiking row, lanes over its slots,
 //   accumulation into LDS), neuron update with subtractive reset, presynaptic
-//   traces, and the readout drive u_k = sum_j W_out[k][j] z_j of the step.
+//   traces F <- fma(alpha, F, spike) in float, and the readout drive
+//   u_k = sum_j W_out[k][j] z_j of the step.  Per block it hands over psi of
+//   every step, the traces at the block start and the block's spike bits.
 //   Input currents are accumulated as 64-bit fixed point (2^-36 resolution) so
 //   the sum does not depend on the order of the LDS atomics.
 // k_readout / k_learning_signal: leaky readout, softmax error and learning
@@ -135,8 +137,12 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     }
   }
 
-  // neuron and trace state of this instance stays on chip for the block
-  double vr[ITEMS], ar[ITEMS], zbr[ITEMS], xbr[ITEMS];
+  // neuron and trace state of this instance stays on chip for the block; the
+  // traces at the block start and the block's spike bits go to the e-prop
+  // hand-off, which rebuilds every step's traces from them
+  double vr[ITEMS], ar[ITEMS];
+  float zbr[ITEMS], xbr[ITEMS];
+  uint32_t zbits[ITEMS], xbits[ITEMS];
   bool zr[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
@@ -144,10 +150,15 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     const bool ok = it < items && j < a.n_rec;
     vr[it] = ok ? a.V[(int64_t)b * a.n_rec + j] : 0.0;
     ar[it] = ok ? a.A[(int64_t)b * a.n_rec + j] : 0.0;
-    zbr[it] = ok ? a.zbar[(int64_t)b * a.n_rec + j] : 0.0;
+    zbr[it] = ok ? a.zbar[(int64_t)b * a.n_rec + j] : 0.0f;
+    if (ok) a.z0[(int64_t)b * a.n_rec + j] = zbr[it];
     const int i = it * FWD_NT + tid;
-    xbr[it] = (it < xitems && i < a.n_in) ? a.xbar[(int64_t)b * a.n_in + i] : 0.0;
+    const bool oki = it < xitems && i < a.n_in;
+    xbr[it] = oki ? a.xbar[(int64_t)b * a.n_in + i] : 0.0f;
+    if (oki) a.x0[(int64_t)b * a.n_in + i] = xbr[it];
     zr[it] = false;
+    zbits[it] = 0u;
+    xbits[it] = 0u;
   }
   if (tid == 0) s_events = 0ull;
   unsigned long long spikes = 0ull;
@@ -247,10 +258,8 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
         const double zf = zr[it] ? 1.0 : 0.0;
         vr[it] = a.alpha * (vr[it] - zf * a.v_thr) + I;
         ar[it] = a.rho * ar[it] + zf;
-        const int64_t q = ((int64_t)tau * B + b) * a.n_rec + j;
-        a.zbar_prev[q] = (float)zbr[it];
-        zbr[it] = a.alpha * zbr[it] + zf;
-        a.zbar_new[q] = (float)zbr[it];
+        zbr[it] = fmaf(a.alpha_f, zbr[it], zr[it] ? 1.0f : 0.0f);
+        zbits[it] |= (zr[it] ? 1u : 0u) << tau;
       }
     }
 #pragma unroll
@@ -258,10 +267,9 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       if (it >= xitems) break;
       const int i = it * FWD_NT + tid;
       if (i < a.n_in) {
-        const uint32_t wd = xflags[i >> 5];
-        const double x = ((wd >> (i & 31)) & 1u) ? 1.0 : 0.0;
-        a.xbar_prev[((int64_t)tau * B + b) * a.n_in + i] = (float)xbr[it];
-        xbr[it] = a.alpha * xbr[it] + x;
+        const uint32_t x = (xflags[i >> 5] >> (i & 31)) & 1u;
+        xbr[it] = fmaf(a.alpha_f, xbr[it], (float)x);
+        xbits[it] |= x << tau;
       }
     }
   }
@@ -277,13 +285,17 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       a.A[m] = ar[it];
       a.zbar[m] = zbr[it];
       a.z[m] = (uint8_t)zr[it];
+      a.zbits[m] = zbits[it];
     }
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     if (it >= xitems) break;
     const int i = it * FWD_NT + tid;
-    if (i < a.n_in) a.xbar[(int64_t)b * a.n_in + i] = xbr[it];
+    if (i < a.n_in) {
+      a.xbar[(int64_t)b * a.n_in + i] = xbr[it];
+      a.xbits[(int64_t)b * a.n_in + i] = xbits[it];
+    }
   }
   __syncthreads();
   if (tid == 0) {
@@ -476,56 +488,109 @@ __device__ __forceinline__ void buf_st4(f4 v, __amdgpu_buffer_rsrc_t r, uint32_t
 }
 
 
+// Vectors of IPL consecutive instances (2 or 4) held by one lane.
+template <int IPL> struct VecT;
+template <> struct VecT<2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecT<4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type buf_ldv(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  typedef typename VecT<IPL>::type V;
+  if constexpr (IPL == 4)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type buf_ldv_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef typename VecT<IPL>::type V;
+  if constexpr (IPL == 4)
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, BUF_NT));
+  else
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, BUF_NT));
+}
+template <int IPL>
+__device__ __forceinline__ void buf_stv_nt(typename VecT<IPL>::type v, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
+  typedef unsigned U __attribute__((ext_vector_type(IPL)));
+  if constexpr (IPL == 4)
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
+  else
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
+}
+// One step of a presynaptic trace for each of a lane's instances:
+// F <- fma(alpha, F, spike t), the forward pass's own float recursion.
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type trace_next(
+    typename VecT<IPL>::type f, float alpha, unsigned __attribute__((ext_vector_type(IPL))) w, int t) {
+#pragma unroll
+  for (int e = 0; e < IPL; ++e) f[e] = fmaf(alpha, f[e], (float)((w[e] >> t) & 1u));
+  return f;
+}
+
+template <int IPL>
+__device__ __forceinline__ float hsum(typename VecT<IPL>::type v) {
+  if constexpr (IPL == 4) return (v.x + v.y) + (v.z + v.w);
+  else return v.x + v.y;
+}
+
 // Readout delta rule over the launch's steps (recurrent classifier section):
 // wave j < n_rec adds sum_t sum_b delta_k z_j to Gout[k][j] for every output
-// k, wave n_rec the bias gradient sum_t sum_b delta_k.  Steps are read four at
-// a time with independent loads, so a wave waits once per group, not per step.
+// k, where z_j after step t is rebuilt from the block's start trace and spike
+// bits; wave n_rec adds the bias gradient sum_t sum_b delta_k.  Outputs are
+// taken 16 at a time, so each step's trace is rebuilt once per 16 outputs.
+constexpr int RG_K = 16;
 __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane) {
   if (j > a.n_rec) return;
   const int B = a.B, T = a.nsteps;
   const bool wt = j < a.n_rec;
   const uint32_t step_bytes = (uint32_t)B * 4u, blk = (uint32_t)T * step_bytes;
-  const auto rz = buf_rsrc(a.zbar_new + ring(a, wt ? j : 0, 0), blk);
-  for (int k = 0; k < a.n_out; ++k) {
-    const auto rd = buf_rsrc(a.deltaT + ring(a, k, 0), blk);
-    float g = 0.0f;
-    if (B % 4 == 0) {
-      for (int c = 4 * lane; c < B; c += 4 * WAVE) {
-        const uint32_t off = (uint32_t)c * 4u;
-        for (int t0 = 0; t0 < T; t0 += 4) {
-          f4 d[4], z[4];
+  const auto rz = buf_rsrc(a.z0 + (int64_t)(wt ? j : 0) * B, step_bytes);
+  const auto rb = buf_rsrc(a.zbits + (int64_t)(wt ? j : 0) * B, step_bytes);
+  const int ipl = B % 4 == 0 ? 4 : 1;  // instances per lane
+  for (int k0 = 0; k0 < a.n_out; k0 += RG_K) {
+    float acc[RG_K];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t so = (uint32_t)min(t0 + u, T - 1) * step_bytes;
-            d[u] = buf_ld4(rd, off, so);
-            z[u] = wt ? buf_ld4(rz, off, so) : f4{1.f, 1.f, 1.f, 1.f};
-          }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (t0 + u < T) g += (d[u].x * z[u].x + d[u].y * z[u].y) + (d[u].z * z[u].z + d[u].w * z[u].w);
+    for (int q = 0; q < RG_K; ++q) acc[q] = 0.0f;
+    for (int c = ipl * lane; c < B; c += ipl * WAVE) {
+      const uint32_t off = (uint32_t)c * 4u;
+      f4 z = {1.f, 1.f, 1.f, 1.f};
+      v4u w = {0u, 0u, 0u, 0u};
+      if (wt) {
+        if (ipl == 4) {
+          z = buf_ldv<4>(rz, off, 0);
+          w = __builtin_bit_cast(v4u, buf_ldv<4>(rb, off, 0));
+        } else {
+          z.x = buf_ld(rz, off, 0);
+          w.x = __builtin_bit_cast(uint32_t, buf_ld(rb, off, 0));
         }
+        for (int t = 0; t < a.tofs; ++t) z = trace_next<4>(z, a.alpha, w, t);
       }
-    } else {
-      for (int c = lane; c < B; c += WAVE) {
-        const uint32_t off = (uint32_t)c * 4u;
-        for (int t0 = 0; t0 < T; t0 += 4) {
-          float d[4], z[4];
+      for (int t = 0; t < T; ++t) {
+        if (wt) z = trace_next<4>(z, a.alpha, w, a.tofs + t);  // the trace after step t
+        const uint32_t so = (uint32_t)t * step_bytes;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const uint32_t so = (uint32_t)min(t0 + u, T - 1) * step_bytes;
-            d[u] = buf_ld(rd, off, so);
-            z[u] = wt ? buf_ld(rz, off, so) : 1.0f;
+        for (int q = 0; q < RG_K; ++q) {
+          if (k0 + q < a.n_out) {
+            const auto rd = buf_rsrc(a.deltaT + ring(a, k0 + q, 0), blk);
+            if (ipl == 4) {
+              const f4 d = buf_ldv<4>(rd, off, so);
+              acc[q] += (d.x * z.x + d.y * z.y) + (d.z * z.z + d.w * z.w);
+            } else {
+              acc[q] = fmaf(buf_ld(rd, off, so), z.x, acc[q]);
+            }
           }
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            if (t0 + u < T) g = fmaf(d[u], z[u], g);
         }
       }
     }
-    g = wave_sum(g);
-    if (lane == 0) {
-      if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
-      else a.Gb[k] += g;
+#pragma unroll
+    for (int q = 0; q < RG_K; ++q) {
+      if (k0 + q < a.n_out) {
+        const float g = wave_sum(acc[q]);
+        if (lane == 0) {
+          if (wt) a.Gout[(int64_t)(k0 + q) * a.n_rec + j] += g;
+          else a.Gb[k0 + q] += g;
+        }
+      }
     }
   }
 }
@@ -559,46 +624,13 @@ __host__ __device__ inline int readout_groups(int n_rec, int nw) {
 constexpr int WL_CH = 4 * WAVE;  // instances per LDS chunk
 constexpr int WL_IPL = 4;  // instances per lane (2 doubles the waves and measured slower)
 
-// IPL instances per lane (2 or 4); NH = 4 / IPL wave groups split a chunk's
-// 256 instances, so a workgroup has 4 * NH waves and wave w works on half
-// w / 4 of the chunk and on synapses w % 4, w % 4 + 4, ...
-template <int IPL> struct VecT;
-template <> struct VecT<2> { typedef float type __attribute__((ext_vector_type(2))); };
-template <> struct VecT<4> { typedef float type __attribute__((ext_vector_type(4))); };
-
-template <int IPL>
-__device__ __forceinline__ typename VecT<IPL>::type buf_ldv(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  typedef typename VecT<IPL>::type V;
-  if constexpr (IPL == 4)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, (int)soff, 0));
-  else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
-}
-template <int IPL>
-__device__ __forceinline__ typename VecT<IPL>::type buf_ldv_nt(__amdgpu_buffer_rsrc_t r, uint32_t voff) {
-  typedef typename VecT<IPL>::type V;
-  if constexpr (IPL == 4)
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voff, 0, BUF_NT));
-  else
-    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, BUF_NT));
-}
-template <int IPL>
-__device__ __forceinline__ void buf_stv_nt(typename VecT<IPL>::type v, __amdgpu_buffer_rsrc_t r, uint32_t voff) {
-  typedef unsigned U __attribute__((ext_vector_type(IPL)));
-  if constexpr (IPL == 4)
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
-  else
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, (int)voff, 0, BUF_NT);
-}
-template <int IPL>
-__device__ __forceinline__ float hsum(typename VecT<IPL>::type v) {
-  if constexpr (IPL == 4) return (v.x + v.y) + (v.z + v.w);
-  else return v.x + v.y;
-}
-
+// IPL instances per lane; NH = 4 / IPL wave groups split a chunk's 256
+// instances, so a workgroup has 4 * NH waves and wave w works on half w / 4
+// of the chunk and on synapses w % 4, w % 4 + 4, ...
 template <bool ALIF, int IPL>
 __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
   typedef typename VecT<IPL>::type V;
+  typedef unsigned U __attribute__((ext_vector_type(IPL)));
   constexpr int NH = 4 / IPL;
   constexpr int LPC = WL_CH / IPL;  // lanes across a chunk: 64 * NH vectors per step
   __shared__ V s_psi[COL_TB][LPC], s_L[COL_TB][LPC];
@@ -647,38 +679,34 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
         const int2 ent = a.col[sc + k];
         const bool fin = ent.x < a.n_in;
         const int i = fin ? ent.x : ent.x - a.n_in;
-        const auto rpre = buf_rsrc((fin ? a.xbar_prev : a.zbar_prev) + ring(a, i, 0), blk_bytes);
         const int64_t rec = (int64_t)ent.y * B;
         const auto reb = buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
         const auto rep = buf_rsrc(ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : a.in.ebar, step_bytes);
+        // presynaptic trace of the block start and the block's spike bits;
+        // the trace of each step is rebuilt with the forward pass's float
+        // recursion F <- fma(alpha, F, spike), so it equals the forward's value
+        const auto rx0 = buf_rsrc((fin ? a.x0 : a.z0) + (int64_t)i * B, step_bytes);
+        const auto rbt = buf_rsrc((fin ? a.xbits : a.zbits) + (int64_t)i * B, step_bytes);
         V eb = buf_ldv_nt<IPL>(reb, off);
         V ep = ALIF ? buf_ldv_nt<IPL>(rep, off) : zero;
-        // presynaptic traces in groups of four steps, each group loaded while
-        // the previous one is computed
-        V p[COL_TB];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) p[t] = buf_ldv<IPL>(rpre, off, st_off(t));
+        V pr = buf_ldv<IPL>(rx0, off, 0);
+        const U bits = __builtin_bit_cast(U, buf_ldv<IPL>(rbt, off, 0));
+        for (int t = 0; t < a.tofs; ++t) pr = trace_next<IPL>(pr, alpha, bits, t);
         V g = zero;
 #pragma unroll
         for (int t = 0; t < COL_TB; ++t) {
-          if (t % 4 == 0) {
-            __asm__ volatile("" ::: "memory");
-            if (t + 4 < COL_TB) {
-#pragma unroll
-              for (int u = t + 4; u < t + 8; ++u) p[u] = buf_ldv<IPL>(rpre, off, st_off(u));
-            }
-          }
           if (t < T) {
             const V psi = s_psi[t][lv], L = s_L[t][lv];
             if (ALIF) {
-              const V e = psi * (p[t] - beta * ep);
+              const V e = psi * (pr - beta * ep);
               const V d = e - omr * ep;
               ep = ep + d;
               eb = alpha * eb + e;
             } else {
-              eb = alpha * eb + psi * p[t];
+              eb = alpha * eb + psi * pr;
             }
             g = g + L * eb;
+            pr = trace_next<IPL>(pr, alpha, bits, a.tofs + t);
           }
         }
         if (act) {
@@ -769,38 +797,44 @@ void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const 
   hipLaunchKernelGGL(k_col_fill, dim3(in.n_pre + rec.n_pre), dim3(WAVE), 0, s, in, rec, cv.cnt, cv.col);
 }
 
-// Hand-off transpose: [tau][B][n] -> [n][nslot][B] through a 64 x 64 LDS tile
-// (both sides coalesced).  blockIdx.z = array * nsteps + tau.
-__global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B, int nsteps, int slot0,
-                                                           int nslot) {
-  __shared__ float tile[64][65];
-  const int arr = blockIdx.z / nsteps, tau = blockIdx.z % nsteps;
-  const int n = h.n[arr];
+// Hand-off transpose: [step][B][n] -> [n][nslot][B] (slot slot0 + step) through
+// a 64 x 64 LDS tile, both sides coalesced; 32-bit words are moved unchanged.
+// blockIdx.z enumerates (array, step) pairs.
+__global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B) {
+  __shared__ uint32_t tile[64][65];
+  int z = blockIdx.z, arr = 0;
+  while (arr + 1 < HANDOFF_ARRAYS && z >= h.steps[arr]) z -= h.steps[arr++];
+  const int tau = z, n = h.n[arr];
   const int n0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
-  if (n0 >= n || b0 >= B) return;
-  const float* src = h.src[arr] + (int64_t)tau * B * n;
-  float* dst = h.dst[arr];
+  if (n0 >= n || b0 >= B || tau >= h.steps[arr]) return;
+  const uint32_t* src = h.src[arr] + (int64_t)tau * B * n;
+  uint32_t* dst = h.dst[arr];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
   for (int r = ty; r < 64; r += 4) {
     const int b = b0 + r, j = n0 + tx;
-    tile[r][tx] = (b < B && j < n) ? src[(int64_t)b * n + j] : 0.0f;
+    tile[r][tx] = (b < B && j < n) ? src[(int64_t)b * n + j] : 0u;
   }
   __syncthreads();
   for (int r = ty; r < 64; r += 4) {
     const int j = n0 + r, b = b0 + tx;
-    if (j < n && b < B) dst[((int64_t)j * nslot + slot0 + tau) * B + b] = tile[tx][r];
+    if (j < n && b < B) dst[((int64_t)j * h.nslot[arr] + h.slot0[arr] + tau) * B + b] = tile[tx][r];
   }
 }
 
-void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot) {
-  int nmax = 0;
-  for (int q = 0; q < HANDOFF_ARRAYS; ++q) nmax = max(nmax, h.n[q]);
-  dim3 grid((nmax + 63) / 64, (B + 63) / 64, HANDOFF_ARRAYS * nsteps);
-  hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B, nsteps, slot0, nslot);
+void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B) {
+  int nmax = 0, zs = 0;
+  for (int q = 0; q < HANDOFF_ARRAYS; ++q) {
+    nmax = max(nmax, h.n[q]);
+    zs += h.steps[q];
+  }
+  if (zs <= 0) return;
+  dim3 grid((nmax + 63) / 64, (B + 63) / 64, zs);
+  hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B);
 }
 
-// Narrow form (B < 32): threads over a row's synapses, each looping over steps
-// and instances; used for small batches such as single-instance learning.
+// Narrow form (B % 4 != 0): threads over a row's synapses, each looping over
+// instances and steps; used for small or odd batches such as single-instance
+// learning.  Same trace recursion and arithmetic as the target-major form.
 template <bool ALIF>
 __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   const int row = blockIdx.x, tid = threadIdx.x;
@@ -808,20 +842,22 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   const int B = a.B;
   if (row >= n_rows) {
     const int j = (row - n_rows) * EP_NT + tid;
-    for (int tau = 0; tau < a.nsteps; ++tau) {
-      if (j < a.n_rec) {
-        for (int k = 0; k < a.n_out; ++k) {
-          float g = 0.0f;
-          for (int b = 0; b < B; ++b) g += a.deltaT[ring(a, k, tau) + b] * a.zbar_new[ring(a, j, tau) + b];
-          a.Gout[(int64_t)k * a.n_rec + j] += g;
-        }
-      } else if (j == a.n_rec) {
-        for (int k = 0; k < a.n_out; ++k) {
-          float g = 0.0f;
-          for (int b = 0; b < B; ++b) g += a.deltaT[ring(a, k, tau) + b];
-          a.Gb[k] += g;
+    if (j > a.n_rec) return;
+    const bool wt = j < a.n_rec;
+    for (int k = 0; k < a.n_out; ++k) {
+      float g = 0.0f;
+      for (int b = 0; b < B; ++b) {
+        float z = wt ? a.z0[(int64_t)j * B + b] : 1.0f;
+        const uint32_t w = wt ? a.zbits[(int64_t)j * B + b] : 0u;
+        if (wt)
+          for (int t = 0; t < a.tofs; ++t) z = fmaf(a.alpha, z, (float)((w >> t) & 1u));
+        for (int tau = 0; tau < a.nsteps; ++tau) {
+          if (wt) z = fmaf(a.alpha, z, (float)((w >> (a.tofs + tau)) & 1u));
+          g = fmaf(a.deltaT[ring(a, k, tau) + b], z, g);
         }
       }
+      if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
+      else a.Gb[k] += g;
     }
     return;
   }
@@ -833,35 +869,36 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   float* G = from_in ? a.in.G : a.rec.G;
   float* eps = from_in ? a.in.eps : a.rec.eps;
   float* ebar = from_in ? a.in.ebar : a.rec.ebar;
-  const float* pre = from_in ? a.xbar_prev : a.zbar_prev;
+  const float* x0 = (from_in ? a.x0 : a.z0) + (int64_t)i * B;
+  const uint32_t* bits = (from_in ? a.xbits : a.zbits) + (int64_t)i * B;
   for (int k = tid; k < n; k += EP_NT) {
     const int64_t s = (int64_t)i * cap + k;
     const int j = ind[s];
-    float gsum = G[s];
-    for (int tau = 0; tau < a.nsteps; ++tau) {
-      float g = 0.0f;
-      for (int b = 0; b < B; ++b) {
-        const float p = pre[ring(a, i, tau) + b];
+    float gsum = 0.0f;
+    for (int b = 0; b < B; ++b) {
+      float p = x0[b];
+      const uint32_t w = bits[b];
+      for (int t = 0; t < a.tofs; ++t) p = fmaf(a.alpha, p, (float)((w >> t) & 1u));
+      float ep = ALIF ? eps[s * B + b] : 0.0f, eb = ebar[s * B + b];
+      for (int tau = 0; tau < a.nsteps; ++tau) {
         const float psi = a.psiT[ring(a, j, tau) + b];
-        float e;
         if (ALIF) {
-          const float ep = eps[s * B + b];
-          e = psi * (p - a.beta * ep);
-          const float k = psi * a.beta + a.one_m_rho;
-          eps[s * B + b] = ep + (psi * p - k * ep);
+          const float e = psi * (p - a.beta * ep);
+          const float d = e - a.one_m_rho * ep;
+          ep = ep + d;
+          eb = a.alpha * eb + e;
         } else {
-          e = psi * p;
+          eb = a.alpha * eb + psi * p;
         }
-        const float eb = a.alpha * ebar[s * B + b] + e;
-        ebar[s * B + b] = eb;
-        g += a.LT[ring(a, j, tau) + b] * eb;
+        gsum = fmaf(a.LT[ring(a, j, tau) + b], eb, gsum);
+        p = fmaf(a.alpha, p, (float)((w >> (a.tofs + tau)) & 1u));
       }
-      gsum += g;
+      if (ALIF) eps[s * B + b] = ep;
+      ebar[s * B + b] = eb;
     }
-    G[s] = gsum;
+    G[s] += gsum;
   }
 }
-
 
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
@@ -871,6 +908,7 @@ void launch_eprop(hipStream_t s, const EpropArgs& a) {
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;
       p.slot0 = a.slot0 + t0;
+      p.tofs = a.tofs + t0;
       p.nsteps = min(COL_TB, a.nsteps - t0);
       // the step count stays a runtime value: fixed at 16, the compiler
       // schedules for registers beyond the occupancy the LDS allows

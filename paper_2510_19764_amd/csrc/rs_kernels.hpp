@@ -44,15 +44,16 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes);
 // ---------------------------------------------------------------- e-prop step
 struct FwdArgs {
   int n_in, n_rec, n_out, B;
-  double alpha, rho, v_thr, beta;            // recurrences are evaluated in double
+  double alpha, rho, v_thr, beta;            // neuron recurrences are evaluated in double
   double psi_scale;                          // 0.3 / v_thr
+  float alpha_f;                             // trace decay: F <- fma(alpha_f, F, spike) in float
   double* V; double* A;                      // [B][n_rec]
-  double* xbar; double* zbar;                // [B][n_in], [B][n_rec] trace masters
-  // hand-off of step tau, instance-major staging [tau][B][n] (coalesced writes):
-  float* xbar_prev;                          // n = n_in: trace before this step's input
-  float* zbar_prev; float* zbar_new;         // n = n_rec: before / after this step's spikes
-  float* psi;                                // n = n_rec
-  float* u;                                  // n = n_out: readout drive sum_j W_out[k][j] z_j
+  float* xbar; float* zbar;                  // [B][n_in], [B][n_rec] presynaptic traces
+  // hand-off, instance-major staging (coalesced writes):
+  float* psi;                                // [tau][B][n_rec] surrogate derivative of each step
+  float* u;                                  // [tau][B][n_out] readout drive sum_j W_out[k][j] z_j
+  float* x0; float* z0;                      // [B][n] traces at the start of the block
+  uint32_t* xbits; uint32_t* zbits;          // [B][n] spikes of the block, bit tau = step tau
   uint8_t* z;                                // [B][n_rec]
   const int* len_in; const int* ind_in; const float* w_in; int cap_in;
   const int* len_rec; const int* ind_rec; const float* w_rec; int cap_rec;
@@ -79,25 +80,28 @@ struct ReadoutArgs {
 };
 void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal);
 
-// Move the staged hand-off of `nsteps` steps ([tau][B][n] for each array) into
-// the e-prop ring ([n][nslot][B], slots slot0 + tau).
-constexpr int HANDOFF_ARRAYS = 4;  // xbar_prev, zbar_prev, zbar_new, psi
+// Move staged hand-off arrays ([step][B][n], 32-bit words) into neuron-major
+// layout ([n][nslot][B], step tau to slot slot0 + tau).
+constexpr int HANDOFF_ARRAYS = 5;  // psi (per step); x0, z0, xbits, zbits (per block)
 struct HandoffArrays {
-  const float* src[HANDOFF_ARRAYS];
-  float* dst[HANDOFF_ARRAYS];
-  int n[HANDOFF_ARRAYS];
+  const uint32_t* src[HANDOFF_ARRAYS];
+  uint32_t* dst[HANDOFF_ARRAYS];
+  int n[HANDOFF_ARRAYS], steps[HANDOFF_ARRAYS], slot0[HANDOFF_ARRAYS], nslot[HANDOFF_ARRAYS];
 };
-void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B, int nsteps, int slot0, int nslot);
+void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B);
 
 struct EpropArgs {
   int n_in, n_rec, n_out, B, alif;
   float alpha, rho, beta;   // eligibility arithmetic is float; state is float
   float one_m_rho;          // 1 - rho, so the slow eps decay carries no rounding bias
   ProjDev in, rec;
-  // hand-off ring [n][nslot][B]; this launch applies steps slot0 .. slot0+nsteps-1
-  const float* xbar_prev;   // n_in: presynaptic traces before each step's spikes
-  const float* zbar_prev;   // n_rec
-  const float* zbar_new;    // n_rec: after each step (readout gradient)
+  // presynaptic traces of the block, rebuilt step by step with
+  // F <- fma(alpha, F, spike) from the block's start values and spike bits
+  // ([n][B]; bit t of a word = step t of the block)
+  const float* x0; const float* z0;
+  const uint32_t* xbits; const uint32_t* zbits;
+  int tofs;                 // steps of the block before this launch's first step
+  // ring [n][nslot][B]; this launch applies steps slot0 .. slot0+nsteps-1
   const float* psiT; const float* LT; const float* deltaT;
   int slot0, nsteps, nslot;
   float* Gout; float* Gb;

@@ -51,8 +51,10 @@ def effective_params(cfg: rb.EpropConfig):
     the comparison measures arithmetic, not parameter rounding."""
     dt, tm, ta = np.float64(np.float32(cfg.dt_ms)), np.float64(np.float32(cfg.tau_mem_ms)), \
         np.float64(np.float32(cfg.tau_adapt_ms))
-    return dict(v_thr=f32(cfg.v_thr), beta=f32(cfg.beta), alpha_value=float(np.exp(-dt / tm)),
-                rho_value=float(np.exp(-dt / ta)))
+    alpha = float(np.exp(-dt / tm))
+    # the presynaptic traces decay by the float-rounded alpha
+    return dict(v_thr=f32(cfg.v_thr), beta=f32(cfg.beta), alpha_value=alpha,
+                rho_value=float(np.exp(-dt / ta)), alpha_trace_value=f32(alpha))
 
 
 def oracle_net(snap, cfg: rb.EpropConfig, with_traces=True):
