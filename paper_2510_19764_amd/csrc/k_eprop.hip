@@ -536,9 +536,8 @@ __device__ __forceinline__ float hsum(typename VecT<IPL>::type v) {
 // Readout delta rule over the launch's steps (recurrent classifier section):
 // wave j < n_rec adds sum_t sum_b delta_k z_j to Gout[k][j] for every output
 // k, where z_j after step t is rebuilt from the block's start trace and spike
-// bits; wave n_rec adds the bias gradient sum_t sum_b delta_k.  Outputs are
-// taken 16 at a time, so each step's trace is rebuilt once per 16 outputs.
-constexpr int RG_K = 16;
+// bits; wave n_rec adds the bias gradient sum_t sum_b delta_k.  Steps are read
+// four at a time with independent loads.
 __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane) {
   if (j > a.n_rec) return;
   const int B = a.B, T = a.nsteps;
@@ -547,10 +546,9 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
   const auto rz = buf_rsrc(a.z0 + (int64_t)(wt ? j : 0) * B, step_bytes);
   const auto rb = buf_rsrc(a.zbits + (int64_t)(wt ? j : 0) * B, step_bytes);
   const int ipl = B % 4 == 0 ? 4 : 1;  // instances per lane
-  for (int k0 = 0; k0 < a.n_out; k0 += RG_K) {
-    float acc[RG_K];
-#pragma unroll
-    for (int q = 0; q < RG_K; ++q) acc[q] = 0.0f;
+  for (int k = 0; k < a.n_out; ++k) {
+    const auto rd = buf_rsrc(a.deltaT + ring(a, k, 0), blk);
+    float g = 0.0f;
     for (int c = ipl * lane; c < B; c += ipl * WAVE) {
       const uint32_t off = (uint32_t)c * 4u;
       f4 z = {1.f, 1.f, 1.f, 1.f};
@@ -565,32 +563,28 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
         }
         for (int t = 0; t < a.tofs; ++t) z = trace_next<4>(z, a.alpha, w, t);
       }
-      for (int t = 0; t < T; ++t) {
-        if (wt) z = trace_next<4>(z, a.alpha, w, a.tofs + t);  // the trace after step t
-        const uint32_t so = (uint32_t)t * step_bytes;
+      for (int t0 = 0; t0 < T; t0 += 4) {
+        f4 d[4];
 #pragma unroll
-        for (int q = 0; q < RG_K; ++q) {
-          if (k0 + q < a.n_out) {
-            const auto rd = buf_rsrc(a.deltaT + ring(a, k0 + q, 0), blk);
-            if (ipl == 4) {
-              const f4 d = buf_ldv<4>(rd, off, so);
-              acc[q] += (d.x * z.x + d.y * z.y) + (d.z * z.z + d.w * z.w);
-            } else {
-              acc[q] = fmaf(buf_ld(rd, off, so), z.x, acc[q]);
-            }
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t so = (uint32_t)min(t0 + u, T - 1) * step_bytes;
+          if (ipl == 4) d[u] = buf_ldv<4>(rd, off, so);
+          else d[u].x = buf_ld(rd, off, so);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (t0 + u < T) {
+            if (wt) z = trace_next<4>(z, a.alpha, w, a.tofs + t0 + u);  // the trace after the step
+            if (ipl == 4) g += (d[u].x * z.x + d[u].y * z.y) + (d[u].z * z.z + d[u].w * z.w);
+            else g = fmaf(d[u].x, z.x, g);
           }
         }
       }
     }
-#pragma unroll
-    for (int q = 0; q < RG_K; ++q) {
-      if (k0 + q < a.n_out) {
-        const float g = wave_sum(acc[q]);
-        if (lane == 0) {
-          if (wt) a.Gout[(int64_t)(k0 + q) * a.n_rec + j] += g;
-          else a.Gb[k0 + q] += g;
-        }
-      }
+    g = wave_sum(g);
+    if (lane == 0) {
+      if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
+      else a.Gb[k] += g;
     }
   }
 }
@@ -622,21 +616,20 @@ __host__ __device__ inline int readout_groups(int n_rec, int nw) {
 // in chunk order by the one wave that owns the synapse, so the result does
 // not depend on scheduling or on the order of the column list.
 constexpr int WL_CH = 4 * WAVE;  // instances per LDS chunk
-constexpr int WL_IPL = 4;  // instances per lane (2 doubles the waves and measured slower)
+constexpr int WL_IPL = 4;  // instances per lane
 
-// IPL instances per lane; NH = 4 / IPL wave groups split a chunk's 256
-// instances, so a workgroup has 4 * NH waves and wave w works on half w / 4
-// of the chunk and on synapses w % 4, w % 4 + 4, ...
+// IPL = 4 instances per lane: a workgroup's 4 waves share a chunk of 256
+// instances and wave w works on synapses w, w + 4, ...
 template <bool ALIF, int IPL>
 __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
   typedef typename VecT<IPL>::type V;
   typedef unsigned U __attribute__((ext_vector_type(IPL)));
-  constexpr int NH = 4 / IPL;
-  constexpr int LPC = WL_CH / IPL;  // lanes across a chunk: 64 * NH vectors per step
+  static_assert(IPL == 4, "one wave covers a 256-instance chunk");
+  constexpr int LPC = WL_CH / IPL;  // vectors across a chunk
+  // 32 KB: with more, the compiler budgets registers for fewer waves
   __shared__ V s_psi[COL_TB][LPC], s_L[COL_TB][LPC];
-  __shared__ float gpart[NH][WAVE];
   const int wv = wave_id(), lane = lane_id();
-  const int nw = blockDim.x / WAVE;  // 4 * NH
+  const int nw = blockDim.x / WAVE;
   const int n_ro = readout_groups(a.n_rec, nw);
   if ((int)blockIdx.x < n_ro) {
     readout_grad(a, blockIdx.x * nw + wv, lane);
@@ -646,7 +639,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
   const int j = wg / COL_OCT;
   const int q0 = a.col_off[wg], q1 = a.col_off[wg + 1];
   if (q1 <= q0) return;
-  const int half = wv / 4, sub = wv % 4;
+  const int sub = wv;
   const int B = a.B, T = a.nsteps;
   const int n_ch = (B + WL_CH - 1) / WL_CH;
   const uint32_t step_bytes = (uint32_t)B * 4u, blk_bytes = (uint32_t)T * step_bytes;
@@ -656,7 +649,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
   for (int e = 0; e < IPL; ++e) zero[e] = 0.0f;
   auto st_off = [&](int t) { return (uint32_t)(t < T ? t : T - 1) * step_bytes; };
   for (int m = 0; m < n_ch; ++m) {
-    const int lv = half * WAVE + lane;  // this lane's vector within the chunk
+    const int lv = lane;  // this lane's vector within the chunk
     const int b0 = m * WL_CH + IPL * lv;
     const bool act = b0 < B;
     const uint32_t off = (uint32_t)(act ? b0 : 0) * 4u;  // idle lanes read instance 0, never store
@@ -665,13 +658,14 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
       const auto rp = buf_rsrc(a.psiT + ring(a, j, 0), blk_bytes);
       const auto rl = buf_rsrc(a.LT + ring(a, j, 0), blk_bytes);
       for (int t = sub; t < COL_TB; t += 4) {
-        s_psi[t][lv] = buf_ldv<IPL>(rp, off, st_off(t));
+        s_psi[t][lv] = t < T ? buf_ldv<IPL>(rp, off, st_off(t)) : zero;
         s_L[t][lv] = act && t < T ? buf_ldv<IPL>(rl, off, st_off(t)) : zero;
       }
     }
     __syncthreads();
     for (int sc = q0; sc < q1; sc += WAVE) {  // chunks of 64 list entries
       const int ns = min(WAVE, q1 - sc);
+#pragma unroll 1
       for (int k = sub; k < ns; k += 4) {
         // keeps the per-step LDS reads and the trace loads inside their
         // groups (hoisted, they would cost registers, hence occupancy)
@@ -695,41 +689,33 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
         V g = zero;
 #pragma unroll
         for (int t = 0; t < COL_TB; ++t) {
-          if (t < T) {
-            const V psi = s_psi[t][lv], L = s_L[t][lv];
-            if (ALIF) {
-              const V e = psi * (pr - beta * ep);
-              const V d = e - omr * ep;
-              ep = ep + d;
-              eb = alpha * eb + e;
-            } else {
-              eb = alpha * eb + psi * pr;
-            }
-            g = g + L * eb;
-            pr = trace_next<IPL>(pr, alpha, bits, a.tofs + t);
+          // step groups of four: the launch's steps end at a group boundary
+          // or inside the last group; LDS reads stay inside their group
+          if (t % 4 == 0) {
+            if (t >= T) break;
+            __asm__ volatile("" ::: "memory");
           }
+          const V psi = s_psi[t][lv], L = s_L[t][lv];
+          // decay factors (alpha, 1 - rho) for the launch's steps and (1, 0)
+          // past them, where psi = L = 0 as well: padded steps change nothing
+          const float da = t < T ? alpha : 1.0f, dr = t < T ? omr : 0.0f;
+          if (ALIF) {
+            const V e = psi * (pr - beta * ep);
+            const V d = e - dr * ep;
+            ep = ep + d;
+            eb = da * eb + e;
+          } else {
+            eb = da * eb + psi * pr;
+          }
+          g = g + L * eb;
+          pr = trace_next<IPL>(pr, alpha, bits, a.tofs + t);
         }
         if (act) {
           buf_stv_nt<IPL>(eb, reb, off);
           if (ALIF) buf_stv_nt<IPL>(ep, rep, off);
         }
         const float gs = wave_sum(hsum<IPL>(g));
-        if (NH == 1) {
-          if (lane == 0) (fin ? a.in.G : a.rec.G)[ent.y] += gs;
-        } else if (lane == 0) {
-          gpart[half][k] = gs;
-        }
-      }
-      if (NH > 1) {  // halves of each synapse, added in half order
-        __syncthreads();
-        if ((int)threadIdx.x < ns) {
-          const int2 ent = a.col[sc + threadIdx.x];
-          float gsum = 0.0f;
-#pragma unroll
-          for (int h = 0; h < NH; ++h) gsum += gpart[h][threadIdx.x];
-          (ent.x < a.n_in ? a.in.G : a.rec.G)[ent.y] += gsum;
-        }
-        __syncthreads();
+        if (lane == 0) (fin ? a.in.G : a.rec.G)[ent.y] += gs;
       }
     }
   }
@@ -903,7 +889,7 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
   if (a.B % 4 == 0 && a.col && a.col_off) {
-    const int nw = 4 * (4 / WL_IPL);
+    const int nw = 4;
     const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_OCT;
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;
