@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def classifier_config(seed=1, trace_block=16):
+def classifier_config(seed=1, trace_block=20):
     from paper_2510_19764_amd import binding as rb
     from paper_2510_19764_amd import workload as wl
     c = wl.SHD_CLASSIFIER
@@ -210,7 +210,7 @@ def main():
     n_syn_after = int(net.get(rb.PROJ(0, rb.P_LEN)).sum() + net.get(rb.PROJ(1, rb.P_LEN)).sum())
     assert n_syn_after == n_syn, "DEEP R must keep the synapse count"
 
-    inf_k = cfg.trace_block or 16
+    inf_k = cfg.trace_block or 20
     samples = args.steps * cfg.batch
     value = samples / elapsed
     ep_ms, ep_n = phases["eprop"]

@@ -74,8 +74,10 @@ typedef struct rs_eprop_params {
   uint32_t update_interval;  /* steps between automatic update + rewire (0 = never) */
   uint32_t sample_steps;     /* steps per presented sample; state resets after each */
   uint64_t seed;
-  uint32_t trace_block;      /* steps whose eligibility updates one launch applies
-                                together, 1..32 (0 = 16); results do not depend on it */
+  uint32_t trace_block;      /* steps whose eligibility updates the library applies
+                                together, 1..32 (0 = 20); neuron state, traces and
+                                eps/ebar do not depend on it, the gradient only by
+                                float rounding of its sum */
   uint32_t reserved;         /* must be 0 */
 } rs_eprop_params;
 

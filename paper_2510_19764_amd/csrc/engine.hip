@@ -276,7 +276,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->z0T, 2 * NR * B));
   TRY(ar.alloc(&n->xbitsT, 2 * NI * B));
   TRY(ar.alloc(&n->zbitsT, 2 * NR * B));
-  n->K = prm->trace_block ? (int)prm->trace_block : 16;
+  n->K = prm->trace_block ? (int)prm->trace_block : 20;
   n->nslot = 2 * n->K;
   const size_t NS = (size_t)n->nslot;
   TRY(ar.alloc(&n->psiT, NR * NS * B));

@@ -445,7 +445,10 @@ void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal) {
 // before the batch reduction, so G depends on the block length only through
 // float rounding.
 constexpr int EP_NT = 256;
-constexpr int COL_TB = 16;  // steps per launch of the target-major kernel
+// Steps per launch of the target-major kernel.  20 divides the usual update
+// intervals (100 steps), so no block ends in a short tail launch; psi and L of
+// 20 steps take 40 KB of LDS, four workgroups per CU.
+constexpr int COL_TB = 20;
 constexpr int COL_OCT = 8;  // source octants, one per XCD
 
 __device__ __forceinline__ int64_t ring(const EpropArgs& a, int n, int tau) {
