@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# fp32 vector FMA rate without packed instructions (the library is built with
+# them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
+FP32_PEAK_TFLOPS = 78.6
 
 
 def classifier_config(seed=1, trace_block=20):
@@ -52,6 +55,17 @@ def eprop_algorithmic_bytes(cfg, n_syn: int, n_launch: int, n_steps: int) -> int
     per_launch = n_syn * (per_unit * B + 16) + 8 * cfg.n_out * cfg.n_rec + 8 * cfg.n_out
     per_step = 4 * B * (cfg.n_in + 4 * cfg.n_rec + cfg.n_out)
     return n_launch * per_launch + n_steps * per_step
+
+
+def eprop_algorithmic_flops(cfg, n_syn: int, n_steps: int) -> int:
+    """Float operations of the method over n_steps steps: per synapse, instance
+    and step e = psi (p - beta eps) (3), eps' = psi p + (rho - psi beta) eps
+    as eps + (e - (1 - rho) eps) (3), ebar' = alpha ebar + e (2) and
+    G += L ebar' (2) for ALIF; e = psi p (1), ebar' (2), G (2) for LIF; plus
+    the readout gradient, 2 per readout weight, instance and step."""
+    per_syn = 10 if cfg.alif else 5
+    B = cfg.batch
+    return n_steps * B * (n_syn * per_syn + 2 * cfg.n_out * cfg.n_rec + cfg.n_out)
 
 
 def recorded_traffic(kernel: str):
@@ -217,6 +231,8 @@ def main():
     ep_avg_s = ep_ms / 1e3 / max(ep_n, 1)
     alg_bytes = eprop_algorithmic_bytes(cfg, n_syn, ep_n, args.steps * T)
     achieved = alg_bytes / (ep_ms / 1e3) / 1e9
+    alg_flops = eprop_algorithmic_flops(cfg, n_syn, args.steps * T)
+    achieved_tf = alg_flops / (ep_ms / 1e3) / 1e12
     result = {
         "metric": "train samples/s (e-prop + DEEP R, sparse classifier)",
         "value": round(value, 2),
@@ -237,12 +253,15 @@ def main():
         "synaptic_events_per_s": round(events / elapsed, 1),
         "timesteps_per_s": round(args.steps * T / elapsed, 1),
         "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
-        "roofline": {"bound": "hbm", "kernel": "k_eprop_wl<true>", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic("k_eprop_wl<true>"),
+        "roofline": {"bound": "alu", "kernel": "k_eprop_wl<true, 4>", "achieved": round(achieved_tf, 2),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic("k_eprop_wl<true, 4>"),
                      "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
                      "trace_block": inf_k,
-                     "algorithmic_bytes_per_launch": round(alg_bytes / max(ep_n, 1))},
+                     "algorithmic_flops_per_launch": round(alg_flops / max(ep_n, 1)),
+                     "hbm": {"achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes_per_launch": round(alg_bytes / max(ep_n, 1))}},
     }
     net.close()
     if not args.no_topo:
