@@ -158,6 +158,8 @@ rs_status rs_eprop_reset(rs_eprop* net);
 #define RS_VOUT 0x0F
 #define RS_MB 0x10     /* float[n_out] */
 #define RS_VB 0x11
+#define RS_ZCOUNT 0x12 /* uint32[batch][n_rec]  spikes per neuron since creation or the
+                          last rs_eprop_set of this variable */
 /* Projection variables: RS_PROJ(p, field), p = 0 input, 1 recurrent;
  * cap = row capacity (rs_eprop_info), words = ceil(n_post/32). */
 #define RS_PROJ(p, f) (0x100 * ((p) + 1) + (f))
@@ -190,6 +192,7 @@ typedef struct rs_eprop_info {
   uint64_t synaptic_events;       /* spikes x row lengths propagated so far */
   uint64_t spikes;                /* recurrent spikes emitted so far */
   uint64_t device_bytes;          /* device memory held */
+  uint64_t eliminated, formed;    /* DEEP R synapses removed / created so far, both projections */
 } rs_eprop_info;
 /* Synchronises the stream. */
 rs_status rs_eprop_info_get(rs_eprop* net, rs_eprop_info* out);

@@ -151,7 +151,8 @@ struct rs_eprop {
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
   float *Mout = nullptr, *Vout = nullptr, *Mb = nullptr, *Vb = nullptr;
   unsigned long long* counters = nullptr;  // [0] events, [1] spikes
-  long long* rw_stats = nullptr;           // [2]
+  long long* rw_stats = nullptr;           // [2] DEEP R eliminated / formed since creation
+  uint32_t* zcount = nullptr;              // [B][n_rec] spikes per neuron
   const int32_t *x_off = nullptr, *x_idx = nullptr, *labels = nullptr;
   long long n_idx = 0;
   uint64_t step = 0;
@@ -308,6 +309,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->cv.off, NR * 8 + 1));
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
   TRY(ar.alloc(&n->rw_stats, 2));
+  TRY(ar.alloc(&n->zcount, (size_t)B * NR));
 
   for (ProjDev* P : {&n->in, &n->rec}) {  // padding slots start defined
     launch_fill_zero(s, P->ind, (size_t)P->n_pre * P->cap * 4);
@@ -338,6 +340,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   for (float* q : {n->bout, n->Gb, n->Mb, n->Vb}) launch_fill_zero(s, q, K * 4);
   launch_fill_zero(s, n->counters, 16);
   launch_fill_zero(s, n->rw_stats, 16);
+  launch_fill_zero(s, n->zcount, (size_t)B * NR * 4);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
   return RS_OK;
@@ -418,7 +421,6 @@ void flush_block(rs_eprop* n) {
   f.xbar = n->xbar; f.zbar = n->zbar;
   f.psi = (float*)n->stg[0]; f.x0 = (float*)n->stg[1]; f.z0 = (float*)n->stg[2];
   f.xbits = n->stg[3]; f.zbits = n->stg[4]; f.z = n->z;
-  // the readout drive goes to the block's half, read on the side stream
   f.u = n->u_stg + (size_t)h * n->K * n->B * n->p.n_out;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
@@ -426,6 +428,7 @@ void flush_block(rs_eprop* n) {
   f.x_off = n->x_off; f.x_idx = n->x_idx; f.n_idx = n->n_idx;
   f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
   f.counters = n->counters;
+  f.zcount = n->zcount;
   n->timer.begin(s, 0);
   launch_fwd(s, f);
   HandoffArrays ho{};
@@ -443,21 +446,20 @@ void flush_block(rs_eprop* n) {
     ho.nslot[q] = q == 0 ? n->nslot : 1;
   }
   launch_handoff_transpose(s, ho, n->B);
-  n->timer.end(s);
-  n->last_slot = h * n->K + n->blk_n - 1;
-  (void)hipEventRecord(n->ev_fwd, s);
-  (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
   // readout state, softmax error and (when learning) the learning signal of
-  // the block, on the side stream ahead of its e-prop launch
+  // the block, still on the forward stream: the e-prop stream, which carries
+  // the longer work, starts with the eligibility launch itself
   ReadoutArgs ro{};
   ro.n_rec = f.n_rec; ro.n_out = f.n_out; ro.B = n->B; ro.nsteps = n->blk_n;
   ro.slot0 = h * n->K; ro.nslot = n->nslot;
   ro.alpha = n->alpha;
   ro.u = f.u; ro.Y = n->Y; ro.Wout = n->Wout; ro.bout = n->bout; ro.labels = n->labels;
   ro.deltaT = n->deltaT; ro.LT = n->LT;
-  n->timer.begin(e, 0);
-  launch_readout(e, ro, n->blk_learn);
-  n->timer.end(e);
+  launch_readout(s, ro, n->blk_learn);
+  n->timer.end(s);
+  n->last_slot = h * n->K + n->blk_n - 1;
+  (void)hipEventRecord(n->ev_fwd, s);
+  (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
   if (n->blk_learn) {
     EpropArgs a{};
     a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B;
@@ -547,6 +549,7 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_VOUT: *r = {n->Vout, K * NR * 4}; return true;
       case RS_MB: *r = {n->Mb, K * 4}; return true;
       case RS_VB: *r = {n->Vb, K * 4}; return true;
+      case RS_ZCOUNT: *r = {n->zcount, B * NR * 4}; return true;
       default: return false;
     }
   }
@@ -626,18 +629,21 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
   if (proj > 1 || !((n->p.deepr_mask >> proj) & 1u))
     return fail(RS_EINVAL, "projection %u is not rewired by DEEP R", proj);
-  launch_fill_zero(n->stream, n->rw_stats, 16);
+  long long before[2] = {0, 0}, after[2];
+  if (st) {  // the counters accumulate over the object's life; report this call's share
+    HIP_OK(hipMemcpyAsync(before, n->rw_stats, sizeof before, hipMemcpyDeviceToHost, n->stream));
+    HIP_OK(hipStreamSynchronize(n->stream));
+  }
   do_rewire(n, (int)proj, n->stream);
   rebuild_columns(n, n->stream);
   HIP_OK(hipGetLastError());
   if (st) {
-    long long h[2];
-    HIP_OK(hipMemcpyAsync(h, n->rw_stats, sizeof h, hipMemcpyDeviceToHost, n->stream));
+    HIP_OK(hipMemcpyAsync(after, n->rw_stats, sizeof after, hipMemcpyDeviceToHost, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
-    st->eliminated = h[0];
-    st->formed = h[1];
+    st->eliminated = after[0] - before[0];
+    st->formed = after[1] - before[1];
     st->blocked = 0;
-    st->attempts = h[0];
+    st->attempts = st->eliminated;
   }
   return RS_OK;
 }
@@ -702,7 +708,9 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
 rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   if (!n || !o) return fail(RS_EINVAL, "NULL argument");
   unsigned long long c[2];
+  long long r[2];
   HIP_OK(hipMemcpyAsync(c, n->counters, sizeof c, hipMemcpyDeviceToHost, n->stream));
+  HIP_OK(hipMemcpyAsync(r, n->rw_stats, sizeof r, hipMemcpyDeviceToHost, n->stream));
   HIP_OK(hipStreamSynchronize(n->stream));
   memset(o, 0, sizeof *o);
   o->cap_in = (uint32_t)n->in.cap;
@@ -714,6 +722,8 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   o->synaptic_events = c[0];
   o->spikes = c[1];
   o->device_bytes = n->arena.bytes;
+  o->eliminated = (uint64_t)r[0];
+  o->formed = (uint64_t)r[1];
   return RS_OK;
 }
 

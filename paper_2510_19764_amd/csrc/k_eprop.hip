@@ -286,6 +286,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       a.zbar[m] = zbr[it];
       a.z[m] = (uint8_t)zr[it];
       a.zbits[m] = zbits[it];
+      a.zcount[m] += (uint32_t)__popc(zbits[it]);
     }
   }
 #pragma unroll

@@ -63,6 +63,7 @@ struct FwdArgs {
   int wout_lds;                              // 1: stage W_out in LDS for the block
   int xcap;                                  // LDS capacity for the block's input spike lists
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
+  uint32_t* zcount;                          // [B][n_rec] spikes per neuron, accumulated
 };
 // One launch runs `nsteps` consecutive steps into the staging buffers.
 void launch_fwd(hipStream_t s, const FwdArgs& a);

@@ -77,16 +77,23 @@ def test_lockstep_100_steps(name):
     N = oracle_net(snapshot(net), cfg)
     resync = 0
     spikes = 0
+    counts = np.zeros((cfg.batch, cfg.n_rec), np.uint32)
     for t in range(100):
         net.step(1, rb.RS_LEARN)
         snap = snapshot(net)
         resync += oracle_step_resync(N, raster, t, labels, snap["z"])
         spikes += int(snap["z"].sum())
+        counts += snap["z"].astype(np.uint32)
         compare_state(snap, N, cfg)
     assert spikes > 0
     assert resync <= 2, f"{resync} threshold ties in 100 steps"
     inf = net.info()
     assert inf.step == 100 and inf.spikes == spikes
+    # per-neuron spike counts read back, and cleared through the setter
+    assert np.array_equal(net.get(rb.ZCOUNT), counts)
+    net.set(rb.ZCOUNT, np.zeros_like(counts))
+    net.step(3, rb.RS_LEARN)
+    assert int(net.get(rb.ZCOUNT).sum()) == net.info().spikes - spikes
 
 
 @pytest.mark.parametrize("name", ["tiny-lif-b1", "alif-b64-col", "alif-b3-narrow"])
@@ -133,7 +140,10 @@ def test_deepr_rewire_bit_exact(name):
     for proj in (0, 1):
         pre = snapshot(net)
         step = net.info().step
+        before = net.info()
         st = net.rewire(proj)
+        after = net.info()
+        assert (after.eliminated - before.eliminated, after.formed - before.formed) == (st.eliminated, st.formed)
         post = snapshot(net)
         N = oracle_net(pre, cfg)
         P = N.inp if proj == 0 else N.rec
@@ -174,6 +184,7 @@ def test_training_loop_invariants_and_determinism(B, alif, steps):
         s = snapshot(net)
         inf = net.info()
         assert inf.adam_step == steps // 25 and inf.step == steps
+        assert inf.eliminated == inf.formed  # DEEP R keeps the synapse count
         for p, tag in ((0, "in"), (1, "rec")):
             g = s[tag]
             assert int(g["len"].sum()) == total0[p]
