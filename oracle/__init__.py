@@ -14,6 +14,7 @@ Per-function citations live in the C sources:
   update.c   L1 term for DEEP R projections + Adam
   deepr.c    DEEP R elimination and formation
   topomap.c  topographic-map rewiring
+  input.c    Poisson input spikes on the counter-based generator
 """
 from __future__ import annotations
 
@@ -25,12 +26,13 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c"]
+_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c", "input.c"]
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 TAG_CONN, TAG_WINIT, TAG_SIGN = 1, 2, 3
 TAG_DR_ROW, TAG_DR_TGT = 4, 5
 TAG_TP_ROW, TAG_TP_TGT, TAG_TP_ELIM, TAG_TP_FORM = 6, 7, 8, 9
+TAG_INPUT = 10
 MAX_TRIES = 64
 
 
@@ -116,6 +118,11 @@ def _declare(L):
     L.orc_threshold.restype = C.c_uint64
     L.orc_normal.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32] + [C.c_uint64] * 4
     L.orc_normal.restype = C.c_double
+    L.orc_rate_threshold.argtypes = [C.c_double, C.c_double]
+    L.orc_rate_threshold.restype = C.c_uint64
+    L.orc_poisson_input.argtypes = [C.c_uint64, C.c_uint64, C.c_int32, C.c_int32, P_u64, C.c_int32,
+                                    P_i32, P_i32]
+    L.orc_poisson_input.restype = C.c_int64
     L.orc_fixed_prob_rows.argtypes = [C.c_uint64, C.POINTER(_CProj), C.c_double, C.c_double]
     L.orc_fixed_prob_rows.restype = C.c_int32
     L.orc_gauss_rows.argtypes = [C.c_uint64, C.POINTER(_CProj), C.c_int32, C.c_double,
@@ -163,6 +170,27 @@ def below(u: int, n: int) -> int:
 
 def threshold(p: float) -> int:
     return int(lib().orc_threshold(p))
+
+
+def rate_thresholds(rates_hz, dt_ms: float = 1.0) -> np.ndarray:
+    """Per-step Bernoulli thresholds floor(rate*dt*2^32) of Poisson channels."""
+    r = np.ascontiguousarray(rates_hz, np.float64)
+    return np.array([lib().orc_rate_threshold(float(x), float(dt_ms)) for x in r.ravel()],
+                    np.uint64).reshape(r.shape)
+
+
+def poisson_input(seed: int, step: int, B: int, thr: np.ndarray):
+    """Input spike lists (idx, off[B+1]) of one step; thr is [n_in] (shared by
+    the instances) or [B][n_in]."""
+    thr = np.ascontiguousarray(thr, np.uint64)
+    n_in = thr.shape[-1]
+    per_instance = 1 if thr.ndim == 2 else 0
+    assert not per_instance or thr.shape[0] == B
+    idx = np.zeros(max(B * n_in, 1), np.int32)
+    off = np.zeros(B + 1, np.int32)
+    n = lib().orc_poisson_input(seed, step, B, n_in, _ptr(thr, P_u64), per_instance,
+                                _ptr(idx, P_i32), _ptr(off, P_i32))
+    return idx[:n].copy(), off
 
 
 def normal(seed, tag, proj, c0, c1, c2, c3=0) -> float:

@@ -40,7 +40,8 @@ enum {
     ORC_TAG_TP_ROW = 6,  /* topomap attempt -> row,       counter (step, a, 0, 0) */
     ORC_TAG_TP_TGT = 7,  /* topomap candidate target,     counter (step, r, q, try) */
     ORC_TAG_TP_ELIM = 8, /* topomap elimination draw,     counter (step, r, s, 0) */
-    ORC_TAG_TP_FORM = 9  /* topomap formation draw,       counter (step, r, j, 0) */
+    ORC_TAG_TP_FORM = 9, /* topomap formation draw,       counter (step, r, j, 0) */
+    ORC_TAG_INPUT = 10   /* Poisson input spike,          counter (step, b, i, 0) */
 };
 
 /* Draws per (row, activation) before the bounded fallback scan takes over. */
@@ -56,6 +57,17 @@ uint32_t orc_below(uint32_t u, uint32_t n);
 uint64_t orc_threshold(double p);
 double orc_normal(uint64_t seed, uint32_t tag, uint32_t proj, uint64_t c0, uint64_t c1,
                   uint64_t c2, uint64_t c3);
+
+/* ---- Poisson input -------------------------------------------------------- */
+/* Bernoulli threshold of one step of a Poisson train: floor(rate*dt*2^32). */
+uint64_t orc_rate_threshold(double rate_hz, double dt_ms);
+/* Input spikes of step `step` for every instance: channel i of instance b
+ * fires when u32(INPUT; step, b, i, 0) < thr[i] (thr[b*n_in + i] with
+ * per_instance).  Writes ascending channel lists, x_off[B+1] delimiting each
+ * instance's list in x_idx (capacity B*n_in); returns the spike count. */
+int64_t orc_poisson_input(uint64_t seed, uint64_t step, int32_t B, int32_t n_in,
+                          const uint64_t *thr, int32_t per_instance,
+                          int32_t *x_idx, int32_t *x_off);
 
 /* ---- one ragged projection ----------------------------------------------- */
 typedef struct orc_proj {

@@ -5,21 +5,7 @@ import numpy as np
 import pytest
 from scipy import stats
 
-
-def numpy_block(key0, key1, ctr):
-    # numpy advances the counter before producing a block, so the block at
-    # counter c is the first output of a generator started at c - 1.
-    c = np.array(ctr, dtype=np.uint64)
-    c0 = [int(x) for x in c]
-    # subtract one with borrow over the 256-bit counter
-    for k in range(4):
-        if c0[k] > 0:
-            c0[k] -= 1
-            break
-        c0[k] = (1 << 64) - 1
-    bg = np.random.Philox(key=np.array([key0, key1], dtype=np.uint64),
-                          counter=np.array(c0, dtype=np.uint64))
-    return np.array(bg.random_raw(4), dtype=np.uint64)
+from helpers import numpy_block
 
 
 def test_philox_known_answer_zero(orc):
