@@ -107,6 +107,22 @@ rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_ep
 rs_status rs_eprop_set_input(rs_eprop* net, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
                              const int32_t* labels_dev);
 
+/* Attach a Poisson input source instead of a raster (the topographic-map
+ * model's input layer, Tab. A and B, and Poisson input neurons in general):
+ * in every step each input channel fires with probability rate * dt, drawn on
+ * the counter-based generator.  Channel i of instance b fires at step t (the
+ * object's step count, so successive samples draw fresh spikes) when the
+ * 32-bit draw of stream INPUT (tag 10, proj 0) at counter (t, b, i, 0) is
+ * below floor(p * 2^32), p = rate_hz * dt_ms / 1000 computed in double (p <= 0:
+ * never, p >= 1: every step).  rate_hz is a host array, copied, of n_in
+ * entries (one table for every instance) or batch * n_in entries ([b][i]);
+ * labels_dev int32[batch] as for rs_eprop_set_input, kept by pointer.
+ * Synchronises the stream.  A later rs_eprop_set_input returns to a raster.
+ * Errors: RS_EINVAL (NULL pointer, n_rates neither n_in nor batch * n_in, a
+ * NaN rate, trace_block * batch * n_in above 2^31), RS_ENOMEM. */
+rs_status rs_eprop_set_input_poisson(rs_eprop* net, const double* rate_hz, size_t n_rates,
+                                     const int32_t* labels_dev);
+
 /* Advance n_steps timesteps.  Each step: spikes and surrogate derivatives from
  * the current state, eligibility traces (eq. eprop_elig_1/2 or eprop_elig_lif),
  * propagation of input and recurrent spikes through the ragged rows, neuron

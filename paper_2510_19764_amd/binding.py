@@ -69,7 +69,8 @@ class _TopoParams(C.Structure):
 
 
 EXPORTS = [
-    "rs_last_error", "rs_eprop_create", "rs_eprop_set_input", "rs_eprop_step", "rs_eprop_update",
+    "rs_last_error", "rs_eprop_create", "rs_eprop_set_input", "rs_eprop_set_input_poisson",
+    "rs_eprop_step", "rs_eprop_update",
     "rs_eprop_rewire", "rs_eprop_reset", "rs_eprop_get", "rs_eprop_set", "rs_eprop_info_get",
     "rs_eprop_timing", "rs_eprop_phase_times", "rs_eprop_destroy",
     "rs_topo_create", "rs_topo_rewire", "rs_topo_get_rows", "rs_topo_set_rows", "rs_topo_get_bits",
@@ -94,6 +95,7 @@ def lib():
         L.rs_last_error.restype = C.c_char_p
         L.rs_eprop_create.argtypes = [C.POINTER(_EpropParams), vp, C.POINTER(vp)]
         L.rs_eprop_set_input.argtypes = [vp, vp, vp, C.c_size_t, vp]
+        L.rs_eprop_set_input_poisson.argtypes = [vp, C.POINTER(C.c_double), C.c_size_t, vp]
         L.rs_eprop_step.argtypes = [vp, C.c_uint32, C.c_uint32]
         L.rs_eprop_update.argtypes = [vp]
         L.rs_eprop_rewire.argtypes = [vp, C.c_uint32, C.POINTER(_Stats)]
@@ -210,6 +212,17 @@ class EpropNet:
         self._input_refs = (off, idx, labels)
         _check(lib().rs_eprop_set_input(self._h, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
                                         idx.numel(), C.c_void_p(labels.data_ptr())))
+
+    def set_input_poisson(self, rates_hz, labels):
+        """rates_hz: host float64 [n_in] or [batch][n_in]; labels: int32 CUDA
+        tensor (kept alive by this object)."""
+        import torch
+        assert isinstance(labels, torch.Tensor) and labels.is_cuda and labels.dtype == torch.int32
+        assert labels.is_contiguous()
+        r = np.ascontiguousarray(rates_hz, np.float64)
+        self._input_refs = (labels,)
+        _check(lib().rs_eprop_set_input_poisson(self._h, r.ctypes.data_as(C.POINTER(C.c_double)), r.size,
+                                                C.c_void_p(labels.data_ptr())))
 
     # ---- simulation
     def step(self, n: int = 1, flags: int = RS_LEARN):

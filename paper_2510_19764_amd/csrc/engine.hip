@@ -155,6 +155,12 @@ struct rs_eprop {
   uint32_t* zcount = nullptr;              // [B][n_rec] spikes per neuron
   const int32_t *x_off = nullptr, *x_idx = nullptr, *labels = nullptr;
   long long n_idx = 0;
+  // Poisson input source (instead of a raster): per-step Bernoulli thresholds
+  // and the forward kernel's per-block spike lists [K][B][n_in]
+  bool poisson = false;
+  uint64_t* x_thr = nullptr;               // [B][n_in] capacity
+  int x_thr_stride = 0;                    // 0: one table for every instance, n_in: per instance
+  int32_t* x_list = nullptr;
   uint64_t step = 0;
   uint32_t adam_k = 0;
   double alpha = 0.0, rho = 0.0, beta = 0.0;  // decay factors exp(-dt/tau) in double
@@ -426,6 +432,10 @@ void flush_block(rs_eprop* n) {
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
   f.Wout = n->Wout;
   f.x_off = n->x_off; f.x_idx = n->x_idx; f.n_idx = n->n_idx;
+  if (n->poisson) {
+    f.x_thr = n->x_thr; f.x_thr_stride = n->x_thr_stride; f.x_list = n->x_list;
+    f.seed = n->p.seed; f.step0 = n->blk_t0;
+  }
   f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
   f.counters = n->counters;
   f.zcount = n->zcount;
@@ -601,12 +611,43 @@ rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t*
   n->x_idx = idx_dev;
   n->n_idx = (long long)n_idx;
   n->labels = labels_dev;
+  n->poisson = false;
+  return RS_OK;
+}
+
+rs_status rs_eprop_set_input_poisson(rs_eprop* n, const double* rate_hz, size_t n_rates, const int32_t* labels_dev) {
+  if (!n) return fail(RS_EINVAL, "net is NULL");
+  if (!rate_hz || !labels_dev) return fail(RS_EINVAL, "rate table and labels must not be NULL");
+  const size_t NI = n->p.n_in, B = n->B;
+  if (n_rates != NI && n_rates != B * NI) return fail(RS_EINVAL, "n_rates must be n_in or batch * n_in");
+  if ((size_t)n->K * B * NI > (size_t)INT32_MAX) return fail(RS_EINVAL, "trace_block * batch * n_in exceeds 2^31");
+  std::vector<uint64_t> thr(n_rates);
+  for (size_t q = 0; q < n_rates; ++q) {
+    if (std::isnan(rate_hz[q])) return fail(RS_EINVAL, "rate %zu is NaN", q);
+    thr[q] = threshold(rate_hz[q] * (double)n->p.dt_ms / 1000.0);
+  }
+  if (!n->x_thr) {
+    TRY(n->arena.alloc(&n->x_thr, B * NI));
+    TRY(n->arena.alloc(&n->x_list, (size_t)n->K * B * NI));
+  }
+  // blocks already queued read the table: the copy follows them on the stream
+  flush_block(n);
+  HIP_OK(hipEventRecord(n->ev_join, n->side));
+  HIP_OK(hipStreamWaitEvent(n->stream, n->ev_join, 0));
+  HIP_OK(hipMemcpyAsync(n->x_thr, thr.data(), n_rates * 8, hipMemcpyHostToDevice, n->stream));
+  HIP_OK(hipStreamSynchronize(n->stream));
+  n->x_thr_stride = n_rates == NI ? 0 : (int)NI;
+  n->labels = labels_dev;
+  n->x_off = nullptr;
+  n->x_idx = nullptr;
+  n->n_idx = 0;
+  n->poisson = true;
   return RS_OK;
 }
 
 rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
-  if (!n->x_off) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input)");
+  if (!n->x_off && !n->poisson) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input*)");
   if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
   HIP_OK(hipEventRecord(n->ev_join, n->stream));  // side stream follows earlier caller work
   HIP_OK(hipStreamWaitEvent(n->side, n->ev_join, 0));

@@ -108,14 +108,36 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     const int nw = a.n_out * a.n_rec;
     for (int q = tid; q < nw; q += FWD_NT) w[q] = a.Wout[q];
   }
-  if (tid <= a.nsteps) {
-    const int tau = tid < a.nsteps ? tid : a.nsteps - 1;
-    const int xq = ((a.t0 + tau) % a.sample_steps) * B + b;
-    // clamp the caller's offsets into the index array
-    const long long lo = min(max((long long)a.x_off[xq], 0ll), a.n_idx);
-    const long long hi = min(max((long long)a.x_off[xq + 1], lo), a.n_idx);
-    s_xsrc[tid] = tid < a.nsteps ? (int)lo : 0;
-    s_xcnt[tid] = tid < a.nsteps ? (int)(hi - lo) : 0;
+  const int* xsrc_base;  // the step lists: the caller's raster, or drawn below
+  if (a.x_thr) {
+    // Poisson source: one Bernoulli draw per (step, channel) of the block,
+    // spread over the workgroup; spikes are appended to each step's list in
+    // arrival order (the propagation sums are order-independent)
+    xsrc_base = a.x_list;
+    if (tid < 33) s_xcnt[tid] = 0;
+    __syncthreads();
+    const uint64_t* thr = a.x_thr + (int64_t)b * a.x_thr_stride;
+    const int total = a.nsteps * a.n_in;
+    for (int q = tid; q < total; q += FWD_NT) {
+      const int tau = q / a.n_in, i = q - tau * a.n_in;
+      const uint32_t u = draw_u32(a.seed, TAG_INPUT, 0, a.step0 + (uint64_t)tau, (uint64_t)b, (uint64_t)i, 0);
+      if ((uint64_t)u < thr[i]) {
+        const int pos = atomicAdd(&s_xcnt[tau], 1);
+        a.x_list[((int64_t)tau * B + b) * a.n_in + pos] = i;
+      }
+    }
+    if (tid < a.nsteps) s_xsrc[tid] = (tid * B + b) * a.n_in;
+  } else {
+    xsrc_base = a.x_idx;
+    if (tid <= a.nsteps) {
+      const int tau = tid < a.nsteps ? tid : a.nsteps - 1;
+      const int xq = ((a.t0 + tau) % a.sample_steps) * B + b;
+      // clamp the caller's offsets into the index array
+      const long long lo = min(max((long long)a.x_off[xq], 0ll), a.n_idx);
+      const long long hi = min(max((long long)a.x_off[xq + 1], lo), a.n_idx);
+      s_xsrc[tid] = tid < a.nsteps ? (int)lo : 0;
+      s_xcnt[tid] = tid < a.nsteps ? (int)(hi - lo) : 0;
+    }
   }
   for (int q = tid; q < 2 * xwords; q += FWD_NT) xflags2[q] = 0u;
   __syncthreads();
@@ -133,7 +155,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   if (xstaged) {
     for (int t = wv; t < a.nsteps; t += FWD_NT / WAVE) {
       const int n = s_xcnt[t];
-      for (int l = lane; l < n; l += WAVE) xbuf[xpos[t] + l] = a.x_idx[s_xsrc[t] + l];
+      for (int l = lane; l < n; l += WAVE) xbuf[xpos[t] + l] = xsrc_base[s_xsrc[t] + l];
     }
   }
 
@@ -175,7 +197,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     // ---- spikes, surrogate derivative, ordered compaction of the spike list
     int nz = 0;
     const int nx = s_xcnt[tau];
-    const int* xs = xstaged ? xbuf + xpos[tau] : a.x_idx + s_xsrc[tau];
+    const int* xs = xstaged ? xbuf + xpos[tau] : xsrc_base + s_xsrc[tau];
     // input spikes of (t, b) as bits, published by the scan's barrier
     for (int q = tid; q < nx; q += FWD_NT) {
       const int i = xs[q];

@@ -60,6 +60,11 @@ struct FwdArgs {
   const float* Wout;                         // [n_out][n_rec]
   const int* x_off; const int* x_idx; long long n_idx;
   int t0, sample_steps, nsteps;              // steps t0 .. t0+nsteps-1 (raster step t % sample_steps)
+  // Poisson source (x_thr != null, raster unused): channel i of instance b
+  // fires at step step0 + tau when draw_u32(seed, INPUT; step0+tau, b, i, 0)
+  // < x_thr[b * x_thr_stride + i]; the block's lists go to x_list [K][B][n_in]
+  const uint64_t* x_thr; int x_thr_stride; int* x_list;
+  uint64_t seed, step0;
   int wout_lds;                              // 1: stage W_out in LDS for the block
   int xcap;                                  // LDS capacity for the block's input spike lists
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
