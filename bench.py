@@ -84,9 +84,20 @@ def recorded_traffic(kernel: str):
     return int(rec["hbm_bytes_per_dispatch"])
 
 
-def run_cpu_baseline(cfg, raster, labels, n_steps: int):
-    """Time the oracle (single-threaded fp64 C) on a bounded sample of the same
-    workload: n_steps timesteps plus one update and two DEEP R rewires."""
+def tiny_config(seed=1):
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    c = wl.TINY_EPROP
+    f32 = lambda x: float(np.float32(x))
+    return rb.EpropConfig(n_in=c["n_in"], n_rec=c["n_rec"], n_out=c["n_out"], batch=c["batch"], alif=c["alif"],
+                          p_in=c["p_in"], p_rec=c["p_rec"], sigma_in=f32(wl.sigma_init(c["p_in"], c["n_in"])),
+                          sigma_rec=f32(wl.sigma_init(c["p_rec"], c["n_rec"])),
+                          sigma_out=f32(1.0 / np.sqrt(c["n_rec"])), deepr_mask=c["deepr_mask"], l1=c["l1"],
+                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed)
+
+
+def oracle_from_seed(cfg):
+    """The oracle network built from the same seed as the library's."""
     import oracle
     B = cfg.batch
     f32 = lambda x: float(np.float32(x))
@@ -103,6 +114,15 @@ def run_cpu_baseline(cfg, raster, labels, n_steps: int):
                              v_thr=f32(cfg.v_thr), beta=f32(cfg.beta))
     N = oracle.Net(prm, projs[0], projs[1])
     N.Wout[:] = oracle.dense_init(cfg.seed, 2, cfg.n_out, cfg.n_rec, cfg.sigma_out)
+    return N
+
+
+def run_cpu_baseline(cfg, raster, labels, n_steps: int):
+    """Time the oracle (single-threaded fp64 C) on a bounded sample of the same
+    workload: n_steps timesteps plus one update and two DEEP R rewires."""
+    import oracle
+    B = cfg.batch
+    N = oracle_from_seed(cfg)
     t0 = time.perf_counter()
     for t in range(n_steps):
         idx, off = raster.step_lists(t)
@@ -119,6 +139,62 @@ def run_cpu_baseline(cfg, raster, labels, n_steps: int):
             "sample": f"{n_steps} of {T} timesteps and 1 of {T // U} update+DEEP R intervals of one "
                       f"{B}-sample batch, extrapolated linearly to the batch",
             "seconds_per_timestep": t_step, "seconds_per_update_rewire": t_upd}
+
+
+def tiny_net_leg(samples=20, oracle_samples=2):
+    """The tiny e-prop network (100 Poisson inputs at U[0, 50) Hz -> 128 LIF ->
+    4 readouts, p = 0.1, batch 1, 500 steps per sample, Adam + DEEP R every 25
+    steps) trained sample after sample with the device Poisson source; the
+    oracle runs the same workload (its own Poisson source) beside it."""
+    import torch
+    import oracle
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    cfg = tiny_config()
+    T, U = cfg.sample_steps, cfg.update_interval
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, wl.TINY_EPROP["max_rates_hz"])
+    labels = np.zeros(cfg.batch, np.int32)
+    net = rb.EpropNet(cfg)
+    net.set_input_poisson(rates, torch.tensor(labels, device="cuda"))
+    flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+    net.step(T, flags)
+    torch.cuda.synchronize()
+    i0 = net.info()
+    ev0, el0 = i0.synaptic_events, i0.eliminated
+    t0 = time.perf_counter()
+    for _ in range(samples):
+        net.step(T, flags)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    i1 = net.info()
+    n_syn = int(net.get(rb.PROJ(0, rb.P_LEN)).sum() + net.get(rb.PROJ(1, rb.P_LEN)).sum())
+    net.close()
+    steps = samples * T
+    # the oracle: same steps, updates, rewires and resets
+    N = oracle_from_seed(cfg)
+    thr = oracle.rate_thresholds(rates, cfg.dt_ms)
+    k = 0
+    t1 = time.perf_counter()
+    for t in range(oracle_samples * T):
+        idx, off = oracle.poisson_input(cfg.seed, t, cfg.batch, thr)
+        N.step(idx, off, labels)
+        if (t + 1) % U == 0:
+            k += 1
+            N.adam_update(k, lr=cfg.lr, l1=cfg.l1, deepr_mask=cfg.deepr_mask)
+            oracle.deepr_rewire(cfg.seed, N.inp, t + 1)
+            oracle.deepr_rewire(cfg.seed, N.rec, t + 1)
+        if (t + 1) % T == 0:
+            N.reset()
+    orc_s = (time.perf_counter() - t1) / (oracle_samples * T)
+    return {"workload": "tiny e-prop net 100 Poisson (U[0,50) Hz) -> 128 LIF -> 4, p=0.1, batch 1, "
+                        "500 steps/sample, Adam + DEEP R every 25 steps",
+            "samples": samples, "steps_per_s": round(steps / el, 1), "us_per_step": round(1e6 * el / steps, 3),
+            "synaptic_events_per_s": round((i1.synaptic_events - ev0) / el, 1),
+            "synapses": n_syn,
+            "rewired_fraction_per_update": (i1.eliminated - el0) / (samples * (T // U) * n_syn),
+            "oracle_us_per_step": round(1e6 * orc_s, 3), "oracle_cores": 1,
+            "oracle_sample": f"{oracle_samples} samples of the same workload",
+            "gpu_over_oracle": round(orc_s / (el / steps), 2)}
 
 
 def topo_rewire_latency(n_rewires=200):
@@ -156,8 +232,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=24)
+    ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-topo", action="store_true")
+    ap.add_argument("--no-tiny", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy of this many MiB 20 times (byte-counter calibration)")
     args = ap.parse_args()
@@ -205,9 +282,8 @@ def main():
     for q in range(args.warmup):
         one_batch(q)
     torch.cuda.synchronize()
-    # rs_eprop_set_input validates the raster (a host round trip); attach both
-    # rasters' validation outside the timed region by pre-validating them here
-    ev0 = net.info().synaptic_events
+    inf0 = net.info()
+    ev0 = inf0.synaptic_events
     net.timing(0b11110)  # every phase except the per-block forward launch
     net.phase_times()
     print(f"[bench] timing {args.steps} batch(es)", file=sys.stderr, flush=True)
@@ -253,6 +329,9 @@ def main():
         "synaptic_events_per_s": round(events / elapsed, 1),
         "timesteps_per_s": round(args.steps * T / elapsed, 1),
         "phase_ms_per_batch": {k: round(v[0] / args.steps, 3) for k, v in phases.items()},
+        # DEEP R: synapses eliminated (and as many formed) per update, over all synapses
+        "rewired_fraction_per_update": (inf.eliminated - inf0.eliminated) / (args.steps * (T // cfg.update_interval)
+                                                                             * n_syn),
         "roofline": {"bound": "alu", "kernel": "k_eprop_wl<true, 4>", "achieved": round(achieved_tf, 2),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic("k_eprop_wl<true, 4>"),
@@ -264,6 +343,9 @@ def main():
                              "algorithmic_bytes_per_launch": round(alg_bytes / max(ep_n, 1))}},
     }
     net.close()
+    if not args.no_tiny:
+        print("[bench] tiny e-prop network", file=sys.stderr, flush=True)
+        result["tiny_net"] = tiny_net_leg()
     if not args.no_topo:
         print("[bench] topographic-map rewiring latency", file=sys.stderr, flush=True)
         result["topomap_rewire"] = topo_rewire_latency()
