@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-topo", action="store_true")
     ap.add_argument("--no-tiny", action="store_true")
+    ap.add_argument("--only-tiny", action="store_true",
+                    help="run only the tiny-network leg and print its figures (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy of this many MiB 20 times (byte-counter calibration)")
     args = ap.parse_args()
@@ -256,6 +258,10 @@ def main():
             rb.calib_copy(b, a, n)
         torch.cuda.synchronize()
         print(json.dumps({"calib_copy_bytes": n, "launches": 20}))
+        return
+
+    if args.only_tiny:
+        print(json.dumps({"tiny_net": tiny_net_leg()}), flush=True)
         return
 
     cfg = classifier_config()
