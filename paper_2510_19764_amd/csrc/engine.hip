@@ -311,8 +311,8 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Mb, K));
   TRY(ar.alloc(&n->Vb, K));
   TRY(ar.alloc(&n->counters, 2));
-  TRY(ar.alloc(&n->cv.cnt, NR * 8));
-  TRY(ar.alloc(&n->cv.off, NR * 8 + 1));
+  TRY(ar.alloc(&n->cv.cnt, NR * COL_GROUPS_MAX));
+  TRY(ar.alloc(&n->cv.off, NR * COL_GROUPS_MAX + 1));
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
   TRY(ar.alloc(&n->rw_stats, 2));
   TRY(ar.alloc(&n->zcount, (size_t)B * NR));
@@ -393,6 +393,7 @@ void do_update(rs_eprop* n, hipStream_t s) {
 // The column view follows the rows after every rewire or restore; it is timed
 // with the rewire phase.
 void rebuild_columns(rs_eprop* n, hipStream_t s) {
+  if (n->B % 4 != 0) return;  // only the target-major e-prop kernel (B % 4 == 0) reads the column view
   n->timer.begin(s, 3);
   launch_columns(s, n->in, n->rec, n->cv);
   n->timer.end(s);

@@ -28,7 +28,13 @@ constexpr int EP_NT = 256;
 // intervals (100 steps), so no block ends in a short tail launch; psi and L of
 // 20 steps take 40 KB of LDS, four workgroups per CU.
 constexpr int COL_TB = 20;
-constexpr int COL_OCT = 8;  // source octants, one per XCD
+// Source groups per target: the synapses onto target j are split by row
+// r % COL_GRP.  Group g's workgroups land on XCDs g and g + 4, so each XCD
+// gathers presynaptic traces from a quarter of the rows; psi_j and L_j are
+// fetched once per group.  Eight groups (one per XCD) fetched psi/L eight
+// times; one or two groups gathered from too many rows per XCD.
+constexpr int COL_GRP = 4;
+static_assert(COL_GRP <= COL_GROUPS_MAX && 8 % COL_GRP == 0, "groups must divide the 8 XCDs");
 
 __device__ __forceinline__ int64_t ring(const EpropArgs& a, int n, int tau) {
   return ((int64_t)n * a.nslot + a.slot0 + tau) * a.B;
@@ -173,19 +179,20 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
 
 // Workgroups of an e-prop launch: the readout waves come first (they form a
 // long dependent chain per wave and would otherwise trail the launch), padded
-// to a multiple of 8 so that workgroup n_ro + 8j + o still lands on XCD o.
+// to a multiple of 8 so that workgroup n_ro + COL_GRP*j + g lands on XCD
+// (COL_GRP*j + g) % 8.
 __host__ __device__ inline int readout_groups(int n_rec, int nw) {
   return ((n_rec + 1 + nw - 1) / nw + 7) & ~7;
 }
 
-// Target-major form (B % 4 == 0).  Workgroup n_ro + 8j + o owns target
-// neuron j and the synapses onto it from rows r with r % 8 == o (r = i for
-// input rows, n_in + i for recurrent rows).  Workgroups are dealt to the 8 XCDs
-// in turn, so XCD o only gathers the presynaptic traces of its own eighth of
-// the rows, which fits its L2.  Every lane holds four consecutive instances,
+// Target-major form (B % 4 == 0).  Workgroup n_ro + COL_GRP*j + g owns target
+// neuron j and the synapses onto it from rows r with r % COL_GRP == g (r = i
+// for input rows, n_in + i for recurrent rows).  Workgroups are dealt to the 8
+// XCDs in turn, so an XCD only gathers the presynaptic traces of one group of
+// rows, which fits its L2.  Every lane holds four consecutive instances,
 // so one wave covers 256 instances of a synapse with 16-byte accesses; wave w
 // takes synapses w, w + 4, ... of the list.  psi_j and L_j of the block's
-// steps for the current 256-instance chunk are staged once in LDS (32 KB) and
+// steps for the current 256-instance chunk are staged once in LDS (40 KB) and
 // shared by the workgroup's waves, so a synapse step costs one gathered
 // presynaptic trace and six float operations per instance (ALIF):
 //   e = psi (p - beta eps),  d = e - (1 - rho) eps,  eps' = eps + d,
@@ -218,7 +225,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
     return;
   }
   const int wg = blockIdx.x - n_ro;
-  const int j = wg / COL_OCT;
+  const int j = wg / COL_GRP;
   const int q0 = a.col_off[wg], q1 = a.col_off[wg + 1];
   if (q1 <= q0) return;
   const int sub = wv;
@@ -304,8 +311,8 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
 }
 
 // Column view of both projections for k_eprop_wl: entries
-// col[col_off[j*8+o] .. col_off[j*8+o+1]) are (r, slot) of every synapse of a
-// row r with r % 8 == o onto target j.  Rebuilt whenever rows change; the
+// col[col_off[j*G+g] .. col_off[j*G+g+1]) (G = COL_GRP) are (r, slot) of every
+// synapse of a row r with r % G == g onto target j.  Rebuilt whenever rows change; the
 // order inside a list is arbitrary.
 __global__ void __launch_bounds__(WAVE) k_col_count(ProjDev in, ProjDev rec, int* cnt) {
   const int r = blockIdx.x;
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(WAVE) k_col_count(ProjDev in, ProjDev rec, int
   const int i = fin ? r : r - in.n_pre;
   const int n = P.len[i];
   const int64_t base = (int64_t)i * P.cap;
-  for (int k = lane_id(); k < n; k += WAVE) atomicAdd(&cnt[P.ind[base + k] * COL_OCT + (r & 7)], 1);
+  for (int k = lane_id(); k < n; k += WAVE) atomicAdd(&cnt[P.ind[base + k] * COL_GRP + r % COL_GRP], 1);
 }
 
 // Exclusive scan of n counts (one workgroup): off[0..n]; cnt becomes the fill
@@ -352,13 +359,13 @@ __global__ void __launch_bounds__(WAVE) k_col_fill(ProjDev in, ProjDev rec, int*
   const int n = P.len[i];
   const int64_t base = (int64_t)i * P.cap;
   for (int k = lane_id(); k < n; k += WAVE) {
-    const int pos = atomicAdd(&cur[P.ind[base + k] * COL_OCT + (r & 7)], 1);
+    const int pos = atomicAdd(&cur[P.ind[base + k] * COL_GRP + r % COL_GRP], 1);
     col[pos] = make_int2(r, (int)(base + k));
   }
 }
 
 void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const ColumnView& cv) {
-  const int n = rec.n_post * COL_OCT;
+  const int n = rec.n_post * COL_GRP;
   launch_fill_zero(s, cv.cnt, (size_t)n * 4);
   hipLaunchKernelGGL(k_col_count, dim3(in.n_pre + rec.n_pre), dim3(WAVE), 0, s, in, rec, cv.cnt);
   hipLaunchKernelGGL(k_col_scan, dim3(1), dim3(1024), 0, s, cv.cnt, cv.off, n);
@@ -437,7 +444,7 @@ void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
   if (a.B % 4 == 0 && a.col && a.col_off) {
     const int nw = 4;
-    const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_OCT;
+    const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_GRP;
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;
       p.slot0 = a.slot0 + t0;

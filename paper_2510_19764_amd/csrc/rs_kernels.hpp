@@ -23,13 +23,14 @@ struct ProjDev {
 };
 
 // Column view of the two projections onto the recurrent layer, for the
-// target-major e-prop kernel: col[off[j*8+o] .. off[j*8+o+1]) holds (r, slot)
-// of every synapse onto target j from a row r with r % 8 == o, where
-// r = i for input rows and n_in + i for recurrent rows.  Rebuilt whenever
-// rows change.
+// target-major e-prop kernel: col[off[j*G+g] .. off[j*G+g+1]) holds (r, slot)
+// of every synapse onto target j from a row r with r % G == g, where G is the
+// kernel's number of source groups (at most COL_GROUPS_MAX) and r = i for input
+// rows and n_in + i for recurrent rows.  Rebuilt whenever rows change.
+constexpr int COL_GROUPS_MAX = 8;
 struct ColumnView {
-  int* cnt;          // [n_rec*8] counts, then the fill cursor
-  int* off;          // [n_rec*8 + 1]
+  int* cnt;          // [n_rec*COL_GROUPS_MAX] counts, then the fill cursor
+  int* off;          // [n_rec*COL_GROUPS_MAX + 1]
   int2* col;         // [n_in*cap_in + n_rec*cap_rec]
 };
 
