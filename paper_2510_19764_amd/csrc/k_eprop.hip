@@ -204,6 +204,57 @@ __host__ __device__ inline int readout_groups(int n_rec, int nw) {
 // and its four instances, reduced once per synapse and chunk, and added to G
 // in chunk order by the one wave that owns the synapse, so the result does
 // not depend on scheduling or on the order of the column list.
+// One synapse's inputs to a launch: its eps/ebar records, the presynaptic
+// start trace and spike mask of the lane's instances, and its gradient before
+// the launch.  r = i (input row) or n_in + i (recurrent row) and
+// slot = i * cap + k are wave-uniform.
+template <int IPL>
+struct SynIn {
+  typedef typename VecT<IPL>::type V;
+  typedef unsigned U __attribute__((ext_vector_type(IPL)));
+  V eb, ep, pr;
+  U bits;
+  float g0;
+  int fin, slot;
+};
+template <bool ALIF, int IPL>
+__device__ __forceinline__ void syn_load(const EpropArgs& a, int r, int slot, uint32_t off,
+                                         uint32_t step_bytes, SynIn<IPL>& s) {
+  s.fin = r < a.n_in;
+  s.slot = slot;
+  const int i = s.fin ? r : r - a.n_in;
+  const int64_t rec = (int64_t)slot * a.B;
+  const auto reb = buf_rsrc((s.fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
+  s.eb = buf_ldv_nt<IPL>(reb, off);
+  if (ALIF) {
+    s.ep = buf_ldv_nt<IPL>(buf_rsrc((s.fin ? a.in.eps : a.rec.eps) + rec, step_bytes), off);
+  } else {
+#pragma unroll
+    for (int e = 0; e < IPL; ++e) s.ep[e] = 0.0f;
+  }
+  // presynaptic trace of the block start and the block's spike bits; the
+  // trace of each step is rebuilt with the forward pass's float recursion
+  // F <- fma(alpha, F, spike), so it equals the forward's value
+  s.pr = buf_ldv<IPL>(buf_rsrc((s.fin ? a.x0 : a.z0) + (int64_t)i * a.B, step_bytes), off, 0);
+  s.bits = __builtin_bit_cast(typename SynIn<IPL>::U,
+                              buf_ldv<IPL>(buf_rsrc((s.fin ? a.xbits : a.zbits) + (int64_t)i * a.B, step_bytes), off, 0));
+  s.g0 = buf_ld(buf_rsrc((s.fin ? a.in.G : a.rec.G) + slot, 4u), 0u, 0u);  // every lane reads the one word
+}
+// Write back a synapse's traces and gradient.  The stores are unconditional:
+// a lane that must not store passes an offset past the buffer's size, which
+// the buffer unit drops, so the wave's memory counter stays path-independent.
+template <bool ALIF, int IPL>
+__device__ __forceinline__ void syn_store(const EpropArgs& a, const SynIn<IPL>& s, uint32_t soff,
+                                          uint32_t step_bytes, typename VecT<IPL>::type eb,
+                                          typename VecT<IPL>::type ep, float g, uint32_t goff) {
+  // uniform values, restated so the address arithmetic stays scalar
+  const int fin = __builtin_amdgcn_readfirstlane(s.fin), slot = __builtin_amdgcn_readfirstlane(s.slot);
+  const int64_t rec = (int64_t)slot * a.B;
+  buf_stv_nt<IPL>(eb, buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes), soff);
+  if (ALIF) buf_stv_nt<IPL>(ep, buf_rsrc((fin ? a.in.eps : a.rec.eps) + rec, step_bytes), soff);
+  buf_st(g, buf_rsrc((fin ? a.in.G : a.rec.G) + slot, 4u), goff);
+}
+
 constexpr int WL_CH = 4 * WAVE;  // instances per LDS chunk
 constexpr int WL_IPL = 4;  // instances per lane
 
@@ -215,7 +266,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
   typedef unsigned U __attribute__((ext_vector_type(IPL)));
   static_assert(IPL == 4, "one wave covers a 256-instance chunk");
   constexpr int LPC = WL_CH / IPL;  // vectors across a chunk
-  // 32 KB: with more, the compiler budgets registers for fewer waves
+  // 40 KB at 20 steps: four workgroups per CU
   __shared__ V s_psi[COL_TB][LPC], s_L[COL_TB][LPC];
   const int wv = wave_id(), lane = lane_id();
   const int nw = blockDim.x / WAVE;
@@ -252,59 +303,68 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
       }
     }
     __syncthreads();
+    // stores of idle lanes (instances past B) and gradient stores of all
+    // lanes but 0 go past their buffer and are dropped
+    const uint32_t soff = act ? off : 0x40000000u, goff = lane == 0 ? 0u : 0x40000000u;
+    // one synapse: the block's steps on its loaded inputs, then the write-back
+    auto run = [&](const SynIn<IPL>& in) {
+      V eb = in.eb, ep = in.ep, pr = in.pr;
+      for (int t = 0; t < a.tofs; ++t) pr = trace_next<IPL>(pr, alpha, in.bits, t);
+      V g = zero;
+#pragma unroll
+      for (int t = 0; t < COL_TB; ++t) {
+        // step groups of four: the launch's steps end at a group boundary
+        // or inside the last group; LDS reads stay inside their group
+        // (hoisted, they would cost registers, hence occupancy)
+        if (t % 4 == 0) {
+          if (t >= T) break;
+          __asm__ volatile("" ::: "memory");
+        }
+        const V psi = s_psi[t][lv], L = s_L[t][lv];
+        // decay factors (alpha, 1 - rho) for the launch's steps and (1, 0)
+        // past them, where psi = L = 0 as well: padded steps change nothing
+        const float da = t < T ? alpha : 1.0f, dr = t < T ? omr : 0.0f;
+        // every product-sum is an explicit fma, so each unrolled copy of the
+        // step rounds alike and the result does not depend on the block length
+        if (ALIF) {
+          const V e = psi * __builtin_elementwise_fma((V)(-beta), ep, pr);
+          const V d = __builtin_elementwise_fma((V)(-dr), ep, e);
+          ep = ep + d;
+          eb = __builtin_elementwise_fma((V)da, eb, e);
+        } else {
+          eb = __builtin_elementwise_fma((V)da, eb, psi * pr);
+        }
+        g = __builtin_elementwise_fma(L, eb, g);
+        pr = trace_next<IPL>(pr, alpha, in.bits, a.tofs + t);
+      }
+      syn_store<ALIF, IPL>(a, in, soff, step_bytes, eb, ep, in.g0 + wave_sum(hsum<IPL>(g)), goff);
+    };
     for (int sc = q0; sc < q1; sc += WAVE) {  // chunks of 64 list entries
       const int ns = min(WAVE, q1 - sc);
+      if (sub >= ns) break;  // only the last chunk is short
+      // the chunk's list entries, one per lane; a synapse's entry is read
+      // from its lane, so no memory access waits on it
+      const int2 ents = a.col[sc + min(lane, ns - 1)];
+      auto load = [&](int k, SynIn<IPL>& in) {
+        syn_load<ALIF, IPL>(a, __builtin_amdgcn_readlane(ents.x, k), __builtin_amdgcn_readlane(ents.y, k), off,
+                            step_bytes, in);
+      };
+      // Each synapse's inputs are loaded one synapse ahead, alternating
+      // between two register sets: while the wave computes synapse k, the
+      // loads of k + 4 are in flight, and the gradient is written back
+      // without being read again.  The loads are unconditional (past the
+      // list the last entry is read again and not used), so the number of
+      // memory operations in flight is the same on every path and the waits
+      // before a synapse's steps cover only its own loads.
+      SynIn<IPL> s0, s1;
+      load(sub, s0);
 #pragma unroll 1
-      for (int k = sub; k < ns; k += 4) {
-        // keeps the per-step LDS reads and the trace loads inside their
-        // groups (hoisted, they would cost registers, hence occupancy)
-        __asm__ volatile("" ::: "memory");
-        const int2 ent = a.col[sc + k];
-        const bool fin = ent.x < a.n_in;
-        const int i = fin ? ent.x : ent.x - a.n_in;
-        const int64_t rec = (int64_t)ent.y * B;
-        const auto reb = buf_rsrc((fin ? a.in.ebar : a.rec.ebar) + rec, step_bytes);
-        const auto rep = buf_rsrc(ALIF ? (fin ? a.in.eps : a.rec.eps) + rec : a.in.ebar, step_bytes);
-        // presynaptic trace of the block start and the block's spike bits;
-        // the trace of each step is rebuilt with the forward pass's float
-        // recursion F <- fma(alpha, F, spike), so it equals the forward's value
-        const auto rx0 = buf_rsrc((fin ? a.x0 : a.z0) + (int64_t)i * B, step_bytes);
-        const auto rbt = buf_rsrc((fin ? a.xbits : a.zbits) + (int64_t)i * B, step_bytes);
-        V eb = buf_ldv_nt<IPL>(reb, off);
-        V ep = ALIF ? buf_ldv_nt<IPL>(rep, off) : zero;
-        V pr = buf_ldv<IPL>(rx0, off, 0);
-        const U bits = __builtin_bit_cast(U, buf_ldv<IPL>(rbt, off, 0));
-        for (int t = 0; t < a.tofs; ++t) pr = trace_next<IPL>(pr, alpha, bits, t);
-        V g = zero;
-#pragma unroll
-        for (int t = 0; t < COL_TB; ++t) {
-          // step groups of four: the launch's steps end at a group boundary
-          // or inside the last group; LDS reads stay inside their group
-          if (t % 4 == 0) {
-            if (t >= T) break;
-            __asm__ volatile("" ::: "memory");
-          }
-          const V psi = s_psi[t][lv], L = s_L[t][lv];
-          // decay factors (alpha, 1 - rho) for the launch's steps and (1, 0)
-          // past them, where psi = L = 0 as well: padded steps change nothing
-          const float da = t < T ? alpha : 1.0f, dr = t < T ? omr : 0.0f;
-          if (ALIF) {
-            const V e = psi * (pr - beta * ep);
-            const V d = e - dr * ep;
-            ep = ep + d;
-            eb = da * eb + e;
-          } else {
-            eb = da * eb + psi * pr;
-          }
-          g = g + L * eb;
-          pr = trace_next<IPL>(pr, alpha, bits, a.tofs + t);
-        }
-        if (act) {
-          buf_stv_nt<IPL>(eb, reb, off);
-          if (ALIF) buf_stv_nt<IPL>(ep, rep, off);
-        }
-        const float gs = wave_sum(hsum<IPL>(g));
-        if (lane == 0) (fin ? a.in.G : a.rec.G)[ent.y] += gs;
+      for (int k = sub; k < ns; k += 8) {
+        load(min(k + 4, ns - 1), s1);
+        run(s0);
+        if (k + 4 >= ns) break;
+        load(min(k + 8, ns - 1), s0);
+        run(s1);
       }
     }
   }
@@ -423,12 +483,12 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
       for (int tau = 0; tau < a.nsteps; ++tau) {
         const float psi = a.psiT[ring(a, j, tau) + b];
         if (ALIF) {
-          const float e = psi * (p - a.beta * ep);
-          const float d = e - a.one_m_rho * ep;
+          const float e = psi * fmaf(-a.beta, ep, p);
+          const float d = fmaf(-a.one_m_rho, ep, e);
           ep = ep + d;
-          eb = a.alpha * eb + e;
+          eb = fmaf(a.alpha, eb, e);
         } else {
-          eb = a.alpha * eb + psi * p;
+          eb = fmaf(a.alpha, eb, psi * p);
         }
         gsum = fmaf(a.LT[ring(a, j, tau) + b], eb, gsum);
         p = fmaf(a.alpha, p, (float)((w >> (a.tofs + tau)) & 1u));
