@@ -32,6 +32,9 @@ CASES = {
     "lif-b256-col": (make_cfg(50, 80, 6, 256, False, seed=4), 150.0),
     "alif-b320-col": (make_cfg(40, 70, 4, 320, True, seed=5), 150.0),
     "alif-b33-narrow": (make_cfg(36, 50, 3, 33, True, seed=6), 150.0),
+    # about 112 synapses per target and source group: the target-major kernel
+    # walks each list in several 64-entry chunks, the last one short
+    "alif-b64-dense": (make_cfg(300, 200, 5, 64, True, p=0.9, seed=7), 60.0),
 }
 
 
@@ -69,6 +72,14 @@ def test_build_matches_oracle(name):
     Wo = oracle.dense_init(cfg.seed, 2, cfg.n_out, cfg.n_rec, cfg.sigma_out)
     close("Wout", snap["Wout"], Wo, 0.0, rtol=1e-6)
     assert not snap["bout"].any()
+    if name == "alif-b64-dense":
+        # synapses per (target, row % 4): every list spans more than one 64-entry chunk
+        cnt = np.zeros((cfg.n_rec, 4), int)
+        for tag, off in (("in", 0), ("rec", cfg.n_in)):
+            g = snap[tag]
+            for i in range(g["len"].size):
+                np.add.at(cnt, (g["ind"][i, :g["len"][i]], (off + i) % 4), 1)
+        assert cnt.min() > 64 and cnt.max() < 128
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -236,7 +247,8 @@ def test_error_paths():
     assert code == rb.RS_ECAPACITY
 
 
-@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col", "alif-b3-narrow", "alif-b320-col"])
+@pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col", "alif-b3-narrow", "alif-b320-col",
+                                  "alif-b64-dense"])
 def test_trace_block_length_invariance(name):
     """Applying eligibility updates in blocks of K steps gives bit-identical
     neuron state, traces and eps/ebar for every K, over uneven step calls.  The
@@ -355,7 +367,7 @@ def test_lockstep_after_rewire(name):
     assert resync <= 2
 
 
-@pytest.mark.parametrize("name", ["alif-b64-col", "alif-b3-narrow"])
+@pytest.mark.parametrize("name", ["alif-b64-col", "alif-b3-narrow", "alif-b64-dense"])
 def test_slot_order_is_irrelevant(name):
     """Restoring rows with every row's slots reversed (all per-synapse arrays
     permuted alike) gives bit-identical results after 20 learning steps:
