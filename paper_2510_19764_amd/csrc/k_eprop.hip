@@ -28,6 +28,7 @@ constexpr int EP_NT = 256;
 // intervals (100 steps), so no block ends in a short tail launch; psi and L of
 // 20 steps take 40 KB of LDS, four workgroups per CU.
 constexpr int COL_TB = 20;
+static_assert(COL_TB % 4 == 0, "the step loop runs in groups of four");
 // Source groups per target: the synapses onto target j are split by row
 // r % COL_GRP.  Group g's workgroups land on XCDs g and g + 4, so each XCD
 // gathers presynaptic traces from a quarter of the rows; psi_j and L_j are
@@ -112,6 +113,25 @@ __device__ __forceinline__ typename VecT<IPL>::type trace_next(
     typename VecT<IPL>::type f, float alpha, unsigned __attribute__((ext_vector_type(IPL))) w, int t) {
 #pragma unroll
   for (int e = 0; e < IPL; ++e) f[e] = fmaf(alpha, f[e], (float)((w[e] >> t) & 1u));
+  return f;
+}
+// The spike bits of steps t .. t+3 moved to bit 0 of bytes 0 .. 3: with
+// x = b0 + 2 b1 + 4 b2 + 8 b3, x * (1 + 2^7 + 2^14 + 2^21) puts b_k at bit
+// k + 7m for the m-th term, sixteen distinct positions (no carries), of which
+// the mask keeps 0, 8, 16 and 24.  A step's spike is then one byte conversion
+// (v_cvt_f32_ubyteN).  The mask is applied in asm: seen by the compiler, the
+// known-zero bits would turn those conversions back into bit extracts.
+__device__ __forceinline__ uint32_t spikes4(uint32_t w, int t) {
+  const uint32_t m = __umul24((w >> t) & 15u, 0x204081u);
+  uint32_t r;
+  __asm__("v_and_b32 %0, 0x1010101, %1" : "=v"(r) : "v"(m));
+  return r;
+}
+template <int IPL>
+__device__ __forceinline__ typename VecT<IPL>::type trace_next_byte(
+    typename VecT<IPL>::type f, float alpha, unsigned __attribute__((ext_vector_type(IPL))) sp, int byte) {
+#pragma unroll
+  for (int e = 0; e < IPL; ++e) f[e] = fmaf(alpha, f[e], (float)((sp[e] >> (8 * byte)) & 0xFFu));
   return f;
 }
 
@@ -311,6 +331,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
       V eb = in.eb, ep = in.ep, pr = in.pr;
       for (int t = 0; t < a.tofs; ++t) pr = trace_next<IPL>(pr, alpha, in.bits, t);
       V g = zero;
+      U sp;  // spikes of the current group of four steps, one per byte
 #pragma unroll
       for (int t = 0; t < COL_TB; ++t) {
         // step groups of four: the launch's steps end at a group boundary
@@ -319,6 +340,8 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
         if (t % 4 == 0) {
           if (t >= T) break;
           __asm__ volatile("" ::: "memory");
+#pragma unroll
+          for (int e = 0; e < IPL; ++e) sp[e] = spikes4(in.bits[e], a.tofs + t);
         }
         const V psi = s_psi[t][lv], L = s_L[t][lv];
         // decay factors (alpha, 1 - rho) for the launch's steps and (1, 0)
@@ -335,7 +358,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
           eb = __builtin_elementwise_fma((V)da, eb, psi * pr);
         }
         g = __builtin_elementwise_fma(L, eb, g);
-        pr = trace_next<IPL>(pr, alpha, in.bits, a.tofs + t);
+        pr = trace_next_byte<IPL>(pr, alpha, sp, t % 4);
       }
       syn_store<ALIF, IPL>(a, in, soff, step_bytes, eb, ep, in.g0 + wave_sum(hsum<IPL>(g)), goff);
     };
