@@ -519,7 +519,6 @@ void do_step(rs_eprop* n, uint32_t flags) {
       do_update(n, e);
       if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
       if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
-      if (n->p.deepr_mask) rebuild_columns(n, e);
     }
     if (rst) {
       n->timer.begin(e, 4);
@@ -528,6 +527,9 @@ void do_step(rs_eprop* n, uint32_t flags) {
     }
     (void)hipEventRecord(n->ev_back, e);
     (void)hipStreamWaitEvent(s, n->ev_back, 0);
+    // only the e-prop launches, later on this stream, read the column view:
+    // the next forward block runs while it is rebuilt
+    if (upd && n->p.deepr_mask) rebuild_columns(n, e);
   }
 }
 
