@@ -145,7 +145,9 @@ struct rs_eprop {
   uint64_t blk_t0 = 0;
   bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
+  hipStream_t side2 = nullptr;                        // input-projection rewire, beside the recurrent one
   hipEvent_t ev_fwd = nullptr, ev_ep[2] = {}, ev_join = nullptr, ev_back = nullptr;
+  hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
   bool ep_pending[2] = {false, false};
   uint8_t* z = nullptr;
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
@@ -297,6 +299,9 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
     TRY(ar.alloc(&n->u_stg, 2 * KB * K));
   }
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
+  HIP_OK(hipStreamCreateWithFlags(&n->side2, hipStreamNonBlocking));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_upd, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_rw, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
   for (int q = 0; q < 2; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
@@ -517,8 +522,19 @@ void do_step(rs_eprop* n, uint32_t flags) {
     (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
     if (upd) {
       do_update(n, e);
-      if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
-      if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
+      if (n->p.deepr_mask == 3) {
+        // the two projections' rewires share nothing but the summed counts:
+        // the input projection's runs on a third stream beside the other
+        (void)hipEventRecord(n->ev_upd, e);
+        (void)hipStreamWaitEvent(n->side2, n->ev_upd, 0);
+        do_rewire(n, 0, n->side2);
+        do_rewire(n, 1, e);
+        (void)hipEventRecord(n->ev_rw, n->side2);
+        (void)hipStreamWaitEvent(e, n->ev_rw, 0);
+      } else {
+        if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
+        if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
+      }
     }
     if (rst) {
       n->timer.begin(e, 4);
@@ -794,10 +810,12 @@ void rs_eprop_destroy(rs_eprop* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->stream);
   if (n->side) (void)hipStreamSynchronize(n->side);
+  if (n->side2) (void)hipStreamSynchronize(n->side2);
   n->timer.destroy();
-  for (hipEvent_t ev : {n->ev_fwd, n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back})
+  for (hipEvent_t ev : {n->ev_fwd, n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
     if (ev) (void)hipEventDestroy(ev);
   if (n->side) (void)hipStreamDestroy(n->side);
+  if (n->side2) (void)hipStreamDestroy(n->side2);
   n->arena.release();
   delete n;
 }
