@@ -16,10 +16,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def make_cfg(n_in, n_rec, n_out, B, alif, p=0.2, seed=3, U=25, T=500, mask=3, lr=1e-3):
+def make_cfg(n_in, n_rec, n_out, B, alif, p=0.2, seed=3, U=25, T=500, mask=3, lr=1e-3, p_in=None, p_rec=None):
     f32 = lambda x: float(np.float32(x))
-    return rb.EpropConfig(n_in=n_in, n_rec=n_rec, n_out=n_out, batch=B, alif=alif, p_in=p, p_rec=p,
-                          sigma_in=f32(wl.sigma_init(p, n_in)), sigma_rec=f32(wl.sigma_init(p, n_rec)),
+    p_in = p if p_in is None else p_in
+    p_rec = p if p_rec is None else p_rec
+    sig = lambda q, n: f32(wl.sigma_init(q, n)) if q > 0 else 1.0
+    return rb.EpropConfig(n_in=n_in, n_rec=n_rec, n_out=n_out, batch=B, alif=alif, p_in=p_in, p_rec=p_rec,
+                          sigma_in=sig(p_in, n_in), sigma_rec=sig(p_rec, n_rec),
                           sigma_out=f32(1.0 / np.sqrt(n_rec)), deepr_mask=mask, update_interval=U,
                           sample_steps=T, seed=seed, lr=lr)
 
@@ -35,6 +38,13 @@ CASES = {
     # about 112 synapses per target and source group: the target-major kernel
     # walks each list in several 64-entry chunks, the last one short
     "alif-b64-dense": (make_cfg(300, 200, 5, 64, True, p=0.9, seed=7), 60.0),
+    # 5000 recurrent neurons: five neurons per forward thread (the widest
+    # forward kernel) and 20000 target-major workgroups
+    "alif-b4-wide": (make_cfg(2500, 5000, 5, 4, True, p=0.02, seed=8), 40.0),
+    # empty projections: no recurrent synapses (and 8 instances, 2 lanes of a
+    # 256-instance chunk), no input synapses
+    "alif-b8-norec": (make_cfg(40, 60, 3, 8, True, seed=9, p_rec=0.0), 150.0),
+    "lif-b4-noinput": (make_cfg(30, 50, 3, 4, False, seed=10, p_in=0.0), 150.0),
 }
 
 
@@ -60,7 +70,7 @@ def test_build_matches_oracle(name):
         g = snap[tag]
         cap = g["ind"].shape[1]
         lens, mx = oracle.fixed_prob_count(cfg.seed, n_pre, cfg.n_rec, p, rec, pid)
-        assert cap == min(2 * mx, cfg.n_rec)
+        assert cap == max(min(2 * mx, cfg.n_rec), 1)
         P = oracle.Proj(n_pre, cfg.n_rec, cap, rec, pid, bitfields=True)
         oracle.fixed_prob_rows(cfg.seed, P, p, sigma)
         compare_rows_exact(tag, g, P)
@@ -96,7 +106,10 @@ def test_lockstep_100_steps(name):
         spikes += int(snap["z"].sum())
         counts += snap["z"].astype(np.uint32)
         compare_state(snap, N, cfg)
-    assert spikes > 0
+    if cfg.p_in > 0:
+        assert spikes > 0
+    else:  # no input synapses: the network stays at rest
+        assert spikes == 0 and not snap["v"].any()
     assert resync <= 2, f"{resync} threshold ties in 100 steps"
     inf = net.info()
     assert inf.step == 100 and inf.spikes == spikes
@@ -160,7 +173,8 @@ def test_deepr_rewire_bit_exact(name):
         P = N.inp if proj == 0 else N.rec
         dormant, ost = oracle.deepr_rewire(cfg.seed, P, step)
         assert (st.eliminated, st.formed) == (int(ost[0]), int(ost[1]))
-        assert st.eliminated > 0
+        empty = (cfg.p_in if proj == 0 else cfg.p_rec) == 0.0
+        assert st.eliminated == 0 if empty else st.eliminated > 0
         tag = "in" if proj == 0 else "rec"
         g = post[tag]
         cap = g["ind"].shape[1]
