@@ -120,6 +120,8 @@ struct PhaseTimer {
 
 }  // namespace
 
+constexpr int RING_MAX = 8;  // hand-off ring segments at most
+
 struct rs_eprop {
   rs_eprop_params p;
   hipStream_t stream = nullptr;
@@ -129,26 +131,28 @@ struct rs_eprop {
   ColumnView cv{};                                    // target-major view of both projections
   double *V = nullptr, *A = nullptr, *Y = nullptr;   // fp64 neuron and readout state
   float *xbar = nullptr, *zbar = nullptr;             // presynaptic traces [B][n]
-  // Hand-off from the forward kernel to the e-prop kernel: a ring of 2K step
-  // slots laid out [n][2K][B].  Steps are grouped in blocks of K; the forward
-  // pass fills one half while the e-prop launch of the previous block reads
-  // the other.
+  // Hand-off from the forward kernel to the e-prop kernel: a ring of Q
+  // segments of K step slots, laid out [n][Q*K][B].  Steps are grouped in
+  // blocks of K; the forward pass fills one segment while e-prop launches read
+  // earlier ones.  With a segment per block of an update interval (plus one),
+  // the forward stream never waits for an e-prop launch inside an interval:
+  // the join at each update covers them all.
   float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
-  // per block half: traces at the block start and the block's spike bits, [2][n][B]
+  // per segment: traces at the block start and the block's spike bits, [Q][n][B]
   float *x0T = nullptr, *z0T = nullptr;
   uint32_t *xbitsT = nullptr, *zbitsT = nullptr;
   // the forward kernel's coalesced staging of one block, [tau][B][n]
   uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [K][B][NR]; x0, z0, xbits, zbits [B][n]
-  float *u_stg = nullptr;                             // readout drive [2 halves][K][B][n_out]
-  int K = 8, nslot = 16;
-  int blk_half = 0, blk_n = 0, last_slot = 0;
+  float *u_stg = nullptr;                             // readout drive [Q segments][K][B][n_out]
+  int K = 8, Q = 2, nslot = 16;
+  int blk_seg = 0, blk_n = 0, last_slot = 0;
   uint64_t blk_t0 = 0;
   bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
   hipStream_t side2 = nullptr;                        // input-projection rewire, beside the recurrent one
-  hipEvent_t ev_fwd = nullptr, ev_ep[2] = {}, ev_join = nullptr, ev_back = nullptr;
+  hipEvent_t ev_fwd = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
   hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
-  bool ep_pending[2] = {false, false};
+  bool ep_pending[RING_MAX] = {};  // an e-prop launch reading the segment may still run
   uint8_t* z = nullptr;
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
   float *Mout = nullptr, *Vout = nullptr, *Mb = nullptr, *Vb = nullptr;
@@ -281,12 +285,17 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  TRY(ar.alloc(&n->x0T, 2 * NI * B));
-  TRY(ar.alloc(&n->z0T, 2 * NR * B));
-  TRY(ar.alloc(&n->xbitsT, 2 * NI * B));
-  TRY(ar.alloc(&n->zbitsT, 2 * NR * B));
   n->K = prm->trace_block ? (int)prm->trace_block : 20;
-  n->nslot = 2 * n->K;
+  {
+    const uint32_t U = prm->update_interval, Kb = (uint32_t)n->K;
+    n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>((U + Kb - 1) / Kb + 1, 2), RING_MAX) : 2;
+  }
+  const size_t QS = (size_t)n->Q;
+  TRY(ar.alloc(&n->x0T, QS * NI * B));
+  TRY(ar.alloc(&n->z0T, QS * NR * B));
+  TRY(ar.alloc(&n->xbitsT, QS * NI * B));
+  TRY(ar.alloc(&n->zbitsT, QS * NR * B));
+  n->nslot = n->Q * n->K;
   const size_t NS = (size_t)n->nslot;
   TRY(ar.alloc(&n->psiT, NR * NS * B));
   TRY(ar.alloc(&n->LT, NR * NS * B));
@@ -296,14 +305,14 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
     TRY(ar.alloc(&n->stg[0], KB * NR));                   // psi
     const size_t dims[HANDOFF_ARRAYS] = {NR, NI, NR, NI, NR};  // psi, x0, z0, xbits, zbits
     for (int q = 1; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], (size_t)B * dims[q]));
-    TRY(ar.alloc(&n->u_stg, 2 * KB * K));
+    TRY(ar.alloc(&n->u_stg, QS * KB * K));
   }
   HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
   HIP_OK(hipStreamCreateWithFlags(&n->side2, hipStreamNonBlocking));
   HIP_OK(hipEventCreateWithFlags(&n->ev_upd, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_rw, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
-  for (int q = 0; q < 2; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
+  for (int q = 0; q < n->Q; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_back, hipEventDisableTiming));
   TRY(ar.alloc(&n->z, B * NR));
@@ -339,10 +348,10 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   for (double* q : {n->V, n->A}) launch_fill_zero(s, q, B * NR * 8);
   launch_fill_zero(s, n->zbar, B * NR * 4);
   for (float* q : {n->psiT, n->LT}) launch_fill_zero(s, q, B * NR * NS * 4);
-  launch_fill_zero(s, n->x0T, 2 * B * NI * 4);
-  launch_fill_zero(s, n->z0T, 2 * B * NR * 4);
-  launch_fill_zero(s, n->xbitsT, 2 * B * NI * 4);
-  launch_fill_zero(s, n->zbitsT, 2 * B * NR * 4);
+  launch_fill_zero(s, n->x0T, QS * B * NI * 4);
+  launch_fill_zero(s, n->z0T, QS * B * NR * 4);
+  launch_fill_zero(s, n->xbitsT, QS * B * NI * 4);
+  launch_fill_zero(s, n->zbitsT, QS * B * NR * 4);
   launch_fill_zero(s, n->deltaT, B * K * NS * 4);
   launch_fill_zero(s, n->xbar, B * NI * 4);
   launch_fill_zero(s, n->Y, B * K * 8);
@@ -412,14 +421,14 @@ void do_rewire(rs_eprop* n, int proj, hipStream_t s) {
 }
 
 // Run the open block (steps accumulated since the last flush): one forward
-// launch for all its steps on the caller's stream, writing ring half
-// blk_half, then the e-prop launch on the side stream.  The forward pass of
-// the next block (other half) overlaps this e-prop launch; a half is reused
-// only after the e-prop launch that read it has finished.
+// launch for all its steps on the caller's stream, writing ring segment
+// blk_seg, then the e-prop launch on the side stream.  The forward pass of
+// the next block (next segment) overlaps this e-prop launch; a segment is
+// reused only after the e-prop launch that read it has finished.
 void flush_block(rs_eprop* n) {
   if (n->blk_n == 0) return;
   hipStream_t s = n->stream, e = n->side;
-  const int h = n->blk_half;
+  const int h = n->blk_seg;
   if (n->ep_pending[h]) {
     (void)hipStreamWaitEvent(s, n->ev_ep[h], 0);
     n->ep_pending[h] = false;
@@ -497,7 +506,7 @@ void flush_block(rs_eprop* n) {
   // the next forward launch into this half waits for everything above
   (void)hipEventRecord(n->ev_ep[h], e);
   n->ep_pending[h] = true;
-  n->blk_half ^= 1;
+  n->blk_seg = (n->blk_seg + 1) % n->Q;
   n->blk_n = 0;
 }
 
@@ -517,9 +526,9 @@ void do_step(rs_eprop* n, uint32_t flags) {
   const bool upd = (flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0;
   const bool rst = (flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0;
   if (upd || rst) {
+    // the side stream follows the last forward launch: every flush ends with
+    // that wait, and the open block was flushed here or at its last step
     flush_block(n);
-    (void)hipEventRecord(n->ev_fwd, s);  // side stream after the last forward launch
-    (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
     if (upd) {
       do_update(n, e);
       if (n->p.deepr_mask == 3) {
@@ -543,6 +552,7 @@ void do_step(rs_eprop* n, uint32_t flags) {
     }
     (void)hipEventRecord(n->ev_back, e);
     (void)hipStreamWaitEvent(s, n->ev_back, 0);
+    for (bool& p : n->ep_pending) p = false;  // covered by that wait
     // only the e-prop launches, later on this stream, read the column view:
     // the next forward block runs while it is rebuilt
     if (upd && n->p.deepr_mask) rebuild_columns(n, e);
@@ -674,6 +684,7 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   flush_block(n);
   HIP_OK(hipEventRecord(n->ev_back, n->side));     // caller's stream covers all of it
   HIP_OK(hipStreamWaitEvent(n->stream, n->ev_back, 0));
+  for (bool& p : n->ep_pending) p = false;
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
@@ -812,7 +823,9 @@ void rs_eprop_destroy(rs_eprop* n) {
   if (n->side) (void)hipStreamSynchronize(n->side);
   if (n->side2) (void)hipStreamSynchronize(n->side2);
   n->timer.destroy();
-  for (hipEvent_t ev : {n->ev_fwd, n->ev_ep[0], n->ev_ep[1], n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
+  for (hipEvent_t ev : {n->ev_fwd, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : n->ev_ep)
     if (ev) (void)hipEventDestroy(ev);
   if (n->side) (void)hipStreamDestroy(n->side);
   if (n->side2) (void)hipStreamDestroy(n->side2);
