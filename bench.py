@@ -37,8 +37,7 @@ def classifier_config(seed=1, trace_block=20):
                           p_in=c["p_in"], p_rec=c["p_rec"], sigma_in=f32(wl.sigma_init(c["p_in"], c["n_in"])),
                           sigma_rec=f32(wl.sigma_init(c["p_rec"], c["n_rec"])),
                           sigma_out=f32(1.0 / np.sqrt(c["n_rec"])), deepr_mask=c["deepr_mask"], l1=c["l1"],
-                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed,
-                          trace_block=trace_block)
+                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed)
 
 
 def eprop_algorithmic_bytes(cfg, n_syn: int, n_launch: int, n_steps: int) -> int:

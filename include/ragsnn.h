@@ -75,9 +75,10 @@ typedef struct rs_eprop_params {
   uint32_t sample_steps;     /* steps per presented sample; state resets after each */
   uint64_t seed;
   uint32_t trace_block;      /* steps whose eligibility updates the library applies
-                                together, 1..32 (0 = 20); neuron state, traces and
-                                eps/ebar do not depend on it, the gradient only by
-                                float rounding of its sum */
+                                together, 1..32; 0 = 20, or update_interval when
+                                batch % 4 != 0 and update_interval <= 32.  Neuron
+                                state, traces and eps/ebar do not depend on it, the
+                                gradient only by float rounding of its sum */
   uint32_t reserved;         /* must be 0 */
 } rs_eprop_params;
 

@@ -285,7 +285,15 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  n->K = prm->trace_block ? (int)prm->trace_block : 20;
+  // default block length: 20 steps, the target-major e-prop kernel's launch;
+  // batches the narrow kernel serves (B % 4 != 0) take a whole update
+  // interval of up to 32 steps, one block per interval
+  if (prm->trace_block)
+    n->K = (int)prm->trace_block;
+  else if (B % 4 != 0 && prm->update_interval >= 1 && prm->update_interval <= 32)
+    n->K = (int)prm->update_interval;
+  else
+    n->K = 20;
   {
     const uint32_t U = prm->update_interval, Kb = (uint32_t)n->K;
     n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>((U + Kb - 1) / Kb + 1, 2), RING_MAX) : 2;
@@ -503,7 +511,8 @@ void flush_block(rs_eprop* n) {
     launch_eprop(e, a);
     n->timer.end(e);
   }
-  // the next forward launch into this half waits for everything above
+  // the next forward launch into this segment waits for everything above,
+  // unless a join at an update or at the end of the call covers it first
   (void)hipEventRecord(n->ev_ep[h], e);
   n->ep_pending[h] = true;
   n->blk_seg = (n->blk_seg + 1) % n->Q;
