@@ -92,7 +92,12 @@ typedef struct rs_eprop_params {
  * (bias 0) and, for projections in deepr_mask, the DEEP R connectivity and
  * sign bitfields (Sec. 2.1.2: signs of all potential synapses random, then
  * matched to the initial weights of existing ones).  Synchronises the stream.
- * `hip_stream` is a hipStream_t or NULL.  Errors: RS_EINVAL (bad parameters),
+ * `hip_stream` is a hipStream_t or NULL.  Networks with more than 2^21 expected
+ * synapse-instances (p * n_pre * n_post summed over projections, times batch)
+ * also own two internal streams, so that a block's forward pass overlaps the
+ * previous block's eligibility work; every call still orders its work after
+ * earlier work on `hip_stream` and the stream after its own.  Smaller networks
+ * run every kernel on `hip_stream`.  Errors: RS_EINVAL (bad parameters),
  * RS_ENOMEM, RS_EDEVICE.  *out is NULL on failure. */
 rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_eprop** out);
 

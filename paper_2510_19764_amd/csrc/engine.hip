@@ -150,6 +150,7 @@ struct rs_eprop {
   bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
   hipStream_t side2 = nullptr;                        // input-projection rewire, beside the recurrent one
+  bool single = false;                                // small network: everything on the caller's stream
   hipEvent_t ev_fwd = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
   hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
   bool ep_pending[RING_MAX] = {};  // an e-prop launch reading the segment may still run
@@ -315,8 +316,19 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
     for (int q = 1; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], (size_t)B * dims[q]));
     TRY(ar.alloc(&n->u_stg, QS * KB * K));
   }
-  HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
-  HIP_OK(hipStreamCreateWithFlags(&n->side2, hipStreamNonBlocking));
+  // A small network's kernels are short and latency-bound: overlapping its
+  // forward pass with its eligibility work gains less than the 10-30 us each
+  // cross-stream wait costs, so all of its work stays on the caller's stream.
+  {
+    const double syn = (double)prm->p_in * NI * NR + (double)prm->p_rec * NR * (NR - 1);
+    n->single = syn * B <= (double)(1u << 21);
+  }
+  if (n->single) {
+    n->side = n->side2 = n->stream;
+  } else {
+    HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
+    HIP_OK(hipStreamCreateWithFlags(&n->side2, hipStreamNonBlocking));
+  }
   HIP_OK(hipEventCreateWithFlags(&n->ev_upd, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_rw, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
@@ -428,6 +440,13 @@ void do_rewire(rs_eprop* n, int proj, hipStream_t s) {
   n->timer.end(s);
 }
 
+// Order stream `to` after the work enqueued so far on stream `from`.
+void order(hipEvent_t ev, hipStream_t from, hipStream_t to) {
+  if (from == to) return;
+  (void)hipEventRecord(ev, from);
+  (void)hipStreamWaitEvent(to, ev, 0);
+}
+
 // Run the open block (steps accumulated since the last flush): one forward
 // launch for all its steps on the caller's stream, writing ring segment
 // blk_seg, then the e-prop launch on the side stream.  The forward pass of
@@ -491,8 +510,7 @@ void flush_block(rs_eprop* n) {
   launch_readout(s, ro, n->blk_learn);
   n->timer.end(s);
   n->last_slot = h * n->K + n->blk_n - 1;
-  (void)hipEventRecord(n->ev_fwd, s);
-  (void)hipStreamWaitEvent(e, n->ev_fwd, 0);
+  order(n->ev_fwd, s, e);
   if (n->blk_learn) {
     EpropArgs a{};
     a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B;
@@ -513,8 +531,10 @@ void flush_block(rs_eprop* n) {
   }
   // the next forward launch into this segment waits for everything above,
   // unless a join at an update or at the end of the call covers it first
-  (void)hipEventRecord(n->ev_ep[h], e);
-  n->ep_pending[h] = true;
+  if (e != s) {
+    (void)hipEventRecord(n->ev_ep[h], e);
+    n->ep_pending[h] = true;
+  }
   n->blk_seg = (n->blk_seg + 1) % n->Q;
   n->blk_n = 0;
 }
@@ -543,12 +563,10 @@ void do_step(rs_eprop* n, uint32_t flags) {
       if (n->p.deepr_mask == 3) {
         // the two projections' rewires share nothing but the summed counts:
         // the input projection's runs on a third stream beside the other
-        (void)hipEventRecord(n->ev_upd, e);
-        (void)hipStreamWaitEvent(n->side2, n->ev_upd, 0);
+        order(n->ev_upd, e, n->side2);
         do_rewire(n, 0, n->side2);
         do_rewire(n, 1, e);
-        (void)hipEventRecord(n->ev_rw, n->side2);
-        (void)hipStreamWaitEvent(e, n->ev_rw, 0);
+        order(n->ev_rw, n->side2, e);
       } else {
         if (n->p.deepr_mask & 1) do_rewire(n, 0, e);
         if (n->p.deepr_mask & 2) do_rewire(n, 1, e);
@@ -559,8 +577,7 @@ void do_step(rs_eprop* n, uint32_t flags) {
       reset_state(n, e);
       n->timer.end(e);
     }
-    (void)hipEventRecord(n->ev_back, e);
-    (void)hipStreamWaitEvent(s, n->ev_back, 0);
+    order(n->ev_back, e, s);
     for (bool& p : n->ep_pending) p = false;  // covered by that wait
     // only the e-prop launches, later on this stream, read the column view:
     // the next forward block runs while it is rebuilt
@@ -670,8 +687,7 @@ rs_status rs_eprop_set_input_poisson(rs_eprop* n, const double* rate_hz, size_t 
   }
   // blocks already queued read the table: the copy follows them on the stream
   flush_block(n);
-  HIP_OK(hipEventRecord(n->ev_join, n->side));
-  HIP_OK(hipStreamWaitEvent(n->stream, n->ev_join, 0));
+  order(n->ev_join, n->side, n->stream);
   HIP_OK(hipMemcpyAsync(n->x_thr, thr.data(), n_rates * 8, hipMemcpyHostToDevice, n->stream));
   HIP_OK(hipStreamSynchronize(n->stream));
   n->x_thr_stride = n_rates == NI ? 0 : (int)NI;
@@ -687,12 +703,10 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   if (!n) return fail(RS_EINVAL, "net is NULL");
   if (!n->x_off && !n->poisson) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input*)");
   if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
-  HIP_OK(hipEventRecord(n->ev_join, n->stream));  // side stream follows earlier caller work
-  HIP_OK(hipStreamWaitEvent(n->side, n->ev_join, 0));
+  order(n->ev_join, n->stream, n->side);  // side stream follows earlier caller work
   for (uint32_t q = 0; q < n_steps; ++q) do_step(n, flags);
   flush_block(n);
-  HIP_OK(hipEventRecord(n->ev_back, n->side));     // caller's stream covers all of it
-  HIP_OK(hipStreamWaitEvent(n->stream, n->ev_back, 0));
+  order(n->ev_back, n->side, n->stream);  // caller's stream covers all of it
   for (bool& p : n->ep_pending) p = false;
   HIP_OK(hipGetLastError());
   return RS_OK;
@@ -829,15 +843,19 @@ rs_status rs_eprop_phase_times(rs_eprop* n, double* ms, uint64_t* count) {
 void rs_eprop_destroy(rs_eprop* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->stream);
-  if (n->side) (void)hipStreamSynchronize(n->side);
-  if (n->side2) (void)hipStreamSynchronize(n->side2);
+  if (!n->single) {
+    if (n->side) (void)hipStreamSynchronize(n->side);
+    if (n->side2) (void)hipStreamSynchronize(n->side2);
+  }
   n->timer.destroy();
   for (hipEvent_t ev : {n->ev_fwd, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : n->ev_ep)
     if (ev) (void)hipEventDestroy(ev);
-  if (n->side) (void)hipStreamDestroy(n->side);
-  if (n->side2) (void)hipStreamDestroy(n->side2);
+  if (!n->single) {
+    if (n->side) (void)hipStreamDestroy(n->side);
+    if (n->side2) (void)hipStreamDestroy(n->side2);
+  }
   n->arena.release();
   delete n;
 }
