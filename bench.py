@@ -26,6 +26,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # fp32 vector FMA rate without packed instructions (the library is built with
 # them disabled): 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz
 FP32_PEAK_TFLOPS = 78.6
+# the chip's fp32 vector figure counts packed FMAs (two per lane and cycle)
+FP32_PACKED_PEAK_TFLOPS = 157.3
 
 
 def classifier_config(seed=1, trace_block=20):
@@ -349,6 +351,8 @@ def main():
                                                                              * n_syn),
         "roofline": {"bound": "alu", "kernel": "k_eprop_wl<true, 4>", "achieved": round(achieved_tf, 2),
                      "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4),
+                     "peak_note": "fp32 FMA without packed instructions, which the build disables",
+                     "frac_of_packed_fp32_peak": round(achieved_tf / FP32_PACKED_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic("k_eprop_wl<true, 4>"),
                      "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
                      "trace_block": inf_k,
