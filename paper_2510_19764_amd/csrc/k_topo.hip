@@ -44,18 +44,18 @@ __device__ __forceinline__ int torus_d2_t(int L, int i, int j) {
   return dx * dx + dy * dy;
 }
 
-__global__ void __launch_bounds__(WAVE) k_topo_rewire(uint64_t seed, TopoDev t, uint64_t step) {
-  extern __shared__ __align__(16) unsigned char smem[];
+// Rewire row r, which received kr attempts, as one wave.  smem holds the
+// row's bitfield section, kr candidates and the compaction plan.
+__device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, int r, int kr,
+                                unsigned char* smem) {
   const ProjDev& P = t.P;
   uint32_t* bits = (uint32_t*)smem;          // [words]
   int* cand = (int*)(bits + P.words);        // [n_attempts]
   int* holes = cand + t.n_attempts;          // [cap]
   int* tail = holes + P.cap;                 // [cap]
   uint8_t* remf = (uint8_t*)(tail + P.cap);  // [cap]
-  const int q = blockIdx.x, lane = lane_id();
-  if (q >= *t.nrows) return;
-  const int r = t.rowlist[q];
-  int kr = min(t.kcount[r], P.n_post);
+  const int lane = lane_id();
+  kr = min(kr, P.n_post);
   __shared__ int s_kr;
   if (lane == 0) s_kr = kr;
   uint32_t* gbits = t.bits + (int64_t)r * P.words;
@@ -141,15 +141,54 @@ __global__ void __launch_bounds__(WAVE) k_topo_rewire(uint64_t seed, TopoDev t, 
   for (int w = lane; w < P.words; w += WAVE) gbits[w] = bits[w];
 }
 
+// Two launches: the row list from k_topo_distribute, one wave per listed row.
+__global__ void __launch_bounds__(WAVE) k_topo_rewire(uint64_t seed, TopoDev t, uint64_t step) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int q = blockIdx.x;
+  if (q >= *t.nrows) return;
+  const int r = t.rowlist[q];
+  topo_rewire_row(seed, t, step, r, t.kcount[r], smem);
+}
+
+// One launch (up to TOPO_FUSED_MAX attempts): wave a draws the row of every
+// attempt itself and rewires row rows[a] if a is the first attempt on it,
+// with the row's attempt count as k.  Same rows, counts and draws as the
+// two-launch form.
+constexpr int TOPO_FUSED_MAX = 2048;
+__global__ void __launch_bounds__(WAVE) k_topo_rewire_fused(uint64_t seed, TopoDev t, uint64_t step) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* rows = (int*)smem;  // [n_attempts]
+  const int a = blockIdx.x, lane = lane_id(), na = t.n_attempts;
+  for (int i = lane; i < na; i += WAVE)
+    rows[i] = (int)below(draw_u32(seed, TAG_TP_ROW, t.P.proj_id, step, (uint64_t)i, 0, 0), (uint32_t)t.P.n_pre);
+  __syncthreads();
+  const int r = rows[a];
+  bool earlier = false;
+  int cnt = 0;
+  for (int i = lane; i < na; i += WAVE)
+    if (rows[i] == r) {
+      ++cnt;
+      earlier |= i < a;
+    }
+  if (ballot(earlier)) return;  // another wave owns the row
+  const int kr = wave_sum_i(cnt);
+  topo_rewire_row(seed, t, step, r, kr, smem + (((size_t)na * 4 + 15) & ~(size_t)15));
+}
+
 void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step) {
   static bool attr_set = false;
   if (!attr_set) {
     allow_dynamic_lds((const void*)k_topo_distribute, 128 * 1024);
     attr_set = true;
   }
+  const size_t sm = (size_t)t.P.words * 4 + (size_t)t.n_attempts * 4 + (size_t)t.P.cap * 9 + 16;
+  if (t.n_attempts > 0 && t.n_attempts <= TOPO_FUSED_MAX) {
+    const size_t rows = ((size_t)t.n_attempts * 4 + 15) & ~(size_t)15;
+    hipLaunchKernelGGL(k_topo_rewire_fused, dim3(t.n_attempts), dim3(WAVE), rows + sm, s, seed, t, step);
+    return;
+  }
   hipLaunchKernelGGL(k_topo_distribute, dim3(1), dim3(TD_NT), (size_t)t.P.n_pre * 4, s, seed, t, step);
   if (t.n_attempts == 0) return;
-  const size_t sm = (size_t)t.P.words * 4 + (size_t)t.n_attempts * 4 + (size_t)t.P.cap * 9 + 16;
   hipLaunchKernelGGL(k_topo_rewire, dim3(t.n_attempts), dim3(WAVE), sm, s, seed, t, step);
 }
 

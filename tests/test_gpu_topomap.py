@@ -41,6 +41,10 @@ CASES = {
                                    g_init=0.2, seed=9),
     "full-rows-L8": rb.TopoConfig(L=8, cap=4, n_attempts=300, proj_id=2, p_form=1.0, sigma_form=50.0,
                                   g_theta=0.1, p_elim_dep=0.0, p_elim_pot=0.0, g_new=0.2, g_init=0.2, seed=5),
+    # more attempts than the one-launch form takes: the separate distribution launch
+    "many-attempts-L32": rb.TopoConfig(L=32, cap=16, n_attempts=3000, proj_id=4, p_form=0.5, sigma_form=2.0,
+                                       g_theta=0.1, p_elim_dep=0.3, p_elim_pot=0.05, g_new=0.2, g_init=0.2,
+                                       seed=11),
 }
 
 
