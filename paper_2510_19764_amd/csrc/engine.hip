@@ -151,6 +151,7 @@ struct rs_eprop {
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
   hipStream_t side2 = nullptr;                        // input-projection rewire, beside the recurrent one
   bool single = false;                                // small network: everything on the caller's stream
+  bool auto_upd = false;                              // inside a step call with RS_AUTO_UPDATE
   hipEvent_t ev_fwd = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
   hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
   bool ep_pending[RING_MAX] = {};  // an e-prop launch reading the segment may still run
@@ -531,7 +532,16 @@ void flush_block(rs_eprop* n) {
   }
   // the next forward launch into this segment waits for everything above,
   // unless a join at an update or at the end of the call covers it first
-  if (e != s) {
+  // The forward launch that next writes this segment comes Q blocks later.
+  // Inside a call with automatic updates, the join at the next update comes
+  // first when fewer than Q blocks remain to it; that join then orders the
+  // forward stream after this launch and no event is needed.
+  bool covered = false;
+  if (n->auto_upd) {
+    const uint64_t U = n->p.update_interval, rem = (U - n->step % U) % U;
+    covered = (rem + (uint64_t)n->K - 1) / (uint64_t)n->K < (uint64_t)n->Q;
+  }
+  if (e != s && !covered) {
     (void)hipEventRecord(n->ev_ep[h], e);
     n->ep_pending[h] = true;
   }
@@ -704,8 +714,10 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
   if (!n->x_off && !n->poisson) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input*)");
   if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
   order(n->ev_join, n->stream, n->side);  // side stream follows earlier caller work
+  n->auto_upd = (flags & RS_AUTO_UPDATE) && n->p.update_interval > 0;
   for (uint32_t q = 0; q < n_steps; ++q) do_step(n, flags);
   flush_block(n);
+  n->auto_upd = false;
   order(n->ev_back, n->side, n->stream);  // caller's stream covers all of it
   for (bool& p : n->ep_pending) p = false;
   HIP_OK(hipGetLastError());
