@@ -182,6 +182,9 @@ rs_status rs_eprop_reset(rs_eprop* net);
 #define RS_VB 0x11
 #define RS_ZCOUNT 0x12 /* uint32[batch][n_rec]  spikes per neuron since creation or the
                           last rs_eprop_set of this variable */
+#define RS_ZBITS 0x13  /* uint32[n_rec][batch]  spike raster of the last block of steps run
+                          (rs_eprop_info.last_block steps, the end of the last step call):
+                          bit t = the block's t-th step; read-only */
 /* Projection variables: RS_PROJ(p, field), p = 0 input, 1 recurrent;
  * cap = row capacity (rs_eprop_info), words = ceil(n_post/32). */
 #define RS_PROJ(p, f) (0x100 * ((p) + 1) + (f))
@@ -210,7 +213,7 @@ typedef struct rs_eprop_info {
   uint32_t words_in, words_rec;   /* bitfield words per row */
   uint64_t step;                  /* timesteps done */
   uint32_t adam_step;             /* Adam updates done */
-  uint32_t _pad;
+  uint32_t last_block;            /* steps in the block RS_ZBITS covers */
   uint64_t synaptic_events;       /* spikes x row lengths propagated so far */
   uint64_t spikes;                /* recurrent spikes emitted so far */
   uint64_t device_bytes;          /* device memory held */

@@ -22,6 +22,7 @@ PHASES = ("forward", "eprop", "update", "rewire", "reset")
 V, A, Y, XBAR, ZBAR, PSI, LSIG, DELTA, Z = range(1, 10)
 WOUT, BOUT, GOUT, GB, MOUT, VOUT, MB, VB = range(0x0A, 0x12)
 ZCOUNT = 0x12
+ZBITS = 0x13
 P_LEN, P_IND, P_W, P_M, P_V, P_G, P_EPS, P_EBAR, P_CONN, P_SIGN, P_DORMANT = range(1, 12)
 
 
@@ -57,7 +58,7 @@ class _Stats(C.Structure):
 class _Info(C.Structure):
     _fields_ = [("cap_in", C.c_uint32), ("cap_rec", C.c_uint32), ("words_in", C.c_uint32),
                 ("words_rec", C.c_uint32), ("step", C.c_uint64), ("adam_step", C.c_uint32),
-                ("_pad", C.c_uint32), ("synaptic_events", C.c_uint64), ("spikes", C.c_uint64),
+                ("last_block", C.c_uint32), ("synaptic_events", C.c_uint64), ("spikes", C.c_uint64),
                 ("device_bytes", C.c_uint64), ("eliminated", C.c_uint64), ("formed", C.c_uint64)]
 
 
@@ -248,7 +249,8 @@ class EpropNet:
                LSIG: ((NR, B), np.float32), DELTA: ((K, B), np.float32), Z: ((B, NR), np.uint8),
                WOUT: ((K, NR), np.float32), BOUT: ((K,), np.float32), GOUT: ((K, NR), np.float32),
                GB: ((K,), np.float32), MOUT: ((K, NR), np.float32), VOUT: ((K, NR), np.float32),
-               MB: ((K,), np.float32), VB: ((K,), np.float32), ZCOUNT: ((B, NR), np.uint32)}
+               MB: ((K,), np.float32), VB: ((K,), np.float32), ZCOUNT: ((B, NR), np.uint32),
+               ZBITS: ((NR, B), np.uint32)}
         if var in net:
             return net[var]
         p, f = var // 0x100 - 1, var % 0x100

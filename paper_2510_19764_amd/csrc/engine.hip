@@ -146,6 +146,7 @@ struct rs_eprop {
   float *u_stg = nullptr;                             // readout drive [Q segments][K][B][n_out]
   int K = 8, Q = 2, nslot = 16;
   int blk_seg = 0, blk_n = 0, last_slot = 0;
+  int last_seg = 0, last_blk_n = 0;                   // the most recently run block
   uint64_t blk_t0 = 0;
   bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
@@ -545,6 +546,8 @@ void flush_block(rs_eprop* n) {
     (void)hipEventRecord(n->ev_ep[h], e);
     n->ep_pending[h] = true;
   }
+  n->last_seg = h;
+  n->last_blk_n = n->blk_n;
   n->blk_seg = (n->blk_seg + 1) % n->Q;
   n->blk_n = 0;
 }
@@ -625,6 +628,7 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_MB: *r = {n->Mb, K * 4}; return true;
       case RS_VB: *r = {n->Vb, K * 4}; return true;
       case RS_ZCOUNT: *r = {n->zcount, B * NR * 4}; return true;
+      case RS_ZBITS: *r = {n->zbitsT + (size_t)n->last_seg * NR * B, NR * B * 4}; return !for_write;
       default: return false;
     }
   }
@@ -825,6 +829,7 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   o->words_rec = (uint32_t)n->rec.words;
   o->step = n->step;
   o->adam_step = n->adam_k;
+  o->last_block = (uint32_t)n->last_blk_n;
   o->synaptic_events = c[0];
   o->spikes = c[1];
   o->device_bytes = n->arena.bytes;

@@ -262,6 +262,26 @@ def test_overlapped_training_matches_joined_calls():
     assert infos[0].adam_step == infos[1].adam_step == 2
 
 
+@pytest.mark.parametrize("name", ["alif-b64-col", "alif-b3-narrow"])
+def test_spike_raster_of_last_block(name):
+    """The last block's spike bits equal the spikes of the same steps taken one
+    at a time."""
+    cfg, net, raster, labels = setup_case(name)
+    zs = []
+    for _ in range(20):
+        net.step(1, rb.RS_LEARN)
+        zs.append(net.get(rb.Z).T)  # [n_rec][B]
+    assert net.info().last_block == 1
+    _, other, _, _ = setup_case(name)
+    other.step(20, rb.RS_LEARN)
+    assert other.info().last_block == 20
+    bits = other.get(rb.ZBITS)
+    for t in range(20):
+        assert np.array_equal((bits >> t) & 1, zs[t].astype(np.uint32)), t
+    assert not (bits >> 20).any()
+    assert int(sum(z.sum() for z in zs)) > 0
+
+
 def test_error_paths():
     cfg, _ = CASES["tiny-lif-b1"]
     net = rb.EpropNet(cfg)
