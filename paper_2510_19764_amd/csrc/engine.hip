@@ -482,6 +482,9 @@ void flush_block(rs_eprop* n) {
   }
   f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
   f.counters = n->counters;
+  // small networks keep their rows on chip for the block; a large one's
+  // forward workgroups leave LDS to the e-prop launch beside them
+  f.rows_lds = n->single ? 1 : 0;
   f.zcount = n->zcount;
   n->timer.begin(s, 0);
   launch_fwd(s, f);

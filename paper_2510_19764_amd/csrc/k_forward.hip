@@ -55,11 +55,14 @@ __device__ __forceinline__ int block_scan_flag_fwd(bool f, int* s_wave, int* tot
 //   xpos     int[33]             start of each step's input list in xbuf
 //   xbuf     int[xcap]           the launch's input spike lists
 //   wout     float[n_out*n_rec]  readout weights (when wout_lds)
+//   rows     int[n_in*cap_in], float[n_in*cap_in], int[n_rec*cap_rec],
+//            float[n_rec*cap_rec]  both projections' rows (when rows_lds)
 struct FwdLds {
-  size_t acc, zlist, len_in, len_rec, xflags, xpos, xbuf, wout, total;
+  size_t acc, zlist, len_in, len_rec, xflags, xpos, xbuf, wout, ind_in, w_in, ind_rec, w_rec, total;
 };
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
-__host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out, int xcap, int wout_lds) {
+__host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out, int xcap, int wout_lds,
+                                                 int rows_lds = 0, int cap_in = 0, int cap_rec = 0) {
   FwdLds L;
   size_t o = 0;
   L.acc = o; o = align16(o + (size_t)n_rec * 8);
@@ -70,6 +73,11 @@ __host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out,
   L.xpos = o; o = align16(o + 33 * 4);
   L.xbuf = o; o = align16(o + (size_t)xcap * 4);
   L.wout = o; o = align16(o + (wout_lds ? (size_t)n_out * n_rec * 4 : 0));
+  const size_t si = rows_lds ? (size_t)n_in * cap_in * 4 : 0, sr = rows_lds ? (size_t)n_rec * cap_rec * 4 : 0;
+  L.ind_in = o; o = align16(o + si);
+  L.w_in = o; o = align16(o + si);
+  L.ind_rec = o; o = align16(o + sr);
+  L.w_rec = o; o = align16(o + sr);
   L.total = o;
   return L;
 }
@@ -77,10 +85,12 @@ __host__ __device__ inline FwdLds fwd_lds_layout(int n_in, int n_rec, int n_out,
 constexpr int PROP_U = 4;  // slots per lane loaded ahead of the LDS atomics
 constexpr size_t WOUT_LDS_MAX = 16 * 1024;  // largest readout matrix staged in LDS
 
-template <int ITEMS>
+// ROWS: both projections' rows are staged in LDS for the launch (small
+// networks), so propagation reads no global memory.
+template <int ITEMS, bool ROWS>
 __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const FwdLds lay = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds);
+  const FwdLds lay = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, ROWS, a.cap_in, a.cap_rec);
   long long* acc = (long long*)(smem + lay.acc);
   int* zlist = (int*)(smem + lay.zlist);
   int* len_in = (int*)(smem + lay.len_in);
@@ -107,6 +117,29 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     float* w = (float*)(smem + lay.wout);
     const int nw = a.n_out * a.n_rec;
     for (int q = tid; q < nw; q += FWD_NT) w[q] = a.Wout[q];
+  }
+  const int* ind_in = a.ind_in;
+  const float* w_in = a.w_in;
+  const int* ind_rec = a.ind_rec;
+  const float* w_rec = a.w_rec;
+  if constexpr (ROWS) {
+    int* si = (int*)(smem + lay.ind_in);
+    float* sw = (float*)(smem + lay.w_in);
+    int* sir = (int*)(smem + lay.ind_rec);
+    float* swr = (float*)(smem + lay.w_rec);
+    const int ni = a.n_in * a.cap_in, nr = a.n_rec * a.cap_rec;
+    for (int q = tid; q < ni; q += FWD_NT) {
+      si[q] = a.ind_in[q];
+      sw[q] = a.w_in[q];
+    }
+    for (int q = tid; q < nr; q += FWD_NT) {
+      sir[q] = a.ind_rec[q];
+      swr[q] = a.w_rec[q];
+    }
+    ind_in = si;
+    w_in = sw;
+    ind_rec = sir;
+    w_rec = swr;
   }
   const int* xsrc_base;  // the step lists: the caller's raster, or drawn below
   if (a.x_thr) {
@@ -237,8 +270,8 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       const bool from_in = r < nx;
       const int i = from_in ? xs[r] : zlist[r - nx];
       if (from_in && (unsigned)i >= (unsigned)a.n_in) continue;  // out-of-range channel: ignored
-      const int* ind = from_in ? a.ind_in : a.ind_rec;
-      const float* w = from_in ? a.w_in : a.w_rec;
+      const int* ind = from_in ? ind_in : ind_rec;
+      const float* w = from_in ? w_in : w_rec;
       const int cap = from_in ? a.cap_in : a.cap_rec;
       const int n = from_in ? len_in[i] : len_rec[i];
       const int64_t base = (int64_t)i * cap;
@@ -349,20 +382,26 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
   if (fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total > (size_t)lds_cap) a.wout_lds = 0;
   while (fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total > (size_t)lds_cap && a.xcap > 0)
     a.xcap /= 2;
-  const size_t sm = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total;
+  const int need = (max(a.n_rec, a.n_in) + FWD_NT - 1) / FWD_NT;
+  // rows in LDS when asked for, one neuron per thread and everything fits
+  const bool rows = a.rows_lds && need <= 1 &&
+                    fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, 1, a.cap_in, a.cap_rec).total <=
+                        (size_t)lds_cap;
+  const size_t sm = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, rows, a.cap_in, a.cap_rec).total;
   static bool attr_set = false;
   if (!attr_set) {
-    allow_dynamic_lds((const void*)k_fwd<1>, 150 * 1024);
-    allow_dynamic_lds((const void*)k_fwd<2>, 150 * 1024);
-    allow_dynamic_lds((const void*)k_fwd<4>, 150 * 1024);
-    allow_dynamic_lds((const void*)k_fwd<8>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd<1, true>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd<1, false>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd<2, false>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd<4, false>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd<8, false>, 150 * 1024);
     attr_set = true;
   }
-  const int need = (max(a.n_rec, a.n_in) + FWD_NT - 1) / FWD_NT;
-  if (need <= 1) hipLaunchKernelGGL(k_fwd<1>, dim3(a.B), dim3(FWD_NT), sm, s, a);
-  else if (need <= 2) hipLaunchKernelGGL(k_fwd<2>, dim3(a.B), dim3(FWD_NT), sm, s, a);
-  else if (need <= 4) hipLaunchKernelGGL(k_fwd<4>, dim3(a.B), dim3(FWD_NT), sm, s, a);
-  else hipLaunchKernelGGL(k_fwd<8>, dim3(a.B), dim3(FWD_NT), sm, s, a);
+  if (rows) hipLaunchKernelGGL((k_fwd<1, true>), dim3(a.B), dim3(FWD_NT), sm, s, a);
+  else if (need <= 1) hipLaunchKernelGGL((k_fwd<1, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
+  else if (need <= 2) hipLaunchKernelGGL((k_fwd<2, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
+  else if (need <= 4) hipLaunchKernelGGL((k_fwd<4, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
+  else hipLaunchKernelGGL((k_fwd<8, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
 }
 
 // Leaky readout and softmax error over a block (recurrent classifier

@@ -67,6 +67,7 @@ struct FwdArgs {
   const uint64_t* x_thr; int x_thr_stride; int* x_list;
   uint64_t seed, step0;
   int wout_lds;                              // 1: stage W_out in LDS for the block
+  int rows_lds;                              // 1: stage both projections' rows in LDS if they fit
   int xcap;                                  // LDS capacity for the block's input spike lists
   unsigned long long* counters;              // [0] synaptic events, [1] spikes
   uint32_t* zcount;                          // [B][n_rec] spikes per neuron, accumulated
