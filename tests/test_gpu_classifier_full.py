@@ -92,3 +92,38 @@ def test_full_training_interval_invariants(setup):
             assert len(np.unique(row)) == row.size
     y = net.get(rb.Y)
     assert np.isfinite(y).all()
+
+
+def test_full_batch_training_deterministic():
+    """One whole training batch (1000 steps, 10 updates, 20 DEEP R rewires and
+    the reset) at the full size, in the benchmark's schedule, twice from the
+    same seed: bit-identical state, constant synapse counts, finite values."""
+    cfg = classifier_cfg()
+    labels, raster = wl.ShdLike().batch(seed=1, batch_index=0, B=cfg.batch)
+    flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+    snaps = []
+    for rep in range(2):
+        net = rb.EpropNet(cfg)
+        net.set_input(*gpu_input(raster, labels))
+        lens0 = [int(net.get(rb.PROJ(p, rb.P_LEN)).sum()) for p in (0, 1)]
+        net.step(cfg.sample_steps, flags)
+        inf = net.info()
+        assert inf.adam_step == cfg.sample_steps // cfg.update_interval
+        assert inf.eliminated == inf.formed
+        s = snapshot(net)
+        for p, tag in ((0, "in"), (1, "rec")):
+            assert int(s[tag]["len"].sum()) == lens0[p]
+            m = real_slots(s[tag])
+            for k in ("w", "m", "vv", "G"):
+                assert np.isfinite(s[tag][k][m]).all(), (tag, k)
+        for k in ("Wout", "bout", "Mout", "Vout"):
+            assert np.isfinite(s[k]).all(), k
+        snaps.append(s)
+        net.close()
+    a, b = snaps
+    for k in a:
+        if isinstance(a[k], dict):
+            for f in a[k]:
+                assert np.array_equal(a[k][f], b[k][f]), (k, f)
+        else:
+            assert np.array_equal(a[k], b[k]), k
