@@ -39,7 +39,8 @@ def classifier_config(seed=1, trace_block=20):
                           p_in=c["p_in"], p_rec=c["p_rec"], sigma_in=f32(wl.sigma_init(c["p_in"], c["n_in"])),
                           sigma_rec=f32(wl.sigma_init(c["p_rec"], c["n_rec"])),
                           sigma_out=f32(1.0 / np.sqrt(c["n_rec"])), deepr_mask=c["deepr_mask"], l1=c["l1"],
-                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed)
+                          lr=c["lr"], update_interval=c["update_interval"], sample_steps=c["T"], seed=seed,
+                          trace_block=trace_block)
 
 
 def eprop_algorithmic_bytes(cfg, n_syn: int, n_launch: int, n_steps: int) -> int:
@@ -198,6 +199,34 @@ def tiny_net_leg(samples=20, oracle_samples=2):
             "gpu_over_oracle": round(orc_s / (el / steps), 2)}
 
 
+def forward_only_leg(steps=1000):
+    """The classifier's forward pass alone (no eligibility work): wall time and
+    the forward launches' device time over `steps` steps, after as many
+    warm-up steps."""
+    import torch
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    cfg = classifier_config()
+    labels, raster = wl.ShdLike(T=cfg.sample_steps).batch(seed=1, batch_index=0, B=cfg.batch)
+    dev = (torch.tensor(raster.off, dtype=torch.int32, device="cuda"),
+           torch.tensor(raster.idx, dtype=torch.int32, device="cuda"),
+           torch.tensor(labels, dtype=torch.int32, device="cuda"))
+    net = rb.EpropNet(cfg)
+    net.set_input(*dev)
+    net.step(steps, 0)
+    torch.cuda.synchronize()
+    net.timing(0b00001)  # the forward launches
+    net.phase_times()
+    t0 = time.perf_counter()
+    net.step(steps, 0)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, n = net.phase_times()["forward"]
+    net.close()
+    return {"steps": steps, "trace_block": cfg.trace_block, "wall_ms": round(1e3 * el, 3),
+            "forward_ms": round(ms, 3), "forward_launches": n}
+
+
 def topo_rewire_latency(n_rewires=200):
     """Topographic-map rewiring (64 x 64 sheets, cap 32, 160 attempts)."""
     from paper_2510_19764_amd import binding as rb
@@ -238,6 +267,8 @@ def main():
     ap.add_argument("--no-tiny", action="store_true")
     ap.add_argument("--only-tiny", action="store_true",
                     help="run only the tiny-network leg and print its figures (for profiling)")
+    ap.add_argument("--forward-only", action="store_true",
+                    help="time only the classifier's forward pass, without learning (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="only run a plain copy of this many MiB 20 times (byte-counter calibration)")
     args = ap.parse_args()
@@ -263,6 +294,9 @@ def main():
 
     if args.only_tiny:
         print(json.dumps({"tiny_net": tiny_net_leg()}), flush=True)
+        return
+    if args.forward_only:
+        print(json.dumps({"forward_only": forward_only_leg()}), flush=True)
         return
 
     cfg = classifier_config()
