@@ -97,8 +97,10 @@ typedef struct rs_eprop_params {
  * also own two internal streams, so that a block's forward pass overlaps the
  * previous block's eligibility work; every call still orders its work after
  * earlier work on `hip_stream` and the stream after its own.  Smaller networks
- * run every kernel on `hip_stream`.  Errors: RS_EINVAL (bad parameters),
- * RS_ENOMEM, RS_EDEVICE.  *out is NULL on failure. */
+ * run every kernel on `hip_stream`.  Errors: RS_EINVAL (bad parameters, or a
+ * network whose per-instance neuron state does not fit one workgroup's LDS:
+ * about 16 * n_rec + 4.25 * n_in bytes must stay within 149 KB), RS_ENOMEM,
+ * RS_EDEVICE.  *out is NULL on failure. */
 rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_eprop** out);
 
 /* Attach the input of one sample batch: a compressed raster of

@@ -250,6 +250,8 @@ rs_status validate(const rs_eprop_params* p) {
 
 rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) {
   TRY(validate(prm));
+  if (!fwd_fits((int)prm->n_in, (int)prm->n_rec, (int)prm->n_out))
+    return fail(RS_EINVAL, "n_in %u and n_rec %u need more LDS than a forward workgroup has", prm->n_in, prm->n_rec);
   rs_eprop* n = new rs_eprop();
   *out = n;
   n->p = *prm;

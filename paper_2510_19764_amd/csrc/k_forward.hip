@@ -362,17 +362,28 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
 
 // Items per thread: neurons (and input channels) handled by each of the
 // workgroup's threads, kept in registers across the block of steps.
-void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
-  // LDS budget: stage W_out and up to 2048 input spikes when they fit
+// LDS a forward workgroup may take: the device's limit, at most 150 KB, less
+// 1 KB for the kernel's static arrays.
+static int fwd_lds_cap() {
   static int lds_cap = 0;
   if (!lds_cap) {
-    int dev = 0;
+    int dev = 0, cap = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&lds_cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      lds_cap = 64 * 1024;
+        hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      cap = 64 * 1024;
     (void)hipGetLastError();
-    lds_cap = (lds_cap < 150 * 1024 ? lds_cap : 150 * 1024) - 1024;
+    lds_cap = (cap < 150 * 1024 ? cap : 150 * 1024) - 1024;
   }
+  return lds_cap;
+}
+
+bool fwd_fits(int n_in, int n_rec, int n_out) {
+  return fwd_lds_layout(n_in, n_rec, n_out, 0, 0).total <= (size_t)fwd_lds_cap();
+}
+
+void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
+  // LDS budget: stage W_out and up to 2048 input spikes when they fit
+  const int lds_cap = fwd_lds_cap();
   FwdArgs a = a_in;
   a.xcap = 2048;
   // W_out is staged only while small: the forward workgroups stay resident on

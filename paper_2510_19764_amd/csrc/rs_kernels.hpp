@@ -74,6 +74,8 @@ struct FwdArgs {
 };
 // One launch runs `nsteps` consecutive steps into the staging buffers.
 void launch_fwd(hipStream_t s, const FwdArgs& a);
+// Whether one forward workgroup's LDS holds a network of this size.
+bool fwd_fits(int n_in, int n_rec, int n_out);
 
 // Readout over a block: y, softmax error delta into the ring, and (if asked)
 // the learning signal L = W_out^T delta into the ring.

@@ -310,6 +310,11 @@ def test_error_paths():
     buf = np.zeros(3, np.float32)
     code = rb.lib().rs_eprop_get(net._h, rb.V, buf.ctypes.data_as(ctypes.c_void_p), buf.nbytes)
     assert code == rb.RS_ECAPACITY
+    # a network whose per-instance neuron state exceeds one workgroup's LDS is
+    # refused at creation, before any allocation
+    with pytest.raises(rb.RagsnnError) as e:
+        rb.EpropNet(make_cfg(8192, 8192, 4, 1, False, p=0.001))
+    assert e.value.code == rb.RS_EINVAL
 
 
 @pytest.mark.parametrize("name", ["alif-b64-col", "lif-b256-col", "alif-b3-narrow", "alif-b320-col",
