@@ -16,8 +16,9 @@
  *     "device" pointers must stay valid for as long as the call's work may run
  *     on the object's stream, "host" pointers only for the duration of the call.
  *   - Streams: every object is bound to the HIP stream given at creation
- *     (NULL = the default stream).  Calls enqueue work on it and return without
- *     waiting, except where a call is documented as synchronising.
+ *     (NULL = the default stream).  Calls order their work after earlier work
+ *     on it, and later work on it after theirs, and return without waiting,
+ *     except where a call is documented as synchronising.
  *   - Threads: an object must not be used by two threads at once.
  *   - Randomness: every random decision is a Philox4x64-10 draw keyed by
  *     (seed, stream tag, projection) with a counter of (step, row, slot/target,
@@ -59,10 +60,10 @@ typedef struct rs_rewire_stats {
 typedef struct rs_eprop rs_eprop;
 
 typedef struct rs_eprop_params {
-  uint32_t n_in;        /* input channels */
+  uint32_t n_in;        /* input channels, 1..8192 */
   uint32_t n_rec;       /* recurrent neurons, 1..8192 */
   uint32_t n_out;       /* readout units, 1..256 */
-  uint32_t batch;       /* batch instances simulated together, >= 1 */
+  uint32_t batch;       /* batch instances simulated together, 1..65536 */
   int32_t alif;         /* 1: ALIF neurons, 0: LIF (beta = rho = 0) */
   float dt_ms, tau_mem_ms, tau_adapt_ms, v_thr, beta;
   float p_in, p_rec;    /* fixed connection probabilities */
