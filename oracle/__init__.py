@@ -14,6 +14,7 @@ Per-function citations live in the C sources:
   update.c   L1 term for DEEP R projections + Adam
   deepr.c    DEEP R elimination and formation
   topomap.c  topographic-map rewiring
+  topo_sim.c topographic-map simulation: conductance LIF, STDP, stimulus
   input.c    Poisson input spikes on the counter-based generator
 """
 from __future__ import annotations
@@ -26,7 +27,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c", "input.c"]
+_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c", "input.c", "topo_sim.c"]
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 TAG_CONN, TAG_WINIT, TAG_SIGN = 1, 2, 3
@@ -98,6 +99,22 @@ class _CTopoParams(C.Structure):
                 ("p_elim_dep", C.c_double), ("p_elim_pot", C.c_double), ("g_new", C.c_double)]
 
 
+class _CTopoModel(C.Structure):
+    _fields_ = [("L", C.c_int32), ("h", C.c_double),
+                ("C_m", C.c_double), ("tau_m", C.c_double), ("V_rest", C.c_double),
+                ("E_exc", C.c_double), ("V_th", C.c_double), ("V_reset", C.c_double),
+                ("tau_s", C.c_double), ("ref_steps", C.c_int32),
+                ("f_base", C.c_double), ("f_peak", C.c_double), ("sigma_stim", C.c_double),
+                ("stim_steps", C.c_int32), ("stim_kind", C.c_int32), ("stdp", C.c_int32),
+                ("g_max", C.c_double), ("A_plus", C.c_double), ("A_minus", C.c_double),
+                ("tau_plus", C.c_double), ("tau_minus", C.c_double), ("rewire_steps", C.c_int32)]
+
+
+class _CTopoState(C.Structure):
+    _fields_ = [("V", P_f64), ("g", P_f64), ("y", P_f64), ("ref", P_i32), ("count", P_i32),
+                ("zout", P_u8), ("x", P_f64), ("zin", P_u8)]
+
+
 _ROW_FN = C.CFUNCTYPE(C.c_uint32, C.c_void_p, C.c_int32)
 _TGT_FN = C.CFUNCTYPE(C.c_uint32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32)
 _RS_FN = C.CFUNCTYPE(C.c_uint32, C.c_void_p, C.c_int32, C.c_int32)
@@ -142,6 +159,16 @@ def _declare(L):
     L.orc_topo_rewire.argtypes = [C.c_uint64, C.POINTER(_CProj), C.POINTER(_CTopoParams),
                                   C.c_uint64, P_u32, P_i32]
     L.orc_torus_d2.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.orc_topo_stimulus.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.c_uint64, P_i32, P_i32, P_i32]
+    L.orc_topo_stim_d2.argtypes = [C.POINTER(_CTopoModel), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.orc_topo_stim_d2.restype = C.c_int32
+    L.orc_topo_rate.argtypes = [C.POINTER(_CTopoModel), C.c_int32]
+    L.orc_topo_rate.restype = C.c_double
+    L.orc_topo_sim_step.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
+                                    C.POINTER(_CTopoState), C.c_uint64]
+    L.orc_topo_run.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
+                               C.POINTER(_CTopoParams), C.POINTER(_CTopoState), C.c_uint64,
+                               C.c_uint64, P_u32, P_i32]
     L.orc_torus_d2.restype = C.c_int32
 
 
@@ -453,3 +480,88 @@ def topo_rewire_scripted(P: Proj, tp: TopoParams, attempt_row, target, elim_u32,
     ctp = tp.c()
     lib().orc_topo_rewire_with(C.byref(P.c()), C.byref(ctp), C.byref(d), _ptr(bits, P_u32), _ptr(stats, P_i32))
     return stats, bits
+
+
+# ---------------------------------------------------------------- topographic-map simulation
+STIM_BLOB, STIM_BAR = 0, 1
+
+
+@dataclass
+class TopoModel:
+    """Topographic-map model parameters (Tab. D, E, F, G, H), GeNN units: ms, mV, nF, uS, Hz."""
+    L: int
+    h: float = 0.1
+    C_m: float = 20.0
+    tau_m: float = 20.0
+    V_rest: float = -70.0
+    E_exc: float = 0.0
+    V_th: float = -54.0
+    V_reset: float = -70.0
+    tau_s: float = 5.0
+    ref_steps: int = 50
+    f_base: float = 5.0
+    f_peak: float = 152.8
+    sigma_stim: float = 2.0
+    stim_steps: int = 200
+    stim_kind: int = STIM_BLOB
+    stdp: int = 1
+    g_max: float = 0.2
+    A_plus: float = 0.02
+    A_minus: float = 0.2 * 0.1 * 1.2 * 20.0 / 64.0
+    tau_plus: float = 20.0
+    tau_minus: float = 64.0
+    rewire_steps: int = 10
+
+    def c(self):
+        return _CTopoModel(*[getattr(self, f) for f, _ in _CTopoModel._fields_])
+
+
+class TopoState:
+    """Both sheets' state; V starts at V_rest, everything else at zero."""
+
+    def __init__(self, M: TopoModel):
+        N = M.L * M.L
+        self.V = np.full(N, M.V_rest, np.float64)
+        self.g = np.zeros(N, np.float64)
+        self.y = np.zeros(N, np.float64)
+        self.ref = np.zeros(N, np.int32)
+        self.count = np.zeros(N, np.int32)
+        self.zout = np.zeros(N, np.uint8)
+        self.x = np.zeros(N, np.float64)
+        self.zin = np.zeros(N, np.uint8)
+
+    def c(self):
+        return _CTopoState(_ptr(self.V, P_f64), _ptr(self.g, P_f64), _ptr(self.y, P_f64),
+                           _ptr(self.ref, P_i32), _ptr(self.count, P_i32), _ptr(self.zout, P_u8),
+                           _ptr(self.x, P_f64), _ptr(self.zin, P_u8))
+
+
+def topo_stimulus(seed: int, M: TopoModel, step: int):
+    cx, cy, o = C.c_int32(), C.c_int32(), C.c_int32()
+    lib().orc_topo_stimulus(seed, C.byref(M.c()), step, C.byref(cx), C.byref(cy), C.byref(o))
+    return cx.value, cy.value, o.value
+
+
+def topo_stim_d2(M: TopoModel, i: int, cx: int, cy: int, orient: int) -> int:
+    return lib().orc_topo_stim_d2(C.byref(M.c()), i, cx, cy, orient)
+
+
+def topo_rate(M: TopoModel, d2: int) -> float:
+    return lib().orc_topo_rate(C.byref(M.c()), d2)
+
+
+def topo_sim_step(seed: int, M: TopoModel, P: Proj, S: TopoState, t: int):
+    cm, cs = M.c(), S.c()
+    lib().orc_topo_sim_step(seed, C.byref(cm), C.byref(P.c()), C.byref(cs), t)
+
+
+def topo_run(seed: int, M: TopoModel, P: Proj, tp: TopoParams, S: TopoState, t0: int, n: int,
+             bits: np.ndarray | None = None):
+    """Steps t0 .. t0+n-1 with a rewire after every rewire_steps; returns summed rewire stats."""
+    if bits is None:
+        bits = np.zeros(P.n_pre * P.words, np.uint32)
+    stats = np.zeros(4, np.int32)
+    cm, cs, ctp = M.c(), S.c(), tp.c()
+    lib().orc_topo_run(seed, C.byref(cm), C.byref(P.c()), C.byref(ctp), C.byref(cs), t0, n,
+                       _ptr(bits, P_u32), _ptr(stats, P_i32))
+    return stats

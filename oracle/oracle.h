@@ -41,7 +41,8 @@ enum {
     ORC_TAG_TP_TGT = 7,  /* topomap candidate target,     counter (step, r, q, try) */
     ORC_TAG_TP_ELIM = 8, /* topomap elimination draw,     counter (step, r, s, 0) */
     ORC_TAG_TP_FORM = 9, /* topomap formation draw,       counter (step, r, j, 0) */
-    ORC_TAG_INPUT = 10   /* Poisson input spike,          counter (step, b, i, 0) */
+    ORC_TAG_INPUT = 10,  /* Poisson input spike,          counter (step, b, i, 0) */
+    ORC_TAG_STIM = 11    /* topomap stimulus position,    counter (epoch, k, 0, 0) */
 };
 
 /* Draws per (row, activation) before the bounded fallback scan takes over. */
@@ -163,5 +164,42 @@ void orc_topo_rewire(uint64_t seed, orc_proj *P, const orc_topo_params *tp, uint
                      uint32_t *bits, int32_t *stats);
 /* Squared torus distance between node i of one sheet and node j of the other. */
 int32_t orc_torus_d2(int32_t L, int32_t i, int32_t j);
+
+/* Topographic-map simulation (paper, topographic-map model, Tab. A-F, H). */
+enum { ORC_STIM_BLOB = 0, ORC_STIM_BAR = 1 };
+typedef struct orc_topo_model {
+    int32_t L;
+    double h;                                  /* time step, ms */
+    double C_m, tau_m, V_rest, E_exc, V_th, V_reset, tau_s;   /* nF, ms, mV, ms */
+    int32_t ref_steps;                         /* tau_ref / h */
+    double f_base, f_peak, sigma_stim;         /* Hz, Hz, cells */
+    int32_t stim_steps, stim_kind;             /* t_stim / h; ORC_STIM_* */
+    int32_t stdp;                              /* 0: weights fixed */
+    double g_max, A_plus, A_minus, tau_plus, tau_minus;      /* uS, uS, uS, ms, ms */
+    int32_t rewire_steps;                      /* t_rewiring / h; 0: no rewiring */
+} orc_topo_model;
+/* State of both sheets, L*L entries each. */
+typedef struct orc_topo_state {
+    double *V, *g, *y;   /* target sheet: membrane (mV), conductance (uS), post trace */
+    int32_t *ref;        /* remaining refractory steps */
+    int32_t *count;      /* spikes emitted so far */
+    uint8_t *zout;       /* spikes of the last step */
+    double *x;           /* source sheet: pre trace */
+    uint8_t *zin;        /* spikes drawn last step, delivered next step */
+} orc_topo_state;
+/* Stimulus position of the epoch containing `step`. */
+void orc_topo_stimulus(uint64_t seed, const orc_topo_model *M, uint64_t step, int32_t *cx,
+                       int32_t *cy, int32_t *orient);
+/* Squared distance of source node i from the stimulus (blob: point, bar: line). */
+int32_t orc_topo_stim_d2(const orc_topo_model *M, int32_t i, int32_t cx, int32_t cy, int32_t orient);
+/* Firing rate (Hz) at squared stimulus distance d2. */
+double orc_topo_rate(const orc_topo_model *M, int32_t d2);
+/* One step t of the model (weights change only with stdp). */
+void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_topo_state *S,
+                       uint64_t t);
+/* Steps t0 .. t0+n-1; after step t with (t+1) % rewire_steps == 0 a topomap
+ * rewire keyed by t+1.  stats (may be NULL) accumulates the rewire stats. */
+void orc_topo_run(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
+                  orc_topo_state *S, uint64_t t0, uint64_t n_steps, uint32_t *bits, int32_t *stats);
 
 #endif

@@ -1,0 +1,154 @@
+/*
+ * Oracle topographic-map simulation step (test infrastructure only).
+ *
+ * The model of the topographic-map section, Tab. A-F, on one feed-forward
+ * ragged projection from an L x L Poisson source sheet to an L x L sheet of
+ * conductance-based LIF neurons, with time step h (Tab. H):
+ *
+ *   neuron (Tab. B, D)   tau_m dV/dt = V_rest - V + (g / g_leak)(E_exc - V),
+ *                        g_leak = C_m / tau_m; spike when V >= V_theta, then V
+ *                        is held at V_reset for tau_ref; tau_s dg/dt = -g plus
+ *                        g_syn for every presynaptic spike, delivered t_d later
+ *   input (Tab. B, E)    Poisson trains of rate f_base + f_peak exp(-d^2/2 s^2)
+ *                        around a stimulus position redrawn every t_stim
+ *   STDP (Tab. B, F)     all-to-all additive pairing: a postsynaptic spike adds
+ *                        A_+ x_pre, a presynaptic spike subtracts A_- y_post,
+ *                        dx/dt = -x/tau_+ + pre spikes, dy/dt = -y/tau_- + post
+ *                        spikes, g_syn clipped to [0, g_max]
+ *
+ * Readings where the tables leave the discrete-time form open:
+ *   - exponential Euler with the synaptic current g (E_exc - V) held over the
+ *     step: V <- V_rest + R I + (V - V_rest - R I) exp(-h/tau_m), R = tau_m/C_m;
+ *   - the delay t_d equals h: spikes the source draws at step t are delivered
+ *     at step t+1, and their STDP and trace effects happen at delivery;
+ *   - one step: decay x and y by exp(-h/tau); deliver (add the synapse's
+ *     conductance to g of its target, then depress it by A_- y_target; the
+ *     delivering neuron's x += 1); integrate every neuron and emit spikes; g
+ *     decays by exp(-h/tau_s); potentiate every synapse onto a neuron that
+ *     spiked by A_+ x_source, then y += 1 for it; draw this step's input.
+ *     A pair at lag k steps then changes the weight by exactly A_+ exp(-k h /
+ *     tau_+) (pre first, k >= 0) or -A_- exp(-k h / tau_-) (post first, k >= 1);
+ *   - refractoriness: the tau_ref/h steps after a spike hold V = V_reset and
+ *     emit nothing; g still receives deliveries and decays;
+ *   - the stimulus position is an integer cell, so every rate depends on an
+ *     integer squared torus distance: "blob" (the paper's) uses the distance to
+ *     a centre drawn uniformly each epoch of t_stim; "bar" uses the distance
+ *     along one axis to a line whose orientation (rows or columns) and position
+ *     are drawn each epoch;
+ *   - epoch e's draws: x = below(u32(STIM; e, 0), L), y = below(u32(STIM; e, 1),
+ *     L), orientation = u32(STIM; e, 2) & 1; input channel i spikes at step t
+ *     when u32(INPUT; t, 0, i) < floor(f h 2^32).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+static int32_t axis_d(int32_t L, int32_t a, int32_t b)
+{
+    int32_t d = abs(a - b);
+    return d < L - d ? d : L - d;
+}
+
+void orc_topo_stimulus(uint64_t seed, const orc_topo_model *M, uint64_t step, int32_t *cx,
+                       int32_t *cy, int32_t *orient)
+{
+    const uint64_t e = step / (uint64_t)M->stim_steps;
+    *cx = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 0, 0, 0), (uint32_t)M->L);
+    *cy = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 1, 0, 0), (uint32_t)M->L);
+    *orient = (int32_t)(orc_u32(seed, ORC_TAG_STIM, 0, e, 2, 0, 0) & 1u);
+}
+
+int32_t orc_topo_stim_d2(const orc_topo_model *M, int32_t i, int32_t cx, int32_t cy, int32_t orient)
+{
+    const int32_t dx = axis_d(M->L, i % M->L, cx), dy = axis_d(M->L, i / M->L, cy);
+    if (M->stim_kind == ORC_STIM_BAR) return orient ? dy * dy : dx * dx;
+    return dx * dx + dy * dy;
+}
+
+double orc_topo_rate(const orc_topo_model *M, int32_t d2)
+{
+    return M->f_base + M->f_peak * exp(-(double)d2 / (2.0 * M->sigma_stim * M->sigma_stim));
+}
+
+void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_topo_state *S,
+                       uint64_t t)
+{
+    const int32_t N = M->L * M->L;
+    const double dx_ = exp(-M->h / M->tau_plus), dy_ = exp(-M->h / M->tau_minus);
+    const double em = exp(-M->h / M->tau_m), es = exp(-M->h / M->tau_s);
+    const double R = M->tau_m / M->C_m;
+
+    /* traces decay */
+    for (int32_t i = 0; i < N; ++i) S->x[i] *= dx_;
+    for (int32_t j = 0; j < N; ++j) S->y[j] *= dy_;
+
+    /* delivery of the spikes drawn last step (delay one step), with depression */
+    for (int32_t i = 0; i < N; ++i) {
+        if (!S->zin[i]) continue;
+        for (int32_t s = 0; s < P->len[i]; ++s) {
+            const int64_t k = (int64_t)i * P->cap + s;
+            const int32_t j = P->ind[k];
+            S->g[j] += P->w[k];
+            if (M->stdp) {
+                const double w = P->w[k] - M->A_minus * S->y[j];
+                P->w[k] = w > 0.0 ? w : 0.0;
+            }
+        }
+        S->x[i] += 1.0;
+    }
+
+    /* neurons: exponential Euler, threshold, reset, refractoriness */
+    for (int32_t j = 0; j < N; ++j) {
+        S->zout[j] = 0;
+        if (S->ref[j] > 0) {
+            S->ref[j] -= 1;
+            S->V[j] = M->V_reset;
+        } else {
+            const double I = S->g[j] * (M->E_exc - S->V[j]);
+            S->V[j] = M->V_rest + R * I + (S->V[j] - M->V_rest - R * I) * em;
+            if (S->V[j] >= M->V_th) {
+                S->zout[j] = 1;
+                S->V[j] = M->V_reset;
+                S->ref[j] = M->ref_steps;
+                S->count[j] += 1;
+            }
+        }
+        S->g[j] *= es;
+    }
+
+    /* potentiation of every synapse onto a neuron that spiked, then y */
+    if (M->stdp) {
+        for (int32_t i = 0; i < N; ++i)
+            for (int32_t s = 0; s < P->len[i]; ++s) {
+                const int64_t k = (int64_t)i * P->cap + s;
+                if (!S->zout[P->ind[k]]) continue;
+                const double w = P->w[k] + M->A_plus * S->x[i];
+                P->w[k] = w < M->g_max ? w : M->g_max;
+            }
+    }
+    for (int32_t j = 0; j < N; ++j) S->y[j] += S->zout[j];
+
+    /* this step's input spikes, delivered next step */
+    int32_t cx, cy, orient;
+    orc_topo_stimulus(seed, M, t, &cx, &cy, &orient);
+    for (int32_t i = 0; i < N; ++i) {
+        const double p = orc_topo_rate(M, orc_topo_stim_d2(M, i, cx, cy, orient)) * M->h / 1000.0;
+        const uint32_t u = orc_u32(seed, ORC_TAG_INPUT, 0, t, 0, (uint64_t)i, 0);
+        S->zin[i] = (uint64_t)u < orc_threshold(p) ? 1 : 0;
+    }
+}
+
+void orc_topo_run(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
+                  orc_topo_state *S, uint64_t t0, uint64_t n_steps, uint32_t *bits, int32_t *stats)
+{
+    for (uint64_t t = t0; t < t0 + n_steps; ++t) {
+        orc_topo_sim_step(seed, M, P, S, t);
+        if (M->rewire_steps > 0 && (t + 1) % (uint64_t)M->rewire_steps == 0) {
+            int32_t st[4];
+            orc_topo_rewire(seed, P, tp, t + 1, bits, st);
+            if (stats)
+                for (int q = 0; q < 4; ++q) stats[q] += st[q];
+        }
+    }
+}
