@@ -252,8 +252,8 @@ typedef struct rs_topo_params {
   float p_form, sigma_form;   /* formation: p_form exp(-d^2 / 2 sigma^2) */
   float g_theta;              /* weights below it use p_elim_dep */
   float p_elim_dep, p_elim_pot;
-  float g_new;                /* weight of newly formed synapses */
-  float g_init;               /* weight of initial synapses */
+  float g_new;                /* weight of newly formed synapses, |g_new| <= 1e4 */
+  float g_init;               /* weight of initial synapses, |g_init| <= 1e4 */
   uint64_t seed;
 } rs_topo_params;
 
@@ -269,15 +269,80 @@ rs_status rs_topo_create(const rs_topo_params* params, void* hip_stream, rs_topo
  * synchronises and fills it. */
 rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* stats);
 /* Row access, host buffers: len int32[n_pre], ind int32[n_pre][cap],
- * w float[n_pre][cap].  Synchronise.  Errors: RS_EINVAL (len beyond cap or
- * index out of range on set). */
+ * w float[n_pre][cap].  Synchronise.  Errors: RS_EINVAL (len beyond cap,
+ * index out of range or |w| > 1e4 on set). */
 rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w);
 rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w);
 /* The attempt bitfield uint32[n_pre][ceil(n_post/32)] (all zero between updates). */
 rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits);
-/* Device timing of the last rs_topo_rewire in milliseconds (all kernels). */
+/* Device timing in milliseconds of the last rs_topo_rewire or rs_topo_run
+ * (all kernels). */
 rs_status rs_topo_last_ms(rs_topo* t, double* ms);
 void rs_topo_destroy(rs_topo* t);
+
+/* --------------------------------------------------------------------------
+ * Topographic-map simulation (topographic-map model, Tab. A-F, H): the source
+ * sheet fires Poisson trains around a stimulus position, the projection's
+ * weights are conductances (uS) onto conductance-based LIF targets, STDP
+ * changes them, and the rewiring above runs every rewire_steps steps.
+ *
+ * One step t: decay the STDP traces x (source) and y (target) by
+ * exp(-h/tau_plus), exp(-h/tau_minus); deliver the source spikes drawn at t-1
+ * (delay one step): each synapse adds its weight to its target's conductance
+ * g and, with stdp, loses A_minus*y_target (floored at 0), and x_source += 1;
+ * every target not refractory integrates by exponential Euler with the current
+ * g*(E_exc - V) held over the step, V <- V_rest + R*I + (V - V_rest - R*I) *
+ * exp(-h/tau_m), R = tau_m/C_m, and spikes when V >= V_th (V <- V_reset, then
+ * ref_steps steps held at V_reset); g decays by exp(-h/tau_s); with stdp every
+ * synapse onto a target that spiked gains A_plus*x_source (capped at g_max),
+ * and y += 1 for it; finally the source draws step t's spikes: channel i fires
+ * when u32(INPUT; t, 0, i) < floor(p*2^32), p = (f_base + f_peak*exp(-d2 /
+ * (2*sigma_stim^2))) * h / 1000, with d2 the squared torus distance of i from
+ * the stimulus (blob: a cell; bar: a row or column of cells, distance along
+ * the other axis) whose position is redrawn every stim_steps steps.
+ * -------------------------------------------------------------------------- */
+enum { RS_STIM_BLOB = 0, RS_STIM_BAR = 1 };
+
+typedef struct rs_topo_model {
+  float h;                               /* time step, ms (Tab. H) */
+  float C_m, tau_m, V_rest, E_exc;       /* nF, ms, mV, mV (Tab. D) */
+  float V_th, V_reset, tau_s;            /* mV, mV, ms */
+  uint32_t ref_steps;                    /* tau_ref / h */
+  float f_base, f_peak, sigma_stim;      /* Hz, Hz, cells (Tab. E) */
+  uint32_t stim_steps;                   /* t_stim / h, >= 1 */
+  int32_t stim_kind;                     /* RS_STIM_BLOB or RS_STIM_BAR */
+  int32_t stdp;                          /* 0: weights fixed */
+  float g_max, A_plus, A_minus;          /* uS (Tab. F) */
+  float tau_plus, tau_minus;             /* ms */
+  uint32_t rewire_steps;                 /* t_rewiring / h; 0: no rewiring */
+} rs_topo_model;
+
+/* Attach the simulation to a topographic map and reset its state: V = V_rest,
+ * everything else zero, step counter 0.  Needs L*L <= 4096 (the state of both
+ * sheets is held in one workgroup's LDS).  Synchronises.
+ * Errors: RS_EINVAL (sizes, non-positive time constants or steps), RS_ENOMEM. */
+rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m);
+/* Run n_steps steps from the step counter on, with a rewire (keyed by the
+ * step count reached) after every step count divisible by rewire_steps.
+ * Asynchronous on the map's stream.  Rewire statistics accumulate from the
+ * call's start (rs_topo_run_stats).  Errors: RS_ESTATE before rs_topo_sim_init. */
+rs_status rs_topo_run(rs_topo* t, uint64_t n_steps);
+/* Summed rewire statistics of the last rs_topo_run.  Synchronises. */
+rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* stats);
+/* Simulation variables, host buffers of exactly the stated size.  Synchronise. */
+enum {
+  RS_TV_V = 0,      /* float[L*L] target membrane potential, mV */
+  RS_TV_G = 1,      /* float[L*L] target conductance, uS */
+  RS_TV_Y = 2,      /* float[L*L] target STDP trace */
+  RS_TV_X = 3,      /* float[L*L] source STDP trace */
+  RS_TV_REF = 4,    /* int32[L*L] remaining refractory steps */
+  RS_TV_COUNT = 5,  /* uint32[L*L] target spikes since init */
+  RS_TV_ZIN = 6,    /* uint32[ceil(L*L/32)] source spikes drawn at the last step (delivered next) */
+  RS_TV_ZOUT = 7,   /* uint32[ceil(L*L/32)] target spikes of the last step (read-only) */
+  RS_TV_STEP = 8    /* uint64[1] step counter */
+};
+rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes);
+rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes);
 
 /* ==========================================================================
  * Calibration

@@ -69,13 +69,23 @@ class _TopoParams(C.Structure):
                 ("g_init", C.c_float), ("seed", C.c_uint64)]
 
 
+class _TopoModel(C.Structure):
+    _fields_ = [("h", C.c_float), ("C_m", C.c_float), ("tau_m", C.c_float), ("V_rest", C.c_float),
+                ("E_exc", C.c_float), ("V_th", C.c_float), ("V_reset", C.c_float), ("tau_s", C.c_float),
+                ("ref_steps", C.c_uint32), ("f_base", C.c_float), ("f_peak", C.c_float),
+                ("sigma_stim", C.c_float), ("stim_steps", C.c_uint32), ("stim_kind", C.c_int32),
+                ("stdp", C.c_int32), ("g_max", C.c_float), ("A_plus", C.c_float), ("A_minus", C.c_float),
+                ("tau_plus", C.c_float), ("tau_minus", C.c_float), ("rewire_steps", C.c_uint32)]
+
+
 EXPORTS = [
     "rs_last_error", "rs_eprop_create", "rs_eprop_set_input", "rs_eprop_set_input_poisson",
     "rs_eprop_step", "rs_eprop_update",
     "rs_eprop_rewire", "rs_eprop_reset", "rs_eprop_get", "rs_eprop_set", "rs_eprop_info_get",
     "rs_eprop_timing", "rs_eprop_phase_times", "rs_eprop_destroy",
     "rs_topo_create", "rs_topo_rewire", "rs_topo_get_rows", "rs_topo_set_rows", "rs_topo_get_bits",
-    "rs_topo_last_ms", "rs_topo_destroy", "rs_calib_copy",
+    "rs_topo_last_ms", "rs_topo_destroy", "rs_topo_sim_init", "rs_topo_run", "rs_topo_run_stats",
+    "rs_topo_sim_get", "rs_topo_sim_set", "rs_calib_copy",
 ]
 
 _lib = None
@@ -116,6 +126,11 @@ def lib():
         L.rs_topo_last_ms.argtypes = [vp, C.POINTER(C.c_double)]
         L.rs_topo_destroy.argtypes = [vp]
         L.rs_topo_destroy.restype = None
+        L.rs_topo_sim_init.argtypes = [vp, C.POINTER(_TopoModel)]
+        L.rs_topo_run.argtypes = [vp, C.c_uint64]
+        L.rs_topo_run_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.rs_topo_sim_get.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_topo_sim_set.argtypes = [vp, C.c_int32, vp, C.c_size_t]
         L.rs_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
         for name in EXPORTS:
             f = getattr(L, name)
@@ -365,6 +380,77 @@ class TopoNet:
         ms = C.c_double()
         _check(lib().rs_topo_last_ms(self._h, C.byref(ms)))
         return ms.value
+
+
+    # ---- simulation (rs_topo_sim_*): conductance LIF, STDP, Poisson stimulus
+    def sim_init(self, model: "TopoModel"):
+        _check(lib().rs_topo_sim_init(self._h, C.byref(model.c())))
+        self.model = model
+
+    def run(self, n_steps: int):
+        _check(lib().rs_topo_run(self._h, n_steps))
+
+    def run_stats(self) -> RewireStats:
+        st = _Stats()
+        _check(lib().rs_topo_run_stats(self._h, C.byref(st)))
+        return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
+
+    def _var(self, var: int):
+        if var == TV_STEP:
+            return np.empty(1, np.uint64)
+        if var in (TV_ZIN, TV_ZOUT):
+            return np.empty(self.words, np.uint32)
+        if var == TV_REF:
+            return np.empty(self.n, np.int32)
+        if var == TV_COUNT:
+            return np.empty(self.n, np.uint32)
+        return np.empty(self.n, np.float32)
+
+    def sim_get(self, var: int) -> np.ndarray:
+        a = self._var(var)
+        _check(lib().rs_topo_sim_get(self._h, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+        return a
+
+    def sim_set(self, var: int, value):
+        a = self._var(var)
+        a[...] = np.asarray(value).reshape(a.shape)
+        _check(lib().rs_topo_sim_set(self._h, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+
+
+STIM_BLOB, STIM_BAR = 0, 1
+TV_V, TV_G, TV_Y, TV_X, TV_REF, TV_COUNT, TV_ZIN, TV_ZOUT, TV_STEP = range(9)
+
+
+@dataclass
+class TopoModel:
+    """Topographic-map model (Tab. D-H), GeNN units: ms, mV, nF, uS, Hz."""
+    h: float = 0.1
+    C_m: float = 20.0
+    tau_m: float = 20.0
+    V_rest: float = -70.0
+    E_exc: float = 0.0
+    V_th: float = -54.0
+    V_reset: float = -70.0
+    tau_s: float = 5.0
+    ref_steps: int = 50
+    f_base: float = 5.0
+    f_peak: float = 152.8
+    sigma_stim: float = 2.0
+    stim_steps: int = 200
+    stim_kind: int = STIM_BLOB
+    stdp: int = 1
+    g_max: float = 0.2
+    A_plus: float = 0.1 * 0.2
+    A_minus: float = 1.2 * 0.1 * 0.2 * 20.0 / 64.0
+    tau_plus: float = 20.0
+    tau_minus: float = 64.0
+    rewire_steps: int = 10
+
+    def c(self) -> _TopoModel:
+        m = _TopoModel()
+        for f in fields(self):
+            setattr(m, f.name, getattr(self, f.name))
+        return m
 
 
 def calib_copy(dst, src, nbytes: int, stream=None):

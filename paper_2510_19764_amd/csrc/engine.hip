@@ -885,6 +885,11 @@ void rs_eprop_destroy(rs_eprop* n) {
 }  // extern "C"
 
 // =========================================================================== topomap
+// Largest weight magnitude of a topographic map: the simulation sums a step's
+// deliveries onto one target in 64-bit fixed point (2^-36 resolution), which
+// holds in-degree 4096 at this bound.
+constexpr float TOPO_W_MAX = 1e4f;
+
 struct rs_topo {
   rs_topo_params p;
   hipStream_t stream = nullptr;
@@ -893,6 +898,11 @@ struct rs_topo {
   uint64_t* T_d2 = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   bool timed = false;
+  // simulation (rs_topo_sim_init)
+  bool sim = false;
+  rs_topo_model m{};
+  TopoSimDev sd{};
+  uint64_t step = 0;
 };
 
 namespace {
@@ -903,6 +913,8 @@ rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
   if (p->n_attempts > 4096) return fail(RS_EINVAL, "n_attempts must be <= 4096");
   if (!(p->p_form >= 0) || !(p->sigma_form > 0) || !(p->p_elim_dep >= 0) || !(p->p_elim_pot >= 0))
     return fail(RS_EINVAL, "probabilities must be >= 0 and sigma_form > 0");
+  if (!(std::fabs(p->g_new) <= TOPO_W_MAX) || !(std::fabs(p->g_init) <= TOPO_W_MAX))
+    return fail(RS_EINVAL, "g_new and g_init must lie within +-1e4");
   t->p = *p;
   t->stream = (hipStream_t)stream;
   hipStream_t s = t->stream;
@@ -928,6 +940,7 @@ rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
   TRY(ar.alloc(&t->t.rowlist, (size_t)std::max<uint32_t>(p->n_attempts, 1)));
   TRY(ar.alloc(&t->t.nrows, 1));
   TRY(ar.alloc(&t->t.stats, 4));
+  TRY(ar.alloc(&t->t.col_dirty, 1));
   HIP_OK(hipMemcpyAsync(t->T_d2, T.data(), n_d2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
   t->t.T_d2 = t->T_d2;
   t->t.L = L;
@@ -941,6 +954,7 @@ rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
   launch_gauss_rows(s, p->seed, P, L, t->T_d2, p->g_init, true);
   launch_fill_zero(s, t->t.bits, (size_t)N * P.words * 4);
   launch_fill_zero(s, t->t.stats, 32);
+  launch_fill_zero(s, t->t.col_dirty, 4);
   HIP_OK(hipEventCreate(&t->ev0));
   HIP_OK(hipEventCreate(&t->ev1));
   HIP_OK(hipGetLastError());
@@ -1007,6 +1021,8 @@ rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, c
     for (int k = 0; k < len[i]; ++k) {
       const int32_t j = ind[(size_t)i * P.cap + k];
       if (j < 0 || j >= P.n_post) return fail(RS_EINVAL, "row %d slot %d target %d out of range", i, k, j);
+      const float wk = w[(size_t)i * P.cap + k];
+      if (!(std::fabs(wk) <= TOPO_W_MAX)) return fail(RS_EINVAL, "row %d slot %d weight outside +-1e4", i, k);
     }
   }
   const size_t n = (size_t)P.n_pre * P.cap;
@@ -1014,6 +1030,8 @@ rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, c
   HIP_OK(hipMemcpyAsync(P.len, len, (size_t)P.n_pre * 4, hipMemcpyHostToDevice, t->stream));
   HIP_OK(hipMemcpyAsync(P.ind, ind, n * 4, hipMemcpyHostToDevice, t->stream));
   HIP_OK(hipMemcpyAsync(P.w, w, n * 4, hipMemcpyHostToDevice, t->stream));
+  static const int one = 1;
+  HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
   return RS_OK;
 }
@@ -1033,6 +1051,184 @@ rs_status rs_topo_last_ms(rs_topo* t, double* ms) {
   HIP_OK(hipEventSynchronize(t->ev1));
   HIP_OK(hipEventElapsedTime(&f, t->ev0, t->ev1));
   *ms = f;
+  return RS_OK;
+}
+
+rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
+  if (!t || !m) return fail(RS_EINVAL, "NULL argument");
+  const int L = (int)t->p.L, N = L * L;
+  if (!topo_sim_fits(N)) return fail(RS_EINVAL, "the simulation needs L*L <= 4096 (L = %d)", L);
+  if (!(m->h > 0) || !(m->C_m > 0) || !(m->tau_m > 0) || !(m->tau_s > 0) || !(m->tau_plus > 0) ||
+      !(m->tau_minus > 0))
+    return fail(RS_EINVAL, "h, C_m and every time constant must be > 0");
+  if (m->stim_steps < 1) return fail(RS_EINVAL, "stim_steps must be >= 1");
+  if (m->stim_kind != RS_STIM_BLOB && m->stim_kind != RS_STIM_BAR) return fail(RS_EINVAL, "unknown stim_kind");
+  if (!(m->f_base >= 0) || !(m->f_peak >= 0) || !(m->sigma_stim > 0))
+    return fail(RS_EINVAL, "rates must be >= 0 and sigma_stim > 0");
+  if (m->ref_steps > (1u << 30)) return fail(RS_EINVAL, "ref_steps too large");
+  hipStream_t s = t->stream;
+  TopoSimDev& d = t->sd;
+  const int words = (N + 31) / 32, half = L / 2, n_d2 = 2 * half * half + 1;
+  if (!t->sim) {
+    Arena& ar = t->arena;
+    uint64_t* T_in = nullptr;
+    TRY(ar.alloc(&d.V, (size_t)N));
+    TRY(ar.alloc(&d.g, (size_t)N));
+    TRY(ar.alloc(&d.y, (size_t)N));
+    TRY(ar.alloc(&d.x, (size_t)N));
+    TRY(ar.alloc(&d.ref, (size_t)N));
+    TRY(ar.alloc(&d.count, (size_t)N));
+    TRY(ar.alloc(&d.zin, (size_t)words));
+    TRY(ar.alloc(&d.zout, (size_t)words));
+    TRY(ar.alloc(&d.col_off, (size_t)N + 1));
+    TRY(ar.alloc(&d.col_ent, (size_t)N * t->t.P.cap));
+    TRY(ar.alloc(&T_in, (size_t)n_d2));
+    d.T_in = T_in;
+  }
+  t->m = *m;
+  d.L = L;
+  d.N = N;
+  d.ref_steps = (int)m->ref_steps;
+  d.stim_steps = (int)m->stim_steps;
+  d.stim_kind = m->stim_kind;
+  d.stdp = m->stdp ? 1 : 0;
+  d.V_rest = m->V_rest;
+  d.E_exc = m->E_exc;
+  d.V_th = m->V_th;
+  d.V_reset = m->V_reset;
+  d.R = m->tau_m / m->C_m;
+  d.em = (float)std::exp(-(double)m->h / (double)m->tau_m);
+  d.es = (float)std::exp(-(double)m->h / (double)m->tau_s);
+  d.dx = (float)std::exp(-(double)m->h / (double)m->tau_plus);
+  d.dy = (float)std::exp(-(double)m->h / (double)m->tau_minus);
+  d.A_plus = m->A_plus;
+  d.A_minus = m->A_minus;
+  d.g_max = m->g_max;
+  d.col_dirty = t->t.col_dirty;
+  // Bernoulli threshold of one step of the source's Poisson train, by the
+  // integer squared distance from the stimulus (Tab. E rate profile)
+  std::vector<uint64_t> T(n_d2);
+  const double sg = (double)m->sigma_stim;
+  for (int d2 = 0; d2 < n_d2; ++d2) {
+    const double rate = (double)m->f_base + (double)m->f_peak * std::exp(-(double)d2 / (2.0 * sg * sg));
+    T[d2] = threshold(rate * (double)m->h / 1000.0);
+  }
+  HIP_OK(hipMemcpyAsync((void*)d.T_in, T.data(), n_d2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  std::vector<float> vr((size_t)N, m->V_rest);
+  HIP_OK(hipMemcpyAsync(d.V, vr.data(), (size_t)N * 4, hipMemcpyHostToDevice, s));
+  launch_fill_zero(s, d.g, (size_t)N * 4);
+  launch_fill_zero(s, d.y, (size_t)N * 4);
+  launch_fill_zero(s, d.x, (size_t)N * 4);
+  launch_fill_zero(s, d.ref, (size_t)N * 4);
+  launch_fill_zero(s, d.count, (size_t)N * 4);
+  launch_fill_zero(s, d.zin, (size_t)words * 4);
+  launch_fill_zero(s, d.zout, (size_t)words * 4);
+  static const int one = 1;
+  HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, s));
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(s));
+  t->step = 0;
+  t->sim = true;
+  return RS_OK;
+}
+
+rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
+  if (!t) return fail(RS_EINVAL, "NULL argument");
+  if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
+  hipStream_t s = t->stream;
+  const uint64_t R = t->m.rewire_steps;
+  constexpr uint64_t MAX_CHUNK = 10000;  // steps per launch without rewiring
+  launch_fill_zero(s, t->t.stats, 32);
+  HIP_OK(hipEventRecord(t->ev0, s));
+  uint64_t left = n_steps;
+  while (left > 0) {
+    uint64_t chunk = R ? R - t->step % R : MAX_CHUNK;
+    if (chunk > left) chunk = left;
+    if (chunk > MAX_CHUNK) chunk = MAX_CHUNK;
+    launch_topo_sim(s, t->p.seed, t->t.P, t->sd, t->step, (int)chunk);
+    t->step += chunk;
+    left -= chunk;
+    if (R && t->step % R == 0) launch_topo_rewire(s, t->p.seed, t->t, t->step);
+  }
+  HIP_OK(hipEventRecord(t->ev1, s));
+  t->timed = true;
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* st) {
+  if (!t || !st) return fail(RS_EINVAL, "NULL argument");
+  long long h[4];
+  HIP_OK(hipMemcpyAsync(h, t->t.stats, sizeof h, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  st->eliminated = h[0];
+  st->formed = h[1];
+  st->blocked = h[2];
+  st->attempts = 0;
+  return RS_OK;
+}
+
+namespace {
+rs_status topo_var(rs_topo* t, int32_t var, void** dev, size_t* bytes, bool* writable) {
+  if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
+  const size_t N = (size_t)t->sd.N, words = (N + 31) / 32;
+  *writable = true;
+  switch (var) {
+    case RS_TV_V: *dev = t->sd.V; *bytes = N * 4; return RS_OK;
+    case RS_TV_G: *dev = t->sd.g; *bytes = N * 4; return RS_OK;
+    case RS_TV_Y: *dev = t->sd.y; *bytes = N * 4; return RS_OK;
+    case RS_TV_X: *dev = t->sd.x; *bytes = N * 4; return RS_OK;
+    case RS_TV_REF: *dev = t->sd.ref; *bytes = N * 4; return RS_OK;
+    case RS_TV_COUNT: *dev = t->sd.count; *bytes = N * 4; return RS_OK;
+    case RS_TV_ZIN: *dev = t->sd.zin; *bytes = words * 4; return RS_OK;
+    case RS_TV_ZOUT: *dev = t->sd.zout; *bytes = words * 4; *writable = false; return RS_OK;
+    case RS_TV_STEP: *dev = nullptr; *bytes = 8; return RS_OK;
+    default: return fail(RS_EINVAL, "unknown topomap variable %d", var);
+  }
+}
+}  // namespace
+
+rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes) {
+  if (!t || !host) return fail(RS_EINVAL, "NULL argument");
+  void* dev = nullptr;
+  size_t need = 0;
+  bool wr = false;
+  TRY(topo_var(t, var, &dev, &need, &wr));
+  if (bytes != need) return fail(RS_EINVAL, "variable %d needs %zu bytes, got %zu", var, need, bytes);
+  HIP_OK(hipStreamSynchronize(t->stream));
+  if (var == RS_TV_STEP) {
+    std::memcpy(host, &t->step, 8);
+    return RS_OK;
+  }
+  HIP_OK(hipMemcpyAsync(host, dev, need, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
+}
+
+rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes) {
+  if (!t || !host) return fail(RS_EINVAL, "NULL argument");
+  void* dev = nullptr;
+  size_t need = 0;
+  bool wr = false;
+  TRY(topo_var(t, var, &dev, &need, &wr));
+  if (!wr) return fail(RS_EINVAL, "variable %d is read-only", var);
+  if (bytes != need) return fail(RS_EINVAL, "variable %d needs %zu bytes, got %zu", var, need, bytes);
+  if (var == RS_TV_REF) {
+    const int32_t* r = (const int32_t*)host;
+    for (int j = 0; j < t->sd.N; ++j)
+      if (r[j] < 0) return fail(RS_EINVAL, "refractory count of neuron %d is negative", j);
+  }
+  if (var == RS_TV_ZIN && t->sd.N % 32) {
+    const uint32_t last = ((const uint32_t*)host)[need / 4 - 1];
+    if (last >> (t->sd.N % 32)) return fail(RS_EINVAL, "spike bits beyond the sheet are set");
+  }
+  HIP_OK(hipStreamSynchronize(t->stream));
+  if (var == RS_TV_STEP) {
+    std::memcpy(&t->step, host, 8);
+    return RS_OK;
+  }
+  HIP_OK(hipMemcpyAsync(dev, host, need, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
   return RS_OK;
 }
 

@@ -133,6 +133,7 @@ __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, 
       }
     }
     P.len[r] = len;
+    if (t.col_dirty && (n > n2 || formed)) *t.col_dirty = 1;
     if (n > n2) atomicAdd((unsigned long long*)&t.stats[0], (unsigned long long)(n - n2));
     if (formed) atomicAdd((unsigned long long*)&t.stats[1], (unsigned long long)formed);
     if (blocked) atomicAdd((unsigned long long*)&t.stats[2], (unsigned long long)blocked);

@@ -148,8 +148,26 @@ struct TopoDev {
   int* rowlist;           // [max(n_attempts,1)]
   int* nrows;             // [1]
   long long* stats;       // [4]
+  int* col_dirty;         // [1] set to 1 when a rewire changes any row; may be null
 };
 void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step);
+
+// Topographic-map simulation state and constants (model of Tab. B, D-F).
+struct TopoSimDev {
+  int L, N, ref_steps, stim_steps, stim_kind, stdp;
+  float V_rest, E_exc, V_th, V_reset, R, em, es, dx, dy, A_plus, A_minus, g_max;
+  const uint64_t* T_in;   // [2*(L/2)^2 + 1] input Bernoulli threshold by squared stimulus distance
+  float *V, *g, *y, *x;   // [N]
+  int* ref;               // [N]
+  uint32_t* count;        // [N]
+  uint32_t *zin, *zout;   // [ceil(N/32)] bits
+  int *col_off, *col_ent; // [N+1], [N*cap]
+  int* col_dirty;         // [1]
+};
+bool topo_sim_fits(int N);
+size_t topo_sim_lds_bytes(int N);
+void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
+                     int n_steps);
 
 // ---------------------------------------------------------------- misc
 void launch_copy(hipStream_t s, void* dst, const void* src, size_t bytes);
