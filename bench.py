@@ -256,6 +256,67 @@ def topo_rewire_latency(n_rewires=200):
     return out
 
 
+def topo_sim_leg(steps=100_000, oracle_steps=5000, stim="bar"):
+    """The topographic map end to end (64 x 64 Poisson sheet -> 64 x 64
+    conductance-LIF sheet, cap 32, STDP, 160 rewiring attempts every 10 steps,
+    h = 0.1 ms), from a fresh build: realtime factor, steps/s, and the split
+    between simulation and rewiring from a second run with rewiring off.  The
+    oracle runs the first `oracle_steps` steps of the same workload."""
+    import torch
+    import oracle
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    c = wl.TOPO_S4
+    kind = rb.STIM_BAR if stim == "bar" else rb.STIM_BLOB
+    cfg = rb.TopoConfig(L=c["L"], cap=c["cap"], n_attempts=c["n_attempts"], proj_id=0,
+                        p_form=c["ff"]["p_form"], sigma_form=c["ff"]["sigma"], g_theta=c["g_max"] / 2,
+                        p_elim_dep=c["p_elim_dep"], p_elim_pot=c["p_elim_pot"], g_new=c["g_max"],
+                        g_init=c["g_max"], seed=1)
+    out = {"workload": f"topographic map 64x64 -> 64x64 conductance LIF, cap 32, STDP, {stim} stimulus, "
+                       f"160 rewiring attempts every 10 steps, h = 0.1 ms",
+           "steps": steps, "model_seconds": steps * 1e-4}
+    for name, R in (("with_rewiring", c["rewire_every"]), ("simulation_only", 0)):
+        model = rb.TopoModel(stim_kind=kind, rewire_steps=R)
+        t = rb.TopoNet(cfg)
+        t.sim_init(model)
+        t.run(1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dev_ms = t.last_ms()
+        st = t.run_stats()
+        n_syn = int(t.get_rows()[0].sum())
+        spikes = int(t.sim_get(rb.TV_COUNT).sum())
+        t.close()
+        out[name] = {"wall_s": round(el, 4), "device_ms": round(dev_ms, 3),
+                     "steps_per_s": round(steps / el, 1), "us_per_step": round(1e6 * el / steps, 3),
+                     "realtime_factor": round(steps * 1e-4 / el, 2), "target_spikes": spikes,
+                     "synapses_at_end": n_syn}
+        if R:
+            out[name].update(eliminated=st.eliminated, formed=st.formed, blocked=st.blocked)
+    w, s_ = out["with_rewiring"]["wall_s"], out["simulation_only"]["wall_s"]
+    out["phase_split"] = {"simulation_s": s_, "rewiring_and_remap_s": round(w - s_, 4),
+                          "rewiring_fraction": round((w - s_) / w, 4)}
+    # the oracle on the same workload
+    M = oracle.TopoModel(L=c["L"], stim_kind=kind, h=float(np.float32(0.1)))
+    P = oracle.Proj(c["L"] ** 2, c["L"] ** 2, c["cap"], False, 0)
+    f = lambda x: float(np.float32(x))
+    oracle.gauss_rows(cfg.seed, P, c["L"], f(cfg.p_form), f(cfg.sigma_form), f(cfg.g_init))
+    tp = oracle.TopoParams(L=c["L"], n_attempts=c["n_attempts"], p_form=f(cfg.p_form), sigma_form=f(cfg.sigma_form),
+                           g_theta=f(cfg.g_theta), p_elim_dep=f(cfg.p_elim_dep), p_elim_pot=f(cfg.p_elim_pot),
+                           g_new=f(cfg.g_new))
+    S = oracle.TopoState(M)
+    t0 = time.perf_counter()
+    oracle.topo_run(cfg.seed, M, P, tp, S, 0, oracle_steps)
+    orc = (time.perf_counter() - t0) / oracle_steps
+    out["oracle"] = {"us_per_step": round(1e6 * orc, 3), "cores": 1,
+                     "sample": f"the first {oracle_steps} steps of the same workload"}
+    out["gpu_over_oracle"] = round(orc / (out["with_rewiring"]["wall_s"] / steps), 2)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -267,6 +328,9 @@ def main():
     ap.add_argument("--no-tiny", action="store_true")
     ap.add_argument("--only-tiny", action="store_true",
                     help="run only the tiny-network leg and print its figures (for profiling)")
+    ap.add_argument("--only-topo", action="store_true",
+                    help="run only the topographic-map end-to-end leg and print its figures (for profiling)")
+    ap.add_argument("--topo-steps", type=int, default=100_000)
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the classifier's forward pass, without learning (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -294,6 +358,9 @@ def main():
 
     if args.only_tiny:
         print(json.dumps({"tiny_net": tiny_net_leg()}), flush=True)
+        return
+    if args.only_topo:
+        print(json.dumps({"topomap_sim": topo_sim_leg(steps=args.topo_steps)}), flush=True)
         return
     if args.forward_only:
         print(json.dumps({"forward_only": forward_only_leg()}), flush=True)
@@ -402,6 +469,8 @@ def main():
     if not args.no_topo:
         print("[bench] topographic-map rewiring latency", file=sys.stderr, flush=True)
         result["topomap_rewire"] = topo_rewire_latency()
+        print("[bench] topographic map end to end", file=sys.stderr, flush=True)
+        result["topomap_sim"] = topo_sim_leg(steps=args.topo_steps)
     if not args.no_cpu_baseline:
         print(f"[bench] oracle CPU baseline ({args.cpu_steps} timesteps)", file=sys.stderr, flush=True)
         labels, raster = batches[0]

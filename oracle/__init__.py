@@ -162,6 +162,8 @@ def _declare(L):
     L.orc_topo_stimulus.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.c_uint64, P_i32, P_i32, P_i32]
     L.orc_topo_stim_d2.argtypes = [C.POINTER(_CTopoModel), C.c_int32, C.c_int32, C.c_int32, C.c_int32]
     L.orc_topo_stim_d2.restype = C.c_int32
+    L.orc_topo_input_u32.argtypes = [C.c_uint64, C.c_uint64, C.c_int32]
+    L.orc_topo_input_u32.restype = C.c_uint32
     L.orc_topo_rate.argtypes = [C.POINTER(_CTopoModel), C.c_int32]
     L.orc_topo_rate.restype = C.c_double
     L.orc_topo_sim_step.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
@@ -544,6 +546,10 @@ def topo_stimulus(seed: int, M: TopoModel, step: int):
 
 def topo_stim_d2(M: TopoModel, i: int, cx: int, cy: int, orient: int) -> int:
     return lib().orc_topo_stim_d2(C.byref(M.c()), i, cx, cy, orient)
+
+
+def topo_input_u32(seed: int, t: int, i: int) -> int:
+    return lib().orc_topo_input_u32(seed, t, i)
 
 
 def topo_rate(M: TopoModel, d2: int) -> float:

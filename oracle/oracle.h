@@ -42,7 +42,8 @@ enum {
     ORC_TAG_TP_ELIM = 8, /* topomap elimination draw,     counter (step, r, s, 0) */
     ORC_TAG_TP_FORM = 9, /* topomap formation draw,       counter (step, r, j, 0) */
     ORC_TAG_INPUT = 10,  /* Poisson input spike,          counter (step, b, i, 0) */
-    ORC_TAG_STIM = 11    /* topomap stimulus position,    counter (epoch, k, 0, 0) */
+    ORC_TAG_STIM = 11,   /* topomap stimulus position,    counter (epoch, k, 0, 0) */
+    ORC_TAG_TP_INPUT = 12 /* topomap source spikes,       counter (step, i/8, 0, 0), 8 per call */
 };
 
 /* Draws per (row, activation) before the bounded fallback scan takes over. */
@@ -187,6 +188,9 @@ typedef struct orc_topo_state {
     double *x;           /* source sheet: pre trace */
     uint8_t *zin;        /* spikes drawn last step, delivered next step */
 } orc_topo_state;
+/* Uniform 32-bit draw of source channel i at step t (eight channels per
+ * generator call: word (i%8)/2, upper half for even i). */
+uint32_t orc_topo_input_u32(uint64_t seed, uint64_t t, int32_t i);
 /* Stimulus position of the epoch containing `step`. */
 void orc_topo_stimulus(uint64_t seed, const orc_topo_model *M, uint64_t step, int32_t *cx,
                        int32_t *cy, int32_t *orient);

@@ -37,12 +37,24 @@
  *     are drawn each epoch;
  *   - epoch e's draws: x = below(u32(STIM; e, 0), L), y = below(u32(STIM; e, 1),
  *     L), orientation = u32(STIM; e, 2) & 1; input channel i spikes at step t
- *     when u32(INPUT; t, 0, i) < floor(f h 2^32).
+ *     when its uniform 32-bit draw is below floor(f h 2^32).  The tables leave
+ *     the random stream open; one generator call serves eight channels: the
+ *     draw of channel i is output word (i mod 8)/2 of Philox4x64-10 under key
+ *     (seed, TP_INPUT) at counter (t, floor(i/8), 0, 0), its upper half for even
+ *     i and its lower half for odd i.
  */
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include "oracle.h"
+
+uint32_t orc_topo_input_u32(uint64_t seed, uint64_t t, int32_t i)
+{
+    uint64_t ctr[4] = {t, (uint64_t)(i / 8), 0, 0}, o[4];
+    orc_philox4x64_10(seed, (uint64_t)ORC_TAG_TP_INPUT, ctr, o);
+    const uint64_t w = o[(i % 8) / 2];
+    return (i % 2) ? (uint32_t)w : (uint32_t)(w >> 32);
+}
 
 static int32_t axis_d(int32_t L, int32_t a, int32_t b)
 {
@@ -134,7 +146,7 @@ void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_
     orc_topo_stimulus(seed, M, t, &cx, &cy, &orient);
     for (int32_t i = 0; i < N; ++i) {
         const double p = orc_topo_rate(M, orc_topo_stim_d2(M, i, cx, cy, orient)) * M->h / 1000.0;
-        const uint32_t u = orc_u32(seed, ORC_TAG_INPUT, 0, t, 0, (uint64_t)i, 0);
+        const uint32_t u = orc_topo_input_u32(seed, t, i);
         S->zin[i] = (uint64_t)u < orc_threshold(p) ? 1 : 0;
     }
 }

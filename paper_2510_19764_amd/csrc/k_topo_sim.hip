@@ -5,9 +5,10 @@
 // k_topo_sim is one workgroup of 1024 threads that runs up to a whole
 // rewiring interval of steps without leaving the kernel: per step the work is a
 // few thousand neurons and a handful of spikes, so a launch or a grid barrier
-// per phase would cost more than the phase.  Neuron and trace state lives in
-// LDS for the launch and goes back to HBM at its end; rows stay in global
-// memory (L2-resident, the rewiring kernels edit them between launches).
+// per phase would cost more than the phase.  Target-neuron state lives in
+// registers and the STDP traces in LDS for the launch, and both go back to HBM
+// at its end; rows stay in global memory (L2-resident, the rewiring kernels
+// edit them between launches).
 //
 // One step t (the order of the model readings):
 //   A  decay the STDP traces x (source) and y (target) by exp(-h/tau)
@@ -15,10 +16,14 @@
 //      source, a lane per synapse adds its weight to the target's conductance
 //      (64-bit fixed point in LDS, so the sum does not depend on the order of
 //      arrival) and depresses the weight by A_- y_target; x_source += 1
-//   C  each thread owns target neurons: exponential Euler with the synaptic
-//      current held over the step, threshold, reset, refractory count, g decay;
-//      spiking targets are listed.  The same threads draw this step's input
-//      spikes for their source neurons and list them for step t+1
+//      Meanwhile the upper half of the workgroup draws the source's spikes of
+//      step t, eight channels per generator call, into a second list; each
+//      drawing thread keeps its channels' thresholds in registers and looks
+//      them up again only when the stimulus moves
+//   C  each thread owns up to four target neurons, whose V, g, refractory
+//      count and spike count stay in registers for the launch: exponential
+//      Euler with the synaptic current held over the step, threshold, reset,
+//      refractory count, g decay; spiking targets are listed
 //   D  potentiation: one wave per spiking target walks its column (the
 //      synapses onto it) and adds A_+ x_source, clipped to g_max; y += 1
 // The column view (slot indices grouped by target) is rebuilt at the start of
@@ -32,10 +37,15 @@ namespace rs {
 
 constexpr int TS_NT = 1024;
 constexpr int TS_MAX_N = 4096;
+constexpr int TS_PER = TS_MAX_N / TS_NT;  // target neurons owned by each thread
+static_assert(TS_MAX_N / 8 <= TS_NT / 2, "the upper half of the workgroup draws every source group");
+static_assert((TS_NT / 2) % WAVE == 0, "drawing threads form whole waves");
 
-size_t topo_sim_lds_bytes(int N) {
-  // V, g, y, x (float), ref (int), acc (int64), pre list, post list (int)
-  return (size_t)N * (4 * 4 + 4 + 8 + 4 + 4);
+// acc (int64), y, x (float), two source lists and the target list, column
+// offsets [N+1] (int)
+size_t topo_sim_lds_bytes(int N, int n_d2) {
+  (void)n_d2;
+  return (size_t)N * (8 + 4 + 4 + 4 + 4 + 4) + ((size_t)N + 1) * 4;
 }
 
 bool topo_sim_fits(int N) { return N >= 1 && N <= TS_MAX_N; }
@@ -46,8 +56,9 @@ __device__ __forceinline__ int axis_dist(int L, int a, int b) {
 }
 
 // Rebuild the column view: col_off[j]..col_off[j+1] lists the slots i*cap+s
-// whose target is j.  cnt and cur are LDS scratch of N ints each.
-__device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* cnt, int* cur, int* part) {
+// whose target is j (written to HBM and to the LDS copy coff).  cnt and cur
+// are LDS scratch of N ints each.
+__device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* cnt, int* cur, int* part, int* coff) {
   const int N = sd.N, tid = threadIdx.x;
   for (int j = tid; j < N; j += TS_NT) cnt[j] = 0;
   __syncthreads();
@@ -73,10 +84,14 @@ __device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* cnt, i
   int run = part[tid] - sum;
   for (int j = lo; j < hi; ++j) {
     sd.col_off[j] = run;
+    coff[j] = run;
     cur[j] = run;
     run += cnt[j];
   }
-  if (tid == TS_NT - 1) sd.col_off[N] = part[TS_NT - 1];
+  if (tid == TS_NT - 1) {
+    sd.col_off[N] = part[TS_NT - 1];
+    coff[N] = part[TS_NT - 1];
+  }
   __syncthreads();
   for (int i = tid; i < N; i += TS_NT) {
     const int n = P.len[i];
@@ -90,29 +105,40 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
                                                     int n_steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int N = sd.N, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
-  long long* acc = (long long*)smem;          // [N]
-  float* V = (float*)(acc + N);               // [N]
-  float* g = V + N;                           // [N]
-  float* y = g + N;                           // [N]
-  float* x = y + N;                           // [N]
-  int* ref = (int*)(x + N);                   // [N]
-  int* pre = ref + N;                         // [N] sources to deliver (B), then next step's (C)
-  int* post = pre + N;                        // [N] targets that spiked this step
+  long long* acc = (long long*)smem;          // [N] delivered conductance, fixed point
+  float* y = (float*)(acc + N);               // [N] target trace
+  float* x = y + N;                           // [N] source trace
+  int* pre0 = (int*)(x + N);                  // [N] source lists: this step's deliveries and
+  int* pre1 = pre0 + N;                       // [N]   the next step's, alternating
+  int* post = pre1 + N;                       // [N] targets that spiked this step
+  int* coff = post + N;                       // [N+1] column offsets
   __shared__ int part[TS_NT];
   __shared__ int s_npre[2], s_npost;
   __shared__ int s_stim[3];
 
   if (*sd.col_dirty) {  // uniform: one value read by every thread
-    topo_columns(P, sd, (int*)acc, (int*)acc + N, part);
+    topo_columns(P, sd, (int*)acc, (int*)acc + N, part, coff);
     if (tid == 0) *sd.col_dirty = 0;
+  } else {
+    for (int j = tid; j <= N; j += TS_NT) coff[j] = sd.col_off[j];
   }
   for (int j = tid; j < N; j += TS_NT) {
     acc[j] = 0;
-    V[j] = sd.V[j];
-    g[j] = sd.g[j];
     y[j] = sd.y[j];
     x[j] = sd.x[j];
-    ref[j] = sd.ref[j];
+  }
+  // target neurons j = tid + m*TS_NT live in registers for the launch
+  float Vr[TS_PER], gr[TS_PER];
+  int refr[TS_PER];
+  uint32_t cnt[TS_PER];
+#pragma unroll
+  for (int m = 0; m < TS_PER; ++m) {
+    const int j = tid + m * TS_NT;
+    const bool ok = j < N;
+    Vr[m] = ok ? sd.V[j] : 0.f;
+    gr[m] = ok ? sd.g[j] : 0.f;
+    refr[m] = ok ? sd.ref[j] : 0;
+    cnt[m] = ok ? sd.count[j] : 0u;
   }
   if (tid == 0) {
     s_npre[0] = 0;
@@ -125,11 +151,12 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     while (m) {
       const int b = __builtin_ctz(m);
       m &= m - 1;
-      pre[atomicAdd(&s_npre[0], 1)] = w * 32 + b;
+      pre0[atomicAdd(&s_npre[0], 1)] = w * 32 + b;
     }
   }
 
-  const int L = sd.L;
+  const int L = sd.L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
+  uint64_t thr[8];  // this thread's source thresholds for the current stimulus epoch
   for (int k = 0; k < n_steps; ++k) {
     const uint64_t t = t0 + (uint64_t)k;
     const int cb = k & 1, nb = cb ^ 1;
@@ -148,33 +175,76 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
       s_npost = 0;
     }
     __syncthreads();
-    // ---- B: delivery with depression, one wave per spiking source
+    // ---- B: delivery with depression, one wave per spiking source from wave 0
+    // up; every slot of the padded row is loaded together with the row length.
+    // Meanwhile the upper half of the workgroup draws this step's source spikes,
+    // eight channels per generator call, into the other list.
     const int npre = s_npre[cb];
+    int* cur = cb ? pre1 : pre0;
+    int* nxt = cb ? pre0 : pre1;
     for (int q = wv; q < npre; q += TS_NT / WAVE) {
-      const int i = pre[q];
+      const int i = cur[q];
+      const int64_t base = (int64_t)i * cap;
       const int n = P.len[i];
-      const int64_t base = (int64_t)i * P.cap;
-      for (int s = lane; s < n; s += WAVE) {
+      for (int s = lane; s < cap; s += WAVE) {
         const int j = P.ind[base + s];
         const float w = P.w[base + s];
-        atomicAdd((unsigned long long*)&acc[j], (unsigned long long)__double2ll_rn((double)w * FIX_SCALE));
-        if (sd.stdp) P.w[base + s] = fmaxf(0.f, w - sd.A_minus * y[j]);
+        if (s < n) {
+          atomicAdd((unsigned long long*)&acc[j], (unsigned long long)__double2ll_rn((double)w * FIX_SCALE));
+          if (sd.stdp) P.w[base + s] = fmaxf(0.f, w - sd.A_minus * y[j]);
+        }
       }
       if (lane == 0) x[i] += 1.f;
     }
-    __syncthreads();
-    // ---- C: neurons, then this step's input draws
     const bool last = k == n_steps - 1;
-    const int cx = s_stim[0], cy = s_stim[1], orient = s_stim[2];
-    for (int j0 = 0; j0 < N; j0 += TS_NT) {
-      const int j = j0 + tid;
-      bool z = false, zi = false;
+    if (tid >= TS_NT / 2) {  // whole waves: TS_NT / 2 is a multiple of the wave size
+      const int c = tid - TS_NT / 2;
+      uint32_t byte = 0;
+      if (c < ngrp) {
+        if (k == 0 || t % (uint64_t)sd.stim_steps == 0) {
+          const int cx = s_stim[0], cy = s_stim[1], orient = s_stim[2];
+#pragma unroll
+          for (int b = 0; b < 8; ++b) {
+            const int i = 8 * c + b;
+            thr[b] = 0;  // channels beyond the sheet never fire
+            if (i < N) {
+              const int dxs = axis_dist(L, i % L, cx), dys = axis_dist(L, i / L, cy);
+              const int d2 = sd.stim_kind ? (orient ? dys * dys : dxs * dxs) : dxs * dxs + dys * dys;
+              thr[b] = sd.T_in[d2];
+            }
+          }
+        }
+        const U64x4 o = philox(seed, (uint64_t)TAG_TP_INPUT, t, (uint64_t)c, 0, 0);
+        const uint64_t wd[4] = {o.x0, o.x1, o.x2, o.x3};
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+          const uint32_t u = (b & 1) ? (uint32_t)wd[b >> 1] : (uint32_t)(wd[b >> 1] >> 32);
+          if ((uint64_t)u < thr[b]) {
+            byte |= 1u << b;
+            nxt[atomicAdd(&s_npre[nb], 1)] = 8 * c + b;
+          }
+        }
+      }
+      if (last) {
+        // four consecutive threads hold one 32-bit word of source bits
+        uint32_t wbits = byte << (8 * (lane & 3));
+        wbits |= __shfl_xor(wbits, 1, WAVE);
+        wbits |= __shfl_xor(wbits, 2, WAVE);
+        if ((lane & 3) == 0 && c < ngrp) sd.zin[c >> 2] = wbits;
+      }
+    }
+    __syncthreads();
+    // ---- C: neurons (registers)
+#pragma unroll
+    for (int m = 0; m < TS_PER; ++m) {
+      const int j = tid + m * TS_NT;
+      bool z = false;
       if (j < N) {
-        float gj = g[j] + (float)((double)acc[j] * FIX_INV);
+        const float gj = gr[m] + (float)((double)acc[j] * FIX_INV);
         acc[j] = 0;
-        float v = V[j];
-        if (ref[j] > 0) {
-          ref[j] -= 1;
+        float v = Vr[m];
+        if (refr[m] > 0) {
+          refr[m] -= 1;
           v = sd.V_reset;
         } else {
           const float I = gj * (sd.E_exc - v);
@@ -183,32 +253,19 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
           if (v >= sd.V_th) {
             z = true;
             v = sd.V_reset;
-            ref[j] = sd.ref_steps;
-            sd.count[j] += 1u;
+            refr[m] = sd.ref_steps;
+            cnt[m] += 1u;
             post[atomicAdd(&s_npost, 1)] = j;
           }
         }
-        V[j] = v;
-        g[j] = gj * sd.es;
-        // input neuron j of the source sheet
-        const int dxs = axis_dist(L, j % L, cx), dys = axis_dist(L, j / L, cy);
-        const int d2 = sd.stim_kind ? (orient ? dys * dys : dxs * dxs) : dxs * dxs + dys * dys;
-        const uint32_t u = draw_u32(seed, TAG_INPUT, 0, t, 0, (uint64_t)j, 0);
-        zi = (uint64_t)u < sd.T_in[d2];
-        if (zi) pre[atomicAdd(&s_npre[nb], 1)] = j;  // the list of step t was consumed in B
+        Vr[m] = v;
+        gr[m] = gj * sd.es;
       }
-      if (last) {
-        const uint64_t mz = ballot(z), mi = ballot(zi);
-        const int w0 = (j0 + wv * WAVE) >> 5;
-        const int words = (N + 31) / 32;
-        if (lane == 0 && w0 < words) {
-          sd.zout[w0] = (uint32_t)mz;
-          sd.zin[w0] = (uint32_t)mi;
-        }
-        if (lane == 0 && w0 + 1 < words) {
-          sd.zout[w0 + 1] = (uint32_t)(mz >> 32);
-          sd.zin[w0 + 1] = (uint32_t)(mi >> 32);
-        }
+      if (last && m * TS_NT < N) {
+        const uint64_t mz = ballot(z);
+        const int w0 = (m * TS_NT + wv * WAVE) >> 5, words = (N + 31) / 32;
+        if (lane == 0 && w0 < words) sd.zout[w0] = (uint32_t)mz;
+        if (lane == 0 && w0 + 1 < words) sd.zout[w0 + 1] = (uint32_t)(mz >> 32);
       }
     }
     __syncthreads();
@@ -217,10 +274,10 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     if (sd.stdp) {
       for (int q = wv; q < npost; q += TS_NT / WAVE) {
         const int j = post[q];
-        const int e0 = sd.col_off[j], e1 = sd.col_off[j + 1];
+        const int e0 = coff[j], e1 = coff[j + 1];
         for (int e = e0 + lane; e < e1; e += WAVE) {
           const int slot = sd.col_ent[e];
-          const float w = P.w[slot] + sd.A_plus * x[slot / P.cap];
+          const float w = P.w[slot] + sd.A_plus * x[slot / cap];
           P.w[slot] = fminf(w, sd.g_max);
         }
       }
@@ -228,12 +285,19 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     for (int q = tid; q < npost; q += TS_NT) y[post[q]] += 1.f;
     __syncthreads();
   }
+#pragma unroll
+  for (int m = 0; m < TS_PER; ++m) {
+    const int j = tid + m * TS_NT;
+    if (j < N) {
+      sd.V[j] = Vr[m];
+      sd.g[j] = gr[m];
+      sd.ref[j] = refr[m];
+      sd.count[j] = cnt[m];
+    }
+  }
   for (int j = tid; j < N; j += TS_NT) {
-    sd.V[j] = V[j];
-    sd.g[j] = g[j];
     sd.y[j] = y[j];
     sd.x[j] = x[j];
-    sd.ref[j] = ref[j];
   }
 }
 
@@ -244,7 +308,8 @@ void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoS
     allow_dynamic_lds((const void*)k_topo_sim, 160 * 1024);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N), s, seed, P, sd, t0, n_steps);
+  hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N, sd.n_d2), s, seed, P, sd, t0,
+                     n_steps);
 }
 
 }  // namespace rs

@@ -274,3 +274,31 @@ def test_full_model_invariants():
         assert np.all(w >= 0) and np.all(w <= float(np.float32(M.g_max)))
     assert S.count.sum() > 0
     assert np.all((S.ref >= 0) & (S.ref <= M.ref_steps))
+
+
+def test_input_draws_share_generator_calls_as_stated():
+    """Eight channels per generator call: channel i's draw is word (i % 8) / 2
+    of the Philox block at counter (t, i // 8), upper half for even i, lower
+    half for odd i (the block itself is pinned to numpy's Philox elsewhere)."""
+    key1 = 12  # topomap source tag, projection 0
+    for t, i in [(0, 0), (0, 1), (7, 5), (123, 4095), (99999, 8), (5, 2046)]:
+        words = O.philox4x64_10(SEED, key1, [t, i // 8, 0, 0])
+        w = int(words[(i % 8) // 2])
+        expect = (w & 0xFFFFFFFF) if i % 2 else (w >> 32)
+        assert O.topo_input_u32(SEED, t, i) == expect
+
+
+def test_input_channels_sharing_a_word_are_independent():
+    """Channels 2k and 2k+1 take the two halves of one 64-bit word: at p = 1/2
+    their joint firing frequency is 1/4 within 5 sigma."""
+    L = 16
+    M = O.TopoModel(L=L, f_base=5000.0, f_peak=0.0, stdp=0, rewire_steps=0)
+    P = rows(L, 1, [])
+    S = O.TopoState(M)
+    both = n = 0
+    for t in range(400):
+        O.topo_sim_step(SEED, M, P, S, t)
+        z = S.zin.astype(np.int64)
+        both += int((z[0::2] & z[1::2]).sum())
+        n += L * L // 2
+    assert abs(both - n / 4) < 5 * math.sqrt(n * 3 / 16)
