@@ -324,8 +324,12 @@ typedef struct rs_topo_model {
 rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m);
 /* Run n_steps steps from the step counter on, with a rewire (keyed by the
  * step count reached) after every step count divisible by rewire_steps.
- * Asynchronous on the map's stream.  Rewire statistics accumulate from the
- * call's start (rs_topo_run_stats).  Errors: RS_ESTATE before rs_topo_sim_init. */
+ * Asynchronous on the map's stream.  Runs of 64 whole rewiring intervals are
+ * replayed from a HIP graph recorded at their first use (and again after
+ * rs_topo_sim_init); the results equal those of step-by-step calls bit for
+ * bit.  Rewire statistics accumulate from the call's start
+ * (rs_topo_run_stats).  The step count 2^64-1 is reserved.
+ * Errors: RS_ESTATE before rs_topo_sim_init, RS_EDEVICE if recording fails. */
 rs_status rs_topo_run(rs_topo* t, uint64_t n_steps);
 /* Summed rewire statistics of the last rs_topo_run.  Synchronises. */
 rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* stats);

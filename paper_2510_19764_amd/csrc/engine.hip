@@ -903,7 +903,46 @@ struct rs_topo {
   rs_topo_model m{};
   TopoSimDev sd{};
   uint64_t step = 0;
+  uint64_t* step_dev = nullptr;
+  // GRAPH_INTERVALS whole rewiring intervals (simulation + rewire launches)
+  // recorded once and replayed; the kernels read the step count from step_dev
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
+
+namespace {
+constexpr uint64_t GRAPH_INTERVALS = 64;
+
+void topo_drop_graph(rs_topo* t) {
+  if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
+  if (t->graph) (void)hipGraphDestroy(t->graph);
+  t->gexec = nullptr;
+  t->graph = nullptr;
+}
+
+rs_status topo_build_graph(rs_topo* t) {
+  const int R = (int)t->m.rewire_steps;
+  topo_sim_attrs();
+  topo_rewire_attrs();
+  if (!t->cap_stream) HIP_OK(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (uint64_t g = 0; g < GRAPH_INTERVALS; ++g) {
+    launch_topo_sim(t->cap_stream, t->p.seed, t->t.P, t->sd, STEP_FROM_DEVICE, R);
+    launch_topo_rewire(t->cap_stream, t->p.seed, t->t, STEP_FROM_DEVICE);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(RS_EDEVICE, "capturing the rewiring-interval graph failed: %s", hipGetErrorString(e));
+  }
+  t->graph = g;
+  HIP_OK(hipGraphInstantiate(&t->gexec, t->graph, nullptr, nullptr, 0));
+  return RS_OK;
+}
+}  // namespace
+
 
 namespace {
 
@@ -983,6 +1022,7 @@ rs_status rs_topo_create(const rs_topo_params* p, void* hip_stream, rs_topo** ou
 
 rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
   if (!t) return fail(RS_EINVAL, "NULL argument");
+  if (step == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step 2^64-1 is reserved");
   hipStream_t s = t->stream;
   launch_fill_zero(s, t->t.stats, 32);
   HIP_OK(hipEventRecord(t->ev0, s));
@@ -1083,8 +1123,10 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
     TRY(ar.alloc(&d.col_off, (size_t)N + 1));
     TRY(ar.alloc(&d.col_ent, (size_t)N * t->t.P.cap));
     TRY(ar.alloc(&T_in, (size_t)n_d2));
+    TRY(ar.alloc(&t->step_dev, 1));
     d.T_in = T_in;
   }
+  topo_drop_graph(t);  // the recorded launches carry the old constants
   t->m = *m;
   d.L = L;
   d.N = N;
@@ -1106,6 +1148,8 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   d.A_minus = m->A_minus;
   d.g_max = m->g_max;
   d.col_dirty = t->t.col_dirty;
+  d.step_dev = t->step_dev;
+  t->t.step_dev = t->step_dev;
   // Bernoulli threshold of one step of the source's Poisson train, by the
   // integer squared distance from the stimulus (Tab. E rate profile)
   std::vector<uint64_t> T(n_d2);
@@ -1124,6 +1168,7 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   launch_fill_zero(s, d.count, (size_t)N * 4);
   launch_fill_zero(s, d.zin, (size_t)words * 4);
   launch_fill_zero(s, d.zout, (size_t)words * 4);
+  launch_fill_zero(s, t->step_dev, 8);
   static const int one = 1;
   HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, s));
   HIP_OK(hipGetLastError());
@@ -1143,6 +1188,13 @@ rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
   HIP_OK(hipEventRecord(t->ev0, s));
   uint64_t left = n_steps;
   while (left > 0) {
+    if (R && t->step % R == 0 && left >= R * GRAPH_INTERVALS) {
+      if (!t->gexec) TRY(topo_build_graph(t));
+      HIP_OK(hipGraphLaunch(t->gexec, s));
+      t->step += R * GRAPH_INTERVALS;
+      left -= R * GRAPH_INTERVALS;
+      continue;
+    }
     uint64_t chunk = R ? R - t->step % R : MAX_CHUNK;
     if (chunk > left) chunk = left;
     if (chunk > MAX_CHUNK) chunk = MAX_CHUNK;
@@ -1225,7 +1277,12 @@ rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t byte
   }
   HIP_OK(hipStreamSynchronize(t->stream));
   if (var == RS_TV_STEP) {
+    uint64_t v;
+    std::memcpy(&v, host, 8);
+    if (v == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step count 2^64-1 is reserved");
     std::memcpy(&t->step, host, 8);
+    HIP_OK(hipMemcpyAsync(t->step_dev, &t->step, 8, hipMemcpyHostToDevice, t->stream));
+    HIP_OK(hipStreamSynchronize(t->stream));
     return RS_OK;
   }
   HIP_OK(hipMemcpyAsync(dev, host, need, hipMemcpyHostToDevice, t->stream));
@@ -1236,6 +1293,8 @@ rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t byte
 void rs_topo_destroy(rs_topo* t) {
   if (!t) return;
   (void)hipStreamSynchronize(t->stream);
+  topo_drop_graph(t);
+  if (t->cap_stream) (void)hipStreamDestroy(t->cap_stream);
   if (t->ev0) (void)hipEventDestroy(t->ev0);
   if (t->ev1) (void)hipEventDestroy(t->ev1);
   t->arena.release();

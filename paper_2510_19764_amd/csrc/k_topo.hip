@@ -19,6 +19,7 @@ namespace rs {
 constexpr int TD_NT = 1024;
 
 __global__ void __launch_bounds__(TD_NT) k_topo_distribute(uint64_t seed, TopoDev t, uint64_t step) {
+  if (step == STEP_FROM_DEVICE) step = *t.step_dev;
   extern __shared__ __align__(16) unsigned char smem[];
   int* k = (int*)smem;  // [n_pre]
   __shared__ int s_n;
@@ -144,6 +145,7 @@ __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, 
 
 // Two launches: the row list from k_topo_distribute, one wave per listed row.
 __global__ void __launch_bounds__(WAVE) k_topo_rewire(uint64_t seed, TopoDev t, uint64_t step) {
+  if (step == STEP_FROM_DEVICE) step = *t.step_dev;
   extern __shared__ __align__(16) unsigned char smem[];
   const int q = blockIdx.x;
   if (q >= *t.nrows) return;
@@ -157,6 +159,7 @@ __global__ void __launch_bounds__(WAVE) k_topo_rewire(uint64_t seed, TopoDev t, 
 // two-launch form.
 constexpr int TOPO_FUSED_MAX = 2048;
 __global__ void __launch_bounds__(WAVE) k_topo_rewire_fused(uint64_t seed, TopoDev t, uint64_t step) {
+  if (step == STEP_FROM_DEVICE) step = *t.step_dev;
   extern __shared__ __align__(16) unsigned char smem[];
   int* rows = (int*)smem;  // [n_attempts]
   const int a = blockIdx.x, lane = lane_id(), na = t.n_attempts;
@@ -176,12 +179,16 @@ __global__ void __launch_bounds__(WAVE) k_topo_rewire_fused(uint64_t seed, TopoD
   topo_rewire_row(seed, t, step, r, kr, smem + (((size_t)na * 4 + 15) & ~(size_t)15));
 }
 
-void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step) {
+void topo_rewire_attrs() {
   static bool attr_set = false;
   if (!attr_set) {
     allow_dynamic_lds((const void*)k_topo_distribute, 128 * 1024);
     attr_set = true;
   }
+}
+
+void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step) {
+  topo_rewire_attrs();
   const size_t sm = (size_t)t.P.words * 4 + (size_t)t.n_attempts * 4 + (size_t)t.P.cap * 9 + 16;
   if (t.n_attempts > 0 && t.n_attempts <= TOPO_FUSED_MAX) {
     const size_t rows = ((size_t)t.n_attempts * 4 + 15) & ~(size_t)15;

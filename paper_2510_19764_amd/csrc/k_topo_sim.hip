@@ -104,6 +104,7 @@ __device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* cnt, i
 __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, TopoSimDev sd, uint64_t t0,
                                                     int n_steps) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (t0 == STEP_FROM_DEVICE) t0 = *sd.step_dev;
   const int N = sd.N, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   long long* acc = (long long*)smem;          // [N] delivered conductance, fixed point
   float* y = (float*)(acc + N);               // [N] target trace
@@ -299,15 +300,20 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     sd.y[j] = y[j];
     sd.x[j] = x[j];
   }
+  if (tid == 0) *sd.step_dev = t0 + (uint64_t)n_steps;
 }
 
-void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
-                     int n_steps) {
+void topo_sim_attrs() {
   static bool attr_set = false;
   if (!attr_set) {
     allow_dynamic_lds((const void*)k_topo_sim, 160 * 1024);
     attr_set = true;
   }
+}
+
+void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
+                     int n_steps) {
+  topo_sim_attrs();
   hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N, sd.n_d2), s, seed, P, sd, t0,
                      n_steps);
 }

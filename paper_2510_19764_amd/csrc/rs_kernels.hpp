@@ -149,7 +149,11 @@ struct TopoDev {
   int* nrows;             // [1]
   long long* stats;       // [4]
   int* col_dirty;         // [1] set to 1 when a rewire changes any row; may be null
+  const uint64_t* step_dev;  // [1] step count, read when a launch passes STEP_FROM_DEVICE
 };
+// Step argument telling a topographic-map kernel to read the step count from
+// device memory (launches recorded once in a graph and replayed).
+constexpr uint64_t STEP_FROM_DEVICE = ~0ull;
 void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step);
 
 // Topographic-map simulation state and constants (model of Tab. B, D-F).
@@ -163,11 +167,15 @@ struct TopoSimDev {
   uint32_t *zin, *zout;   // [ceil(N/32)] bits
   int *col_off, *col_ent; // [N+1], [N*cap]
   int* col_dirty;         // [1]
+  uint64_t* step_dev;     // [1] step count: read for t0 == STEP_FROM_DEVICE, written at the end
 };
 bool topo_sim_fits(int N);
 size_t topo_sim_lds_bytes(int N, int n_d2);
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
                      int n_steps);
+// Set the kernels' launch attributes ahead of a stream capture (idempotent).
+void topo_sim_attrs();
+void topo_rewire_attrs();
 
 // ---------------------------------------------------------------- misc
 void launch_copy(hipStream_t s, void* dst, const void* src, size_t bytes);

@@ -143,6 +143,55 @@ def test_topo_sim_split_runs_are_identical():
     assert a.sim_get(rb.TV_COUNT).sum() > 0
 
 
+def _same_state(a, b):
+    for var in (rb.TV_V, rb.TV_G, rb.TV_Y, rb.TV_X, rb.TV_REF, rb.TV_COUNT, rb.TV_ZIN, rb.TV_ZOUT, rb.TV_STEP):
+        assert np.array_equal(a.sim_get(var), b.sim_get(var)), var
+    for x, y in zip(a.get_rows(), b.get_rows()):
+        assert np.array_equal(x, y)
+
+
+def test_topo_sim_graph_replays_match_direct_launches():
+    """Whole rewiring intervals run as replays of a recorded graph of 64
+    intervals.  Replays mixed with direct launches and host reads give the same
+    state and rows, bit for bit, as the same steps in 10-step calls."""
+    cfg, model = CASES["hot-L16-blob"]
+    a, b = rb.TopoNet(cfg), rb.TopoNet(cfg)
+    a.sim_init(model)
+    b.sim_init(model)
+    a.run(5)                 # direct, within an interval
+    a.run(5 + 640 * 2)       # direct to the boundary, then two replays
+    a.sim_get(rb.TV_V)       # host read between replays
+    a.run(640 * 3 + 7)       # three replays, then a direct partial interval
+    total = 5 + 5 + 1280 + 1920 + 7
+    b.run(5)
+    done = 5
+    while done < total:
+        n = min(10 - done % 10, total - done)
+        b.run(n)
+        done += n
+    _same_state(a, b)
+    assert a.sim_get(rb.TV_COUNT).sum() > 0
+
+
+def test_topo_sim_graph_follows_new_model():
+    """After rs_topo_sim_init with another rewiring interval the recorded
+    launches are replaced: replays equal direct 5-step calls under the new model."""
+    cfg, model = CASES["hot-L16-blob"]
+    m2 = rb.TopoModel(f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.02, rewire_steps=5)
+    a = rb.TopoNet(cfg)
+    a.sim_init(model)
+    a.run(640)
+    a.sim_init(m2)
+    ln, ind, w = a.get_rows()
+    b = rb.TopoNet(cfg)
+    b.set_rows(ln, ind, w)
+    b.sim_init(m2)
+    a.run(320 * 4)
+    for _ in range(256):
+        b.run(5)
+    _same_state(a, b)
+
+
 def test_topo_sim_uses_rows_set_by_caller():
     """Rows replaced through set_rows (a new column layout) drive both delivery
     and potentiation of the next run."""
