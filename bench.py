@@ -256,7 +256,7 @@ def topo_rewire_latency(n_rewires=200):
     return out
 
 
-def topo_sim_leg(steps=100_000, oracle_steps=5000, stim="bar"):
+def topo_sim_leg(steps=1_000_000, oracle_steps=5000, stim="bar"):
     """The topographic map end to end (64 x 64 Poisson sheet -> 64 x 64
     conductance-LIF sheet, cap 32, STDP, 160 rewiring attempts every 10 steps,
     h = 0.1 ms), from a fresh build: realtime factor, steps/s, and the split
@@ -330,7 +330,8 @@ def main():
                     help="run only the tiny-network leg and print its figures (for profiling)")
     ap.add_argument("--only-topo", action="store_true",
                     help="run only the topographic-map end-to-end leg and print its figures (for profiling)")
-    ap.add_argument("--topo-steps", type=int, default=100_000)
+    ap.add_argument("--topo-steps", type=int, default=1_000_000,
+                    help="steps of the topographic-map leg (default 10^6 = 100 s of model time)")
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the classifier's forward pass, without learning (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,

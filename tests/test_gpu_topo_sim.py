@@ -98,6 +98,16 @@ CASES = {
                                  g_init=0.5, seed=5),
                    rb.TopoModel(f_peak=600.0, g_max=0.5, stdp=0, rewire_steps=7)),
     "paper-L64": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, seed=9), rb.TopoModel()),
+    # the largest map, driven, bar stimulus moving every 5 ms
+    "hot-L64-bar": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, g_theta=0.25, g_new=0.5, g_init=0.5,
+                                  seed=10),
+                    rb.TopoModel(f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.01875, stim_kind=rb.STIM_BAR,
+                                 stim_steps=50)),
+    # 36 neurons: the last generator call covers 4 channels beyond the sheet, bit words end mid-word
+    "ragged-L6": (rb.TopoConfig(L=6, cap=8, n_attempts=5, proj_id=3, p_form=0.6, sigma_form=1.5, g_theta=0.25,
+                                g_new=0.5, g_init=0.5, seed=12),
+                  rb.TopoModel(f_base=200.0, f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.02, stim_steps=30,
+                               ref_steps=7, rewire_steps=3)),
 }
 
 
@@ -121,7 +131,7 @@ def test_topo_sim_lockstep_matches_oracle(name):
         changed += st.eliminated + st.formed
         compare(t, cfg, M, P, S)
         spikes = int(S.count.sum())
-    if cfg.L < 64:
+    if name != "paper-L64":
         assert spikes > 0
         assert changed > 0
 
