@@ -1144,6 +1144,7 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   d.es = (float)std::exp(-(double)m->h / (double)m->tau_s);
   d.dx = (float)std::exp(-(double)m->h / (double)m->tau_plus);
   d.dy = (float)std::exp(-(double)m->h / (double)m->tau_minus);
+  d.inv_dx = (float)(1.0 / (double)d.dx);
   d.A_plus = m->A_plus;
   d.A_minus = m->A_minus;
   d.g_max = m->g_max;

@@ -11,7 +11,10 @@
 // edit them between launches).
 //
 // One step t (the order of the model readings):
-//   A  decay the STDP traces x (source) and y (target) by exp(-h/tau)
+//   A  decay the STDP traces x (source) and y (target) by exp(-h/tau); done
+//      for the first step of a launch only, the others take it at the end of
+//      phase C of the step before (y then also takes the step's spikes, and
+//      potentiation reads x through 1/exp(-h/tau_+)), which saves a barrier
 //   B  deliver the spikes drawn at t-1 (delay t_d = h): one wave per spiking
 //      source, a lane per synapse adds its weight to the target's conductance
 //      (64-bit fixed point in LDS, so the sum does not depend on the order of
@@ -25,7 +28,7 @@
 //      Euler with the synaptic current held over the step, threshold, reset,
 //      refractory count, g decay; spiking targets are listed
 //   D  potentiation: one wave per spiking target walks its column (the
-//      synapses onto it) and adds A_+ x_source, clipped to g_max; y += 1
+//      synapses onto it) and adds A_+ x_source, clipped to g_max
 // The column view (slot indices grouped by target) is rebuilt at the start of
 // a launch only when the rows changed since the last build (the rewiring
 // kernels raise a flag), so an interval in which no synapse was formed or
@@ -158,24 +161,21 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
 
   const int L = sd.L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
   uint64_t thr[8];  // this thread's source thresholds for the current stimulus epoch
+  // ---- A of the first step: trace decay, stimulus position.  Later steps
+  // decay their traces at the end of the step before (phase C).
+  for (int j = tid; j < N; j += TS_NT) {
+    x[j] *= sd.dx;
+    y[j] *= sd.dy;
+  }
+  if (tid < 3) {
+    const uint32_t u = draw_u32(seed, TAG_STIM, 0, t0 / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
+    s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
+  }
+  __syncthreads();
   for (int k = 0; k < n_steps; ++k) {
     const uint64_t t = t0 + (uint64_t)k;
     const int cb = k & 1, nb = cb ^ 1;
-    // ---- A: trace decay; stimulus position for this step's epoch
-    for (int j = tid; j < N; j += TS_NT) {
-      x[j] *= sd.dx;
-      y[j] *= sd.dy;
-    }
-    if (tid < 3 && (k == 0 || t % (uint64_t)sd.stim_steps == 0)) {
-      const uint64_t e = t / (uint64_t)sd.stim_steps;
-      const uint32_t u = draw_u32(seed, TAG_STIM, 0, e, (uint64_t)tid, 0, 0);
-      s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
-    }
-    if (tid == 0) {
-      s_npre[nb] = 0;
-      s_npost = 0;
-    }
-    __syncthreads();
+    if (tid == 0) s_npost = 0;  // D of the step before read it before the barrier
     // ---- B: delivery with depression, one wave per spiking source from wave 0
     // up; every slot of the padded row is loaded together with the row length.
     // Meanwhile the upper half of the workgroup draws this step's source spikes,
@@ -261,6 +261,11 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
         }
         Vr[m] = v;
         gr[m] = gj * sd.es;
+        // traces: y += z now (potentiation does not read y), and both traces
+        // take the next step's decay, except after a launch's last step
+        const float yz = y[j] + (z ? 1.f : 0.f);
+        y[j] = last ? yz : yz * sd.dy;
+        if (!last) x[j] *= sd.dx;
       }
       if (last && m * TS_NT < N) {
         const uint64_t mz = ballot(z);
@@ -269,21 +274,28 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
         if (lane == 0 && w0 + 1 < words) sd.zout[w0 + 1] = (uint32_t)(mz >> 32);
       }
     }
+    if (tid == 0) s_npre[cb] = 0;  // the list step k+1 draws into; read at the start of B
     __syncthreads();
-    // ---- D: potentiation along the columns of spiking targets
+    // ---- D: potentiation along the columns of spiking targets.  x already
+    // carries the next step's decay unless this is the launch's last step.
     const int npost = s_npost;
+    const float xs = last ? 1.f : sd.inv_dx;
     if (sd.stdp) {
       for (int q = wv; q < npost; q += TS_NT / WAVE) {
         const int j = post[q];
         const int e0 = coff[j], e1 = coff[j + 1];
         for (int e = e0 + lane; e < e1; e += WAVE) {
           const int slot = sd.col_ent[e];
-          const float w = P.w[slot] + sd.A_plus * x[slot / cap];
+          const float w = P.w[slot] + sd.A_plus * (x[slot / cap] * xs);
           P.w[slot] = fminf(w, sd.g_max);
         }
       }
     }
-    for (int q = tid; q < npost; q += TS_NT) y[post[q]] += 1.f;
+    // stimulus position of the next step's epoch
+    if (tid < 3 && !last && (t + 1) % (uint64_t)sd.stim_steps == 0) {
+      const uint32_t u = draw_u32(seed, TAG_STIM, 0, (t + 1) / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
+      s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
+    }
     __syncthreads();
   }
 #pragma unroll

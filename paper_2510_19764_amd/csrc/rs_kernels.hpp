@@ -159,7 +159,7 @@ void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t
 // Topographic-map simulation state and constants (model of Tab. B, D-F).
 struct TopoSimDev {
   int L, N, n_d2, ref_steps, stim_steps, stim_kind, stdp;
-  float V_rest, E_exc, V_th, V_reset, R, em, es, dx, dy, A_plus, A_minus, g_max;
+  float V_rest, E_exc, V_th, V_reset, R, em, es, dx, dy, inv_dx, A_plus, A_minus, g_max;
   const uint64_t* T_in;   // [2*(L/2)^2 + 1] input Bernoulli threshold by squared stimulus distance
   float *V, *g, *y, *x;   // [N]
   int* ref;               // [N]
