@@ -43,6 +43,7 @@ constexpr int TS_MAX_N = 4096;
 constexpr int TS_PER = TS_MAX_N / TS_NT;  // target neurons owned by each thread
 static_assert(TS_MAX_N / 8 <= TS_NT / 2, "the upper half of the workgroup draws every source group");
 static_assert((TS_NT / 2) % WAVE == 0, "drawing threads form whole waves");
+static_assert(TS_MAX_N / 32 <= TS_NT, "one thread per word of source spike bits");
 
 // acc (int64), y, x (float), two source lists and the target list, column
 // offsets [N+1] (int)
@@ -120,19 +121,10 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
   __shared__ int s_npre[2], s_npost;
   __shared__ int s_stim[3];
 
-  if (*sd.col_dirty) {  // uniform: one value read by every thread
-    topo_columns(P, sd, (int*)acc, (int*)acc + N, part, coff);
-    if (tid == 0) *sd.col_dirty = 0;
-  } else {
-    for (int j = tid; j <= N; j += TS_NT) coff[j] = sd.col_off[j];
-  }
-  for (int j = tid; j < N; j += TS_NT) {
-    acc[j] = 0;
-    y[j] = sd.y[j];
-    x[j] = sd.x[j];
-  }
-  // target neurons j = tid + m*TS_NT live in registers for the launch
-  float Vr[TS_PER], gr[TS_PER];
+  // Every load of the launch's starting state is issued before any of it is
+  // used, so the prologue costs one memory round trip (two with a rebuild).
+  const int dirty = *sd.col_dirty;  // uniform: one value read by every thread
+  float Vr[TS_PER], gr[TS_PER], xr[TS_PER], yr[TS_PER];  // target neurons j = tid + m*TS_NT
   int refr[TS_PER];
   uint32_t cnt[TS_PER];
 #pragma unroll
@@ -143,34 +135,44 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     gr[m] = ok ? sd.g[j] : 0.f;
     refr[m] = ok ? sd.ref[j] : 0;
     cnt[m] = ok ? sd.count[j] : 0u;
+    xr[m] = ok ? sd.x[j] : 0.f;
+    yr[m] = ok ? sd.y[j] : 0.f;
+  }
+  const int words = (N + 31) / 32;  // <= TS_NT
+  uint32_t zw = tid < words ? sd.zin[tid] : 0u;  // spikes drawn at the step before t0
+  const int L = sd.L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
+  if (tid < 3) {  // stimulus position of t0's epoch
+    const uint32_t u = draw_u32(seed, TAG_STIM, 0, t0 / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
+    s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
   }
   if (tid == 0) {
     s_npre[0] = 0;
     s_npre[1] = 0;
   }
-  __syncthreads();
-  // spikes drawn at the step before t0 (a bit per source)
-  for (int w = tid; w < (N + 31) / 32; w += TS_NT) {
-    uint32_t m = sd.zin[w];
-    while (m) {
-      const int b = __builtin_ctz(m);
-      m &= m - 1;
-      pre0[atomicAdd(&s_npre[0], 1)] = w * 32 + b;
+  if (dirty) {
+    topo_columns(P, sd, (int*)acc, (int*)acc + N, part, coff);
+    if (tid == 0) *sd.col_dirty = 0;
+  } else {
+    for (int j = tid; j <= N; j += TS_NT) coff[j] = sd.col_off[j];
+  }
+  // ---- A of the first step: trace decay.  Later steps decay their traces at
+  // the end of the step before (phase C).
+#pragma unroll
+  for (int m = 0; m < TS_PER; ++m) {
+    const int j = tid + m * TS_NT;
+    if (j < N) {
+      acc[j] = 0;
+      x[j] = xr[m] * sd.dx;
+      y[j] = yr[m] * sd.dy;
     }
   }
-
-  const int L = sd.L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
+  __syncthreads();
+  while (zw) {
+    const int b = __builtin_ctz(zw);
+    zw &= zw - 1;
+    pre0[atomicAdd(&s_npre[0], 1)] = tid * 32 + b;
+  }
   uint64_t thr[8];  // this thread's source thresholds for the current stimulus epoch
-  // ---- A of the first step: trace decay, stimulus position.  Later steps
-  // decay their traces at the end of the step before (phase C).
-  for (int j = tid; j < N; j += TS_NT) {
-    x[j] *= sd.dx;
-    y[j] *= sd.dy;
-  }
-  if (tid < 3) {
-    const uint32_t u = draw_u32(seed, TAG_STIM, 0, t0 / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
-    s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
-  }
   __syncthreads();
   for (int k = 0; k < n_steps; ++k) {
     const uint64_t t = t0 + (uint64_t)k;
