@@ -922,6 +922,7 @@ void topo_drop_graph(rs_topo* t) {
 }
 
 rs_status topo_build_graph(rs_topo* t) {
+  topo_drop_graph(t);  // a failed earlier attempt may have left a graph without its instance
   const int R = (int)t->m.rewire_steps;
   topo_sim_attrs();
   topo_rewire_attrs();
