@@ -90,11 +90,12 @@ HOT = rb.TopoModel(f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.05 * 1.2 * 20
 CASES = {
     "hot-L16-blob": (rb.TopoConfig(L=16, cap=32, n_attempts=10, proj_id=0, g_theta=0.25, g_new=0.5,
                                    g_init=0.5, seed=3), HOT),
-    "hot-L20-bar": (rb.TopoConfig(L=20, cap=24, n_attempts=40, proj_id=2, g_theta=0.25, g_new=0.5,
+    # capacities above 32 and not a multiple of 4
+    "hot-L20-bar": (rb.TopoConfig(L=20, cap=40, n_attempts=40, proj_id=2, g_theta=0.25, g_new=0.5,
                                   g_init=0.5, seed=4),
                     rb.TopoModel(f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.01875, stim_kind=rb.STIM_BAR,
                                  stim_steps=50)),
-    "nostdp-L12": (rb.TopoConfig(L=12, cap=16, n_attempts=10, proj_id=1, g_theta=0.25, g_new=0.5,
+    "nostdp-L12": (rb.TopoConfig(L=12, cap=18, n_attempts=10, proj_id=1, g_theta=0.25, g_new=0.5,
                                  g_init=0.5, seed=5),
                    rb.TopoModel(f_peak=600.0, g_max=0.5, stdp=0, rewire_steps=7)),
     "paper-L64": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, seed=9), rb.TopoModel()),
