@@ -1131,7 +1131,6 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   t->m = *m;
   d.L = L;
   d.N = N;
-  d.n_d2 = n_d2;
   d.ref_steps = (int)m->ref_steps;
   d.stim_steps = (int)m->stim_steps;
   d.stim_kind = m->stim_kind;

@@ -32,7 +32,9 @@
 // The column view (slot indices grouped by target) is rebuilt at the start of
 // a launch only when the rows changed since the last build (the rewiring
 // kernels raise a flag), so an interval in which no synapse was formed or
-// eliminated skips the remap.
+// eliminated skips the remap.  Launched from a recorded graph, the kernel
+// takes its first step from device memory (STEP_FROM_DEVICE) and every launch
+// writes the step count it reached back.
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -47,8 +49,7 @@ static_assert(TS_MAX_N / 32 <= TS_NT, "one thread per word of source spike bits"
 
 // acc (int64), y, x (float), two source lists and the target list, column
 // offsets [N+1] (int)
-size_t topo_sim_lds_bytes(int N, int n_d2) {
-  (void)n_d2;
+size_t topo_sim_lds_bytes(int N) {
   return (size_t)N * (8 + 4 + 4 + 4 + 4 + 4) + ((size_t)N + 1) * 4;
 }
 
@@ -328,7 +329,7 @@ void topo_sim_attrs() {
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
                      int n_steps) {
   topo_sim_attrs();
-  hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N, sd.n_d2), s, seed, P, sd, t0,
+  hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N), s, seed, P, sd, t0,
                      n_steps);
 }
 

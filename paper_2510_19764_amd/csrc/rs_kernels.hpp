@@ -158,7 +158,7 @@ void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t
 
 // Topographic-map simulation state and constants (model of Tab. B, D-F).
 struct TopoSimDev {
-  int L, N, n_d2, ref_steps, stim_steps, stim_kind, stdp;
+  int L, N, ref_steps, stim_steps, stim_kind, stdp;
   float V_rest, E_exc, V_th, V_reset, R, em, es, dx, dy, inv_dx, A_plus, A_minus, g_max;
   const uint64_t* T_in;   // [2*(L/2)^2 + 1] input Bernoulli threshold by squared stimulus distance
   float *V, *g, *y, *x;   // [N]
@@ -170,7 +170,7 @@ struct TopoSimDev {
   uint64_t* step_dev;     // [1] step count: read for t0 == STEP_FROM_DEVICE, written at the end
 };
 bool topo_sim_fits(int N);
-size_t topo_sim_lds_bytes(int N, int n_d2);
+size_t topo_sim_lds_bytes(int N);
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
                      int n_steps);
 // Set the kernels' launch attributes ahead of a stream capture (idempotent).
