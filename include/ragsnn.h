@@ -270,7 +270,7 @@ rs_status rs_topo_create(const rs_topo_params* params, void* hip_stream, rs_topo
 rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* stats);
 /* Row access, host buffers: len int32[n_pre], ind int32[n_pre][cap],
  * w float[n_pre][cap].  Synchronise.  Errors: RS_EINVAL (len beyond cap,
- * index out of range or |w| > 1e4 on set). */
+ * index out of range, a target twice in one row or |w| > 1e4 on set). */
 rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w);
 rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w);
 /* The attempt bitfield uint32[n_pre][ceil(n_post/32)] (all zero between updates). */

@@ -1065,6 +1065,9 @@ rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, c
       const float wk = w[(size_t)i * P.cap + k];
       if (!(std::fabs(wk) <= TOPO_W_MAX)) return fail(RS_EINVAL, "row %d slot %d weight outside +-1e4", i, k);
     }
+    std::vector<int32_t> r(ind + (size_t)i * P.cap, ind + (size_t)i * P.cap + len[i]);
+    std::sort(r.begin(), r.end());
+    if (std::adjacent_find(r.begin(), r.end()) != r.end()) return fail(RS_EINVAL, "row %d holds a target twice", i);
   }
   const size_t n = (size_t)P.n_pre * P.cap;
   HIP_OK(hipStreamSynchronize(t->stream));
@@ -1121,8 +1124,8 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
     TRY(ar.alloc(&d.count, (size_t)N));
     TRY(ar.alloc(&d.zin, (size_t)words));
     TRY(ar.alloc(&d.zout, (size_t)words));
-    TRY(ar.alloc(&d.col_off, (size_t)N + 1));
-    TRY(ar.alloc(&d.col_ent, (size_t)N * t->t.P.cap));
+    TRY(ar.alloc(&d.col_len, (size_t)N));
+    TRY(ar.alloc(&d.col_ent, (size_t)N * N));
     TRY(ar.alloc(&T_in, (size_t)n_d2));
     TRY(ar.alloc(&t->step_dev, 1));
     d.T_in = T_in;
@@ -1151,6 +1154,10 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   d.col_dirty = t->t.col_dirty;
   d.step_dev = t->step_dev;
   t->t.step_dev = t->step_dev;
+  d.col_cap = N;
+  t->t.col_len = d.col_len;  // from here on the rewire edits the simulation's column view
+  t->t.col_ent = d.col_ent;
+  t->t.col_cap = N;
   // Bernoulli threshold of one step of the source's Poisson train, by the
   // integer squared distance from the stimulus (Tab. E rate profile)
   std::vector<uint64_t> T(n_d2);

@@ -45,6 +45,25 @@ __device__ __forceinline__ int torus_d2_t(int L, int i, int j) {
   return dx * dx + dy * dy;
 }
 
+// Column view of an attached simulation: column j holds col_len[j] slot
+// indices at col_ent[j*col_cap ...]; -1 marks a removed synapse.  Entries of
+// one row are only ever touched by the wave rewiring that row, and appends
+// take their place by an atomic, so concurrent rows do not conflict.
+__device__ void col_rename(const TopoDev& t, int j, int from, int to) {
+  int* col = t.col_ent + (int64_t)j * t.col_cap;
+  const int n = min(t.col_len[j], t.col_cap);
+  for (int k = 0; k < n; ++k)
+    if (col[k] == from) {
+      col[k] = to;
+      return;
+    }
+}
+__device__ void col_append(const TopoDev& t, int j, int slot) {
+  const int pos = atomicAdd(&t.col_len[j], 1);
+  if (pos < t.col_cap) t.col_ent[(int64_t)j * t.col_cap + pos] = slot;
+  else *t.col_dirty = 1;  // full column: the next simulation launch rebuilds the view
+}
+
 // Rewire row r, which received kr attempts, as one wave.  smem holds the
 // row's bitfield section, kr candidates and the compaction plan.
 __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, int r, int kr,
@@ -99,12 +118,19 @@ __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, 
     remf[s] = rem;
   }
   __syncthreads();
+  // the simulation's column view: removed synapses leave a tombstone
+  if (t.col_len)
+    for (int s = lane; s < n; s += WAVE)
+      if (remf[s]) col_rename(t, P.ind[base + s], (int)(base + s), -1);
+  __syncthreads();
   int n2;
   const int pairs = wave_compaction_plan(n, remf, holes, tail, &n2);
   for (int p = lane; p < pairs; p += WAVE) {
     const int64_t d = base + holes[p], s = base + tail[p];
-    P.ind[d] = P.ind[s];
+    const int j = P.ind[s];
+    P.ind[d] = j;
     P.w[d] = P.w[s];
+    if (t.col_len) col_rename(t, j, (int)s, (int)d);  // moved synapses keep their entry
   }
   __syncthreads();
   // formation attempts on the remaining candidates, ascending target order
@@ -126,6 +152,7 @@ __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, 
         if (len < P.cap) {
           P.ind[base + len] = j;
           P.w[base + len] = t.g_new;
+          if (t.col_len) col_append(t, j, (int)(base + len));
           ++len;
           ++formed;
         } else {
@@ -134,7 +161,7 @@ __device__ void topo_rewire_row(uint64_t seed, const TopoDev& t, uint64_t step, 
       }
     }
     P.len[r] = len;
-    if (t.col_dirty && (n > n2 || formed)) *t.col_dirty = 1;
+    if (t.col_dirty && !t.col_len && (n > n2 || formed)) *t.col_dirty = 1;
     if (n > n2) atomicAdd((unsigned long long*)&t.stats[0], (unsigned long long)(n - n2));
     if (formed) atomicAdd((unsigned long long*)&t.stats[1], (unsigned long long)formed);
     if (blocked) atomicAdd((unsigned long long*)&t.stats[2], (unsigned long long)blocked);

@@ -29,10 +29,10 @@
 //      refractory count, g decay; spiking targets are listed
 //   D  potentiation: one wave per spiking target walks its column (the
 //      synapses onto it) and adds A_+ x_source, clipped to g_max
-// The column view (slot indices grouped by target) is rebuilt at the start of
-// a launch only when the rows changed since the last build (the rewiring
-// kernels raise a flag), so an interval in which no synapse was formed or
-// eliminated skips the remap.  Launched from a recorded graph, the kernel
+// The column view (slot indices grouped by target, one padded column per
+// target) is kept up to date by the rewiring kernels, which know every slot
+// they remove, move or fill; it is rebuilt from the rows at the start of a
+// launch only after the build, a restore of rows or a full column.  Launched from a recorded graph, the kernel
 // takes its first step from device memory (STEP_FROM_DEVICE) and every launch
 // writes the step count it reached back.
 #include "rs_device.hpp"
@@ -47,10 +47,10 @@ static_assert(TS_MAX_N / 8 <= TS_NT / 2, "the upper half of the workgroup draws 
 static_assert((TS_NT / 2) % WAVE == 0, "drawing threads form whole waves");
 static_assert(TS_MAX_N / 32 <= TS_NT, "one thread per word of source spike bits");
 
-// acc (int64), y, x (float), two source lists and the target list, column
-// offsets [N+1] (int)
+// acc (int64), y, x (float), two source lists, the target list and the
+// column lengths (int)
 size_t topo_sim_lds_bytes(int N) {
-  return (size_t)N * (8 + 4 + 4 + 4 + 4 + 4) + ((size_t)N + 1) * 4;
+  return (size_t)N * (8 + 4 + 4 + 4 + 4 + 4 + 4);
 }
 
 bool topo_sim_fits(int N) { return N >= 1 && N <= TS_MAX_N; }
@@ -60,50 +60,26 @@ __device__ __forceinline__ int axis_dist(int L, int a, int b) {
   return min(d, L - d);
 }
 
-// Rebuild the column view: col_off[j]..col_off[j+1] lists the slots i*cap+s
-// whose target is j (written to HBM and to the LDS copy coff).  cnt and cur
-// are LDS scratch of N ints each.
-__device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* cnt, int* cur, int* part, int* coff) {
+// Rebuild the column view from the rows: column j lists at col_ent[j*col_cap]
+// the slot indices i*cap+s of the col_len[j] synapses onto j (the LDS copy
+// clen holds the lengths).  Needed only after the build, a restore of rows or
+// a full column; otherwise the rewiring kernels edit the view in place.  A row
+// holds each target at most once, so no column exceeds N = col_cap entries.
+__device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* clen) {
   const int N = sd.N, tid = threadIdx.x;
-  for (int j = tid; j < N; j += TS_NT) cnt[j] = 0;
-  __syncthreads();
-  for (int i = tid; i < N; i += TS_NT) {
-    const int n = P.len[i];
-    const int* ind = P.ind + (int64_t)i * P.cap;
-    for (int s = 0; s < n; ++s) atomicAdd(&cnt[ind[s]], 1);
-  }
-  __syncthreads();
-  // exclusive scan of cnt: each thread sums a contiguous chunk, then a
-  // Hillis-Steele scan over the 1024 chunk sums
-  const int per = (N + TS_NT - 1) / TS_NT, lo = min(tid * per, N), hi = min(lo + per, N);
-  int sum = 0;
-  for (int j = lo; j < hi; ++j) sum += cnt[j];
-  part[tid] = sum;
-  __syncthreads();
-  for (int off = 1; off < TS_NT; off <<= 1) {
-    const int v = tid >= off ? part[tid - off] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = part[tid] - sum;
-  for (int j = lo; j < hi; ++j) {
-    sd.col_off[j] = run;
-    coff[j] = run;
-    cur[j] = run;
-    run += cnt[j];
-  }
-  if (tid == TS_NT - 1) {
-    sd.col_off[N] = part[TS_NT - 1];
-    coff[N] = part[TS_NT - 1];
-  }
+  for (int j = tid; j < N; j += TS_NT) clen[j] = 0;
   __syncthreads();
   for (int i = tid; i < N; i += TS_NT) {
     const int n = P.len[i];
     const int64_t base = (int64_t)i * P.cap;
-    for (int s = 0; s < n; ++s) sd.col_ent[atomicAdd(&cur[P.ind[base + s]], 1)] = (int)(base + s);
+    for (int s = 0; s < n; ++s) {
+      const int j = P.ind[base + s];
+      const int pos = atomicAdd(&clen[j], 1);
+      if (pos < sd.col_cap) sd.col_ent[(int64_t)j * sd.col_cap + pos] = (int)(base + s);
+    }
   }
   __syncthreads();
+  for (int j = tid; j < N; j += TS_NT) sd.col_len[j] = clen[j];
 }
 
 __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, TopoSimDev sd, uint64_t t0,
@@ -117,8 +93,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
   int* pre0 = (int*)(x + N);                  // [N] source lists: this step's deliveries and
   int* pre1 = pre0 + N;                       // [N]   the next step's, alternating
   int* post = pre1 + N;                       // [N] targets that spiked this step
-  int* coff = post + N;                       // [N+1] column offsets
-  __shared__ int part[TS_NT];
+  int* clen = post + N;                       // [N] column lengths
   __shared__ int s_npre[2], s_npost;
   __shared__ int s_stim[3];
 
@@ -151,10 +126,10 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     s_npre[1] = 0;
   }
   if (dirty) {
-    topo_columns(P, sd, (int*)acc, (int*)acc + N, part, coff);
+    topo_columns(P, sd, clen);
     if (tid == 0) *sd.col_dirty = 0;
   } else {
-    for (int j = tid; j <= N; j += TS_NT) coff[j] = sd.col_off[j];
+    for (int j = tid; j < N; j += TS_NT) clen[j] = min(sd.col_len[j], sd.col_cap);
   }
   // ---- A of the first step: trace decay.  Later steps decay their traces at
   // the end of the step before (phase C).
@@ -286,9 +261,10 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     if (sd.stdp) {
       for (int q = wv; q < npost; q += TS_NT / WAVE) {
         const int j = post[q];
-        const int e0 = coff[j], e1 = coff[j + 1];
-        for (int e = e0 + lane; e < e1; e += WAVE) {
-          const int slot = sd.col_ent[e];
+        const int* col = sd.col_ent + (int64_t)j * sd.col_cap;
+        for (int e = lane; e < clen[j]; e += WAVE) {
+          const int slot = col[e];
+          if (slot < 0) continue;  // removed by a rewire
           const float w = P.w[slot] + sd.A_plus * (x[slot / cap] * xs);
           P.w[slot] = fminf(w, sd.g_max);
         }

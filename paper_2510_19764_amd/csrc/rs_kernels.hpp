@@ -150,6 +150,10 @@ struct TopoDev {
   long long* stats;       // [4]
   int* col_dirty;         // [1] set to 1 when a rewire changes any row; may be null
   const uint64_t* step_dev;  // [1] step count, read when a launch passes STEP_FROM_DEVICE
+  // column view of an attached simulation, edited by the rewire; null without one
+  int* col_len;           // [n_post]
+  int* col_ent;           // [n_post][col_cap]
+  int col_cap;
 };
 // Step argument telling a topographic-map kernel to read the step count from
 // device memory (launches recorded once in a graph and replayed).
@@ -165,7 +169,8 @@ struct TopoSimDev {
   int* ref;               // [N]
   uint32_t* count;        // [N]
   uint32_t *zin, *zout;   // [ceil(N/32)] bits
-  int *col_off, *col_ent; // [N+1], [N*cap]
+  int *col_len, *col_ent; // [N], [N][col_cap]: column j's slot indices, -1 for removed synapses
+  int col_cap;            // N: no target can have more synapses than there are rows
   int* col_dirty;         // [1]
   uint64_t* step_dev;     // [1] step count: read for t0 == STEP_FROM_DEVICE, written at the end
 };

@@ -262,3 +262,8 @@ def test_topo_sim_errors():
         t.sim_set(rb.TV_REF, np.full(64, -1, np.int32))
     t.run(25)
     assert int(t.sim_get(rb.TV_STEP)[0]) == 25
+    ln, ind, w = t.get_rows()
+    i = int(np.argmax(ln))
+    ind[i, 1] = ind[i, 0]  # a target twice in one row
+    with pytest.raises(RuntimeError, match="twice"):
+        t.set_rows(ln, ind, w)
