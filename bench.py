@@ -289,6 +289,18 @@ def topo_sim_leg(steps=1_000_000, oracle_steps=5000, stim="bar"):
         st = t.run_stats()
         n_syn = int(t.get_rows()[0].sum())
         spikes = int(t.sim_get(rb.TV_COUNT).sum())
+        if R:
+            # the Fig. 10 style split, from the kernel's phase timers over 100000 further steps
+            n_ph = 100_000
+            t.sim_timing(True)
+            t.run(n_ph)
+            torch.cuda.synchronize()
+            ph = t.sim_phase_ms()
+            tot = t.last_ms()
+            t.sim_timing(False)
+            split = {k: round(1e3 * v / n_ph, 3) for k, v in ph.items()}
+            split["rewire_kernels_and_launch_gaps"] = round(1e3 * (tot - sum(ph.values())) / n_ph, 3)
+            out["phase_us_per_step"] = split
         t.close()
         out[name] = {"wall_s": round(el, 4), "device_ms": round(dev_ms, 3),
                      "steps_per_s": round(steps / el, 1), "us_per_step": round(1e6 * el / steps, 3),

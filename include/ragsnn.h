@@ -333,6 +333,18 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m);
 rs_status rs_topo_run(rs_topo* t, uint64_t n_steps);
 /* Summed rewire statistics of the last rs_topo_run.  Synchronises. */
 rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* stats);
+/* Per-phase timers of the simulation kernel, in the manner of the paper's
+ * Fig. 10 split: one thread reads the device wall clock at each phase
+ * boundary.  on != 0 enables them, 0 disables them; either way the
+ * accumulated times restart from zero.  Timing changes no result.
+ * Synchronises.  Errors: RS_ESTATE before rs_topo_sim_init. */
+rs_status rs_topo_sim_timing(rs_topo* t, int32_t on);
+/* Milliseconds accumulated per phase since the last rs_topo_sim_timing:
+ * ms[0] delivery with the source draws, ms[1] neuron update, ms[2]
+ * potentiation, ms[3] launch prologue (state loads and any column rebuild).
+ * The rewire kernels and launch gaps make up the rest of rs_topo_last_ms.
+ * Synchronises.  Errors: RS_ESTATE before rs_topo_sim_init, RS_EDEVICE. */
+rs_status rs_topo_sim_phase_ms(rs_topo* t, double ms[4]);
 /* Simulation variables, host buffers of exactly the stated size.  Synchronise. */
 enum {
   RS_TV_V = 0,      /* float[L*L] target membrane potential, mV */

@@ -85,7 +85,7 @@ EXPORTS = [
     "rs_eprop_timing", "rs_eprop_phase_times", "rs_eprop_destroy",
     "rs_topo_create", "rs_topo_rewire", "rs_topo_get_rows", "rs_topo_set_rows", "rs_topo_get_bits",
     "rs_topo_last_ms", "rs_topo_destroy", "rs_topo_sim_init", "rs_topo_run", "rs_topo_run_stats",
-    "rs_topo_sim_get", "rs_topo_sim_set", "rs_calib_copy",
+    "rs_topo_sim_get", "rs_topo_sim_set", "rs_topo_sim_timing", "rs_topo_sim_phase_ms", "rs_calib_copy",
 ]
 
 _lib = None
@@ -131,6 +131,8 @@ def lib():
         L.rs_topo_run_stats.argtypes = [vp, C.POINTER(_Stats)]
         L.rs_topo_sim_get.argtypes = [vp, C.c_int32, vp, C.c_size_t]
         L.rs_topo_sim_set.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_topo_sim_timing.argtypes = [vp, C.c_int32]
+        L.rs_topo_sim_phase_ms.argtypes = [vp, C.POINTER(C.c_double)]
         L.rs_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
         for name in EXPORTS:
             f = getattr(L, name)
@@ -395,6 +397,14 @@ class TopoNet:
         _check(lib().rs_topo_run_stats(self._h, C.byref(st)))
         return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
 
+    def sim_timing(self, on: bool):
+        _check(lib().rs_topo_sim_timing(self._h, 1 if on else 0))
+
+    def sim_phase_ms(self) -> dict:
+        ms = (C.c_double * 4)()
+        _check(lib().rs_topo_sim_phase_ms(self._h, ms))
+        return dict(zip(TOPO_PHASES, ms))
+
     def _var(self, var: int):
         if var == TV_STEP:
             return np.empty(1, np.uint64)
@@ -418,6 +428,7 @@ class TopoNet:
 
 
 STIM_BLOB, STIM_BAR = 0, 1
+TOPO_PHASES = ("delivery_and_source", "neurons", "potentiation", "launch_prologue")
 TV_V, TV_G, TV_Y, TV_X, TV_REF, TV_COUNT, TV_ZIN, TV_ZOUT, TV_STEP = range(9)
 
 

@@ -904,6 +904,7 @@ struct rs_topo {
   TopoSimDev sd{};
   uint64_t step = 0;
   uint64_t* step_dev = nullptr;
+  unsigned long long* ticks = nullptr;  // [TOPO_PHASES] phase timers
   // GRAPH_INTERVALS whole rewiring intervals (simulation + rewire launches)
   // recorded once and replayed; the kernels read the step count from step_dev
   hipStream_t cap_stream = nullptr;
@@ -1128,6 +1129,7 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
     TRY(ar.alloc(&d.col_ent, (size_t)N * N));
     TRY(ar.alloc(&T_in, (size_t)n_d2));
     TRY(ar.alloc(&t->step_dev, 1));
+    TRY(ar.alloc(&t->ticks, (size_t)TOPO_PHASES));
     d.T_in = T_in;
   }
   topo_drop_graph(t);  // the recorded launches carry the old constants
@@ -1177,6 +1179,8 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   launch_fill_zero(s, d.zin, (size_t)words * 4);
   launch_fill_zero(s, d.zout, (size_t)words * 4);
   launch_fill_zero(s, t->step_dev, 8);
+  launch_fill_zero(s, t->ticks, 8 * TOPO_PHASES);
+  d.ticks = nullptr;  // timers off until rs_topo_sim_timing
   static const int one = 1;
   HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, s));
   HIP_OK(hipGetLastError());
@@ -1214,6 +1218,35 @@ rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
   HIP_OK(hipEventRecord(t->ev1, s));
   t->timed = true;
   HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_topo_sim_timing(rs_topo* t, int32_t on) {
+  if (!t) return fail(RS_EINVAL, "NULL argument");
+  if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
+  HIP_OK(hipStreamSynchronize(t->stream));
+  launch_fill_zero(t->stream, t->ticks, 8 * TOPO_PHASES);
+  unsigned long long* want = on ? t->ticks : nullptr;
+  if (t->sd.ticks != want) {
+    t->sd.ticks = want;
+    topo_drop_graph(t);  // the recorded launches carry the old setting
+  }
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
+}
+
+rs_status rs_topo_sim_phase_ms(rs_topo* t, double* ms) {
+  if (!t || !ms) return fail(RS_EINVAL, "NULL argument");
+  if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
+  unsigned long long h[TOPO_PHASES];
+  HIP_OK(hipMemcpyAsync(h, t->ticks, sizeof h, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  int dev = 0, khz = 0;
+  HIP_OK(hipGetDevice(&dev));
+  HIP_OK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(RS_EDEVICE, "the device reports no wall-clock rate");
+  for (int q = 0; q < TOPO_PHASES; ++q) ms[q] = (double)h[q] / (double)khz;
   return RS_OK;
 }
 

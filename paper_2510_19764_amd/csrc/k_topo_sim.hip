@@ -55,6 +55,13 @@ size_t topo_sim_lds_bytes(int N) {
 
 bool topo_sim_fits(int N) { return N >= 1 && N <= TS_MAX_N; }
 
+// Add the wall-clock ticks since `prev` to `acc` and restart from now.
+__device__ __forceinline__ void phase_mark(long long& acc, long long& prev) {
+  const long long now = (long long)wall_clock64();
+  acc += now - prev;
+  prev = now;
+}
+
 __device__ __forceinline__ int axis_dist(int L, int a, int b) {
   const int d = abs(a - b);
   return min(d, L - d);
@@ -86,6 +93,9 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
                                                     int n_steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (t0 == STEP_FROM_DEVICE) t0 = *sd.step_dev;
+  // optional phase timers (Fig. 10 split): thread 0 reads the device wall clock
+  const bool tm = sd.ticks != nullptr && threadIdx.x == 0;
+  long long tprev = tm ? (long long)wall_clock64() : 0, tk[TOPO_PHASES] = {0, 0, 0, 0};
   const int N = sd.N, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   long long* acc = (long long*)smem;          // [N] delivered conductance, fixed point
   float* y = (float*)(acc + N);               // [N] target trace
@@ -150,6 +160,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
   }
   uint64_t thr[8];  // this thread's source thresholds for the current stimulus epoch
   __syncthreads();
+  if (tm) phase_mark(tk[3], tprev);
   for (int k = 0; k < n_steps; ++k) {
     const uint64_t t = t0 + (uint64_t)k;
     const int cb = k & 1, nb = cb ^ 1;
@@ -213,6 +224,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
       }
     }
     __syncthreads();
+    if (tm) phase_mark(tk[0], tprev);
     // ---- C: neurons (registers)
 #pragma unroll
     for (int m = 0; m < TS_PER; ++m) {
@@ -254,6 +266,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     }
     if (tid == 0) s_npre[cb] = 0;  // the list step k+1 draws into; read at the start of B
     __syncthreads();
+    if (tm) phase_mark(tk[1], tprev);
     // ---- D: potentiation along the columns of spiking targets.  x already
     // carries the next step's decay unless this is the launch's last step.
     const int npost = s_npost;
@@ -276,6 +289,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
       s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
     }
     __syncthreads();
+    if (tm) phase_mark(tk[2], tprev);
   }
 #pragma unroll
   for (int m = 0; m < TS_PER; ++m) {
@@ -292,6 +306,8 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     sd.x[j] = x[j];
   }
   if (tid == 0) *sd.step_dev = t0 + (uint64_t)n_steps;
+  if (tm)
+    for (int q = 0; q < TOPO_PHASES; ++q) atomicAdd(&sd.ticks[q], (unsigned long long)tk[q]);
 }
 
 void topo_sim_attrs() {

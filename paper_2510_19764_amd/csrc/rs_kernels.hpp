@@ -173,7 +173,11 @@ struct TopoSimDev {
   int col_cap;            // N: no target can have more synapses than there are rows
   int* col_dirty;         // [1]
   uint64_t* step_dev;     // [1] step count: read for t0 == STEP_FROM_DEVICE, written at the end
+  unsigned long long* ticks;  // [TOPO_PHASES] wall-clock ticks per phase, or null (timers off)
 };
+// Phases of the simulation's timers: delivery with the source draws, neuron
+// update, potentiation, launch prologue (state loads and any column rebuild).
+constexpr int TOPO_PHASES = 4;
 bool topo_sim_fits(int N);
 size_t topo_sim_lds_bytes(int N);
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,

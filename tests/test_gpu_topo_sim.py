@@ -203,6 +203,26 @@ def test_topo_sim_graph_follows_new_model():
     _same_state(a, b)
 
 
+def test_topo_sim_phase_timers():
+    """The per-phase timers change no result, stay within the run's device
+    time, and restart from zero when switched."""
+    cfg, model = CASES["hot-L16-blob"]
+    a, b = rb.TopoNet(cfg), rb.TopoNet(cfg)
+    a.sim_init(model)
+    b.sim_init(model)
+    a.sim_timing(True)
+    a.run(1280 + 35)  # graph replays and direct launches
+    b.run(1280 + 35)
+    _same_state(a, b)
+    ph = a.sim_phase_ms()
+    assert all(v > 0 for v in ph.values()), ph
+    assert sum(ph.values()) <= a.last_ms() * 1.01
+    a.sim_timing(False)
+    assert all(v == 0 for v in a.sim_phase_ms().values())
+    a.run(20)
+    assert all(v == 0 for v in a.sim_phase_ms().values())
+
+
 def test_topo_sim_uses_rows_set_by_caller():
     """Rows replaced through set_rows (a new column layout) drive both delivery
     and potentiation of the next run."""
