@@ -89,12 +89,15 @@ __device__ void topo_columns(const ProjDev& P, const TopoSimDev& sd, int* clen) 
   for (int j = tid; j < N; j += TS_NT) sd.col_len[j] = clen[j];
 }
 
+// TIMED: the phase timers are compiled in (a separate instance, so that the
+// untimed kernel carries none of their registers or branches).
+template <bool TIMED>
 __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, TopoSimDev sd, uint64_t t0,
                                                     int n_steps) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (t0 == STEP_FROM_DEVICE) t0 = *sd.step_dev;
   // optional phase timers (Fig. 10 split): thread 0 reads the device wall clock
-  const bool tm = sd.ticks != nullptr && threadIdx.x == 0;
+  const bool tm = TIMED && threadIdx.x == 0;
   long long tprev = tm ? (long long)wall_clock64() : 0, tk[TOPO_PHASES] = {0, 0, 0, 0};
   const int N = sd.N, tid = threadIdx.x, lane = lane_id(), wv = wave_id();
   long long* acc = (long long*)smem;          // [N] delivered conductance, fixed point
@@ -313,7 +316,8 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
 void topo_sim_attrs() {
   static bool attr_set = false;
   if (!attr_set) {
-    allow_dynamic_lds((const void*)k_topo_sim, 160 * 1024);
+    allow_dynamic_lds((const void*)k_topo_sim<false>, 160 * 1024);
+    allow_dynamic_lds((const void*)k_topo_sim<true>, 160 * 1024);
     attr_set = true;
   }
 }
@@ -321,8 +325,12 @@ void topo_sim_attrs() {
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
                      int n_steps) {
   topo_sim_attrs();
-  hipLaunchKernelGGL(k_topo_sim, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N), s, seed, P, sd, t0,
-                     n_steps);
+  if (sd.ticks)
+    hipLaunchKernelGGL(k_topo_sim<true>, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N), s, seed, P, sd, t0,
+                       n_steps);
+  else
+    hipLaunchKernelGGL(k_topo_sim<false>, dim3(1), dim3(TS_NT), topo_sim_lds_bytes(sd.N), s, seed, P, sd, t0,
+                       n_steps);
 }
 
 }  // namespace rs
