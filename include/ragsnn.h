@@ -9,8 +9,9 @@
  *   - Return value: RS_OK (0) or a negative rs_status.  Arguments are validated
  *     before anything is enqueued, so a call that fails with RS_EINVAL,
  *     RS_ECAPACITY or RS_ESTATE leaves the object unchanged.  RS_EDEVICE reports
- *     a HIP runtime error; the object is then unusable.  rs_last_error()
- *     describes the most recent failure of the calling thread.
+ *     a HIP runtime error; it is sticky: every later call on that object
+ *     returns RS_EDEVICE without enqueuing work (destroy still releases it).
+ *     rs_last_error() describes the most recent failure of the calling thread.
  *   - Ownership: the library allocates and owns all device state of an object
  *     (released by its destroy call).  Buffers passed in belong to the caller;
  *     "device" pointers must stay valid for as long as the call's work may run
@@ -48,8 +49,12 @@ const char* rs_last_error(void);
 typedef struct rs_rewire_stats {
   int64_t eliminated;  /* synapses removed */
   int64_t formed;      /* synapses added */
-  int64_t blocked;     /* formations skipped because the row was full */
-  int64_t attempts;    /* DEEP R: dormant total D; topomap: rewiring attempts */
+  int64_t blocked;     /* topomap: formations skipped because the row was full;
+                          DEEP R: activations for which no row had room (0 while
+                          the rows' capacity exceeds the synapse count) */
+  int64_t attempts;    /* topomap: rewiring attempts; DEEP R: activations
+                          distributed over the rows (the dormant total D less
+                          `blocked`) */
 } rs_rewire_stats;
 
 /* ==========================================================================
@@ -296,10 +301,14 @@ void rs_topo_destroy(rs_topo* t);
  * ref_steps steps held at V_reset); g decays by exp(-h/tau_s); with stdp every
  * synapse onto a target that spiked gains A_plus*x_source (capped at g_max),
  * and y += 1 for it; finally the source draws step t's spikes: channel i fires
- * when u32(INPUT; t, 0, i) < floor(p*2^32), p = (f_base + f_peak*exp(-d2 /
+ * when its 32-bit draw is below floor(p*2^32), p = (f_base + f_peak*exp(-d2 /
  * (2*sigma_stim^2))) * h / 1000, with d2 the squared torus distance of i from
  * the stimulus (blob: a cell; bar: a row or column of cells, distance along
- * the other axis) whose position is redrawn every stim_steps steps.
+ * the other axis) whose position is redrawn every stim_steps steps.  Draws:
+ * one Philox4x64-10 call under key (seed, TP_INPUT = 12) at counter
+ * (t, c, 0, 0) serves channels 8c .. 8c+7; channel 8c + b takes 32-bit half
+ * b of the call's output (word b/2; the upper half for even b, the lower half
+ * for odd b).
  * -------------------------------------------------------------------------- */
 enum { RS_STIM_BLOB = 0, RS_STIM_BAR = 1 };
 

@@ -78,19 +78,20 @@ class _CProj(C.Structure):
                 ("len", P_i32), ("ind", P_i32),
                 ("w", P_f64), ("m", P_f64), ("v", P_f64), ("G", P_f64),
                 ("eps", P_f64), ("ebar", P_f64),
-                ("conn", P_u32), ("sign", P_u32), ("words", C.c_int32)]
+                ("conn", P_u32), ("sign", P_u32), ("words", C.c_int32), ("Gabs", P_f64)]
 
 
 class _CNet(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_rec", C.c_int32), ("n_out", C.c_int32),
                 ("batch", C.c_int32), ("alif", C.c_int32),
                 ("alpha", C.c_double), ("rho", C.c_double), ("v_thr", C.c_double),
-                ("beta", C.c_double), ("alpha_trace", C.c_double),
+                ("beta", C.c_double),
                 ("inp", C.POINTER(_CProj)), ("rec", C.POINTER(_CProj)),
                 ("v", P_f64), ("a", P_f64), ("y", P_f64), ("xbar", P_f64), ("zbar", P_f64),
                 ("Wout", P_f64), ("bout", P_f64), ("Gout", P_f64), ("Gb", P_f64),
                 ("Mout", P_f64), ("Vout", P_f64), ("Mb", P_f64), ("Vb", P_f64),
-                ("psi", P_f64), ("L", P_f64), ("z", P_u8), ("delta", P_f64)]
+                ("psi", P_f64), ("L", P_f64), ("z", P_u8), ("delta", P_f64),
+                ("Labs", P_f64), ("Goutabs", P_f64), ("Gbabs", P_f64)]
 
 
 class _CTopoParams(C.Structure):
@@ -242,6 +243,8 @@ class Proj:
     trained: bool = False
     traces: str = "none"  # "none" | "lif" | "alif"
     bitfields: bool = False
+    # error-bound bookkeeping for tests: Gabs accumulates sum |L ebar| beside G
+    abs_sums: bool = False
     len: np.ndarray = field(init=False)
     ind: np.ndarray = field(init=False)
     w: np.ndarray = field(init=False)
@@ -252,6 +255,7 @@ class Proj:
     ebar: np.ndarray | None = field(init=False, default=None)
     conn: np.ndarray | None = field(init=False, default=None)
     sign: np.ndarray | None = field(init=False, default=None)
+    Gabs: np.ndarray | None = field(init=False, default=None)
 
     def __post_init__(self):
         n = self.n_pre * max(self.cap, 1)
@@ -263,6 +267,8 @@ class Proj:
             self.m = np.zeros(n)
             self.v = np.zeros(n)
             self.G = np.zeros(n)
+            if self.abs_sums:
+                self.Gabs = np.zeros(n)
         if self.traces != "none":
             self.ebar = np.zeros(n * self.batch)
             if self.traces == "alif":
@@ -281,6 +287,7 @@ class Proj:
         s.m, s.v, s.G = _ptr(self.m, P_f64), _ptr(self.v, P_f64), _ptr(self.G, P_f64)
         s.eps, s.ebar = _ptr(self.eps, P_f64), _ptr(self.ebar, P_f64)
         s.conn, s.sign = _ptr(self.conn, P_u32), _ptr(self.sign, P_u32)
+        s.Gabs = _ptr(self.Gabs, P_f64)
         self._c = s  # keep alive
         return s
 
@@ -351,20 +358,12 @@ class EpropParams:
     # explicit decay factors; None derives them from dt and the time constants
     alpha_value: float | None = None
     rho_value: float | None = None
-    # decay of the presynaptic traces; None uses alpha
-    alpha_trace_value: float | None = None
 
     @property
     def alpha(self):
         if self.alpha_value is not None:
             return float(self.alpha_value)
         return float(np.exp(-self.dt_ms / self.tau_mem_ms))
-
-    @property
-    def alpha_trace(self):
-        if self.alpha_trace_value is not None:
-            return float(self.alpha_trace_value)
-        return self.alpha
 
     @property
     def rho(self):
@@ -380,9 +379,11 @@ class EpropParams:
 
 
 class Net:
-    """fp64 e-prop network state; arrays are numpy views the C code updates in place."""
+    """fp64 e-prop network state; arrays are numpy views the C code updates in place.
+    With abs_sums, Labs / Goutabs / Gbabs hold the magnitude sums of the terms of
+    L, Gout and Gb (error-bound bookkeeping for tests)."""
 
-    def __init__(self, prm: EpropParams, inp: Proj, rec: Proj):
+    def __init__(self, prm: EpropParams, inp: Proj, rec: Proj, abs_sums: bool = False):
         self.prm = prm
         B, NR, NI, K = prm.batch, prm.n_rec, prm.n_in, prm.n_out
         self.inp, self.rec = inp, rec
@@ -403,19 +404,23 @@ class Net:
         self.L = np.zeros((B, NR))
         self.z = np.zeros((B, NR), np.uint8)
         self.delta = np.zeros((B, K))
+        self.Labs = np.zeros((B, NR)) if abs_sums else None
+        self.Goutabs = np.zeros((K, NR)) if abs_sums else None
+        self.Gbabs = np.zeros(K) if abs_sums else None
 
     def c(self) -> _CNet:
         p = self.prm
         s = _CNet()
         s.n_in, s.n_rec, s.n_out, s.batch, s.alif = p.n_in, p.n_rec, p.n_out, p.batch, int(p.alif)
         s.alpha, s.rho, s.v_thr, s.beta = p.alpha, p.rho, p.v_thr, p.beta_eff
-        s.alpha_trace = p.alpha_trace
         self._ci, self._cr = self.inp.c(), self.rec.c()
         s.inp, s.rec = C.pointer(self._ci), C.pointer(self._cr)
         for name in ["v", "a", "y", "xbar", "zbar", "Wout", "bout", "Gout", "Gb",
                      "Mout", "Vout", "Mb", "Vb", "psi", "L", "delta"]:
             setattr(s, name, _ptr(getattr(self, name), P_f64))
         s.z = _ptr(self.z, P_u8)
+        s.Labs, s.Goutabs, s.Gbabs = (_ptr(self.Labs, P_f64), _ptr(self.Goutabs, P_f64),
+                                      _ptr(self.Gbabs, P_f64))
         self._c = s
         return s
 

@@ -41,6 +41,7 @@ static void move_record(orc_proj *P, int32_t B, int64_t to, int64_t from)
     if (P->m) P->m[to] = P->m[from];
     if (P->v) P->v[to] = P->v[from];
     if (P->G) P->G[to] = P->G[from];
+    if (P->Gabs) P->Gabs[to] = P->Gabs[from];
     if (P->eps) memcpy(&P->eps[to * B], &P->eps[from * B], sizeof(double) * B);
     if (P->ebar) memcpy(&P->ebar[to * B], &P->ebar[from * B], sizeof(double) * B);
 }
@@ -132,6 +133,7 @@ void orc_deepr_rewire(uint64_t seed, orc_proj *P, int32_t B, uint64_t step, int3
             if (P->m) P->m[s] = 0.0;
             if (P->v) P->v[s] = 0.0;
             if (P->G) P->G[s] = 0.0;
+            if (P->Gabs) P->Gabs[s] = 0.0;
             if (P->eps) memset(&P->eps[s * B], 0, sizeof(double) * B);
             if (P->ebar) memset(&P->ebar[s * B], 0, sizeof(double) * B);
             put_bit(P->conn, P->words, r, j, 1);

@@ -82,6 +82,11 @@ typedef struct orc_proj {
     double *eps, *ebar;    /* [n_pre*cap*B]; eps NULL for LIF, both NULL untrained */
     uint32_t *conn, *sign; /* [n_pre*words] or NULL */
     int32_t words;         /* ceil(n_post/32) */
+    /* Error-bound bookkeeping for tests, no part of the method (may be NULL):
+     * Gabs[s] accumulates sum |L_j ebar_ji| beside G, the magnitude of the
+     * terms whose sum G is, so that a test can bound a sum with cancellation
+     * per element.  It is cleared, moved and zeroed together with G. */
+    double *Gabs;
 } orc_proj;
 
 /* ---- e-prop classifier (input -> LIF/ALIF recurrent -> leaky readout) ---- */
@@ -89,8 +94,6 @@ typedef struct orc_net {
     int32_t n_in, n_rec, n_out, batch;
     int32_t alif;           /* 0: LIF (beta = rho = 0) */
     double alpha, rho, v_thr, beta;
-    double alpha_trace;     /* decay of the presynaptic traces xbar, zbar (equals
-                               alpha unless a test passes a rounded value) */
     orc_proj *in, *rec;
     double *v, *a;          /* [B][n_rec] */
     double *y;              /* [B][n_out] */
@@ -103,6 +106,10 @@ typedef struct orc_net {
     double *psi, *L;        /* [B][n_rec] */
     uint8_t *z;             /* [B][n_rec] spikes emitted this step */
     double *delta;          /* [B][n_out] pi - onehot(label) */
+    /* Error-bound bookkeeping for tests (each may be NULL): Labs[B][n_rec]
+     * = sum_k |W_out[k][j] delta_k| of the last step; Goutabs and Gbabs
+     * accumulate |delta_k zbar_j| and |delta_k| beside Gout and Gb. */
+    double *Labs, *Goutabs, *Gbabs;
 } orc_net;
 
 /* Build: fixed-probability rows (paper, classifier model section).  Row i

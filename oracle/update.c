@@ -34,6 +34,7 @@ static void update_proj(orc_proj *P, int32_t B, int32_t with_l1, double l1, doub
             }
             adam(&P->w[s], &P->m[s], &P->v[s], g, lr, b1, b2, eps, c1, c2);
             P->G[s] = 0.0;
+            if (P->Gabs) P->Gabs[s] = 0.0;
         }
 }
 
@@ -48,9 +49,11 @@ void orc_adam_update(orc_net *N, int32_t k, double lr, double b1, double b2, dou
     for (int64_t q = 0; q < nout; ++q) {
         adam(&N->Wout[q], &N->Mout[q], &N->Vout[q], N->Gout[q] / (double)B, lr, b1, b2, eps, c1, c2);
         N->Gout[q] = 0.0;
+        if (N->Goutabs) N->Goutabs[q] = 0.0;
     }
     for (int32_t q = 0; q < N->n_out; ++q) {
         adam(&N->bout[q], &N->Mb[q], &N->Vb[q], N->Gb[q] / (double)B, lr, b1, b2, eps, c1, c2);
         N->Gb[q] = 0.0;
+        if (N->Gbabs) N->Gbabs[q] = 0.0;
     }
 }

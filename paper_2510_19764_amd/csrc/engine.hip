@@ -18,6 +18,9 @@ using namespace rs;
 namespace {
 
 thread_local std::string g_err;
+// The object of the call in progress on this thread: a device error marks it
+// unusable (sticky RS_EDEVICE).
+thread_local bool* g_dead = nullptr;
 
 rs_status fail(rs_status code, const char* fmt, ...) {
   char buf[512];
@@ -26,8 +29,21 @@ rs_status fail(rs_status code, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+  if (code == RS_EDEVICE && g_dead) *g_dead = true;
   return code;
 }
+
+// Entry of a call on an object: refuses an object an earlier device error
+// left unusable, and lets fail() mark this one for the call's duration.
+struct CallScope {
+  bool* prev;
+  explicit CallScope(bool* dead) : prev(g_dead) { g_dead = dead; }
+  ~CallScope() { g_dead = prev; }
+};
+#define ENTER(obj)                                                                                  \
+  if (!(obj)) return fail(RS_EINVAL, "NULL object");                                                \
+  if ((obj)->dead) return fail(RS_EDEVICE, "an earlier device error left this object unusable"); \
+  CallScope call_scope_(&(obj)->dead)
 
 #define HIP_OK(expr)                                                                        \
   do {                                                                                      \
@@ -160,7 +176,8 @@ struct rs_eprop {
   float *Wout = nullptr, *bout = nullptr, *Gout = nullptr, *Gb = nullptr;
   float *Mout = nullptr, *Vout = nullptr, *Mb = nullptr, *Vb = nullptr;
   unsigned long long* counters = nullptr;  // [0] events, [1] spikes
-  long long* rw_stats = nullptr;           // [2] DEEP R eliminated / formed since creation
+  long long* rw_stats = nullptr;           // [4] DEEP R eliminated, formed, activations distributed,
+                                           // activations without a row, since creation
   uint32_t* zcount = nullptr;              // [B][n_rec] spikes per neuron
   const int32_t *x_off = nullptr, *x_idx = nullptr, *labels = nullptr;
   long long n_idx = 0;
@@ -174,6 +191,7 @@ struct rs_eprop {
   uint32_t adam_k = 0;
   double alpha = 0.0, rho = 0.0, beta = 0.0;  // decay factors exp(-dt/tau) in double
   PhaseTimer timer;
+  bool dead = false;  // a device error occurred: every later call fails with RS_EDEVICE
 };
 
 namespace {
@@ -352,7 +370,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   TRY(ar.alloc(&n->cv.cnt, NR * COL_GROUPS_MAX));
   TRY(ar.alloc(&n->cv.off, NR * COL_GROUPS_MAX + 1));
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
-  TRY(ar.alloc(&n->rw_stats, 2));
+  TRY(ar.alloc(&n->rw_stats, 4));
   TRY(ar.alloc(&n->zcount, (size_t)B * NR));
 
   for (ProjDev* P : {&n->in, &n->rec}) {  // padding slots start defined
@@ -383,7 +401,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
   for (float* q : {n->Gout, n->Mout, n->Vout}) launch_fill_zero(s, q, K * NR * 4);
   for (float* q : {n->bout, n->Gb, n->Mb, n->Vb}) launch_fill_zero(s, q, K * 4);
   launch_fill_zero(s, n->counters, 16);
-  launch_fill_zero(s, n->rw_stats, 16);
+  launch_fill_zero(s, n->rw_stats, 32);
   launch_fill_zero(s, n->zcount, (size_t)B * NR * 4);
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
@@ -678,7 +696,7 @@ rs_status rs_eprop_create(const rs_eprop_params* params, void* hip_stream, rs_ep
 
 rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
                              const int32_t* labels_dev) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   if (!off_dev || !idx_dev || !labels_dev) return fail(RS_EINVAL, "input pointers must not be NULL");
   if (n_idx > (size_t)INT32_MAX) return fail(RS_EINVAL, "index array larger than 2^31 entries");
   n->x_off = off_dev;
@@ -690,7 +708,7 @@ rs_status rs_eprop_set_input(rs_eprop* n, const int32_t* off_dev, const int32_t*
 }
 
 rs_status rs_eprop_set_input_poisson(rs_eprop* n, const double* rate_hz, size_t n_rates, const int32_t* labels_dev) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   if (!rate_hz || !labels_dev) return fail(RS_EINVAL, "rate table and labels must not be NULL");
   const size_t NI = n->p.n_in, B = n->B;
   if (n_rates != NI && n_rates != B * NI) return fail(RS_EINVAL, "n_rates must be n_in or batch * n_in");
@@ -719,7 +737,7 @@ rs_status rs_eprop_set_input_poisson(rs_eprop* n, const double* rate_hz, size_t 
 }
 
 rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   if (!n->x_off && !n->poisson) return fail(RS_ESTATE, "no input attached (rs_eprop_set_input*)");
   if (flags & ~(RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)) return fail(RS_EINVAL, "unknown step flags");
   order(n->ev_join, n->stream, n->side);  // side stream follows earlier caller work
@@ -734,17 +752,17 @@ rs_status rs_eprop_step(rs_eprop* n, uint32_t n_steps, uint32_t flags) {
 }
 
 rs_status rs_eprop_update(rs_eprop* n) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   do_update(n, n->stream);
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
 
 rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   if (proj > 1 || !((n->p.deepr_mask >> proj) & 1u))
     return fail(RS_EINVAL, "projection %u is not rewired by DEEP R", proj);
-  long long before[2] = {0, 0}, after[2];
+  long long before[4] = {0, 0, 0, 0}, after[4];
   if (st) {  // the counters accumulate over the object's life; report this call's share
     HIP_OK(hipMemcpyAsync(before, n->rw_stats, sizeof before, hipMemcpyDeviceToHost, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
@@ -757,21 +775,22 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
     HIP_OK(hipStreamSynchronize(n->stream));
     st->eliminated = after[0] - before[0];
     st->formed = after[1] - before[1];
-    st->blocked = 0;
-    st->attempts = st->eliminated;
+    st->attempts = after[2] - before[2];
+    st->blocked = after[3] - before[3];
   }
   return RS_OK;
 }
 
 rs_status rs_eprop_reset(rs_eprop* n) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   reset_state(n, n->stream);
   HIP_OK(hipGetLastError());
   return RS_OK;
 }
 
 rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
-  if (!n || !host) return fail(RS_EINVAL, "NULL argument");
+  ENTER(n);
+  if (!host) return fail(RS_EINVAL, "NULL argument");
   VarRef r;
   if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
@@ -786,7 +805,8 @@ rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
 }
 
 rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes) {
-  if (!n || !host) return fail(RS_EINVAL, "NULL argument");
+  ENTER(n);
+  if (!host) return fail(RS_EINVAL, "NULL argument");
   VarRef r;
   if (!var_ref(n, var, &r, true)) return fail(RS_EINVAL, "unknown or read-only variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
@@ -821,7 +841,8 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
 }
 
 rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
-  if (!n || !o) return fail(RS_EINVAL, "NULL argument");
+  ENTER(n);
+  if (!o) return fail(RS_EINVAL, "NULL argument");
   unsigned long long c[2];
   long long r[2];
   HIP_OK(hipMemcpyAsync(c, n->counters, sizeof c, hipMemcpyDeviceToHost, n->stream));
@@ -844,14 +865,15 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
 }
 
 rs_status rs_eprop_timing(rs_eprop* n, int32_t phase_mask) {
-  if (!n) return fail(RS_EINVAL, "net is NULL");
+  ENTER(n);
   if (phase_mask < 0 || phase_mask >= (1 << RS_NUM_PHASES)) return fail(RS_EINVAL, "phase_mask out of range");
   n->timer.mask = phase_mask;
   return RS_OK;
 }
 
 rs_status rs_eprop_phase_times(rs_eprop* n, double* ms, uint64_t* count) {
-  if (!n || !ms || !count) return fail(RS_EINVAL, "NULL argument");
+  ENTER(n);
+  if (!ms || !count) return fail(RS_EINVAL, "NULL argument");
   n->timer.collect();
   for (int q = 0; q < RS_NUM_PHASES; ++q) {
     ms[q] = n->timer.ms[q];
@@ -910,6 +932,7 @@ struct rs_topo {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  bool dead = false;  // a device error occurred: every later call fails with RS_EDEVICE
 };
 
 namespace {
@@ -1023,7 +1046,7 @@ rs_status rs_topo_create(const rs_topo_params* p, void* hip_stream, rs_topo** ou
 }
 
 rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
-  if (!t) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
   if (step == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step 2^64-1 is reserved");
   hipStream_t s = t->stream;
   launch_fill_zero(s, t->t.stats, 32);
@@ -1045,7 +1068,8 @@ rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
 }
 
 rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
-  if (!t || !len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
   const ProjDev& P = t->t.P;
   const size_t n = (size_t)P.n_pre * P.cap;
   HIP_OK(hipMemcpyAsync(len, P.len, (size_t)P.n_pre * 4, hipMemcpyDeviceToHost, t->stream));
@@ -1056,7 +1080,8 @@ rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
 }
 
 rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w) {
-  if (!t || !len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
   const ProjDev& P = t->t.P;
   for (int i = 0; i < P.n_pre; ++i) {
     if (len[i] < 0 || len[i] > P.cap) return fail(RS_EINVAL, "row %d length %d outside 0..%d", i, len[i], P.cap);
@@ -1082,7 +1107,8 @@ rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, c
 }
 
 rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits) {
-  if (!t || !bits) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!bits) return fail(RS_EINVAL, "NULL argument");
   const ProjDev& P = t->t.P;
   HIP_OK(hipMemcpyAsync(bits, t->t.bits, (size_t)P.n_pre * P.words * 4, hipMemcpyDeviceToHost, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
@@ -1090,7 +1116,8 @@ rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits) {
 }
 
 rs_status rs_topo_last_ms(rs_topo* t, double* ms) {
-  if (!t || !ms) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!ms) return fail(RS_EINVAL, "NULL argument");
   if (!t->timed) return fail(RS_ESTATE, "no rewire has run");
   float f = 0.f;
   HIP_OK(hipEventSynchronize(t->ev1));
@@ -1100,7 +1127,8 @@ rs_status rs_topo_last_ms(rs_topo* t, double* ms) {
 }
 
 rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
-  if (!t || !m) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!m) return fail(RS_EINVAL, "NULL argument");
   const int L = (int)t->p.L, N = L * L;
   if (!topo_sim_fits(N)) return fail(RS_EINVAL, "the simulation needs L*L <= 4096 (L = %d)", L);
   if (!(m->h > 0) || !(m->C_m > 0) || !(m->tau_m > 0) || !(m->tau_s > 0) || !(m->tau_plus > 0) ||
@@ -1111,6 +1139,11 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   if (!(m->f_base >= 0) || !(m->f_peak >= 0) || !(m->sigma_stim > 0))
     return fail(RS_EINVAL, "rates must be >= 0 and sigma_stim > 0");
   if (m->ref_steps > (1u << 30)) return fail(RS_EINVAL, "ref_steps too large");
+  // potentiation clips weights at g_max: keep it within the range the
+  // fixed-point delivery sums hold
+  if (!(m->g_max >= 0 && m->g_max <= TOPO_W_MAX)) return fail(RS_EINVAL, "g_max must lie in [0, 1e4]");
+  if (!(m->A_plus >= 0 && m->A_plus <= TOPO_W_MAX) || !(m->A_minus >= 0 && m->A_minus <= TOPO_W_MAX))
+    return fail(RS_EINVAL, "A_plus and A_minus must lie in [0, 1e4]");
   hipStream_t s = t->stream;
   TopoSimDev& d = t->sd;
   const int words = (N + 31) / 32, half = L / 2, n_d2 = 2 * half * half + 1;
@@ -1178,6 +1211,9 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   launch_fill_zero(s, d.count, (size_t)N * 4);
   launch_fill_zero(s, d.zin, (size_t)words * 4);
   launch_fill_zero(s, d.zout, (size_t)words * 4);
+  // the column view is rebuilt by the first simulation launch (col_dirty);
+  // until then a rewire's column edits find empty columns
+  launch_fill_zero(s, d.col_len, (size_t)N * 4);
   launch_fill_zero(s, t->step_dev, 8);
   launch_fill_zero(s, t->ticks, 8 * TOPO_PHASES);
   d.ticks = nullptr;  // timers off until rs_topo_sim_timing
@@ -1191,7 +1227,7 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
 }
 
 rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
-  if (!t) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
   if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
   hipStream_t s = t->stream;
   const uint64_t R = t->m.rewire_steps;
@@ -1222,7 +1258,7 @@ rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
 }
 
 rs_status rs_topo_sim_timing(rs_topo* t, int32_t on) {
-  if (!t) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
   if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
   HIP_OK(hipStreamSynchronize(t->stream));
   launch_fill_zero(t->stream, t->ticks, 8 * TOPO_PHASES);
@@ -1237,7 +1273,8 @@ rs_status rs_topo_sim_timing(rs_topo* t, int32_t on) {
 }
 
 rs_status rs_topo_sim_phase_ms(rs_topo* t, double* ms) {
-  if (!t || !ms) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!ms) return fail(RS_EINVAL, "NULL argument");
   if (!t->sim) return fail(RS_ESTATE, "rs_topo_sim_init has not run");
   unsigned long long h[TOPO_PHASES];
   HIP_OK(hipMemcpyAsync(h, t->ticks, sizeof h, hipMemcpyDeviceToHost, t->stream));
@@ -1251,7 +1288,8 @@ rs_status rs_topo_sim_phase_ms(rs_topo* t, double* ms) {
 }
 
 rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* st) {
-  if (!t || !st) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!st) return fail(RS_EINVAL, "NULL argument");
   long long h[4];
   HIP_OK(hipMemcpyAsync(h, t->t.stats, sizeof h, hipMemcpyDeviceToHost, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
@@ -1283,7 +1321,8 @@ rs_status topo_var(rs_topo* t, int32_t var, void** dev, size_t* bytes, bool* wri
 }  // namespace
 
 rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes) {
-  if (!t || !host) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!host) return fail(RS_EINVAL, "NULL argument");
   void* dev = nullptr;
   size_t need = 0;
   bool wr = false;
@@ -1300,7 +1339,8 @@ rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes) {
 }
 
 rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes) {
-  if (!t || !host) return fail(RS_EINVAL, "NULL argument");
+  ENTER(t);
+  if (!host) return fail(RS_EINVAL, "NULL argument");
   void* dev = nullptr;
   size_t need = 0;
   bool wr = false;

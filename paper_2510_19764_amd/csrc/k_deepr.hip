@@ -15,6 +15,8 @@
 //                  whose connectivity bit is clear (and that are not the row
 //                  itself in recurrent projections), sets the bits and appends
 //                  synapses; the wave zeroes their records.
+#include <mutex>
+
 #include "rs_compact.hpp"
 #include "rs_kernels.hpp"
 
@@ -76,7 +78,8 @@ __device__ __forceinline__ int block_sum_i(int v, int* s_red) {
   return t;
 }
 
-__global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, ProjDev P, uint64_t step) {
+__global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, ProjDev P, uint64_t step,
+                                                              long long* stats) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* cnt = (int*)smem;           // [n_pre]
   int* asg = cnt + P.n_pre;        // [n_pre]
@@ -118,7 +121,16 @@ __global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, Pro
     }
   }
   __syncthreads();
-  for (int r = tid; r < P.n_pre; r += DIST_NT) P.assigned[r] = asg[r];
+  int placed = 0;
+  for (int r = tid; r < P.n_pre; r += DIST_NT) {
+    P.assigned[r] = asg[r];
+    placed += asg[r];
+  }
+  placed = block_sum_i(placed, s_red);
+  if (tid == 0) {
+    atomicAdd((unsigned long long*)&stats[2], (unsigned long long)placed);
+    if (pending > 0) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)pending);
+  }
 }
 
 __global__ void __launch_bounds__(WAVE) k_deepr_form(uint64_t seed, ProjDev P, int B, uint64_t step,
@@ -180,14 +192,11 @@ __global__ void __launch_bounds__(WAVE) k_deepr_form(uint64_t seed, ProjDev P, i
 }
 
 void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step, long long* stats) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    allow_dynamic_lds((const void*)k_deepr_distribute, 128 * 1024);
-    attr_set = true;
-  }
+  static std::once_flag once;
+  std::call_once(once, [] { allow_dynamic_lds((const void*)k_deepr_distribute, 128 * 1024); });
   const size_t sm_elim = (size_t)P.cap * 9 + 16;
   hipLaunchKernelGGL(k_deepr_elim, dim3(P.n_pre), dim3(WAVE), sm_elim, s, P, B, stats);
-  hipLaunchKernelGGL(k_deepr_distribute, dim3(1), dim3(DIST_NT), (size_t)P.n_pre * 8, s, seed, P, step);
+  hipLaunchKernelGGL(k_deepr_distribute, dim3(1), dim3(DIST_NT), (size_t)P.n_pre * 8, s, seed, P, step, stats);
   hipLaunchKernelGGL(k_deepr_form, dim3(P.n_pre), dim3(WAVE), (size_t)P.cap * 4 + 16, s, seed, P, B, step,
                      stats);
 }

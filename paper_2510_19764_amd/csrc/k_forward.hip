@@ -17,6 +17,8 @@
 //   forward kernel's sequential path.
 // k_handoff_transpose: the forward kernel's instance-major staging into the
 //   neuron-major rings the eligibility kernels read.
+#include <mutex>
+
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -365,15 +367,14 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
 // LDS a forward workgroup may take: the device's limit, at most 150 KB, less
 // 1 KB for the kernel's static arrays.
 static int fwd_lds_cap() {
-  static int lds_cap = 0;
-  if (!lds_cap) {
+  static const int lds_cap = [] {
     int dev = 0, cap = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
       cap = 64 * 1024;
     (void)hipGetLastError();
-    lds_cap = (cap < 150 * 1024 ? cap : 150 * 1024) - 1024;
-  }
+    return (cap < 150 * 1024 ? cap : 150 * 1024) - 1024;
+  }();
   return lds_cap;
 }
 
@@ -399,15 +400,14 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
                     fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, 1, a.cap_in, a.cap_rec).total <=
                         (size_t)lds_cap;
   const size_t sm = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, rows, a.cap_in, a.cap_rec).total;
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag once;
+  std::call_once(once, [] {
     allow_dynamic_lds((const void*)k_fwd<1, true>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<1, false>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<2, false>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<4, false>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<8, false>, 150 * 1024);
-    attr_set = true;
-  }
+  });
   if (rows) hipLaunchKernelGGL((k_fwd<1, true>), dim3(a.B), dim3(FWD_NT), sm, s, a);
   else if (need <= 1) hipLaunchKernelGGL((k_fwd<1, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
   else if (need <= 2) hipLaunchKernelGGL((k_fwd<2, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);

@@ -11,6 +11,8 @@
 //                     remaining candidates in ascending target order and forms
 //                     synapses with the distance-dependent probability while
 //                     the row has room.  All bits end cleared.
+#include <mutex>
+
 #include "rs_compact.hpp"
 #include "rs_kernels.hpp"
 
@@ -60,7 +62,7 @@ __device__ void col_rename(const TopoDev& t, int j, int from, int to) {
 }
 __device__ void col_append(const TopoDev& t, int j, int slot) {
   const int pos = atomicAdd(&t.col_len[j], 1);
-  if (pos < t.col_cap) t.col_ent[(int64_t)j * t.col_cap + pos] = slot;
+  if (pos >= 0 && pos < t.col_cap) t.col_ent[(int64_t)j * t.col_cap + pos] = slot;
   else *t.col_dirty = 1;  // full column: the next simulation launch rebuilds the view
 }
 
@@ -207,11 +209,8 @@ __global__ void __launch_bounds__(WAVE) k_topo_rewire_fused(uint64_t seed, TopoD
 }
 
 void topo_rewire_attrs() {
-  static bool attr_set = false;
-  if (!attr_set) {
-    allow_dynamic_lds((const void*)k_topo_distribute, 128 * 1024);
-    attr_set = true;
-  }
+  static std::once_flag once;
+  std::call_once(once, [] { allow_dynamic_lds((const void*)k_topo_distribute, 128 * 1024); });
 }
 
 void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step) {

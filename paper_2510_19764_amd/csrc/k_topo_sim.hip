@@ -35,6 +35,8 @@
 // launch only after the build, a restore of rows or a full column.  Launched from a recorded graph, the kernel
 // takes its first step from device memory (STEP_FROM_DEVICE) and every launch
 // writes the step count it reached back.
+#include <mutex>
+
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -314,12 +316,11 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
 }
 
 void topo_sim_attrs() {
-  static bool attr_set = false;
-  if (!attr_set) {
+  static std::once_flag once;
+  std::call_once(once, [] {
     allow_dynamic_lds((const void*)k_topo_sim<false>, 160 * 1024);
     allow_dynamic_lds((const void*)k_topo_sim<true>, 160 * 1024);
-    attr_set = true;
-  }
+  });
 }
 
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,

@@ -132,7 +132,9 @@ struct UpdateArgs {
 void launch_update(hipStream_t s, const UpdateArgs& a);
 
 // ---------------------------------------------------------------- DEEP R
-// stats: int64[2] device counters, incremented (0: eliminated = D, 1: formed)
+// stats: int64[4] device counters, incremented: 0 eliminated (= D, the dormant
+// total), 1 formed, 2 activations distributed to rows, 3 activations no row had
+// room for
 void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step,
                   long long* stats);
 

@@ -4,9 +4,10 @@ layout, oracle networks built from a snapshot, and the comparison rules.
 Tolerance (single precision against the fp64 oracle): |gpu - orc| <=
 RTOL * max(|orc|, scale) with RTOL = 1e-5, scale = v_thr for voltages and the
 readout, 1 for spike traces and eligibility traces, the initial weight spread
-for weights, and the largest magnitude in the array for accumulated sums
-(gradients, learning signals), whose cancellation makes a per-element relative
-bound meaningless."""
+for weights.  A sum with cancellation (learning signal, gradients) is bounded
+per element by RTOL * (|orc| + sum of its terms' magnitudes): each term may
+carry the relative error of its factors, and the sum its own rounding.  The
+oracle accumulates those magnitude sums beside the sums themselves."""
 from __future__ import annotations
 
 import numpy as np
@@ -45,16 +46,14 @@ def f32(x):
 
 
 def effective_params(cfg: rb.EpropConfig):
-    """The parameter values the library actually runs with: parameters cross the
-    C-ABI as float32, and the decay factors are exp(-dt/tau) evaluated in double
-    from the float32 dt and tau.  The oracle receives these same values so that
-    the comparison measures arithmetic, not parameter rounding."""
+    """The parameter values the library is given: parameters cross the C-ABI as
+    float32, and the decay factors are exp(-dt/tau) evaluated in double from the
+    float32 dt and tau.  The oracle decays every filter, the presynaptic traces
+    included, by that one double alpha, as the paper's filters share tau_mem."""
     dt, tm, ta = np.float64(np.float32(cfg.dt_ms)), np.float64(np.float32(cfg.tau_mem_ms)), \
         np.float64(np.float32(cfg.tau_adapt_ms))
-    alpha = float(np.exp(-dt / tm))
-    # the presynaptic traces decay by the float-rounded alpha
-    return dict(v_thr=f32(cfg.v_thr), beta=f32(cfg.beta), alpha_value=alpha,
-                rho_value=float(np.exp(-dt / ta)), alpha_trace_value=f32(alpha))
+    return dict(v_thr=f32(cfg.v_thr), beta=f32(cfg.beta), alpha_value=float(np.exp(-dt / tm)),
+                rho_value=float(np.exp(-dt / ta)))
 
 
 def oracle_net(snap, cfg: rb.EpropConfig, with_traces=True):
@@ -66,7 +65,7 @@ def oracle_net(snap, cfg: rb.EpropConfig, with_traces=True):
         cap = d["ind"].shape[1]
         P = oracle.Proj(n_pre, cfg.n_rec, cap, rec, pid, batch=B, trained=True,
                         traces=("alif" if cfg.alif else "lif") if with_traces else "none",
-                        bitfields="conn" in d)
+                        bitfields="conn" in d, abs_sums=True)
         P.len[:] = d["len"]
         P.ind[:] = d["ind"].ravel()
         P.w[:] = d["w"].ravel()
@@ -84,7 +83,7 @@ def oracle_net(snap, cfg: rb.EpropConfig, with_traces=True):
     prm = oracle.EpropParams(n_in=cfg.n_in, n_rec=cfg.n_rec, n_out=cfg.n_out, batch=B, alif=cfg.alif,
                              dt_ms=cfg.dt_ms, tau_mem_ms=cfg.tau_mem_ms, tau_adapt_ms=cfg.tau_adapt_ms,
                              **effective_params(cfg))
-    N = oracle.Net(prm, projs[0], projs[1])
+    N = oracle.Net(prm, projs[0], projs[1], abs_sums=True)
     N.v[:] = snap["v"]
     N.a[:] = snap["a"]
     N.y[:] = snap["y"]
@@ -95,17 +94,25 @@ def oracle_net(snap, cfg: rb.EpropConfig, with_traces=True):
     return N
 
 
-def close(name, gpu, orc, scale, rtol=RTOL):
+def close(name, gpu, orc, scale, rtol=RTOL, bound=None):
+    """|gpu - orc| <= rtol * max(|orc|, scale) per element, or <= bound."""
     gpu = np.asarray(gpu, np.float64)
     orc = np.asarray(orc, np.float64)
     assert gpu.shape == orc.shape, (name, gpu.shape, orc.shape)
-    bound = rtol * np.maximum(np.abs(orc), scale)
+    if bound is None:
+        bound = rtol * np.maximum(np.abs(orc), scale)
     err = np.abs(gpu - orc)
     bad = err > bound
     if bad.any():
         q = np.argwhere(bad)[0]
         raise AssertionError(f"{name}: {int(bad.sum())} elements off, first at {tuple(q)}: "
                              f"gpu={gpu[tuple(q)]!r} oracle={orc[tuple(q)]!r} bound={bound[tuple(q)]!r}")
+
+
+def close_sum(name, gpu, orc, abs_sum, rtol=RTOL):
+    """A sum with cancellation: rtol * (|orc| + sum of the terms' magnitudes)."""
+    orc = np.asarray(orc, np.float64)
+    close(name, gpu, orc, 0.0, bound=rtol * (np.abs(orc) + np.asarray(abs_sum, np.float64)))
 
 
 def real_slots(d):
@@ -129,18 +136,18 @@ def compare_state(snap, N: oracle.Net, cfg: rb.EpropConfig, sigma_w=(1.0, 1.0), 
     close("zbar", snap["zbar"], N.zbar, 1.0, rtol)
     close("psi", snap["psiT"].T, N.psi, 0.3 / cfg.v_thr, rtol)
     close("delta", snap["deltaT"].T, N.delta, 1.0, rtol)
-    close("L", snap["LT"].T, N.L, max(1e-12, np.abs(N.L).max()), rtol)
+    close_sum("L", snap["LT"].T, N.L, N.Labs, rtol)
     if not learn:
         return
-    close("Gout", snap["Gout"], N.Gout, max(1e-12, np.abs(N.Gout).max()), rtol)
-    close("Gb", snap["Gb"], N.Gb, max(1e-12, np.abs(N.Gb).max()), rtol)
+    close_sum("Gout", snap["Gout"], N.Gout, N.Goutabs, rtol)
+    close_sum("Gb", snap["Gb"], N.Gb, N.Gbabs, rtol)
     B = cfg.batch
     for tag, P in (("in", N.inp), ("rec", N.rec)):
         g = snap[tag]
         cap = g["ind"].shape[1]
         m = real_slots(g)
         compare_rows_exact(tag, g, P)
-        close(tag + ".G", g["G"][m], P.G.reshape(-1, cap)[m], max(1e-12, np.abs(P.G).max()), rtol)
+        close_sum(tag + ".G", g["G"][m], P.G.reshape(-1, cap)[m], P.Gabs.reshape(-1, cap)[m], rtol)
         eb = P.ebar.reshape(-1, cap, B)
         close(tag + ".ebar", g["ebar"][m], eb[m], 1.0, rtol)
         if cfg.alif:
@@ -170,3 +177,143 @@ def oracle_step_resync(N: oracle.Net, raster, t_local: int, labels, z_gpu, learn
     else:
         N.step(idx, off, labels, learn=learn)
     return n_resync
+
+
+# ---------------------------------------------------------------------------
+# One step call in the benchmark's schedule (blocks of steps, the two-stream
+# hand-off ring, automatic update and DEEP R of both projections inside the
+# call) against the oracle stepping the same steps one by one.
+
+def _adam_bounds(P_or_none, G_pre, Gabs_pre, m_old, g, m, v, w, cfg, k, wscale):
+    """Bounds on m, v and w after one Adam step whose gradient g = G/B (+ L1)
+    carries the error rtol * (|G| + sum of |terms|) / B of the accumulated sum:
+    first-order propagation through the step, plus each value's own rounding."""
+    b1, b2, lr, eps = cfg.adam_b1, cfg.adam_b2, cfg.lr, cfg.adam_eps
+    c1, c2 = 1 - b1 ** k, 1 - b2 ** k
+    g_err = RTOL * (np.abs(G_pre) + Gabs_pre) / cfg.batch
+    bm = RTOL * (np.abs(m) + b1 * np.abs(m_old) + (1 - b1) * np.abs(g)) + (1 - b1) * g_err
+    bv = 2 * RTOL * np.abs(v) + (1 - b2) * 2 * (np.abs(g) + g_err) * g_err
+    s = np.sqrt(v / c2)
+    mh = m / c1
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dm = (1 - b1) / c1 / (s + eps)
+        ds = np.where(s > 0, (1 - b2) * (np.abs(g) + g_err) / (c2 * s), 0.0)
+        dratio = dm + np.abs(mh) / (s + eps) ** 2 * ds
+    bw = RTOL * np.maximum(np.abs(w), wscale) + 2 * lr * dratio * g_err
+    return bm, bv, bw
+
+
+def _carry(bound_pre, len_pre, ind_pre, len_post, ind_post, n_post):
+    """Move per-slot bounds along with their synapses through a rewire: a
+    synapse is identified by (row, target).  New synapses get bound 0 (they
+    start at exactly zero on both sides)."""
+    n_pre, cap = ind_pre.shape
+    slot_of = np.full((n_pre, n_post), -1, np.int64)
+    rows = np.repeat(np.arange(n_pre), len_pre)
+    m_pre = np.arange(cap)[None, :] < len_pre[:, None]
+    slot_of[rows, ind_pre[m_pre]] = np.nonzero(m_pre)[1]
+    m_post = np.arange(cap)[None, :] < len_post[:, None]
+    rows_post = np.repeat(np.arange(n_pre), len_post)
+    s = slot_of[rows_post, ind_post[m_post]]
+    out = np.zeros(m_post.sum())
+    have = s >= 0
+    out[have] = bound_pre[rows_post[have], s[have]]
+    return out
+
+
+def interval_vs_oracle(net, cfg, raster, labels, n_steps):
+    """Run net.step(n_steps, LEARN | AUTO_UPDATE) from the current state, which
+    must sit at an update boundary and within one sample, and the oracle over
+    the same steps with its own updates and DEEP R rewires.  Compares spike
+    counts and the last block's raster exactly, rows, bitfields and dormant
+    counts bit for bit, and every value within its bound.  Returns the number
+    of updates inside the call."""
+    U, T = cfg.update_interval, cfg.sample_steps
+    t0 = int(net.info().step)
+    assert t0 % U == 0 and t0 % T + n_steps <= T
+    pre = snapshot(net)
+    zc0 = net.get(rb.ZCOUNT).astype(np.int64)
+    adam0 = int(net.info().adam_step)
+    net.step(n_steps, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
+    post = snapshot(net)
+    zc1 = net.get(rb.ZCOUNT).astype(np.int64)
+    zbits = net.get(rb.ZBITS)
+    last_blk = int(net.info().last_block)
+
+    N = oracle_net(pre, cfg)
+    counts = np.zeros((cfg.batch, cfg.n_rec), np.int64)
+    raster_tail = []
+    bounds = None
+    n_upd = 0
+    for t in range(t0, t0 + n_steps):
+        idx, off = raster.step_lists(t % T)
+        N.step(idx, off, labels)
+        counts += N.z
+        if t >= t0 + n_steps - last_blk:
+            raster_tail.append(N.z.T.copy())
+        if (t + 1) % U == 0:
+            n_upd += 1
+            k = adam0 + n_upd
+            snap_pre = {}
+            for tag, P in (("in", N.inp), ("rec", N.rec)):
+                cap = P.cap
+                snap_pre[tag] = dict(G=P.G.reshape(-1, cap).copy(), Gabs=P.Gabs.reshape(-1, cap).copy(),
+                                     m=P.m.reshape(-1, cap).copy())
+            ro = dict(G=N.Gout.copy(), Gabs=N.Goutabs.copy(), m=N.Mout.copy(),
+                      Gb=N.Gb.copy(), Gbabs=N.Gbabs.copy(), mb=N.Mb.copy())
+            N.adam_update(k, lr=cfg.lr, b1=cfg.adam_b1, b2=cfg.adam_b2, eps=cfg.adam_eps, l1=cfg.l1,
+                          deepr_mask=cfg.deepr_mask)
+            bounds = {}
+            for tag, P, sig, bit in (("in", N.inp, cfg.sigma_in, 1), ("rec", N.rec, cfg.sigma_rec, 2)):
+                cap = P.cap
+                d = snap_pre[tag]
+                g = d["G"] / cfg.batch
+                if cfg.deepr_mask & bit:
+                    words = P.sign.reshape(P.n_pre, -1)
+                    ind = P.ind.reshape(-1, cap)
+                    neg = (words[np.arange(P.n_pre)[:, None], ind >> 5] >> (ind & 31)) & 1
+                    g = g + np.where(neg == 1, -cfg.l1, cfg.l1)
+                bm, bv, bw = _adam_bounds(P, d["G"], d["Gabs"], d["m"], g, P.m.reshape(-1, cap),
+                                          P.v.reshape(-1, cap), P.w.reshape(-1, cap), cfg, k, sig)
+                bounds[tag] = dict(len=P.len.copy(), ind=P.ind.reshape(-1, cap).copy(), m=bm, v=bv, w=bw)
+            bm, bv, bw = _adam_bounds(None, ro["G"], ro["Gabs"], ro["m"], ro["G"] / cfg.batch, N.Mout, N.Vout,
+                                      N.Wout, cfg, k, cfg.sigma_out)
+            bounds["out"] = dict(m=bm, v=bv, w=bw)
+            bm, bv, bw = _adam_bounds(None, ro["Gb"], ro["Gbabs"], ro["mb"], ro["Gb"] / cfg.batch, N.Mb, N.Vb,
+                                      N.bout, cfg, k, 1e-3)
+            bounds["b"] = dict(m=bm, v=bv, w=bw)
+            step = t + 1
+            dormant = {}
+            for p, (tag, P) in enumerate((("in", N.inp), ("rec", N.rec))):
+                if (cfg.deepr_mask >> p) & 1:
+                    dormant[tag], _ = oracle.deepr_rewire(cfg.seed, P, step)
+    assert n_upd >= 1, "the call must contain an update"
+    assert int(net.info().adam_step) == adam0 + n_upd
+
+    # spikes: per-neuron counts over the call and the last block's raster
+    assert np.array_equal(zc1 - zc0, counts), "spike counts differ"
+    for q, z in enumerate(raster_tail):
+        assert np.array_equal((zbits >> q) & 1, z.astype(np.uint32)), f"raster differs at block step {q}"
+
+    # neuron, readout and trace state
+    compare_state(post, N, cfg)
+    # rows, bitfields and dormant counts bit for bit; parameters within bounds
+    for p, (tag, P) in enumerate((("in", N.inp), ("rec", N.rec))):
+        g = post[tag]
+        cap = P.cap
+        compare_rows_exact(tag, g, P)
+        if "conn" in g:
+            assert np.array_equal(g["conn"].ravel(), P.conn), tag + ": connectivity bits differ"
+            assert np.array_equal(g["sign"].ravel(), P.sign), tag + ": sign bits differ"
+            assert np.array_equal(g["dormant"], dormant[tag]), tag + ": dormant counts differ"
+        b = bounds[tag]
+        m = real_slots(g)
+        for f, arr in (("w", P.w), ("m", P.m), ("vv", P.v)):
+            bf = b["v" if f == "vv" else f]
+            carried = _carry(bf, b["len"], b["ind"], P.len, P.ind.reshape(-1, cap), P.n_post)
+            close(f"{tag}.{f}", g[f][m], arr.reshape(-1, cap)[m], 0.0, bound=carried)
+    for f, arr, key in (("Wout", N.Wout, "w"), ("Mout", N.Mout, "m"), ("Vout", N.Vout, "v")):
+        close(f, post[f], arr, 0.0, bound=bounds["out"][key])
+    for f, arr, key in (("bout", N.bout, "w"), ("Mb", N.Mb, "m"), ("Vb", N.Vb, "v")):
+        close(f, post[f], arr, 0.0, bound=bounds["b"][key])
+    return n_upd

@@ -1,13 +1,16 @@
 """Parity at the full sparse-classifier size (700 inputs, 1024 ALIF, 20
-readouts, 10% connectivity, batch 256) in the launch configuration the
-benchmark times: one full-size step compared element by element with the
-oracle, DEEP R bit-exact on the full rows, and invariants after a complete
-training interval."""
+readouts, 10% connectivity, batch 256): 120 steps in the schedule the
+benchmark times (20-step blocks through the two-stream hand-off ring, the
+automatic Adam update and both DEEP R rewires inside the call, the column view
+rebuilt beside the next forward block) compared element by element with the
+oracle; single full-size steps; DEEP R bit-exact on the full rows; invariants
+after a complete training interval; and a whole training batch run twice."""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_harness import compare_state, gpu_input, oracle_net, oracle_step_resync, real_slots, snapshot
+from gpu_harness import (compare_state, gpu_input, interval_vs_oracle, oracle_net, oracle_step_resync, real_slots,
+                         snapshot)
 from paper_2510_19764_amd import binding as rb
 from paper_2510_19764_amd import workload as wl
 
@@ -127,3 +130,20 @@ def test_full_batch_training_deterministic():
                 assert np.array_equal(a[k][f], b[k][f]), (k, f)
         else:
             assert np.array_equal(a[k], b[k]), k
+
+
+def test_full_size_interval_in_bench_schedule():
+    """From the update boundary at step 100, one call of 120 steps with
+    RS_LEARN | RS_AUTO_UPDATE and the default block length (five 20-step
+    blocks, the update and both rewires at step 200, one more block after it),
+    against the oracle's 120 steps, Adam update and two rewires from the same
+    snapshot: spike counts and the last block's raster exact, rows, bitfields
+    and dormant counts bit for bit, state and parameters within their bounds."""
+    cfg = classifier_cfg()
+    labels, raster = wl.ShdLike().batch(seed=1, batch_index=0, B=cfg.batch)
+    net = rb.EpropNet(cfg)
+    net.set_input(*gpu_input(raster, labels))
+    net.step(cfg.update_interval, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
+    print("classifier full size: 120 steps against the oracle", flush=True)
+    assert interval_vs_oracle(net, cfg, raster, labels, 120) == 1
+    net.close()

@@ -98,7 +98,9 @@ CASES = {
     "nostdp-L12": (rb.TopoConfig(L=12, cap=18, n_attempts=10, proj_id=1, g_theta=0.25, g_new=0.5,
                                  g_init=0.5, seed=5),
                    rb.TopoModel(f_peak=600.0, g_max=0.5, stdp=0, rewire_steps=7)),
-    "paper-L64": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, seed=9), rb.TopoModel()),
+    # the benchmark's map: the paper's parameters with the moving bar
+    "paper-L64": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, seed=9),
+                  rb.TopoModel(stim_kind=rb.STIM_BAR)),
     # the largest map, driven, bar stimulus moving every 5 ms
     "hot-L64-bar": (rb.TopoConfig(L=64, cap=32, n_attempts=160, proj_id=0, g_theta=0.25, g_new=0.5, g_init=0.5,
                                   seed=10),
@@ -132,9 +134,8 @@ def test_topo_sim_lockstep_matches_oracle(name):
         changed += st.eliminated + st.formed
         compare(t, cfg, M, P, S)
         spikes = int(S.count.sum())
-    if name != "paper-L64":
-        assert spikes > 0
-        assert changed > 0
+    assert spikes > 0
+    assert changed > 0
 
 
 def test_topo_sim_split_runs_are_identical():
@@ -161,11 +162,12 @@ def _same_state(a, b):
         assert np.array_equal(x, y)
 
 
-def test_topo_sim_graph_replays_match_direct_launches():
+@pytest.mark.parametrize("name", ["hot-L16-blob", "paper-L64"])
+def test_topo_sim_graph_replays_match_direct_launches(name):
     """Whole rewiring intervals run as replays of a recorded graph of 64
     intervals.  Replays mixed with direct launches and host reads give the same
     state and rows, bit for bit, as the same steps in 10-step calls."""
-    cfg, model = CASES["hot-L16-blob"]
+    cfg, model = CASES[name]
     a, b = rb.TopoNet(cfg), rb.TopoNet(cfg)
     a.sim_init(model)
     b.sim_init(model)
@@ -247,11 +249,13 @@ def test_topo_sim_uses_rows_set_by_caller():
         compare(t, cfg, M, P, S)
 
 
-def test_topo_sim_long_run_spike_counts():
+@pytest.mark.parametrize("name", ["hot-L16-blob", "paper-L64"])
+def test_topo_sim_long_run_spike_counts(name):
     """Independent runs of 20000 steps (2 s of model time) from the same start:
     total spike counts agree within 1% (the input draws are shared, the
-    floating-point state is not resynchronised)."""
-    cfg, model = CASES["hot-L16-blob"]
+    floating-point state is not resynchronised).  paper-L64 is the benchmark's
+    map: 64 x 64, the paper's parameters, the moving bar."""
+    cfg, model = CASES[name]
     t = rb.TopoNet(cfg)
     t.sim_init(model)
     M = omodel(model, cfg.L)
