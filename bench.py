@@ -199,6 +199,158 @@ def tiny_net_leg(samples=20, oracle_samples=2):
             "gpu_over_oracle": round(orc_s / (el / steps), 2)}
 
 
+def batched_configs(n=None, seed=1):
+    """The batched-instances workload: n classifiers (recurrent sizes
+    log-uniform in [256, 4096], connection probabilities uniform in
+    [0.05, 0.2]) on the sparse classifier's input, batch 1 each."""
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    c = wl.BATCHED
+    n = n or c["n_inst"]
+    f32 = lambda x: float(np.float32(x))
+    cfgs = []
+    for i, (n_rec, p) in enumerate(wl.batched_sizes(seed, n, c["n_rec_lo"], c["n_rec_hi"], c["p_lo"], c["p_hi"])):
+        cfgs.append(rb.EpropConfig(n_in=c["n_in"], n_rec=n_rec, n_out=c["n_out"], batch=c["batch"], alif=c["alif"],
+                                   p_in=p, p_rec=p, sigma_in=f32(wl.sigma_init(p, c["n_in"])),
+                                   sigma_rec=f32(wl.sigma_init(p, n_rec)), sigma_out=f32(1.0 / np.sqrt(n_rec)),
+                                   deepr_mask=c["deepr_mask"], l1=c["l1"], lr=c["lr"],
+                                   update_interval=c["update_interval"], sample_steps=c["T"], seed=seed + 1 + i))
+    return cfgs
+
+
+def batched_leg(n=None, samples=3, plain_rounds=1):
+    """Batched instances: the set trained together (rs_multi: one launch per
+    kernel and block for all instances, the sample replayed from a graph,
+    the tuned e-prop schedule) against the plain loop that trains the same
+    networks one after another (rs_eprop_step per network), on the same GPU.
+    Both compute the same results bit for bit (tests/test_gpu_multi.py); one
+    round of the plain loop and one sample of the set both train every
+    instance on one sample."""
+    import torch
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    cfgs = batched_configs(n)
+    T = cfgs[0].sample_steps
+    gen = wl.ShdLike(T=T)
+    dev = []
+    for i in range(len(cfgs)):
+        labels, raster = gen.batch(seed=1, batch_index=i, B=1)
+        dev.append((torch.tensor(raster.off, dtype=torch.int32, device="cuda"),
+                    torch.tensor(raster.idx, dtype=torch.int32, device="cuda"),
+                    torch.tensor(labels, dtype=torch.int32, device="cuda")))
+    m = rb.MultiNet(cfgs)
+    for i, d in enumerate(dev):
+        m.set_input(i, *d)
+    n_syn = sum(int(m.get(i, rb.PROJ(0, rb.P_LEN)).sum() + m.get(i, rb.PROJ(1, rb.P_LEN)).sum())
+                for i in range(len(cfgs)))
+    m.train(5)  # tuning: one sample per e-prop schedule
+    m.train(1)  # the graph is recorded
+    torch.cuda.synchronize()
+    ev0 = sum(m.info(i).synaptic_events for i in range(len(cfgs)))
+    t0 = time.perf_counter()
+    m.train(samples)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ev1 = sum(m.info(i).synaptic_events for i in range(len(cfgs)))
+    sch = m.schedule()
+    m.close()
+    nets = [rb.EpropNet(c) for c in cfgs]
+    flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+    for net, d in zip(nets, dev):
+        net.set_input(*d)
+        net.step(T, flags)  # warm-up round
+    torch.cuda.synchronize()
+    pev0 = sum(net.info().synaptic_events for net in nets)
+    t1 = time.perf_counter()
+    for _ in range(plain_rounds):
+        for net in nets:
+            net.step(T, flags)
+    torch.cuda.synchronize()
+    pel = time.perf_counter() - t1
+    pev1 = sum(net.info().synaptic_events for net in nets)
+    for net in nets:
+        net.close()
+    ni = len(cfgs)
+    batched = ni * samples / el
+    plain = ni * plain_rounds / pel
+    return {"workload": f"{ni} e-prop classifiers 700 -> N_i ALIF -> 20, N_i log-uniform in [256, 4096], "
+                        f"p_i uniform in [0.05, 0.2], batch 1 each, {T} steps/sample, Adam + DEEP R every "
+                        f"{cfgs[0].update_interval} steps, synthetic SHD-shaped input",
+            "instances": ni, "synapses": n_syn,
+            "batched": {"samples_per_s": round(batched, 2), "ms_per_sample_of_the_set": round(1e3 * el / samples, 3),
+                        "synaptic_events_per_s": round((ev1 - ev0) / el, 1), "samples_timed": samples,
+                        "schedule": sch},
+            "plain_loop": {"samples_per_s": round(plain, 2), "ms_per_round": round(1e3 * pel / plain_rounds, 3),
+                           "synaptic_events_per_s": round((pev1 - pev0) / pel, 1), "rounds_timed": plain_rounds},
+            "batched_over_plain": round(batched / plain, 2),
+            "results": "identical bit for bit (tests/test_gpu_multi.py)"}
+
+
+def served_leg(duration_s=2.0, rate_hz=2000.0, baseline_requests=150, seed=1):
+    """Served inference: a Poisson request stream (mean rate_hz) of
+    classification runs on networks of 512, 1024, 2048 and 4096 ALIF neurons
+    (p = 0.1, 700 inputs, 20 readouts, weights from a fixed seed), presentation
+    lengths uniform in [200, 1500] steps, inputs from a pool of synthetic
+    SHD-shaped samples resident on the device.  Replayed against the wall
+    clock with continuous batching (rs_serve: requests join the running block
+    launches as slots free), and the first requests of the same trace with one
+    request per launch."""
+    import torch
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    f32 = lambda x: float(np.float32(x))
+    sizes = (512, 1024, 2048, 4096)
+    models = [rb.EpropNet(rb.EpropConfig(n_in=700, n_rec=n, n_out=20, batch=1, alif=True, p_in=0.1, p_rec=0.1,
+                                         sigma_in=f32(wl.sigma_init(0.1, 700)), sigma_rec=f32(wl.sigma_init(0.1, n)),
+                                         sigma_out=f32(1.0 / np.sqrt(n)), update_interval=0, sample_steps=1500,
+                                         seed=seed + q))
+              for q, n in enumerate(sizes)]
+    T = 1500
+    gen = wl.ShdLike(T=T)
+    pool = []
+    for q in range(16):
+        labels, raster = gen.batch(seed=seed, batch_index=100 + q, B=1)
+        pool.append((torch.tensor(raster.off, dtype=torch.int32, device="cuda"),
+                     torch.tensor(raster.idx, dtype=torch.int32, device="cuda"), T))
+    rng = np.random.Generator(np.random.Philox(seed + 31337))
+    n = int(rate_hz * duration_s)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate_hz, n))
+    ms = rng.integers(0, len(sizes), n)
+    lens = rng.integers(200, 1501, n)
+    rasters = [pool[q % len(pool)] for q in range(n)]
+    out = {"workload": f"Poisson requests at {rate_hz:g}/s for {duration_s:g} s on 700 -> N ALIF -> 20 classifiers, "
+                       f"N in {list(sizes)}, p = 0.1, presentation lengths uniform in [200, 1500] steps, "
+                       f"synthetic SHD-shaped inputs", "requests": n}
+    srv = rb.Server(models, slots_per_model=1024, block_steps=20, max_running=4096, state_budget_bytes=2 << 30)
+    # warm-up: a few requests through every model
+    srv.replay(np.zeros(8), np.arange(8) % 4, np.full(8, 40), rasters[:8])
+    t0 = time.perf_counter()
+    lat, dec, spk = srv.replay(arrivals, ms, lens, rasters)
+    el = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    ok = lat >= 0
+    out["continuous_batching"] = {
+        "p50_ms": round(float(np.percentile(lat[ok], 50)), 3), "p99_ms": round(float(np.percentile(lat[ok], 99)), 3),
+        "mean_ms": round(float(lat[ok].mean()), 3), "completed": int(ok.sum()), "rejected": int((~ok).sum()),
+        "samples_per_s": round(float(ok.sum()) / el, 1), "wall_s": round(el, 3),
+        "request_steps_per_s": round(float(lens[ok].sum()) / el, 1), "blocks": st["blocks"]}
+    nb = min(baseline_requests, n)
+    one = rb.Server(models, slots_per_model=1, block_steps=20, max_running=1, state_budget_bytes=2 << 30)
+    t0 = time.perf_counter()
+    lat1, dec1, spk1 = one.replay(arrivals[:nb], ms[:nb], lens[:nb], rasters[:nb])
+    el1 = time.perf_counter() - t0
+    one.close()
+    out["one_request_per_launch"] = {
+        "requests": nb, "p50_ms": round(float(np.percentile(lat1, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat1, 99)), 3), "samples_per_s": round(nb / el1, 1),
+        "wall_s": round(el1, 3)}
+    out["same_results_as_continuous"] = bool(np.array_equal(dec1, dec[:nb]) and np.array_equal(spk1, spk[:nb]))
+    for m in models:
+        m.close()
+    return out
+
+
 def forward_only_leg(steps=1000):
     """The classifier's forward pass alone (no eligibility work): wall time and
     the forward launches' device time over `steps` steps, after as many
@@ -344,6 +496,13 @@ def main():
                     help="run only the topographic-map end-to-end leg and print its figures (for profiling)")
     ap.add_argument("--topo-steps", type=int, default=1_000_000,
                     help="steps of the topographic-map leg (default 10^6 = 100 s of model time)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched-instances leg and print its figures (for profiling)")
+    ap.add_argument("--batched-instances", type=int, default=0, help="instances of the batched leg (default 64)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-served", action="store_true",
+                    help="run only the served-inference leg and print its figures (for profiling)")
+    ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--forward-only", action="store_true",
                     help="time only the classifier's forward pass, without learning (for profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -374,6 +533,12 @@ def main():
         return
     if args.only_topo:
         print(json.dumps({"topomap_sim": topo_sim_leg(steps=args.topo_steps)}), flush=True)
+        return
+    if args.only_served:
+        print(json.dumps({"served": served_leg()}), flush=True)
+        return
+    if args.only_batched:
+        print(json.dumps({"batched": batched_leg(args.batched_instances or None)}), flush=True)
         return
     if args.forward_only:
         print(json.dumps({"forward_only": forward_only_leg()}), flush=True)
@@ -479,6 +644,12 @@ def main():
     if not args.no_tiny:
         print("[bench] tiny e-prop network", file=sys.stderr, flush=True)
         result["tiny_net"] = tiny_net_leg()
+    if not args.no_batched:
+        print("[bench] batched instances against the plain loop", file=sys.stderr, flush=True)
+        result["batched"] = batched_leg(args.batched_instances or None)
+    if not args.no_served:
+        print("[bench] served inference", file=sys.stderr, flush=True)
+        result["served"] = served_leg()
     if not args.no_topo:
         print("[bench] topographic-map rewiring latency", file=sys.stderr, flush=True)
         result["topomap_rewire"] = topo_rewire_latency()

@@ -244,6 +244,138 @@ rs_status rs_eprop_phase_times(rs_eprop* net, double* ms, uint64_t* count);
 void rs_eprop_destroy(rs_eprop* net);
 
 /* ==========================================================================
+ * Batched networks: a set of e-prop classifiers of different sizes trained
+ * together, in the manner of the paper's batching of model copies (several
+ * instances of a model simulated in one kernel launch), here copies that
+ * differ in size and connection density.  Every kernel of a block of steps
+ * runs once for the whole set over a work list of (network, tile) entries;
+ * one whole training sample (its blocks of steps, the Adam updates, the DEEP R
+ * rewiring and the reset) is recorded once as a HIP graph and replayed.  Each
+ * network computes exactly what an rs_eprop object with the same parameters
+ * computes alone (bit for bit), whatever the schedule.
+ * ========================================================================== */
+typedef struct rs_multi rs_multi;
+
+/* Create the set from params[0 .. n-1] (n in 1..4096), built as
+ * rs_eprop_create builds each.  The networks may differ in n_rec, connection
+ * probabilities, weight spreads, capacities, DEEP R mask, L1 strength,
+ * learning rate and seed; they share n_in, n_out, batch, alif, dt and the time
+ * constants, update_interval, sample_steps, trace_block and the Adam decay
+ * rates.  The batch must not be a multiple of 4, and sample_steps a multiple
+ * of update_interval.  Synchronises.  Errors: RS_EINVAL, RS_ENOMEM,
+ * RS_EDEVICE. */
+rs_status rs_multi_create(const rs_eprop_params* params, uint32_t n, void* hip_stream, rs_multi** out);
+/* Input of network i, as rs_eprop_set_input / rs_eprop_set_input_poisson. */
+rs_status rs_multi_set_input(rs_multi* m, uint32_t i, const int32_t* off_dev, const int32_t* idx_dev,
+                             size_t n_idx, const int32_t* labels_dev);
+rs_status rs_multi_set_input_poisson(rs_multi* m, uint32_t i, const double* rate_hz, size_t n_rates,
+                                     const int32_t* labels_dev);
+/* Train every network of the set over n_samples whole samples: for each, what
+ * rs_eprop_step(net, sample_steps, RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)
+ * does.  Until the schedule is tuned, each sample runs with the next untried
+ * e-prop schedule by direct launches and is timed on the device; after the
+ * last the fastest is kept, and later samples replay the recorded graph.
+ * Errors: RS_ESTATE (an input is missing, or the set is not at a sample
+ * boundary), RS_EDEVICE. */
+rs_status rs_multi_train(rs_multi* m, uint32_t n_samples);
+
+#define RS_MULTI_SCHEDULES 8
+typedef struct rs_multi_schedule {
+  uint32_t tuned;            /* 1 once every schedule has been timed */
+  uint32_t schedule;         /* the schedule in use */
+  uint32_t threads_per_row;  /* e-prop: threads sharing one row's synapses (64 or 256) */
+  uint32_t rows_per_tile;    /* e-prop: rows per work-list entry */
+  uint32_t workgroups;       /* e-prop: persistent workgroups, 0 = one per entry */
+  uint32_t graph;            /* 1: samples replay the recorded graph */
+  uint32_t trace_block;      /* steps per block */
+  uint32_t reserved;
+  double sample_ms[RS_MULTI_SCHEDULES];  /* device time of the tuning sample run with each schedule */
+  uint64_t samples;          /* samples trained */
+} rs_multi_schedule;
+rs_status rs_multi_schedule_get(rs_multi* m, rs_multi_schedule* out);
+/* Fix the e-prop schedule (0..4), or -1 to tune again over the next samples;
+ * use_graph 0 runs samples by direct launches instead of graph replay. */
+rs_status rs_multi_schedule_set(rs_multi* m, int32_t schedule, int32_t use_graph);
+/* Variables and counters of network i, as rs_eprop_get / rs_eprop_set /
+ * rs_eprop_info_get (synchronising). */
+rs_status rs_multi_get(rs_multi* m, uint32_t i, int32_t var, void* host, size_t bytes);
+rs_status rs_multi_set(rs_multi* m, uint32_t i, int32_t var, const void* host, size_t bytes);
+rs_status rs_multi_info_get(rs_multi* m, uint32_t i, rs_eprop_info* out);
+void rs_multi_destroy(rs_multi* m);
+
+/* ==========================================================================
+ * Served inference: classification requests on trained networks (the
+ * recurrent classifier without learning: input, spikes, propagation, neuron
+ * update and leaky readout), with continuous batching.  A request presents an
+ * input raster to one model for n_steps steps; its decision is the argmax
+ * over readout units k of the summed softmax sum_t pi_k^t.  Each running
+ * request holds its neuron and readout state in a slot on the device; every
+ * rs_serve_step admits queued requests (in arrival order, skipping those
+ * whose model has no free slot) while their state fits the memory budget,
+ * then runs one block of steps for every running request in one forward and
+ * one readout launch.  A request's result depends only on its model and
+ * input, not on the others running beside it.
+ * ========================================================================== */
+typedef struct rs_serve rs_serve;
+typedef struct rs_serve_params {
+  uint32_t slots_per_model;      /* state slots allocated per model, 1..4096 */
+  uint32_t block_steps;          /* steps per block, 1..32 */
+  uint32_t max_running;          /* requests running at once (1: one request per launch) */
+  uint32_t max_queue;            /* queued requests beyond which submissions are rejected */
+  uint64_t state_budget_bytes;   /* device bytes the running requests' state may take */
+} rs_serve_params;
+typedef struct rs_serve_result {
+  uint64_t ticket;
+  uint32_t model, steps;
+  int32_t decision;              /* argmax_k sum_t pi_k^t */
+  uint32_t reserved;
+  uint64_t spikes, events;       /* recurrent spikes, synaptic events of the request */
+  double submit_s, admit_s, done_s;  /* host clock, seconds since the server's creation */
+} rs_serve_result;
+typedef struct rs_serve_stats {
+  uint64_t admitted, rejected, completed, blocks;
+  uint64_t queued;
+  uint32_t running, n_out_max;
+  uint64_t state_bytes_used, state_budget_bytes;
+  double clock_s;
+} rs_serve_stats;
+/* Create a server for the models (trained networks, kept by pointer: they
+ * must outlive the server and not be stepped while it runs; weights and rows
+ * are read in place).  Every model takes the same n_in.  Errors: RS_EINVAL,
+ * RS_ENOMEM, RS_EDEVICE. */
+rs_status rs_serve_create(rs_eprop* const* models, uint32_t n_models, const rs_serve_params* params,
+                          void* hip_stream, rs_serve** out);
+/* Queue a request: model index, the input raster (device pointers, B = 1
+ * layout of rs_eprop_set_input with raster_steps steps, read cyclically), the
+ * presentation length.  Errors: RS_ECAPACITY (rejected: queue full, or the
+ * request's state exceeds the budget), RS_EINVAL. */
+rs_status rs_serve_submit(rs_serve* s, uint32_t model, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
+                          uint32_t raster_steps, uint32_t n_steps, uint64_t* ticket);
+/* Admit, run one block for every running request and synchronise; *n_done =
+ * requests that finished in it. */
+rs_status rs_serve_step(rs_serve* s, uint32_t* n_done);
+/* Take up to max finished results (in completion order); scores (NULL or
+ * [max][n_out_max] doubles) receives each one's sum_t pi. */
+rs_status rs_serve_poll(rs_serve* s, rs_serve_result* out, double* scores, uint32_t max, uint32_t* n);
+rs_status rs_serve_stats_get(rs_serve* s, rs_serve_stats* out);
+/* One request of a trace: arrival time in seconds from the replay's start. */
+typedef struct rs_serve_request {
+  double arrival_s;
+  uint32_t model, n_steps, raster_steps, reserved;
+  const int32_t* off_dev;
+  const int32_t* idx_dev;
+  size_t n_idx;
+} rs_serve_request;
+/* Replay a trace (arrivals ascending) against the host's wall clock: each
+ * request is submitted once its arrival time has passed, blocks run while
+ * requests run, and the call returns when every request has finished or
+ * been rejected.  Per request (arrays of n, each may be NULL): latency from
+ * arrival to completion in ms (-1 if rejected), decision, spikes. */
+rs_status rs_serve_replay(rs_serve* s, const rs_serve_request* reqs, uint32_t n, double* latency_ms,
+                          int32_t* decision, uint64_t* spikes);
+void rs_serve_destroy(rs_serve* s);
+
+/* ==========================================================================
  * Topographic-map projection (Sec. 2.1.3, Fig. 3; model in Tab. A-H): two
  * L x L sheets with periodic boundaries, rows capped at `cap` synapses.
  * ========================================================================== */

@@ -85,7 +85,7 @@ class _CNet(C.Structure):
     _fields_ = [("n_in", C.c_int32), ("n_rec", C.c_int32), ("n_out", C.c_int32),
                 ("batch", C.c_int32), ("alif", C.c_int32),
                 ("alpha", C.c_double), ("rho", C.c_double), ("v_thr", C.c_double),
-                ("beta", C.c_double),
+                ("beta", C.c_double), ("alpha_trace", C.c_double),
                 ("inp", C.POINTER(_CProj)), ("rec", C.POINTER(_CProj)),
                 ("v", P_f64), ("a", P_f64), ("y", P_f64), ("xbar", P_f64), ("zbar", P_f64),
                 ("Wout", P_f64), ("bout", P_f64), ("Gout", P_f64), ("Gb", P_f64),
@@ -358,12 +358,20 @@ class EpropParams:
     # explicit decay factors; None derives them from dt and the time constants
     alpha_value: float | None = None
     rho_value: float | None = None
+    # decay of the presynaptic traces; None uses alpha
+    alpha_trace_value: float | None = None
 
     @property
     def alpha(self):
         if self.alpha_value is not None:
             return float(self.alpha_value)
         return float(np.exp(-self.dt_ms / self.tau_mem_ms))
+
+    @property
+    def alpha_trace(self):
+        if self.alpha_trace_value is not None:
+            return float(self.alpha_trace_value)
+        return self.alpha
 
     @property
     def rho(self):
@@ -413,6 +421,7 @@ class Net:
         s = _CNet()
         s.n_in, s.n_rec, s.n_out, s.batch, s.alif = p.n_in, p.n_rec, p.n_out, p.batch, int(p.alif)
         s.alpha, s.rho, s.v_thr, s.beta = p.alpha, p.rho, p.v_thr, p.beta_eff
+        s.alpha_trace = p.alpha_trace
         self._ci, self._cr = self.inp.c(), self.rec.c()
         s.inp, s.rec = C.pointer(self._ci), C.pointer(self._cr)
         for name in ["v", "a", "y", "xbar", "zbar", "Wout", "bout", "Gout", "Gb",

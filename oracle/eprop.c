@@ -91,9 +91,9 @@ static void accumulate_grad(const orc_net *N, orc_proj *P)
             int32_t j = P->ind[s];
             double g = 0.0, ga = 0.0;
             for (int32_t b = 0; b < B; ++b) {
-                double term = N->L[(int64_t)b * N->n_rec + j] * P->ebar[s * B + b];
-                g += term;
-                ga += fabs(term);
+                double L = N->L[(int64_t)b * N->n_rec + j], eb = P->ebar[s * B + b];
+                g += L * eb;
+                if (N->Labs) ga += fabs(eb) * (2.0 * fabs(L) + N->Labs[(int64_t)b * N->n_rec + j]);
             }
             P->G[s] += g;
             if (P->Gabs) P->Gabs[s] += ga;
@@ -153,9 +153,9 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         }
         /* 5. presynaptic traces */
         for (int32_t i = 0; i < NI; ++i)
-            N->xbar[(int64_t)b * NI + i] = N->alpha * N->xbar[(int64_t)b * NI + i] + x[i];
+            N->xbar[(int64_t)b * NI + i] = N->alpha_trace * N->xbar[(int64_t)b * NI + i] + x[i];
         for (int32_t j = 0; j < NR; ++j)
-            N->zbar[(int64_t)b * NR + j] = N->alpha * N->zbar[(int64_t)b * NR + j] + zb[j];
+            N->zbar[(int64_t)b * NR + j] = N->alpha_trace * N->zbar[(int64_t)b * NR + j] + zb[j];
         /* 6. leaky readout, softmax, output error */
         double *yb = N->y + (int64_t)b * K;
         double ymax = -INFINITY;
@@ -175,9 +175,9 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         for (int32_t j = 0; j < NR; ++j) {
             double l = 0.0, la = 0.0;
             for (int32_t k = 0; k < K; ++k) {
-                double term = N->Wout[(int64_t)k * NR + j] * N->delta[(int64_t)b * K + k];
-                l += term;
-                la += fabs(term);
+                double d = N->delta[(int64_t)b * K + k], pi = d + (k == labels[b] ? 1.0 : 0.0);
+                l += N->Wout[(int64_t)k * NR + j] * d;
+                la += fabs(N->Wout[(int64_t)k * NR + j]) * (fabs(d) + pi);
             }
             N->L[(int64_t)b * NR + j] = l;
             if (N->Labs) N->Labs[(int64_t)b * NR + j] = la;
@@ -186,12 +186,14 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         if (learn) {
             for (int32_t k = 0; k < K; ++k) {
                 double d = N->delta[(int64_t)b * K + k];
+                double pi = d + (k == labels[b] ? 1.0 : 0.0);
                 for (int32_t j = 0; j < NR; ++j) {
-                    N->Gout[(int64_t)k * NR + j] += d * N->zbar[(int64_t)b * NR + j];
-                    if (N->Goutabs) N->Goutabs[(int64_t)k * NR + j] += fabs(d * N->zbar[(int64_t)b * NR + j]);
+                    double zb_ = N->zbar[(int64_t)b * NR + j];
+                    N->Gout[(int64_t)k * NR + j] += d * zb_;
+                    if (N->Goutabs) N->Goutabs[(int64_t)k * NR + j] += fabs(zb_) * (2.0 * fabs(d) + pi);
                 }
                 N->Gb[k] += d;
-                if (N->Gbabs) N->Gbabs[k] += fabs(d);
+                if (N->Gbabs) N->Gbabs[k] += fabs(d) + pi;
             }
         }
     }

@@ -83,9 +83,11 @@ typedef struct orc_proj {
     uint32_t *conn, *sign; /* [n_pre*words] or NULL */
     int32_t words;         /* ceil(n_post/32) */
     /* Error-bound bookkeeping for tests, no part of the method (may be NULL):
-     * Gabs[s] accumulates sum |L_j ebar_ji| beside G, the magnitude of the
-     * terms whose sum G is, so that a test can bound a sum with cancellation
-     * per element.  It is cleared, moved and zeroed together with G. */
+     * Gabs[s] accumulates, beside G, the first-order error scale of its terms
+     * L_j ebar_ji when L is known to r (|L| + Labs) and ebar to r |ebar|:
+     * sum_b |ebar| (2 |L| + Labs), so that a test can bound G per element by
+     * r (|G| + Gabs) despite cancellation.  Needs the net's Labs; cleared,
+     * moved and zeroed together with G. */
     double *Gabs;
 } orc_proj;
 
@@ -94,6 +96,8 @@ typedef struct orc_net {
     int32_t n_in, n_rec, n_out, batch;
     int32_t alif;           /* 0: LIF (beta = rho = 0) */
     double alpha, rho, v_thr, beta;
+    double alpha_trace;     /* decay of the presynaptic traces xbar, zbar: alpha, or
+                               alpha as a float implementation stores it */
     orc_proj *in, *rec;
     double *v, *a;          /* [B][n_rec] */
     double *y;              /* [B][n_out] */
@@ -106,9 +110,12 @@ typedef struct orc_net {
     double *psi, *L;        /* [B][n_rec] */
     uint8_t *z;             /* [B][n_rec] spikes emitted this step */
     double *delta;          /* [B][n_out] pi - onehot(label) */
-    /* Error-bound bookkeeping for tests (each may be NULL): Labs[B][n_rec]
-     * = sum_k |W_out[k][j] delta_k| of the last step; Goutabs and Gbabs
-     * accumulate |delta_k zbar_j| and |delta_k| beside Gout and Gb. */
+    /* Error-bound bookkeeping for tests (each may be NULL): first-order
+     * error scales of the sums with cancellation when delta_k = pi_k -
+     * [k = label] is known to r (|delta_k| + pi_k) (pi rounds relative to
+     * itself) and zbar to r |zbar|.  Labs[B][n_rec] = sum_k |W_out[k][j]|
+     * (|delta_k| + pi_k) of the last step; beside Gout and Gb, Goutabs
+     * accumulates |zbar_j| (2 |delta_k| + pi_k) and Gbabs |delta_k| + pi_k. */
     double *Labs, *Goutabs, *Gbabs;
 } orc_net;
 

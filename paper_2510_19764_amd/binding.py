@@ -86,6 +86,11 @@ EXPORTS = [
     "rs_topo_create", "rs_topo_rewire", "rs_topo_get_rows", "rs_topo_set_rows", "rs_topo_get_bits",
     "rs_topo_last_ms", "rs_topo_destroy", "rs_topo_sim_init", "rs_topo_run", "rs_topo_run_stats",
     "rs_topo_sim_get", "rs_topo_sim_set", "rs_topo_sim_timing", "rs_topo_sim_phase_ms", "rs_calib_copy",
+    "rs_multi_create", "rs_multi_set_input", "rs_multi_set_input_poisson", "rs_multi_train",
+    "rs_multi_schedule_get", "rs_multi_schedule_set", "rs_multi_get", "rs_multi_set", "rs_multi_info_get",
+    "rs_multi_destroy",
+    "rs_serve_create", "rs_serve_submit", "rs_serve_step", "rs_serve_poll", "rs_serve_stats_get",
+    "rs_serve_replay", "rs_serve_destroy",
 ]
 
 _lib = None
@@ -134,9 +139,32 @@ def lib():
         L.rs_topo_sim_timing.argtypes = [vp, C.c_int32]
         L.rs_topo_sim_phase_ms.argtypes = [vp, C.POINTER(C.c_double)]
         L.rs_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
+        L.rs_multi_create.argtypes = [C.POINTER(_EpropParams), C.c_uint32, vp, C.POINTER(vp)]
+        L.rs_multi_set_input.argtypes = [vp, C.c_uint32, vp, vp, C.c_size_t, vp]
+        L.rs_multi_set_input_poisson.argtypes = [vp, C.c_uint32, C.POINTER(C.c_double), C.c_size_t, vp]
+        L.rs_multi_train.argtypes = [vp, C.c_uint32]
+        L.rs_multi_schedule_get.argtypes = [vp, C.POINTER(_MultiSchedule)]
+        L.rs_multi_schedule_set.argtypes = [vp, C.c_int32, C.c_int32]
+        L.rs_multi_get.argtypes = [vp, C.c_uint32, C.c_int32, vp, C.c_size_t]
+        L.rs_multi_set.argtypes = [vp, C.c_uint32, C.c_int32, vp, C.c_size_t]
+        L.rs_multi_info_get.argtypes = [vp, C.c_uint32, C.POINTER(_Info)]
+        L.rs_multi_destroy.argtypes = [vp]
+        L.rs_multi_destroy.restype = None
+        L.rs_serve_create.argtypes = [C.POINTER(vp), C.c_uint32, C.POINTER(_ServeParams), vp, C.POINTER(vp)]
+        L.rs_serve_submit.argtypes = [vp, C.c_uint32, vp, vp, C.c_size_t, C.c_uint32, C.c_uint32,
+                                      C.POINTER(C.c_uint64)]
+        L.rs_serve_step.argtypes = [vp, C.POINTER(C.c_uint32)]
+        L.rs_serve_poll.argtypes = [vp, C.POINTER(_ServeResult), C.POINTER(C.c_double), C.c_uint32,
+                                    C.POINTER(C.c_uint32)]
+        L.rs_serve_stats_get.argtypes = [vp, C.POINTER(_ServeStats)]
+        L.rs_serve_replay.argtypes = [vp, C.POINTER(_ServeRequest), C.c_uint32, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]
+        L.rs_serve_destroy.argtypes = [vp]
+        L.rs_serve_destroy.restype = None
         for name in EXPORTS:
             f = getattr(L, name)
-            if name not in ("rs_last_error", "rs_eprop_destroy", "rs_topo_destroy"):
+            if name not in ("rs_last_error", "rs_eprop_destroy", "rs_topo_destroy", "rs_multi_destroy",
+                            "rs_serve_destroy"):
                 f.restype = st
         _lib = L
     return _lib
@@ -259,26 +287,7 @@ class EpropNet:
 
     # ---- snapshots
     def shape_of(self, var: int):
-        c, inf = self.cfg, self._info
-        B, NR, NI, K = c.batch, c.n_rec, c.n_in, c.n_out
-        net = {V: ((B, NR), np.float64), A: ((B, NR), np.float64), Y: ((B, K), np.float64),
-               XBAR: ((B, NI), np.float32), ZBAR: ((B, NR), np.float32), PSI: ((NR, B), np.float32),
-               LSIG: ((NR, B), np.float32), DELTA: ((K, B), np.float32), Z: ((B, NR), np.uint8),
-               WOUT: ((K, NR), np.float32), BOUT: ((K,), np.float32), GOUT: ((K, NR), np.float32),
-               GB: ((K,), np.float32), MOUT: ((K, NR), np.float32), VOUT: ((K, NR), np.float32),
-               MB: ((K,), np.float32), VB: ((K,), np.float32), ZCOUNT: ((B, NR), np.uint32),
-               ZBITS: ((NR, B), np.uint32)}
-        if var in net:
-            return net[var]
-        p, f = var // 0x100 - 1, var % 0x100
-        n_pre = NI if p == 0 else NR
-        cap = inf.cap_in if p == 0 else inf.cap_rec
-        words = inf.words_in if p == 0 else inf.words_rec
-        return {P_LEN: ((n_pre,), np.int32), P_IND: ((n_pre, cap), np.int32), P_W: ((n_pre, cap), np.float32),
-                P_M: ((n_pre, cap), np.float32), P_V: ((n_pre, cap), np.float32), P_G: ((n_pre, cap), np.float32),
-                P_EPS: ((n_pre, cap, B), np.float32), P_EBAR: ((n_pre, cap, B), np.float32),
-                P_CONN: ((n_pre, words), np.uint32), P_SIGN: ((n_pre, words), np.uint32),
-                P_DORMANT: ((n_pre,), np.int32)}[f]
+        return _shape_of(self.cfg, self._info, var)
 
     def get(self, var: int) -> np.ndarray:
         shape, dt = self.shape_of(var)
@@ -307,6 +316,215 @@ class EpropNet:
         cnt = (C.c_uint64 * NUM_PHASES)()
         _check(lib().rs_eprop_phase_times(self._h, ms, cnt))
         return {PHASES[q]: (ms[q], cnt[q]) for q in range(NUM_PHASES)}
+
+
+def _shape_of(c, inf, var: int):
+    """Shape and dtype of variable `var` of a network with config c and info inf."""
+    B, NR, NI, K = c.batch, c.n_rec, c.n_in, c.n_out
+    net = {V: ((B, NR), np.float64), A: ((B, NR), np.float64), Y: ((B, K), np.float64),
+           XBAR: ((B, NI), np.float32), ZBAR: ((B, NR), np.float32), PSI: ((NR, B), np.float32),
+           LSIG: ((NR, B), np.float32), DELTA: ((K, B), np.float32), Z: ((B, NR), np.uint8),
+           WOUT: ((K, NR), np.float32), BOUT: ((K,), np.float32), GOUT: ((K, NR), np.float32),
+           GB: ((K,), np.float32), MOUT: ((K, NR), np.float32), VOUT: ((K, NR), np.float32),
+           MB: ((K,), np.float32), VB: ((K,), np.float32), ZCOUNT: ((B, NR), np.uint32),
+           ZBITS: ((NR, B), np.uint32)}
+    if var in net:
+        return net[var]
+    p, f = var // 0x100 - 1, var % 0x100
+    n_pre = NI if p == 0 else NR
+    cap = inf.cap_in if p == 0 else inf.cap_rec
+    words = inf.words_in if p == 0 else inf.words_rec
+    return {P_LEN: ((n_pre,), np.int32), P_IND: ((n_pre, cap), np.int32), P_W: ((n_pre, cap), np.float32),
+            P_M: ((n_pre, cap), np.float32), P_V: ((n_pre, cap), np.float32), P_G: ((n_pre, cap), np.float32),
+            P_EPS: ((n_pre, cap, B), np.float32), P_EBAR: ((n_pre, cap, B), np.float32),
+            P_CONN: ((n_pre, words), np.uint32), P_SIGN: ((n_pre, words), np.uint32),
+            P_DORMANT: ((n_pre,), np.int32)}[f]
+
+
+class _ServeParams(C.Structure):
+    _fields_ = [("slots_per_model", C.c_uint32), ("block_steps", C.c_uint32), ("max_running", C.c_uint32),
+                ("max_queue", C.c_uint32), ("state_budget_bytes", C.c_uint64)]
+
+
+class _ServeResult(C.Structure):
+    _fields_ = [("ticket", C.c_uint64), ("model", C.c_uint32), ("steps", C.c_uint32), ("decision", C.c_int32),
+                ("reserved", C.c_uint32), ("spikes", C.c_uint64), ("events", C.c_uint64),
+                ("submit_s", C.c_double), ("admit_s", C.c_double), ("done_s", C.c_double)]
+
+
+class _ServeStats(C.Structure):
+    _fields_ = [("admitted", C.c_uint64), ("rejected", C.c_uint64), ("completed", C.c_uint64),
+                ("blocks", C.c_uint64), ("queued", C.c_uint64), ("running", C.c_uint32),
+                ("n_out_max", C.c_uint32), ("state_bytes_used", C.c_uint64), ("state_budget_bytes", C.c_uint64),
+                ("clock_s", C.c_double)]
+
+
+class _ServeRequest(C.Structure):
+    _fields_ = [("arrival_s", C.c_double), ("model", C.c_uint32), ("n_steps", C.c_uint32),
+                ("raster_steps", C.c_uint32), ("reserved", C.c_uint32), ("off_dev", C.c_void_p),
+                ("idx_dev", C.c_void_p), ("n_idx", C.c_size_t)]
+
+
+class Server:
+    """Served inference with continuous batching over trained networks (rs_serve_*).
+    `models` are EpropNet objects, kept alive by the server."""
+
+    def __init__(self, models, slots_per_model=256, block_steps=20, max_running=1024, max_queue=1 << 20,
+                 state_budget_bytes=1 << 30, stream=None):
+        self.models = list(models)
+        arr = (C.c_void_p * len(self.models))(*[m._h.value for m in self.models])
+        prm = _ServeParams(slots_per_model, block_steps, max_running, max_queue, state_budget_bytes)
+        self._h = C.c_void_p()
+        self._refs = []
+        _check(lib().rs_serve_create(arr, len(self.models), C.byref(prm), _stream_ptr(stream), C.byref(self._h)))
+        self.n_out_max = max(m.cfg.n_out for m in self.models)
+
+    def close(self):
+        if self._h:
+            lib().rs_serve_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, model, off, idx, raster_steps, n_steps):
+        """off/idx: int32 CUDA tensors of a batch-1 raster (kept alive by the server).
+        Returns the ticket, or None if the request was rejected."""
+        self._refs.append((off, idx))
+        t = C.c_uint64()
+        code = lib().rs_serve_submit(self._h, model, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
+                                     idx.numel(), raster_steps, n_steps, C.byref(t))
+        if code == RS_ECAPACITY:
+            return None
+        _check(code)
+        return t.value
+
+    def step(self) -> int:
+        n = C.c_uint32()
+        _check(lib().rs_serve_step(self._h, C.byref(n)))
+        return n.value
+
+    def poll(self, max_results=4096):
+        out = (_ServeResult * max_results)()
+        sc = np.zeros((max_results, self.n_out_max), np.float64)
+        n = C.c_uint32()
+        _check(lib().rs_serve_poll(self._h, out, sc.ctypes.data_as(C.POINTER(C.c_double)), max_results,
+                                   C.byref(n)))
+        res = []
+        for q in range(n.value):
+            r = out[q]
+            res.append(dict(ticket=r.ticket, model=r.model, steps=r.steps, decision=r.decision, spikes=r.spikes,
+                            events=r.events, submit_s=r.submit_s, admit_s=r.admit_s, done_s=r.done_s,
+                            scores=sc[q].copy()))
+        return res
+
+    def stats(self) -> dict:
+        st = _ServeStats()
+        _check(lib().rs_serve_stats_get(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in _ServeStats._fields_}
+
+    def replay(self, arrivals_s, models, n_steps, rasters):
+        """rasters: list of (off, idx, raster_steps) device inputs, one per request.
+        Returns latency_ms, decision, spikes arrays (latency -1 if rejected)."""
+        n = len(arrivals_s)
+        reqs = (_ServeRequest * n)()
+        for q in range(n):
+            off, idx, T = rasters[q]
+            self._refs.append((off, idx))
+            reqs[q] = _ServeRequest(float(arrivals_s[q]), int(models[q]), int(n_steps[q]), int(T), 0,
+                                    C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()), idx.numel())
+        lat = np.zeros(n, np.float64)
+        dec = np.zeros(n, np.int32)
+        spk = np.zeros(n, np.uint64)
+        _check(lib().rs_serve_replay(self._h, reqs, n, lat.ctypes.data_as(C.POINTER(C.c_double)),
+                                     dec.ctypes.data_as(C.POINTER(C.c_int32)),
+                                     spk.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return lat, dec, spk
+
+
+class _MultiSchedule(C.Structure):
+    _fields_ = [("tuned", C.c_uint32), ("schedule", C.c_uint32), ("threads_per_row", C.c_uint32),
+                ("rows_per_tile", C.c_uint32), ("workgroups", C.c_uint32), ("graph", C.c_uint32),
+                ("trace_block", C.c_uint32), ("reserved", C.c_uint32), ("sample_ms", C.c_double * 8),
+                ("samples", C.c_uint64)]
+
+
+class MultiNet:
+    """A set of e-prop networks of different sizes trained together (rs_multi_*)."""
+
+    def __init__(self, cfgs, stream=None):
+        self.cfgs = list(cfgs)
+        arr = (_EpropParams * len(self.cfgs))(*[c.c() for c in self.cfgs])
+        self._h = C.c_void_p()
+        self._stream = _stream_ptr(stream)
+        self._input_refs = [None] * len(self.cfgs)
+        _check(lib().rs_multi_create(arr, len(self.cfgs), self._stream, C.byref(self._h)))
+        self._infos = [None] * len(self.cfgs)
+        for i in range(len(self.cfgs)):
+            self.info(i)
+
+    def close(self):
+        if self._h:
+            lib().rs_multi_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.cfgs)
+
+    def set_input(self, i, off, idx, labels):
+        import torch
+        for t in (off, idx, labels):
+            assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int32 and t.is_contiguous()
+        self._input_refs[i] = (off, idx, labels)
+        _check(lib().rs_multi_set_input(self._h, i, C.c_void_p(off.data_ptr()), C.c_void_p(idx.data_ptr()),
+                                        idx.numel(), C.c_void_p(labels.data_ptr())))
+
+    def set_input_poisson(self, i, rates_hz, labels):
+        import torch
+        assert isinstance(labels, torch.Tensor) and labels.is_cuda and labels.dtype == torch.int32
+        r = np.ascontiguousarray(rates_hz, np.float64)
+        self._input_refs[i] = (labels,)
+        _check(lib().rs_multi_set_input_poisson(self._h, i, r.ctypes.data_as(C.POINTER(C.c_double)), r.size,
+                                                C.c_void_p(labels.data_ptr())))
+
+    def train(self, n_samples: int = 1):
+        _check(lib().rs_multi_train(self._h, n_samples))
+
+    def schedule(self) -> dict:
+        s = _MultiSchedule()
+        _check(lib().rs_multi_schedule_get(self._h, C.byref(s)))
+        return dict(tuned=bool(s.tuned), schedule=s.schedule, threads_per_row=s.threads_per_row,
+                    rows_per_tile=s.rows_per_tile, workgroups=s.workgroups, graph=bool(s.graph),
+                    trace_block=s.trace_block, sample_ms=list(s.sample_ms)[:5], samples=s.samples)
+
+    def set_schedule(self, schedule: int, use_graph: bool = True):
+        _check(lib().rs_multi_schedule_set(self._h, schedule, int(use_graph)))
+
+    def get(self, i: int, var: int) -> np.ndarray:
+        shape, dt = _shape_of(self.cfgs[i], self._infos[i], var)
+        a = np.empty(shape, dt)
+        _check(lib().rs_multi_get(self._h, i, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+        return a
+
+    def set(self, i: int, var: int, value):
+        shape, dt = _shape_of(self.cfgs[i], self._infos[i], var)
+        a = np.ascontiguousarray(np.asarray(value, dtype=dt).reshape(shape))
+        _check(lib().rs_multi_set(self._h, i, var, a.ctypes.data_as(C.c_void_p), a.nbytes))
+
+    def info(self, i: int) -> _Info:
+        inf = _Info()
+        _check(lib().rs_multi_info_get(self._h, i, C.byref(inf)))
+        self._infos[i] = inf
+        return inf
 
 
 @dataclass

@@ -9,12 +9,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libragsnn.so")
-SOURCES = ["engine.hip", "k_build.hip", "k_forward.hip", "k_eprop.hip", "k_update.hip", "k_deepr.hip", "k_topo.hip", "k_topo_sim.hip"]
+SOURCES = ["engine.hip", "k_build.hip", "k_forward.hip", "k_eprop.hip", "k_update.hip", "k_deepr.hip", "k_topo.hip", "k_topo_sim.hip", "k_serve.hip"]
 HEADERS = ["rs_device.hpp", "rs_kernels.hpp", "rs_compact.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # every multiply-add is rounded as written (or is an explicit fma): the
+    # compiler may not fuse differently in different instantiations of a kernel
+    "-ffp-contract=off",
     # packed FP32 instructions stay disabled in every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",

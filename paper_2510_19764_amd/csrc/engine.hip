@@ -3,11 +3,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/ragsnn.h"
@@ -422,16 +425,18 @@ void reset_state(rs_eprop* n, hipStream_t s) {
   }
 }
 
-void do_update(rs_eprop* n, hipStream_t s) {
-  n->adam_k += 1;
+// Bias corrections of Adam update k, rounded to float as the kernels use them.
+float adam_inv_c(double b, uint32_t k) { return (float)(1.0 / (1.0 - std::pow(b, (double)k))); }
+
+UpdateArgs update_args(const rs_eprop* n, uint32_t k) {
   UpdateArgs u{};
   u.B = n->B;
   u.lr = n->p.lr;
   u.b1 = n->p.adam_b1;
   u.b2 = n->p.adam_b2;
   u.eps = n->p.adam_eps;
-  u.inv_c1 = (float)(1.0 / (1.0 - std::pow((double)n->p.adam_b1, (double)n->adam_k)));
-  u.inv_c2 = (float)(1.0 / (1.0 - std::pow((double)n->p.adam_b2, (double)n->adam_k)));
+  u.inv_c1 = adam_inv_c((double)n->p.adam_b1, k);
+  u.inv_c2 = adam_inv_c((double)n->p.adam_b2, k);
   u.l1 = n->p.l1;
   u.l1_in = (n->p.deepr_mask & 1) != 0;
   u.l1_rec = (n->p.deepr_mask & 2) != 0;
@@ -441,8 +446,13 @@ void do_update(rs_eprop* n, hipStream_t s) {
   u.Mout = n->Mout; u.Vout = n->Vout; u.Mb = n->Mb; u.Vb = n->Vb;
   u.n_out_elems = (int)(n->p.n_out * n->p.n_rec);
   u.n_b = (int)n->p.n_out;
+  return u;
+}
+
+void do_update(rs_eprop* n, hipStream_t s) {
+  n->adam_k += 1;
   n->timer.begin(s, 2);
-  launch_update(s, u);
+  launch_update(s, update_args(n, n->adam_k));
   n->timer.end(s);
 }
 
@@ -469,19 +479,10 @@ void order(hipEvent_t ev, hipStream_t from, hipStream_t to) {
   (void)hipStreamWaitEvent(to, ev, 0);
 }
 
-// Run the open block (steps accumulated since the last flush): one forward
-// launch for all its steps on the caller's stream, writing ring segment
-// blk_seg, then the e-prop launch on the side stream.  The forward pass of
-// the next block (next segment) overlaps this e-prop launch; a segment is
-// reused only after the e-prop launch that read it has finished.
-void flush_block(rs_eprop* n) {
-  if (n->blk_n == 0) return;
-  hipStream_t s = n->stream, e = n->side;
-  const int h = n->blk_seg;
-  if (n->ep_pending[h]) {
-    (void)hipStreamWaitEvent(s, n->ev_ep[h], 0);
-    n->ep_pending[h] = false;
-  }
+// Arguments of one block's launches: steps t0 .. t0 + nsteps - 1 (absolute
+// step numbers), ring segment h.  Shared by the one-network path and the
+// multi-network launches, so both compute the same thing.
+FwdArgs block_fwd_args(const rs_eprop* n, int h, uint64_t t0, int nsteps) {
   FwdArgs f{};
   f.n_in = (int)n->p.n_in; f.n_rec = (int)n->p.n_rec; f.n_out = (int)n->p.n_out; f.B = n->B;
   f.alpha = n->alpha; f.rho = n->rho; f.v_thr = n->p.v_thr; f.beta = n->beta;
@@ -498,16 +499,18 @@ void flush_block(rs_eprop* n) {
   f.x_off = n->x_off; f.x_idx = n->x_idx; f.n_idx = n->n_idx;
   if (n->poisson) {
     f.x_thr = n->x_thr; f.x_thr_stride = n->x_thr_stride; f.x_list = n->x_list;
-    f.seed = n->p.seed; f.step0 = n->blk_t0;
+    f.seed = n->p.seed; f.step0 = t0;
   }
-  f.t0 = (int)(n->blk_t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = n->blk_n;
+  f.t0 = (int)(t0 % n->p.sample_steps); f.sample_steps = (int)n->p.sample_steps; f.nsteps = nsteps;
   f.counters = n->counters;
   // small networks keep their rows on chip for the block; a large one's
   // forward workgroups leave LDS to the e-prop launch beside them
   f.rows_lds = n->single ? 1 : 0;
   f.zcount = n->zcount;
-  n->timer.begin(s, 0);
-  launch_fwd(s, f);
+  return f;
+}
+
+HandoffArrays block_handoff_args(const rs_eprop* n, int h, int nsteps) {
   HandoffArrays ho{};
   const size_t NI = n->p.n_in, NR = n->p.n_rec, B = n->B;
   uint32_t* dst[HANDOFF_ARRAYS] = {(uint32_t*)n->psiT, (uint32_t*)(n->x0T + h * NI * B),
@@ -518,44 +521,70 @@ void flush_block(rs_eprop* n) {
     ho.src[q] = n->stg[q];
     ho.dst[q] = dst[q];
     ho.n[q] = dims[q];
-    ho.steps[q] = q == 0 ? n->blk_n : 1;  // psi per step into the ring, the rest once per block
+    ho.steps[q] = q == 0 ? nsteps : 1;  // psi per step into the ring, the rest once per block
     ho.slot0[q] = q == 0 ? h * n->K : 0;
     ho.nslot[q] = q == 0 ? n->nslot : 1;
   }
-  launch_handoff_transpose(s, ho, n->B);
+  return ho;
+}
+
+ReadoutArgs block_readout_args(const rs_eprop* n, int h, int nsteps) {
+  ReadoutArgs ro{};
+  ro.n_rec = (int)n->p.n_rec; ro.n_out = (int)n->p.n_out; ro.B = n->B; ro.nsteps = nsteps;
+  ro.slot0 = h * n->K; ro.nslot = n->nslot;
+  ro.alpha = n->alpha;
+  ro.u = n->u_stg + (size_t)h * n->K * n->B * n->p.n_out;
+  ro.Y = n->Y; ro.Wout = n->Wout; ro.bout = n->bout; ro.labels = n->labels;
+  ro.deltaT = n->deltaT; ro.LT = n->LT;
+  return ro;
+}
+
+EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
+  const size_t NI = n->p.n_in, NR = n->p.n_rec, B = n->B;
+  EpropArgs a{};
+  a.n_in = (int)NI; a.n_rec = (int)NR; a.n_out = (int)n->p.n_out; a.B = n->B;
+  a.alif = n->p.alif ? 1 : 0;
+  a.alpha = (float)n->alpha; a.rho = (float)n->rho; a.beta = (float)n->beta;
+  a.one_m_rho = (float)(1.0 - n->rho);
+  a.in = n->in; a.rec = n->rec;
+  a.x0 = n->x0T + h * NI * B; a.z0 = n->z0T + h * NR * B;
+  a.xbits = n->xbitsT + h * NI * B; a.zbits = n->zbitsT + h * NR * B;
+  a.tofs = 0;
+  a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
+  a.slot0 = h * n->K; a.nsteps = nsteps; a.nslot = n->nslot;
+  a.Gout = n->Gout; a.Gb = n->Gb;
+  a.col_off = n->cv.off; a.col = n->cv.col;
+  return a;
+}
+
+// Run the open block (steps accumulated since the last flush): one forward
+// launch for all its steps on the caller's stream, writing ring segment
+// blk_seg, then the e-prop launch on the side stream.  The forward pass of
+// the next block (next segment) overlaps this e-prop launch; a segment is
+// reused only after the e-prop launch that read it has finished.
+void flush_block(rs_eprop* n) {
+  if (n->blk_n == 0) return;
+  hipStream_t s = n->stream, e = n->side;
+  const int h = n->blk_seg;
+  if (n->ep_pending[h]) {
+    (void)hipStreamWaitEvent(s, n->ev_ep[h], 0);
+    n->ep_pending[h] = false;
+  }
+  n->timer.begin(s, 0);
+  launch_fwd(s, block_fwd_args(n, h, n->blk_t0, n->blk_n));
+  launch_handoff_transpose(s, block_handoff_args(n, h, n->blk_n), n->B);
   // readout state, softmax error and (when learning) the learning signal of
   // the block, still on the forward stream: the e-prop stream, which carries
   // the longer work, starts with the eligibility launch itself
-  ReadoutArgs ro{};
-  ro.n_rec = f.n_rec; ro.n_out = f.n_out; ro.B = n->B; ro.nsteps = n->blk_n;
-  ro.slot0 = h * n->K; ro.nslot = n->nslot;
-  ro.alpha = n->alpha;
-  ro.u = f.u; ro.Y = n->Y; ro.Wout = n->Wout; ro.bout = n->bout; ro.labels = n->labels;
-  ro.deltaT = n->deltaT; ro.LT = n->LT;
-  launch_readout(s, ro, n->blk_learn);
+  launch_readout(s, block_readout_args(n, h, n->blk_n), n->blk_learn);
   n->timer.end(s);
   n->last_slot = h * n->K + n->blk_n - 1;
   order(n->ev_fwd, s, e);
   if (n->blk_learn) {
-    EpropArgs a{};
-    a.n_in = f.n_in; a.n_rec = f.n_rec; a.n_out = f.n_out; a.B = n->B;
-    a.alif = n->p.alif ? 1 : 0;
-    a.alpha = (float)n->alpha; a.rho = (float)n->rho; a.beta = (float)n->beta;
-    a.one_m_rho = (float)(1.0 - n->rho);
-    a.in = n->in; a.rec = n->rec;
-    a.x0 = n->x0T + h * NI * B; a.z0 = n->z0T + h * NR * B;
-    a.xbits = n->xbitsT + h * NI * B; a.zbits = n->zbitsT + h * NR * B;
-    a.tofs = 0;
-    a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
-    a.slot0 = h * n->K; a.nsteps = n->blk_n; a.nslot = n->nslot;
-    a.Gout = n->Gout; a.Gb = n->Gb;
-    a.col_off = n->cv.off; a.col = n->cv.col;
     n->timer.begin(e, 1);
-    launch_eprop(e, a);
+    launch_eprop(e, block_eprop_args(n, h, n->blk_n));
     n->timer.end(e);
   }
-  // the next forward launch into this segment waits for everything above,
-  // unless a join at an update or at the end of the call covers it first
   // The forward launch that next writes this segment comes Q blocks later.
   // Inside a call with automatic updates, the join at the next update comes
   // first when fewer than Q blocks remain to it; that join then orders the
@@ -675,6 +704,16 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
 }
 
 }  // namespace
+
+// Error reporting for the library's other source files.
+rs_status rs_internal_fail(rs_status code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return fail(code, "%s", buf);
+}
 
 // =========================================================================== C-ABI
 extern "C" {
@@ -1387,6 +1426,1033 @@ rs_status rs_calib_copy(void* dst, const void* src, size_t bytes, void* hip_stre
   launch_copy((hipStream_t)hip_stream, dst, src, bytes);
   HIP_OK(hipGetLastError());
   return RS_OK;
+}
+
+}  // extern "C"
+
+// =========================================================================== batched networks
+// A set of e-prop networks of different sizes trained together (the paper's
+// batching of model copies, here copies of different sizes): every kernel of
+// a step block runs once for all networks, over a work list of (network, tile)
+// entries, and one whole training sample (its blocks, updates, DEEP R rewires
+// and the reset) is recorded once as a HIP graph and replayed.  Each network
+// is an ordinary rs_eprop object underneath, so it computes exactly what it
+// computes alone.
+namespace {
+
+constexpr int MULTI_SCHEDULES = 5;
+// e-prop schedules the tuner tries: threads per row, rows per work tile,
+// persistent workgroups (0: one per tile)
+constexpr int SCHED_TPR[MULTI_SCHEDULES] = {256, 64, 64, 64, 256};
+constexpr int SCHED_TILE[MULTI_SCHEDULES] = {1, 4, 16, 4, 4};
+constexpr int SCHED_GRID[MULTI_SCHEDULES] = {0, 0, 0, 2048, 2048};
+
+// Bump allocator over a host image of the device tables.
+struct TableImage {
+  std::vector<unsigned char> host;
+  template <class T>
+  size_t put(const T* v, size_t n) {
+    const size_t off = (host.size() + 255) & ~(size_t)255;
+    host.resize(off + sizeof(T) * n);
+    if (n) memcpy(host.data() + off, v, sizeof(T) * n);
+    return off;
+  }
+  template <class T>
+  size_t put(const std::vector<T>& v) { return put(v.data(), v.size()); }
+};
+
+struct MultiBlock {
+  int h, nsteps;
+  uint64_t t0;          // first step, from the sample's start
+  bool covered;         // the next update's join orders the segment's reuse
+  size_t fwd, work_fwd, ho, ho_B, work_ho, ro, work_ro, work_ls, ep;
+  int n_fwd, n_ho, n_ro, n_ls;
+  size_t work_ep[MULTI_SCHEDULES];
+  int n_ep[MULTI_SCHEDULES];
+};
+struct MultiUpdate {
+  uint64_t t;           // the update follows step t - 1 (from the sample's start)
+  size_t up, work_up, dr, work_dr;
+  int n_up, n_proj, n_rows;
+};
+
+}  // namespace
+
+struct rs_multi {
+  std::vector<rs_eprop*> inst;
+  hipStream_t stream = nullptr;       // the caller's: forward pass of every block
+  hipStream_t side = nullptr;         // e-prop, updates, rewiring, reset
+  Arena arena;
+  int n = 0, B = 1, K = 20, Q = 2;
+  uint32_t U = 0, T = 0;
+  bool alif = true;
+  int fwd_items = 1, max_cap = 1, max_pre = 1;
+  size_t fwd_lds = 0;
+  uint64_t* step_dev = nullptr;       // steps done, at the start of the sample being run
+  uint32_t* adam_dev = nullptr;       // updates done, at the start of the sample
+  float* adam_tab = nullptr;          // [2 * (adam_kmax + 1)] bias corrections by update count
+  int adam_kmax = 0;
+  unsigned char* tab = nullptr;       // device tables of the recorded sample
+  size_t tab_bytes = 0;
+  std::vector<MultiBlock> blocks;
+  std::vector<MultiUpdate> updates;
+  size_t zero_ranges = 0;
+  int n_zero = 0;
+  unsigned long long zero_max = 0;
+  bool tables_ok = false;
+  int sched = 0;                      // e-prop schedule in use
+  bool tuned = false;
+  double sched_ms[MULTI_SCHEDULES] = {0};  // device time of one sample per schedule (tuning)
+  bool use_graph = true;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int graph_sched = -1;
+  hipEvent_t ev_fwd = nullptr, ev_back = nullptr, ev_join = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
+  hipEvent_t ev_ep[RING_MAX] = {};
+  uint64_t samples = 0;
+  bool dead = false;
+};
+
+namespace {
+
+void multi_drop_graph(rs_multi* m) {
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  if (m->graph) (void)hipGraphDestroy(m->graph);
+  m->gexec = nullptr;
+  m->graph = nullptr;
+  m->graph_sched = -1;
+}
+
+// Lay out one training sample exactly as the one-network path cuts it into
+// blocks (cut at every update and at the sample's end) and write every
+// launch's arguments and work lists into the device tables.
+rs_status multi_build_tables(rs_multi* m) {
+  TableImage im;
+  m->blocks.clear();
+  m->updates.clear();
+  const int n = m->n;
+  // block and update positions within one sample
+  struct Op { bool upd; uint64_t t0; int nsteps; };
+  std::vector<Op> ops;
+  {
+    uint64_t open_t0 = 0;
+    int open_n = 0;
+    for (uint64_t st = 1; st <= m->T; ++st) {
+      if (open_n == 0) open_t0 = st - 1;
+      ++open_n;
+      if (open_n == m->K) { ops.push_back({false, open_t0, open_n}); open_n = 0; }
+      if (st % m->U == 0 || st == m->T) {
+        if (open_n) { ops.push_back({false, open_t0, open_n}); open_n = 0; }
+        if (st % m->U == 0) ops.push_back({true, st, 0});
+      }
+    }
+  }
+  int blk = 0;
+  for (size_t q = 0; q < ops.size(); ++q) {
+    const Op& o = ops[q];
+    if (o.upd) {
+      MultiUpdate u{};
+      u.t = o.t0;
+      std::vector<UpdateArgs> ua(n);
+      std::vector<int4> uw;
+      std::vector<DeeprArgs> da;
+      std::vector<int2> dw;
+      const uint32_t k_in_sample = (uint32_t)m->updates.size() + 1;
+      for (int i = 0; i < n; ++i) {
+        rs_eprop* e = m->inst[i];
+        ua[i] = update_args(e, 1);
+        ua[i].adam_tab = m->adam_tab;
+        ua[i].adam_base = m->adam_dev;
+        ua[i].adam_off = (int)k_in_sample;
+        ua[i].adam_kmax = m->adam_kmax;
+        const int nb = update_blocks(ua[i]);
+        for (int b = 0; b < nb; ++b) uw.push_back(make_int4(i, b, nb, 0));
+        for (int p = 0; p < 2; ++p) {
+          if (!((e->p.deepr_mask >> p) & 1u)) continue;
+          DeeprArgs d{};
+          d.seed = e->p.seed;
+          d.P = p == 0 ? e->in : e->rec;
+          d.B = e->B;
+          d.step = o.t0;
+          d.step_base = m->step_dev;
+          d.stats = e->rw_stats;
+          for (int r = 0; r < d.P.n_pre; ++r) dw.push_back(make_int2((int)da.size(), r));
+          da.push_back(d);
+        }
+      }
+      u.up = im.put(ua);
+      u.work_up = im.put(uw);
+      u.n_up = (int)uw.size();
+      u.dr = im.put(da);
+      u.work_dr = im.put(dw);
+      u.n_proj = (int)da.size();
+      u.n_rows = (int)dw.size();
+      m->updates.push_back(u);
+      continue;
+    }
+    MultiBlock b{};
+    b.h = blk % m->Q;
+    b.t0 = o.t0;
+    b.nsteps = o.nsteps;
+    {  // covered: fewer than Q blocks remain to the next update from this block's end
+      const uint64_t end = o.t0 + (uint64_t)o.nsteps, U = m->U, rem = (U - end % U) % U;
+      b.covered = (rem + (uint64_t)m->K - 1) / (uint64_t)m->K < (uint64_t)m->Q;
+    }
+    std::vector<FwdArgs> fa(n);
+    std::vector<HandoffArrays> ha(n);
+    std::vector<int> hB(n);
+    std::vector<ReadoutArgs> ra(n);
+    std::vector<EpropArgs> ea(n);
+    std::vector<int2> fw;
+    std::vector<int4> hw, rw, lw;
+    std::vector<int4> ew[MULTI_SCHEDULES];
+    for (int i = 0; i < n; ++i) {
+      rs_eprop* e = m->inst[i];
+      fa[i] = block_fwd_args(e, b.h, o.t0, o.nsteps);
+      fa[i].rows_lds = 0;
+      fa[i].step_base = m->step_dev;
+      if (e->poisson) fa[i].step0 = o.t0;  // from the sample's start; the device adds the sample's first step
+      fa[i].t0 = (int)(o.t0 % e->p.sample_steps);
+      const size_t lds = fwd_plan(fa[i]);
+      m->fwd_lds = std::max(m->fwd_lds, lds);
+      m->fwd_items = std::max(m->fwd_items, fwd_items(fa[i].n_in, fa[i].n_rec));
+      for (int bb = 0; bb < e->B; ++bb) fw.push_back(make_int2(i, bb));
+      ha[i] = block_handoff_args(e, b.h, o.nsteps);
+      hB[i] = e->B;
+      int g[3];
+      handoff_grid(ha[i], e->B, g);
+      for (int z = 0; z < g[2]; ++z)
+        for (int y = 0; y < g[1]; ++y)
+          for (int x = 0; x < g[0]; ++x) hw.push_back(make_int4(i, x, y, z));
+      ra[i] = block_readout_args(e, b.h, o.nsteps);
+      for (int x = 0; x < readout_grid(ra[i]); ++x) rw.push_back(make_int4(i, x, 0, 0));
+      learning_signal_grid(ra[i], g);
+      for (int z = 0; z < g[2]; ++z)
+        for (int y = 0; y < g[1]; ++y)
+          for (int x = 0; x < g[0]; ++x) lw.push_back(make_int4(i, x, y, z));
+      ea[i] = block_eprop_args(e, b.h, o.nsteps);
+      const int rows = ea[i].n_in + ea[i].n_rec, chunks = narrow_readout_chunks(ea[i].n_rec);
+      for (int sc = 0; sc < MULTI_SCHEDULES; ++sc) {
+        for (int r = 0; r < rows; r += SCHED_TILE[sc])
+          ew[sc].push_back(make_int4(i, r, std::min(SCHED_TILE[sc], rows - r), 0));
+        for (int c = 0; c < chunks; ++c) ew[sc].push_back(make_int4(i, rows + c, 1, 0));
+      }
+    }
+    b.fwd = im.put(fa);
+    b.work_fwd = im.put(fw);
+    b.n_fwd = (int)fw.size();
+    b.ho = im.put(ha);
+    b.ho_B = im.put(hB);
+    b.work_ho = im.put(hw);
+    b.n_ho = (int)hw.size();
+    b.ro = im.put(ra);
+    b.work_ro = im.put(rw);
+    b.n_ro = (int)rw.size();
+    b.work_ls = im.put(lw);
+    b.n_ls = (int)lw.size();
+    b.ep = im.put(ea);
+    for (int sc = 0; sc < MULTI_SCHEDULES; ++sc) {
+      b.work_ep[sc] = im.put(ew[sc]);
+      b.n_ep[sc] = (int)ew[sc].size();
+    }
+    m->blocks.push_back(b);
+    ++blk;
+  }
+  // the reset at the sample's end
+  std::vector<ZeroRange> zr;
+  for (rs_eprop* e : m->inst) {
+    const size_t B = e->B, NR = e->p.n_rec, NI = e->p.n_in, K = e->p.n_out;
+    zr.push_back({e->V, B * NR * 8});
+    zr.push_back({e->A, B * NR * 8});
+    zr.push_back({e->Y, B * K * 8});
+    zr.push_back({e->xbar, B * NI * 4});
+    zr.push_back({e->zbar, B * NR * 4});
+    for (const ProjDev* P : {&e->in, &e->rec}) {
+      const size_t bytes = (size_t)P->n_pre * P->cap * B * 4;
+      zr.push_back({P->ebar, bytes});
+      if (P->eps) zr.push_back({P->eps, bytes});
+    }
+  }
+  m->zero_max = 0;
+  for (const ZeroRange& z : zr) m->zero_max = std::max(m->zero_max, z.bytes);
+  m->zero_ranges = im.put(zr);
+  m->n_zero = (int)zr.size();
+  // upload
+  multi_drop_graph(m);
+  if (im.host.size() > m->tab_bytes) {
+    if (m->tab) (void)hipFree(m->tab);
+    m->tab = nullptr;
+    m->tab_bytes = 0;
+    if (hipMalloc(&m->tab, im.host.size()) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(RS_ENOMEM, "device allocation of %zu bytes of launch tables failed", im.host.size());
+    }
+    m->tab_bytes = im.host.size();
+  }
+  HIP_OK(hipStreamSynchronize(m->stream));
+  HIP_OK(hipStreamSynchronize(m->side));
+  HIP_OK(hipMemcpy(m->tab, im.host.data(), im.host.size(), hipMemcpyHostToDevice));
+  m->tables_ok = true;
+  return RS_OK;
+}
+
+// Issue one training sample: the forward pass of each block on `s`, its
+// e-prop launch on `e`, updates, rewiring and the reset on `e`, with the
+// one-network path's event pattern between the two streams.  The same calls
+// run directly or under stream capture.
+void multi_issue_sample(rs_multi* m, int sched, hipStream_t s, hipStream_t e) {
+  unsigned char* T = m->tab;
+  bool pending[RING_MAX] = {};
+  size_t bi = 0, ui = 0;
+  const size_t nb = m->blocks.size(), nu = m->updates.size();
+  while (bi < nb || ui < nu) {
+    const bool take_update = ui < nu && (bi >= nb || m->updates[ui].t <= m->blocks[bi].t0);
+    if (!take_update) {
+      const MultiBlock& b = m->blocks[bi++];
+      if (pending[b.h]) {
+        (void)hipStreamWaitEvent(s, m->ev_ep[b.h], 0);
+        pending[b.h] = false;
+      }
+      launch_fwd_multi(s, (const FwdArgs*)(T + b.fwd), (const int2*)(T + b.work_fwd), b.n_fwd, m->fwd_items,
+                       m->fwd_lds);
+      launch_handoff_multi(s, (const HandoffArrays*)(T + b.ho), (const int*)(T + b.ho_B),
+                           (const int4*)(T + b.work_ho), b.n_ho);
+      launch_readout_multi(s, (const ReadoutArgs*)(T + b.ro), (const int4*)(T + b.work_ro), b.n_ro,
+                           (const int4*)(T + b.work_ls), b.n_ls);
+      (void)hipEventRecord(m->ev_fwd, s);
+      (void)hipStreamWaitEvent(e, m->ev_fwd, 0);
+      launch_eprop_narrow_multi(e, (const EpropArgs*)(T + b.ep), (const int4*)(T + b.work_ep[sched]),
+                                b.n_ep[sched], m->alif, SCHED_TPR[sched], SCHED_GRID[sched]);
+      if (!b.covered) {
+        (void)hipEventRecord(m->ev_ep[b.h], e);
+        pending[b.h] = true;
+      }
+      continue;
+    }
+    const MultiUpdate& u = m->updates[ui++];
+    launch_update_multi(e, (const UpdateArgs*)(T + u.up), (const int4*)(T + u.work_up), u.n_up);
+    launch_deepr_multi(e, (const DeeprArgs*)(T + u.dr), u.n_proj, (const int2*)(T + u.work_dr), u.n_rows,
+                       m->max_cap, m->max_pre);
+    if (u.t == m->T)
+      launch_fill_zero_ranges(e, (const ZeroRange*)(T + m->zero_ranges), m->n_zero, m->zero_max);
+    (void)hipEventRecord(m->ev_back, e);
+    (void)hipStreamWaitEvent(s, m->ev_back, 0);
+    for (bool& p : pending) p = false;
+  }
+  // next sample: the device counts move on (the e stream follows the last join)
+  launch_advance_counts(e, m->step_dev, m->T, m->adam_dev, (uint32_t)nu);
+  (void)hipEventRecord(m->ev_back, e);
+  (void)hipStreamWaitEvent(s, m->ev_back, 0);
+}
+
+rs_status multi_build_graph(rs_multi* m) {
+  multi_drop_graph(m);
+  hipStream_t s = m->stream;
+  // capture on a stream of our own, joined to the caller's around replays
+  hipStream_t cs = nullptr;
+  fwd_attrs();  // launch attributes are set outside the capture
+  deepr_attrs();
+  HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  hipError_t err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (err == hipSuccess) {
+    (void)hipEventRecord(m->ev_join, cs);
+    (void)hipStreamWaitEvent(m->side, m->ev_join, 0);  // the side stream joins the capture
+    multi_issue_sample(m, m->sched, cs, m->side);
+    hipGraph_t g = nullptr;
+    err = hipStreamEndCapture(cs, &g);
+    if (err == hipSuccess) {
+      m->graph = g;
+      err = hipGraphInstantiate(&m->gexec, g, nullptr, nullptr, 0);
+    }
+  }
+  (void)hipStreamDestroy(cs);
+  (void)s;
+  if (err != hipSuccess) {
+    (void)hipGetLastError();
+    multi_drop_graph(m);
+    return fail(RS_EDEVICE, "recording the training-sample graph failed: %s", hipGetErrorString(err));
+  }
+  m->graph_sched = m->sched;
+  return RS_OK;
+}
+
+// One sample, by graph replay or by direct launches; host counters follow.
+rs_status multi_run_sample(rs_multi* m, int sched, bool graph) {
+  if (graph) {
+    if (!m->gexec || m->graph_sched != sched) {
+      m->sched = sched;
+      TRY(multi_build_graph(m));
+    }
+    HIP_OK(hipGraphLaunch(m->gexec, m->stream));
+  } else {
+    order(m->ev_join, m->stream, m->side);
+    multi_issue_sample(m, sched, m->stream, m->side);
+  }
+  for (rs_eprop* e : m->inst) {
+    e->step += m->T;
+    e->adam_k += (uint32_t)m->updates.size();
+    const MultiBlock& last = m->blocks.back();
+    e->last_seg = last.h;
+    e->last_blk_n = last.nsteps;
+    e->last_slot = last.h * e->K + last.nsteps - 1;
+  }
+  ++m->samples;
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status multi_validate(const rs_eprop_params* p, uint32_t n) {
+  if (!p) return fail(RS_EINVAL, "params is NULL");
+  if (n < 1 || n > 4096) return fail(RS_EINVAL, "the set holds 1..4096 networks");
+  for (uint32_t i = 0; i < n; ++i) {
+    TRY(validate(&p[i]));
+    const rs_eprop_params &a = p[0], &b = p[i];
+    if (b.batch % 4 == 0)
+      return fail(RS_EINVAL, "network %u: batched sets take batches not divisible by 4 (the narrow kernel)", i);
+    if (b.update_interval < 1 || b.sample_steps % b.update_interval != 0)
+      return fail(RS_EINVAL, "network %u: sample_steps must be a multiple of update_interval >= 1", i);
+    if (b.n_in != a.n_in || b.n_out != a.n_out || b.batch != a.batch || b.alif != a.alif ||
+        b.dt_ms != a.dt_ms || b.tau_mem_ms != a.tau_mem_ms || b.tau_adapt_ms != a.tau_adapt_ms ||
+        b.update_interval != a.update_interval || b.sample_steps != a.sample_steps ||
+        b.trace_block != a.trace_block || b.adam_b1 != a.adam_b1 || b.adam_b2 != a.adam_b2)
+      return fail(RS_EINVAL, "network %u differs from network 0 in n_in, n_out, batch, alif, time constants, "
+                  "update interval, sample length, block length or Adam decay rates", i);
+  }
+  return RS_OK;
+}
+
+rs_status multi_create_impl(const rs_eprop_params* p, uint32_t n, void* stream, rs_multi* m) {
+  TRY(multi_validate(p, n));
+  m->stream = (hipStream_t)stream;
+  m->n = (int)n;
+  for (uint32_t i = 0; i < n; ++i) {
+    rs_eprop* e = nullptr;
+    rs_status st = create_impl(&p[i], stream, &e);
+    if (st != RS_OK) {
+      if (e) rs_eprop_destroy(e);
+      return st;
+    }
+    m->inst.push_back(e);
+  }
+  rs_eprop* e0 = m->inst[0];
+  m->B = e0->B;
+  m->K = e0->K;
+  m->Q = e0->Q;
+  m->U = e0->p.update_interval;
+  m->T = e0->p.sample_steps;
+  m->alif = e0->p.alif != 0;
+  for (rs_eprop* e : m->inst) {
+    m->max_cap = std::max({m->max_cap, e->in.cap, e->rec.cap});
+    m->max_pre = std::max({m->max_pre, e->in.n_pre, e->rec.n_pre});
+  }
+  HIP_OK(hipStreamCreateWithFlags(&m->side, hipStreamNonBlocking));
+  for (hipEvent_t* ev : {&m->ev_fwd, &m->ev_back, &m->ev_join})
+    HIP_OK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+  for (int q = 0; q < m->Q; ++q) HIP_OK(hipEventCreateWithFlags(&m->ev_ep[q], hipEventDisableTiming));
+  HIP_OK(hipEventCreate(&m->ev_t0));
+  HIP_OK(hipEventCreate(&m->ev_t1));
+  // Adam bias corrections by update count, as the one-network path computes
+  // them; beyond kmax both round to exactly 1
+  {
+    const double b1 = e0->p.adam_b1, b2 = e0->p.adam_b2;
+    std::vector<float> tab = {1.0f, 1.0f};
+    uint32_t k = 1;
+    for (; k < (1u << 20); ++k) {
+      const float c1 = adam_inv_c(b1, k), c2 = adam_inv_c(b2, k);
+      tab.push_back(c1);
+      tab.push_back(c2);
+      if (c1 == 1.0f && c2 == 1.0f) break;
+    }
+    m->adam_kmax = (int)(tab.size() / 2 - 1);
+    TRY(m->arena.alloc(&m->adam_tab, tab.size()));
+    HIP_OK(hipMemcpyAsync(m->adam_tab, tab.data(), tab.size() * 4, hipMemcpyHostToDevice, m->stream));
+  }
+  TRY(m->arena.alloc(&m->step_dev, 1));
+  TRY(m->arena.alloc(&m->adam_dev, 1));
+  launch_fill_zero(m->stream, m->step_dev, 8);
+  launch_fill_zero(m->stream, m->adam_dev, 4);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(m->stream));
+  return RS_OK;
+}
+
+rs_status multi_index(rs_multi* m, uint32_t i) {
+  if (i >= (uint32_t)m->n) return fail(RS_EINVAL, "network %u outside the set of %d", i, m->n);
+  return RS_OK;
+}
+
+// The set's work on the side stream is ordered before later work on the
+// caller's stream after every call; instance calls then see finished state.
+void multi_join(rs_multi* m) { order(m->ev_back, m->side, m->stream); }
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_multi_create(const rs_eprop_params* params, uint32_t n, void* hip_stream, rs_multi** out) {
+  if (!out) return fail(RS_EINVAL, "out is NULL");
+  *out = nullptr;
+  rs_multi* m = new rs_multi();
+  rs_status st = multi_create_impl(params, n, hip_stream, m);
+  if (st != RS_OK) {
+    rs_multi_destroy(m);
+    return st;
+  }
+  *out = m;
+  return RS_OK;
+}
+
+rs_status rs_multi_set_input(rs_multi* m, uint32_t i, const int32_t* off_dev, const int32_t* idx_dev,
+                             size_t n_idx, const int32_t* labels_dev) {
+  ENTER(m);
+  TRY(multi_index(m, i));
+  multi_join(m);
+  TRY(rs_eprop_set_input(m->inst[i], off_dev, idx_dev, n_idx, labels_dev));
+  m->tables_ok = false;
+  return RS_OK;
+}
+
+rs_status rs_multi_set_input_poisson(rs_multi* m, uint32_t i, const double* rate_hz, size_t n_rates,
+                                     const int32_t* labels_dev) {
+  ENTER(m);
+  TRY(multi_index(m, i));
+  multi_join(m);
+  TRY(rs_eprop_set_input_poisson(m->inst[i], rate_hz, n_rates, labels_dev));
+  m->tables_ok = false;
+  return RS_OK;
+}
+
+rs_status rs_multi_train(rs_multi* m, uint32_t n_samples) {
+  ENTER(m);
+  for (rs_eprop* e : m->inst) {
+    if (!e->x_off && !e->poisson) return fail(RS_ESTATE, "a network of the set has no input attached");
+    if (e->step % m->T != 0) return fail(RS_ESTATE, "the set is not at a sample boundary");
+  }
+  if (!m->tables_ok) TRY(multi_build_tables(m));
+  for (uint32_t q = 0; q < n_samples; ++q) {
+    if (!m->tuned) {
+      // the tuner: the next untried schedule runs this sample (every schedule
+      // computes the same results), timed on the device; after the last one
+      // the fastest is kept
+      int c = 0;
+      while (c < MULTI_SCHEDULES && m->sched_ms[c] > 0) ++c;
+      order(m->ev_join, m->stream, m->side);
+      HIP_OK(hipEventRecord(m->ev_t0, m->stream));
+      TRY(multi_run_sample(m, c, false));
+      HIP_OK(hipEventRecord(m->ev_t1, m->stream));
+      HIP_OK(hipEventSynchronize(m->ev_t1));
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, m->ev_t0, m->ev_t1));
+      m->sched_ms[c] = ms > 0 ? ms : 1e-6;
+      if (c + 1 == MULTI_SCHEDULES) {
+        int best = 0;
+        for (int q2 = 1; q2 < MULTI_SCHEDULES; ++q2)
+          if (m->sched_ms[q2] < m->sched_ms[best]) best = q2;
+        m->sched = best;
+        m->tuned = true;
+      }
+      continue;
+    }
+    TRY(multi_run_sample(m, m->sched, m->use_graph));
+  }
+  multi_join(m);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_multi_schedule_get(rs_multi* m, rs_multi_schedule* out) {
+  ENTER(m);
+  if (!out) return fail(RS_EINVAL, "NULL argument");
+  memset(out, 0, sizeof *out);
+  out->tuned = m->tuned ? 1 : 0;
+  out->schedule = (uint32_t)m->sched;
+  out->threads_per_row = (uint32_t)SCHED_TPR[m->sched];
+  out->rows_per_tile = (uint32_t)SCHED_TILE[m->sched];
+  out->workgroups = (uint32_t)SCHED_GRID[m->sched];
+  out->graph = m->use_graph ? 1 : 0;
+  out->trace_block = (uint32_t)m->K;
+  for (int q = 0; q < MULTI_SCHEDULES && q < RS_MULTI_SCHEDULES; ++q) out->sample_ms[q] = m->sched_ms[q];
+  out->samples = m->samples;
+  return RS_OK;
+}
+
+rs_status rs_multi_schedule_set(rs_multi* m, int32_t schedule, int32_t use_graph) {
+  ENTER(m);
+  if (schedule < -1 || schedule >= MULTI_SCHEDULES) return fail(RS_EINVAL, "schedule must be -1..%d", MULTI_SCHEDULES - 1);
+  if (schedule == -1) {  // tune again over the next samples
+    m->tuned = false;
+    for (double& t : m->sched_ms) t = 0;
+  } else {
+    m->sched = schedule;
+    m->tuned = true;
+  }
+  m->use_graph = use_graph != 0;
+  return RS_OK;
+}
+
+rs_status rs_multi_get(rs_multi* m, uint32_t i, int32_t var, void* host, size_t bytes) {
+  ENTER(m);
+  TRY(multi_index(m, i));
+  multi_join(m);
+  return rs_eprop_get(m->inst[i], var, host, bytes);
+}
+
+rs_status rs_multi_set(rs_multi* m, uint32_t i, int32_t var, const void* host, size_t bytes) {
+  ENTER(m);
+  TRY(multi_index(m, i));
+  multi_join(m);
+  return rs_eprop_set(m->inst[i], var, host, bytes);
+}
+
+rs_status rs_multi_info_get(rs_multi* m, uint32_t i, rs_eprop_info* out) {
+  ENTER(m);
+  TRY(multi_index(m, i));
+  multi_join(m);
+  return rs_eprop_info_get(m->inst[i], out);
+}
+
+void rs_multi_destroy(rs_multi* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->stream);
+  if (m->side) (void)hipStreamSynchronize(m->side);
+  multi_drop_graph(m);
+  for (rs_eprop* e : m->inst) rs_eprop_destroy(e);
+  for (hipEvent_t ev : {m->ev_fwd, m->ev_back, m->ev_join, m->ev_t0, m->ev_t1})
+    if (ev) (void)hipEventDestroy(ev);
+  for (hipEvent_t ev : m->ev_ep)
+    if (ev) (void)hipEventDestroy(ev);
+  if (m->side) (void)hipStreamDestroy(m->side);
+  if (m->tab) (void)hipFree(m->tab);
+  m->arena.release();
+  delete m;
+}
+
+}  // extern "C"
+
+// =========================================================================== served inference
+// Continuous batching of inference requests on trained networks: each
+// request is one presentation of an input raster to one model; its neuron and
+// readout state sits in a slot on the device for the request's whole life.
+// Every call of rs_serve_step admits queued requests into free slots (while
+// their state fits the memory budget) and runs one block of steps for every
+// running request in one forward launch (a work list over the requests, each
+// at its own position in its own input) and one readout launch; requests
+// that reach their last step free their slot.
+
+namespace {
+
+double host_seconds() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct ServeSlot {
+  int model = 0;
+  bool busy = false;
+  uint64_t ticket = 0;
+  const int32_t *off = nullptr, *idx = nullptr;
+  long long n_idx = 0;
+  uint32_t n_steps = 0, done = 0, raster_steps = 0;
+  double submit_s = 0, admit_s = 0;
+  // device state
+  double *V = nullptr, *A = nullptr, *Y = nullptr, *score = nullptr;
+  float *xbar = nullptr, *zbar = nullptr, *u = nullptr;
+  uint8_t* z = nullptr;
+  uint32_t* zcount = nullptr;
+  unsigned long long* counters = nullptr;
+};
+
+struct ServeRequest {
+  uint64_t ticket;
+  int model;
+  const int32_t *off, *idx;
+  long long n_idx;
+  uint32_t n_steps, raster_steps;
+  double submit_s;
+};
+
+}  // namespace
+
+struct rs_serve {
+  std::vector<rs_eprop*> models;
+  std::vector<size_t> footprint;      // device bytes of one request's state, per model
+  std::vector<int> first_slot;        // slots of model m: first_slot[m] .. first_slot[m+1]-1
+  std::vector<ServeSlot> slots;
+  std::deque<ServeRequest> queue;
+  rs_serve_params p{};
+  hipStream_t stream = nullptr;
+  Arena arena;
+  uint64_t budget = 0, used = 0;
+  int K = 20, items = 1;
+  size_t lds = 0;
+  uint64_t next_ticket = 1;
+  // per-block launch tables: device and pinned host images
+  FwdArgs* fwd_dev = nullptr;
+  int2* work_dev = nullptr;
+  ServeReadout* ro_dev = nullptr;
+  ZeroRange* zero_dev = nullptr;
+  unsigned char* host_img = nullptr;  // pinned
+  size_t img_bytes = 0, off_work = 0, off_ro = 0, off_zero = 0;
+  int max_active = 0;
+  std::vector<rs_serve_result> done;
+  std::vector<double> done_scores;    // n_out_max per finished request
+  int n_out_max = 1;
+  uint64_t admitted = 0, rejected = 0, completed = 0, blocks = 0;
+  double t0 = 0;
+  bool dead = false;
+};
+
+namespace {
+
+size_t serve_footprint(const rs_eprop* n, int K) {
+  const size_t NR = n->p.n_rec, NI = n->p.n_in, NO = n->p.n_out;
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return al(NR * 8) * 2 + al(NO * 8) * 2 + al(NI * 4) + al(NR * 4) + al((size_t)K * NO * 4) + al(NR) + al(NR * 4) +
+         al(16);
+}
+
+rs_status serve_create_impl(rs_eprop* const* models, uint32_t n_models, const rs_serve_params* prm, void* stream,
+                            rs_serve* s) {
+  if (!models || n_models < 1 || n_models > 64) return fail(RS_EINVAL, "1..64 models");
+  if (!prm) return fail(RS_EINVAL, "params is NULL");
+  if (prm->slots_per_model < 1 || prm->slots_per_model > 4096) return fail(RS_EINVAL, "slots_per_model in 1..4096");
+  if (prm->block_steps < 1 || prm->block_steps > 32) return fail(RS_EINVAL, "block_steps in 1..32");
+  if (prm->max_running < 1) return fail(RS_EINVAL, "max_running >= 1");
+  s->p = *prm;
+  s->stream = (hipStream_t)stream;
+  s->K = (int)prm->block_steps;
+  s->budget = prm->state_budget_bytes;
+  const uint32_t n_in = models[0] ? models[0]->p.n_in : 0;
+  for (uint32_t m = 0; m < n_models; ++m) {
+    rs_eprop* e = models[m];
+    if (!e) return fail(RS_EINVAL, "model %u is NULL", m);
+    if (e->dead) return fail(RS_EDEVICE, "model %u is unusable after a device error", m);
+    if (e->p.n_in != n_in) return fail(RS_EINVAL, "every model takes the same n_in");
+    s->models.push_back(e);
+    s->footprint.push_back(serve_footprint(e, s->K));
+    s->n_out_max = std::max(s->n_out_max, (int)e->p.n_out);
+    s->items = std::max(s->items, fwd_items((int)e->p.n_in, (int)e->p.n_rec));
+    FwdArgs f = block_fwd_args(e, 0, 0, s->K);
+    s->lds = std::max(s->lds, fwd_plan(f));
+  }
+  // slots: every model's state for slots_per_model requests
+  Arena& ar = s->arena;
+  for (uint32_t m = 0; m < n_models; ++m) {
+    rs_eprop* e = s->models[m];
+    const size_t NR = e->p.n_rec, NI = e->p.n_in, NO = e->p.n_out;
+    s->first_slot.push_back((int)s->slots.size());
+    for (uint32_t q = 0; q < prm->slots_per_model; ++q) {
+      ServeSlot sl;
+      sl.model = (int)m;
+      TRY(ar.alloc(&sl.V, NR));
+      TRY(ar.alloc(&sl.A, NR));
+      TRY(ar.alloc(&sl.Y, NO));
+      TRY(ar.alloc(&sl.score, NO));
+      TRY(ar.alloc(&sl.xbar, NI));
+      TRY(ar.alloc(&sl.zbar, NR));
+      TRY(ar.alloc(&sl.u, (size_t)s->K * NO));
+      TRY(ar.alloc(&sl.z, NR));
+      TRY(ar.alloc(&sl.zcount, NR));
+      TRY(ar.alloc(&sl.counters, 2));
+      s->slots.push_back(sl);
+    }
+  }
+  s->first_slot.push_back((int)s->slots.size());
+  s->max_active = (int)std::min<size_t>(prm->max_running, s->slots.size());
+  const int A = s->max_active, Z = A * 10;
+  TRY(ar.alloc(&s->fwd_dev, (size_t)A));
+  TRY(ar.alloc(&s->work_dev, (size_t)A));
+  TRY(ar.alloc(&s->ro_dev, (size_t)A));
+  TRY(ar.alloc(&s->zero_dev, (size_t)Z));
+  auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  s->off_work = al(sizeof(FwdArgs) * A);
+  s->off_ro = s->off_work + al(sizeof(int2) * A);
+  s->off_zero = s->off_ro + al(sizeof(ServeReadout) * A);
+  s->img_bytes = s->off_zero + al(sizeof(ZeroRange) * Z);
+  HIP_OK(hipHostMalloc((void**)&s->host_img, s->img_bytes, hipHostMallocDefault));
+  fwd_attrs();
+  s->t0 = host_seconds();
+  return RS_OK;
+}
+
+// Admit queued requests, in arrival order, into free slots of their model
+// while the budget holds their state.
+int serve_admit(rs_serve* s, ZeroRange* zr, int* nz) {
+  int running = 0;
+  for (const ServeSlot& sl : s->slots) running += sl.busy ? 1 : 0;
+  int admitted = 0;
+  for (auto it = s->queue.begin(); it != s->queue.end() && running < s->max_active;) {
+    const ServeRequest& r = *it;
+    const size_t fp = s->footprint[r.model];
+    int slot = -1;
+    if (s->used + fp <= s->budget)
+      for (int q = s->first_slot[r.model]; q < s->first_slot[r.model + 1]; ++q)
+        if (!s->slots[q].busy) { slot = q; break; }
+    if (slot < 0) { ++it; continue; }
+    ServeSlot& sl = s->slots[slot];
+    sl.busy = true;
+    sl.ticket = r.ticket;
+    sl.off = r.off;
+    sl.idx = r.idx;
+    sl.n_idx = r.n_idx;
+    sl.n_steps = r.n_steps;
+    sl.raster_steps = r.raster_steps;
+    sl.done = 0;
+    sl.submit_s = r.submit_s;
+    sl.admit_s = host_seconds() - s->t0;
+    const rs_eprop* e = s->models[sl.model];
+    const size_t NR = e->p.n_rec, NI = e->p.n_in, NO = e->p.n_out;
+    ZeroRange z[] = {{sl.V, NR * 8}, {sl.A, NR * 8}, {sl.Y, NO * 8}, {sl.score, NO * 8}, {sl.xbar, NI * 4},
+                     {sl.zbar, NR * 4}, {sl.zcount, NR * 4}, {sl.counters, 16}};
+    for (const ZeroRange& q : z) zr[(*nz)++] = q;
+    s->used += fp;
+    ++running;
+    ++admitted;
+    ++s->admitted;
+    it = s->queue.erase(it);
+  }
+  return admitted;
+}
+
+rs_status serve_step_impl(rs_serve* s, uint32_t* n_done) {
+  if (n_done) *n_done = 0;
+  unsigned char* H = s->host_img;
+  FwdArgs* fa = (FwdArgs*)H;
+  int2* work = (int2*)(H + s->off_work);
+  ServeReadout* ro = (ServeReadout*)(H + s->off_ro);
+  ZeroRange* zr = (ZeroRange*)(H + s->off_zero);
+  int nz = 0;
+  serve_admit(s, zr, &nz);
+  std::vector<int> act;
+  for (int q = 0; q < (int)s->slots.size(); ++q)
+    if (s->slots[q].busy) act.push_back(q);
+  if (act.empty()) return RS_OK;
+  unsigned long long zmax = 0;
+  for (int q = 0; q < nz; ++q) zmax = std::max(zmax, zr[q].bytes);
+  int n = 0;
+  for (int q : act) {
+    ServeSlot& sl = s->slots[q];
+    rs_eprop* e = s->models[sl.model];
+    const int nsteps = (int)std::min<uint32_t>((uint32_t)s->K, sl.n_steps - sl.done);
+    FwdArgs f = block_fwd_args(e, 0, 0, nsteps);
+    f.B = 1;
+    f.V = sl.V; f.A = sl.A; f.xbar = sl.xbar; f.zbar = sl.zbar;
+    f.psi = nullptr; f.x0 = nullptr; f.z0 = nullptr; f.xbits = nullptr; f.zbits = nullptr;
+    f.z = sl.z; f.u = sl.u;
+    f.x_off = sl.off; f.x_idx = sl.idx; f.n_idx = sl.n_idx;
+    f.x_thr = nullptr; f.x_list = nullptr;
+    f.t0 = (int)(sl.done % sl.raster_steps);
+    f.sample_steps = (int)sl.raster_steps;
+    f.rows_lds = 0;
+    f.counters = sl.counters;
+    f.zcount = sl.zcount;
+    fwd_plan(f);
+    fa[n] = f;
+    work[n] = make_int2(n, 0);
+    ServeReadout r{};
+    r.n_out = (int)e->p.n_out;
+    r.nsteps = nsteps;
+    r.alpha = e->alpha;
+    r.u = sl.u;
+    r.Y = sl.Y;
+    r.bout = e->bout;
+    r.score = sl.score;
+    ro[n] = r;
+    ++n;
+  }
+  hipStream_t st = s->stream;
+  // the tables are copied from pinned memory the host rewrites next block:
+  // the block is waited for below before that happens
+  if (nz) {
+    HIP_OK(hipMemcpyAsync(s->zero_dev, zr, sizeof(ZeroRange) * nz, hipMemcpyHostToDevice, st));
+    launch_fill_zero_ranges(st, s->zero_dev, nz, zmax);
+  }
+  HIP_OK(hipMemcpyAsync(s->fwd_dev, fa, sizeof(FwdArgs) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(s->work_dev, work, sizeof(int2) * n, hipMemcpyHostToDevice, st));
+  HIP_OK(hipMemcpyAsync(s->ro_dev, ro, sizeof(ServeReadout) * n, hipMemcpyHostToDevice, st));
+  launch_fwd_multi(st, s->fwd_dev, s->work_dev, n, s->items, s->lds);
+  launch_serve_readout(st, s->ro_dev, n);
+  HIP_OK(hipGetLastError());
+  HIP_OK(hipStreamSynchronize(st));
+  ++s->blocks;
+  const double now = host_seconds() - s->t0;
+  uint32_t fin = 0;
+  for (int q : act) {
+    ServeSlot& sl = s->slots[q];
+    sl.done += (uint32_t)std::min<uint32_t>((uint32_t)s->K, sl.n_steps - sl.done);
+    if (sl.done < sl.n_steps) continue;
+    const rs_eprop* e = s->models[sl.model];
+    const int NO = (int)e->p.n_out;
+    std::vector<double> sc((size_t)NO);
+    unsigned long long c[2];
+    HIP_OK(hipMemcpyAsync(sc.data(), sl.score, (size_t)NO * 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(c, sl.counters, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    rs_serve_result r{};
+    r.ticket = sl.ticket;
+    r.model = (uint32_t)sl.model;
+    r.steps = sl.n_steps;
+    int best = 0;
+    for (int k = 1; k < NO; ++k)
+      if (sc[k] > sc[best]) best = k;
+    r.decision = best;
+    r.events = c[0];
+    r.spikes = c[1];
+    r.submit_s = sl.submit_s;
+    r.admit_s = sl.admit_s;
+    r.done_s = now;
+    s->done.push_back(r);
+    const size_t base = s->done_scores.size();
+    s->done_scores.resize(base + (size_t)s->n_out_max, 0.0);
+    std::copy(sc.begin(), sc.end(), s->done_scores.begin() + base);
+    sl.busy = false;
+    s->used -= s->footprint[sl.model];
+    ++s->completed;
+    ++fin;
+  }
+  if (n_done) *n_done = fin;
+  return RS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_serve_create(rs_eprop* const* models, uint32_t n_models, const rs_serve_params* params,
+                          void* hip_stream, rs_serve** out) {
+  if (!out) return fail(RS_EINVAL, "out is NULL");
+  *out = nullptr;
+  rs_serve* s = new rs_serve();
+  rs_status st = serve_create_impl(models, n_models, params, hip_stream, s);
+  if (st != RS_OK) {
+    rs_serve_destroy(s);
+    return st;
+  }
+  *out = s;
+  return RS_OK;
+}
+
+rs_status rs_serve_submit(rs_serve* s, uint32_t model, const int32_t* off_dev, const int32_t* idx_dev, size_t n_idx,
+                          uint32_t raster_steps, uint32_t n_steps, uint64_t* ticket) {
+  ENTER(s);
+  if (model >= s->models.size()) return fail(RS_EINVAL, "model %u outside 0..%zu", model, s->models.size() - 1);
+  if (!off_dev || !idx_dev) return fail(RS_EINVAL, "input pointers must not be NULL");
+  if (n_steps < 1 || raster_steps < 1) return fail(RS_EINVAL, "n_steps and raster_steps must be >= 1");
+  if (n_idx > (size_t)INT32_MAX) return fail(RS_EINVAL, "index array larger than 2^31 entries");
+  if (s->footprint[model] > s->budget) {
+    ++s->rejected;
+    return fail(RS_ECAPACITY, "the request's state (%zu bytes) exceeds the budget", s->footprint[model]);
+  }
+  if (s->queue.size() >= s->p.max_queue) {
+    ++s->rejected;
+    return fail(RS_ECAPACITY, "queue full (%u requests)", s->p.max_queue);
+  }
+  ServeRequest r{s->next_ticket++, (int)model, off_dev, idx_dev, (long long)n_idx, n_steps, raster_steps,
+                 host_seconds() - s->t0};
+  s->queue.push_back(r);
+  if (ticket) *ticket = r.ticket;
+  return RS_OK;
+}
+
+rs_status rs_serve_step(rs_serve* s, uint32_t* n_done) {
+  ENTER(s);
+  return serve_step_impl(s, n_done);
+}
+
+rs_status rs_serve_poll(rs_serve* s, rs_serve_result* out, double* scores, uint32_t max, uint32_t* n) {
+  ENTER(s);
+  if (!out || !n) return fail(RS_EINVAL, "NULL argument");
+  const uint32_t k = (uint32_t)std::min<size_t>(max, s->done.size());
+  for (uint32_t q = 0; q < k; ++q) out[q] = s->done[q];
+  if (scores)
+    std::copy(s->done_scores.begin(), s->done_scores.begin() + (size_t)k * s->n_out_max, scores);
+  s->done.erase(s->done.begin(), s->done.begin() + k);
+  s->done_scores.erase(s->done_scores.begin(), s->done_scores.begin() + (size_t)k * s->n_out_max);
+  *n = k;
+  return RS_OK;
+}
+
+rs_status rs_serve_stats_get(rs_serve* s, rs_serve_stats* out) {
+  ENTER(s);
+  if (!out) return fail(RS_EINVAL, "NULL argument");
+  memset(out, 0, sizeof *out);
+  out->admitted = s->admitted;
+  out->rejected = s->rejected;
+  out->completed = s->completed;
+  out->queued = s->queue.size();
+  int running = 0;
+  for (const ServeSlot& sl : s->slots) running += sl.busy ? 1 : 0;
+  out->running = (uint32_t)running;
+  out->blocks = s->blocks;
+  out->state_bytes_used = s->used;
+  out->state_budget_bytes = s->budget;
+  out->n_out_max = (uint32_t)s->n_out_max;
+  out->clock_s = host_seconds() - s->t0;
+  return RS_OK;
+}
+
+// Replay a request trace against the wall clock: request q is submitted once
+// arrival_s[q] seconds have passed since the call began; blocks run while
+// requests are running; the call returns when every request has finished or
+// been rejected.  latency_ms[q] (arrival to completion) is -1 for rejected ones.
+rs_status rs_serve_replay(rs_serve* s, const rs_serve_request* reqs, uint32_t n, double* latency_ms,
+                          int32_t* decision, uint64_t* spikes) {
+  ENTER(s);
+  if (!reqs && n) return fail(RS_EINVAL, "NULL requests");
+  for (uint32_t q = 1; q < n; ++q)
+    if (reqs[q].arrival_s < reqs[q - 1].arrival_s) return fail(RS_EINVAL, "arrivals must be in order");
+  std::unordered_map<uint64_t, uint32_t> of_ticket;  // ticket -> request
+  for (uint32_t q = 0; q < n; ++q) {
+    if (latency_ms) latency_ms[q] = -1.0;
+    if (decision) decision[q] = -1;
+    if (spikes) spikes[q] = 0;
+  }
+  const double start = host_seconds() - s->t0;
+  uint32_t next = 0, finished = 0, rejected = 0;
+  std::vector<rs_serve_result> res(256);
+  while (finished + rejected < n) {
+    const double now = host_seconds() - s->t0 - start;
+    for (; next < n && reqs[next].arrival_s <= now; ++next) {
+      const rs_serve_request& r = reqs[next];
+      uint64_t t = 0;
+      rs_status st = rs_serve_submit(s, r.model, r.off_dev, r.idx_dev, r.n_idx, r.raster_steps, r.n_steps, &t);
+      if (st == RS_ECAPACITY) { ++rejected; continue; }
+      TRY(st);
+      of_ticket[t] = next;
+    }
+    uint32_t nd = 0;
+    TRY(serve_step_impl(s, &nd));
+    int running = 0;
+    for (const ServeSlot& sl : s->slots) running += sl.busy ? 1 : 0;
+    if (running == 0 && s->queue.empty() && next < n) {
+      // idle until the next arrival
+      while (host_seconds() - s->t0 - start < reqs[next].arrival_s) {
+      }
+    }
+    for (;;) {
+      uint32_t k = 0;
+      TRY(rs_serve_poll(s, res.data(), nullptr, (uint32_t)res.size(), &k));
+      for (uint32_t q = 0; q < k; ++q) {
+        const auto f = of_ticket.find(res[q].ticket);
+        if (f == of_ticket.end()) continue;  // submitted before this replay
+        const uint32_t lo = f->second;
+        if (latency_ms) latency_ms[lo] = 1e3 * (res[q].done_s - start - reqs[lo].arrival_s);
+        if (decision) decision[lo] = res[q].decision;
+        if (spikes) spikes[lo] = res[q].spikes;
+        ++finished;
+      }
+      if (k < res.size()) break;
+    }
+  }
+  return RS_OK;
+}
+
+void rs_serve_destroy(rs_serve* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->host_img) (void)hipHostFree(s->host_img);
+  s->arena.release();
+  delete s;
 }
 
 }  // extern "C"

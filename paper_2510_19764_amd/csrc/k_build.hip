@@ -145,6 +145,34 @@ void launch_fill_zero(hipStream_t s, void* p, size_t bytes) {
     hipLaunchKernelGGL(k_fill_zero_bytes, dim3(1), dim3(16), 0, s, (uint8_t*)p + n16 * 16, rem);
 }
 
+// Zero several ranges: blockIdx.y picks the range, x strides over its words.
+__global__ void __launch_bounds__(256) k_fill_zero_ranges(const ZeroRange* __restrict__ R) {
+  const ZeroRange r = R[blockIdx.y];
+  uint32_t* p = (uint32_t*)r.p;
+  const unsigned long long n = r.bytes / 4;
+  for (unsigned long long q = (unsigned long long)blockIdx.x * 256 + threadIdx.x; q < n;
+       q += (unsigned long long)gridDim.x * 256)
+    p[q] = 0u;
+}
+
+void launch_fill_zero_ranges(hipStream_t s, const ZeroRange* ranges, int n, unsigned long long max_bytes) {
+  if (n <= 0 || max_bytes == 0) return;
+  unsigned long long bx = (max_bytes / 4 + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(k_fill_zero_ranges, dim3((unsigned)bx, (unsigned)n), dim3(256), 0, s, ranges);
+}
+
+__global__ void k_advance_counts(uint64_t* step, uint64_t steps, uint32_t* updates, uint32_t n_upd) {
+  if (threadIdx.x == 0) {
+    *step += steps;
+    *updates += n_upd;
+  }
+}
+
+void launch_advance_counts(hipStream_t s, uint64_t* step, uint64_t steps, uint32_t* updates, uint32_t n_upd) {
+  hipLaunchKernelGGL(k_advance_counts, dim3(1), dim3(64), 0, s, step, steps, updates, n_upd);
+}
+
 __global__ void k_copy(uint4* __restrict__ d, const uint4* __restrict__ s, size_t n16) {
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < n16; q += stride) d[q] = s[q];

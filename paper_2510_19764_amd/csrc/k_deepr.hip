@@ -22,12 +22,12 @@
 
 namespace rs {
 
-__global__ void __launch_bounds__(WAVE) k_deepr_elim(ProjDev P, int B, long long* stats) {
+__device__ __forceinline__ void elim_body(const ProjDev& P, const int B, long long* stats, const int i) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* holes = (int*)smem;
   int* tail = holes + P.cap;
   uint8_t* remf = (uint8_t*)(tail + P.cap);
-  const int i = blockIdx.x, lane = lane_id();
+  const int lane = lane_id();
   const int n = P.len[i];
   const int64_t base = (int64_t)i * P.cap;
   for (int k = lane; k < n; k += WAVE) {
@@ -64,6 +64,9 @@ __global__ void __launch_bounds__(WAVE) k_deepr_elim(ProjDev P, int B, long long
     if (n > n2) atomicAdd((unsigned long long*)&stats[0], (unsigned long long)(n - n2));
   }
 }
+__global__ void __launch_bounds__(WAVE) k_deepr_elim(ProjDev P, int B, long long* stats) {
+  elim_body(P, B, stats, blockIdx.x);
+}
 
 constexpr int DIST_NT = 1024;
 
@@ -78,8 +81,8 @@ __device__ __forceinline__ int block_sum_i(int v, int* s_red) {
   return t;
 }
 
-__global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, ProjDev P, uint64_t step,
-                                                              long long* stats) {
+__device__ __forceinline__ void distribute_body(const uint64_t seed, const ProjDev& P, const uint64_t step,
+                                                long long* stats) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* cnt = (int*)smem;           // [n_pre]
   int* asg = cnt + P.n_pre;        // [n_pre]
@@ -132,12 +135,16 @@ __global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, Pro
     if (pending > 0) atomicAdd((unsigned long long*)&stats[3], (unsigned long long)pending);
   }
 }
+__global__ void __launch_bounds__(DIST_NT) k_deepr_distribute(uint64_t seed, ProjDev P, uint64_t step,
+                                                              long long* stats) {
+  distribute_body(seed, P, step, stats);
+}
 
-__global__ void __launch_bounds__(WAVE) k_deepr_form(uint64_t seed, ProjDev P, int B, uint64_t step,
-                                                     long long* stats) {
+__device__ __forceinline__ void form_body(const uint64_t seed, const ProjDev& P, const int B, const uint64_t step,
+                                          long long* stats, const int r) {
   extern __shared__ __align__(16) unsigned char smem[];
   int* newj = (int*)smem;  // [cap]
-  const int r = blockIdx.x, lane = lane_id();
+  const int lane = lane_id();
   const int na = P.assigned[r];
   if (na == 0) return;
   const int n0 = P.len[r];
@@ -190,10 +197,45 @@ __global__ void __launch_bounds__(WAVE) k_deepr_form(uint64_t seed, ProjDev P, i
     if (nf) atomicAdd((unsigned long long*)&stats[1], (unsigned long long)nf);
   }
 }
+__global__ void __launch_bounds__(WAVE) k_deepr_form(uint64_t seed, ProjDev P, int B, uint64_t step,
+                                                     long long* stats) {
+  form_body(seed, P, B, step, stats, blockIdx.x);
+}
+
+// DEEP R of several projections (of several networks) in one launch per
+// phase.  Elimination and formation: workgroup g takes row work[g].y of
+// projection work[g].x; distribution: one workgroup per projection.  The
+// random step is D.step plus the device step count where the launch replays.
+__device__ __forceinline__ uint64_t deepr_step(const DeeprArgs& d) {
+  return d.step + (d.step_base ? *d.step_base : 0ull);
+}
+__global__ void __launch_bounds__(WAVE) k_deepr_elim_multi(const DeeprArgs* __restrict__ D,
+                                                           const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const DeeprArgs& d = D[w.x];
+  elim_body(d.P, d.B, d.stats, w.y);
+}
+__global__ void __launch_bounds__(DIST_NT) k_deepr_distribute_multi(const DeeprArgs* __restrict__ D) {
+  const DeeprArgs& d = D[blockIdx.x];
+  distribute_body(d.seed, d.P, deepr_step(d), d.stats);
+}
+__global__ void __launch_bounds__(WAVE) k_deepr_form_multi(const DeeprArgs* __restrict__ D,
+                                                           const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  const DeeprArgs& d = D[w.x];
+  form_body(d.seed, d.P, d.B, deepr_step(d), d.stats, w.y);
+}
+
+void deepr_attrs() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    allow_dynamic_lds((const void*)k_deepr_distribute, 128 * 1024);
+    allow_dynamic_lds((const void*)k_deepr_distribute_multi, 128 * 1024);
+  });
+}
 
 void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step, long long* stats) {
-  static std::once_flag once;
-  std::call_once(once, [] { allow_dynamic_lds((const void*)k_deepr_distribute, 128 * 1024); });
+  deepr_attrs();
   const size_t sm_elim = (size_t)P.cap * 9 + 16;
   hipLaunchKernelGGL(k_deepr_elim, dim3(P.n_pre), dim3(WAVE), sm_elim, s, P, B, stats);
   hipLaunchKernelGGL(k_deepr_distribute, dim3(1), dim3(DIST_NT), (size_t)P.n_pre * 8, s, seed, P, step, stats);
@@ -201,4 +243,15 @@ void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_
                      stats);
 }
 
+}  // namespace rs
+
+namespace rs {
+void launch_deepr_multi(hipStream_t s, const DeeprArgs* D, int n_proj, const int2* rows, int n_rows, int max_cap,
+                        int max_pre) {
+  deepr_attrs();
+  if (n_proj <= 0) return;
+  hipLaunchKernelGGL(k_deepr_elim_multi, dim3(n_rows), dim3(WAVE), (size_t)max_cap * 9 + 16, s, D, rows);
+  hipLaunchKernelGGL(k_deepr_distribute_multi, dim3(n_proj), dim3(DIST_NT), (size_t)max_pre * 8, s, D);
+  hipLaunchKernelGGL(k_deepr_form_multi, dim3(n_rows), dim3(WAVE), (size_t)max_cap * 4 + 16, s, D, rows);
+}
 }  // namespace rs

@@ -458,32 +458,13 @@ void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const 
 // Narrow form (B % 4 != 0): threads over a row's synapses, each looping over
 // instances and steps; used for small or odd batches such as single-instance
 // learning.  Same trace recursion and arithmetic as the target-major form.
+// Narrow kernel, for any batch size: a row's synapses are spread over `nsub`
+// threads (thread `sub` takes slots sub, sub + nsub, ...), each looping over
+// the batch instances and the block's steps; the readout delta rule runs on
+// further workgroups, one thread per readout column j (j = n_rec: the bias).
 template <bool ALIF>
-__global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
-  const int row = blockIdx.x, tid = threadIdx.x;
-  const int n_rows = a.n_in + a.n_rec;
+__device__ __forceinline__ void narrow_row(const EpropArgs& a, const int row, const int sub, const int nsub) {
   const int B = a.B;
-  if (row >= n_rows) {
-    const int j = (row - n_rows) * EP_NT + tid;
-    if (j > a.n_rec) return;
-    const bool wt = j < a.n_rec;
-    for (int k = 0; k < a.n_out; ++k) {
-      float g = 0.0f;
-      for (int b = 0; b < B; ++b) {
-        float z = wt ? a.z0[(int64_t)j * B + b] : 1.0f;
-        const uint32_t w = wt ? a.zbits[(int64_t)j * B + b] : 0u;
-        if (wt)
-          for (int t = 0; t < a.tofs; ++t) z = fmaf(a.alpha, z, (float)((w >> t) & 1u));
-        for (int tau = 0; tau < a.nsteps; ++tau) {
-          if (wt) z = fmaf(a.alpha, z, (float)((w >> (a.tofs + tau)) & 1u));
-          g = fmaf(a.deltaT[ring(a, k, tau) + b], z, g);
-        }
-      }
-      if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
-      else a.Gb[k] += g;
-    }
-    return;
-  }
   const bool from_in = row < a.n_in;
   const int i = from_in ? row : row - a.n_in;
   const int cap = from_in ? a.in.cap : a.rec.cap;
@@ -494,7 +475,7 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   float* ebar = from_in ? a.in.ebar : a.rec.ebar;
   const float* x0 = (from_in ? a.x0 : a.z0) + (int64_t)i * B;
   const uint32_t* bits = (from_in ? a.xbits : a.zbits) + (int64_t)i * B;
-  for (int k = tid; k < n; k += EP_NT) {
+  for (int k = sub; k < n; k += nsub) {
     const int64_t s = (int64_t)i * cap + k;
     const int j = ind[s];
     float gsum = 0.0f;
@@ -523,6 +504,73 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
   }
 }
 
+__device__ __forceinline__ void narrow_readout(const EpropArgs& a, const int chunk, const int tid) {
+  const int B = a.B;
+  const int j = chunk * EP_NT + tid;
+  if (j > a.n_rec) return;
+  const bool wt = j < a.n_rec;
+  for (int k = 0; k < a.n_out; ++k) {
+    float g = 0.0f;
+    for (int b = 0; b < B; ++b) {
+      float z = wt ? a.z0[(int64_t)j * B + b] : 1.0f;
+      const uint32_t w = wt ? a.zbits[(int64_t)j * B + b] : 0u;
+      if (wt)
+        for (int t = 0; t < a.tofs; ++t) z = fmaf(a.alpha, z, (float)((w >> t) & 1u));
+      for (int tau = 0; tau < a.nsteps; ++tau) {
+        if (wt) z = fmaf(a.alpha, z, (float)((w >> (a.tofs + tau)) & 1u));
+        g = fmaf(a.deltaT[ring(a, k, tau) + b], z, g);
+      }
+    }
+    if (wt) a.Gout[(int64_t)k * a.n_rec + j] += g;
+    else a.Gb[k] += g;
+  }
+}
+
+template <bool ALIF>
+__global__ void __launch_bounds__(EP_NT) k_eprop_narrow(EpropArgs a) {
+  const int row = blockIdx.x, n_rows = a.n_in + a.n_rec;
+  if (row >= n_rows) narrow_readout(a, row - n_rows, threadIdx.x);
+  else narrow_row<ALIF>(a, row, threadIdx.x, EP_NT);
+}
+
+// The narrow kernel for several networks, persistent: workgroups stride over
+// a work list of row tiles (network work[g].x, rows work[g].y ..
+// work[g].y + work[g].z - 1; rows from n_in + n_rec on are readout chunks).
+// TPR threads share a row: 256 gives a row the whole workgroup, 64 a wave
+// (four rows of the tile at a time).  Every synapse is computed exactly as in
+// the one-network kernel, whatever the schedule.
+template <bool ALIF, int TPR>
+__global__ void __launch_bounds__(EP_NT) k_eprop_narrow_multi(const EpropArgs* __restrict__ A,
+                                                              const int4* __restrict__ work, int n_work) {
+  const int tid = threadIdx.x;
+  for (int g = blockIdx.x; g < n_work; g += gridDim.x) {
+    const int4 w = work[g];
+    const EpropArgs& a = A[w.x];
+    const int n_rows = a.n_in + a.n_rec;
+    if (w.y >= n_rows) {
+      narrow_readout(a, w.y - n_rows, tid);
+      continue;
+    }
+    const int end = min(w.y + w.z, n_rows);
+    for (int r = w.y + tid / TPR; r < end; r += EP_NT / TPR) narrow_row<ALIF>(a, r, tid % TPR, TPR);
+  }
+}
+
+int narrow_readout_chunks(int n_rec) { return (n_rec + 1 + EP_NT - 1) / EP_NT; }
+
+void launch_eprop_narrow_multi(hipStream_t s, const EpropArgs* A, const int4* work, int n_work, bool alif, int tpr,
+                               int grid) {
+  if (n_work <= 0) return;
+  const int g = grid > 0 && grid < n_work ? grid : n_work;
+  if (tpr == 64) {
+    if (alif) hipLaunchKernelGGL((k_eprop_narrow_multi<true, 64>), dim3(g), dim3(EP_NT), 0, s, A, work, n_work);
+    else hipLaunchKernelGGL((k_eprop_narrow_multi<false, 64>), dim3(g), dim3(EP_NT), 0, s, A, work, n_work);
+  } else {
+    if (alif) hipLaunchKernelGGL((k_eprop_narrow_multi<true, EP_NT>), dim3(g), dim3(EP_NT), 0, s, A, work, n_work);
+    else hipLaunchKernelGGL((k_eprop_narrow_multi<false, EP_NT>), dim3(g), dim3(EP_NT), 0, s, A, work, n_work);
+  }
+}
+
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
   if (a.B % 4 == 0 && a.col && a.col_off) {
@@ -540,7 +588,7 @@ void launch_eprop(hipStream_t s, const EpropArgs& a) {
     }
   } else {
     const int n_rows = a.n_in + a.n_rec;
-    const int extra = (a.n_rec + 1 + EP_NT - 1) / EP_NT;
+    const int extra = narrow_readout_chunks(a.n_rec);
     if (a.alif) hipLaunchKernelGGL(k_eprop_narrow<true>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);
     else hipLaunchKernelGGL(k_eprop_narrow<false>, dim3(n_rows + extra), dim3(EP_NT), 0, s, a);
   }

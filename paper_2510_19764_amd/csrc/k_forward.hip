@@ -90,7 +90,7 @@ constexpr size_t WOUT_LDS_MAX = 16 * 1024;  // largest readout matrix staged in 
 // ROWS: both projections' rows are staged in LDS for the launch (small
 // networks), so propagation reads no global memory.
 template <int ITEMS, bool ROWS>
-__global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
+__device__ __forceinline__ void fwd_body(const FwdArgs& a, const int b) {
   extern __shared__ __align__(16) unsigned char smem[];
   const FwdLds lay = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, ROWS, a.cap_in, a.cap_rec);
   long long* acc = (long long*)(smem + lay.acc);
@@ -107,7 +107,10 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
   __shared__ int s_xsrc[33], s_xcnt[33];
   __shared__ int s_xstaged;
 
-  const int b = blockIdx.x, tid = threadIdx.x, B = a.B;
+  const int tid = threadIdx.x, B = a.B;
+  // Poisson draws are keyed by the absolute step: the block's first step,
+  // plus the device step count where a recorded launch replays
+  const uint64_t step0 = a.step0 + (a.step_base ? *a.step_base : 0ull);
   const int lane = lane_id(), wv = wave_id();
   const int items = (a.n_rec + FWD_NT - 1) / FWD_NT;
   const int xitems = (a.n_in + FWD_NT - 1) / FWD_NT;
@@ -155,7 +158,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     const int total = a.nsteps * a.n_in;
     for (int q = tid; q < total; q += FWD_NT) {
       const int tau = q / a.n_in, i = q - tau * a.n_in;
-      const uint32_t u = draw_u32(a.seed, TAG_INPUT, 0, a.step0 + (uint64_t)tau, (uint64_t)b, (uint64_t)i, 0);
+      const uint32_t u = draw_u32(a.seed, TAG_INPUT, 0, step0 + (uint64_t)tau, (uint64_t)b, (uint64_t)i, 0);
       if ((uint64_t)u < thr[i]) {
         const int pos = atomicAdd(&s_xcnt[tau], 1);
         a.x_list[((int64_t)tau * B + b) * a.n_in + pos] = i;
@@ -208,11 +211,11 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     vr[it] = ok ? a.V[(int64_t)b * a.n_rec + j] : 0.0;
     ar[it] = ok ? a.A[(int64_t)b * a.n_rec + j] : 0.0;
     zbr[it] = ok ? a.zbar[(int64_t)b * a.n_rec + j] : 0.0f;
-    if (ok) a.z0[(int64_t)b * a.n_rec + j] = zbr[it];
+    if (ok && a.z0) a.z0[(int64_t)b * a.n_rec + j] = zbr[it];
     const int i = it * FWD_NT + tid;
     const bool oki = it < xitems && i < a.n_in;
     xbr[it] = oki ? a.xbar[(int64_t)b * a.n_in + i] : 0.0f;
-    if (oki) a.x0[(int64_t)b * a.n_in + i] = xbr[it];
+    if (oki && a.x0) a.x0[(int64_t)b * a.n_in + i] = xbr[it];
     zr[it] = false;
     zbits[it] = 0u;
     xbits[it] = 0u;
@@ -247,7 +250,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
         const double thr = a.v_thr + a.beta * ar[it];
         z = vr[it] >= thr;
         const double h = 1.0 - fabs(vr[it] - thr) / a.v_thr;
-        a.psi[((int64_t)tau * B + b) * a.n_rec + j] = (float)(a.psi_scale * fmax(h, 0.0));
+        if (a.psi) a.psi[((int64_t)tau * B + b) * a.n_rec + j] = (float)(a.psi_scale * fmax(h, 0.0));
         acc[j] = 0ll;
       }
       zr[it] = z;
@@ -342,7 +345,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
       a.A[m] = ar[it];
       a.zbar[m] = zbr[it];
       a.z[m] = (uint8_t)zr[it];
-      a.zbits[m] = zbits[it];
+      if (a.zbits) a.zbits[m] = zbits[it];
       a.zcount[m] += (uint32_t)__popc(zbits[it]);
     }
   }
@@ -352,7 +355,7 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     const int i = it * FWD_NT + tid;
     if (i < a.n_in) {
       a.xbar[(int64_t)b * a.n_in + i] = xbr[it];
-      a.xbits[(int64_t)b * a.n_in + i] = xbits[it];
+      if (a.xbits) a.xbits[(int64_t)b * a.n_in + i] = xbits[it];
     }
   }
   __syncthreads();
@@ -360,6 +363,20 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
     atomicAdd(&a.counters[0], s_events);
     atomicAdd(&a.counters[1], spikes);
   }
+}
+
+template <int ITEMS, bool ROWS>
+__global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
+  fwd_body<ITEMS, ROWS>(a, blockIdx.x);
+}
+
+// Several networks in one launch: workgroup g runs batch instance work[g].y of
+// network work[g].x, whose arguments are A[work[g].x].
+template <int ITEMS>
+__global__ void __launch_bounds__(FWD_NT) k_fwd_multi(const FwdArgs* __restrict__ A,
+                                                      const int2* __restrict__ work) {
+  const int2 w = work[blockIdx.x];
+  fwd_body<ITEMS, false>(A[w.x], w.y);
 }
 
 // Items per thread: neurons (and input channels) handled by each of the
@@ -382,10 +399,9 @@ bool fwd_fits(int n_in, int n_rec, int n_out) {
   return fwd_lds_layout(n_in, n_rec, n_out, 0, 0).total <= (size_t)fwd_lds_cap();
 }
 
-void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
+size_t fwd_plan(FwdArgs& a) {
   // LDS budget: stage W_out and up to 2048 input spikes when they fit
   const int lds_cap = fwd_lds_cap();
-  FwdArgs a = a_in;
   a.xcap = 2048;
   // W_out is staged only while small: the forward workgroups stay resident on
   // their CUs beside the e-prop launch of the previous block, and every
@@ -394,12 +410,15 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
   if (fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total > (size_t)lds_cap) a.wout_lds = 0;
   while (fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total > (size_t)lds_cap && a.xcap > 0)
     a.xcap /= 2;
-  const int need = (max(a.n_rec, a.n_in) + FWD_NT - 1) / FWD_NT;
-  // rows in LDS when asked for, one neuron per thread and everything fits
-  const bool rows = a.rows_lds && need <= 1 &&
-                    fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, 1, a.cap_in, a.cap_rec).total <=
-                        (size_t)lds_cap;
-  const size_t sm = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, rows, a.cap_in, a.cap_rec).total;
+  return fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds).total;
+}
+
+int fwd_items(int n_in, int n_rec) {
+  const int need = (max(n_rec, n_in) + FWD_NT - 1) / FWD_NT;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+void fwd_attrs() {
   static std::once_flag once;
   std::call_once(once, [] {
     allow_dynamic_lds((const void*)k_fwd<1, true>, 150 * 1024);
@@ -407,7 +426,33 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
     allow_dynamic_lds((const void*)k_fwd<2, false>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<4, false>, 150 * 1024);
     allow_dynamic_lds((const void*)k_fwd<8, false>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd_multi<1>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd_multi<2>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd_multi<4>, 150 * 1024);
+    allow_dynamic_lds((const void*)k_fwd_multi<8>, 150 * 1024);
   });
+}
+
+void launch_fwd_multi(hipStream_t s, const FwdArgs* A, const int2* work, int n_work, int items, size_t lds) {
+  if (n_work <= 0) return;
+  fwd_attrs();
+  if (items <= 1) hipLaunchKernelGGL(k_fwd_multi<1>, dim3(n_work), dim3(FWD_NT), lds, s, A, work);
+  else if (items <= 2) hipLaunchKernelGGL(k_fwd_multi<2>, dim3(n_work), dim3(FWD_NT), lds, s, A, work);
+  else if (items <= 4) hipLaunchKernelGGL(k_fwd_multi<4>, dim3(n_work), dim3(FWD_NT), lds, s, A, work);
+  else hipLaunchKernelGGL(k_fwd_multi<8>, dim3(n_work), dim3(FWD_NT), lds, s, A, work);
+}
+
+void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
+  const int lds_cap = fwd_lds_cap();
+  FwdArgs a = a_in;
+  fwd_plan(a);
+  const int need = (max(a.n_rec, a.n_in) + FWD_NT - 1) / FWD_NT;
+  // rows in LDS when asked for, one neuron per thread and everything fits
+  const bool rows = a.rows_lds && need <= 1 &&
+                    fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, 1, a.cap_in, a.cap_rec).total <=
+                        (size_t)lds_cap;
+  const size_t sm = fwd_lds_layout(a.n_in, a.n_rec, a.n_out, a.xcap, a.wout_lds, rows, a.cap_in, a.cap_rec).total;
+  fwd_attrs();
   if (rows) hipLaunchKernelGGL((k_fwd<1, true>), dim3(a.B), dim3(FWD_NT), sm, s, a);
   else if (need <= 1) hipLaunchKernelGGL((k_fwd<1, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
   else if (need <= 2) hipLaunchKernelGGL((k_fwd<2, false>), dim3(a.B), dim3(FWD_NT), sm, s, a);
@@ -423,8 +468,8 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
 // goes into the ring [k][slot][b].  Labels outside 0..n_out-1 contribute no
 // target term.
 constexpr int RO_KMAX = 4;  // n_out <= 4 * WAVE
-__global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) {
-  const int b = blockIdx.x * 4 + wave_id(), lane = lane_id();
+__device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx) {
+  const int b = bx * 4 + wave_id(), lane = lane_id();
   if (b >= a.B) return;
   const int label = a.labels[b];
   double y[RO_KMAX];
@@ -467,15 +512,17 @@ __global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) {
     if (k < a.n_out) a.Y[(int64_t)b * a.n_out + k] = y[q];
   }
 }
+__global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) { readout_body(a, blockIdx.x); }
 
 // Learning signal L_j = sum_k W_out[k][j] delta_k (recurrent classifier
 // section), written straight into the ring [j][slot][b]: lanes over
 // instances, each thread 16 consecutive neurons of a 64-neuron tile whose
 // readout weights are staged in LDS.  blockIdx = (neuron tile, instance tile,
 // step).
-__global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
+__device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const int bx, const int by,
+                                                     const int bz) {
   __shared__ float w[64][65];  // [k in chunk][j in tile]
-  const int j0 = blockIdx.x * 64, b = blockIdx.y * 64 + lane_id(), tau = blockIdx.z;
+  const int j0 = bx * 64, b = by * 64 + lane_id(), tau = bz;
   const int jq = wave_id() * 16;  // this wave's 16 neurons of the tile
   const bool act = b < a.B;
   float acc[16];
@@ -502,23 +549,37 @@ __global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
     if (j < a.n_rec) a.LT[((int64_t)j * a.nslot + a.slot0 + tau) * a.B + b] = acc[q];
   }
 }
+__global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
+  learning_signal_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+int readout_grid(const ReadoutArgs& a) { return (a.B + 3) / 4; }
+void learning_signal_grid(const ReadoutArgs& a, int g[3]) {
+  g[0] = (a.n_rec + 63) / 64;
+  g[1] = (a.B + 63) / 64;
+  g[2] = a.nsteps;
+}
 
 void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal) {
   if (a.nsteps <= 0) return;
-  hipLaunchKernelGGL(k_readout, dim3((a.B + 3) / 4), dim3(256), 0, s, a);
-  if (learning_signal)
-    hipLaunchKernelGGL(k_learning_signal, dim3((a.n_rec + 63) / 64, (a.B + 63) / 64, a.nsteps), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_readout, dim3(readout_grid(a)), dim3(256), 0, s, a);
+  if (learning_signal) {
+    int g[3];
+    learning_signal_grid(a, g);
+    hipLaunchKernelGGL(k_learning_signal, dim3(g[0], g[1], g[2]), dim3(256), 0, s, a);
+  }
 }
 
 // Hand-off transpose: [step][B][n] -> [n][nslot][B] (slot slot0 + step) through
 // a 64 x 64 LDS tile, both sides coalesced; 32-bit words are moved unchanged.
 // blockIdx.z enumerates (array, step) pairs.
-__global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B) {
+__device__ __forceinline__ void handoff_body(const HandoffArrays& h, const int B, const int bx, const int by,
+                                             const int bz) {
   __shared__ uint32_t tile[64][65];
-  int z = blockIdx.z, arr = 0;
+  int z = bz, arr = 0;
   while (arr + 1 < HANDOFF_ARRAYS && z >= h.steps[arr]) z -= h.steps[arr++];
   const int tau = z, n = h.n[arr];
-  const int n0 = blockIdx.x * 64, b0 = blockIdx.y * 64;
+  const int n0 = bx * 64, b0 = by * 64;
   if (n0 >= n || b0 >= B || tau >= h.steps[arr]) return;
   const uint32_t* src = h.src[arr] + (int64_t)tau * B * n;
   uint32_t* dst = h.dst[arr];
@@ -533,16 +594,54 @@ __global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int 
     if (j < n && b < B) dst[((int64_t)j * h.nslot[arr] + h.slot0[arr] + tau) * B + b] = tile[tx][r];
   }
 }
+__global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B) {
+  handoff_body(h, B, blockIdx.x, blockIdx.y, blockIdx.z);
+}
 
-void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B) {
+// The three block kernels above for several networks in one launch: workgroup
+// g runs tile (work[g].y, work[g].z, work[g].w) of network work[g].x.
+__global__ void __launch_bounds__(256) k_handoff_multi(const HandoffArrays* __restrict__ H,
+                                                       const int* __restrict__ Bs, const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  handoff_body(H[w.x], Bs[w.x], w.y, w.z, w.w);
+}
+__global__ void __launch_bounds__(256) k_readout_multi(const ReadoutArgs* __restrict__ A,
+                                                       const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  readout_body(A[w.x], w.y);
+}
+__global__ void __launch_bounds__(256) k_learning_signal_multi(const ReadoutArgs* __restrict__ A,
+                                                               const int4* __restrict__ work) {
+  const int4 w = work[blockIdx.x];
+  learning_signal_body(A[w.x], w.y, w.z, w.w);
+}
+
+void handoff_grid(const HandoffArrays& h, int B, int g[3]) {
   int nmax = 0, zs = 0;
   for (int q = 0; q < HANDOFF_ARRAYS; ++q) {
     nmax = max(nmax, h.n[q]);
     zs += h.steps[q];
   }
-  if (zs <= 0) return;
-  dim3 grid((nmax + 63) / 64, (B + 63) / 64, zs);
-  hipLaunchKernelGGL(k_handoff_transpose, grid, dim3(256), 0, s, h, B);
+  g[0] = (nmax + 63) / 64;
+  g[1] = (B + 63) / 64;
+  g[2] = zs;
+}
+
+void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B) {
+  int g[3];
+  handoff_grid(h, B, g);
+  if (g[2] <= 0) return;
+  hipLaunchKernelGGL(k_handoff_transpose, dim3(g[0], g[1], g[2]), dim3(256), 0, s, h, B);
+}
+
+void launch_handoff_multi(hipStream_t s, const HandoffArrays* H, const int* Bs, const int4* work, int n_work) {
+  if (n_work > 0) hipLaunchKernelGGL(k_handoff_multi, dim3(n_work), dim3(256), 0, s, H, Bs, work);
+}
+
+void launch_readout_multi(hipStream_t s, const ReadoutArgs* A, const int4* ro_work, int n_ro, const int4* ls_work,
+                          int n_ls) {
+  if (n_ro > 0) hipLaunchKernelGGL(k_readout_multi, dim3(n_ro), dim3(256), 0, s, A, ro_work);
+  if (n_ls > 0) hipLaunchKernelGGL(k_learning_signal_multi, dim3(n_ls), dim3(256), 0, s, A, ls_work);
 }
 
 }  // namespace rs

@@ -50,7 +50,8 @@ struct FwdArgs {
   float alpha_f;                             // trace decay: F <- fma(alpha_f, F, spike) in float
   double* V; double* A;                      // [B][n_rec]
   float* xbar; float* zbar;                  // [B][n_in], [B][n_rec] presynaptic traces
-  // hand-off, instance-major staging (coalesced writes):
+  // hand-off, instance-major staging (coalesced writes); psi, x0, z0, xbits
+  // and zbits may be null (inference: no eligibility work follows)
   float* psi;                                // [tau][B][n_rec] surrogate derivative of each step
   float* u;                                  // [tau][B][n_out] readout drive sum_j W_out[k][j] z_j
   float* x0; float* z0;                      // [B][n] traces at the start of the block
@@ -66,6 +67,7 @@ struct FwdArgs {
   // < x_thr[b * x_thr_stride + i]; the block's lists go to x_list [K][B][n_in]
   const uint64_t* x_thr; int x_thr_stride; int* x_list;
   uint64_t seed, step0;
+  const uint64_t* step_base;                 // null, or a device step count added to step0 (replayed launches)
   int wout_lds;                              // 1: stage W_out in LDS for the block
   int rows_lds;                              // 1: stage both projections' rows in LDS if they fit
   int xcap;                                  // LDS capacity for the block's input spike lists
@@ -74,6 +76,13 @@ struct FwdArgs {
 };
 // One launch runs `nsteps` consecutive steps into the staging buffers.
 void launch_fwd(hipStream_t s, const FwdArgs& a);
+// LDS plan of one network's forward launch (xcap, wout_lds set in `a`); returns the bytes it needs.
+size_t fwd_plan(FwdArgs& a);
+// Items per thread a network needs (1, 2, 4 or 8).
+int fwd_items(int n_in, int n_rec);
+// Several networks in one launch: A[work[g].x] runs batch instance work[g].y;
+// `items` covers every network, `lds` is the largest plan.
+void launch_fwd_multi(hipStream_t s, const FwdArgs* A, const int2* work, int n_work, int items, size_t lds);
 // Whether one forward workgroup's LDS holds a network of this size.
 bool fwd_fits(int n_in, int n_rec, int n_out);
 
@@ -89,6 +98,11 @@ struct ReadoutArgs {
   float* deltaT; float* LT;                  // rings [n_out][nslot][B], [n_rec][nslot][B]
 };
 void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal);
+// Several networks: work lists of (network, x, y, z) tiles of each kernel's grid.
+void launch_readout_multi(hipStream_t s, const ReadoutArgs* A, const int4* ro_work, int n_ro,
+                          const int4* ls_work, int n_ls);
+int readout_grid(const ReadoutArgs& a);                 // k_readout workgroups
+void learning_signal_grid(const ReadoutArgs& a, int g[3]);
 
 // Move staged hand-off arrays ([step][B][n], 32-bit words) into neuron-major
 // layout ([n][nslot][B], step tau to slot slot0 + tau).
@@ -99,6 +113,8 @@ struct HandoffArrays {
   int n[HANDOFF_ARRAYS], steps[HANDOFF_ARRAYS], slot0[HANDOFF_ARRAYS], nslot[HANDOFF_ARRAYS];
 };
 void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B);
+void handoff_grid(const HandoffArrays& h, int B, int g[3]);
+void launch_handoff_multi(hipStream_t s, const HandoffArrays* H, const int* Bs, const int4* work, int n_work);
 
 struct EpropArgs {
   int n_in, n_rec, n_out, B, alif;
@@ -118,6 +134,13 @@ struct EpropArgs {
   const int* col_off; const int2* col;   // ColumnView (B % 4 == 0)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+// Narrow e-prop kernel over several networks, persistent over a work list of
+// row tiles (network, first row, rows; rows >= n_in + n_rec are readout
+// chunks): `grid` workgroups (0: one per work item), `tpr` threads per row (64
+// or 256).
+void launch_eprop_narrow_multi(hipStream_t s, const EpropArgs* A, const int4* work, int n_work, bool alif,
+                               int tpr, int grid);
+int narrow_readout_chunks(int n_rec);
 void launch_columns(hipStream_t s, const ProjDev& in, const ProjDev& rec, const ColumnView& cv);
 
 // ---------------------------------------------------------------- update
@@ -128,8 +151,14 @@ struct UpdateArgs {
   ProjDev in, rec;
   float* Wout; float* bout; float* Gout; float* Gb; float* Mout; float* Vout; float* Mb; float* Vb;
   int n_out_elems, n_b;
+  // replayed launches: the bias corrections of update k = *adam_base + adam_off
+  // come from adam_tab[2 min(k, adam_kmax)], [.. + 1] (inv_c1, inv_c2); null: the fields above
+  const float* adam_tab; const uint32_t* adam_base; int adam_off, adam_kmax;
 };
 void launch_update(hipStream_t s, const UpdateArgs& a);
+int update_blocks(const UpdateArgs& a);
+// work[g] = (network, block, blocks of that network)
+void launch_update_multi(hipStream_t s, const UpdateArgs* A, const int4* work, int n_work);
 
 // ---------------------------------------------------------------- DEEP R
 // stats: int64[4] device counters, incremented: 0 eliminated (= D, the dormant
@@ -137,6 +166,17 @@ void launch_update(hipStream_t s, const UpdateArgs& a);
 // room for
 void launch_deepr(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step,
                   long long* stats);
+struct DeeprArgs {
+  uint64_t seed;
+  ProjDev P;
+  int B;
+  uint64_t step;               // random step, plus *step_base when step_base is set
+  const uint64_t* step_base;
+  long long* stats;            // int64[4] as above
+};
+// DEEP R of n_proj projections; rows[g] = (projection, row) over all their rows.
+void launch_deepr_multi(hipStream_t s, const DeeprArgs* D, int n_proj, const int2* rows, int n_rows, int max_cap,
+                        int max_pre);
 
 // ---------------------------------------------------------------- topomap
 struct TopoDev {
@@ -187,8 +227,28 @@ void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoS
 // Set the kernels' launch attributes ahead of a stream capture (idempotent).
 void topo_sim_attrs();
 void topo_rewire_attrs();
+void fwd_attrs();
+void deepr_attrs();
+
+// ---------------------------------------------------------------- served inference
+// Readout of one running request over a block of steps.
+struct ServeReadout {
+  int n_out, nsteps;
+  double alpha;
+  const float* u;      // [nsteps][n_out] readout drive of the block
+  double* Y;           // [n_out] readout state
+  const float* bout;   // [n_out]
+  double* score;       // [n_out] sum over the request's steps of softmax(y)
+};
+void launch_serve_readout(hipStream_t s, const ServeReadout* R, int n);
 
 // ---------------------------------------------------------------- misc
 void launch_copy(hipStream_t s, void* dst, const void* src, size_t bytes);
+// Zero a list of device ranges in one launch (a kernel, so it can be recorded
+// in a graph): ranges[q] = {pointer, bytes}, bytes a multiple of 4.
+struct ZeroRange { void* p; unsigned long long bytes; };
+void launch_fill_zero_ranges(hipStream_t s, const ZeroRange* ranges, int n, unsigned long long max_bytes);
+// Add `steps` to a device step count and `updates` to an update count (one thread).
+void launch_advance_counts(hipStream_t s, uint64_t* step, uint64_t steps, uint32_t* updates, uint32_t n_upd);
 
 }  // namespace rs

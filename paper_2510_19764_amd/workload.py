@@ -127,3 +127,19 @@ TOPO_S4 = dict(name="topomap-64x64-cap32", L=64, cap=32, n_attempts=160, g_max=0
 def sigma_init(p: float, n_pre: int) -> float:
     """Initial weight spread 1/sqrt(expected in-degree)."""
     return float(1.0 / np.sqrt(p * n_pre))
+
+# Batched instances: 64 classifiers on the sparse-classifier input, recurrent
+# sizes log-uniform in [256, 4096], connection probabilities uniform in
+# [0.05, 0.2], one sample per instance and step.
+BATCHED = dict(name="batched-64-classifiers", n_inst=64, n_rec_lo=256, n_rec_hi=4096, p_lo=0.05, p_hi=0.2,
+               n_in=700, n_out=20, batch=1, alif=True, T=1000, update_interval=100, deepr_mask=3, l1=0.005,
+               lr=1e-3)
+
+
+def batched_sizes(seed: int, n: int, lo: int = 256, hi: int = 4096, p_lo: float = 0.05, p_hi: float = 0.2):
+    """Recurrent sizes (log-uniform in [lo, hi]) and connection probabilities
+    (uniform in [p_lo, p_hi]) of n network instances."""
+    rng = np.random.Generator(np.random.Philox(seed + 104729))
+    n_rec = np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), n))).astype(int)
+    p = rng.uniform(p_lo, p_hi, n)
+    return [(int(a), float(b)) for a, b in zip(n_rec, p)]

@@ -18,3 +18,14 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+def pytest_sessionfinish(session, exitstatus):
+    """With RS_MARGINS_OUT set, write the largest error / bound ratio seen per
+    compared quantity by the GPU parity tests (JSON)."""
+    out = os.environ.get("RS_MARGINS_OUT")
+    h = sys.modules.get("gpu_harness")
+    if out and h is not None and h.MARGINS:
+        import json
+        with open(out, "w") as f:
+            json.dump(dict(sorted(h.MARGINS.items())), f, indent=1)

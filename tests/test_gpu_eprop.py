@@ -6,8 +6,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_harness import (close, close_sum, compare_rows_exact, compare_state, gpu_input, interval_vs_oracle,
-                         oracle_net, oracle_step_resync, real_slots, snapshot)
+from gpu_harness import (MARGINS, close, close_sum, compare_rows_exact, compare_state, gpu_input,
+                         interval_vs_oracle, oracle_net, oracle_step_resync, real_slots, snapshot)
 from paper_2510_19764_amd import binding as rb
 from paper_2510_19764_amd import workload as wl
 
@@ -480,12 +480,13 @@ def test_slot_order_is_irrelevant(name):
 
 @pytest.mark.parametrize("name", ["alif-b64-dense", "alif-b64-col", "alif-b3-narrow", "tiny-lif-b1"])
 def test_update_interval_in_one_call_matches_oracle(name):
-    """One step call that crosses an update boundary in the schedule the
-    benchmark uses (blocks of steps; for alif-b64-dense the two-stream hand-off
-    ring, 20 + 5-step blocks, ring segments reused without events), with the
-    automatic Adam update and both DEEP R rewires inside the call, against the
-    oracle taking the same steps, update and rewires one by one.  lr = 0.05
-    so that the update flips signs and DEEP R moves synapses."""
+    """One step call of a whole update interval in the schedule the benchmark
+    uses (blocks of steps; for alif-b64-dense the two-stream hand-off ring,
+    20 + 5-step blocks, ring segments reused without events), ending with the
+    automatic Adam update and both DEEP R rewires, against the oracle taking
+    the same steps, update and rewires one by one; then 10 more steps past the
+    update boundary from the GPU's updated state.  lr = 0.05 so that the
+    update flips signs and DEEP R moves synapses."""
     base, rate = CASES[name]
     cfg = rb.EpropConfig(**{**base.__dict__, "lr": 0.05})
     net = rb.EpropNet(cfg)
@@ -496,8 +497,9 @@ def test_update_interval_in_one_call_matches_oracle(name):
     print(f"{name}: warm-up interval", flush=True)
     net.step(cfg.update_interval, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
     elim0 = net.info().eliminated
-    assert interval_vs_oracle(net, cfg, raster, labels, cfg.update_interval + 10) == 1
+    assert interval_vs_oracle(net, cfg, raster, labels, cfg.update_interval, after=10) == 1
     assert net.info().eliminated > elim0
+    print("worst error / bound:", {k: round(v, 3) for k, v in sorted(MARGINS.items())}, flush=True)
 
 
 def test_long_run_spike_counts_tiny_network():
@@ -540,3 +542,23 @@ def test_long_run_spike_counts_tiny_network():
     assert o > 1000
     assert abs(g - o) <= 0.01 * o, (gpu_counts, orc_counts)
     assert net.info().adam_step == n_samples * T // U
+
+
+@pytest.mark.parametrize("name", ["alif-b64-col", "alif-b64-dense", "alif-b33-narrow"])
+def test_lockstep_with_the_papers_alpha(name):
+    """The 100-step lockstep with the oracle's presynaptic traces decaying by
+    tau_mem's alpha itself (in double) instead of alpha rounded to float as the
+    library stores it.  The float factor is off by 3e-8 relative, which the
+    traces' memory of ~20 steps and the eligibility filter amplify: the
+    traces stay within 1.5e-5 (measured worst element 1.24e-5 of ~30 M), every
+    other quantity within the 1e-5 of the other tests."""
+    cfg, net, raster, labels = setup_case(name)
+    N = oracle_net(snapshot(net), cfg, paper_alpha=True)
+    resync = 0
+    for t in range(100):
+        net.step(1, rb.RS_LEARN)
+        snap = snapshot(net)
+        resync += oracle_step_resync(N, raster, t, labels, snap["z"])
+        compare_state(snap, N, cfg, trace_rtol=1.5e-5)
+    assert resync <= 2
+    print("worst error / bound:", {k: round(v, 3) for k, v in sorted(MARGINS.items())}, flush=True)

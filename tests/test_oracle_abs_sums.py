@@ -1,9 +1,11 @@
 """The oracle's error-bound bookkeeping: beside each sum with cancellation
-(learning signal L, gradients G, Gout, Gb) it keeps the sum of its terms'
-magnitudes, which the GPU parity tests use as the per-element scale of their
-tolerance.  Checked against the terms recomputed from the oracle's per-step
-values, and for the invariants |sum| <= sum of magnitudes, equality when every
-term has one sign, and clearing with the update."""
+(learning signal L, gradients G, Gout, Gb) it keeps the first-order error
+scale of its terms (for L the magnitude of its terms; for the gradients the
+magnitude of each term's factors times the error scales of the others), which
+the GPU parity tests use as the per-element scale of their tolerance.
+Checked against the terms recomputed from the oracle's per-step values, and
+for the invariants |sum| <= scale, its closed form when every term has one
+sign, and clearing with the update."""
 import numpy as np
 
 from helpers import set_rows
@@ -37,38 +39,39 @@ def test_magnitude_sums_follow_their_terms(orc):
         idx = np.nonzero(x)[1].astype(np.int32)
         off = np.concatenate([[0], np.cumsum(x.sum(1))]).astype(np.int32)
         N.step(idx, off, labels)
-        # L and its magnitude sum over the readout units, this step
+        # L and its error scale over the readout units, this step
+        pi = N.delta + (np.arange(N.prm.n_out)[None, :] == labels[:, None])
         terms = N.Wout[None, :, :] * N.delta[:, :, None]          # [B][k][j]
         assert np.allclose(N.L, terms.sum(1), rtol=1e-13, atol=1e-15)
-        assert np.allclose(N.Labs, np.abs(terms).sum(1), rtol=1e-13, atol=1e-15)
-        gout += np.abs(N.delta[:, :, None] * N.zbar[:, None, :]).sum(0)
-        gb += np.abs(N.delta).sum(0)
+        scale = (np.abs(N.Wout)[None, :, :] * (np.abs(N.delta) + pi)[:, :, None]).sum(1)
+        assert np.allclose(N.Labs, scale, rtol=1e-13, atol=1e-15)
+        assert (np.abs(N.L) <= N.Labs).all()
+        gout += (np.abs(N.zbar[:, None, :]) * (2 * np.abs(N.delta) + pi)[:, :, None]).sum(0)
+        gb += (np.abs(N.delta) + pi).sum(0)
         for P in (N.inp, N.rec):
             eb = P.ebar.reshape(P.n_pre, P.cap, B)
             for i in range(P.n_pre):
                 for k in range(int(P.len[i])):
                     j = P.ind[i * P.cap + k]
-                    expect[id(P)][i * P.cap + k] += np.abs(N.L[:, j] * eb[i, k]).sum()
+                    expect[id(P)][i * P.cap + k] += (np.abs(eb[i, k]) * (2 * np.abs(N.L[:, j]) + N.Labs[:, j])).sum()
     for P in (N.inp, N.rec):
         assert np.allclose(P.Gabs, expect[id(P)], rtol=1e-12, atol=0)
         assert (np.abs(P.G) <= P.Gabs * (1 + 1e-12) + 1e-300).all()
         assert P.Gabs.max() > 0
     assert np.allclose(N.Goutabs, gout, rtol=1e-12, atol=0)
     assert np.allclose(N.Gbabs, gb, rtol=1e-12, atol=0)
-    # Gb: the errors of one instance have opposite signs across k, so the
-    # magnitude sum exceeds the sum
-    assert (np.abs(N.Gb) <= N.Gbabs).all() and (N.Gbabs > np.abs(N.Gb)).any()
+    assert (np.abs(N.Gb) <= N.Gbabs).all() and (np.abs(N.Gout) <= N.Goutabs).all()
     N.adam_update(1, l1=0.005, deepr_mask=3)
     for P in (N.inp, N.rec):
         assert not P.Gabs.any() and not P.G.any()
     assert not N.Goutabs.any() and not N.Gbabs.any()
 
 
-def test_single_sign_terms_give_equal_sums(orc):
-    """One instance, one readout unit whose label is the other unit: delta of
-    unit 0 is pi_0 > 0 at every step, so Gb[0] equals its magnitude sum."""
+def test_single_sign_terms_closed_form(orc):
+    """One instance, two readout units, label 1: delta of unit 0 is pi_0 > 0
+    at every step, so its scale sum_t (|delta| + pi) is exactly 2 Gb[0]."""
     rng = np.random.default_rng(5)
     N = net(orc, rng, B=1, n_out=2)
     for t in range(10):
         N.step(np.zeros(1, np.int32), np.zeros(2, np.int32), np.array([1], np.int32))
-    assert N.Gb[0] > 0 and np.isclose(N.Gb[0], N.Gbabs[0], rtol=1e-14)
+    assert N.Gb[0] > 0 and np.isclose(2 * N.Gb[0], N.Gbabs[0], rtol=1e-14)

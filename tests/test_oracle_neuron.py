@@ -151,11 +151,14 @@ def test_propagation_dense_equivalence(orc):
         assert np.allclose(N.a, p.rho * a0 + zf, rtol=1e-14, atol=0)
 
 
-def test_trace_impulse_response(orc):
-    """An input spike at step 0 leaves xbar = alpha^k after k further steps: the
-    presynaptic filter and the membrane share the one tau_mem decay."""
+@pytest.mark.parametrize("alpha_trace", [None, 0.95122945])
+def test_trace_impulse_response(orc, alpha_trace):
+    """An input spike at step 0 leaves xbar = a^k after k further steps, with a
+    the trace decay: tau_mem's alpha itself, or alpha as a float
+    implementation stores it; the membrane keeps alpha."""
     N = tiny_net(orc, 1, 1, 1, 1, False, [[0]], [[0.1]], [[]], [[]])
-    a = N.prm.alpha
+    N.prm.alpha_trace_value = alpha_trace
+    a = N.prm.alpha if alpha_trace is None else alpha_trace
     N.step(*one_input(1, 0), labels=[0])
     for k in range(30):
         assert N.xbar[0, 0] == pytest.approx(a ** k, rel=1e-14, abs=0)
