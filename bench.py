@@ -119,11 +119,27 @@ def oracle_from_seed(cfg):
     return N
 
 
-def run_cpu_baseline(cfg, raster, labels, n_steps: int):
-    """Time the oracle (single-threaded fp64 C) on a bounded sample of the same
-    workload: n_steps timesteps plus one update and two DEEP R rewires."""
+def host_cpu_info():
+    """The timing host: logical CPUs, those this process may use, the model."""
+    import platform
+    import subprocess
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None, "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "machine": platform.machine()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            if k.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Core(s) per socket", "Socket(s)"):
+                info["lscpu " + k.strip()] = v.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def time_oracle_interval(cfg, raster, labels, n_steps: int):
+    """Seconds per timestep and per update + two DEEP R rewires of the oracle
+    (whichever build is in use) over n_steps steps of the workload."""
     import oracle
-    B = cfg.batch
     N = oracle_from_seed(cfg)
     t0 = time.perf_counter()
     for t in range(n_steps):
@@ -134,13 +150,34 @@ def run_cpu_baseline(cfg, raster, labels, n_steps: int):
     N.adam_update(1, lr=cfg.lr, l1=cfg.l1, deepr_mask=cfg.deepr_mask)
     oracle.deepr_rewire(cfg.seed, N.inp, n_steps)
     oracle.deepr_rewire(cfg.seed, N.rec, n_steps)
-    t_upd = time.perf_counter() - t1
-    T, U = cfg.sample_steps, cfg.update_interval
-    t_batch = T * t_step + (T // U) * t_upd
-    return {"value": B / t_batch, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} of {T} timesteps and 1 of {T // U} update+DEEP R intervals of one "
-                      f"{B}-sample batch, extrapolated linearly to the batch",
-            "seconds_per_timestep": t_step, "seconds_per_update_rewire": t_upd}
+    return t_step, time.perf_counter() - t1
+
+
+def run_cpu_baseline(cfg, raster, labels, n_steps: int):
+    """The oracle (fp64 C) timed on the host's cores: its multi-core build
+    (OpenMP over independent instances, rows and readout units; results equal
+    to the parity build's bit for bit) over one whole update interval (the
+    interval's steps, the update and both DEEP R rewires), and the
+    single-threaded parity build over n_steps steps and one update; each
+    extrapolated linearly to the 1000-step, 10-update batch."""
+    import oracle
+    B, T, U = cfg.batch, cfg.sample_steps, cfg.update_interval
+    threads = oracle.use_multicore(True)
+    try:
+        mc_step, mc_upd = time_oracle_interval(cfg, raster, labels, U)
+    finally:
+        oracle.use_multicore(False)
+    st_step, st_upd = time_oracle_interval(cfg, raster, labels, n_steps)
+    mc_batch = T * mc_step + (T // U) * mc_upd
+    st_batch = T * st_step + (T // U) * st_upd
+    return {"value": B / mc_batch, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"one whole update interval ({U} timesteps, the Adam update and both DEEP R rewires) of one "
+                      f"{B}-sample batch on {threads} threads, extrapolated linearly to the {T}-step batch",
+            "seconds_per_timestep": mc_step, "seconds_per_update_rewire": mc_upd,
+            "single_thread": {"value": B / st_batch, "unit": "samples/s", "cores": 1,
+                              "sample": f"{n_steps} of {T} timesteps and one update + DEEP R, extrapolated",
+                              "seconds_per_timestep": st_step, "seconds_per_update_rewire": st_upd},
+            "host": host_cpu_info()}
 
 
 def tiny_net_leg(samples=20, oracle_samples=2):

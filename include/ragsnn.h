@@ -45,6 +45,13 @@ typedef int32_t rs_status;
 /* Message describing the last failed call on this thread ("" if none). */
 const char* rs_last_error(void);
 
+/* Device allocator a caller may hand to rs_create (for example one bound to
+ * a framework's caching allocator): returns `bytes` of device memory on the
+ * current device, or NULL; the free function releases such a block.  `user`
+ * is passed through. */
+typedef void* (*rs_alloc_fn)(size_t bytes, void* user);
+typedef void (*rs_free_fn)(void* ptr, void* user);
+
 /* Counts returned by a rewiring call. */
 typedef struct rs_rewire_stats {
   int64_t eliminated;  /* synapses removed */
@@ -273,8 +280,9 @@ rs_status rs_multi_set_input_poisson(rs_multi* m, uint32_t i, const double* rate
 /* Train every network of the set over n_samples whole samples: for each, what
  * rs_eprop_step(net, sample_steps, RS_LEARN | RS_AUTO_UPDATE | RS_AUTO_RESET)
  * does.  Until the schedule is tuned, each sample runs with the next untried
- * e-prop schedule by direct launches and is timed on the device; after the
- * last the fastest is kept, and later samples replay the recorded graph.
+ * e-prop schedule by direct launches, its e-prop launches timed on the device;
+ * after the last the fastest is kept, and later samples replay the recorded
+ * graph.
  * Errors: RS_ESTATE (an input is missing, or the set is not at a sample
  * boundary), RS_EDEVICE. */
 rs_status rs_multi_train(rs_multi* m, uint32_t n_samples);
@@ -289,7 +297,8 @@ typedef struct rs_multi_schedule {
   uint32_t graph;            /* 1: samples replay the recorded graph */
   uint32_t trace_block;      /* steps per block */
   uint32_t reserved;
-  double sample_ms[RS_MULTI_SCHEDULES];  /* device time of the tuning sample run with each schedule */
+  double sample_ms[RS_MULTI_SCHEDULES];  /* device time of the e-prop launches of the tuning sample run
+                                            with each schedule */
   uint64_t samples;          /* samples trained */
 } rs_multi_schedule;
 rs_status rs_multi_schedule_get(rs_multi* m, rs_multi_schedule* out);
@@ -500,6 +509,133 @@ enum {
 };
 rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes);
 rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes);
+
+/* ==========================================================================
+ * Custom connectivity updates (Sec. 2.1): a rule's host part runs on the
+ * host, its row parts on the device in parallel over the rows, each visiting
+ * its row's synapses (removing some, with the ragged rule: the row's last
+ * synapse moves into the freed slot) and appending new ones.  The rules here
+ * are written on the library's C++ row-update interface (rs_custom.hpp),
+ * which new rules compiled into the library use too:
+ *   RS_RULE_ADD_DIAGONAL   every row i < n_post adds a synapse onto target i,
+ *                          weight 1 (skipped where a connectivity bitfield
+ *                          shows it present); no host part
+ *   RS_RULE_REMOVE_RANDOM  host part: row i picks target below(u32(CUSTOM = 13;
+ *                          step, i, 0, 0), n_post); row part: the first synapse
+ *                          onto it (slot order) is removed
+ *   RS_RULE_DEEPR          DEEP R (Sec. 2.1.2) as elimination row part, the
+ *                          dormant total spread over the rows on the host, and
+ *                          formation row part: the same rows, records and bits
+ *                          as rs_eprop_rewire at the same step
+ *   RS_RULE_TOPO           the topographic rewiring (Sec. 2.1.3): attempts
+ *                          spread over rows on the host, the row part as
+ *                          rs_topo_rewire's: the same rows and weights
+ * New synapses' other variables (optimiser state, gradient, traces) start at
+ * zero.  A host function, when given, runs after the rule's host part and may
+ * change its per-row variable (REMOVE_RANDOM: the target per row; DEEPR: the
+ * activations per row, which must fit each row's room; TOPO: the attempts
+ * per row) before the row part reads it.
+ * ========================================================================== */
+enum { RS_RULE_ADD_DIAGONAL = 1, RS_RULE_REMOVE_RANDOM = 2, RS_RULE_DEEPR = 3, RS_RULE_TOPO = 4 };
+typedef struct rs_custom_host {
+  int32_t n_pre, n_post, cap, recurrent;
+  const int32_t* len;   /* row lengths when the host part runs (read-only) */
+  uint32_t* pre_var;    /* the rule's per-row variable [n_pre] */
+  uint64_t seed, step;
+  uint32_t proj_id;
+  int32_t rule;
+} rs_custom_host;
+typedef void (*rs_host_update_fn)(void* user, rs_custom_host* host);
+/* Run `rule` on projection proj (0 input, 1 recurrent) of an e-prop network
+ * (after the work queued on it), draws keyed by `step`.  Synchronises; with
+ * stats: eliminated = removed, formed = added, attempts = DEEP R's
+ * activations placed, blocked = activations without room.  Errors: RS_EINVAL
+ * (unknown rule, DEEP R without bitfields, a host function's assignment
+ * beyond a row's room). */
+rs_status rs_eprop_custom_update(rs_eprop* net, uint32_t proj, int32_t rule, uint64_t step, rs_host_update_fn fn,
+                                 void* user, rs_rewire_stats* stats);
+/* The same on a topographic map's projection (RS_RULE_TOPO: stats as
+ * rs_topo_rewire's).  An attached simulation rebuilds its column view at its
+ * next launch. */
+rs_status rs_topo_custom_update(rs_topo* t, int32_t rule, uint64_t step, rs_host_update_fn fn, void* user,
+                                rs_rewire_stats* stats);
+
+/* ==========================================================================
+ * Composed networks: the paper's problem statement (Sec. 2.1) as calls --
+ * declare populations and projections with their initialisation, learning
+ * rule and structural-plasticity rule, build, step, trigger the rule, read and
+ * write state.  rs_build recognises the models the kernels implement:
+ *   - the e-prop classifier: a spike source, a LIF or ALIF population and a
+ *     readout; source -> recurrent and recurrent -> recurrent fixed-probability
+ *     projections (DEEP R on either), recurrent -> readout dense; all learn by
+ *     e-prop with one Adam optimiser and update interval;
+ *   - the topographic map: a Poisson sheet projecting onto a conductance-LIF
+ *     sheet of the same size by Gaussian pairwise-Bernoulli rows, STDP or
+ *     fixed weights, topographic rewiring or none.
+ * Any other composition is refused at build with RS_EINVAL naming the misfit.
+ * With an allocator (both functions non-NULL) every device buffer of the
+ * built network comes from it and returns to it at rs_destroy.
+ * ========================================================================== */
+typedef struct rs_net rs_net;
+enum {
+  RS_POP_SPIKE_SOURCE = 0,   /* input channels: a raster or Poisson rates attached by rs_eprop_set_input* */
+  RS_POP_LIF = 1,            /* leaky integrate-and-fire, subtractive reset */
+  RS_POP_ALIF = 2,           /* adaptive LIF */
+  RS_POP_READOUT = 3,        /* leaky readout units */
+  RS_POP_POISSON_SHEET = 4,  /* L x L Poisson source around a moving stimulus */
+  RS_POP_COND_LIF_SHEET = 5  /* L x L conductance-based LIF with refractoriness */
+};
+typedef struct rs_pop_params {
+  float dt_ms, tau_mem_ms, tau_adapt_ms, v_thr, beta;  /* LIF, ALIF */
+  uint32_t L;                                          /* sheets: side, n = L * L */
+  rs_topo_model model;  /* COND_LIF_SHEET: neuron and synapse fields; POISSON_SHEET: stimulus fields */
+} rs_pop_params;
+enum { RS_INIT_FIXED_PROB = 0, RS_INIT_GAUSS_TORUS = 1, RS_INIT_DENSE = 2 };
+enum { RS_LEARN_NONE = 0, RS_LEARN_EPROP = 1, RS_LEARN_STDP = 2 };
+enum { RS_REWIRE_NONE = 0, RS_REWIRE_DEEPR = 1, RS_REWIRE_TOPO = 2 };
+typedef struct rs_proj_desc {
+  int32_t init;                 /* RS_INIT_* */
+  float p, sigma_w;             /* FIXED_PROB: probability, weights sigma_w N(0,1); DENSE: sigma_w N(0,1) */
+  float p_form, sigma_form, g_init;  /* GAUSS_TORUS: p_form exp(-d^2 / 2 sigma_form^2), weight g_init */
+  uint32_t cap;                 /* row capacity, 0 = twice the longest initial row */
+  int32_t learn;                /* RS_LEARN_* (STDP parameters: the target sheet's model) */
+  float lr, adam_b1, adam_b2, adam_eps;  /* EPROP */
+  int32_t rewire;               /* RS_REWIRE_* */
+  float l1;                     /* DEEPR */
+  uint32_t n_attempts;          /* TOPO */
+  float g_theta, p_elim_dep, p_elim_pot, g_new;  /* TOPO */
+  uint32_t update_interval;     /* EPROP: steps between updates (and DEEP R); TOPO: steps between rewires */
+} rs_proj_desc;
+rs_status rs_create(void* hip_stream, rs_alloc_fn alloc_fn, rs_free_fn free_fn, void* user, uint64_t seed,
+                    rs_net** out);
+rs_status rs_add_pop(rs_net* net, int32_t kind, uint32_t n, const rs_pop_params* params, uint32_t* pop);
+rs_status rs_add_proj(rs_net* net, uint32_t pre, uint32_t post, const rs_proj_desc* desc, uint32_t* proj);
+/* Build (the classifier: `batch` instances, samples of sample_steps steps,
+ * trace_block as in rs_eprop_params; the map ignores the three).
+ * Synchronises.  Errors: RS_EINVAL (a composition no model implements, or
+ * invalid parameters), RS_ENOMEM, RS_EDEVICE, RS_ESTATE (built before). */
+rs_status rs_build(rs_net* net, uint32_t batch, uint32_t sample_steps, uint32_t trace_block);
+/* The built model's own object, for the calls specific to it (input, timers,
+ * snapshots); owned by the network. */
+rs_status rs_eprop_of(rs_net* net, rs_eprop** out);
+rs_status rs_topo_of(rs_net* net, rs_topo** out);
+/* Step: rs_eprop_step with `flags`, or rs_topo_run (flags ignored). */
+rs_status rs_step(rs_net* net, uint32_t n_steps, uint32_t flags);
+rs_status rs_update(rs_net* net);
+/* Trigger the projection's structural-plasticity rule now (DEEP R, or one
+ * topographic rewire keyed by the step count). */
+rs_status rs_rewire(rs_net* net, uint32_t proj, rs_rewire_stats* stats);
+/* Rows of a ragged projection: len int32[n_pre], ind int32[n_pre][cap],
+ * w float[n_pre][cap]; *needed = n_pre * cap.  Errors: RS_ECAPACITY when
+ * cap_elems is smaller. */
+rs_status rs_get_rows(rs_net* net, uint32_t proj, int32_t* len, int32_t* ind, float* w, size_t cap_elems,
+                      size_t* needed);
+/* Variables: the classifier's RS_* ids (rs_eprop_get/set), the map's RS_TV_* ids. */
+rs_status rs_get_var(rs_net* net, int32_t var, void* host, size_t bytes);
+rs_status rs_set_var(rs_net* net, int32_t var, const void* host, size_t bytes);
+rs_status rs_sync(rs_net* net);
+uint64_t rs_step_counter(const rs_net* net);
+void rs_destroy(rs_net* net);
 
 /* ==========================================================================
  * Calibration

@@ -27,42 +27,69 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c", "input.c", "topo_sim.c"]
+_SRCS = ["philox.c", "build.c", "eprop.c", "update.c", "deepr.c", "topomap.c", "input.c", "topo_sim.c", "custom.c"]
 _LIB_PATH = os.path.join(_HERE, "_build", "liboracle.so")
 
 TAG_CONN, TAG_WINIT, TAG_SIGN = 1, 2, 3
 TAG_DR_ROW, TAG_DR_TGT = 4, 5
 TAG_TP_ROW, TAG_TP_TGT, TAG_TP_ELIM, TAG_TP_FORM = 6, 7, 8, 9
 TAG_INPUT = 10
+TAG_CUSTOM = 13
 MAX_TRIES = 64
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc into oracle/_build/liboracle.so."""
-    if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
-    os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
+_OMP_LIB_PATH = os.path.join(_HERE, "_build", "liboracle_omp.so")
+
+
+def build(force: bool = True, omp: bool = False) -> str:
+    """Compile the oracle with gcc into oracle/_build/liboracle.so (the
+    single-threaded parity build), or with omp into liboracle_omp.so (the
+    multi-core timing build: the same sources with OpenMP enabled)."""
+    path = _OMP_LIB_PATH if omp else _LIB_PATH
+    if not force and os.path.exists(path):
+        return path
+    os.makedirs(os.path.dirname(path), exist_ok=True)
     srcs = [os.path.join(_HERE, s) for s in _SRCS]
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+    tmp = path + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-Wall", "-Wextra",
-           "-fno-fast-math", "-ffp-contract=off", "-o", tmp] + srcs + ["-lm"]
+           "-fno-fast-math", "-ffp-contract=off"] + (["-fopenmp"] if omp else ["-Wno-unknown-pragmas"]) + \
+        ["-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+    os.replace(tmp, path)
+    return path
 
 
 _lib = None
+_omp_lib = None
+
+
+def _load(path, omp):
+    newest_src = max(os.path.getmtime(os.path.join(_HERE, s)) for s in _SRCS + ["oracle.h"])
+    if not os.path.exists(path) or os.path.getmtime(path) < newest_src:
+        build(omp=omp)
+    L = C.CDLL(path)
+    _declare(L)
+    return L
 
 
 def lib():
     global _lib
     if _lib is None:
-        newest_src = max(os.path.getmtime(os.path.join(_HERE, s)) for s in _SRCS + ["oracle.h"])
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest_src:
-            build()
-        _lib = C.CDLL(_LIB_PATH)
-        _declare(_lib)
+        _lib = _load(_LIB_PATH, False)
     return _lib
+
+
+def use_multicore(on: bool = True) -> int:
+    """Route the calls below to the multi-core timing build (on) or back to
+    the parity build; returns the threads the build runs on."""
+    global _lib, _omp_lib
+    if on:
+        if _omp_lib is None:
+            _omp_lib = _load(_OMP_LIB_PATH, True)
+        _lib = _omp_lib
+    else:
+        _lib = None
+    return int(lib().orc_threads())
 
 
 P_i32 = C.POINTER(C.c_int32)
@@ -127,6 +154,7 @@ class _CTopoDraws(C.Structure):
 
 
 def _declare(L):
+    L.orc_threads.restype = C.c_int32
     L.orc_philox4x64_10.argtypes = [C.c_uint64, C.c_uint64, P_u64, P_u64]
     L.orc_u32.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32] + [C.c_uint64] * 4
     L.orc_u32.restype = C.c_uint32
@@ -173,6 +201,11 @@ def _declare(L):
                                C.POINTER(_CTopoParams), C.POINTER(_CTopoState), C.c_uint64,
                                C.c_uint64, P_u32, P_i32]
     L.orc_torus_d2.restype = C.c_int32
+    L.orc_add_diagonal.argtypes = [C.POINTER(_CProj), C.c_int32]
+    L.orc_add_diagonal.restype = C.c_int32
+    L.orc_remove_random_targets.argtypes = [C.c_uint64, C.POINTER(_CProj), C.c_uint64, P_u32]
+    L.orc_remove_targets.argtypes = [C.POINTER(_CProj), C.c_int32, P_u32]
+    L.orc_remove_targets.restype = C.c_int32
 
 
 def _ptr(a, t):
@@ -340,6 +373,24 @@ def deepr_rewire(seed: int, P: Proj, step: int):
     stats = np.zeros(2, np.int32)
     lib().orc_deepr_rewire(seed, C.byref(P.c()), P.batch, step, _ptr(dormant, P_i32), _ptr(stats, P_i32))
     return dormant, stats
+
+
+def add_diagonal(P: Proj) -> int:
+    """The paper's add_diagonal example (custom connectivity update)."""
+    return int(lib().orc_add_diagonal(C.byref(P.c()), P.batch))
+
+
+def remove_random_targets(seed: int, P: Proj, step: int) -> np.ndarray:
+    """Host part of the paper's remove_random example: one target per row."""
+    out = np.zeros(P.n_pre, np.uint32)
+    lib().orc_remove_random_targets(seed, C.byref(P.c()), step, _ptr(out, P_u32))
+    return out
+
+
+def remove_targets(P: Proj, post_ind) -> int:
+    """Row part of remove_random: remove each row's first synapse onto post_ind[row]."""
+    a = np.ascontiguousarray(post_ind, np.uint32)
+    return int(lib().orc_remove_targets(C.byref(P.c()), P.batch, _ptr(a, P_u32)))
 
 
 # ---------------------------------------------------------------- e-prop network

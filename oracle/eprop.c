@@ -23,6 +23,11 @@
  *     with ebar including this step's e, i.e. the loss is summed over steps.
  *   - z = 1 when v >= threshold; recurrent rows never contain autapses.
  * All sums over the batch are plain sums; the update divides by B.
+ *
+ * Loops over independent items (batch instances, rows, readout units) carry
+ * OpenMP pragmas for the multi-core timing build; every value is computed by
+ * the same operations in the same order in either build, so the two agree
+ * bit for bit.  The parity build compiles without OpenMP.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -61,6 +66,7 @@ void orc_eprop_reset(orc_net *N)
 static void eligibility(const orc_net *N, orc_proj *P, const double *pre)
 {
     int32_t B = N->batch;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < P->n_pre; ++i)
         for (int32_t k = 0; k < P->len[i]; ++k) {
             int64_t s = (int64_t)i * P->cap + k;
@@ -85,6 +91,7 @@ static void eligibility(const orc_net *N, orc_proj *P, const double *pre)
 static void accumulate_grad(const orc_net *N, orc_proj *P)
 {
     int32_t B = N->batch;
+#pragma omp parallel for schedule(dynamic, 16)
     for (int32_t i = 0; i < P->n_pre; ++i)
         for (int32_t k = 0; k < P->len[i]; ++k) {
             int64_t s = (int64_t)i * P->cap + k;
@@ -104,10 +111,9 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
                     const int32_t *labels, const uint8_t *z_force, int32_t learn)
 {
     const int32_t B = N->batch, NR = N->n_rec, NI = N->n_in, K = N->n_out;
-    double *I = (double *)calloc((size_t)NR, sizeof(double));
-    uint8_t *x = (uint8_t *)calloc((size_t)NI, 1);
 
     /* 1. spikes and surrogate derivative from the state at the start of the step */
+#pragma omp parallel for schedule(static)
     for (int32_t b = 0; b < B; ++b)
         for (int32_t j = 0; j < NR; ++j) {
             int64_t q = (int64_t)b * NR + j;
@@ -123,68 +129,80 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         eligibility(N, N->rec, N->zbar);
     }
 
-    for (int32_t b = 0; b < B; ++b) {
-        const int32_t *xs = x_idx + x_off[b];
-        int32_t nx = x_off[b + 1] - x_off[b];
-        uint8_t *zb = N->z + (int64_t)b * NR;
-        memset(I, 0, sizeof(double) * NR);
-        memset(x, 0, (size_t)NI);
-        /* 3. propagation through the ragged rows of spiking sources */
-        for (int32_t q = 0; q < nx; ++q) {
-            int32_t i = xs[q];
-            x[i] = 1;
-            for (int32_t k = 0; k < N->in->len[i]; ++k) {
-                int64_t s = (int64_t)i * N->in->cap + k;
-                I[N->in->ind[s]] += N->in->w[s];
+    /* 3.-7. per batch instance; the instances are independent */
+#pragma omp parallel
+    {
+        double *I = (double *)calloc((size_t)NR, sizeof(double));
+        uint8_t *x = (uint8_t *)calloc((size_t)NI, 1);
+#pragma omp for schedule(static)
+        for (int32_t b = 0; b < B; ++b) {
+            const int32_t *xs = x_idx + x_off[b];
+            int32_t nx = x_off[b + 1] - x_off[b];
+            uint8_t *zb = N->z + (int64_t)b * NR;
+            memset(I, 0, sizeof(double) * NR);
+            memset(x, 0, (size_t)NI);
+            /* 3. propagation through the ragged rows of spiking sources */
+            for (int32_t q = 0; q < nx; ++q) {
+                int32_t i = xs[q];
+                x[i] = 1;
+                for (int32_t k = 0; k < N->in->len[i]; ++k) {
+                    int64_t s = (int64_t)i * N->in->cap + k;
+                    I[N->in->ind[s]] += N->in->w[s];
+                }
             }
-        }
-        for (int32_t i = 0; i < NR; ++i) {
-            if (!zb[i]) continue;
-            for (int32_t k = 0; k < N->rec->len[i]; ++k) {
-                int64_t s = (int64_t)i * N->rec->cap + k;
-                I[N->rec->ind[s]] += N->rec->w[s];
+            for (int32_t i = 0; i < NR; ++i) {
+                if (!zb[i]) continue;
+                for (int32_t k = 0; k < N->rec->len[i]; ++k) {
+                    int64_t s = (int64_t)i * N->rec->cap + k;
+                    I[N->rec->ind[s]] += N->rec->w[s];
+                }
             }
-        }
-        /* 4. neuron update with subtractive reset */
-        for (int32_t j = 0; j < NR; ++j) {
-            int64_t q = (int64_t)b * NR + j;
-            N->v[q] = N->alpha * (N->v[q] - zb[j] * N->v_thr) + I[j];
-            N->a[q] = N->rho * N->a[q] + zb[j];
-        }
-        /* 5. presynaptic traces */
-        for (int32_t i = 0; i < NI; ++i)
-            N->xbar[(int64_t)b * NI + i] = N->alpha_trace * N->xbar[(int64_t)b * NI + i] + x[i];
-        for (int32_t j = 0; j < NR; ++j)
-            N->zbar[(int64_t)b * NR + j] = N->alpha_trace * N->zbar[(int64_t)b * NR + j] + zb[j];
-        /* 6. leaky readout, softmax, output error */
-        double *yb = N->y + (int64_t)b * K;
-        double ymax = -INFINITY;
-        for (int32_t k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int32_t j = 0; j < NR; ++j) s += N->Wout[(int64_t)k * NR + j] * zb[j];
-            yb[k] = N->alpha * yb[k] + s + N->bout[k];
-            if (yb[k] > ymax) ymax = yb[k];
-        }
-        double den = 0.0;
-        for (int32_t k = 0; k < K; ++k) den += exp(yb[k] - ymax);
-        for (int32_t k = 0; k < K; ++k) {
-            double pi = exp(yb[k] - ymax) / den;
-            N->delta[(int64_t)b * K + k] = pi - (k == labels[b] ? 1.0 : 0.0);
-        }
-        /* 7. learning signal through B = W_out^T */
-        for (int32_t j = 0; j < NR; ++j) {
-            double l = 0.0, la = 0.0;
+            /* 4. neuron update with subtractive reset */
+            for (int32_t j = 0; j < NR; ++j) {
+                int64_t q = (int64_t)b * NR + j;
+                N->v[q] = N->alpha * (N->v[q] - zb[j] * N->v_thr) + I[j];
+                N->a[q] = N->rho * N->a[q] + zb[j];
+            }
+            /* 5. presynaptic traces */
+            for (int32_t i = 0; i < NI; ++i)
+                N->xbar[(int64_t)b * NI + i] = N->alpha_trace * N->xbar[(int64_t)b * NI + i] + x[i];
+            for (int32_t j = 0; j < NR; ++j)
+                N->zbar[(int64_t)b * NR + j] = N->alpha_trace * N->zbar[(int64_t)b * NR + j] + zb[j];
+            /* 6. leaky readout, softmax, output error */
+            double *yb = N->y + (int64_t)b * K;
+            double ymax = -INFINITY;
             for (int32_t k = 0; k < K; ++k) {
-                double d = N->delta[(int64_t)b * K + k], pi = d + (k == labels[b] ? 1.0 : 0.0);
-                l += N->Wout[(int64_t)k * NR + j] * d;
-                la += fabs(N->Wout[(int64_t)k * NR + j]) * (fabs(d) + pi);
+                double s = 0.0;
+                for (int32_t j = 0; j < NR; ++j) s += N->Wout[(int64_t)k * NR + j] * zb[j];
+                yb[k] = N->alpha * yb[k] + s + N->bout[k];
+                if (yb[k] > ymax) ymax = yb[k];
             }
-            N->L[(int64_t)b * NR + j] = l;
-            if (N->Labs) N->Labs[(int64_t)b * NR + j] = la;
-        }
-        /* 8. readout delta rule */
-        if (learn) {
+            double den = 0.0;
+            for (int32_t k = 0; k < K; ++k) den += exp(yb[k] - ymax);
             for (int32_t k = 0; k < K; ++k) {
+                double pi = exp(yb[k] - ymax) / den;
+                N->delta[(int64_t)b * K + k] = pi - (k == labels[b] ? 1.0 : 0.0);
+            }
+            /* 7. learning signal through B = W_out^T */
+            for (int32_t j = 0; j < NR; ++j) {
+                double l = 0.0, la = 0.0;
+                for (int32_t k = 0; k < K; ++k) {
+                    double d = N->delta[(int64_t)b * K + k], pi = d + (k == labels[b] ? 1.0 : 0.0);
+                    l += N->Wout[(int64_t)k * NR + j] * d;
+                    la += fabs(N->Wout[(int64_t)k * NR + j]) * (fabs(d) + pi);
+                }
+                N->L[(int64_t)b * NR + j] = l;
+                if (N->Labs) N->Labs[(int64_t)b * NR + j] = la;
+            }
+        }
+        free(I);
+        free(x);
+    }
+    /* 8. readout delta rule, summed over the instances in their order */
+    if (learn) {
+#pragma omp parallel for schedule(static)
+        for (int32_t k = 0; k < K; ++k) {
+            for (int32_t b = 0; b < B; ++b) {
                 double d = N->delta[(int64_t)b * K + k];
                 double pi = d + (k == labels[b] ? 1.0 : 0.0);
                 for (int32_t j = 0; j < NR; ++j) {
@@ -202,6 +220,4 @@ void orc_eprop_step(orc_net *N, const int32_t *x_idx, const int32_t *x_off,
         accumulate_grad(N, N->in);
         accumulate_grad(N, N->rec);
     }
-    free(I);
-    free(x);
 }

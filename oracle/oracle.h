@@ -43,13 +43,17 @@ enum {
     ORC_TAG_TP_FORM = 9, /* topomap formation draw,       counter (step, r, j, 0) */
     ORC_TAG_INPUT = 10,  /* Poisson input spike,          counter (step, b, i, 0) */
     ORC_TAG_STIM = 11,   /* topomap stimulus position,    counter (epoch, k, 0, 0) */
-    ORC_TAG_TP_INPUT = 12 /* topomap source spikes,       counter (step, i/8, 0, 0), 8 per call */
+    ORC_TAG_TP_INPUT = 12, /* topomap source spikes,      counter (step, i/8, 0, 0), 8 per call */
+    ORC_TAG_CUSTOM = 13  /* custom update draws,          counter (step, i, 0, 0) */
 };
 
 /* Draws per (row, activation) before the bounded fallback scan takes over. */
 #define ORC_MAX_TRIES 64
 /* Distribution rounds before the deterministic fallback assignment. */
 #define ORC_MAX_ROUNDS 64
+
+/* Threads of the multi-core timing build (1 in the parity build). */
+int32_t orc_threads(void);
 
 /* ---- counter-based generator --------------------------------------------- */
 void orc_philox4x64_10(uint64_t key0, uint64_t key1, const uint64_t ctr[4], uint64_t out[4]);
@@ -155,6 +159,17 @@ void orc_adam_update(orc_net *N, int32_t k, double lr, double b1, double b2, dou
  * stats[0] = eliminated, stats[1] = formed. */
 void orc_deepr_rewire(uint64_t seed, orc_proj *P, int32_t batch, uint64_t step,
                       int32_t *dormant, int32_t *stats);
+
+/* Custom connectivity updates: the paper's worked examples (Sec. 2.1).
+ * add_diagonal adds synapse i -> i (weight 1) to every row i < n_post with
+ * room (and, with a bitfield, not yet connected); returns the count.
+ * remove_random's host part draws post_ind[i] = below(u32(CUSTOM; step, i, 0,
+ * 0), n_post); its row part removes each row's first synapse (slot order)
+ * onto post_ind[i] by moving the row's last synapse into its slot; returns
+ * the count removed. */
+int32_t orc_add_diagonal(orc_proj *P, int32_t batch);
+void orc_remove_random_targets(uint64_t seed, const orc_proj *P, uint64_t step, uint32_t *post_ind);
+int32_t orc_remove_targets(orc_proj *P, int32_t batch, const uint32_t *post_ind);
 
 /* Topographic-map rewiring (paper, Sec. 2.1.3, Fig. 3, Tab. B and G). */
 typedef struct orc_topo_params {

@@ -82,3 +82,11 @@ double orc_normal(uint64_t seed, uint32_t tag, uint32_t proj, uint64_t c0, uint6
     double u2 = (double)(o[1] >> 11) * two_m53;       /* [0, 1) */
     return sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
 }
+
+/* Threads the loops with OpenMP pragmas run on: 1 in the parity build. */
+#ifdef _OPENMP
+#include <omp.h>
+int32_t orc_threads(void) { return (int32_t)omp_get_max_threads(); }
+#else
+int32_t orc_threads(void) { return 1; }
+#endif

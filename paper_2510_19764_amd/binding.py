@@ -91,6 +91,9 @@ EXPORTS = [
     "rs_multi_destroy",
     "rs_serve_create", "rs_serve_submit", "rs_serve_step", "rs_serve_poll", "rs_serve_stats_get",
     "rs_serve_replay", "rs_serve_destroy",
+    "rs_create", "rs_add_pop", "rs_add_proj", "rs_build", "rs_eprop_of", "rs_topo_of", "rs_step", "rs_update",
+    "rs_rewire", "rs_get_rows", "rs_get_var", "rs_set_var", "rs_sync", "rs_step_counter", "rs_destroy",
+    "rs_eprop_custom_update", "rs_topo_custom_update",
 ]
 
 _lib = None
@@ -161,10 +164,29 @@ def lib():
                                       C.POINTER(C.c_int32), C.POINTER(C.c_uint64)]
         L.rs_serve_destroy.argtypes = [vp]
         L.rs_serve_destroy.restype = None
+        L.rs_create.argtypes = [vp, _ALLOC_FN, _FREE_FN, vp, C.c_uint64, C.POINTER(vp)]
+        L.rs_add_pop.argtypes = [vp, C.c_int32, C.c_uint32, C.POINTER(_PopParams), C.POINTER(C.c_uint32)]
+        L.rs_add_proj.argtypes = [vp, C.c_uint32, C.c_uint32, C.POINTER(_ProjDesc), C.POINTER(C.c_uint32)]
+        L.rs_build.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
+        L.rs_eprop_of.argtypes = [vp, C.POINTER(vp)]
+        L.rs_topo_of.argtypes = [vp, C.POINTER(vp)]
+        L.rs_step.argtypes = [vp, C.c_uint32, C.c_uint32]
+        L.rs_update.argtypes = [vp]
+        L.rs_rewire.argtypes = [vp, C.c_uint32, C.POINTER(_Stats)]
+        L.rs_get_rows.argtypes = [vp, C.c_uint32, vp, vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+        L.rs_get_var.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_set_var.argtypes = [vp, C.c_int32, vp, C.c_size_t]
+        L.rs_sync.argtypes = [vp]
+        L.rs_step_counter.argtypes = [vp]
+        L.rs_step_counter.restype = C.c_uint64
+        L.rs_destroy.argtypes = [vp]
+        L.rs_destroy.restype = None
+        L.rs_eprop_custom_update.argtypes = [vp, C.c_uint32, C.c_int32, C.c_uint64, _HOST_FN, vp, C.POINTER(_Stats)]
+        L.rs_topo_custom_update.argtypes = [vp, C.c_int32, C.c_uint64, _HOST_FN, vp, C.POINTER(_Stats)]
         for name in EXPORTS:
             f = getattr(L, name)
             if name not in ("rs_last_error", "rs_eprop_destroy", "rs_topo_destroy", "rs_multi_destroy",
-                            "rs_serve_destroy"):
+                            "rs_serve_destroy", "rs_destroy", "rs_step_counter"):
                 f.restype = st
         _lib = L
     return _lib
@@ -238,7 +260,19 @@ class EpropNet:
         _check(lib().rs_eprop_create(C.byref(cfg.c()), self._stream, C.byref(self._h)))
         self.info()
 
+    @classmethod
+    def _view(cls, handle, cfg, owner):
+        """A network owned by another object (it is not destroyed by close)."""
+        v = cls.__new__(cls)
+        v.cfg, v._h, v._owner, v._input_refs = cfg, handle, owner, None
+        v._stream = None
+        v.info()
+        return v
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = C.c_void_p()
+            return
         if self._h:
             lib().rs_eprop_destroy(self._h)
             self._h = C.c_void_p()
@@ -284,6 +318,14 @@ class EpropNet:
 
     def reset(self):
         _check(lib().rs_eprop_reset(self._h))
+
+    def custom_update(self, proj: int, rule: int, step: int, host_fn=None) -> RewireStats:
+        """A custom connectivity update (rs_eprop_custom_update); host_fn(len,
+        pre_var, info) may change the rule's per-row variable in place."""
+        st = _Stats()
+        cb = _host_fn(host_fn)
+        _check(lib().rs_eprop_custom_update(self._h, proj, rule, step, cb, None, C.byref(st)))
+        return _custom_stats(st)
 
     # ---- snapshots
     def shape_of(self, var: int):
@@ -339,6 +381,143 @@ def _shape_of(c, inf, var: int):
             P_EPS: ((n_pre, cap, B), np.float32), P_EBAR: ((n_pre, cap, B), np.float32),
             P_CONN: ((n_pre, words), np.uint32), P_SIGN: ((n_pre, words), np.uint32),
             P_DORMANT: ((n_pre,), np.int32)}[f]
+
+
+RULE_ADD_DIAGONAL, RULE_REMOVE_RANDOM, RULE_DEEPR, RULE_TOPO = 1, 2, 3, 4
+
+
+class _CustomHost(C.Structure):
+    _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("cap", C.c_int32), ("recurrent", C.c_int32),
+                ("len", C.POINTER(C.c_int32)), ("pre_var", C.POINTER(C.c_uint32)), ("seed", C.c_uint64),
+                ("step", C.c_uint64), ("proj_id", C.c_uint32), ("rule", C.c_int32)]
+
+
+_HOST_FN = C.CFUNCTYPE(None, C.c_void_p, C.POINTER(_CustomHost))
+
+
+def _host_fn(fn):
+    """Wrap fn(len: np.ndarray, pre_var: np.ndarray (writable), info: dict) as
+    a host function of a custom connectivity update."""
+    if fn is None:
+        return _HOST_FN()
+
+    def call(user, hp):
+        h = hp.contents
+        ln = np.ctypeslib.as_array(h.len, shape=(h.n_pre,))
+        var = np.ctypeslib.as_array(h.pre_var, shape=(h.n_pre,))
+        fn(ln, var, dict(n_pre=h.n_pre, n_post=h.n_post, cap=h.cap, recurrent=bool(h.recurrent), seed=h.seed,
+                         step=h.step, proj_id=h.proj_id, rule=h.rule))
+    return _HOST_FN(call)
+
+
+def _custom_stats(st):
+    return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
+
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+POP_SPIKE_SOURCE, POP_LIF, POP_ALIF, POP_READOUT, POP_POISSON_SHEET, POP_COND_LIF_SHEET = range(6)
+INIT_FIXED_PROB, INIT_GAUSS_TORUS, INIT_DENSE = range(3)
+LEARN_NONE, LEARN_EPROP, LEARN_STDP = range(3)
+REWIRE_NONE, REWIRE_DEEPR, REWIRE_TOPO = range(3)
+
+
+class _PopParams(C.Structure):
+    _fields_ = [("dt_ms", C.c_float), ("tau_mem_ms", C.c_float), ("tau_adapt_ms", C.c_float), ("v_thr", C.c_float),
+                ("beta", C.c_float), ("L", C.c_uint32), ("model", _TopoModel)]
+
+
+class _ProjDesc(C.Structure):
+    _fields_ = [("init", C.c_int32), ("p", C.c_float), ("sigma_w", C.c_float), ("p_form", C.c_float),
+                ("sigma_form", C.c_float), ("g_init", C.c_float), ("cap", C.c_uint32), ("learn", C.c_int32),
+                ("lr", C.c_float), ("adam_b1", C.c_float), ("adam_b2", C.c_float), ("adam_eps", C.c_float),
+                ("rewire", C.c_int32), ("l1", C.c_float), ("n_attempts", C.c_uint32), ("g_theta", C.c_float),
+                ("p_elim_dep", C.c_float), ("p_elim_pot", C.c_float), ("g_new", C.c_float),
+                ("update_interval", C.c_uint32)]
+
+
+def torch_allocator():
+    """Allocator callbacks bound to torch's caching allocator (on the current
+    device and stream)."""
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes))
+        except Exception:
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    return _ALLOC_FN(alloc), _FREE_FN(free)
+
+
+class ComposedNet:
+    """A network declared population by population and projection by
+    projection (rs_create / rs_add_pop / rs_add_proj / rs_build).  With
+    allocator=True its device memory comes from torch's caching allocator."""
+
+    def __init__(self, seed=1, allocator=True, stream=None):
+        self._h = C.c_void_p()
+        self._fns = torch_allocator() if allocator else (_ALLOC_FN(), _FREE_FN())
+        _check(lib().rs_create(_stream_ptr(stream), self._fns[0], self._fns[1], None, seed, C.byref(self._h)))
+        self.pops, self.projs = [], []
+
+    def close(self):
+        if self._h:
+            lib().rs_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def add_pop(self, kind, n, dt_ms=1.0, tau_mem_ms=20.0, tau_adapt_ms=2000.0, v_thr=0.6, beta=0.0174, L=0,
+                model=None):
+        p = _PopParams(dt_ms, tau_mem_ms, tau_adapt_ms, v_thr, beta, L, (model or TopoModel()).c())
+        q = C.c_uint32()
+        _check(lib().rs_add_pop(self._h, kind, n, C.byref(p), C.byref(q)))
+        self.pops.append((kind, n))
+        return q.value
+
+    def add_proj(self, pre, post, **kw):
+        d = _ProjDesc()
+        d.adam_b1, d.adam_b2, d.adam_eps, d.lr = 0.9, 0.999, 1e-8, 1e-3
+        for k, v in kw.items():
+            setattr(d, k, v)
+        q = C.c_uint32()
+        _check(lib().rs_add_proj(self._h, pre, post, C.byref(d), C.byref(q)))
+        self.projs.append(kw)
+        return q.value
+
+    def build(self, batch=1, sample_steps=1000, trace_block=0):
+        _check(lib().rs_build(self._h, batch, sample_steps, trace_block))
+
+    def eprop(self, cfg):
+        """The built classifier as an EpropNet view (owned by this network)."""
+        h = C.c_void_p()
+        _check(lib().rs_eprop_of(self._h, C.byref(h)))
+        return EpropNet._view(h, cfg, self)
+
+    def topo(self, cfg):
+        h = C.c_void_p()
+        _check(lib().rs_topo_of(self._h, C.byref(h)))
+        return TopoNet._view(h, cfg, self)
+
+    def step(self, n, flags=RS_LEARN):
+        _check(lib().rs_step(self._h, n, flags))
+
+    def rewire(self, proj) -> RewireStats:
+        st = _Stats()
+        _check(lib().rs_rewire(self._h, proj, C.byref(st)))
+        return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
+
+    def step_counter(self) -> int:
+        return int(lib().rs_step_counter(self._h))
 
 
 class _ServeParams(C.Structure):
@@ -559,7 +738,18 @@ class TopoNet:
         self.n = cfg.L * cfg.L
         self.words = (self.n + 31) // 32
 
+    @classmethod
+    def _view(cls, handle, cfg, owner):
+        v = cls.__new__(cls)
+        v.cfg, v._h, v._owner = cfg, handle, owner
+        v.n = cfg.L * cfg.L
+        v.words = (v.n + 31) // 32
+        return v
+
     def close(self):
+        if getattr(self, "_owner", None) is not None:
+            self._h = C.c_void_p()
+            return
         if self._h:
             lib().rs_topo_destroy(self._h)
             self._h = C.c_void_p()
@@ -590,6 +780,12 @@ class TopoNet:
         w = np.ascontiguousarray(w, np.float32)
         _check(lib().rs_topo_set_rows(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
                                       w.ctypes.data_as(C.c_void_p)))
+
+    def custom_update(self, rule: int, step: int, host_fn=None) -> RewireStats:
+        st = _Stats()
+        cb = _host_fn(host_fn)
+        _check(lib().rs_topo_custom_update(self._h, rule, step, cb, None, C.byref(st)))
+        return _custom_stats(st)
 
     def get_bits(self):
         b = np.empty((self.n, self.words), np.uint32)

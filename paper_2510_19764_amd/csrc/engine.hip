@@ -14,6 +14,8 @@
 #include <vector>
 
 #include "../../include/ragsnn.h"
+#include "rs_device.hpp"
+#include "rs_host_rng.hpp"
 #include "rs_kernels.hpp"
 
 using namespace rs;
@@ -60,27 +62,41 @@ uint64_t threshold(double p) {
   return (uint64_t)std::floor(p * 4294967296.0);
 }
 
-// Device allocation list owned by one object.
+// Device allocation list owned by one object: through the caller's
+// allocator when one was given (rs_create), else hipMalloc.
 struct Arena {
   std::vector<void*> ptrs;
   uint64_t bytes = 0;
+  rs_alloc_fn afn = nullptr;
+  rs_free_fn ffn = nullptr;
+  void* user = nullptr;
+  void* raw(size_t b) {
+    void* q = nullptr;
+    if (afn) return afn(b, user);
+    if (hipMalloc(&q, b) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return q;
+  }
+  void raw_free(void* q) {
+    if (ffn) ffn(q, user);
+    else (void)hipFree(q);
+  }
   template <class T>
   rs_status alloc(T** p, size_t n) {
     *p = nullptr;
     if (n == 0) return RS_OK;
-    void* q = nullptr;
     size_t b = (n * sizeof(T) + 255) & ~(size_t)255;
-    if (hipMalloc(&q, b) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(RS_ENOMEM, "device allocation of %zu bytes failed", b);
-    }
+    void* q = raw(b);
+    if (!q) return fail(RS_ENOMEM, "device allocation of %zu bytes failed", b);
     ptrs.push_back(q);
     bytes += b;
     *p = (T*)q;
     return RS_OK;
   }
   void release() {
-    for (void* q : ptrs) (void)hipFree(q);
+    for (void* q : ptrs) raw_free(q);
     ptrs.clear();
     bytes = 0;
   }
@@ -141,6 +157,9 @@ struct PhaseTimer {
 
 constexpr int RING_MAX = 8;  // hand-off ring segments at most
 
+struct rs_custom_state;
+void delete_custom(rs_custom_state* c);
+
 struct rs_eprop {
   rs_eprop_params p;
   hipStream_t stream = nullptr;
@@ -194,6 +213,7 @@ struct rs_eprop {
   uint32_t adam_k = 0;
   double alpha = 0.0, rho = 0.0, beta = 0.0;  // decay factors exp(-dt/tau) in double
   PhaseTimer timer;
+  struct rs_custom_state* custom = nullptr;  // scratch of custom connectivity updates
   bool dead = false;  // a device error occurred: every later call fails with RS_EDEVICE
 };
 
@@ -230,9 +250,9 @@ void zero_proj_state(hipStream_t s, const ProjDev& P, int B) {
 }
 
 // Count rows on the device, return the longest.
-rs_status count_rows(hipStream_t s, uint64_t seed, ProjDev& P, uint64_t T, int* max_len) {
-  int* d_len = nullptr;
-  HIP_OK(hipMalloc(&d_len, sizeof(int) * P.n_pre));
+rs_status count_rows(Arena& ar, hipStream_t s, uint64_t seed, ProjDev& P, uint64_t T, int* max_len) {
+  int* d_len = (int*)ar.raw(((size_t)P.n_pre * sizeof(int) + 255) & ~(size_t)255);
+  if (!d_len) return fail(RS_ENOMEM, "device allocation for row counts failed");
   ProjDev tmp = P;
   tmp.len = d_len;
   tmp.cap = 0;
@@ -240,7 +260,7 @@ rs_status count_rows(hipStream_t s, uint64_t seed, ProjDev& P, uint64_t T, int* 
   std::vector<int> h(P.n_pre);
   hipError_t e = hipMemcpyAsync(h.data(), d_len, sizeof(int) * P.n_pre, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(d_len);
+  ar.raw_free(d_len);
   if (e != hipSuccess) return fail(RS_EDEVICE, "row count: %s", hipGetErrorString(e));
   *max_len = P.n_pre ? *std::max_element(h.begin(), h.end()) : 0;
   return RS_OK;
@@ -269,12 +289,17 @@ rs_status validate(const rs_eprop_params* p) {
   return RS_OK;
 }
 
-rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) {
+rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, const Arena* alloc = nullptr) {
   TRY(validate(prm));
   if (!fwd_fits((int)prm->n_in, (int)prm->n_rec, (int)prm->n_out))
     return fail(RS_EINVAL, "n_in %u and n_rec %u need more LDS than a forward workgroup has", prm->n_in, prm->n_rec);
   rs_eprop* n = new rs_eprop();
   *out = n;
+  if (alloc) {
+    n->arena.afn = alloc->afn;
+    n->arena.ffn = alloc->ffn;
+    n->arena.user = alloc->user;
+  }
   n->p = *prm;
   n->stream = (hipStream_t)stream;
   n->B = (int)prm->batch;
@@ -292,7 +317,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out) 
     P.proj_id = id;
     P.words = (n_post + 31) / 32;
     int mx = 0;
-    TRY(count_rows(s, seed, P, threshold(p), &mx));
+    TRY(count_rows(n->arena, s, seed, P, threshold(p), &mx));
     int cap = cap_req ? (int)cap_req : 2 * mx;
     cap = std::min(cap, n_post);
     cap = std::max(cap, 1);
@@ -940,6 +965,7 @@ void rs_eprop_destroy(rs_eprop* n) {
     if (n->side2) (void)hipStreamDestroy(n->side2);
   }
   n->arena.release();
+  delete_custom(n->custom);
   delete n;
 }
 
@@ -971,6 +997,7 @@ struct rs_topo {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  struct rs_custom_state* custom = nullptr;  // scratch of custom connectivity updates
   bool dead = false;  // a device error occurred: every later call fails with RS_EDEVICE
 };
 
@@ -1418,6 +1445,7 @@ void rs_topo_destroy(rs_topo* t) {
   if (t->ev0) (void)hipEventDestroy(t->ev0);
   if (t->ev1) (void)hipEventDestroy(t->ev1);
   t->arena.release();
+  delete_custom(t->custom);
   delete t;
 }
 
@@ -1700,7 +1728,7 @@ rs_status multi_build_tables(rs_multi* m) {
 // e-prop launch on `e`, updates, rewiring and the reset on `e`, with the
 // one-network path's event pattern between the two streams.  The same calls
 // run directly or under stream capture.
-void multi_issue_sample(rs_multi* m, int sched, hipStream_t s, hipStream_t e) {
+void multi_issue_sample(rs_multi* m, int sched, hipStream_t s, hipStream_t e, std::vector<hipEvent_t>* ep_ev = nullptr) {
   unsigned char* T = m->tab;
   bool pending[RING_MAX] = {};
   size_t bi = 0, ui = 0;
@@ -1721,8 +1749,17 @@ void multi_issue_sample(rs_multi* m, int sched, hipStream_t s, hipStream_t e) {
                            (const int4*)(T + b.work_ls), b.n_ls);
       (void)hipEventRecord(m->ev_fwd, s);
       (void)hipStreamWaitEvent(e, m->ev_fwd, 0);
+      if (ep_ev) {
+        hipEvent_t a = nullptr, z = nullptr;
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&z);
+        ep_ev->push_back(a);
+        ep_ev->push_back(z);
+        (void)hipEventRecord(a, e);
+      }
       launch_eprop_narrow_multi(e, (const EpropArgs*)(T + b.ep), (const int4*)(T + b.work_ep[sched]),
                                 b.n_ep[sched], m->alif, SCHED_TPR[sched], SCHED_GRID[sched]);
+      if (ep_ev) (void)hipEventRecord(ep_ev->back(), e);
       if (!b.covered) {
         (void)hipEventRecord(m->ev_ep[b.h], e);
         pending[b.h] = true;
@@ -1777,7 +1814,8 @@ rs_status multi_build_graph(rs_multi* m) {
 }
 
 // One sample, by graph replay or by direct launches; host counters follow.
-rs_status multi_run_sample(rs_multi* m, int sched, bool graph) {
+// With ep_ms, the e-prop launches are timed (direct launches only).
+rs_status multi_run_sample(rs_multi* m, int sched, bool graph, double* ep_ms = nullptr) {
   if (graph) {
     if (!m->gexec || m->graph_sched != sched) {
       m->sched = sched;
@@ -1786,7 +1824,18 @@ rs_status multi_run_sample(rs_multi* m, int sched, bool graph) {
     HIP_OK(hipGraphLaunch(m->gexec, m->stream));
   } else {
     order(m->ev_join, m->stream, m->side);
-    multi_issue_sample(m, sched, m->stream, m->side);
+    std::vector<hipEvent_t> ev;
+    multi_issue_sample(m, sched, m->stream, m->side, ep_ms ? &ev : nullptr);
+    if (ep_ms) {
+      *ep_ms = 0;
+      for (size_t q = 0; q + 1 < ev.size(); q += 2) {
+        float t = 0.f;
+        HIP_OK(hipEventSynchronize(ev[q + 1]));
+        HIP_OK(hipEventElapsedTime(&t, ev[q], ev[q + 1]));
+        *ep_ms += t;
+      }
+      for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+    }
   }
   for (rs_eprop* e : m->inst) {
     e->step += m->T;
@@ -1932,17 +1981,14 @@ rs_status rs_multi_train(rs_multi* m, uint32_t n_samples) {
   for (uint32_t q = 0; q < n_samples; ++q) {
     if (!m->tuned) {
       // the tuner: the next untried schedule runs this sample (every schedule
-      // computes the same results), timed on the device; after the last one
-      // the fastest is kept
+      // computes the same results) with its e-prop launches timed on the
+      // device; after the last one the fastest is kept.  Only the e-prop
+      // launches are compared: their work is the same in every sample, while
+      // the forward pass follows the networks' activity as they learn.
       int c = 0;
       while (c < MULTI_SCHEDULES && m->sched_ms[c] > 0) ++c;
-      order(m->ev_join, m->stream, m->side);
-      HIP_OK(hipEventRecord(m->ev_t0, m->stream));
-      TRY(multi_run_sample(m, c, false));
-      HIP_OK(hipEventRecord(m->ev_t1, m->stream));
-      HIP_OK(hipEventSynchronize(m->ev_t1));
-      float ms = 0.f;
-      HIP_OK(hipEventElapsedTime(&ms, m->ev_t0, m->ev_t1));
+      double ms = 0;
+      TRY(multi_run_sample(m, c, false, &ms));
       m->sched_ms[c] = ms > 0 ? ms : 1e-6;
       if (c + 1 == MULTI_SCHEDULES) {
         int best = 0;
@@ -2453,6 +2499,521 @@ void rs_serve_destroy(rs_serve* s) {
   if (s->host_img) (void)hipHostFree(s->host_img);
   s->arena.release();
   delete s;
+}
+
+}  // extern "C"
+
+// =========================================================================== composed networks
+// The paper's problem statement as calls: declare populations and
+// projections (each with its initialisation, learning rule and structural-
+// plasticity rule), build, step, trigger the rule, read and write state.  A
+// build recognises the models the kernels implement and assembles them: the
+// e-prop classifier (spike source -> LIF/ALIF -> readout, with DEEP R on
+// either ragged projection) and the topographic map (Poisson sheet ->
+// conductance-LIF sheet with STDP and distance-dependent rewiring).
+struct rs_net {
+  hipStream_t stream = nullptr;
+  Arena alloc;  // the caller's allocator (callbacks only; owns nothing)
+  uint64_t seed = 0;
+  struct Pop { int32_t kind; uint32_t n; rs_pop_params p; };
+  struct Proj { uint32_t pre, post; rs_proj_desc d; };
+  std::vector<Pop> pops;
+  std::vector<Proj> projs;
+  bool built = false;
+  int model = 0;                 // 1: e-prop classifier, 2: topographic map
+  int proj_map[3] = {-1, -1, -1};  // classifier: composed projection -> 0 input, 1 recurrent, 2 readout
+  rs_eprop* ep = nullptr;
+  rs_topo* tp = nullptr;
+  bool dead = false;
+};
+
+namespace {
+
+rs_status net_build_classifier(rs_net* n, uint32_t batch, uint32_t sample_steps, uint32_t trace_block) {
+  // populations: one spike source, one LIF or ALIF population, one readout
+  int src = -1, rec = -1, out = -1;
+  for (int q = 0; q < (int)n->pops.size(); ++q) {
+    const int k = n->pops[q].kind;
+    if (k == RS_POP_SPIKE_SOURCE && src < 0) src = q;
+    else if ((k == RS_POP_LIF || k == RS_POP_ALIF) && rec < 0) rec = q;
+    else if (k == RS_POP_READOUT && out < 0) out = q;
+    else return fail(RS_EINVAL, "population %d does not fit the e-prop classifier", q);
+  }
+  if (src < 0 || rec < 0 || out < 0)
+    return fail(RS_EINVAL, "the e-prop classifier needs a spike source, a LIF or ALIF population and a readout");
+  if (n->projs.size() != 3) return fail(RS_EINVAL, "the e-prop classifier has three projections");
+  rs_eprop_params p{};
+  const rs_pop_params& rp = n->pops[rec].p;
+  p.n_in = n->pops[src].n;
+  p.n_rec = n->pops[rec].n;
+  p.n_out = n->pops[out].n;
+  p.batch = batch;
+  p.alif = n->pops[rec].kind == RS_POP_ALIF;
+  p.dt_ms = rp.dt_ms;
+  p.tau_mem_ms = rp.tau_mem_ms;
+  p.tau_adapt_ms = p.alif ? rp.tau_adapt_ms : 2000.0f;
+  p.v_thr = rp.v_thr;
+  p.beta = p.alif ? rp.beta : 0.0f;
+  p.sample_steps = sample_steps;
+  p.trace_block = trace_block;
+  p.seed = n->seed;
+  bool have[3] = {false, false, false};
+  for (int q = 0; q < 3; ++q) {
+    const rs_net::Proj& pr = n->projs[q];
+    const rs_proj_desc& d = pr.d;
+    int role = -1;
+    if ((int)pr.pre == src && (int)pr.post == rec) role = 0;
+    else if ((int)pr.pre == rec && (int)pr.post == rec) role = 1;
+    else if ((int)pr.pre == rec && (int)pr.post == out) role = 2;
+    if (role < 0 || have[role]) return fail(RS_EINVAL, "projection %d does not fit the e-prop classifier", q);
+    have[role] = true;
+    n->proj_map[q] = role;
+    if (d.learn != RS_LEARN_EPROP) return fail(RS_EINVAL, "projection %d: the classifier learns by e-prop", q);
+    if (q == 0) {  // one optimiser and update interval for the whole network
+      p.lr = d.lr;
+      p.adam_b1 = d.adam_b1;
+      p.adam_b2 = d.adam_b2;
+      p.adam_eps = d.adam_eps;
+      p.update_interval = d.update_interval;
+    } else if (!(d.lr == p.lr && d.adam_b1 == p.adam_b1 && d.adam_b2 == p.adam_b2 && d.adam_eps == p.adam_eps &&
+                 d.update_interval == p.update_interval)) {
+      return fail(RS_EINVAL, "the projections share one optimiser and update interval");
+    }
+    if (role == 2) {
+      if (d.init != RS_INIT_DENSE || d.rewire != RS_REWIRE_NONE)
+        return fail(RS_EINVAL, "the readout projection is dense, without rewiring");
+      p.sigma_out = d.sigma_w;
+      continue;
+    }
+    if (d.init != RS_INIT_FIXED_PROB) return fail(RS_EINVAL, "projection %d: fixed-probability rows", q);
+    if (d.rewire != RS_REWIRE_NONE && d.rewire != RS_REWIRE_DEEPR)
+      return fail(RS_EINVAL, "projection %d: the classifier rewires by DEEP R", q);
+    (role == 0 ? p.p_in : p.p_rec) = d.p;
+    (role == 0 ? p.sigma_in : p.sigma_rec) = d.sigma_w;
+    (role == 0 ? p.cap_in : p.cap_rec) = d.cap;
+    if (d.rewire == RS_REWIRE_DEEPR) {
+      if (p.deepr_mask && d.l1 != p.l1) return fail(RS_EINVAL, "the DEEP R projections share one L1 strength");
+      p.deepr_mask |= 1u << role;
+      p.l1 = d.l1;
+    }
+  }
+  rs_eprop* e = nullptr;
+  rs_status st = create_impl(&p, n->stream, &e, &n->alloc);
+  if (st != RS_OK) {
+    if (e) rs_eprop_destroy(e);
+    return st;
+  }
+  n->ep = e;
+  n->model = 1;
+  return RS_OK;
+}
+
+rs_status net_build_topomap(rs_net* n) {
+  if (n->pops.size() != 2 || n->projs.size() != 1)
+    return fail(RS_EINVAL, "the topographic map has two sheets and one projection");
+  const rs_net::Pop &a = n->pops[0], &b = n->pops[1];
+  if (a.kind != RS_POP_POISSON_SHEET || b.kind != RS_POP_COND_LIF_SHEET || a.p.L != b.p.L || a.n != a.p.L * a.p.L ||
+      b.n != a.n)
+    return fail(RS_EINVAL, "the topographic map projects a Poisson sheet onto a conductance-LIF sheet of one size");
+  const rs_proj_desc& d = n->projs[0].d;
+  if (n->projs[0].pre != 0 || n->projs[0].post != 1 || d.init != RS_INIT_GAUSS_TORUS)
+    return fail(RS_EINVAL, "the sheet projection has Gaussian pairwise-Bernoulli rows");
+  if (d.learn != RS_LEARN_NONE && d.learn != RS_LEARN_STDP) return fail(RS_EINVAL, "the map learns by STDP or not");
+  if (d.rewire != RS_REWIRE_NONE && d.rewire != RS_REWIRE_TOPO) return fail(RS_EINVAL, "the map rewires topographically");
+  rs_topo_params tp{};
+  tp.L = a.p.L;
+  tp.cap = d.cap;
+  tp.n_attempts = d.rewire == RS_REWIRE_TOPO ? d.n_attempts : 0;
+  tp.proj_id = 0;
+  tp.p_form = d.p_form;
+  tp.sigma_form = d.sigma_form;
+  tp.g_theta = d.g_theta;
+  tp.p_elim_dep = d.p_elim_dep;
+  tp.p_elim_pot = d.p_elim_pot;
+  tp.g_new = d.g_new;
+  tp.g_init = d.g_init;
+  tp.seed = n->seed;
+  rs_topo_model m = b.p.model;  // neuron and synapse of the target sheet
+  const rs_topo_model& sm = a.p.model;  // stimulus of the source sheet
+  m.f_base = sm.f_base;
+  m.f_peak = sm.f_peak;
+  m.sigma_stim = sm.sigma_stim;
+  m.stim_steps = sm.stim_steps;
+  m.stim_kind = sm.stim_kind;
+  m.stdp = d.learn == RS_LEARN_STDP;
+  m.rewire_steps = d.rewire == RS_REWIRE_TOPO ? d.update_interval : 0;
+  rs_topo* t = new rs_topo();
+  t->arena.afn = n->alloc.afn;
+  t->arena.ffn = n->alloc.ffn;
+  t->arena.user = n->alloc.user;
+  rs_status st = topo_create_impl(&tp, n->stream, t);
+  if (st == RS_OK) st = rs_topo_sim_init(t, &m);
+  if (st != RS_OK) {
+    rs_topo_destroy(t);
+    return st;
+  }
+  n->tp = t;
+  n->model = 2;
+  return RS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_create(void* hip_stream, rs_alloc_fn alloc_fn, rs_free_fn free_fn, void* user, uint64_t seed,
+                    rs_net** out) {
+  if (!out) return fail(RS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return fail(RS_EINVAL, "give both allocator functions or neither");
+  rs_net* n = new rs_net();
+  n->stream = (hipStream_t)hip_stream;
+  n->alloc.afn = alloc_fn;
+  n->alloc.ffn = free_fn;
+  n->alloc.user = user;
+  n->seed = seed;
+  *out = n;
+  return RS_OK;
+}
+
+rs_status rs_add_pop(rs_net* n, int32_t kind, uint32_t size, const rs_pop_params* p, uint32_t* pop) {
+  ENTER(n);
+  if (n->built) return fail(RS_ESTATE, "the network is built");
+  if (!p) return fail(RS_EINVAL, "params is NULL");
+  if (kind < RS_POP_SPIKE_SOURCE || kind > RS_POP_COND_LIF_SHEET) return fail(RS_EINVAL, "unknown population kind");
+  if (size < 1) return fail(RS_EINVAL, "a population has at least one neuron");
+  n->pops.push_back({kind, size, *p});
+  if (pop) *pop = (uint32_t)n->pops.size() - 1;
+  return RS_OK;
+}
+
+rs_status rs_add_proj(rs_net* n, uint32_t pre, uint32_t post, const rs_proj_desc* d, uint32_t* proj) {
+  ENTER(n);
+  if (n->built) return fail(RS_ESTATE, "the network is built");
+  if (!d) return fail(RS_EINVAL, "descriptor is NULL");
+  if (pre >= n->pops.size() || post >= n->pops.size()) return fail(RS_EINVAL, "unknown population");
+  n->projs.push_back({pre, post, *d});
+  if (proj) *proj = (uint32_t)n->projs.size() - 1;
+  return RS_OK;
+}
+
+rs_status rs_build(rs_net* n, uint32_t batch, uint32_t sample_steps, uint32_t trace_block) {
+  ENTER(n);
+  if (n->built) return fail(RS_ESTATE, "the network is built");
+  bool sheet = false;
+  for (const auto& q : n->pops) sheet |= q.kind == RS_POP_POISSON_SHEET || q.kind == RS_POP_COND_LIF_SHEET;
+  TRY(sheet ? net_build_topomap(n) : net_build_classifier(n, batch, sample_steps, trace_block));
+  n->built = true;
+  return RS_OK;
+}
+
+rs_status rs_eprop_of(rs_net* n, rs_eprop** out) {
+  ENTER(n);
+  if (!out) return fail(RS_EINVAL, "NULL argument");
+  if (!n->ep) return fail(RS_ESTATE, "not an e-prop classifier, or not built");
+  *out = n->ep;
+  return RS_OK;
+}
+
+rs_status rs_topo_of(rs_net* n, rs_topo** out) {
+  ENTER(n);
+  if (!out) return fail(RS_EINVAL, "NULL argument");
+  if (!n->tp) return fail(RS_ESTATE, "not a topographic map, or not built");
+  *out = n->tp;
+  return RS_OK;
+}
+
+rs_status rs_step(rs_net* n, uint32_t n_steps, uint32_t flags) {
+  ENTER(n);
+  if (n->ep) return rs_eprop_step(n->ep, n_steps, flags);
+  if (n->tp) return rs_topo_run(n->tp, n_steps);
+  return fail(RS_ESTATE, "the network is not built");
+}
+
+rs_status rs_update(rs_net* n) {
+  ENTER(n);
+  if (!n->ep) return fail(RS_ESTATE, "only an e-prop classifier has a parameter update");
+  return rs_eprop_update(n->ep);
+}
+
+rs_status rs_rewire(rs_net* n, uint32_t proj, rs_rewire_stats* st) {
+  ENTER(n);
+  if (proj >= n->projs.size()) return fail(RS_EINVAL, "unknown projection %u", proj);
+  if (n->ep) {
+    const int role = n->proj_map[proj];
+    if (role > 1) return fail(RS_EINVAL, "projection %u is not rewired", proj);
+    return rs_eprop_rewire(n->ep, (uint32_t)role, st);
+  }
+  if (n->tp) {
+    uint64_t step = 0;
+    TRY(rs_topo_sim_get(n->tp, RS_TV_STEP, &step, 8));
+    return rs_topo_rewire(n->tp, step, st);
+  }
+  return fail(RS_ESTATE, "the network is not built");
+}
+
+rs_status rs_get_rows(rs_net* n, uint32_t proj, int32_t* len, int32_t* ind, float* w, size_t cap_elems,
+                      size_t* needed) {
+  ENTER(n);
+  if (proj >= n->projs.size()) return fail(RS_EINVAL, "unknown projection %u", proj);
+  if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
+  if (n->tp) {
+    const ProjDev& P = n->tp->t.P;
+    const size_t need = (size_t)P.n_pre * P.cap;
+    if (needed) *needed = need;
+    if (cap_elems < need) return fail(RS_ECAPACITY, "row buffers need %zu elements", need);
+    return rs_topo_get_rows(n->tp, len, ind, w);
+  }
+  if (!n->ep) return fail(RS_ESTATE, "the network is not built");
+  const int role = n->proj_map[proj];
+  if (role > 1) return fail(RS_EINVAL, "projection %u is dense, not ragged", proj);
+  const ProjDev& P = role == 0 ? n->ep->in : n->ep->rec;
+  const size_t need = (size_t)P.n_pre * P.cap;
+  if (needed) *needed = need;
+  if (cap_elems < need) return fail(RS_ECAPACITY, "row buffers need %zu elements", need);
+  TRY(rs_eprop_get(n->ep, RS_PROJ(role, RS_P_LEN), len, (size_t)P.n_pre * 4));
+  TRY(rs_eprop_get(n->ep, RS_PROJ(role, RS_P_IND), ind, need * 4));
+  return rs_eprop_get(n->ep, RS_PROJ(role, RS_P_W), w, need * 4);
+}
+
+rs_status rs_get_var(rs_net* n, int32_t var, void* host, size_t bytes) {
+  ENTER(n);
+  if (n->ep) return rs_eprop_get(n->ep, var, host, bytes);
+  if (n->tp) return rs_topo_sim_get(n->tp, var, host, bytes);
+  return fail(RS_ESTATE, "the network is not built");
+}
+
+rs_status rs_set_var(rs_net* n, int32_t var, const void* host, size_t bytes) {
+  ENTER(n);
+  if (n->ep) return rs_eprop_set(n->ep, var, host, bytes);
+  if (n->tp) return rs_topo_sim_set(n->tp, var, host, bytes);
+  return fail(RS_ESTATE, "the network is not built");
+}
+
+rs_status rs_sync(rs_net* n) {
+  ENTER(n);
+  if (n->ep) {
+    order(n->ep->ev_back, n->ep->side, n->ep->stream);
+    HIP_OK(hipStreamSynchronize(n->ep->stream));
+  } else {
+    HIP_OK(hipStreamSynchronize(n->stream));
+  }
+  return RS_OK;
+}
+
+uint64_t rs_step_counter(const rs_net* n) {
+  if (!n) return 0;
+  if (n->ep) return n->ep->step;
+  if (n->tp) return n->tp->step;
+  return 0;
+}
+
+void rs_destroy(rs_net* n) {
+  if (!n) return;
+  if (n->ep) rs_eprop_destroy(n->ep);
+  if (n->tp) rs_topo_destroy(n->tp);
+  delete n;
+}
+
+}  // extern "C"
+
+// =========================================================================== custom connectivity updates
+// A rule's host part runs here on the host (the paper's host_update_code,
+// with the counter-based generator's host implementation), its row parts on
+// the device (rs_custom.hpp).  A caller's host function may inspect and
+// change the rule's per-row variable between the two.
+
+namespace {
+
+struct CustomScratch {
+  long long* stats = nullptr;     // [4]
+  uint32_t* pre_var = nullptr;    // [n_pre] the rule's per-row variable on the device
+  size_t n_pre = 0;
+};
+
+rs_status custom_scratch(Arena& ar, CustomScratch& cs, size_t n_pre) {
+  if (!cs.stats) TRY(ar.alloc(&cs.stats, 4));
+  if (cs.n_pre < n_pre) {
+    TRY(ar.alloc(&cs.pre_var, n_pre));
+    cs.n_pre = n_pre;
+  }
+  return RS_OK;
+}
+
+// DEEP R's distribution of the dormant total over the rows, on the host: the
+// device kernel's rounds and fallback, the same draws.
+int64_t host_deepr_distribute(uint64_t seed, const ProjDev& P, uint64_t step, const std::vector<int>& len,
+                              const std::vector<int>& dormant, std::vector<uint32_t>& asg, int64_t* unplaced) {
+  int limit = P.n_post - (P.recurrent ? 1 : 0);
+  limit = std::min(limit, P.cap);
+  asg.assign((size_t)P.n_pre, 0u);
+  int64_t pending = 0;
+  for (int d : dormant) pending += d;
+  std::vector<int> cnt((size_t)P.n_pre);
+  for (int round = 0; pending > 0 && round < MAX_ROUNDS; ++round) {
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t a = 0; a < pending; ++a)
+      ++cnt[host_below(host_draw_u32(seed, TAG_DR_ROW, (uint32_t)P.proj_id, step, (uint64_t)a, (uint64_t)round, 0),
+                       (uint32_t)P.n_pre)];
+    int64_t rej = 0;
+    for (int r = 0; r < P.n_pre; ++r) {
+      const int room = std::max(limit - len[r] - (int)asg[r], 0);
+      const int acc = std::min(cnt[r], room);
+      asg[r] += (uint32_t)acc;
+      rej += cnt[r] - acc;
+    }
+    pending = rej;
+  }
+  for (int r = 0; r < P.n_pre && pending > 0; ++r) {
+    const int room = limit - len[r] - (int)asg[r];
+    if (room <= 0) continue;
+    const int take = (int)std::min<int64_t>(pending, room);
+    asg[r] += (uint32_t)take;
+    pending -= take;
+  }
+  *unplaced = pending;
+  int64_t placed = 0;
+  for (uint32_t a : asg) placed += a;
+  return placed;
+}
+
+rs_status run_host_fn(rs_host_update_fn fn, void* user, const ProjDev& P, int32_t rule, uint64_t seed, uint64_t step,
+                      const std::vector<int>& len, std::vector<uint32_t>& var) {
+  if (!fn) return RS_OK;
+  rs_custom_host h{};
+  h.n_pre = P.n_pre;
+  h.n_post = P.n_post;
+  h.cap = P.cap;
+  h.recurrent = P.recurrent;
+  h.len = len.data();
+  h.pre_var = var.data();
+  h.seed = seed;
+  h.step = step;
+  h.proj_id = (uint32_t)P.proj_id;
+  h.rule = rule;
+  fn(user, &h);
+  return RS_OK;
+}
+
+// One custom update of projection P (rows, records and bitfields on the
+// device), on stream s.  Fills the host stats (synchronising).
+rs_status custom_update(Arena& ar, CustomScratch& cs, hipStream_t s, uint64_t seed, ProjDev P, int B, int32_t rule,
+                        uint64_t step, rs_host_update_fn fn, void* user, const TopoDev* topo, rs_rewire_stats* st) {
+  TRY(custom_scratch(ar, cs, (size_t)P.n_pre));
+  launch_fill_zero(s, cs.stats, 32);
+  if (topo) launch_fill_zero(s, topo->stats, 32);
+  std::vector<int> len((size_t)P.n_pre);
+  std::vector<uint32_t> var((size_t)P.n_pre, 0u);
+  int64_t placed = 0, unplaced = 0;
+  auto pull_len = [&]() -> rs_status {
+    HIP_OK(hipMemcpyAsync(len.data(), P.len, len.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return RS_OK;
+  };
+  auto push_var = [&]() -> rs_status {
+    HIP_OK(hipMemcpyAsync(cs.pre_var, var.data(), var.size() * 4, hipMemcpyHostToDevice, s));
+    return RS_OK;
+  };
+  switch (rule) {
+    case RS_RULE_ADD_DIAGONAL:
+      launch_add_diagonal(s, P, B, cs.stats);
+      break;
+    case RS_RULE_REMOVE_RANDOM: {
+      // host part: each row picks a random target to try and remove
+      TRY(pull_len());
+      for (int i = 0; i < P.n_pre; ++i)
+        var[i] = host_below(host_draw_u32(seed, TAG_CUSTOM, (uint32_t)P.proj_id, step, (uint64_t)i, 0, 0),
+                            (uint32_t)P.n_post);
+      TRY(run_host_fn(fn, user, P, rule, seed, step, len, var));
+      TRY(push_var());
+      launch_remove_post(s, P, cs.pre_var, B, cs.stats);
+      break;
+    }
+    case RS_RULE_DEEPR: {
+      if (!P.conn || !P.sign) return fail(RS_EINVAL, "DEEP R needs the projection's connectivity and sign bits");
+      launch_deepr_elim_rule(s, P, B, cs.stats);
+      // host part: sum the dormant counts, spread them over the rows
+      std::vector<int> dormant((size_t)P.n_pre);
+      HIP_OK(hipMemcpyAsync(dormant.data(), P.dormant, dormant.size() * 4, hipMemcpyDeviceToHost, s));
+      TRY(pull_len());
+      placed = host_deepr_distribute(seed, P, step, len, dormant, var, &unplaced);
+      TRY(run_host_fn(fn, user, P, rule, seed, step, len, var));
+      const int limit = std::min(P.n_post - (P.recurrent ? 1 : 0), P.cap);
+      for (int r = 0; r < P.n_pre; ++r)
+        if ((int64_t)len[r] + var[r] > limit) return fail(RS_EINVAL, "row %d assigned beyond its room", r);
+      HIP_OK(hipMemcpyAsync(P.assigned, var.data(), var.size() * 4, hipMemcpyHostToDevice, s));
+      launch_deepr_form_rule(s, seed, P, B, step, cs.stats);
+      break;
+    }
+    case RS_RULE_TOPO: {
+      if (!topo) return fail(RS_EINVAL, "the topographic rule needs a topographic map");
+      // host part: the attempts go to rows drawn uniformly, with replacement
+      TRY(pull_len());
+      for (int a = 0; a < topo->n_attempts; ++a)
+        ++var[host_below(host_draw_u32(seed, TAG_TP_ROW, (uint32_t)P.proj_id, step, (uint64_t)a, 0, 0),
+                         (uint32_t)P.n_pre)];
+      TRY(run_host_fn(fn, user, P, rule, seed, step, len, var));
+      TRY(push_var());
+      TopoDev t = *topo;
+      t.stats = cs.stats;  // removed, added from the row kernel; blocked beside them
+      launch_topo_rule(s, seed, t, step, (const int*)cs.pre_var, cs.stats);
+      break;
+    }
+    default:
+      return fail(RS_EINVAL, "unknown rule %d", rule);
+  }
+  HIP_OK(hipGetLastError());
+  if (st) {
+    long long h[4];
+    HIP_OK(hipMemcpyAsync(h, cs.stats, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    st->eliminated = h[0];
+    st->formed = h[1];
+    st->blocked = rule == RS_RULE_TOPO ? h[2] : unplaced;
+    st->attempts = rule == RS_RULE_TOPO ? topo->n_attempts : rule == RS_RULE_DEEPR ? placed : 0;
+  }
+  return RS_OK;
+}
+
+}  // namespace
+
+struct rs_custom_state {
+  CustomScratch cs;
+};
+void delete_custom(rs_custom_state* c) { delete c; }
+
+extern "C" {
+
+rs_status rs_eprop_custom_update(rs_eprop* n, uint32_t proj, int32_t rule, uint64_t step, rs_host_update_fn fn,
+                                 void* user, rs_rewire_stats* st) {
+  ENTER(n);
+  if (proj > 1) return fail(RS_EINVAL, "projection %u: 0 input, 1 recurrent", proj);
+  if (rule == RS_RULE_TOPO) return fail(RS_EINVAL, "the topographic rule runs on a topographic map");
+  if (step == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step 2^64-1 is reserved");
+  // the update follows everything queued on the network
+  order(n->ev_join, n->side, n->stream);
+  for (bool& p : n->ep_pending) p = false;
+  if (!n->custom) n->custom = new rs_custom_state();
+  TRY(custom_update(n->arena, n->custom->cs, n->stream, n->p.seed, proj == 0 ? n->in : n->rec, n->B, rule, step, fn,
+                    user, nullptr, st));
+  rebuild_columns(n, n->stream);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status rs_topo_custom_update(rs_topo* t, int32_t rule, uint64_t step, rs_host_update_fn fn, void* user,
+                                rs_rewire_stats* st) {
+  ENTER(t);
+  if (rule == RS_RULE_DEEPR) return fail(RS_EINVAL, "DEEP R runs on an e-prop projection");
+  if (step == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step 2^64-1 is reserved");
+  if (!t->custom) t->custom = new rs_custom_state();
+  TopoDev td = t->t;
+  td.col_len = nullptr;  // the rules do not edit an attached simulation's column view ...
+  TRY(custom_update(t->arena, t->custom->cs, t->stream, t->p.seed, t->t.P, 1, rule, step, fn, user, &td, st));
+  static const int one = 1;  // ... which the next simulation launch rebuilds
+  HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  return RS_OK;
 }
 
 }  // extern "C"

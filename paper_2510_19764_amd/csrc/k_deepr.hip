@@ -212,17 +212,17 @@ __device__ __forceinline__ uint64_t deepr_step(const DeeprArgs& d) {
 __global__ void __launch_bounds__(WAVE) k_deepr_elim_multi(const DeeprArgs* __restrict__ D,
                                                            const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
-  const DeeprArgs& d = D[w.x];
+  const DeeprArgs d = D[w.x];
   elim_body(d.P, d.B, d.stats, w.y);
 }
 __global__ void __launch_bounds__(DIST_NT) k_deepr_distribute_multi(const DeeprArgs* __restrict__ D) {
-  const DeeprArgs& d = D[blockIdx.x];
+  const DeeprArgs d = D[blockIdx.x];
   distribute_body(d.seed, d.P, deepr_step(d), d.stats);
 }
 __global__ void __launch_bounds__(WAVE) k_deepr_form_multi(const DeeprArgs* __restrict__ D,
                                                            const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
-  const DeeprArgs& d = D[w.x];
+  const DeeprArgs d = D[w.x];
   form_body(d.seed, d.P, d.B, deepr_step(d), d.stats, w.y);
 }
 

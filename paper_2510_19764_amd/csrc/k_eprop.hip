@@ -475,6 +475,50 @@ __device__ __forceinline__ void narrow_row(const EpropArgs& a, const int row, co
   float* ebar = from_in ? a.in.ebar : a.rec.ebar;
   const float* x0 = (from_in ? a.x0 : a.z0) + (int64_t)i * B;
   const uint32_t* bits = (from_in ? a.xbits : a.zbits) + (int64_t)i * B;
+  if (B == 1 && a.nslot % 4 == 0 && a.slot0 % 4 == 0) {
+    // One instance: psi_j and L_j of the block's steps are contiguous in the
+    // ring, so they are read four steps at a time, the next four loaded while
+    // the current ones are applied; each step's arithmetic is the one below.
+    for (int k = sub; k < n; k += nsub) {
+      const int64_t s = (int64_t)i * cap + k;
+      const int j = ind[s];
+      const f4* ps = (const f4*)(a.psiT + (int64_t)j * a.nslot + a.slot0);
+      const f4* ls = (const f4*)(a.LT + (int64_t)j * a.nslot + a.slot0);
+      float p = x0[0];
+      const uint32_t w = bits[0];
+      for (int t = 0; t < a.tofs; ++t) p = fmaf(a.alpha, p, (float)((w >> t) & 1u));
+      float ep = ALIF ? eps[s] : 0.0f, eb = ebar[s], gsum = 0.0f;
+      const int nq = (a.nsteps + 3) / 4;
+      f4 pv = ps[0], lv = ls[0];
+      for (int q = 0; q < nq; ++q) {
+        const f4 pc = pv, lc = lv;
+        if (q + 1 < nq) {
+          pv = ps[q + 1];
+          lv = ls[q + 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int tau = 4 * q + u;
+          if (tau >= a.nsteps) break;
+          const float psi = pc[u];
+          if (ALIF) {
+            const float e = psi * fmaf(-a.beta, ep, p);
+            const float d = fmaf(-a.one_m_rho, ep, e);
+            ep = ep + d;
+            eb = fmaf(a.alpha, eb, e);
+          } else {
+            eb = fmaf(a.alpha, eb, psi * p);
+          }
+          gsum = fmaf(lc[u], eb, gsum);
+          p = fmaf(a.alpha, p, (float)((w >> (a.tofs + tau)) & 1u));
+        }
+      }
+      if (ALIF) eps[s] = ep;
+      ebar[s] = eb;
+      G[s] += gsum;
+    }
+    return;
+  }
   for (int k = sub; k < n; k += nsub) {
     const int64_t s = (int64_t)i * cap + k;
     const int j = ind[s];
@@ -545,7 +589,7 @@ __global__ void __launch_bounds__(EP_NT) k_eprop_narrow_multi(const EpropArgs* _
   const int tid = threadIdx.x;
   for (int g = blockIdx.x; g < n_work; g += gridDim.x) {
     const int4 w = work[g];
-    const EpropArgs& a = A[w.x];
+    const EpropArgs a = A[w.x];
     const int n_rows = a.n_in + a.n_rec;
     if (w.y >= n_rows) {
       narrow_readout(a, w.y - n_rows, tid);

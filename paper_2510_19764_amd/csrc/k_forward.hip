@@ -372,11 +372,14 @@ __global__ void __launch_bounds__(FWD_NT) k_fwd(FwdArgs a) {
 
 // Several networks in one launch: workgroup g runs batch instance work[g].y of
 // network work[g].x, whose arguments are A[work[g].x].
+// The arguments are copied out of the table first: read through the table,
+// every field would be read again after each store the kernel makes.
 template <int ITEMS>
 __global__ void __launch_bounds__(FWD_NT) k_fwd_multi(const FwdArgs* __restrict__ A,
                                                       const int2* __restrict__ work) {
   const int2 w = work[blockIdx.x];
-  fwd_body<ITEMS, false>(A[w.x], w.y);
+  const FwdArgs a = A[w.x];
+  fwd_body<ITEMS, false>(a, w.y);
 }
 
 // Items per thread: neurons (and input channels) handled by each of the
@@ -603,17 +606,20 @@ __global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int 
 __global__ void __launch_bounds__(256) k_handoff_multi(const HandoffArrays* __restrict__ H,
                                                        const int* __restrict__ Bs, const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  handoff_body(H[w.x], Bs[w.x], w.y, w.z, w.w);
+  const HandoffArrays h = H[w.x];
+  handoff_body(h, Bs[w.x], w.y, w.z, w.w);
 }
 __global__ void __launch_bounds__(256) k_readout_multi(const ReadoutArgs* __restrict__ A,
                                                        const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  readout_body(A[w.x], w.y);
+  const ReadoutArgs a = A[w.x];
+  readout_body(a, w.y);
 }
 __global__ void __launch_bounds__(256) k_learning_signal_multi(const ReadoutArgs* __restrict__ A,
                                                                const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  learning_signal_body(A[w.x], w.y, w.z, w.w);
+  const ReadoutArgs a = A[w.x];
+  learning_signal_body(a, w.y, w.z, w.w);
 }
 
 void handoff_grid(const HandoffArrays& h, int B, int g[3]) {

@@ -84,7 +84,8 @@ __global__ void __launch_bounds__(UPD_NT) k_update(UpdateArgs a) { update_body(a
 __global__ void __launch_bounds__(UPD_NT) k_update_multi(const UpdateArgs* __restrict__ A,
                                                          const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
-  update_body(A[w.x], w.y, w.z);
+  const UpdateArgs a = A[w.x];
+  update_body(a, w.y, w.z);
 }
 
 int update_blocks(const UpdateArgs& a) {

@@ -11,7 +11,7 @@ constexpr int WAVE = 64;
 enum Tag : uint32_t {
   TAG_CONN = 1, TAG_WINIT = 2, TAG_SIGN = 3, TAG_DR_ROW = 4, TAG_DR_TGT = 5,
   TAG_TP_ROW = 6, TAG_TP_TGT = 7, TAG_TP_ELIM = 8, TAG_TP_FORM = 9, TAG_INPUT = 10,
-  TAG_STIM = 11, TAG_TP_INPUT = 12
+  TAG_STIM = 11, TAG_TP_INPUT = 12, TAG_CUSTOM = 13
 };
 constexpr int MAX_TRIES = 64;   // draws before the bounded fallback scan
 constexpr int MAX_ROUNDS = 64;  // redistribution rounds before deterministic fallback

@@ -230,6 +230,17 @@ void topo_rewire_attrs();
 void fwd_attrs();
 void deepr_attrs();
 
+// ---------------------------------------------------------------- custom connectivity updates
+// Rules on the row-update interface (rs_custom.hpp, k_custom.hip); stats
+// int64: [0] removed, [1] added (incremented).
+void launch_add_diagonal(hipStream_t s, const ProjDev& P, int B, long long* stats);
+void launch_remove_post(hipStream_t s, const ProjDev& P, const uint32_t* post_ind, int B, long long* stats);
+void launch_deepr_elim_rule(hipStream_t s, const ProjDev& P, int B, long long* stats);  // writes P.dormant
+void launch_deepr_form_rule(hipStream_t s, uint64_t seed, const ProjDev& P, int B, uint64_t step,
+                            long long* stats);  // reads P.assigned
+void launch_topo_rule(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step, const int* kcount,
+                      long long* stats);  // stats = t.stats ([2] blocked)
+
 // ---------------------------------------------------------------- served inference
 // Readout of one running request over a block of steps.
 struct ServeReadout {

@@ -110,9 +110,9 @@ def test_results_match_oracle(models):
 
 def test_admission_follows_the_budget(models):
     pool = raster_pool(2)
-    probe = rb.Server(models, slots_per_model=2)
-    probe.submit(2, pool[0][1], pool[0][2], 160, 10)
-    probe.step()
+    probe = rb.Server(models, slots_per_model=2, block_steps=20)
+    probe.submit(2, pool[0][1], pool[0][2], 160, 100)
+    probe.step()  # one block: the request is still running
     fp = probe.stats()["state_bytes_used"]  # one request of the largest model
     assert fp > 0
     probe.close()
