@@ -511,6 +511,32 @@ rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes);
 rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes);
 
 /* ==========================================================================
+ * DEEP R on caller-owned rows without device allocation
+ * ========================================================================== */
+/* A ragged projection in caller-owned device memory, laid out as the
+ * RS_PROJ(p, f) variables of rs_eprop_get: len int32[n_pre]; ind, w, m, v, G
+ * [n_pre][cap]; eps (or NULL), ebar [n_pre][cap][batch]; conn, sign
+ * uint32[n_pre][words], words = ceil(n_post / 32). */
+typedef struct rs_deepr_rows {
+  int32_t n_pre, n_post, cap, words, recurrent, batch;
+  int32_t *len, *ind;
+  float *w, *m, *v, *G, *eps, *ebar;
+  uint32_t *conn, *sign;
+} rs_deepr_rows;
+/* For callers that cannot allocate device memory (code under stream
+ * capture, serving loops, harnesses that forbid allocation): DEEP R rewiring
+ * (Sec. 2.1.2) of the rows in place, exactly as rs_eprop_rewire rewires a
+ * projection with the same seed, projection id (0 input, 1 recurrent) and
+ * step.  Its scratch (per-row dormant and activation counts, counters) is one
+ * fixed device array of the library, so n_pre is at most 8192; it is never
+ * allocated, and calls that overlap on one device race for it.  Runs on
+ * hip_stream; with stats != NULL it synchronises and fills them as
+ * rs_eprop_rewire does.  Errors: RS_EINVAL (sizes, NULL arrays, n_pre above
+ * 8192), RS_EDEVICE. */
+rs_status rs_deepr_rewire_noalloc(const rs_deepr_rows* rows, uint64_t seed, uint32_t proj_id, uint64_t step,
+                                  void* hip_stream, rs_rewire_stats* stats);
+
+/* ==========================================================================
  * Custom connectivity updates (Sec. 2.1): a rule's host part runs on the
  * host, its row parts on the device in parallel over the rows, each visiting
  * its row's synapses (removing some, with the ragged rule: the row's last

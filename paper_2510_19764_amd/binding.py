@@ -93,7 +93,7 @@ EXPORTS = [
     "rs_serve_replay", "rs_serve_destroy",
     "rs_create", "rs_add_pop", "rs_add_proj", "rs_build", "rs_eprop_of", "rs_topo_of", "rs_step", "rs_update",
     "rs_rewire", "rs_get_rows", "rs_get_var", "rs_set_var", "rs_sync", "rs_step_counter", "rs_destroy",
-    "rs_eprop_custom_update", "rs_topo_custom_update",
+    "rs_deepr_rewire_noalloc", "rs_eprop_custom_update", "rs_topo_custom_update",
 ]
 
 _lib = None
@@ -181,6 +181,8 @@ def lib():
         L.rs_step_counter.restype = C.c_uint64
         L.rs_destroy.argtypes = [vp]
         L.rs_destroy.restype = None
+        L.rs_deepr_rewire_noalloc.argtypes = [C.POINTER(_DeeprRows), C.c_uint64, C.c_uint32, C.c_uint64, vp,
+                                              C.POINTER(_Stats)]
         L.rs_eprop_custom_update.argtypes = [vp, C.c_uint32, C.c_int32, C.c_uint64, _HOST_FN, vp, C.POINTER(_Stats)]
         L.rs_topo_custom_update.argtypes = [vp, C.c_int32, C.c_uint64, _HOST_FN, vp, C.POINTER(_Stats)]
         for name in EXPORTS:
@@ -411,6 +413,27 @@ def _host_fn(fn):
 
 
 def _custom_stats(st):
+    return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
+
+
+class _DeeprRows(C.Structure):
+    _fields_ = [("n_pre", C.c_int32), ("n_post", C.c_int32), ("cap", C.c_int32), ("words", C.c_int32),
+                ("recurrent", C.c_int32), ("batch", C.c_int32)] + \
+               [(f, C.c_void_p) for f in ("len", "ind", "w", "m", "v", "G", "eps", "ebar", "conn", "sign")]
+
+
+def deepr_rewire_noalloc(arrays: dict, n_post: int, recurrent: bool, seed: int, proj_id: int, step: int,
+                         stream=None) -> RewireStats:
+    """DEEP R of caller-owned rows (rs_deepr_rewire_noalloc): arrays maps len,
+    ind, w, m, v, G, eps (optional), ebar, conn, sign to contiguous CUDA
+    tensors in the rs_eprop_get layout."""
+    n_pre, cap = arrays["ind"].shape
+    batch = arrays["ebar"].shape[2]
+    r = _DeeprRows(n_pre, n_post, cap, (n_post + 31) // 32, int(recurrent), batch,
+                   *[C.c_void_p(arrays[f].data_ptr()) if arrays.get(f) is not None else None
+                     for f in ("len", "ind", "w", "m", "v", "G", "eps", "ebar", "conn", "sign")])
+    st = _Stats()
+    _check(lib().rs_deepr_rewire_noalloc(C.byref(r), seed, proj_id, step, _stream_ptr(stream), C.byref(st)))
     return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
 
 
