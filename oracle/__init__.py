@@ -135,12 +135,13 @@ class _CTopoModel(C.Structure):
                 ("f_base", C.c_double), ("f_peak", C.c_double), ("sigma_stim", C.c_double),
                 ("stim_steps", C.c_int32), ("stim_kind", C.c_int32), ("stdp", C.c_int32),
                 ("g_max", C.c_double), ("A_plus", C.c_double), ("A_minus", C.c_double),
-                ("tau_plus", C.c_double), ("tau_minus", C.c_double), ("rewire_steps", C.c_int32)]
+                ("tau_plus", C.c_double), ("tau_minus", C.c_double), ("rewire_steps", C.c_int32),
+                ("stim_tile", C.c_int32)]
 
 
 class _CTopoState(C.Structure):
     _fields_ = [("V", P_f64), ("g", P_f64), ("y", P_f64), ("ref", P_i32), ("count", P_i32),
-                ("zout", P_u8), ("x", P_f64), ("zin", P_u8)]
+                ("zout", P_u8), ("x", P_f64), ("zin", P_u8), ("xl", P_f64)]
 
 
 _ROW_FN = C.CFUNCTYPE(C.c_uint32, C.c_void_p, C.c_int32)
@@ -197,6 +198,11 @@ def _declare(L):
     L.orc_topo_rate.restype = C.c_double
     L.orc_topo_sim_step.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
                                     C.POINTER(_CTopoState), C.c_uint64]
+    L.orc_topo_sim_step_lat.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
+                                        C.POINTER(_CProj), C.POINTER(_CTopoState), C.c_uint64]
+    L.orc_topo_run_lat.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
+                                   C.POINTER(_CTopoParams), C.POINTER(_CProj), C.POINTER(_CTopoParams),
+                                   C.POINTER(_CTopoState), C.c_uint64, C.c_uint64, P_u32, P_u32, P_i32, P_i32]
     L.orc_topo_run.argtypes = [C.c_uint64, C.POINTER(_CTopoModel), C.POINTER(_CProj),
                                C.POINTER(_CTopoParams), C.POINTER(_CTopoState), C.c_uint64,
                                C.c_uint64, P_u32, P_i32]
@@ -578,6 +584,7 @@ class TopoModel:
     tau_plus: float = 20.0
     tau_minus: float = 64.0
     rewire_steps: int = 10
+    stim_tile: int = 0  # side of the square the stimulus is replicated over (scaled maps); 0: L
 
     def c(self):
         return _CTopoModel(*[getattr(self, f) for f, _ in _CTopoModel._fields_])
@@ -596,11 +603,12 @@ class TopoState:
         self.zout = np.zeros(N, np.uint8)
         self.x = np.zeros(N, np.float64)
         self.zin = np.zeros(N, np.uint8)
+        self.xl = np.zeros(N, np.float64)  # lateral pre trace of the targets
 
     def c(self):
         return _CTopoState(_ptr(self.V, P_f64), _ptr(self.g, P_f64), _ptr(self.y, P_f64),
                            _ptr(self.ref, P_i32), _ptr(self.count, P_i32), _ptr(self.zout, P_u8),
-                           _ptr(self.x, P_f64), _ptr(self.zin, P_u8))
+                           _ptr(self.x, P_f64), _ptr(self.zin, P_u8), _ptr(self.xl, P_f64))
 
 
 def topo_stimulus(seed: int, M: TopoModel, step: int):
@@ -621,18 +629,33 @@ def topo_rate(M: TopoModel, d2: int) -> float:
     return lib().orc_topo_rate(C.byref(M.c()), d2)
 
 
-def topo_sim_step(seed: int, M: TopoModel, P: Proj, S: TopoState, t: int):
+def topo_sim_step(seed: int, M: TopoModel, P: Proj, S: TopoState, t: int, PL: Proj | None = None):
+    """One step; PL is the lateral (target -> target) projection or None."""
     cm, cs = M.c(), S.c()
-    lib().orc_topo_sim_step(seed, C.byref(cm), C.byref(P.c()), C.byref(cs), t)
+    if PL is None:
+        lib().orc_topo_sim_step(seed, C.byref(cm), C.byref(P.c()), C.byref(cs), t)
+    else:
+        lib().orc_topo_sim_step_lat(seed, C.byref(cm), C.byref(P.c()), C.byref(PL.c()), C.byref(cs), t)
 
 
 def topo_run(seed: int, M: TopoModel, P: Proj, tp: TopoParams, S: TopoState, t0: int, n: int,
-             bits: np.ndarray | None = None):
-    """Steps t0 .. t0+n-1 with a rewire after every rewire_steps; returns summed rewire stats."""
+             bits: np.ndarray | None = None, PL: Proj | None = None, tpl: TopoParams | None = None,
+             bits_l: np.ndarray | None = None):
+    """Steps t0 .. t0+n-1 with a rewire after every rewire_steps; returns summed rewire stats
+    (a pair, feed-forward and lateral, when PL is given)."""
     if bits is None:
         bits = np.zeros(P.n_pre * P.words, np.uint32)
     stats = np.zeros(4, np.int32)
     cm, cs, ctp = M.c(), S.c(), tp.c()
-    lib().orc_topo_run(seed, C.byref(cm), C.byref(P.c()), C.byref(ctp), C.byref(cs), t0, n,
-                       _ptr(bits, P_u32), _ptr(stats, P_i32))
-    return stats
+    if PL is None:
+        lib().orc_topo_run(seed, C.byref(cm), C.byref(P.c()), C.byref(ctp), C.byref(cs), t0, n,
+                           _ptr(bits, P_u32), _ptr(stats, P_i32))
+        return stats
+    if bits_l is None:
+        bits_l = np.zeros(PL.n_pre * PL.words, np.uint32)
+    stats_l = np.zeros(4, np.int32)
+    ctpl = tpl.c()
+    lib().orc_topo_run_lat(seed, C.byref(cm), C.byref(P.c()), C.byref(ctp), C.byref(PL.c()), C.byref(ctpl),
+                           C.byref(cs), t0, n, _ptr(bits, P_u32), _ptr(bits_l, P_u32), _ptr(stats, P_i32),
+                           _ptr(stats_l, P_i32))
+    return stats, stats_l

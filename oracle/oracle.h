@@ -207,6 +207,7 @@ typedef struct orc_topo_model {
     int32_t stdp;                              /* 0: weights fixed */
     double g_max, A_plus, A_minus, tau_plus, tau_minus;      /* uS, uS, uS, ms, ms */
     int32_t rewire_steps;                      /* t_rewiring / h; 0: no rewiring */
+    int32_t stim_tile;                         /* side L_0 of the replicated stimulus square; 0: L */
 } orc_topo_model;
 /* State of both sheets, L*L entries each. */
 typedef struct orc_topo_state {
@@ -216,6 +217,7 @@ typedef struct orc_topo_state {
     uint8_t *zout;       /* spikes of the last step */
     double *x;           /* source sheet: pre trace */
     uint8_t *zin;        /* spikes drawn last step, delivered next step */
+    double *xl;          /* target sheet: lateral pre trace (used with a lateral projection) */
 } orc_topo_state;
 /* Uniform 32-bit draw of source channel i at step t (eight channels per
  * generator call: word (i%8)/2, upper half for even i). */
@@ -230,9 +232,18 @@ double orc_topo_rate(const orc_topo_model *M, int32_t d2);
 /* One step t of the model (weights change only with stdp). */
 void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_topo_state *S,
                        uint64_t t);
+/* One step with a lateral projection PL (target -> target rows; NULL: none). */
+void orc_topo_sim_step_lat(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_proj *PL,
+                           orc_topo_state *S, uint64_t t);
 /* Steps t0 .. t0+n-1; after step t with (t+1) % rewire_steps == 0 a topomap
  * rewire keyed by t+1.  stats (may be NULL) accumulates the rewire stats. */
 void orc_topo_run(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
                   orc_topo_state *S, uint64_t t0, uint64_t n_steps, uint32_t *bits, int32_t *stats);
+/* The same with a lateral projection, rewired after the feed-forward one at
+ * the same steps with its own parameters (its draws keyed by its proj_id). */
+void orc_topo_run_lat(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
+                      orc_proj *PL, const orc_topo_params *tpl, orc_topo_state *S, uint64_t t0,
+                      uint64_t n_steps, uint32_t *bits, uint32_t *bits_l, int32_t *stats,
+                      int32_t *stats_l);
 
 #endif

@@ -41,7 +41,28 @@
  *     the random stream open; one generator call serves eight channels: the
  *     draw of channel i is output word (i mod 8)/2 of Philox4x64-10 under key
  *     (seed, TP_INPUT) at counter (t, floor(i/8), 0, 0), its upper half for even
- *     i and its lower half for odd i.
+ *     i and its lower half for odd i;
+ *   - scaled maps (L = s L_0): the correlated input is replicated in each
+ *     L_0 x L_0 square, so the s^2 stimulus locations sit at the same offset in
+ *     every square: the position is drawn in [0, L_0) and a channel's distance
+ *     is measured on the L_0 torus from its coordinates modulo L_0, which is its
+ *     distance to the nearest of the s^2 replicated locations (stim_tile = L_0;
+ *     0 means the whole sheet is one square).
+ *
+ * Lateral projection (Tab. A "feed-forward and lateral connections"): target ->
+ * target rows with their own conductances, STDP and rewiring, read as a
+ * second projection of the same kind onto the same targets:
+ *   - a target spike of step t is delivered at t+1, as source spikes are: it
+ *     adds the lateral weight to g of each lateral target and depresses that
+ *     weight by A_- y_target; the spiking neuron's lateral pre trace xl += 1;
+ *   - xl decays with tau_+ like x; potentiation of a lateral synapse onto a
+ *     target that spiked adds A_+ xl_pre; the post trace y is shared;
+ *   - within a step the feed-forward deliveries come first, then the lateral
+ *     ones, both before the neuron update (the conductance sum is exact in the
+ *     GPU's fixed point, so the order only moves the oracle's last bits);
+ *   - autapses are allowed: at distance zero the lateral formation probability
+ *     is p_form-lat, and the map's connection-change counts at zero distance
+ *     are autapses.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -62,18 +83,26 @@ static int32_t axis_d(int32_t L, int32_t a, int32_t b)
     return d < L - d ? d : L - d;
 }
 
+/* Side of the square the stimulus is replicated over. */
+static int32_t stim_side(const orc_topo_model *M)
+{
+    return M->stim_tile > 0 ? M->stim_tile : M->L;
+}
+
 void orc_topo_stimulus(uint64_t seed, const orc_topo_model *M, uint64_t step, int32_t *cx,
                        int32_t *cy, int32_t *orient)
 {
     const uint64_t e = step / (uint64_t)M->stim_steps;
-    *cx = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 0, 0, 0), (uint32_t)M->L);
-    *cy = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 1, 0, 0), (uint32_t)M->L);
+    const uint32_t Ls = (uint32_t)stim_side(M);
+    *cx = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 0, 0, 0), Ls);
+    *cy = (int32_t)orc_below(orc_u32(seed, ORC_TAG_STIM, 0, e, 1, 0, 0), Ls);
     *orient = (int32_t)(orc_u32(seed, ORC_TAG_STIM, 0, e, 2, 0, 0) & 1u);
 }
 
 int32_t orc_topo_stim_d2(const orc_topo_model *M, int32_t i, int32_t cx, int32_t cy, int32_t orient)
 {
-    const int32_t dx = axis_d(M->L, i % M->L, cx), dy = axis_d(M->L, i / M->L, cy);
+    const int32_t Ls = stim_side(M);
+    const int32_t dx = axis_d(Ls, (i % M->L) % Ls, cx), dy = axis_d(Ls, (i / M->L) % Ls, cy);
     if (M->stim_kind == ORC_STIM_BAR) return orient ? dy * dy : dx * dx;
     return dx * dx + dy * dy;
 }
@@ -83,8 +112,48 @@ double orc_topo_rate(const orc_topo_model *M, int32_t d2)
     return M->f_base + M->f_peak * exp(-(double)d2 / (2.0 * M->sigma_stim * M->sigma_stim));
 }
 
+/* Deliver the spikes flagged in z through the rows of Q: conductance, then
+ * depression by A_- y_target, then the presynaptic trace. */
+static void deliver(const orc_topo_model *M, orc_proj *Q, const uint8_t *z, double *pre_trace,
+                    orc_topo_state *S)
+{
+    for (int32_t i = 0; i < Q->n_pre; ++i) {
+        if (!z[i]) continue;
+        for (int32_t s = 0; s < Q->len[i]; ++s) {
+            const int64_t k = (int64_t)i * Q->cap + s;
+            const int32_t j = Q->ind[k];
+            S->g[j] += Q->w[k];
+            if (M->stdp) {
+                const double w = Q->w[k] - M->A_minus * S->y[j];
+                Q->w[k] = w > 0.0 ? w : 0.0;
+            }
+        }
+        pre_trace[i] += 1.0;
+    }
+}
+
+/* Potentiate every synapse of Q onto a target that spiked by A_+ times its
+ * presynaptic trace, capped at g_max. */
+static void potentiate(const orc_topo_model *M, orc_proj *Q, const double *pre_trace,
+                       const orc_topo_state *S)
+{
+    for (int32_t i = 0; i < Q->n_pre; ++i)
+        for (int32_t s = 0; s < Q->len[i]; ++s) {
+            const int64_t k = (int64_t)i * Q->cap + s;
+            if (!S->zout[Q->ind[k]]) continue;
+            const double w = Q->w[k] + M->A_plus * pre_trace[i];
+            Q->w[k] = w < M->g_max ? w : M->g_max;
+        }
+}
+
 void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_topo_state *S,
                        uint64_t t)
+{
+    orc_topo_sim_step_lat(seed, M, P, NULL, S, t);
+}
+
+void orc_topo_sim_step_lat(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_proj *PL,
+                           orc_topo_state *S, uint64_t t)
 {
     const int32_t N = M->L * M->L;
     const double dx_ = exp(-M->h / M->tau_plus), dy_ = exp(-M->h / M->tau_minus);
@@ -94,21 +163,13 @@ void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_
     /* traces decay */
     for (int32_t i = 0; i < N; ++i) S->x[i] *= dx_;
     for (int32_t j = 0; j < N; ++j) S->y[j] *= dy_;
+    if (PL)
+        for (int32_t i = 0; i < N; ++i) S->xl[i] *= dx_;
 
-    /* delivery of the spikes drawn last step (delay one step), with depression */
-    for (int32_t i = 0; i < N; ++i) {
-        if (!S->zin[i]) continue;
-        for (int32_t s = 0; s < P->len[i]; ++s) {
-            const int64_t k = (int64_t)i * P->cap + s;
-            const int32_t j = P->ind[k];
-            S->g[j] += P->w[k];
-            if (M->stdp) {
-                const double w = P->w[k] - M->A_minus * S->y[j];
-                P->w[k] = w > 0.0 ? w : 0.0;
-            }
-        }
-        S->x[i] += 1.0;
-    }
+    /* delivery of the spikes of the step before (delay one step), with
+     * depression: the source's, then the targets' own through the lateral rows */
+    deliver(M, P, S->zin, S->x, S);
+    if (PL) deliver(M, PL, S->zout, S->xl, S);
 
     /* neurons: exponential Euler, threshold, reset, refractoriness */
     for (int32_t j = 0; j < N; ++j) {
@@ -131,13 +192,8 @@ void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_
 
     /* potentiation of every synapse onto a neuron that spiked, then y */
     if (M->stdp) {
-        for (int32_t i = 0; i < N; ++i)
-            for (int32_t s = 0; s < P->len[i]; ++s) {
-                const int64_t k = (int64_t)i * P->cap + s;
-                if (!S->zout[P->ind[k]]) continue;
-                const double w = P->w[k] + M->A_plus * S->x[i];
-                P->w[k] = w < M->g_max ? w : M->g_max;
-            }
+        potentiate(M, P, S->x, S);
+        if (PL) potentiate(M, PL, S->xl, S);
     }
     for (int32_t j = 0; j < N; ++j) S->y[j] += S->zout[j];
 
@@ -154,13 +210,26 @@ void orc_topo_sim_step(uint64_t seed, const orc_topo_model *M, orc_proj *P, orc_
 void orc_topo_run(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
                   orc_topo_state *S, uint64_t t0, uint64_t n_steps, uint32_t *bits, int32_t *stats)
 {
+    orc_topo_run_lat(seed, M, P, tp, NULL, NULL, S, t0, n_steps, bits, NULL, stats, NULL);
+}
+
+void orc_topo_run_lat(uint64_t seed, const orc_topo_model *M, orc_proj *P, const orc_topo_params *tp,
+                      orc_proj *PL, const orc_topo_params *tpl, orc_topo_state *S, uint64_t t0,
+                      uint64_t n_steps, uint32_t *bits, uint32_t *bits_l, int32_t *stats,
+                      int32_t *stats_l)
+{
     for (uint64_t t = t0; t < t0 + n_steps; ++t) {
-        orc_topo_sim_step(seed, M, P, S, t);
+        orc_topo_sim_step_lat(seed, M, P, PL, S, t);
         if (M->rewire_steps > 0 && (t + 1) % (uint64_t)M->rewire_steps == 0) {
             int32_t st[4];
             orc_topo_rewire(seed, P, tp, t + 1, bits, st);
             if (stats)
                 for (int q = 0; q < 4; ++q) stats[q] += st[q];
+            if (PL) {
+                orc_topo_rewire(seed, PL, tpl, t + 1, bits_l, st);
+                if (stats_l)
+                    for (int q = 0; q < 4; ++q) stats_l[q] += st[q];
+            }
         }
     }
 }
