@@ -518,6 +518,82 @@ def topo_sim_leg(steps=1_000_000, oracle_steps=5000, stim="bar"):
     return out
 
 
+def topo_scaling_leg(steps=20000, scales=(1, 2, 3, 4, 5, 6, 7)):
+    """The paper's scaling experiment (Fig. 10): the full topographic-map model
+    -- feed-forward and lateral projections with STDP and rewiring, blob input
+    replicated in every 16 x 16 square -- at L = 16 s for s = 1..7, 10 s^2
+    rewiring attempts per projection every 1 ms, h = 0.1 ms, on the tiled
+    kernel: wall time per step, realtime factor and the kernel's phase split.
+    Also the 64 x 64 feed-forward map of the end-to-end leg on both kernels."""
+    import torch
+    from paper_2510_19764_amd import binding as rb
+    from paper_2510_19764_amd import workload as wl
+    c = wl.TOPO_S4
+    gm = c["g_max"]
+    out = {"workload": "topographic map L = 16 s, s = 1..7: Poisson sheet -> conductance-LIF sheet (p_form 0.16, "
+                       "sigma 2.5) plus lateral target -> target rows (p_form 1, sigma 1), cap 64, STDP on both, "
+                       "10 s^2 rewiring attempts per projection every 10 steps, blob stimulus replicated per "
+                       "16 x 16 square, h = 0.1 ms",
+           "steps": steps, "model_seconds": steps * 1e-4, "by_scale": {}}
+    for sc in scales:
+        L = 16 * sc
+        ffc = rb.TopoConfig(L=L, cap=64, n_attempts=10 * sc * sc, proj_id=0, p_form=0.16, sigma_form=2.5,
+                            g_theta=gm / 2, p_elim_dep=c["p_elim_dep"], p_elim_pot=c["p_elim_pot"], g_new=gm,
+                            g_init=gm, seed=sc)
+        latc = rb.TopoConfig(L=L, cap=64, n_attempts=10 * sc * sc, proj_id=1, p_form=1.0, sigma_form=1.0,
+                             g_theta=gm / 2, p_elim_dep=c["p_elim_dep"], p_elim_pot=c["p_elim_pot"], g_new=gm,
+                             g_init=gm, seed=sc)
+        t = rb.TopoNet(ffc)
+        t.add_lateral(latc)
+        t.sim_init(rb.TopoModel(stim_tile=16, rewire_steps=10))
+        t.run(1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.run(steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st, sl = t.run_stats(), t.run_stats(lateral=True)
+        n_ph = min(steps, 10000)
+        t.sim_timing(True)
+        t.run(n_ph)
+        torch.cuda.synchronize()
+        ph = t.sim_phase_ms()
+        tot = t.last_ms()
+        t.sim_timing(False)
+        split = {k: round(1e3 * v / n_ph, 3) for k, v in ph.items()}
+        split["rewire_kernels_and_launch_gaps"] = round(1e3 * (tot - sum(ph.values())) / n_ph, 3)
+        out["by_scale"][str(sc)] = {
+            "L": L, "neurons_per_sheet": L * L, "us_per_step": round(1e6 * el / steps, 3),
+            "realtime_factor": round(steps * 1e-4 / el, 2), "target_spikes": int(t.sim_get(rb.TV_COUNT).sum()),
+            "ff_synapses": int(t.get_rows()[0].sum()), "lateral_synapses": int(t.get_rows(lateral=True)[0].sum()),
+            "ff_rewires": {"eliminated": st.eliminated, "formed": st.formed, "blocked": st.blocked},
+            "lateral_rewires": {"eliminated": sl.eliminated, "formed": sl.formed, "blocked": sl.blocked},
+            "phase_us_per_step": split}
+        t.close()
+        print(f"[bench] topomap scale {sc}: {out['by_scale'][str(sc)]['us_per_step']} us/step", file=sys.stderr,
+              flush=True)
+    us = [out["by_scale"][str(sc)]["us_per_step"] for sc in scales]
+    out["time_ratio_largest_to_smallest"] = round(us[-1] / us[0], 2)
+    # the end-to-end leg's 64 x 64 feed-forward map on both kernels
+    cfg = rb.TopoConfig(L=c["L"], cap=c["cap"], n_attempts=c["n_attempts"], proj_id=0, p_form=c["ff"]["p_form"],
+                        sigma_form=c["ff"]["sigma"], g_theta=gm / 2, p_elim_dep=c["p_elim_dep"],
+                        p_elim_pot=c["p_elim_pot"], g_new=gm, g_init=gm, seed=1)
+    kern = {}
+    for name, kind in (("one_workgroup", rb.TOPO_KERNEL_ONE_WG), ("tiled", rb.TOPO_KERNEL_TILED)):
+        t = rb.TopoNet(cfg)
+        t.sim_kernel(kind)
+        t.sim_init(rb.TopoModel(stim_kind=rb.STIM_BAR, rewire_steps=c["rewire_every"]))
+        t.run(1000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        t.run(steps)
+        torch.cuda.synchronize()
+        kern[name] = round(1e6 * (time.perf_counter() - t0) / steps, 3)
+        t.close()
+    out["map64_feed_forward_us_per_step"] = kern
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -531,6 +607,9 @@ def main():
                     help="run only the tiny-network leg and print its figures (for profiling)")
     ap.add_argument("--only-topo", action="store_true",
                     help="run only the topographic-map end-to-end leg and print its figures (for profiling)")
+    ap.add_argument("--only-topo-scaling", action="store_true",
+                    help="run only the topographic-map scaling leg (s = 1..7, lateral projection)")
+    ap.add_argument("--topo-scaling-steps", type=int, default=20000)
     ap.add_argument("--topo-steps", type=int, default=1_000_000,
                     help="steps of the topographic-map leg (default 10^6 = 100 s of model time)")
     ap.add_argument("--only-batched", action="store_true",
@@ -573,6 +652,9 @@ def main():
         return
     if args.only_served:
         print(json.dumps({"served": served_leg()}), flush=True)
+        return
+    if args.only_topo_scaling:
+        print(json.dumps({"topomap_scaling": topo_scaling_leg(steps=args.topo_scaling_steps)}), flush=True)
         return
     if args.only_batched:
         print(json.dumps({"batched": batched_leg(args.batched_instances or None)}), flush=True)
@@ -692,6 +774,8 @@ def main():
         result["topomap_rewire"] = topo_rewire_latency()
         print("[bench] topographic map end to end", file=sys.stderr, flush=True)
         result["topomap_sim"] = topo_sim_leg(steps=args.topo_steps)
+        print("[bench] topographic map scaling, s = 1..7", file=sys.stderr, flush=True)
+        result["topomap_scaling"] = topo_scaling_leg(steps=args.topo_scaling_steps)
     if not args.no_cpu_baseline:
         print(f"[bench] oracle CPU baseline ({args.cpu_steps} timesteps)", file=sys.stderr, flush=True)
         labels, raster = batches[0]

@@ -465,12 +465,54 @@ typedef struct rs_topo_model {
   float g_max, A_plus, A_minus;          /* uS (Tab. F) */
   float tau_plus, tau_minus;             /* ms */
   uint32_t rewire_steps;                 /* t_rewiring / h; 0: no rewiring */
+  uint32_t stim_tile;                    /* scaled maps: the input is replicated in every stim_tile x
+                                            stim_tile square (the s^2 stimulus locations of the scaling
+                                            paragraph, one drawn position at the same offset in each);
+                                            0 = one square, the whole sheet.  Must divide L. */
 } rs_topo_model;
 
+/* Lateral projection (Tab. A "feed-forward and lateral connections"; Tab. G
+ * p_form-lat, sigma_form-lat): target -> target rows built and rewired like
+ * the feed-forward projection, with `lp` giving its capacity, attempts,
+ * formation and elimination parameters and its proj_id (which must differ
+ * from the map's; the map's seed keys its draws).  Autapses are allowed.  In
+ * the simulation a target spike of step t is delivered at t+1 through these
+ * rows after the source spikes: each synapse adds its weight to its target's
+ * g and, with stdp, loses A_minus*y_target; the spiking neuron's lateral trace
+ * xl (decay exp(-h/tau_plus)) gains 1; a target that spikes potentiates its
+ * lateral synapses by A_plus*xl_pre, capped at g_max.  rs_topo_run rewires the
+ * lateral projection after the feed-forward one at the same steps.  Call
+ * before rs_topo_sim_init.  Synchronises.  Errors: RS_EINVAL (parameters, L
+ * different from the map's, equal proj_id), RS_ESTATE (already added, or the
+ * simulation is attached), RS_ENOMEM, RS_EDEVICE. */
+rs_status rs_topo_add_lateral(rs_topo* t, const rs_topo_params* lp);
+/* The rs_topo_rewire / get_rows / set_rows / get_bits / run_stats calls for
+ * the lateral projection (n_pre = n_post = L*L).  Errors: RS_ESTATE without
+ * a lateral projection, else as the feed-forward calls. */
+rs_status rs_topo_lat_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* stats);
+rs_status rs_topo_lat_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w);
+rs_status rs_topo_lat_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w);
+rs_status rs_topo_lat_get_bits(rs_topo* t, uint32_t* bits);
+rs_status rs_topo_lat_run_stats(rs_topo* t, rs_rewire_stats* stats);
+
+/* Simulation kernels.  ONE_WG: one workgroup holds both sheets (L*L <= 4096,
+ * no lateral projection).  TILED: one workgroup per 256 targets with a
+ * device-wide barrier per step (L*L <= 16384, every tile resident at once;
+ * a barrier that waits longer than a few seconds gives up, and the next
+ * synchronising call reports RS_EDEVICE).  AUTO (default): ONE_WG where it
+ * applies, else TILED.  Both compute the model above; they round the traces
+ * differently in the last bits (the one-workgroup kernel folds the decay of x
+ * into potentiation). */
+enum { RS_TOPO_KERNEL_AUTO = 0, RS_TOPO_KERNEL_ONE_WG = 1, RS_TOPO_KERNEL_TILED = 2 };
+/* Choose the kernel (before or after rs_topo_sim_init).  Errors: RS_EINVAL
+ * (unknown kind, or a kind the map does not fit). */
+rs_status rs_topo_sim_kernel(rs_topo* t, int32_t kind);
+
 /* Attach the simulation to a topographic map and reset its state: V = V_rest,
- * everything else zero, step counter 0.  Needs L*L <= 4096 (the state of both
- * sheets is held in one workgroup's LDS).  Synchronises.
- * Errors: RS_EINVAL (sizes, non-positive time constants or steps), RS_ENOMEM. */
+ * everything else zero, step counter 0.  Needs L*L <= 16384 (4096 for the
+ * one-workgroup kernel).  Synchronises.
+ * Errors: RS_EINVAL (sizes, non-positive time constants or steps, stim_tile),
+ * RS_ENOMEM. */
 rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m);
 /* Run n_steps steps from the step counter on, with a rewire (keyed by the
  * step count reached) after every step count divisible by rewire_steps.
@@ -492,6 +534,9 @@ rs_status rs_topo_sim_timing(rs_topo* t, int32_t on);
 /* Milliseconds accumulated per phase since the last rs_topo_sim_timing:
  * ms[0] delivery with the source draws, ms[1] neuron update, ms[2]
  * potentiation, ms[3] launch prologue (state loads and any column rebuild).
+ * On the tiled kernel (timed on its first workgroup) ms[0] is the delivery,
+ * ms[1] the neuron update with the publishing of the tile's spikes and
+ * traces, and ms[3] also holds the source draws and the step-barrier waits.
  * The rewire kernels and launch gaps make up the rest of rs_topo_last_ms.
  * Synchronises.  Errors: RS_ESTATE before rs_topo_sim_init, RS_EDEVICE. */
 rs_status rs_topo_sim_phase_ms(rs_topo* t, double ms[4]);
@@ -505,7 +550,8 @@ enum {
   RS_TV_COUNT = 5,  /* uint32[L*L] target spikes since init */
   RS_TV_ZIN = 6,    /* uint32[ceil(L*L/32)] source spikes drawn at the last step (delivered next) */
   RS_TV_ZOUT = 7,   /* uint32[ceil(L*L/32)] target spikes of the last step (read-only) */
-  RS_TV_STEP = 8    /* uint64[1] step counter */
+  RS_TV_STEP = 8,   /* uint64[1] step counter */
+  RS_TV_XLAT = 9    /* float[L*L] target lateral STDP trace (with a lateral projection) */
 };
 rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes);
 rs_status rs_topo_sim_set(rs_topo* t, int32_t var, const void* host, size_t bytes);
@@ -597,7 +643,9 @@ rs_status rs_topo_custom_update(rs_topo* t, int32_t rule, uint64_t step, rs_host
  *     e-prop with one Adam optimiser and update interval;
  *   - the topographic map: a Poisson sheet projecting onto a conductance-LIF
  *     sheet of the same size by Gaussian pairwise-Bernoulli rows, STDP or
- *     fixed weights, topographic rewiring or none.
+ *     fixed weights, topographic rewiring or none; optionally a second,
+ *     lateral projection from the conductance-LIF sheet onto itself (Gaussian
+ *     rows, the same learning and rewiring interval, rs_topo_add_lateral).
  * Any other composition is refused at build with RS_EINVAL naming the misfit.
  * With an allocator (both functions non-NULL) every device buffer of the
  * built network comes from it and returns to it at rs_destroy.

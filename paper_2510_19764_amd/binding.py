@@ -75,7 +75,8 @@ class _TopoModel(C.Structure):
                 ("ref_steps", C.c_uint32), ("f_base", C.c_float), ("f_peak", C.c_float),
                 ("sigma_stim", C.c_float), ("stim_steps", C.c_uint32), ("stim_kind", C.c_int32),
                 ("stdp", C.c_int32), ("g_max", C.c_float), ("A_plus", C.c_float), ("A_minus", C.c_float),
-                ("tau_plus", C.c_float), ("tau_minus", C.c_float), ("rewire_steps", C.c_uint32)]
+                ("tau_plus", C.c_float), ("tau_minus", C.c_float), ("rewire_steps", C.c_uint32),
+                ("stim_tile", C.c_uint32)]
 
 
 EXPORTS = [
@@ -94,6 +95,8 @@ EXPORTS = [
     "rs_create", "rs_add_pop", "rs_add_proj", "rs_build", "rs_eprop_of", "rs_topo_of", "rs_step", "rs_update",
     "rs_rewire", "rs_get_rows", "rs_get_var", "rs_set_var", "rs_sync", "rs_step_counter", "rs_destroy",
     "rs_deepr_rewire_noalloc", "rs_eprop_custom_update", "rs_topo_custom_update",
+    "rs_topo_add_lateral", "rs_topo_lat_rewire", "rs_topo_lat_get_rows", "rs_topo_lat_set_rows",
+    "rs_topo_lat_get_bits", "rs_topo_lat_run_stats", "rs_topo_sim_kernel",
 ]
 
 _lib = None
@@ -141,6 +144,13 @@ def lib():
         L.rs_topo_sim_set.argtypes = [vp, C.c_int32, vp, C.c_size_t]
         L.rs_topo_sim_timing.argtypes = [vp, C.c_int32]
         L.rs_topo_sim_phase_ms.argtypes = [vp, C.POINTER(C.c_double)]
+        L.rs_topo_add_lateral.argtypes = [vp, C.POINTER(_TopoParams)]
+        L.rs_topo_lat_rewire.argtypes = [vp, C.c_uint64, C.POINTER(_Stats)]
+        L.rs_topo_lat_get_rows.argtypes = [vp, vp, vp, vp]
+        L.rs_topo_lat_set_rows.argtypes = [vp, vp, vp, vp]
+        L.rs_topo_lat_get_bits.argtypes = [vp, vp]
+        L.rs_topo_lat_run_stats.argtypes = [vp, C.POINTER(_Stats)]
+        L.rs_topo_sim_kernel.argtypes = [vp, C.c_int32]
         L.rs_calib_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.rs_multi_create.argtypes = [C.POINTER(_EpropParams), C.c_uint32, vp, C.POINTER(vp)]
         L.rs_multi_set_input.argtypes = [vp, C.c_uint32, vp, vp, C.c_size_t, vp]
@@ -526,10 +536,14 @@ class ComposedNet:
         _check(lib().rs_eprop_of(self._h, C.byref(h)))
         return EpropNet._view(h, cfg, self)
 
-    def topo(self, cfg):
+    def topo(self, cfg, lat_cfg=None):
+        """The built map's rs_topo object (cfg, lat_cfg: its projections' shapes)."""
         h = C.c_void_p()
         _check(lib().rs_topo_of(self._h, C.byref(h)))
-        return TopoNet._view(h, cfg, self)
+        v = TopoNet._view(h, cfg, self)
+        if lat_cfg is not None:
+            v.lat_cfg = lat_cfg
+        return v
 
     def step(self, n, flags=RS_LEARN):
         _check(lib().rs_step(self._h, n, flags))
@@ -783,26 +797,37 @@ class TopoNet:
         except Exception:
             pass
 
-    def rewire(self, step: int, stats: bool = True):
+    def rewire(self, step: int, stats: bool = True, lateral: bool = False):
         st = _Stats()
-        _check(lib().rs_topo_rewire(self._h, step, C.byref(st) if stats else None))
+        fn = lib().rs_topo_lat_rewire if lateral else lib().rs_topo_rewire
+        _check(fn(self._h, step, C.byref(st) if stats else None))
         return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts) if stats else None
 
-    def get_rows(self):
-        n, cap = self.n, self.cfg.cap
+    def add_lateral(self, cfg: "TopoConfig"):
+        """Target -> target projection (rs_topo_add_lateral); before sim_init."""
+        _check(lib().rs_topo_add_lateral(self._h, C.byref(cfg.c())))
+        self.lat_cfg = cfg
+
+    def sim_kernel(self, kind: int):
+        _check(lib().rs_topo_sim_kernel(self._h, kind))
+
+    def get_rows(self, lateral: bool = False):
+        n, cap = self.n, (self.lat_cfg.cap if lateral else self.cfg.cap)
         ln = np.empty(n, np.int32)
         ind = np.empty((n, cap), np.int32)
         w = np.empty((n, cap), np.float32)
-        _check(lib().rs_topo_get_rows(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
-                                      w.ctypes.data_as(C.c_void_p)))
+        fn = lib().rs_topo_lat_get_rows if lateral else lib().rs_topo_get_rows
+        _check(fn(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
+                  w.ctypes.data_as(C.c_void_p)))
         return ln, ind, w
 
-    def set_rows(self, ln, ind, w):
+    def set_rows(self, ln, ind, w, lateral: bool = False):
         ln = np.ascontiguousarray(ln, np.int32)
         ind = np.ascontiguousarray(ind, np.int32)
         w = np.ascontiguousarray(w, np.float32)
-        _check(lib().rs_topo_set_rows(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
-                                      w.ctypes.data_as(C.c_void_p)))
+        fn = lib().rs_topo_lat_set_rows if lateral else lib().rs_topo_set_rows
+        _check(fn(self._h, ln.ctypes.data_as(C.c_void_p), ind.ctypes.data_as(C.c_void_p),
+                  w.ctypes.data_as(C.c_void_p)))
 
     def custom_update(self, rule: int, step: int, host_fn=None) -> RewireStats:
         st = _Stats()
@@ -810,9 +835,10 @@ class TopoNet:
         _check(lib().rs_topo_custom_update(self._h, rule, step, cb, None, C.byref(st)))
         return _custom_stats(st)
 
-    def get_bits(self):
+    def get_bits(self, lateral: bool = False):
         b = np.empty((self.n, self.words), np.uint32)
-        _check(lib().rs_topo_get_bits(self._h, b.ctypes.data_as(C.c_void_p)))
+        fn = lib().rs_topo_lat_get_bits if lateral else lib().rs_topo_get_bits
+        _check(fn(self._h, b.ctypes.data_as(C.c_void_p)))
         return b
 
     def last_ms(self) -> float:
@@ -829,9 +855,10 @@ class TopoNet:
     def run(self, n_steps: int):
         _check(lib().rs_topo_run(self._h, n_steps))
 
-    def run_stats(self) -> RewireStats:
+    def run_stats(self, lateral: bool = False) -> RewireStats:
         st = _Stats()
-        _check(lib().rs_topo_run_stats(self._h, C.byref(st)))
+        fn = lib().rs_topo_lat_run_stats if lateral else lib().rs_topo_run_stats
+        _check(fn(self._h, C.byref(st)))
         return RewireStats(st.eliminated, st.formed, st.blocked, st.attempts)
 
     def sim_timing(self, on: bool):
@@ -866,7 +893,8 @@ class TopoNet:
 
 STIM_BLOB, STIM_BAR = 0, 1
 TOPO_PHASES = ("delivery_and_source", "neurons", "potentiation", "launch_prologue")
-TV_V, TV_G, TV_Y, TV_X, TV_REF, TV_COUNT, TV_ZIN, TV_ZOUT, TV_STEP = range(9)
+TV_V, TV_G, TV_Y, TV_X, TV_REF, TV_COUNT, TV_ZIN, TV_ZOUT, TV_STEP, TV_XLAT = range(10)
+TOPO_KERNEL_AUTO, TOPO_KERNEL_ONE_WG, TOPO_KERNEL_TILED = 0, 1, 2
 
 
 @dataclass
@@ -893,6 +921,7 @@ class TopoModel:
     tau_plus: float = 20.0
     tau_minus: float = 64.0
     rewire_steps: int = 10
+    stim_tile: int = 0  # side of the square the input is replicated over (scaled maps); 0: whole sheet
 
     def c(self) -> _TopoModel:
         m = _TopoModel()

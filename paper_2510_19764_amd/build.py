@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(OUT_DIR, "libragsnn.so")
-SOURCES = ["engine.hip", "k_build.hip", "k_forward.hip", "k_eprop.hip", "k_update.hip", "k_deepr.hip", "k_topo.hip", "k_topo_sim.hip", "k_serve.hip", "k_custom.hip", "noalloc.hip"]
+SOURCES = ["engine.hip", "k_build.hip", "k_forward.hip", "k_eprop.hip", "k_update.hip", "k_deepr.hip", "k_topo.hip", "k_topo_sim.hip", "k_topo_tiles.hip", "k_serve.hip", "k_custom.hip", "noalloc.hip"]
 HEADERS = ["rs_device.hpp", "rs_kernels.hpp", "rs_compact.hpp", "rs_custom.hpp", "rs_host_rng.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -998,11 +998,53 @@ struct rs_topo {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   struct rs_custom_state* custom = nullptr;  // scratch of custom connectivity updates
+  // lateral projection (target -> target, rs_topo_add_lateral)
+  bool lateral = false;
+  rs_topo_params pl{};
+  TopoDev tl{};
+  uint64_t* T_d2_l = nullptr;
+  int32_t kernel = RS_TOPO_KERNEL_AUTO;  // requested simulation kernel
+  bool tiled = false;                    // the simulation runs on the tiled kernel
   bool dead = false;  // a device error occurred: every later call fails with RS_EDEVICE
 };
 
 namespace {
 constexpr uint64_t GRAPH_INTERVALS = 64;
+
+// One simulation launch on the map's kernel.
+void topo_launch_sim(rs_topo* t, hipStream_t s, uint64_t t0, int n) {
+  if (t->tiled) {
+    ProjDev none{};
+    launch_topo_tiles(s, t->p.seed, t->t.P, t->lateral ? t->tl.P : none, t->sd, t0, n);
+  } else {
+    launch_topo_sim(s, t->p.seed, t->t.P, t->sd, t0, n);
+  }
+}
+
+// Choose the simulation kernel: the one-workgroup kernel for maps of up to
+// 4096 neurons without a lateral projection (unless the tiled one is asked
+// for), the tiled kernel otherwise, if the device keeps all of its tiles
+// resident.
+rs_status topo_pick_kernel(rs_topo* t, int32_t kind) {
+  const int N = (int)(t->p.L * t->p.L);
+  bool tiled = kind == RS_TOPO_KERNEL_TILED || (kind == RS_TOPO_KERNEL_AUTO && (t->lateral || !topo_sim_fits(N)));
+  if (!tiled && (t->lateral || !topo_sim_fits(N)))
+    return fail(RS_EINVAL, "the one-workgroup kernel needs L*L <= 4096 and no lateral projection");
+  if (tiled) {
+    if (N > TOPO_TILES_MAX_N) return fail(RS_EINVAL, "the tiled kernel needs L*L <= %d", TOPO_TILES_MAX_N);
+    const int need = topo_tiles_grid(N), have = topo_tiles_resident(N, t->lateral);
+    if (need > have) return fail(RS_EINVAL, "the tiled kernel needs %d resident workgroups, the device keeps %d",
+                                 need, have);
+  }
+  t->tiled = tiled;
+  return RS_OK;
+}
+
+// The rewires after a rewiring interval: feed-forward, then lateral.
+void topo_launch_rewires(rs_topo* t, hipStream_t s, uint64_t step) {
+  if (t->lateral) launch_topo_rewire_pair(s, t->p.seed, t->t, t->tl, step);
+  else launch_topo_rewire(s, t->p.seed, t->t, step);
+}
 
 void topo_drop_graph(rs_topo* t) {
   if (t->gexec) (void)hipGraphExecDestroy(t->gexec);
@@ -1019,8 +1061,8 @@ rs_status topo_build_graph(rs_topo* t) {
   if (!t->cap_stream) HIP_OK(hipStreamCreateWithFlags(&t->cap_stream, hipStreamNonBlocking));
   HIP_OK(hipStreamBeginCapture(t->cap_stream, hipStreamCaptureModeThreadLocal));
   for (uint64_t g = 0; g < GRAPH_INTERVALS; ++g) {
-    launch_topo_sim(t->cap_stream, t->p.seed, t->t.P, t->sd, STEP_FROM_DEVICE, R);
-    launch_topo_rewire(t->cap_stream, t->p.seed, t->t, STEP_FROM_DEVICE);
+    topo_launch_sim(t, t->cap_stream, STEP_FROM_DEVICE, R);
+    topo_launch_rewires(t, t->cap_stream, STEP_FROM_DEVICE);
   }
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(t->cap_stream, &g);
@@ -1037,7 +1079,7 @@ rs_status topo_build_graph(rs_topo* t) {
 
 namespace {
 
-rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
+rs_status topo_check_params(const rs_topo_params* p) {
   if (p->L < 2 || p->L > 128) return fail(RS_EINVAL, "L must be in 2..128");
   if (p->cap < 1 || p->cap > 1024 || p->cap > p->L * p->L) return fail(RS_EINVAL, "cap must be in 1..min(1024, L*L)");
   if (p->n_attempts > 4096) return fail(RS_EINVAL, "n_attempts must be <= 4096");
@@ -1045,11 +1087,16 @@ rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
     return fail(RS_EINVAL, "probabilities must be >= 0 and sigma_form > 0");
   if (!(std::fabs(p->g_new) <= TOPO_W_MAX) || !(std::fabs(p->g_init) <= TOPO_W_MAX))
     return fail(RS_EINVAL, "g_new and g_init must lie within +-1e4");
-  t->p = *p;
-  t->stream = (hipStream_t)stream;
+  return RS_OK;
+}
+
+// Allocate and build one projection between L x L sheets (rows by the
+// pairwise-Bernoulli rule with the formation probability) with its rewiring
+// state; `seed` keys the build draws together with p->proj_id.
+rs_status topo_proj_build(rs_topo* t, const rs_topo_params* p, uint64_t seed, TopoDev& td, uint64_t** T_d2_out) {
   hipStream_t s = t->stream;
   const int L = (int)p->L, N = L * L;
-  ProjDev& P = t->t.P;
+  ProjDev& P = td.P;
   P.n_pre = N;
   P.n_post = N;
   P.cap = (int)p->cap;
@@ -1064,27 +1111,37 @@ rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
   std::vector<uint64_t> T(n_d2);
   for (int d2 = 0; d2 < n_d2; ++d2)
     T[d2] = threshold((double)p->p_form * std::exp(-(double)d2 / (2.0 * (double)p->sigma_form * (double)p->sigma_form)));
-  TRY(ar.alloc(&t->T_d2, (size_t)n_d2));
-  TRY(ar.alloc(&t->t.bits, (size_t)N * P.words));
-  TRY(ar.alloc(&t->t.kcount, (size_t)N));
-  TRY(ar.alloc(&t->t.rowlist, (size_t)std::max<uint32_t>(p->n_attempts, 1)));
-  TRY(ar.alloc(&t->t.nrows, 1));
-  TRY(ar.alloc(&t->t.stats, 4));
-  TRY(ar.alloc(&t->t.col_dirty, 1));
-  HIP_OK(hipMemcpyAsync(t->T_d2, T.data(), n_d2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
-  t->t.T_d2 = t->T_d2;
-  t->t.L = L;
-  t->t.n_attempts = (int)p->n_attempts;
-  t->t.g_theta = p->g_theta;
-  t->t.g_new = p->g_new;
-  t->t.T_dep = threshold(p->p_elim_dep);
-  t->t.T_pot = threshold(p->p_elim_pot);
+  TRY(ar.alloc(T_d2_out, (size_t)n_d2));
+  TRY(ar.alloc(&td.bits, (size_t)N * P.words));
+  TRY(ar.alloc(&td.kcount, (size_t)N));
+  TRY(ar.alloc(&td.rowlist, (size_t)std::max<uint32_t>(p->n_attempts, 1)));
+  TRY(ar.alloc(&td.nrows, 1));
+  TRY(ar.alloc(&td.stats, 4));
+  TRY(ar.alloc(&td.col_dirty, 1));
+  HIP_OK(hipMemcpyAsync(*T_d2_out, T.data(), n_d2 * sizeof(uint64_t), hipMemcpyHostToDevice, s));
+  td.T_d2 = *T_d2_out;
+  td.L = L;
+  td.n_attempts = (int)p->n_attempts;
+  td.g_theta = p->g_theta;
+  td.g_new = p->g_new;
+  td.T_dep = threshold(p->p_elim_dep);
+  td.T_pot = threshold(p->p_elim_pot);
   launch_fill_zero(s, P.ind, (size_t)N * P.cap * 4);
   launch_fill_zero(s, P.w, (size_t)N * P.cap * 4);
-  launch_gauss_rows(s, p->seed, P, L, t->T_d2, p->g_init, true);
-  launch_fill_zero(s, t->t.bits, (size_t)N * P.words * 4);
-  launch_fill_zero(s, t->t.stats, 32);
-  launch_fill_zero(s, t->t.col_dirty, 4);
+  launch_gauss_rows(s, seed, P, L, td.T_d2, p->g_init, true);
+  launch_fill_zero(s, td.bits, (size_t)N * P.words * 4);
+  launch_fill_zero(s, td.stats, 32);
+  launch_fill_zero(s, td.col_dirty, 4);
+  HIP_OK(hipGetLastError());
+  return RS_OK;
+}
+
+rs_status topo_create_impl(const rs_topo_params* p, void* stream, rs_topo* t) {
+  TRY(topo_check_params(p));
+  t->p = *p;
+  t->stream = (hipStream_t)stream;
+  hipStream_t s = t->stream;
+  TRY(topo_proj_build(t, p, p->seed, t->t, &t->T_d2));
   HIP_OK(hipEventCreate(&t->ev0));
   HIP_OK(hipEventCreate(&t->ev1));
   HIP_OK(hipGetLastError());
@@ -1111,32 +1168,33 @@ rs_status rs_topo_create(const rs_topo_params* p, void* hip_stream, rs_topo** ou
   return RS_OK;
 }
 
-rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
-  ENTER(t);
+}  // extern "C"
+
+namespace {
+
+rs_status topo_rewire_impl(rs_topo* t, TopoDev& td, uint32_t n_attempts, uint64_t step, rs_rewire_stats* st) {
   if (step == STEP_FROM_DEVICE) return fail(RS_EINVAL, "step 2^64-1 is reserved");
   hipStream_t s = t->stream;
-  launch_fill_zero(s, t->t.stats, 32);
+  launch_fill_zero(s, td.stats, 32);
   HIP_OK(hipEventRecord(t->ev0, s));
-  launch_topo_rewire(s, t->p.seed, t->t, step);
+  launch_topo_rewire(s, t->p.seed, td, step);
   HIP_OK(hipEventRecord(t->ev1, s));
   t->timed = true;
   HIP_OK(hipGetLastError());
   if (st) {
     long long h[4];
-    HIP_OK(hipMemcpyAsync(h, t->t.stats, sizeof h, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(h, td.stats, sizeof h, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     st->eliminated = h[0];
     st->formed = h[1];
     st->blocked = h[2];
-    st->attempts = t->p.n_attempts;
+    st->attempts = n_attempts;
   }
   return RS_OK;
 }
 
-rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
-  ENTER(t);
+rs_status topo_get_rows_impl(rs_topo* t, const ProjDev& P, int32_t* len, int32_t* ind, float* w) {
   if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
-  const ProjDev& P = t->t.P;
   const size_t n = (size_t)P.n_pre * P.cap;
   HIP_OK(hipMemcpyAsync(len, P.len, (size_t)P.n_pre * 4, hipMemcpyDeviceToHost, t->stream));
   HIP_OK(hipMemcpyAsync(ind, P.ind, n * 4, hipMemcpyDeviceToHost, t->stream));
@@ -1145,10 +1203,9 @@ rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
   return RS_OK;
 }
 
-rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w) {
-  ENTER(t);
+rs_status topo_set_rows_impl(rs_topo* t, TopoDev& td, const int32_t* len, const int32_t* ind, const float* w) {
   if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
-  const ProjDev& P = t->t.P;
+  const ProjDev& P = td.P;
   for (int i = 0; i < P.n_pre; ++i) {
     if (len[i] < 0 || len[i] > P.cap) return fail(RS_EINVAL, "row %d length %d outside 0..%d", i, len[i], P.cap);
     for (int k = 0; k < len[i]; ++k) {
@@ -1167,18 +1224,93 @@ rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, c
   HIP_OK(hipMemcpyAsync(P.ind, ind, n * 4, hipMemcpyHostToDevice, t->stream));
   HIP_OK(hipMemcpyAsync(P.w, w, n * 4, hipMemcpyHostToDevice, t->stream));
   static const int one = 1;
-  HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, t->stream));
+  HIP_OK(hipMemcpyAsync(td.col_dirty, &one, 4, hipMemcpyHostToDevice, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
   return RS_OK;
 }
 
-rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits) {
-  ENTER(t);
+rs_status topo_get_bits_impl(rs_topo* t, const TopoDev& td, uint32_t* bits) {
   if (!bits) return fail(RS_EINVAL, "NULL argument");
-  const ProjDev& P = t->t.P;
-  HIP_OK(hipMemcpyAsync(bits, t->t.bits, (size_t)P.n_pre * P.words * 4, hipMemcpyDeviceToHost, t->stream));
+  const ProjDev& P = td.P;
+  HIP_OK(hipMemcpyAsync(bits, td.bits, (size_t)P.n_pre * P.words * 4, hipMemcpyDeviceToHost, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
   return RS_OK;
+}
+
+// Synchronise and report a step barrier of the tiled kernel that gave up.
+rs_status topo_sync_check(rs_topo* t) {
+  HIP_OK(hipStreamSynchronize(t->stream));
+  if (t->sim && t->tiled) {
+    int e = 0;
+    HIP_OK(hipMemcpyAsync(&e, t->sd.err, 4, hipMemcpyDeviceToHost, t->stream));
+    HIP_OK(hipStreamSynchronize(t->stream));
+    if (e) return fail(RS_EDEVICE, "a step barrier of the tiled simulation timed out (workgroups not resident)");
+  }
+  return RS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rs_status rs_topo_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
+  ENTER(t);
+  return topo_rewire_impl(t, t->t, t->p.n_attempts, step, st);
+}
+
+rs_status rs_topo_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
+  ENTER(t);
+  return topo_get_rows_impl(t, t->t.P, len, ind, w);
+}
+
+rs_status rs_topo_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w) {
+  ENTER(t);
+  return topo_set_rows_impl(t, t->t, len, ind, w);
+}
+
+rs_status rs_topo_get_bits(rs_topo* t, uint32_t* bits) {
+  ENTER(t);
+  return topo_get_bits_impl(t, t->t, bits);
+}
+
+rs_status rs_topo_add_lateral(rs_topo* t, const rs_topo_params* lp) {
+  ENTER(t);
+  if (!lp) return fail(RS_EINVAL, "NULL argument");
+  if (t->lateral) return fail(RS_ESTATE, "the map has a lateral projection");
+  if (t->sim) return fail(RS_ESTATE, "add the lateral projection before rs_topo_sim_init");
+  TRY(topo_check_params(lp));
+  if (lp->L != t->p.L) return fail(RS_EINVAL, "the lateral projection joins the target sheet to itself: L %u != %u",
+                                   lp->L, t->p.L);
+  if (lp->proj_id == t->p.proj_id) return fail(RS_EINVAL, "the lateral projection needs its own proj_id");
+  t->pl = *lp;
+  TRY(topo_proj_build(t, lp, t->p.seed, t->tl, &t->T_d2_l));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  t->lateral = true;
+  return RS_OK;
+}
+
+rs_status rs_topo_lat_rewire(rs_topo* t, uint64_t step, rs_rewire_stats* st) {
+  ENTER(t);
+  if (!t->lateral) return fail(RS_ESTATE, "the map has no lateral projection");
+  return topo_rewire_impl(t, t->tl, t->pl.n_attempts, step, st);
+}
+
+rs_status rs_topo_lat_get_rows(rs_topo* t, int32_t* len, int32_t* ind, float* w) {
+  ENTER(t);
+  if (!t->lateral) return fail(RS_ESTATE, "the map has no lateral projection");
+  return topo_get_rows_impl(t, t->tl.P, len, ind, w);
+}
+
+rs_status rs_topo_lat_set_rows(rs_topo* t, const int32_t* len, const int32_t* ind, const float* w) {
+  ENTER(t);
+  if (!t->lateral) return fail(RS_ESTATE, "the map has no lateral projection");
+  return topo_set_rows_impl(t, t->tl, len, ind, w);
+}
+
+rs_status rs_topo_lat_get_bits(rs_topo* t, uint32_t* bits) {
+  ENTER(t);
+  if (!t->lateral) return fail(RS_ESTATE, "the map has no lateral projection");
+  return topo_get_bits_impl(t, t->tl, bits);
 }
 
 rs_status rs_topo_last_ms(rs_topo* t, double* ms) {
@@ -1196,7 +1328,9 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   ENTER(t);
   if (!m) return fail(RS_EINVAL, "NULL argument");
   const int L = (int)t->p.L, N = L * L;
-  if (!topo_sim_fits(N)) return fail(RS_EINVAL, "the simulation needs L*L <= 4096 (L = %d)", L);
+  TRY(topo_pick_kernel(t, t->kernel));
+  if (m->stim_tile != 0 && (m->stim_tile > (uint32_t)L || L % (int)m->stim_tile))
+    return fail(RS_EINVAL, "stim_tile %u must divide L = %d", m->stim_tile, L);
   if (!(m->h > 0) || !(m->C_m > 0) || !(m->tau_m > 0) || !(m->tau_s > 0) || !(m->tau_plus > 0) ||
       !(m->tau_minus > 0))
     return fail(RS_EINVAL, "h, C_m and every time constant must be > 0");
@@ -1230,6 +1364,18 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
     TRY(ar.alloc(&t->step_dev, 1));
     TRY(ar.alloc(&t->ticks, (size_t)TOPO_PHASES));
     d.T_in = T_in;
+    // the tiled kernel's step exchange and barrier
+    TRY(ar.alloc(&d.zin_b, (size_t)words));
+    TRY(ar.alloc(&d.zout_b, (size_t)words));
+    TRY(ar.alloc(&d.x_b, (size_t)N));
+    TRY(ar.alloc(&d.bar, (size_t)TOPO_TILES_MAX * 16));
+    TRY(ar.alloc(&d.err, 1));
+    if (t->lateral) {
+      TRY(ar.alloc(&d.xl, (size_t)N));
+      TRY(ar.alloc(&d.xl_b, (size_t)N));
+      TRY(ar.alloc(&d.col_len_l, (size_t)N));
+      TRY(ar.alloc(&d.col_ent_l, (size_t)N * N));
+    }
   }
   topo_drop_graph(t);  // the recorded launches carry the old constants
   t->m = *m;
@@ -1238,6 +1384,7 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   d.ref_steps = (int)m->ref_steps;
   d.stim_steps = (int)m->stim_steps;
   d.stim_kind = m->stim_kind;
+  d.stim_L = m->stim_tile ? (int)m->stim_tile : L;
   d.stdp = m->stdp ? 1 : 0;
   d.V_rest = m->V_rest;
   d.E_exc = m->E_exc;
@@ -1259,6 +1406,13 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   t->t.col_len = d.col_len;  // from here on the rewire edits the simulation's column view
   t->t.col_ent = d.col_ent;
   t->t.col_cap = N;
+  if (t->lateral) {
+    d.col_dirty_l = t->tl.col_dirty;
+    t->tl.step_dev = t->step_dev;
+    t->tl.col_len = d.col_len_l;
+    t->tl.col_ent = d.col_ent_l;
+    t->tl.col_cap = N;
+  }
   // Bernoulli threshold of one step of the source's Poisson train, by the
   // integer squared distance from the stimulus (Tab. E rate profile)
   std::vector<uint64_t> T(n_d2);
@@ -1282,9 +1436,16 @@ rs_status rs_topo_sim_init(rs_topo* t, const rs_topo_model* m) {
   launch_fill_zero(s, d.col_len, (size_t)N * 4);
   launch_fill_zero(s, t->step_dev, 8);
   launch_fill_zero(s, t->ticks, 8 * TOPO_PHASES);
+  launch_fill_zero(s, d.bar, (size_t)TOPO_TILES_MAX * 16 * 8);
+  launch_fill_zero(s, d.err, 4);
   d.ticks = nullptr;  // timers off until rs_topo_sim_timing
   static const int one = 1;
   HIP_OK(hipMemcpyAsync(t->t.col_dirty, &one, 4, hipMemcpyHostToDevice, s));
+  if (t->lateral) {
+    launch_fill_zero(s, d.xl, (size_t)N * 4);
+    launch_fill_zero(s, d.col_len_l, (size_t)N * 4);
+    HIP_OK(hipMemcpyAsync(t->tl.col_dirty, &one, 4, hipMemcpyHostToDevice, s));
+  }
   HIP_OK(hipGetLastError());
   HIP_OK(hipStreamSynchronize(s));
   t->step = 0;
@@ -1299,6 +1460,7 @@ rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
   const uint64_t R = t->m.rewire_steps;
   constexpr uint64_t MAX_CHUNK = 10000;  // steps per launch without rewiring
   launch_fill_zero(s, t->t.stats, 32);
+  if (t->lateral) launch_fill_zero(s, t->tl.stats, 32);
   HIP_OK(hipEventRecord(t->ev0, s));
   uint64_t left = n_steps;
   while (left > 0) {
@@ -1312,10 +1474,10 @@ rs_status rs_topo_run(rs_topo* t, uint64_t n_steps) {
     uint64_t chunk = R ? R - t->step % R : MAX_CHUNK;
     if (chunk > left) chunk = left;
     if (chunk > MAX_CHUNK) chunk = MAX_CHUNK;
-    launch_topo_sim(s, t->p.seed, t->t.P, t->sd, t->step, (int)chunk);
+    topo_launch_sim(t, s, t->step, (int)chunk);
     t->step += chunk;
     left -= chunk;
-    if (R && t->step % R == 0) launch_topo_rewire(s, t->p.seed, t->t, t->step);
+    if (R && t->step % R == 0) topo_launch_rewires(t, s, t->step);
   }
   HIP_OK(hipEventRecord(t->ev1, s));
   t->timed = true;
@@ -1353,9 +1515,38 @@ rs_status rs_topo_sim_phase_ms(rs_topo* t, double* ms) {
   return RS_OK;
 }
 
+rs_status rs_topo_lat_run_stats(rs_topo* t, rs_rewire_stats* st) {
+  ENTER(t);
+  if (!st) return fail(RS_EINVAL, "NULL argument");
+  if (!t->lateral) return fail(RS_ESTATE, "the map has no lateral projection");
+  TRY(topo_sync_check(t));
+  long long h[4];
+  HIP_OK(hipMemcpyAsync(h, t->tl.stats, sizeof h, hipMemcpyDeviceToHost, t->stream));
+  HIP_OK(hipStreamSynchronize(t->stream));
+  st->eliminated = h[0];
+  st->formed = h[1];
+  st->blocked = h[2];
+  st->attempts = 0;
+  return RS_OK;
+}
+
+rs_status rs_topo_sim_kernel(rs_topo* t, int32_t kind) {
+  ENTER(t);
+  if (kind != RS_TOPO_KERNEL_AUTO && kind != RS_TOPO_KERNEL_ONE_WG && kind != RS_TOPO_KERNEL_TILED)
+    return fail(RS_EINVAL, "unknown simulation kernel %d", kind);
+  if (t->sim) {
+    TRY(topo_sync_check(t));
+    TRY(topo_pick_kernel(t, kind));
+    topo_drop_graph(t);  // the recorded launches use the old kernel
+  }
+  t->kernel = kind;
+  return RS_OK;
+}
+
 rs_status rs_topo_run_stats(rs_topo* t, rs_rewire_stats* st) {
   ENTER(t);
   if (!st) return fail(RS_EINVAL, "NULL argument");
+  TRY(topo_sync_check(t));
   long long h[4];
   HIP_OK(hipMemcpyAsync(h, t->t.stats, sizeof h, hipMemcpyDeviceToHost, t->stream));
   HIP_OK(hipStreamSynchronize(t->stream));
@@ -1380,6 +1571,9 @@ rs_status topo_var(rs_topo* t, int32_t var, void** dev, size_t* bytes, bool* wri
     case RS_TV_COUNT: *dev = t->sd.count; *bytes = N * 4; return RS_OK;
     case RS_TV_ZIN: *dev = t->sd.zin; *bytes = words * 4; return RS_OK;
     case RS_TV_ZOUT: *dev = t->sd.zout; *bytes = words * 4; *writable = false; return RS_OK;
+    case RS_TV_XLAT:
+      if (!t->lateral) return fail(RS_EINVAL, "the map has no lateral projection");
+      *dev = t->sd.xl; *bytes = N * 4; return RS_OK;
     case RS_TV_STEP: *dev = nullptr; *bytes = 8; return RS_OK;
     default: return fail(RS_EINVAL, "unknown topomap variable %d", var);
   }
@@ -1394,7 +1588,7 @@ rs_status rs_topo_sim_get(rs_topo* t, int32_t var, void* host, size_t bytes) {
   bool wr = false;
   TRY(topo_var(t, var, &dev, &need, &wr));
   if (bytes != need) return fail(RS_EINVAL, "variable %d needs %zu bytes, got %zu", var, need, bytes);
-  HIP_OK(hipStreamSynchronize(t->stream));
+  TRY(topo_sync_check(t));
   if (var == RS_TV_STEP) {
     std::memcpy(host, &t->step, 8);
     return RS_OK;
@@ -2608,9 +2802,27 @@ rs_status net_build_classifier(rs_net* n, uint32_t batch, uint32_t sample_steps,
   return RS_OK;
 }
 
+// The map's projection parameters from a descriptor.
+rs_topo_params topo_params_of(const rs_proj_desc& d, uint32_t L, uint32_t proj_id, uint64_t seed) {
+  rs_topo_params tp{};
+  tp.L = L;
+  tp.cap = d.cap;
+  tp.n_attempts = d.rewire == RS_REWIRE_TOPO ? d.n_attempts : 0;
+  tp.proj_id = proj_id;
+  tp.p_form = d.p_form;
+  tp.sigma_form = d.sigma_form;
+  tp.g_theta = d.g_theta;
+  tp.p_elim_dep = d.p_elim_dep;
+  tp.p_elim_pot = d.p_elim_pot;
+  tp.g_new = d.g_new;
+  tp.g_init = d.g_init;
+  tp.seed = seed;
+  return tp;
+}
+
 rs_status net_build_topomap(rs_net* n) {
-  if (n->pops.size() != 2 || n->projs.size() != 1)
-    return fail(RS_EINVAL, "the topographic map has two sheets and one projection");
+  if (n->pops.size() != 2 || (n->projs.size() != 1 && n->projs.size() != 2))
+    return fail(RS_EINVAL, "the topographic map has two sheets, a feed-forward and optionally a lateral projection");
   const rs_net::Pop &a = n->pops[0], &b = n->pops[1];
   if (a.kind != RS_POP_POISSON_SHEET || b.kind != RS_POP_COND_LIF_SHEET || a.p.L != b.p.L || a.n != a.p.L * a.p.L ||
       b.n != a.n)
@@ -2620,19 +2832,16 @@ rs_status net_build_topomap(rs_net* n) {
     return fail(RS_EINVAL, "the sheet projection has Gaussian pairwise-Bernoulli rows");
   if (d.learn != RS_LEARN_NONE && d.learn != RS_LEARN_STDP) return fail(RS_EINVAL, "the map learns by STDP or not");
   if (d.rewire != RS_REWIRE_NONE && d.rewire != RS_REWIRE_TOPO) return fail(RS_EINVAL, "the map rewires topographically");
-  rs_topo_params tp{};
-  tp.L = a.p.L;
-  tp.cap = d.cap;
-  tp.n_attempts = d.rewire == RS_REWIRE_TOPO ? d.n_attempts : 0;
-  tp.proj_id = 0;
-  tp.p_form = d.p_form;
-  tp.sigma_form = d.sigma_form;
-  tp.g_theta = d.g_theta;
-  tp.p_elim_dep = d.p_elim_dep;
-  tp.p_elim_pot = d.p_elim_pot;
-  tp.g_new = d.g_new;
-  tp.g_init = d.g_init;
-  tp.seed = n->seed;
+  const rs_proj_desc* dl = nullptr;
+  if (n->projs.size() == 2) {
+    dl = &n->projs[1].d;
+    if (n->projs[1].pre != 1 || n->projs[1].post != 1 || dl->init != RS_INIT_GAUSS_TORUS)
+      return fail(RS_EINVAL, "the lateral projection joins the target sheet to itself by Gaussian rows");
+    if (dl->learn != d.learn) return fail(RS_EINVAL, "both projections of the map learn by STDP or neither");
+    if (dl->rewire != d.rewire || (d.rewire == RS_REWIRE_TOPO && dl->update_interval != d.update_interval))
+      return fail(RS_EINVAL, "both projections of the map rewire at the same interval or neither");
+  }
+  rs_topo_params tp = topo_params_of(d, a.p.L, 0, n->seed);
   rs_topo_model m = b.p.model;  // neuron and synapse of the target sheet
   const rs_topo_model& sm = a.p.model;  // stimulus of the source sheet
   m.f_base = sm.f_base;
@@ -2640,6 +2849,7 @@ rs_status net_build_topomap(rs_net* n) {
   m.sigma_stim = sm.sigma_stim;
   m.stim_steps = sm.stim_steps;
   m.stim_kind = sm.stim_kind;
+  m.stim_tile = sm.stim_tile;
   m.stdp = d.learn == RS_LEARN_STDP;
   m.rewire_steps = d.rewire == RS_REWIRE_TOPO ? d.update_interval : 0;
   rs_topo* t = new rs_topo();
@@ -2647,6 +2857,10 @@ rs_status net_build_topomap(rs_net* n) {
   t->arena.ffn = n->alloc.ffn;
   t->arena.user = n->alloc.user;
   rs_status st = topo_create_impl(&tp, n->stream, t);
+  if (st == RS_OK && dl) {
+    const rs_topo_params tl = topo_params_of(*dl, a.p.L, 1, n->seed);
+    st = rs_topo_add_lateral(t, &tl);
+  }
   if (st == RS_OK) st = rs_topo_sim_init(t, &m);
   if (st != RS_OK) {
     rs_topo_destroy(t);
@@ -2747,7 +2961,7 @@ rs_status rs_rewire(rs_net* n, uint32_t proj, rs_rewire_stats* st) {
   if (n->tp) {
     uint64_t step = 0;
     TRY(rs_topo_sim_get(n->tp, RS_TV_STEP, &step, 8));
-    return rs_topo_rewire(n->tp, step, st);
+    return proj == 1 ? rs_topo_lat_rewire(n->tp, step, st) : rs_topo_rewire(n->tp, step, st);
   }
   return fail(RS_ESTATE, "the network is not built");
 }
@@ -2758,11 +2972,11 @@ rs_status rs_get_rows(rs_net* n, uint32_t proj, int32_t* len, int32_t* ind, floa
   if (proj >= n->projs.size()) return fail(RS_EINVAL, "unknown projection %u", proj);
   if (!len || !ind || !w) return fail(RS_EINVAL, "NULL argument");
   if (n->tp) {
-    const ProjDev& P = n->tp->t.P;
+    const ProjDev& P = proj == 1 ? n->tp->tl.P : n->tp->t.P;
     const size_t need = (size_t)P.n_pre * P.cap;
     if (needed) *needed = need;
     if (cap_elems < need) return fail(RS_ECAPACITY, "row buffers need %zu elements", need);
-    return rs_topo_get_rows(n->tp, len, ind, w);
+    return proj == 1 ? rs_topo_lat_get_rows(n->tp, len, ind, w) : rs_topo_get_rows(n->tp, len, ind, w);
   }
   if (!n->ep) return fail(RS_ESTATE, "the network is not built");
   const int role = n->proj_map[proj];

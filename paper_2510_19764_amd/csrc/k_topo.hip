@@ -11,6 +11,7 @@
 //                     remaining candidates in ascending target order and forms
 //                     synapses with the distance-dependent probability while
 //                     the row has room.  All bits end cleared.
+#include <algorithm>
 #include <mutex>
 
 #include "rs_compact.hpp"
@@ -206,6 +207,55 @@ __global__ void __launch_bounds__(WAVE) k_topo_rewire_fused(uint64_t seed, TopoD
   if (ballot(earlier)) return;  // another wave owns the row
   const int kr = wave_sum_i(cnt);
   topo_rewire_row(seed, t, step, r, kr, smem + (((size_t)na * 4 + 15) & ~(size_t)15));
+}
+
+// Both projections of a map with a lateral projection in one launch: waves
+// below a.n_attempts rewire projection a exactly as k_topo_rewire_fused
+// does, the rest projection b.
+__device__ __forceinline__ void rewire_attempt(uint64_t seed, const TopoDev& t, uint64_t step, int at) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  int* rows = (int*)smem;  // [n_attempts]
+  const int lane = lane_id(), na = t.n_attempts;
+  for (int i = lane; i < na; i += WAVE)
+    rows[i] = (int)below(draw_u32(seed, TAG_TP_ROW, t.P.proj_id, step, (uint64_t)i, 0, 0), (uint32_t)t.P.n_pre);
+  __syncthreads();
+  const int r = rows[at];
+  bool earlier = false;
+  int cnt = 0;
+  for (int i = lane; i < na; i += WAVE)
+    if (rows[i] == r) {
+      ++cnt;
+      earlier |= i < at;
+    }
+  if (ballot(earlier)) return;  // another wave owns the row
+  const int kr = wave_sum_i(cnt);
+  topo_rewire_row(seed, t, step, r, kr, smem + (((size_t)na * 4 + 15) & ~(size_t)15));
+}
+__global__ void __launch_bounds__(WAVE) k_topo_rewire_fused_pair(uint64_t seed, TopoDev a, TopoDev b,
+                                                                 uint64_t step) {
+  if (step == STEP_FROM_DEVICE) step = *a.step_dev;
+  // one inlined body per projection, each reading its own kernel argument
+  if ((int)blockIdx.x < a.n_attempts) rewire_attempt(seed, a, step, (int)blockIdx.x);
+  else rewire_attempt(seed, b, step, (int)blockIdx.x - a.n_attempts);
+}
+
+static size_t fused_lds(const TopoDev& t) {
+  return (((size_t)t.n_attempts * 4 + 15) & ~(size_t)15) + (size_t)t.P.words * 4 + (size_t)t.n_attempts * 4 +
+         (size_t)t.P.cap * 9 + 16;
+}
+
+void launch_topo_rewire_pair(hipStream_t s, uint64_t seed, const TopoDev& a, const TopoDev& b, uint64_t step) {
+  const bool fa = a.n_attempts > 0 && a.n_attempts <= TOPO_FUSED_MAX;
+  const bool fb = b.n_attempts > 0 && b.n_attempts <= TOPO_FUSED_MAX;
+  if (!fa || !fb) {
+    launch_topo_rewire(s, seed, a, step);
+    launch_topo_rewire(s, seed, b, step);
+    return;
+  }
+  topo_rewire_attrs();
+  const size_t lds = std::max(fused_lds(a), fused_lds(b));
+  hipLaunchKernelGGL(k_topo_rewire_fused_pair, dim3(a.n_attempts + b.n_attempts), dim3(WAVE), lds, s, seed, a, b,
+                     step);
 }
 
 void topo_rewire_attrs() {

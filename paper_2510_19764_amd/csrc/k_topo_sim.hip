@@ -131,10 +131,10 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
   }
   const int words = (N + 31) / 32;  // <= TS_NT
   uint32_t zw = tid < words ? sd.zin[tid] : 0u;  // spikes drawn at the step before t0
-  const int L = sd.L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
+  const int L = sd.L, Ls = sd.stim_L, cap = P.cap, ngrp = (N + 7) / 8;  // ngrp <= TS_NT / 2
   if (tid < 3) {  // stimulus position of t0's epoch
     const uint32_t u = draw_u32(seed, TAG_STIM, 0, t0 / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
-    s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
+    s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)Ls) : (int)(u & 1u);
   }
   if (tid == 0) {
     s_npre[0] = 0;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
             const int i = 8 * c + b;
             thr[b] = 0;  // channels beyond the sheet never fire
             if (i < N) {
-              const int dxs = axis_dist(L, i % L, cx), dys = axis_dist(L, i / L, cy);
+              const int dxs = axis_dist(Ls, (i % L) % Ls, cx), dys = axis_dist(Ls, (i / L) % Ls, cy);
               const int d2 = sd.stim_kind ? (orient ? dys * dys : dxs * dxs) : dxs * dxs + dys * dys;
               thr[b] = sd.T_in[d2];
             }
@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(TS_NT) k_topo_sim(uint64_t seed, ProjDev P, To
     // stimulus position of the next step's epoch
     if (tid < 3 && !last && (t + 1) % (uint64_t)sd.stim_steps == 0) {
       const uint32_t u = draw_u32(seed, TAG_STIM, 0, (t + 1) / (uint64_t)sd.stim_steps, (uint64_t)tid, 0, 0);
-      s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)L) : (int)(u & 1u);
+      s_stim[tid] = tid < 2 ? (int)below(u, (uint32_t)Ls) : (int)(u & 1u);
     }
     __syncthreads();
     if (tm) phase_mark(tk[2], tprev);

@@ -201,10 +201,13 @@ struct TopoDev {
 // device memory (launches recorded once in a graph and replayed).
 constexpr uint64_t STEP_FROM_DEVICE = ~0ull;
 void launch_topo_rewire(hipStream_t s, uint64_t seed, const TopoDev& t, uint64_t step);
+// Two projections' rewires (the same step), in one launch where both fit it.
+void launch_topo_rewire_pair(hipStream_t s, uint64_t seed, const TopoDev& a, const TopoDev& b, uint64_t step);
 
 // Topographic-map simulation state and constants (model of Tab. B, D-F).
 struct TopoSimDev {
   int L, N, ref_steps, stim_steps, stim_kind, stdp;
+  int stim_L;             // side of the square the stimulus is replicated over (L: one square)
   float V_rest, E_exc, V_th, V_reset, R, em, es, dx, dy, inv_dx, A_plus, A_minus, g_max;
   const uint64_t* T_in;   // [2*(L/2)^2 + 1] input Bernoulli threshold by squared stimulus distance
   float *V, *g, *y, *x;   // [N]
@@ -216,6 +219,16 @@ struct TopoSimDev {
   int* col_dirty;         // [1]
   uint64_t* step_dev;     // [1] step count: read for t0 == STEP_FROM_DEVICE, written at the end
   unsigned long long* ticks;  // [TOPO_PHASES] wall-clock ticks per phase, or null (timers off)
+  // lateral projection (target -> target), tiled kernel only
+  float* xl;                    // [N] lateral pre trace
+  int *col_len_l, *col_ent_l;   // its column view, [N], [N][col_cap]
+  int* col_dirty_l;             // [1]
+  // tiled kernel: second buffer of the per-step exchange (the first is zin,
+  // zout, x, xl), the step barrier's per-tile flags and the barrier-timeout flag
+  uint32_t *zin_b, *zout_b;     // [ceil(N/32)]
+  float *x_b, *xl_b;            // [N]
+  unsigned long long* bar;      // [TOPO_TILES_MAX * 16]: tile g's count at bar[16 g]
+  int* err;                     // [1]
 };
 // Phases of the simulation's timers: delivery with the source draws, neuron
 // update, potentiation, launch prologue (state loads and any column rebuild).
@@ -224,6 +237,17 @@ bool topo_sim_fits(int N);
 size_t topo_sim_lds_bytes(int N);
 void launch_topo_sim(hipStream_t s, uint64_t seed, const ProjDev& P, const TopoSimDev& sd, uint64_t t0,
                      int n_steps);
+// Tiled simulation: one workgroup per TOPO_TILE targets, a device-wide step
+// barrier; PL.n_pre == 0 means no lateral projection.
+constexpr int TOPO_TILE = 256;
+constexpr int TOPO_TILES_MAX_N = 16384;
+constexpr int TOPO_TILES_MAX = TOPO_TILES_MAX_N / TOPO_TILE;  // 64: one polling lane per tile
+size_t topo_tiles_lds_bytes(int N, bool lateral);
+int topo_tiles_grid(int N);
+// Workgroups of the tiled kernel the device keeps resident at once (0 on error).
+int topo_tiles_resident(int N, bool lateral);
+void launch_topo_tiles(hipStream_t s, uint64_t seed, const ProjDev& P, const ProjDev& PL, const TopoSimDev& sd,
+                       uint64_t t0, int n_steps);
 // Set the kernels' launch attributes ahead of a stream capture (idempotent).
 void topo_sim_attrs();
 void topo_rewire_attrs();

@@ -99,6 +99,45 @@ def test_topomap_composed_equals_preset():
     b.close()
 
 
+def test_topomap_with_lateral_composed_equals_preset():
+    """A map with a lateral projection (target sheet onto itself, Tab. G lateral
+    formation rule) built from descriptors equals rs_topo_add_lateral's, bit for
+    bit, on the tiled kernel with the input replicated in 16 x 16 squares."""
+    cfg = rb.TopoConfig(L=32, cap=24, n_attempts=40, proj_id=0, g_theta=0.25, g_new=0.5, g_init=0.5, seed=4)
+    lcfg = rb.TopoConfig(L=32, cap=16, n_attempts=40, proj_id=1, p_form=1.0, sigma_form=1.0, g_theta=0.25,
+                         g_new=0.5, g_init=0.5, seed=4)
+    model = rb.TopoModel(f_peak=600.0, g_max=0.5, A_plus=0.05, A_minus=0.02, stim_tile=16)
+    net = rb.ComposedNet(seed=cfg.seed, allocator=True)
+    src = net.add_pop(rb.POP_POISSON_SHEET, cfg.L * cfg.L, L=cfg.L, model=model)
+    tgt = net.add_pop(rb.POP_COND_LIF_SHEET, cfg.L * cfg.L, L=cfg.L, model=model)
+    common = dict(init=rb.INIT_GAUSS_TORUS, learn=rb.LEARN_STDP, rewire=rb.REWIRE_TOPO,
+                  update_interval=model.rewire_steps)
+    net.add_proj(src, tgt, p_form=cfg.p_form, sigma_form=cfg.sigma_form, g_init=cfg.g_init, cap=cfg.cap,
+                 n_attempts=cfg.n_attempts, g_theta=cfg.g_theta, p_elim_dep=cfg.p_elim_dep,
+                 p_elim_pot=cfg.p_elim_pot, g_new=cfg.g_new, **common)
+    net.add_proj(tgt, tgt, p_form=lcfg.p_form, sigma_form=lcfg.sigma_form, g_init=lcfg.g_init, cap=lcfg.cap,
+                 n_attempts=lcfg.n_attempts, g_theta=lcfg.g_theta, p_elim_dep=lcfg.p_elim_dep,
+                 p_elim_pot=lcfg.p_elim_pot, g_new=lcfg.g_new, **common)
+    net.build()
+    a = net.topo(cfg, lcfg)
+    b = rb.TopoNet(cfg)
+    b.add_lateral(lcfg)
+    b.sim_init(model)
+    net.step(700)
+    b.run(700)
+    for var in (rb.TV_V, rb.TV_G, rb.TV_Y, rb.TV_X, rb.TV_XLAT, rb.TV_REF, rb.TV_COUNT, rb.TV_ZIN, rb.TV_ZOUT,
+                rb.TV_STEP):
+        assert np.array_equal(a.sim_get(var), b.sim_get(var)), var
+    for lateral in (False, True):
+        for x, y in zip(a.get_rows(lateral=lateral), b.get_rows(lateral=lateral)):
+            assert np.array_equal(x, y)
+    assert a.sim_get(rb.TV_COUNT).sum() > 0
+    st = net.rewire(1)  # the lateral projection through the generic call
+    assert st.attempts == lcfg.n_attempts
+    net.close()
+    b.close()
+
+
 def test_unsupported_compositions_are_refused():
     cfg = classifier_cfg()
     net = rb.ComposedNet(seed=1, allocator=False)

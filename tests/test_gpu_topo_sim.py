@@ -269,9 +269,15 @@ def test_topo_sim_long_run_spike_counts(name):
 
 
 def test_topo_sim_errors():
+    # maps above 64 x 64 run on the tiled kernel only
     big = rb.TopoNet(rb.TopoConfig(L=72, cap=8, n_attempts=10, seed=1))
+    big.sim_kernel(rb.TOPO_KERNEL_ONE_WG)
     with pytest.raises(RuntimeError, match="4096"):
         big.sim_init(rb.TopoModel())
+    big.sim_kernel(rb.TOPO_KERNEL_AUTO)
+    big.sim_init(rb.TopoModel())
+    big.run(20)
+    assert int(big.sim_get(rb.TV_STEP)[0]) == 20
     t = rb.TopoNet(rb.TopoConfig(L=8, cap=8, n_attempts=10, seed=1))
     with pytest.raises(RuntimeError, match="sim_init"):
         t.run(10)
