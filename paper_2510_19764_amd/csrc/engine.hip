@@ -336,15 +336,16 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   TRY(ar.alloc(&n->Y, B * K));
   TRY(ar.alloc(&n->xbar, NI * B));
   TRY(ar.alloc(&n->zbar, NR * B));
-  // default block length: 20 steps, the target-major e-prop kernel's launch;
-  // batches the narrow kernel serves (B % 4 != 0) take a whole update
-  // interval of up to 32 steps, one block per interval
+  // default block length: the e-prop kernel's launch (for batches of 32 and
+  // more, the update interval in equal blocks of at most 32 steps); batches
+  // the narrow kernel serves (B % 4 != 0) take a whole update interval of up
+  // to 32 steps, one block per interval
   if (prm->trace_block)
     n->K = (int)prm->trace_block;
   else if (B % 4 != 0 && prm->update_interval >= 1 && prm->update_interval <= 32)
     n->K = (int)prm->update_interval;
   else
-    n->K = 20;
+    n->K = eprop_default_block((int)B, prm->update_interval);
   {
     const uint32_t U = prm->update_interval, Kb = (uint32_t)n->K;
     n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>((U + Kb - 1) / Kb + 1, 2), RING_MAX) : 2;
@@ -398,6 +399,8 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   TRY(ar.alloc(&n->cv.cnt, NR * COL_GROUPS_MAX));
   TRY(ar.alloc(&n->cv.off, NR * COL_GROUPS_MAX + 1));
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
+  n->cv.n_col = (int)((size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap);
+  if (B > 128 && B % 4 == 0) TRY(ar.alloc(&n->cv.gpart, (size_t)((B + 127) / 128) * n->cv.n_col));
   TRY(ar.alloc(&n->rw_stats, 4));
   TRY(ar.alloc(&n->zcount, (size_t)B * NR));
 
@@ -579,6 +582,7 @@ EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
   a.slot0 = h * n->K; a.nsteps = nsteps; a.nslot = n->nslot;
   a.Gout = n->Gout; a.Gb = n->Gb;
   a.col_off = n->cv.off; a.col = n->cv.col;
+  a.gpart = n->cv.gpart; a.n_col = n->cv.n_col;
   return a;
 }
 
@@ -925,6 +929,7 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   o->device_bytes = n->arena.bytes;
   o->eliminated = (uint64_t)r[0];
   o->formed = (uint64_t)r[1];
+  o->trace_block = (uint32_t)n->K;
   return RS_OK;
 }
 

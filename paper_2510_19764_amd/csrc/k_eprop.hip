@@ -8,6 +8,8 @@
 //   ([slot][B], [neuron][B]) so a wave reads consecutive instances.
 // k_col_*: the column view (synapses grouped by target) the target-major
 //   kernel walks, rebuilt by a counting sort whenever rows change.
+#include <mutex>
+
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -211,7 +213,7 @@ __host__ __device__ inline int readout_groups(int n_rec, int nw) {
 // XCDs in turn, so an XCD only gathers the presynaptic traces of one group of
 // rows, which fits its L2.  Every lane holds four consecutive instances,
 // so one wave covers 256 instances of a synapse with 16-byte accesses; wave w
-// takes synapses w, w + 4, ... of the list.  psi_j and L_j of the block's
+// takes synapses w, w + WL_NW, ... of the list.  psi_j and L_j of the block's
 // steps for the current 256-instance chunk are staged once in LDS (40 KB) and
 // shared by the workgroup's waves, so a synapse step costs one gathered
 // presynaptic trace and six float operations per instance (ALIF):
@@ -277,11 +279,16 @@ __device__ __forceinline__ void syn_store(const EpropArgs& a, const SynIn<IPL>& 
 
 constexpr int WL_CH = 4 * WAVE;  // instances per LDS chunk
 constexpr int WL_IPL = 4;  // instances per lane
+// Waves per workgroup.  The 40 KB of staged psi/L are shared by the
+// workgroup's waves: with 8 waves, three workgroups (24 waves) fit a CU's
+// 160 KB of LDS next to a forward workgroup of the next block, where four
+// 4-wave workgroups would leave it no room and lose one of the four.
+constexpr int WL_NW = 8;
 
-// IPL = 4 instances per lane: a workgroup's 4 waves share a chunk of 256
-// instances and wave w works on synapses w, w + 4, ...
+// IPL = 4 instances per lane: a workgroup's WL_NW waves share a chunk of 256
+// instances and wave w works on synapses w, w + WL_NW, ...
 template <bool ALIF, int IPL>
-__global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
+__global__ void __launch_bounds__(WL_NW * WAVE) k_eprop_wl(EpropArgs a) {
   typedef typename VecT<IPL>::type V;
   typedef unsigned U __attribute__((ext_vector_type(IPL)));
   static_assert(IPL == 4, "one wave covers a 256-instance chunk");
@@ -317,7 +324,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
     {
       const auto rp = buf_rsrc(a.psiT + ring(a, j, 0), blk_bytes);
       const auto rl = buf_rsrc(a.LT + ring(a, j, 0), blk_bytes);
-      for (int t = sub; t < COL_TB; t += 4) {
+      for (int t = sub; t < COL_TB; t += WL_NW) {
         s_psi[t][lv] = t < T ? buf_ldv<IPL>(rp, off, st_off(t)) : zero;
         s_L[t][lv] = act && t < T ? buf_ldv<IPL>(rl, off, st_off(t)) : zero;
       }
@@ -374,7 +381,7 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
       };
       // Each synapse's inputs are loaded one synapse ahead, alternating
       // between two register sets: while the wave computes synapse k, the
-      // loads of k + 4 are in flight, and the gradient is written back
+      // loads of k + WL_NW are in flight, and the gradient is written back
       // without being read again.  The loads are unconditional (past the
       // list the last entry is read again and not used), so the number of
       // memory operations in flight is the same on every path and the waits
@@ -382,15 +389,228 @@ __global__ void __launch_bounds__(256 * (4 / IPL)) k_eprop_wl(EpropArgs a) {
       SynIn<IPL> s0, s1;
       load(sub, s0);
 #pragma unroll 1
-      for (int k = sub; k < ns; k += 8) {
-        load(min(k + 4, ns - 1), s1);
+      for (int k = sub; k < ns; k += 2 * WL_NW) {
+        load(min(k + WL_NW, ns - 1), s1);
         run(s0);
-        if (k + 4 >= ns) break;
-        load(min(k + 8, ns - 1), s0);
+        if (k + WL_NW >= ns) break;
+        load(min(k + 2 * WL_NW, ns - 1), s0);
         run(s1);
       }
     }
   }
+}
+
+// Transfer-coefficient form of the same block (eq. eprop_elig_1/2,
+// eprop_elig_lif), one lane per instance.  Within a block the recursions
+//   e_t = psi_t (p_t - beta eps_{t-1}),  eps_t = e_t + rho eps_{t-1},
+//   ebar_t = alpha ebar_{t-1} + e_t,     g += L_t ebar_t,
+//   p_{t+1} = alpha p_t + z_t
+// are linear in a synapse's start state (p_0, eps_{-1}, ebar_{-1}) and its
+// presynaptic spikes z_t, with coefficients that depend only on the target's
+// psi_t and L_t.  A workgroup computes them once for its target and 128
+// instances by the adjoint recursion backwards over the block (one wave each
+// for the gradient, ebar at the block end and eps at the block end; for eps
+// the decay product is carried as 1 - D, so the slow decay keeps full
+// precision) into LDS, and then a synapse step costs one spike conversion and
+// three fused multiply-adds per instance.  The results equal the step-by-step
+// recursion up to float rounding.
+//
+// Workgroup n_ro + k owns target j = k / n_ch and instances 128 c .. 128 c +
+// 127 (two per lane), c = k % n_ch: with two chunks the XCDs of one parity
+// serve one chunk, so the presynaptic traces an XCD gathers are half of all of
+// them.  Its TC_NW waves take the
+// target's synapses in turn, each with the inputs of its next two synapses
+// in flight.  With more than one chunk each chunk writes its part of a synapse's
+// gradient by list position, and k_gpart_sum adds the parts to G in chunk
+// order, so the sum does not depend on scheduling.
+constexpr int TC_NW = 8;
+constexpr int TC_IPL = 2;                 // instances per lane
+constexpr int TC_CH = TC_IPL * WAVE;      // instances per chunk
+constexpr int TC_TB = 32;                 // steps per launch: one 32-bit spike mask
+constexpr int TC_MIN_B = 32;  // below, most lanes would idle: the 4-instances-per-lane kernel serves
+typedef float tcv __attribute__((ext_vector_type(2)));
+typedef unsigned tcu __attribute__((ext_vector_type(2)));
+// LDS of a launch of T steps: the coefficients of z_t for the three outputs
+// (the first two hold L and psi while the coefficients are computed), then
+// those of the start state.
+__host__ __device__ inline size_t tc_lds_bytes(int T, bool alif) {
+  return ((size_t)(alif ? 3 : 2) * T + 8) * TC_CH * sizeof(float);
+}
+template <bool ALIF>
+__global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int lane = lane_id(), wv = wave_id();
+  const int n_ro = readout_groups(a.n_rec, TC_NW);
+  if ((int)blockIdx.x < n_ro) {
+    readout_grad(a, blockIdx.x * TC_NW + wv, lane);
+    return;
+  }
+  const int B = a.B, T = a.nsteps;
+  float* c_g = (float*)smem;                    // [T][TC_CH] gradient; L while staging
+  float* c_b = c_g + T * TC_CH;                 // [T][TC_CH] ebar at the block end; psi while staging
+  float* c_e = c_b + T * TC_CH;                 // [T][TC_CH] eps at the block end (ALIF)
+  float* c_k = c_b + (ALIF ? 2 : 1) * T * TC_CH;  // [8][TC_CH] gradient: p0, eps, ebar; ebar: p0, eps, ebar; eps: p0, D
+  const int n_ch = (B + TC_CH - 1) / TC_CH;
+  const int k = blockIdx.x - n_ro;
+  const int j = k / n_ch, c = k - j * n_ch;
+  const int q0 = a.col_off[j * COL_GRP], q1 = a.col_off[(j + 1) * COL_GRP];
+  if (q1 <= q0) return;
+  const int b0 = c * TC_CH + TC_IPL * lane;  // this lane's first instance (B is a multiple of 4)
+  const bool act = b0 < B;
+  const int bi = act ? b0 : B - TC_IPL;      // idle lanes compute on valid instances and store nothing
+  const float alpha = a.alpha, beta = a.beta, omr = a.one_m_rho;
+
+  // ---- L and psi of the block for target j and the chunk's instances
+  for (int t = wv; t < T; t += TC_NW)
+    for (int e = lane; e < TC_CH; e += WAVE) {
+      const int be = min(c * TC_CH + e, B - 1);
+      c_g[t * TC_CH + e] = a.LT[ring(a, j, t) + be];
+      c_b[t * TC_CH + e] = a.psiT[ring(a, j, t) + be];
+    }
+  __syncthreads();
+  // ---- coefficients, one instance e per lane of waves 0 and 1: the adjoints
+  // after step t, A = d out / d eps_t and Bv = d out / d ebar_t, backwards
+  // over the block, and P = sum over t' >= t of alpha^(t'-t) d out / d p_t'.
+  // The coefficient of z_t is P_{t+1}; slot t of the arrays is written after
+  // its L and psi are read, by the same lane.
+  if (wv < TC_IPL) {
+    const int e = wv * WAVE + lane;
+    float Ag = 0.f, Bg = 0.f, Pg = 0.f;  // gradient
+    float Ab = 0.f, Bb = 0.f, Pb = 0.f;  // ebar at the block end
+    float De = 0.f, Pe = 0.f;            // eps at the block end: A = 1 - De
+    for (int t = T - 1; t >= 0; --t) {
+      const float l = c_g[t * TC_CH + e], p = c_b[t * TC_CH + e];
+      c_g[t * TC_CH + e] = Pg;
+      c_b[t * TC_CH + e] = Pb;
+      if (ALIF) c_e[t * TC_CH + e] = Pe;
+      Bg = fmaf(alpha, Bg, l);
+      Bb = t == T - 1 ? 1.f : alpha * Bb;
+      if (ALIF) {
+        const float del = fmaf(beta, p, omr);  // 1 - (rho - beta psi_t)
+        const float pb = p * beta;
+        Pg = fmaf(alpha, Pg, p * (Ag + Bg));
+        Pb = fmaf(alpha, Pb, p * (Ab + Bb));
+        Pe = fmaf(alpha, Pe, p * (1.f - De));
+        Ag = fmaf(-pb, Bg, fmaf(-Ag, del, Ag));
+        Ab = fmaf(-pb, Bb, fmaf(-Ab, del, Ab));
+        De = fmaf(-De, del, De + del);
+      } else {
+        Pg = fmaf(alpha, Pg, p * Bg);
+        Pb = fmaf(alpha, Pb, p * Bb);
+      }
+    }
+    c_k[0 * TC_CH + e] = Pg;
+    c_k[1 * TC_CH + e] = Ag;
+    c_k[2 * TC_CH + e] = alpha * Bg;
+    c_k[3 * TC_CH + e] = Pb;
+    c_k[4 * TC_CH + e] = Ab;
+    c_k[5 * TC_CH + e] = alpha * Bb;
+    c_k[6 * TC_CH + e] = Pe;
+    c_k[7 * TC_CH + e] = De;
+  }
+  __syncthreads();
+  auto kv = [&](int r) { return *(const tcv*)(c_k + r * TC_CH + TC_IPL * lane); };
+  const tcv kg0 = kv(0), kg1 = kv(1), kg2 = kv(2), kb0 = kv(3), kb1 = kv(4), kb2 = kv(5);
+  const tcv ke0 = ALIF ? kv(6) : (tcv)0.f, ke1 = ALIF ? kv(7) : (tcv)0.f;
+  const tcv* cgv = (const tcv*)c_g + lane;  // step t at [t * WAVE]
+  const tcv* cbv = (const tcv*)c_b + lane;
+  const tcv* cev = (const tcv*)c_e + lane;
+
+  // ---- the target's synapses: wave wv takes list entries q0 + wv, q0 + wv + TC_NW, ...
+  // Records are addressed from a wave-uniform base plus this lane's offset.
+  struct In {
+    tcv eb, ep, pr;
+    tcu bits;
+    float g0;
+    int fin, slot, q;
+  };
+  // list entries of the wave's next 64 synapses, one per lane, read by
+  // readlane so that no load waits on another
+  int2 ents;
+  int base = 0;
+  auto load = [&](int n, In& s) {
+    const int r = __builtin_amdgcn_readlane(ents.x, n), slot = __builtin_amdgcn_readlane(ents.y, n);
+    s.fin = r < a.n_in;
+    s.slot = slot;
+    s.q = base + TC_NW * n;
+    const int i = s.fin ? r : r - a.n_in;
+    const int64_t rec = (int64_t)slot * B + bi;
+    s.eb = __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.ebar : a.rec.ebar) + rec));
+    s.ep = ALIF ? __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.eps : a.rec.eps) + rec)) : (tcv)0.f;
+    s.pr = *(const tcv*)((s.fin ? a.x0 : a.z0) + (int64_t)i * B + bi);
+    s.bits = *(const tcu*)((s.fin ? a.xbits : a.zbits) + (int64_t)i * B + bi);
+    s.g0 = n_ch == 1 ? (s.fin ? a.in.G : a.rec.G)[slot] : 0.f;
+  };
+  auto run = [&](const In& s) {
+    tcv pr = s.pr;
+    for (int t = 0; t < a.tofs; ++t) {
+      const tcv sp = {(float)((s.bits.x >> t) & 1u), (float)((s.bits.y >> t) & 1u)};
+      pr = __builtin_elementwise_fma((tcv)alpha, pr, sp);
+    }
+    tcv g = __builtin_elementwise_fma(kg0, pr, ALIF ? __builtin_elementwise_fma(kg1, s.ep, kg2 * s.eb) : kg2 * s.eb);
+    tcv eb = __builtin_elementwise_fma(kb0, pr, ALIF ? __builtin_elementwise_fma(kb1, s.ep, kb2 * s.eb) : kb2 * s.eb);
+    tcv ep = ALIF ? __builtin_elementwise_fma(ke0, pr, __builtin_elementwise_fma(-ke1, s.ep, s.ep)) : (tcv)0.f;
+#pragma unroll
+    for (int t0 = 0; t0 < TC_TB; t0 += 4) {
+      if (t0 >= T) break;
+      __asm__ volatile("" ::: "memory");
+      const uint32_t sx = spikes4(s.bits.x, a.tofs + t0), sy = spikes4(s.bits.y, a.tofs + t0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (t0 + u >= T) break;
+        const tcv z = {(float)((sx >> (8 * u)) & 0xFFu), (float)((sy >> (8 * u)) & 0xFFu)};
+        const int w = (t0 + u) * WAVE;
+        g = __builtin_elementwise_fma(z, cgv[w], g);
+        eb = __builtin_elementwise_fma(z, cbv[w], eb);
+        if (ALIF) ep = __builtin_elementwise_fma(z, cev[w], ep);
+      }
+    }
+    const int fin = __builtin_amdgcn_readfirstlane(s.fin), slot = __builtin_amdgcn_readfirstlane(s.slot);
+    const int64_t rec = (int64_t)slot * B + bi;
+    if (act) {
+      __builtin_nontemporal_store(eb, (tcv*)((fin ? a.in.ebar : a.rec.ebar) + rec));
+      if (ALIF) __builtin_nontemporal_store(ep, (tcv*)((fin ? a.in.eps : a.rec.eps) + rec));
+    }
+    const float part = wave_sum(act ? g.x + g.y : 0.f);
+    if (lane == 0) {
+      if (n_ch == 1) (fin ? a.in.G : a.rec.G)[slot] = s.g0 + part;
+      else a.gpart[(int64_t)c * a.n_col + s.q] = part;  // this chunk's part, summed into G by k_gpart_sum
+    }
+  };
+  // three register sets in turn: while a synapse runs, the next two load
+  // (past the batch the last entry is loaded again and not used)
+  In s0, s1, s2;
+  for (base = q0 + wv; base < q1; base += TC_NW * WAVE) {
+    const int nb = min(WAVE, (q1 - 1 - base) / TC_NW + 1);  // this wave's synapses in the batch
+    ents = a.col[base + TC_NW * min(lane, nb - 1)];
+    load(0, s0);
+    load(min(1, nb - 1), s1);
+#pragma unroll 1
+    for (int i = 0;;) {
+      load(min(i + 2, nb - 1), s2);
+      run(s0);
+      if (++i >= nb) break;
+      load(min(i + 2, nb - 1), s0);
+      run(s1);
+      if (++i >= nb) break;
+      load(min(i + 2, nb - 1), s1);
+      run(s2);
+      if (++i >= nb) break;
+    }
+  }
+}
+
+// With more than one chunk: add the chunks' gradient parts of every listed
+// synapse to its G, in chunk order (the launch after the e-prop launch; the
+// kernel boundary orders the parts' stores before these loads).
+__global__ void __launch_bounds__(256) k_gpart_sum(EpropArgs a, int n_ch) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.col_off[a.n_rec * COL_GRP]) return;
+  float sum = a.gpart[q];
+  for (int cc = 1; cc < n_ch; ++cc) sum += a.gpart[(int64_t)cc * a.n_col + q];
+  const int2 e = a.col[q];
+  float* G = e.x < a.n_in ? a.in.G : a.rec.G;
+  G[e.y] += sum;
 }
 
 // Column view of both projections for k_eprop_wl: entries
@@ -615,10 +835,41 @@ void launch_eprop_narrow_multi(hipStream_t s, const EpropArgs* A, const int4* wo
   }
 }
 
+static void tc_attrs() {
+  static std::once_flag once;
+  std::call_once(once, [] {
+    allow_dynamic_lds((const void*)k_eprop_tc<true>, (int)tc_lds_bytes(TC_TB, true) + 1024);
+    allow_dynamic_lds((const void*)k_eprop_tc<false>, (int)tc_lds_bytes(TC_TB, false) + 1024);
+  });
+}
+
+int eprop_default_block(int B, uint32_t update_interval) {
+  if (B % 4 != 0 || B < TC_MIN_B) return COL_TB;
+  // the update interval in equal blocks of at most TC_TB steps: each launch
+  // streams every synapse's eps/ebar once, so fewer, longer blocks move fewer bytes
+  if (update_interval == 0) return TC_TB;
+  const uint32_t n = (update_interval + TC_TB - 1) / TC_TB;
+  return (int)((update_interval + n - 1) / n);
+}
+
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;
-  if (a.B % 4 == 0 && a.col && a.col_off) {
-    const int nw = 4;
+  if (a.B % 4 == 0 && a.col && a.col_off && a.B >= TC_MIN_B) {
+    tc_attrs();
+    const int n_ch = (a.B + TC_CH - 1) / TC_CH;
+    const int blocks = readout_groups(a.n_rec, TC_NW) + a.n_rec * n_ch;
+    for (int t0 = 0; t0 < a.nsteps; t0 += TC_TB) {  // blocks longer than TC_TB in parts
+      EpropArgs p = a;
+      p.slot0 = a.slot0 + t0;
+      p.tofs = a.tofs + t0;
+      p.nsteps = min(TC_TB, a.nsteps - t0);
+      const size_t lds = tc_lds_bytes(p.nsteps, a.alif);
+      if (a.alif) hipLaunchKernelGGL((k_eprop_tc<true>), dim3(blocks), dim3(TC_NW * WAVE), lds, s, p);
+      else hipLaunchKernelGGL((k_eprop_tc<false>), dim3(blocks), dim3(TC_NW * WAVE), lds, s, p);
+      if (n_ch > 1) hipLaunchKernelGGL(k_gpart_sum, dim3((a.n_col + 255) / 256), dim3(256), 0, s, p, n_ch);
+    }
+  } else if (a.B % 4 == 0 && a.col && a.col_off) {
+    const int nw = WL_NW;
     const int blocks = readout_groups(a.n_rec, nw) + a.n_rec * COL_GRP;
     for (int t0 = 0; t0 < a.nsteps; t0 += COL_TB) {  // blocks longer than COL_TB in parts
       EpropArgs p = a;

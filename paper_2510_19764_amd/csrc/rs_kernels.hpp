@@ -32,6 +32,10 @@ struct ColumnView {
   int* cnt;          // [n_rec*COL_GROUPS_MAX] counts, then the fill cursor
   int* off;          // [n_rec*COL_GROUPS_MAX + 1]
   int2* col;         // [n_in*cap_in + n_rec*cap_rec]
+  // the transfer-coefficient e-prop kernel with more than 128 instances:
+  // per-chunk gradient partials by list position
+  float* gpart;      // [ceil(B/128)][n_in*cap_in + n_rec*cap_rec]
+  int n_col;         // n_in*cap_in + n_rec*cap_rec
 };
 
 // ---------------------------------------------------------------- build
@@ -132,8 +136,11 @@ struct EpropArgs {
   int slot0, nsteps, nslot;
   float* Gout; float* Gb;
   const int* col_off; const int2* col;   // ColumnView (B % 4 == 0)
+  float* gpart; int n_col;               // ColumnView's gradient partials (B > 128)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+// Default steps per eligibility block (one e-prop launch) for batch B.
+int eprop_default_block(int B, uint32_t update_interval);
 // Narrow e-prop kernel over several networks, persistent over a work list of
 // row tiles (network, first row, rows; rows >= n_in + n_rec are readout
 // chunks): `grid` workgroups (0: one per work item), `tpr` threads per row (64

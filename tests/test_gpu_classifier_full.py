@@ -1,6 +1,6 @@
 """Parity at the full sparse-classifier size (700 inputs, 1024 ALIF, 20
 readouts, 10% connectivity, batch 256): 120 steps in the schedule the
-benchmark times (20-step blocks through the two-stream hand-off ring, the
+benchmark times (25-step blocks through the two-stream hand-off ring, the
 automatic Adam update and both DEEP R rewires inside the call, the column view
 rebuilt beside the next forward block) compared element by element with the
 oracle; single full-size steps; DEEP R bit-exact on the full rows; invariants
@@ -134,13 +134,13 @@ def test_full_batch_training_deterministic():
 
 def test_full_size_interval_in_bench_schedule():
     """From the update boundary at step 100, one call of 100 steps with
-    RS_LEARN | RS_AUTO_UPDATE and the default block length (five 20-step
+    RS_LEARN | RS_AUTO_UPDATE and the default block length (four 25-step
     blocks through the two-stream ring, the update and both rewires at step
     200, the column view rebuilt beside the next block), against the oracle's
     100 steps, Adam update and two rewires from the same snapshot: spike
     counts and the last block's raster exact, rows, bitfields and dormant
-    counts bit for bit, state and parameters within their bounds.  Then one
-    more 20-step block past the boundary from the GPU's updated state."""
+    counts bit for bit, state and parameters within their bounds.  Then 20
+    more steps past the boundary from the GPU's updated state."""
     cfg = classifier_cfg()
     labels, raster = wl.ShdLike().batch(seed=1, batch_index=0, B=cfg.batch)
     net = rb.EpropNet(cfg)

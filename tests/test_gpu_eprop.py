@@ -240,15 +240,15 @@ def test_overlapped_training_matches_joined_calls():
     """A network large enough for the two-stream schedule, trained with
     automatic updates, DEEP R and resets in one call (forward blocks running
     ahead of e-prop, ring segments reused without events inside an interval)
-    ends bit-identical to the same steps in 20-step calls, each of which joins
-    both streams at its end."""
+    ends bit-identical to the same steps in calls of the default block length
+    (25 steps here), each of which joins both streams at its end."""
     cfg = make_cfg(300, 200, 5, 64, True, p=0.9, seed=12, U=100, T=200, lr=0.05)
     rates = wl.poisson_rates(cfg.seed, cfg.n_in, 60.0)
     raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
     labels = (np.arange(cfg.batch) % cfg.n_out).astype(np.int32)
     flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
     snaps, infos = [], []
-    for calls in ((240,), (20,) * 12):
+    for calls in ((240,), (25,) * 9 + (15,)):
         net = rb.EpropNet(cfg)
         net.set_input(*gpu_input(raster, labels))
         for n in calls:
@@ -326,9 +326,10 @@ def test_error_paths():
                                   "alif-b64-dense"])
 def test_trace_block_length_invariance(name):
     """Applying eligibility updates in blocks of K steps gives bit-identical
-    neuron state, traces and eps/ebar for every K, over uneven step calls.  The
-    gradient is summed per lane over a block's steps before the batch
-    reduction, so G may differ by float rounding only."""
+    neuron state and presynaptic traces for every K, over uneven step calls.
+    The eligibility kernel of batches of 32 and more applies a block through
+    coefficients of the block's steps, so eps, ebar and G depend on K by float
+    rounding only (relative 2e-6 of each array's largest value)."""
     base, rate = CASES[name]
     snaps = {}
     for K in (1, 3, 8, 16):
@@ -352,8 +353,8 @@ def test_trace_block_length_invariance(name):
             assert np.abs(s[k] - ref[k]).max() <= tol, (K, k)
         for tag in ("in", "rec"):
             for k in ref[tag]:
-                if k == "G":
-                    tol = 1e-6 * max(float(np.abs(ref[tag][k]).max()), 1e-30)
+                if k in ("G", "eps", "ebar"):
+                    tol = 2e-6 * max(float(np.abs(ref[tag][k]).max()), 1e-30)
                     assert np.abs(s[tag][k] - ref[tag][k]).max() <= tol, (K, tag, k)
                 else:
                     assert np.array_equal(s[tag][k], ref[tag][k]), (K, tag, k)
