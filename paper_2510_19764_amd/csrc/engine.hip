@@ -179,8 +179,9 @@ struct rs_eprop {
   // per segment: traces at the block start and the block's spike bits, [Q][n][B]
   float *x0T = nullptr, *z0T = nullptr;
   uint32_t *xbitsT = nullptr, *zbitsT = nullptr;
-  // the forward kernel's coalesced staging of one block, [tau][B][n]
-  uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [K][B][NR]; x0, z0, xbits, zbits [B][n]
+  // the forward kernel's coalesced staging of a block, one per ring segment,
+  // so that a block's transpose can run beside the next block's forward pass
+  uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [Q][K][B][NR]; x0, z0, xbits, zbits [Q][B][n]
   float *u_stg = nullptr;                             // readout drive [Q segments][K][B][n_out]
   int K = 8, Q = 2, nslot = 16;
   int blk_seg = 0, blk_n = 0, last_slot = 0;
@@ -188,10 +189,12 @@ struct rs_eprop {
   uint64_t blk_t0 = 0;
   bool blk_learn = false;
   hipStream_t side = nullptr;                         // e-prop / update / rewire stream
-  hipStream_t side2 = nullptr;                        // input-projection rewire, beside the recurrent one
+  // each block's hand-off transpose and readout, beside the next forward
+  // block; at updates the input-projection rewire, beside the recurrent one
+  hipStream_t side2 = nullptr;
   bool single = false;                                // small network: everything on the caller's stream
   bool auto_upd = false;                              // inside a step call with RS_AUTO_UPDATE
-  hipEvent_t ev_fwd = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
+  hipEvent_t ev_fwd = nullptr, ev_post = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
   hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
   bool ep_pending[RING_MAX] = {};  // an e-prop launch reading the segment may still run
   uint8_t* z = nullptr;
@@ -362,9 +365,9 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   TRY(ar.alloc(&n->deltaT, K * NS * B));
   {
     const size_t KB = (size_t)n->K * B;
-    TRY(ar.alloc(&n->stg[0], KB * NR));                   // psi
+    TRY(ar.alloc(&n->stg[0], QS * KB * NR));                   // psi
     const size_t dims[HANDOFF_ARRAYS] = {NR, NI, NR, NI, NR};  // psi, x0, z0, xbits, zbits
-    for (int q = 1; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], (size_t)B * dims[q]));
+    for (int q = 1; q < HANDOFF_ARRAYS; ++q) TRY(ar.alloc(&n->stg[q], QS * B * dims[q]));
     TRY(ar.alloc(&n->u_stg, QS * KB * K));
   }
   // A small network's kernels are short and latency-bound: overlapping its
@@ -383,6 +386,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   HIP_OK(hipEventCreateWithFlags(&n->ev_upd, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_rw, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_post, hipEventDisableTiming));
   for (int q = 0; q < n->Q; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_back, hipEventDisableTiming));
@@ -507,6 +511,13 @@ void order(hipEvent_t ev, hipStream_t from, hipStream_t to) {
   (void)hipStreamWaitEvent(to, ev, 0);
 }
 
+// Staging array q (psi, x0, z0, xbits, zbits) of ring segment h.
+uint32_t* stg_seg(const rs_eprop* n, int q, int h) {
+  const size_t B = n->B, NR = n->p.n_rec, NI = n->p.n_in;
+  const size_t per = q == 0 ? (size_t)n->K * B * NR : B * (q == 1 || q == 3 ? NI : NR);
+  return n->stg[q] + (size_t)h * per;
+}
+
 // Arguments of one block's launches: steps t0 .. t0 + nsteps - 1 (absolute
 // step numbers), ring segment h.  Shared by the one-network path and the
 // multi-network launches, so both compute the same thing.
@@ -518,8 +529,8 @@ FwdArgs block_fwd_args(const rs_eprop* n, int h, uint64_t t0, int nsteps) {
   f.alpha_f = (float)n->alpha;
   f.V = n->V; f.A = n->A;
   f.xbar = n->xbar; f.zbar = n->zbar;
-  f.psi = (float*)n->stg[0]; f.x0 = (float*)n->stg[1]; f.z0 = (float*)n->stg[2];
-  f.xbits = n->stg[3]; f.zbits = n->stg[4]; f.z = n->z;
+  f.psi = (float*)stg_seg(n, 0, h); f.x0 = (float*)stg_seg(n, 1, h); f.z0 = (float*)stg_seg(n, 2, h);
+  f.xbits = stg_seg(n, 3, h); f.zbits = stg_seg(n, 4, h); f.z = n->z;
   f.u = n->u_stg + (size_t)h * n->K * n->B * n->p.n_out;
   f.len_in = n->in.len; f.ind_in = n->in.ind; f.w_in = n->in.w; f.cap_in = n->in.cap;
   f.len_rec = n->rec.len; f.ind_rec = n->rec.ind; f.w_rec = n->rec.w; f.cap_rec = n->rec.cap;
@@ -546,7 +557,7 @@ HandoffArrays block_handoff_args(const rs_eprop* n, int h, int nsteps) {
                                    n->zbitsT + h * NR * B};
   const int dims[HANDOFF_ARRAYS] = {(int)NR, (int)NI, (int)NR, (int)NI, (int)NR};
   for (int q = 0; q < HANDOFF_ARRAYS; ++q) {
-    ho.src[q] = n->stg[q];
+    ho.src[q] = stg_seg(n, q, h);
     ho.dst[q] = dst[q];
     ho.n[q] = dims[q];
     ho.steps[q] = q == 0 ? nsteps : 1;  // psi per step into the ring, the rest once per block
@@ -588,12 +599,13 @@ EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
 
 // Run the open block (steps accumulated since the last flush): one forward
 // launch for all its steps on the caller's stream, writing ring segment
-// blk_seg, then the e-prop launch on the side stream.  The forward pass of
-// the next block (next segment) overlaps this e-prop launch; a segment is
-// reused only after the e-prop launch that read it has finished.
+// blk_seg; the block's hand-off transpose and readout on the second side
+// stream; then the e-prop launch on the side stream.  The forward pass of the
+// next block (next segment) overlaps both; a segment is reused only after
+// the e-prop launch that read it has finished.
 void flush_block(rs_eprop* n) {
   if (n->blk_n == 0) return;
-  hipStream_t s = n->stream, e = n->side;
+  hipStream_t s = n->stream, e = n->side, p = n->side2;
   const int h = n->blk_seg;
   if (n->ep_pending[h]) {
     (void)hipStreamWaitEvent(s, n->ev_ep[h], 0);
@@ -601,14 +613,18 @@ void flush_block(rs_eprop* n) {
   }
   n->timer.begin(s, 0);
   launch_fwd(s, block_fwd_args(n, h, n->blk_t0, n->blk_n));
-  launch_handoff_transpose(s, block_handoff_args(n, h, n->blk_n), n->B);
-  // readout state, softmax error and (when learning) the learning signal of
-  // the block, still on the forward stream: the e-prop stream, which carries
-  // the longer work, starts with the eligibility launch itself
-  launch_readout(s, block_readout_args(n, h, n->blk_n), n->blk_learn);
   n->timer.end(s);
+  // the transpose, readout state, softmax error and (when learning) the
+  // learning signal of the block, beside the next block's forward pass: they
+  // read this segment only, and the readouts of successive blocks stay in
+  // order on their stream
+  order(n->ev_fwd, s, p);
+  n->timer.begin(p, 0);
+  launch_handoff_transpose(p, block_handoff_args(n, h, n->blk_n), n->B);
+  launch_readout(p, block_readout_args(n, h, n->blk_n), n->blk_learn);
+  n->timer.end(p);
   n->last_slot = h * n->K + n->blk_n - 1;
-  order(n->ev_fwd, s, e);
+  order(n->ev_post, p, e);
   if (n->blk_learn) {
     n->timer.begin(e, 1);
     launch_eprop(e, block_eprop_args(n, h, n->blk_n));
@@ -961,7 +977,7 @@ void rs_eprop_destroy(rs_eprop* n) {
     if (n->side2) (void)hipStreamSynchronize(n->side2);
   }
   n->timer.destroy();
-  for (hipEvent_t ev : {n->ev_fwd, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
+  for (hipEvent_t ev : {n->ev_fwd, n->ev_post, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : n->ev_ep)
     if (ev) (void)hipEventDestroy(ev);

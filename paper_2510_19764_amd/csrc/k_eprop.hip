@@ -408,12 +408,14 @@ __global__ void __launch_bounds__(WL_NW * WAVE) k_eprop_wl(EpropArgs a) {
 // are linear in a synapse's start state (p_0, eps_{-1}, ebar_{-1}) and its
 // presynaptic spikes z_t, with coefficients that depend only on the target's
 // psi_t and L_t.  A workgroup computes them once for its target and 128
-// instances by the adjoint recursion backwards over the block (one wave each
-// for the gradient, ebar at the block end and eps at the block end; for eps
-// the decay product is carried as 1 - D, so the slow decay keeps full
-// precision) into LDS, and then a synapse step costs one spike conversion and
-// three fused multiply-adds per instance.  The results equal the step-by-step
-// recursion up to float rounding.
+// instances by the adjoint recursion backwards over the block (the gradient,
+// ebar at the block end and eps at the block end; for eps the decay product
+// is carried as 1 - D, so the slow decay keeps full precision) into LDS.  A
+// synapse then costs three multiply-adds per instance for its start state and
+// three adds per presynaptic spike of the block: the wave walks the spikes of
+// its lanes, lowest step first, for as many rounds as its busiest lane has
+// spikes, and lanes without a spike left read a row of zeros.  The results
+// equal the step-by-step recursion up to float rounding.
 //
 // Workgroup n_ro + k owns target j = k / n_ch and instances 128 c .. 128 c +
 // 127 (two per lane), c = k % n_ch: with two chunks the XCDs of one parity
@@ -426,15 +428,15 @@ __global__ void __launch_bounds__(WL_NW * WAVE) k_eprop_wl(EpropArgs a) {
 constexpr int TC_NW = 8;
 constexpr int TC_IPL = 2;                 // instances per lane
 constexpr int TC_CH = TC_IPL * WAVE;      // instances per chunk
-constexpr int TC_TB = 32;                 // steps per launch: one 32-bit spike mask
+constexpr int TC_TB = 31;                 // steps per launch: below the top bit of a 32-bit spike mask
 constexpr int TC_MIN_B = 32;  // below, most lanes would idle: the 4-instances-per-lane kernel serves
 typedef float tcv __attribute__((ext_vector_type(2)));
 typedef unsigned tcu __attribute__((ext_vector_type(2)));
-// LDS of a launch of T steps: the coefficients of z_t for the three outputs
-// (the first two hold L and psi while the coefficients are computed), then
-// those of the start state.
+// LDS of a launch of T steps: the coefficients of z_t for the three outputs,
+// T rows and a row of zeros each (the first two hold L and psi while the
+// coefficients are computed), then those of the start state.
 __host__ __device__ inline size_t tc_lds_bytes(int T, bool alif) {
-  return ((size_t)(alif ? 3 : 2) * T + 8) * TC_CH * sizeof(float);
+  return ((size_t)(alif ? 3 : 2) * (T + 1) + 8) * TC_CH * sizeof(float);
 }
 template <bool ALIF>
 __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
@@ -446,10 +448,13 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     return;
   }
   const int B = a.B, T = a.nsteps;
-  float* c_g = (float*)smem;                    // [T][TC_CH] gradient; L while staging
-  float* c_b = c_g + T * TC_CH;                 // [T][TC_CH] ebar at the block end; psi while staging
-  float* c_e = c_b + T * TC_CH;                 // [T][TC_CH] eps at the block end (ALIF)
-  float* c_k = c_b + (ALIF ? 2 : 1) * T * TC_CH;  // [8][TC_CH] gradient: p0, eps, ebar; ebar: p0, eps, ebar; eps: p0, D
+  // coefficients of z_t: step t's rows for the gradient (L while staging),
+  // ebar at the block end (psi while staging) and eps at the block end (ALIF)
+  // side by side, so one address serves all three; row T is zeros
+  constexpr int NA = ALIF ? 3 : 2;
+  float* c_z = (float*)smem;                    // [T + 1][NA][TC_CH]
+  float* c_k = c_z + (T + 1) * NA * TC_CH;      // [8][TC_CH] gradient: p0, eps, ebar; ebar: p0, eps, ebar; eps: p0, D
+  auto cz = [&](int t, int r, int e) -> float& { return c_z[(t * NA + r) * TC_CH + e]; };
   const int n_ch = (B + TC_CH - 1) / TC_CH;
   const int k = blockIdx.x - n_ro;
   const int j = k / n_ch, c = k - j * n_ch;
@@ -464,8 +469,8 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   for (int t = wv; t < T; t += TC_NW)
     for (int e = lane; e < TC_CH; e += WAVE) {
       const int be = min(c * TC_CH + e, B - 1);
-      c_g[t * TC_CH + e] = a.LT[ring(a, j, t) + be];
-      c_b[t * TC_CH + e] = a.psiT[ring(a, j, t) + be];
+      cz(t, 0, e) = a.LT[ring(a, j, t) + be];
+      cz(t, 1, e) = a.psiT[ring(a, j, t) + be];
     }
   __syncthreads();
   // ---- coefficients, one instance e per lane of waves 0 and 1: the adjoints
@@ -475,14 +480,15 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   // its L and psi are read, by the same lane.
   if (wv < TC_IPL) {
     const int e = wv * WAVE + lane;
+    for (int r = 0; r < NA; ++r) cz(T, r, e) = 0.f;  // read for lanes without a spike left
     float Ag = 0.f, Bg = 0.f, Pg = 0.f;  // gradient
     float Ab = 0.f, Bb = 0.f, Pb = 0.f;  // ebar at the block end
     float De = 0.f, Pe = 0.f;            // eps at the block end: A = 1 - De
     for (int t = T - 1; t >= 0; --t) {
-      const float l = c_g[t * TC_CH + e], p = c_b[t * TC_CH + e];
-      c_g[t * TC_CH + e] = Pg;
-      c_b[t * TC_CH + e] = Pb;
-      if (ALIF) c_e[t * TC_CH + e] = Pe;
+      const float l = cz(t, 0, e), p = cz(t, 1, e);
+      cz(t, 0, e) = Pg;
+      cz(t, 1, e) = Pb;
+      if (ALIF) cz(t, 2, e) = Pe;
       Bg = fmaf(alpha, Bg, l);
       Bb = t == T - 1 ? 1.f : alpha * Bb;
       if (ALIF) {
@@ -512,9 +518,8 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   auto kv = [&](int r) { return *(const tcv*)(c_k + r * TC_CH + TC_IPL * lane); };
   const tcv kg0 = kv(0), kg1 = kv(1), kg2 = kv(2), kb0 = kv(3), kb1 = kv(4), kb2 = kv(5);
   const tcv ke0 = ALIF ? kv(6) : (tcv)0.f, ke1 = ALIF ? kv(7) : (tcv)0.f;
-  const tcv* cgv = (const tcv*)c_g + lane;  // step t at [t * WAVE]
-  const tcv* cbv = (const tcv*)c_b + lane;
-  const tcv* cev = (const tcv*)c_e + lane;
+  const float* czl = c_z + TC_IPL * lane;  // this lane's instances of step t at [t * NA * TC_CH + r * TC_CH] (+1)
+  const uint32_t tmask = (1u << T) - 1u, sent = 1u << T;  // the launch's steps in the spike words; past them
 
   // ---- the target's synapses: wave wv takes list entries q0 + wv, q0 + wv + TC_NW, ...
   // Records are addressed from a wave-uniform base plus this lane's offset.
@@ -550,21 +555,22 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     tcv g = __builtin_elementwise_fma(kg0, pr, ALIF ? __builtin_elementwise_fma(kg1, s.ep, kg2 * s.eb) : kg2 * s.eb);
     tcv eb = __builtin_elementwise_fma(kb0, pr, ALIF ? __builtin_elementwise_fma(kb1, s.ep, kb2 * s.eb) : kb2 * s.eb);
     tcv ep = ALIF ? __builtin_elementwise_fma(ke0, pr, __builtin_elementwise_fma(-ke1, s.ep, s.ep)) : (tcv)0.f;
-#pragma unroll
-    for (int t0 = 0; t0 < TC_TB; t0 += 4) {
-      if (t0 >= T) break;
-      __asm__ volatile("" ::: "memory");
-      const uint32_t sx = spikes4(s.bits.x, a.tofs + t0), sy = spikes4(s.bits.y, a.tofs + t0);
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (t0 + u >= T) break;
-        const tcv z = {(float)((sx >> (8 * u)) & 0xFFu), (float)((sy >> (8 * u)) & 0xFFu)};
-        const int w = (t0 + u) * WAVE;
-        g = __builtin_elementwise_fma(z, cgv[w], g);
-        eb = __builtin_elementwise_fma(z, cbv[w], eb);
-        if (ALIF) ep = __builtin_elementwise_fma(z, cev[w], ep);
+    // the block's spikes, lowest step first; z_t = 1 adds the coefficients of step t
+    uint32_t mx = (s.bits.x >> a.tofs) & tmask, my = (s.bits.y >> a.tofs) & tmask;
+    if (ballot((mx | my) != 0u)) do {
+      const float* zx = czl + __builtin_ctz(mx | sent) * (NA * TC_CH);  // row T (zeros) once mx is empty
+      const float* zy = czl + __builtin_ctz(my | sent) * (NA * TC_CH) + 1;
+      g.x += zx[0];
+      g.y += zy[0];
+      eb.x += zx[TC_CH];
+      eb.y += zy[TC_CH];
+      if (ALIF) {
+        ep.x += zx[2 * TC_CH];
+        ep.y += zy[2 * TC_CH];
       }
-    }
+      mx &= mx - 1u;
+      my &= my - 1u;
+    } while (ballot((mx | my) != 0u));
     const int fin = __builtin_amdgcn_readfirstlane(s.fin), slot = __builtin_amdgcn_readfirstlane(s.slot);
     const int64_t rec = (int64_t)slot * B + bi;
     if (act) {

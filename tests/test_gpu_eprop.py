@@ -332,7 +332,7 @@ def test_trace_block_length_invariance(name):
     rounding only (relative 2e-6 of each array's largest value)."""
     base, rate = CASES[name]
     snaps = {}
-    for K in (1, 3, 8, 16):
+    for K in (1, 3, 8, 16, 32):
         cfg = rb.EpropConfig(**{**base.__dict__, "trace_block": K})
         net = rb.EpropNet(cfg)
         rates = wl.poisson_rates(cfg.seed, cfg.n_in, rate)
@@ -344,7 +344,7 @@ def test_trace_block_length_invariance(name):
         snaps[K] = snapshot(net)
         net.close()
     ref = snaps[1]
-    for K in (3, 8, 16):
+    for K in (3, 8, 16, 32):
         s = snaps[K]
         for k in ("v", "a", "y", "xbar", "zbar", "psiT", "LT", "deltaT", "z", "Wout", "bout"):
             assert np.array_equal(s[k], ref[k]), (K, k)
