@@ -123,6 +123,7 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, const int b) {
     const int nw = a.n_out * a.n_rec;
     for (int q = tid; q < nw; q += FWD_NT) w[q] = a.Wout[q];
   }
+  const int cap_in = a.cap_in, cap_rec = a.cap_rec;
   const int* ind_in = a.ind_in;
   const float* w_in = a.w_in;
   const int* ind_rec = a.ind_rec;
@@ -267,32 +268,34 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, const int b) {
     // update barrier
     for (int q = tid; q < xwords; q += FWD_NT) xflags2[((tau + 1) & 1) * xwords + q] = 0u;
 
-    // ---- propagation: one wave per spiking row, lanes over the row's slots;
-    // up to PROP_U slots per lane are loaded before any LDS atomic, so a row
-    // of up to 256 slots costs one memory latency
+    // ---- propagation: one wave per spiking row, lanes over the row's slots.
+    // All PROP_U slots per lane are loaded, unconditionally (lanes past the
+    // row's end read its last slot again), before any is used, so a row of up
+    // to 256 slots costs one memory latency: loads under a lane condition
+    // would each be waited for before the next is issued.
     unsigned long long ev = 0ull;
     for (int r = wv; r < nx + nz; r += FWD_NT / WAVE) {
       const bool from_in = r < nx;
-      const int i = from_in ? xs[r] : zlist[r - nx];
+      const int i = __builtin_amdgcn_readfirstlane(from_in ? xs[r] : zlist[r - nx]);  // the wave's row
       if (from_in && (unsigned)i >= (unsigned)a.n_in) continue;  // out-of-range channel: ignored
+      const int n = __builtin_amdgcn_readfirstlane(from_in ? len_in[i] : len_rec[i]);
+      if (n <= 0) continue;
       const int* ind = from_in ? ind_in : ind_rec;
       const float* w = from_in ? w_in : w_rec;
-      const int cap = from_in ? a.cap_in : a.cap_rec;
-      const int n = from_in ? len_in[i] : len_rec[i];
-      const int64_t base = (int64_t)i * cap;
+      const int64_t base = (int64_t)i * (from_in ? cap_in : cap_rec);
       ev += (unsigned long long)n;
       for (int c0 = 0; c0 < n; c0 += PROP_U * WAVE) {
         int jj[PROP_U];
         float ww[PROP_U];
 #pragma unroll
         for (int u = 0; u < PROP_U; ++u) {
-          const int k = c0 + u * WAVE + lane;
-          jj[u] = k < n ? ind[base + k] : -1;
-          ww[u] = k < n ? w[base + k] : 0.0f;
+          const int64_t q = base + min(c0 + u * WAVE + lane, n - 1);
+          jj[u] = ind[q];
+          ww[u] = w[q];
         }
 #pragma unroll
         for (int u = 0; u < PROP_U; ++u)
-          if (jj[u] >= 0)
+          if (c0 + u * WAVE + lane < n)
             atomicAdd((unsigned long long*)&acc[jj[u]], (unsigned long long)__double2ll_rn((double)ww[u] * FIX_SCALE));
       }
     }
