@@ -274,40 +274,98 @@ __device__ __forceinline__ void fwd_body(const FwdArgs& a, const int b) {
     // to 256 slots costs one memory latency: loads under a lane condition
     // would each be waited for before the next is issued.
     unsigned long long ev = 0ull;
-    for (int r = wv; r < nx + nz; r += FWD_NT / WAVE) {
-      const bool from_in = r < nx;
-      const int i = __builtin_amdgcn_readfirstlane(from_in ? xs[r] : zlist[r - nx]);  // the wave's row
-      if (from_in && (unsigned)i >= (unsigned)a.n_in) continue;  // out-of-range channel: ignored
-      const int n = __builtin_amdgcn_readfirstlane(from_in ? len_in[i] : len_rec[i]);
-      if (n <= 0) continue;
-      const int* ind = from_in ? ind_in : ind_rec;
-      const float* w = from_in ? w_in : w_rec;
-      const int64_t base = (int64_t)i * (from_in ? cap_in : cap_rec);
-      ev += (unsigned long long)n;
-      for (int c0 = 0; c0 < n; c0 += PROP_U * WAVE) {
-        int jj[PROP_U];
-        float ww[PROP_U];
-#pragma unroll
-        for (int u = 0; u < PROP_U; ++u) {
-          const int64_t q = base + min(c0 + u * WAVE + lane, n - 1);
-          jj[u] = ind[q];
-          ww[u] = w[q];
+    // the readout drive's weights are loaded first, beside the rows: with at
+    // most 64 spikes and 32 outputs, wave wv's outputs wv and wv + 16 need one
+    // weight per lane each (lanes past the spike list read a valid weight and
+    // drop it)
+    constexpr int NWV = FWD_NT / WAVE;
+    const bool ro_fast = nz <= WAVE && a.n_out <= 2 * NWV;
+    float ro_w0 = 0.0f, ro_w1 = 0.0f;
+    bool ro_issued = !ro_fast || wv >= a.n_out;
+    // the readout drive's weights: with at most 64 spikes and 32 outputs, wave
+    // wv's outputs wv and wv + 16 need one weight per lane each (lanes past
+    // the spike list read a valid weight and drop it).  They are requested
+    // right after the wave's first row, so that the row's wait leaves them in
+    // flight.
+    auto issue_readout = [&]() {
+      const int jz = nz > 0 ? zlist[min(lane, nz - 1)] : 0;
+      const int64_t o0 = (int64_t)wv * a.n_rec + jz, o1 = (int64_t)min(wv + NWV, a.n_out - 1) * a.n_rec + jz;
+      if (a.wout_lds) {
+        const float* wl = (const float*)(smem + lay.wout);
+        ro_w0 = wl[o0];
+        ro_w1 = wl[o1];
+      } else {
+        ro_w0 = ld_global(a.Wout + o0);
+        ro_w1 = ld_global(a.Wout + o1);
+      }
+      ro_issued = true;
+    };
+    // The wave's rows r = wv, wv + 16, ... in groups of 64: lane k reads row
+    // wv + 16 (g + k)'s index and length, and the loop reads them by readlane.
+    const int nr_w = nx + nz > wv ? (nx + nz - wv + NWV - 1) / NWV : 0;
+    for (int g = 0; g < nr_w; g += WAVE) {
+      int my_i = -1, my_n = 0;
+      if (g + lane < nr_w) {
+        const int r = wv + (g + lane) * NWV;
+        if (r >= nx) {
+          my_i = zlist[r - nx];
+          my_n = len_rec[my_i];
+        } else {
+          const int i = xstaged ? xbuf[xpos[tau] + r] : ld_global(xsrc_base + s_xsrc[tau] + r);
+          if ((unsigned)i < (unsigned)a.n_in) {  // out-of-range channel: ignored
+            my_i = i;
+            my_n = len_in[i];
+          }
         }
+      }
+      const int kn = min(WAVE, nr_w - g);
+      for (int k = 0; k < kn; ++k) {
+        const int i = __builtin_amdgcn_readlane(my_i, k), n = __builtin_amdgcn_readlane(my_n, k);
+        if (i < 0 || n <= 0) continue;
+        const bool from_in = wv + (g + k) * NWV < nx;
+        const int* ind = from_in ? ind_in : ind_rec;
+        const float* w = from_in ? w_in : w_rec;
+        const int64_t base = (int64_t)i * (from_in ? cap_in : cap_rec);
+        ev += (unsigned long long)n;
+        for (int c0 = 0; c0 < n; c0 += PROP_U * WAVE) {
+          int jj[PROP_U];
+          float ww[PROP_U];
 #pragma unroll
-        for (int u = 0; u < PROP_U; ++u)
-          if (c0 + u * WAVE + lane < n)
-            atomicAdd((unsigned long long*)&acc[jj[u]], (unsigned long long)__double2ll_rn((double)ww[u] * FIX_SCALE));
+          for (int u = 0; u < PROP_U; ++u) {
+            const int64_t q = base + min(c0 + u * WAVE + lane, n - 1);
+            jj[u] = ind[q];
+            ww[u] = w[q];
+          }
+          if (!ro_issued) issue_readout();
+#pragma unroll
+          for (int u = 0; u < PROP_U; ++u)
+            if (c0 + u * WAVE + lane < n)
+              atomicAdd((unsigned long long*)&acc[jj[u]],
+                        (unsigned long long)__double2ll_rn((double)ww[u] * FIX_SCALE));
+        }
       }
     }
+    if (!ro_issued) issue_readout();  // a wave without rows
     if (lane == 0 && ev) atomicAdd(&s_events, ev);
 
     // ---- readout drive u_k = sum_j W_out[k][j] z_j: one wave per output unit
-    for (int k = wv; k < a.n_out; k += FWD_NT / WAVE) {
-      float s = 0.0f;
-      const float* wk = wout + (int64_t)k * a.n_rec;
-      for (int l = lane; l < nz; l += WAVE) s += wk[zlist[l]];
-      s = wave_sum(s);
-      if (lane == 0) a.u[((int64_t)tau * B + b) * a.n_out + k] = s;
+    if (ro_fast) {
+      if (wv < a.n_out) {
+        const float s0 = wave_sum(lane < nz ? ro_w0 : 0.0f);
+        const float s1 = wave_sum(lane < nz ? ro_w1 : 0.0f);
+        if (lane == 0) {
+          a.u[((int64_t)tau * B + b) * a.n_out + wv] = s0;
+          if (wv + NWV < a.n_out) a.u[((int64_t)tau * B + b) * a.n_out + wv + NWV] = s1;
+        }
+      }
+    } else {
+      for (int k = wv; k < a.n_out; k += FWD_NT / WAVE) {
+        float s = 0.0f;
+        const float* wk = wout + (int64_t)k * a.n_rec;
+        for (int l = lane; l < nz; l += WAVE) s += wk[zlist[l]];
+        s = wave_sum(s);
+        if (lane == 0) a.u[((int64_t)tau * B + b) * a.n_out + k] = s;
+      }
     }
     __syncthreads();  // acc complete
 
