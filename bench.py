@@ -717,7 +717,7 @@ def main():
     n_syn_after = int(net.get(rb.PROJ(0, rb.P_LEN)).sum() + net.get(rb.PROJ(1, rb.P_LEN)).sum())
     assert n_syn_after == n_syn, "DEEP R must keep the synapse count"
 
-    inf_k = net.info().trace_block
+    inf_k, inf_k0 = net.info().trace_block, net.info().first_block
     samples = args.steps * cfg.batch
     value = samples / elapsed
     ep_ms, ep_n = phases["eprop"]
@@ -755,7 +755,7 @@ def main():
                      "traffic": recorded_traffic(EPROP_KERNEL),
                      "algorithmic_bytes_per_launch": round(alg_bytes / max(ep_n, 1)),
                      "avg_launch_us": round(ep_avg_s * 1e6, 2), "launches": ep_n,
-                     "trace_block": inf_k,
+                     "trace_block": inf_k, "first_block": inf_k0,
                      # the method's float operations (the step-by-step recursion) per second of e-prop
                      "alu": {"achieved": round(achieved_tf, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": round(achieved_tf / FP32_PEAK_TFLOPS, 4),

@@ -234,7 +234,8 @@ typedef struct rs_eprop_info {
   uint64_t device_bytes;          /* device memory held */
   uint64_t eliminated, formed;    /* DEEP R synapses removed / created so far, both projections */
   uint32_t trace_block;           /* steps per eligibility block (trace_block, or the default chosen) */
-  uint32_t reserved;
+  uint32_t first_block;           /* steps of an update interval's first block under RS_AUTO_UPDATE
+                                     (trace_block when it was given) */
 } rs_eprop_info;
 /* Synchronises the stream. */
 rs_status rs_eprop_info_get(rs_eprop* net, rs_eprop_info* out);

@@ -60,7 +60,7 @@ class _Info(C.Structure):
                 ("words_rec", C.c_uint32), ("step", C.c_uint64), ("adam_step", C.c_uint32),
                 ("last_block", C.c_uint32), ("synaptic_events", C.c_uint64), ("spikes", C.c_uint64),
                 ("device_bytes", C.c_uint64), ("eliminated", C.c_uint64), ("formed", C.c_uint64),
-                ("trace_block", C.c_uint32), ("reserved", C.c_uint32)]
+                ("trace_block", C.c_uint32), ("first_block", C.c_uint32)]
 
 
 class _TopoParams(C.Structure):

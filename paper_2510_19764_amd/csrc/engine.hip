@@ -184,6 +184,7 @@ struct rs_eprop {
   uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [Q][K][B][NR]; x0, z0, xbits, zbits [Q][B][n]
   float *u_stg = nullptr;                             // readout drive [Q segments][K][B][n_out]
   int K = 8, Q = 2, nslot = 16;
+  int K0 = 8;  // the first block of an update interval, under automatic updates
   int blk_seg = 0, blk_n = 0, last_slot = 0;
   int last_seg = 0, last_blk_n = 0;                   // the most recently run block
   uint64_t blk_t0 = 0;
@@ -344,14 +345,16 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   // the narrow kernel serves (B % 4 != 0) take a whole update interval of up
   // to 32 steps, one block per interval
   if (prm->trace_block)
-    n->K = (int)prm->trace_block;
+    n->K = n->K0 = (int)prm->trace_block;
   else if (B % 4 != 0 && prm->update_interval >= 1 && prm->update_interval <= 32)
-    n->K = (int)prm->update_interval;
+    n->K = n->K0 = (int)prm->update_interval;
   else
-    n->K = eprop_default_block((int)B, prm->update_interval);
+    eprop_default_schedule((int)B, prm->update_interval, &n->K, &n->K0);
   {
-    const uint32_t U = prm->update_interval, Kb = (uint32_t)n->K;
-    n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>((U + Kb - 1) / Kb + 1, 2), RING_MAX) : 2;
+    // a segment per block of an interval, plus one
+    const uint32_t U = prm->update_interval, Kb = (uint32_t)n->K, K0 = (uint32_t)n->K0;
+    const uint32_t nb = U ? (U <= K0 ? 1 : 1 + (U - K0 + Kb - 1) / Kb) : 1;
+    n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>(nb + 1, 2), RING_MAX) : 2;
   }
   const size_t QS = (size_t)n->Q;
   TRY(ar.alloc(&n->x0T, QS * NI * B));
@@ -661,7 +664,10 @@ void do_step(rs_eprop* n, uint32_t flags) {
   }
   n->blk_n += 1;
   n->step += 1;
-  if (n->blk_n == n->K) flush_block(n);
+  // under automatic updates an interval's first block is K0 steps
+  const uint64_t U = n->p.update_interval;
+  const bool first = n->auto_upd && U && n->blk_t0 % U == 0;
+  if (n->blk_n == (first ? n->K0 : n->K)) flush_block(n);
   const bool upd = (flags & RS_AUTO_UPDATE) && n->p.update_interval && n->step % n->p.update_interval == 0;
   const bool rst = (flags & RS_AUTO_RESET) && n->step % n->p.sample_steps == 0;
   if (upd || rst) {
@@ -946,6 +952,7 @@ rs_status rs_eprop_info_get(rs_eprop* n, rs_eprop_info* o) {
   o->eliminated = (uint64_t)r[0];
   o->formed = (uint64_t)r[1];
   o->trace_block = (uint32_t)n->K;
+  o->first_block = (uint32_t)n->K0;
   return RS_OK;
 }
 

@@ -849,6 +849,22 @@ static void tc_attrs() {
   });
 }
 
+void eprop_default_schedule(int B, uint32_t update_interval, int* K, int* K0) {
+  *K = *K0 = eprop_default_block(B, update_interval);
+  const uint32_t U = update_interval;
+  if (B % 4 != 0 || B < TC_MIN_B || U <= (uint32_t)TC_TB) return;
+  // The first block of an interval is short (a tenth of it), so the first
+  // e-prop launch, which waits for that block's forward pass and readout,
+  // starts early; the rest of the interval in equal blocks of at most TC_TB
+  // steps.  As many launches as equal blocks would take.
+  const uint32_t nb = (U + TC_TB - 1) / TC_TB;
+  const uint32_t k0 = (U + 5) / 10;
+  const uint32_t k = (U - k0 + nb - 2) / (nb - 1);
+  if (k > (uint32_t)TC_TB) return;
+  *K = (int)k;
+  *K0 = (int)k0;
+}
+
 int eprop_default_block(int B, uint32_t update_interval) {
   if (B % 4 != 0 || B < TC_MIN_B) return COL_TB;
   // the update interval in equal blocks of at most TC_TB steps: each launch

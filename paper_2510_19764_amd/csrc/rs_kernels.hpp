@@ -141,6 +141,9 @@ struct EpropArgs {
 void launch_eprop(hipStream_t s, const EpropArgs& a);
 // Default steps per eligibility block (one e-prop launch) for batch B.
 int eprop_default_block(int B, uint32_t update_interval);
+// Default block lengths when automatic updates run every update_interval
+// steps: the first block of an interval K0 steps, the others at most K.
+void eprop_default_schedule(int B, uint32_t update_interval, int* K, int* K0);
 // Narrow e-prop kernel over several networks, persistent over a work list of
 // row tiles (network, first row, rows; rows >= n_in + n_rec are readout
 // chunks): `grid` workgroups (0: one per work item), `tpr` threads per row (64

@@ -1,6 +1,7 @@
 """Parity at the full sparse-classifier size (700 inputs, 1024 ALIF, 20
 readouts, 10% connectivity, batch 256): 120 steps in the schedule the
-benchmark times (25-step blocks through the two-stream hand-off ring, the
+benchmark times (blocks of 10, 30, 30 and 30 steps per update interval
+through the two-stream hand-off ring, the
 automatic Adam update and both DEEP R rewires inside the call, the column view
 rebuilt beside the next forward block) compared element by element with the
 oracle; single full-size steps; DEEP R bit-exact on the full rows; invariants
@@ -134,8 +135,8 @@ def test_full_batch_training_deterministic():
 
 def test_full_size_interval_in_bench_schedule():
     """From the update boundary at step 100, one call of 100 steps with
-    RS_LEARN | RS_AUTO_UPDATE and the default block length (four 25-step
-    blocks through the two-stream ring, the update and both rewires at step
+    RS_LEARN | RS_AUTO_UPDATE and the default block lengths (10, 30, 30 and
+    30 steps through the two-stream ring, the update and both rewires at step
     200, the column view rebuilt beside the next block), against the oracle's
     100 steps, Adam update and two rewires from the same snapshot: spike
     counts and the last block's raster exact, rows, bitfields and dormant
@@ -146,6 +147,8 @@ def test_full_size_interval_in_bench_schedule():
     net = rb.EpropNet(cfg)
     net.set_input(*gpu_input(raster, labels))
     net.step(cfg.update_interval, rb.RS_LEARN | rb.RS_AUTO_UPDATE)
+    info = net.info()
+    assert (info.first_block, info.trace_block) == (10, 30)
     print("classifier full size: 100 + 20 steps against the oracle", flush=True)
     assert interval_vs_oracle(net, cfg, raster, labels, 100, after=20) == 1
     print("worst error / bound:", {k: round(v, 3) for k, v in sorted(MARGINS.items())}, flush=True)

@@ -240,15 +240,16 @@ def test_overlapped_training_matches_joined_calls():
     """A network large enough for the two-stream schedule, trained with
     automatic updates, DEEP R and resets in one call (forward blocks running
     ahead of e-prop, ring segments reused without events inside an interval)
-    ends bit-identical to the same steps in calls of the default block length
-    (25 steps here), each of which joins both streams at its end."""
+    ends bit-identical to the same steps in calls of the default blocks (10
+    steps at the start of each update interval, then 30), each of which joins
+    both streams at its end."""
     cfg = make_cfg(300, 200, 5, 64, True, p=0.9, seed=12, U=100, T=200, lr=0.05)
     rates = wl.poisson_rates(cfg.seed, cfg.n_in, 60.0)
     raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
     labels = (np.arange(cfg.batch) % cfg.n_out).astype(np.int32)
     flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
     snaps, infos = [], []
-    for calls in ((240,), (25,) * 9 + (15,)):
+    for calls in ((240,), (10, 30, 30, 30) * 2 + (10, 30)):
         net = rb.EpropNet(cfg)
         net.set_input(*gpu_input(raster, labels))
         for n in calls:
@@ -263,6 +264,7 @@ def test_overlapped_training_matches_joined_calls():
                 assert np.array_equal(a[k][f], b[k][f]), (k, f)
         else:
             assert np.array_equal(a[k], b[k]), k
+    assert (infos[0].first_block, infos[0].trace_block) == (10, 30)
     assert infos[0].eliminated == infos[1].eliminated > 0
     assert infos[0].adam_step == infos[1].adam_step == 2
 
