@@ -118,7 +118,8 @@ struct PhaseTimer {
   hipEvent_t get() {
     if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
     hipEvent_t e;
-    (void)hipEventCreate(&e);
+    // timing only: no system-scope fence at the records
+    (void)hipEventCreateWithFlags(&e, hipEventDisableSystemFence);
     return e;
   }
   bool armed = false;  // the last begin() recorded an event
@@ -196,6 +197,7 @@ struct rs_eprop {
   bool single = false;                                // small network: everything on the caller's stream
   bool auto_upd = false;                              // inside a step call with RS_AUTO_UPDATE
   hipEvent_t ev_fwd = nullptr, ev_post = nullptr, ev_ep[RING_MAX] = {}, ev_join = nullptr, ev_back = nullptr;
+  hipEvent_t ev_loop = nullptr;  // the update boundary's join back to the forward stream
   hipEvent_t ev_upd = nullptr, ev_rw = nullptr;
   bool ep_pending[RING_MAX] = {};  // an e-prop launch reading the segment may still run
   uint8_t* z = nullptr;
@@ -386,11 +388,16 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
     HIP_OK(hipStreamCreateWithFlags(&n->side, hipStreamNonBlocking));
     HIP_OK(hipStreamCreateWithFlags(&n->side2, hipStreamNonBlocking));
   }
-  HIP_OK(hipEventCreateWithFlags(&n->ev_upd, hipEventDisableTiming));
-  HIP_OK(hipEventCreateWithFlags(&n->ev_rw, hipEventDisableTiming));
-  HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, hipEventDisableTiming));
-  HIP_OK(hipEventCreateWithFlags(&n->ev_post, hipEventDisableTiming));
-  for (int q = 0; q < n->Q; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], hipEventDisableTiming));
+  // Events between the library's own kernels on its streams order them on
+  // the device only: no system-scope fence (a write-back of the caches) at
+  // each record.  The joins with the caller's work at the ends of a call keep it.
+  const unsigned dev_ev = hipEventDisableTiming | hipEventDisableSystemFence;
+  HIP_OK(hipEventCreateWithFlags(&n->ev_upd, dev_ev));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_rw, dev_ev));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_fwd, dev_ev));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_post, dev_ev));
+  HIP_OK(hipEventCreateWithFlags(&n->ev_loop, dev_ev));
+  for (int q = 0; q < n->Q; ++q) HIP_OK(hipEventCreateWithFlags(&n->ev_ep[q], dev_ev));
   HIP_OK(hipEventCreateWithFlags(&n->ev_join, hipEventDisableTiming));
   HIP_OK(hipEventCreateWithFlags(&n->ev_back, hipEventDisableTiming));
   TRY(ar.alloc(&n->z, B * NR));
@@ -693,7 +700,7 @@ void do_step(rs_eprop* n, uint32_t flags) {
       reset_state(n, e);
       n->timer.end(e);
     }
-    order(n->ev_back, e, s);
+    order(n->ev_loop, e, s);
     for (bool& p : n->ep_pending) p = false;  // covered by that wait
     // only the e-prop launches, later on this stream, read the column view:
     // the next forward block runs while it is rebuilt
@@ -984,7 +991,7 @@ void rs_eprop_destroy(rs_eprop* n) {
     if (n->side2) (void)hipStreamSynchronize(n->side2);
   }
   n->timer.destroy();
-  for (hipEvent_t ev : {n->ev_fwd, n->ev_post, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw})
+  for (hipEvent_t ev : {n->ev_fwd, n->ev_post, n->ev_join, n->ev_back, n->ev_upd, n->ev_rw, n->ev_loop})
     if (ev) (void)hipEventDestroy(ev);
   for (hipEvent_t ev : n->ev_ep)
     if (ev) (void)hipEventDestroy(ev);
