@@ -544,14 +544,30 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
     y[q] = k < a.n_out ? a.Y[(int64_t)b * a.n_out + k] : 0.0;
     bias[q] = k < a.n_out ? a.bout[k] : 0.0f;
   }
+  // the drive of RO_TC steps at a time is loaded before any of them is used
+  // (one memory latency per RO_TC steps; the delta stores in between would
+  // otherwise order each step's loads after the previous step's stores)
+  constexpr int RO_TC = 8;
+  float uc[RO_TC][RO_KMAX];
   for (int tau = 0; tau < a.nsteps; ++tau) {
-    const float* u = a.u + ((int64_t)tau * a.B + b) * a.n_out;
+    const int tc = tau % RO_TC;
+    if (tc == 0) {
+#pragma unroll
+      for (int t = 0; t < RO_TC; ++t) {
+        const int64_t row = ((int64_t)min(tau + t, a.nsteps - 1) * a.B + b) * a.n_out;
+#pragma unroll
+        for (int q = 0; q < RO_KMAX; ++q) uc[t][q] = a.u[row + min(q * WAVE + lane, a.n_out - 1)];
+      }
+    }
     float m = -INFINITY;
 #pragma unroll
     for (int q = 0; q < RO_KMAX; ++q) {
       const int k = q * WAVE + lane;
+      float uk = uc[0][q];
+#pragma unroll
+      for (int t = 1; t < RO_TC; ++t) uk = tc == t ? uc[t][q] : uk;
       if (k < a.n_out) {
-        y[q] = a.alpha * y[q] + (double)u[k] + (double)bias[q];
+        y[q] = a.alpha * y[q] + (double)uk + (double)bias[q];
         m = fmaxf(m, (float)y[q]);
       }
     }
