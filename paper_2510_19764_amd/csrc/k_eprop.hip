@@ -8,6 +8,7 @@
 //   ([slot][B], [neuron][B]) so a wave reads consecutive instances.
 // k_col_*: the column view (synapses grouped by target) the target-major
 //   kernel walks, rebuilt by a counting sort whenever rows change.
+#include <algorithm>
 #include <mutex>
 
 #include "rs_device.hpp"
@@ -858,9 +859,9 @@ void eprop_default_schedule(int B, uint32_t update_interval, int* K, int* K0) {
   // starts early; the rest of the interval in equal blocks of at most TC_TB
   // steps.  As many launches as equal blocks would take.
   const uint32_t nb = (U + TC_TB - 1) / TC_TB;
-  const uint32_t k0 = (U + 5) / 10;
+  const uint32_t k0 = std::min<uint32_t>((U + 5) / 10, (uint32_t)*K);  // a block holds at most 31 steps
   const uint32_t k = (U - k0 + nb - 2) / (nb - 1);
-  if (k > (uint32_t)TC_TB) return;
+  if (k > (uint32_t)TC_TB || k0 < 1) return;
   *K = (int)k;
   *K0 = (int)k0;
 }

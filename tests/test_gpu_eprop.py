@@ -269,6 +269,35 @@ def test_overlapped_training_matches_joined_calls():
     assert infos[0].adam_step == infos[1].adam_step == 2
 
 
+def test_default_blocks_long_update_interval():
+    """The default blocks stay within one 32-bit spike word for any update
+    interval: at 1000 steps they are 31 steps long (no short first block
+    then), and 1100 steps of training with automatic updates and resets end
+    bit-identical to the same run with trace_block 31 given."""
+    base = make_cfg(40, 70, 4, 64, True, p=0.3, seed=21, U=1000, T=550, lr=0.05)
+    rates = wl.poisson_rates(base.seed, base.n_in, 80.0)
+    raster = wl.poisson_raster(base.seed, rates, base.sample_steps, base.batch)
+    labels = (np.arange(base.batch) % base.n_out).astype(np.int32)
+    flags = rb.RS_LEARN | rb.RS_AUTO_UPDATE | rb.RS_AUTO_RESET
+    snaps = []
+    for K in (0, 31):
+        net = rb.EpropNet(rb.EpropConfig(**{**base.__dict__, "trace_block": K}))
+        net.set_input(*gpu_input(raster, labels))
+        info = net.info()
+        assert (info.trace_block, info.first_block) == (31, 31)
+        net.step(1100, flags)
+        assert net.info().adam_step == 1
+        snaps.append(snapshot(net))
+        net.close()
+    a, b = snaps
+    for k in a:
+        if isinstance(a[k], dict):
+            for f in a[k]:
+                assert np.array_equal(a[k][f], b[k][f]), (k, f)
+        else:
+            assert np.array_equal(a[k], b[k]), k
+
+
 @pytest.mark.parametrize("name", ["alif-b64-col", "alif-b3-narrow"])
 def test_spike_raster_of_last_block(name):
     """The last block's spike bits equal the spikes of the same steps taken one
