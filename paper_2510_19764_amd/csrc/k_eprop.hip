@@ -527,25 +527,27 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   struct In {
     tcv eb, ep, pr;
     tcu bits;
-    float g0;
-    int fin, slot, q;
+    int fin, slot, n;
   };
   // list entries of the wave's next 64 synapses, one per lane, read by
   // readlane so that no load waits on another
   int2 ents;
   int base = 0;
+  // the batch's gradients, one synapse per lane: G before this launch (one
+  // chunk), and this launch's part, gathered as the synapses run and stored
+  // once per batch
+  float gbat = 0.f, gacc = 0.f;
   auto load = [&](int n, In& s) {
     const int r = __builtin_amdgcn_readlane(ents.x, n), slot = __builtin_amdgcn_readlane(ents.y, n);
     s.fin = r < a.n_in;
     s.slot = slot;
-    s.q = base + TC_NW * n;
+    s.n = n;
     const int i = s.fin ? r : r - a.n_in;
     const int64_t rec = (int64_t)slot * B + bi;
     s.eb = __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.ebar : a.rec.ebar) + rec));
     s.ep = ALIF ? __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.eps : a.rec.eps) + rec)) : (tcv)0.f;
     s.pr = *(const tcv*)((s.fin ? a.x0 : a.z0) + (int64_t)i * B + bi);
     s.bits = *(const tcu*)((s.fin ? a.xbits : a.zbits) + (int64_t)i * B + bi);
-    s.g0 = n_ch == 1 ? (s.fin ? a.in.G : a.rec.G)[slot] : 0.f;
   };
   auto run = [&](const In& s) {
     tcv pr = s.pr;
@@ -579,10 +581,7 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
       if (ALIF) __builtin_nontemporal_store(ep, (tcv*)((fin ? a.in.eps : a.rec.eps) + rec));
     }
     const float part = wave_sum(act ? g.x + g.y : 0.f);
-    if (lane == 0) {
-      if (n_ch == 1) (fin ? a.in.G : a.rec.G)[slot] = s.g0 + part;
-      else a.gpart[(int64_t)c * a.n_col + s.q] = part;  // this chunk's part, summed into G by k_gpart_sum
-    }
+    gacc = lane == s.n ? part : gacc;
   };
   // three register sets in turn: while a synapse runs, the next two load
   // (past the batch the last entry is loaded again and not used)
@@ -590,6 +589,8 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   for (base = q0 + wv; base < q1; base += TC_NW * WAVE) {
     const int nb = min(WAVE, (q1 - 1 - base) / TC_NW + 1);  // this wave's synapses in the batch
     ents = a.col[base + TC_NW * min(lane, nb - 1)];
+    const bool efin = ents.x < a.n_in;
+    if (n_ch == 1) gbat = (efin ? a.in.G : a.rec.G)[ents.y];
     load(0, s0);
     load(min(1, nb - 1), s1);
 #pragma unroll 1
@@ -603,6 +604,10 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
       load(min(i + 2, nb - 1), s1);
       run(s2);
       if (++i >= nb) break;
+    }
+    if (lane < nb) {
+      if (n_ch == 1) (efin ? a.in.G : a.rec.G)[ents.y] = gbat + gacc;
+      else a.gpart[(int64_t)c * a.n_col + base + TC_NW * lane] = gacc;  // this chunk's part, summed into G by k_gpart_sum
     }
   }
 }
