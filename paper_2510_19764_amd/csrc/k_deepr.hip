@@ -149,30 +149,46 @@ __device__ __forceinline__ void form_body(const uint64_t seed, const ProjDev& P,
   if (na == 0) return;
   const int n0 = P.len[r];
   __shared__ int s_found;
-  if (lane == 0) {
-    uint32_t* row = P.conn + (int64_t)r * P.words;
-    int found = 0;
-    for (int k = 0; k < na; ++k) {
-      int j = -1;
-      for (int t = 0; t < MAX_TRIES; ++t) {
-        const int c = (int)below(draw_u32(seed, TAG_DR_TGT, P.proj_id, step, r, k, t), (uint32_t)P.n_post);
-        if (!((row[c >> 5] >> (c & 31)) & 1u) && !(P.recurrent && c == r)) { j = c; break; }
-      }
-      if (j < 0) {
-        const int start = (int)below(draw_u32(seed, TAG_DR_TGT, P.proj_id, step, r, k, MAX_TRIES),
-                                     (uint32_t)P.n_post);
-        for (int dd = 0; dd < P.n_post; ++dd) {
-          const int c = (start + dd) % P.n_post;
+  __shared__ int s_cand[WAVE];  // first candidate target of each of the next 64 activations
+  // Activations take their targets in order (each sees the targets taken
+  // before it), so lane 0 decides them one by one; the draws of their first
+  // candidates do not depend on that order and are made by all lanes at once.
+  uint32_t* row = P.conn + (int64_t)r * P.words;
+  int found = 0;
+  bool stop = false;
+  for (int k0 = 0; k0 < na; k0 += WAVE) {
+    if (k0 + lane < na)
+      s_cand[lane] = (int)below(draw_u32(seed, TAG_DR_TGT, P.proj_id, step, r, k0 + lane, 0), (uint32_t)P.n_post);
+    __syncthreads();
+    if (lane == 0 && !stop) {
+      const int k1 = min(na, k0 + WAVE);
+      for (int k = k0; k < k1; ++k) {
+        int j = -1;
+        for (int t = 0; t < MAX_TRIES; ++t) {
+          const int c = t == 0 ? s_cand[k - k0]
+                               : (int)below(draw_u32(seed, TAG_DR_TGT, P.proj_id, step, r, k, t), (uint32_t)P.n_post);
           if (!((row[c >> 5] >> (c & 31)) & 1u) && !(P.recurrent && c == r)) { j = c; break; }
         }
+        if (j < 0) {
+          const int start = (int)below(draw_u32(seed, TAG_DR_TGT, P.proj_id, step, r, k, MAX_TRIES),
+                                       (uint32_t)P.n_post);
+          for (int dd = 0; dd < P.n_post; ++dd) {
+            const int c = (start + dd) % P.n_post;
+            if (!((row[c >> 5] >> (c & 31)) & 1u) && !(P.recurrent && c == r)) { j = c; break; }
+          }
+        }
+        if (j < 0) {  // no free target: bitfield inconsistent with the row
+          stop = true;
+          break;
+        }
+        row[j >> 5] |= 1u << (j & 31);
+        newj[k] = j;
+        ++found;
       }
-      if (j < 0) break;  // no free target: bitfield inconsistent with the row
-      row[j >> 5] |= 1u << (j & 31);
-      newj[k] = j;
-      ++found;
     }
-    s_found = found;
+    __syncthreads();  // s_cand is rewritten for the next 64
   }
+  if (lane == 0) s_found = found;
   __syncthreads();
   const int nf = s_found;
   const int64_t base = (int64_t)r * P.cap + n0;
