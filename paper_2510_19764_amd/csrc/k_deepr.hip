@@ -30,13 +30,35 @@ __device__ __forceinline__ void elim_body(const ProjDev& P, const int B, long lo
   const int lane = lane_id();
   const int n = P.len[i];
   const int64_t base = (int64_t)i * P.cap;
-  for (int k = lane; k < n; k += WAVE) {
-    const int j = P.ind[base + k];
-    const float w = P.w[base + k];
-    const bool neg = get_bit(P.sign, P.words, i, j);
-    const bool rem = (w > 0.0f && neg) || (w < 0.0f && !neg);
-    remf[k] = rem;
-    if (rem) atomicAnd(&P.conn[(int64_t)i * P.words + (j >> 5)], ~(1u << (j & 31)));
+  // 256 slots at a time: their indices and weights loaded together
+  // (unconditionally: lanes past the row's end read its last slot again),
+  // then their sign words, then the tests; two memory round trips per 256
+  // slots instead of two per 64
+  constexpr int EU = 4;
+  const int64_t wbase = (int64_t)i * P.words;
+  for (int k0 = 0; k0 < n; k0 += EU * WAVE) {
+    int jj[EU];
+    float ww[EU];
+    uint32_t sw[EU];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int64_t q = base + min(k0 + u * WAVE + lane, n - 1);
+      jj[u] = P.ind[q];
+      ww[u] = P.w[q];
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) sw[u] = P.sign[wbase + (jj[u] >> 5)];
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int k = k0 + u * WAVE + lane;
+      if (k < n) {
+        const int j = jj[u];
+        const bool neg = (sw[u] >> (j & 31)) & 1u;
+        const bool rem = (ww[u] > 0.0f && neg) || (ww[u] < 0.0f && !neg);
+        remf[k] = rem;
+        if (rem) atomicAnd(&P.conn[wbase + (j >> 5)], ~(1u << (j & 31)));
+      }
+    }
   }
   __syncthreads();
   int n2;
