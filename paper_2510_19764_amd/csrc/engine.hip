@@ -414,7 +414,11 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   TRY(ar.alloc(&n->cv.off, NR * COL_GROUPS_MAX + 1));
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
   n->cv.n_col = (int)((size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap);
-  if (B > 128 && B % 4 == 0) TRY(ar.alloc(&n->cv.gpart, (size_t)((B + 127) / 128) * n->cv.n_col));
+  if (B > 128 && B % 4 == 0) {
+    const size_t gx = (size_t)((B + 127) / 128 - 1) * n->cv.n_col;
+    TRY(ar.alloc(&n->cv.gx, gx));
+    launch_fill_zero(s, n->cv.gx, gx * 4);
+  }
   TRY(ar.alloc(&n->rw_stats, 4));
   TRY(ar.alloc(&n->zcount, (size_t)B * NR));
 
@@ -488,7 +492,16 @@ UpdateArgs update_args(const rs_eprop* n, uint32_t k) {
   u.Mout = n->Mout; u.Vout = n->Vout; u.Mb = n->Mb; u.Vb = n->Vb;
   u.n_out_elems = (int)(n->p.n_out * n->p.n_rec);
   u.n_b = (int)n->p.n_out;
+  u.gx = n->cv.gx;
+  u.gx_stride = n->cv.n_col;
+  u.gx_n = n->cv.gx ? (n->B + 127) / 128 - 1 : 0;
   return u;
+}
+
+// Bring every chunk's gradient into G (before G is read or written, or rows
+// move, outside the update).
+void fold_gradients(rs_eprop* n, hipStream_t s) {
+  if (n->cv.gx) launch_gx_fold(s, update_args(n, 1));
 }
 
 void do_update(rs_eprop* n, hipStream_t s) {
@@ -603,7 +616,7 @@ EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
   a.slot0 = h * n->K; a.nsteps = nsteps; a.nslot = n->nslot;
   a.Gout = n->Gout; a.Gb = n->Gb;
   a.col_off = n->cv.off; a.col = n->cv.col;
-  a.gpart = n->cv.gpart; a.n_col = n->cv.n_col;
+  a.gx = n->cv.gx; a.n_col = n->cv.n_col;
   return a;
 }
 
@@ -864,6 +877,7 @@ rs_status rs_eprop_rewire(rs_eprop* n, uint32_t proj, rs_rewire_stats* st) {
     HIP_OK(hipMemcpyAsync(before, n->rw_stats, sizeof before, hipMemcpyDeviceToHost, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
   }
+  fold_gradients(n, n->stream);
   do_rewire(n, (int)proj, n->stream);
   rebuild_columns(n, n->stream);
   HIP_OK(hipGetLastError());
@@ -891,6 +905,7 @@ rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
   VarRef r;
   if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
+  if (var % 0x100 == RS_P_G && var >= 0x100) fold_gradients(n, n->stream);
   if (r.rows) {
     const size_t w = bytes / r.rows;
     HIP_OK(hipMemcpy2DAsync(host, w, r.ptr, r.pitch, w, r.rows, hipMemcpyDeviceToHost, n->stream));
@@ -931,6 +946,9 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
     }
   }
   HIP_OK(hipStreamSynchronize(n->stream));
+  // the chunks' parts go into G first: a new G replaces them too, and new
+  // rows must not inherit them at slots the update no longer visits
+  fold_gradients(n, n->stream);
   HIP_OK(hipMemcpyAsync(r.ptr, host, bytes, hipMemcpyHostToDevice, n->stream));
   if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) rebuild_columns(n, n->stream);
   HIP_OK(hipStreamSynchronize(n->stream));
@@ -3243,6 +3261,7 @@ rs_status rs_eprop_custom_update(rs_eprop* n, uint32_t proj, int32_t rule, uint6
   order(n->ev_join, n->side, n->stream);
   for (bool& p : n->ep_pending) p = false;
   if (!n->custom) n->custom = new rs_custom_state();
+  fold_gradients(n, n->stream);
   TRY(custom_update(n->arena, n->custom->cs, n->stream, n->p.seed, proj == 0 ? n->in : n->rec, n->B, rule, step, fn,
                     user, nullptr, st));
   rebuild_columns(n, n->stream);

@@ -421,11 +421,11 @@ __global__ void __launch_bounds__(WL_NW * WAVE) k_eprop_wl(EpropArgs a) {
 // Workgroup n_ro + k owns target j = k / n_ch and instances 128 c .. 128 c +
 // 127 (two per lane), c = k % n_ch: with two chunks the XCDs of one parity
 // serve one chunk, so the presynaptic traces an XCD gathers are half of all of
-// them.  Its TC_NW waves take the
-// target's synapses in turn, each with the inputs of its next two synapses
-// in flight.  With more than one chunk each chunk writes its part of a synapse's
-// gradient by list position, and k_gpart_sum adds the parts to G in chunk
-// order, so the sum does not depend on scheduling.
+// them.  Its TC_NW waves take the target's synapses in turn, each with the
+// inputs of its next two synapses in flight.  Chunk 0 adds its part of a
+// synapse's gradient to G; chunk c > 0 adds its part to its own array (gx),
+// which the parameter update (or a fold before G is read or rows move) adds
+// to G in chunk order, so the sums do not depend on scheduling.
 constexpr int TC_NW = 8;
 constexpr int TC_IPL = 2;                 // instances per lane
 constexpr int TC_CH = TC_IPL * WAVE;      // instances per chunk
@@ -533,10 +533,12 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   // readlane so that no load waits on another
   int2 ents;
   int base = 0;
-  // the batch's gradients, one synapse per lane: G before this launch (one
-  // chunk), and this launch's part, gathered as the synapses run and stored
+  // the batch's gradients, one synapse per lane: the chunk's sum before this
+  // launch and this launch's part, gathered as the synapses run and stored
   // once per batch
   float gbat = 0.f, gacc = 0.f;
+  float* const gx_in = c == 0 ? a.in.G : a.gx + (int64_t)(c - 1) * a.n_col;
+  float* const gx_rec = c == 0 ? a.rec.G : gx_in + (int64_t)a.in.n_pre * a.in.cap;
   auto load = [&](int n, In& s) {
     const int r = __builtin_amdgcn_readlane(ents.x, n), slot = __builtin_amdgcn_readlane(ents.y, n);
     s.fin = r < a.n_in;
@@ -590,7 +592,7 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     const int nb = min(WAVE, (q1 - 1 - base) / TC_NW + 1);  // this wave's synapses in the batch
     ents = a.col[base + TC_NW * min(lane, nb - 1)];
     const bool efin = ents.x < a.n_in;
-    if (n_ch == 1) gbat = (efin ? a.in.G : a.rec.G)[ents.y];
+    gbat = (efin ? gx_in : gx_rec)[ents.y];
     load(0, s0);
     load(min(1, nb - 1), s1);
 #pragma unroll 1
@@ -605,24 +607,8 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
       run(s2);
       if (++i >= nb) break;
     }
-    if (lane < nb) {
-      if (n_ch == 1) (efin ? a.in.G : a.rec.G)[ents.y] = gbat + gacc;
-      else a.gpart[(int64_t)c * a.n_col + base + TC_NW * lane] = gacc;  // this chunk's part, summed into G by k_gpart_sum
-    }
+    if (lane < nb) (efin ? gx_in : gx_rec)[ents.y] = gbat + gacc;
   }
-}
-
-// With more than one chunk: add the chunks' gradient parts of every listed
-// synapse to its G, in chunk order (the launch after the e-prop launch; the
-// kernel boundary orders the parts' stores before these loads).
-__global__ void __launch_bounds__(256) k_gpart_sum(EpropArgs a, int n_ch) {
-  const int q = blockIdx.x * 256 + threadIdx.x;
-  if (q >= a.col_off[a.n_rec * COL_GRP]) return;
-  float sum = a.gpart[q];
-  for (int cc = 1; cc < n_ch; ++cc) sum += a.gpart[(int64_t)cc * a.n_col + q];
-  const int2 e = a.col[q];
-  float* G = e.x < a.n_in ? a.in.G : a.rec.G;
-  G[e.y] += sum;
 }
 
 // Column view of both projections for k_eprop_wl: entries
@@ -894,7 +880,6 @@ void launch_eprop(hipStream_t s, const EpropArgs& a) {
       const size_t lds = tc_lds_bytes(p.nsteps, a.alif);
       if (a.alif) hipLaunchKernelGGL((k_eprop_tc<true>), dim3(blocks), dim3(TC_NW * WAVE), lds, s, p);
       else hipLaunchKernelGGL((k_eprop_tc<false>), dim3(blocks), dim3(TC_NW * WAVE), lds, s, p);
-      if (n_ch > 1) hipLaunchKernelGGL(k_gpart_sum, dim3((a.n_col + 255) / 256), dim3(256), 0, s, p, n_ch);
     }
   } else if (a.B % 4 == 0 && a.col && a.col_off) {
     const int nw = WL_NW;

@@ -544,45 +544,56 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
     y[q] = k < a.n_out ? a.Y[(int64_t)b * a.n_out + k] : 0.0;
     bias[q] = k < a.n_out ? a.bout[k] : 0.0f;
   }
-  // the drive of RO_TC steps at a time is loaded before any of them is used
-  // (one memory latency per RO_TC steps; the delta stores in between would
-  // otherwise order each step's loads after the previous step's stores)
+  // Steps go in groups of RO_TC: the group's drive is loaded before any of it
+  // is used (one memory latency per group), the leaky outputs of its steps
+  // are advanced in order, and then the group's softmaxes, which depend only
+  // on their own step's outputs, are reduced side by side.
   constexpr int RO_TC = 8;
-  float uc[RO_TC][RO_KMAX];
-  for (int tau = 0; tau < a.nsteps; ++tau) {
-    const int tc = tau % RO_TC;
-    if (tc == 0) {
+  for (int t0 = 0; t0 < a.nsteps; t0 += RO_TC) {
+    const int nt = min(RO_TC, a.nsteps - t0);
+    float uc[RO_TC][RO_KMAX];
 #pragma unroll
-      for (int t = 0; t < RO_TC; ++t) {
-        const int64_t row = ((int64_t)min(tau + t, a.nsteps - 1) * a.B + b) * a.n_out;
+    for (int t = 0; t < RO_TC; ++t) {
+      const int64_t row = ((int64_t)min(t0 + t, a.nsteps - 1) * a.B + b) * a.n_out;
 #pragma unroll
-        for (int q = 0; q < RO_KMAX; ++q) uc[t][q] = a.u[row + min(q * WAVE + lane, a.n_out - 1)];
+      for (int q = 0; q < RO_KMAX; ++q) uc[t][q] = ld_global(a.u + row + min(q * WAVE + lane, a.n_out - 1));
+    }
+    // outputs after each step of the group (steps past the block leave y as it is)
+    float yf[RO_TC][RO_KMAX], m[RO_TC];
+#pragma unroll
+    for (int t = 0; t < RO_TC; ++t) {
+      m[t] = -INFINITY;
+#pragma unroll
+      for (int q = 0; q < RO_KMAX; ++q) {
+        if (t < nt && q * WAVE + lane < a.n_out) y[q] = a.alpha * y[q] + (double)uc[t][q] + (double)bias[q];
+        yf[t][q] = (float)y[q];
+        if (q * WAVE + lane < a.n_out) m[t] = fmaxf(m[t], yf[t][q]);
       }
     }
-    float m = -INFINITY;
 #pragma unroll
-    for (int q = 0; q < RO_KMAX; ++q) {
-      const int k = q * WAVE + lane;
-      float uk = uc[0][q];
+    for (int t = 0; t < RO_TC; ++t) m[t] = wave_max(m[t]);
+    float ex[RO_TC][RO_KMAX], den[RO_TC];
 #pragma unroll
-      for (int t = 1; t < RO_TC; ++t) uk = tc == t ? uc[t][q] : uk;
-      if (k < a.n_out) {
-        y[q] = a.alpha * y[q] + (double)uk + (double)bias[q];
-        m = fmaxf(m, (float)y[q]);
+    for (int t = 0; t < RO_TC; ++t) {
+      den[t] = 0.0f;
+#pragma unroll
+      for (int q = 0; q < RO_KMAX; ++q) {
+        ex[t][q] = expf(yf[t][q] - m[t]);
+        if (q * WAVE + lane < a.n_out) den[t] += ex[t][q];
       }
     }
-    m = wave_max(m);
-    float den = 0.0f;
 #pragma unroll
-    for (int q = 0; q < RO_KMAX; ++q)
-      if (q * WAVE + lane < a.n_out) den += expf((float)y[q] - m);
-    den = wave_sum(den);
+    for (int t = 0; t < RO_TC; ++t) den[t] = wave_sum(den[t]);
 #pragma unroll
-    for (int q = 0; q < RO_KMAX; ++q) {
-      const int k = q * WAVE + lane;
-      if (k < a.n_out) {
-        const float d = expf((float)y[q] - m) / den - (k == label ? 1.0f : 0.0f);
-        a.deltaT[((int64_t)k * a.nslot + a.slot0 + tau) * a.B + b] = d;
+    for (int t = 0; t < RO_TC; ++t) {
+      if (t >= nt) break;
+#pragma unroll
+      for (int q = 0; q < RO_KMAX; ++q) {
+        const int k = q * WAVE + lane;
+        if (k < a.n_out) {
+          const float d = ex[t][q] / den[t] - (k == label ? 1.0f : 0.0f);
+          a.deltaT[((int64_t)k * a.nslot + a.slot0 + t0 + t) * a.B + b] = d;
+        }
       }
     }
   }
@@ -598,35 +609,54 @@ __global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) { readout_body(a
 // section), written straight into the ring [j][slot][b]: lanes over
 // instances, each thread 16 consecutive neurons of a 64-neuron tile whose
 // readout weights are staged in LDS.  blockIdx = (neuron tile, instance tile,
-// step).
+// step).  A thread requests its weights and up to LS_KC deltas before using
+// any (rows and outputs past the ends are read again, clamped, and not used),
+// and the products are added in output order.
+constexpr int LS_KC = 32;
 __device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const int bx, const int by,
                                                      const int bz) {
   __shared__ float w[64][65];  // [k in chunk][j in tile]
-  const int j0 = bx * 64, b = by * 64 + lane_id(), tau = bz;
-  const int jq = wave_id() * 16;  // this wave's 16 neurons of the tile
-  const bool act = b < a.B;
+  const int lane = lane_id(), wv = wave_id();
+  const int j0 = bx * 64, b = by * 64 + lane, tau = bz;
+  const int jq = wv * 16;  // this wave's 16 neurons of the tile
+  const int bl = min(b, a.B - 1), jl = min(j0 + lane, a.n_rec - 1);
+  const int64_t dcol = (int64_t)a.slot0 + tau;
   float acc[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) acc[q] = 0.0f;
   for (int k0 = 0; k0 < a.n_out; k0 += 64) {
     const int kn = min(64, a.n_out - k0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-      const int kk = e / 64, jj = e % 64;
-      w[kk][jj] = (kk < kn && j0 + jj < a.n_rec) ? a.Wout[(int64_t)(k0 + kk) * a.n_rec + j0 + jj] : 0.0f;
+    float wl[16], d[LS_KC];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) wl[i] = ld_global(a.Wout + (int64_t)(k0 + min(wv + 4 * i, kn - 1)) * a.n_rec + jl);
+    auto load_d = [&](int kc) {
+#pragma unroll
+      for (int i = 0; i < LS_KC; ++i)
+        d[i] = ld_global(a.deltaT + ((int64_t)(k0 + min(kc + i, kn - 1)) * a.nslot + dcol) * a.B + bl);
+    };
+    load_d(0);
+    __syncthreads();  // the previous chunk's reads of w are done
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      const int kk = wv + 4 * i;
+      w[kk][lane] = (kk < kn && j0 + lane < a.n_rec) ? wl[i] : 0.0f;
     }
     __syncthreads();
-    for (int kk = 0; kk < kn; ++kk) {
-      const float d = act ? a.deltaT[((int64_t)(k0 + kk) * a.nslot + a.slot0 + tau) * a.B + b] : 0.0f;
+    for (int kc = 0; kc < kn; kc += LS_KC) {
+      if (kc > 0) load_d(kc);
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = fmaf(w[kk][jq + q], d, acc[q]);
+      for (int i = 0; i < LS_KC; ++i) {
+        if (kc + i >= kn) break;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] = fmaf(w[kc + i][jq + q], d[i], acc[q]);
+      }
     }
   }
-  if (!act) return;
+  if (b >= a.B) return;
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int j = j0 + jq + q;
-    if (j < a.n_rec) a.LT[((int64_t)j * a.nslot + a.slot0 + tau) * a.B + b] = acc[q];
+    if (j < a.n_rec) a.LT[((int64_t)j * a.nslot + dcol) * a.B + b] = acc[q];
   }
 }
 __global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
@@ -652,7 +682,9 @@ void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal) {
 
 // Hand-off transpose: [step][B][n] -> [n][nslot][B] (slot slot0 + step) through
 // a 64 x 64 LDS tile, both sides coalesced; 32-bit words are moved unchanged.
-// blockIdx.z enumerates (array, step) pairs.
+// blockIdx.z enumerates (array, step) pairs.  A thread's sixteen loads are all
+// issued before the first is used (past the array's edges the last row or
+// column is read again and not stored), so a workgroup waits for memory once.
 __device__ __forceinline__ void handoff_body(const HandoffArrays& h, const int B, const int bx, const int by,
                                              const int bz) {
   __shared__ uint32_t tile[64][65];
@@ -664,14 +696,22 @@ __device__ __forceinline__ void handoff_body(const HandoffArrays& h, const int B
   const uint32_t* src = h.src[arr] + (int64_t)tau * B * n;
   uint32_t* dst = h.dst[arr];
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  for (int r = ty; r < 64; r += 4) {
-    const int b = b0 + r, j = n0 + tx;
-    tile[r][tx] = (b < B && j < n) ? src[(int64_t)b * n + j] : 0u;
-  }
+  const int jl = min(n0 + tx, n - 1);
+  uint32_t v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = ld_global(src + (int64_t)min(b0 + ty + 4 * i, B - 1) * n + jl);
+#pragma unroll
+  for (int i = 0; i < 16; ++i) tile[ty + 4 * i][tx] = v[i];
   __syncthreads();
-  for (int r = ty; r < 64; r += 4) {
-    const int j = n0 + r, b = b0 + tx;
-    if (j < n && b < B) dst[((int64_t)j * h.nslot[arr] + h.slot0[arr] + tau) * B + b] = tile[tx][r];
+  const int b = b0 + tx;
+  if (b >= B) return;
+  const int64_t col = (int64_t)h.slot0[arr] + tau, nslot = h.nslot[arr];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = tile[tx][ty + 4 * i];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int j = n0 + ty + 4 * i;
+    if (j < n) dst[((int64_t)j * nslot + col) * B + b] = v[i];
   }
 }
 __global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B) {

@@ -62,8 +62,6 @@ template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
 }
-// Sum over the 64 lanes: DPP adds within each row of 16 lanes (quad swaps,
-// half-row and row mirrors), then the four row sums combined in a fixed order.
 // A read through a pointer known to address global memory: a global load
 // counts only in the vector-memory counter, so waits for LDS reads after it
 // do not wait for it (a flat load counts in both).
@@ -72,6 +70,8 @@ __device__ __forceinline__ T ld_global(const T* p) {
   return *(const __attribute__((address_space(1))) T*)p;
 }
 
+// Sum over the 64 lanes: DPP adds within each row of 16 lanes (quad swaps,
+// half-row and row mirrors), then the four row sums combined in a fixed order.
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f32<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_f32<0x4E>(v);   // quad_perm [2,3,0,1]
