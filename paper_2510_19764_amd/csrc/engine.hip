@@ -415,7 +415,7 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   TRY(ar.alloc(&n->cv.col, (size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap));
   n->cv.n_col = (int)((size_t)n->in.n_pre * n->in.cap + (size_t)n->rec.n_pre * n->rec.cap);
   if (B > 128 && B % 4 == 0) {
-    const size_t gx = (size_t)((B + 127) / 128 - 1) * n->cv.n_col;
+    const size_t gx = (size_t)((B + 127) / 128) * n->cv.n_col;
     TRY(ar.alloc(&n->cv.gx, gx));
     launch_fill_zero(s, n->cv.gx, gx * 4);
   }
@@ -492,21 +492,15 @@ UpdateArgs update_args(const rs_eprop* n, uint32_t k) {
   u.Mout = n->Mout; u.Vout = n->Vout; u.Mb = n->Mb; u.Vb = n->Vb;
   u.n_out_elems = (int)(n->p.n_out * n->p.n_rec);
   u.n_b = (int)n->p.n_out;
-  u.gx = n->cv.gx;
-  u.gx_stride = n->cv.n_col;
-  u.gx_n = n->cv.gx ? (n->B + 127) / 128 - 1 : 0;
   return u;
 }
 
-// Bring every chunk's gradient into G (before G is read or written, or rows
-// move, outside the update).
-void fold_gradients(rs_eprop* n, hipStream_t s) {
-  if (n->cv.gx) launch_gx_fold(s, update_args(n, 1));
-}
+void fold_gradients(rs_eprop* n, hipStream_t s);
 
 void do_update(rs_eprop* n, hipStream_t s) {
   n->adam_k += 1;
   n->timer.begin(s, 2);
+  fold_gradients(n, s);
   launch_update(s, update_args(n, n->adam_k));
   n->timer.end(s);
 }
@@ -618,6 +612,12 @@ EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
   a.col_off = n->cv.off; a.col = n->cv.col;
   a.gx = n->cv.gx; a.n_col = n->cv.n_col;
   return a;
+}
+
+// Bring every chunk's gradient into G: before the update, and before G is
+// read or written or rows move outside it.
+void fold_gradients(rs_eprop* n, hipStream_t s) {
+  if (n->cv.gx) launch_gx_fold(s, block_eprop_args(n, 0, 0));
 }
 
 // Run the open block (steps accumulated since the last flush): one forward

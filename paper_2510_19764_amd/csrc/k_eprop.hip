@@ -422,10 +422,11 @@ __global__ void __launch_bounds__(WL_NW * WAVE) k_eprop_wl(EpropArgs a) {
 // 127 (two per lane), c = k % n_ch: with two chunks the XCDs of one parity
 // serve one chunk, so the presynaptic traces an XCD gathers are half of all of
 // them.  Its TC_NW waves take the target's synapses in turn, each with the
-// inputs of its next two synapses in flight.  Chunk 0 adds its part of a
-// synapse's gradient to G; chunk c > 0 adds its part to its own array (gx),
-// which the parameter update (or a fold before G is read or rows move) adds
-// to G in chunk order, so the sums do not depend on scheduling.
+// inputs of its next two synapses in flight.  With one chunk the workgroup
+// adds a synapse's gradient to G; with more, each chunk adds its part to an
+// array of its own by list position (coalesced, where G's slots are
+// scattered), and k_gx_fold adds the arrays to G in chunk order before the
+// parameter update, so the sums do not depend on scheduling.
 constexpr int TC_NW = 8;
 constexpr int TC_IPL = 2;                 // instances per lane
 constexpr int TC_CH = TC_IPL * WAVE;      // instances per chunk
@@ -537,8 +538,7 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
   // launch and this launch's part, gathered as the synapses run and stored
   // once per batch
   float gbat = 0.f, gacc = 0.f;
-  float* const gx_in = c == 0 ? a.in.G : a.gx + (int64_t)(c - 1) * a.n_col;
-  float* const gx_rec = c == 0 ? a.rec.G : gx_in + (int64_t)a.in.n_pre * a.in.cap;
+  float* const gpos = n_ch > 1 ? a.gx + (int64_t)c * a.n_col : nullptr;
   auto load = [&](int n, In& s) {
     const int r = __builtin_amdgcn_readlane(ents.x, n), slot = __builtin_amdgcn_readlane(ents.y, n);
     s.fin = r < a.n_in;
@@ -592,7 +592,8 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     const int nb = min(WAVE, (q1 - 1 - base) / TC_NW + 1);  // this wave's synapses in the batch
     ents = a.col[base + TC_NW * min(lane, nb - 1)];
     const bool efin = ents.x < a.n_in;
-    gbat = (efin ? gx_in : gx_rec)[ents.y];
+    float* const gl = gpos ? gpos + base + TC_NW * min(lane, nb - 1) : (efin ? a.in.G : a.rec.G) + ents.y;
+    gbat = *gl;
     load(0, s0);
     load(min(1, nb - 1), s1);
 #pragma unroll 1
@@ -607,8 +608,29 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
       run(s2);
       if (++i >= nb) break;
     }
-    if (lane < nb) (efin ? gx_in : gx_rec)[ents.y] = gbat + gacc;
+    if (lane < nb) *gl = gbat + gacc;
   }
+}
+
+// The chunks' gradients of every listed synapse added to its G in chunk
+// order and cleared (each slot is listed once).
+__global__ void __launch_bounds__(256) k_gx_fold(EpropArgs a, int n_ch) {
+  const int q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= a.col_off[a.n_rec * COL_GRP]) return;
+  const int2 e = a.col[q];
+  float* G = (e.x < a.n_in ? a.in.G : a.rec.G) + e.y;
+  float g = *G;
+  for (int c = 0; c < n_ch; ++c) {
+    g += a.gx[(int64_t)c * a.n_col + q];
+    a.gx[(int64_t)c * a.n_col + q] = 0.0f;
+  }
+  *G = g;
+}
+
+void launch_gx_fold(hipStream_t s, const EpropArgs& a) {
+  if (!a.gx || a.n_col <= 0) return;
+  const int n_ch = (a.B + TC_CH - 1) / TC_CH;
+  hipLaunchKernelGGL(k_gx_fold, dim3((a.n_col + 255) / 256), dim3(256), 0, s, a, n_ch);
 }
 
 // Column view of both projections for k_eprop_wl: entries

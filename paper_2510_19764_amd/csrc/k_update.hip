@@ -3,8 +3,6 @@
 // regularisation"), one Adam step (Kingma & Ba defaults), gradient cleared.
 // One thread per slot of the padded row arrays; slots past a row's length are
 // skipped, the dense readout follows in the same grid.
-#include <algorithm>
-
 #include "rs_device.hpp"
 #include "rs_kernels.hpp"
 
@@ -33,21 +31,10 @@ __device__ __forceinline__ AdamC adam_c(const UpdateArgs& a) {
   return {a.adam_tab[2 * k], a.adam_tab[2 * k + 1]};
 }
 
-// G of slot q plus the per-chunk gradients (chunk order), which are cleared;
-// gx is the projection's first array.
-__device__ __forceinline__ float fold_slot(float g, float* gx, int64_t q, const UpdateArgs& a) {
-  for (int c = 0; c < a.gx_n; ++c) {
-    g += gx[c * a.gx_stride + q];
-    gx[c * a.gx_stride + q] = 0.0f;
-  }
-  return g;
-}
-
-__device__ __forceinline__ void update_slot(const ProjDev& P, float* gx, int64_t q, bool l1, const UpdateArgs& a,
-                                            AdamC c) {
+__device__ __forceinline__ void update_slot(const ProjDev& P, int64_t q, bool l1, const UpdateArgs& a, AdamC c) {
   const int i = (int)(q / P.cap), k = (int)(q % P.cap);
   if (k >= P.len[i]) return;
-  float g = fold_slot(P.G[q], gx, q, a) / (float)a.B;
+  float g = P.G[q] / (float)a.B;
   if (l1) {
     const int j = P.ind[q];
     g += get_bit(P.sign, P.words, i, j) ? -a.l1 : a.l1;
@@ -67,9 +54,9 @@ __device__ __forceinline__ void update_body(const UpdateArgs& a, const int blk, 
   const int64_t stride = (int64_t)nblk * UPD_NT;
   for (int64_t q = (int64_t)blk * UPD_NT + threadIdx.x; q < total; q += stride) {
     if (q < n_in) {
-      update_slot(a.in, a.gx, q, a.l1_in, a, c);
+      update_slot(a.in, q, a.l1_in, a, c);
     } else if (q < n_in + n_rec) {
-      update_slot(a.rec, a.gx ? a.gx + n_in : nullptr, q - n_in, a.l1_rec, a, c);
+      update_slot(a.rec, q - n_in, a.l1_rec, a, c);
     } else if (q < n_in + n_rec + a.n_out_elems) {
       const int64_t r = q - n_in - n_rec;
       float w = a.Wout[r], m = a.Mout[r], v = a.Vout[r];
@@ -113,23 +100,6 @@ void launch_update_multi(hipStream_t s, const UpdateArgs* A, const int4* work, i
 
 void launch_update(hipStream_t s, const UpdateArgs& a) {
   hipLaunchKernelGGL(k_update, dim3((unsigned)update_blocks(a)), dim3(UPD_NT), 0, s, a);
-}
-
-// Every slot of both projections (padding slots hold zeros in gx and keep
-// their G).
-__global__ void __launch_bounds__(UPD_NT) k_gx_fold(UpdateArgs a) {
-  const int64_t n_in = (int64_t)a.in.n_pre * a.in.cap, n = n_in + (int64_t)a.rec.n_pre * a.rec.cap;
-  for (int64_t q = (int64_t)blockIdx.x * UPD_NT + threadIdx.x; q < n; q += (int64_t)gridDim.x * UPD_NT) {
-    float* G = q < n_in ? a.in.G + q : a.rec.G + (q - n_in);
-    *G = fold_slot(*G, a.gx, q, a);
-  }
-}
-
-void launch_gx_fold(hipStream_t s, const UpdateArgs& a) {
-  if (a.gx_n <= 0) return;
-  const int64_t n = (int64_t)a.in.n_pre * a.in.cap + (int64_t)a.rec.n_pre * a.rec.cap;
-  const int64_t blocks = std::min<int64_t>((n + UPD_NT - 1) / UPD_NT, 4096);
-  if (blocks > 0) hipLaunchKernelGGL(k_gx_fold, dim3((unsigned)blocks), dim3(UPD_NT), 0, s, a);
 }
 
 }  // namespace rs

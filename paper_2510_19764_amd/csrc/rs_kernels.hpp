@@ -33,10 +33,10 @@ struct ColumnView {
   int* off;          // [n_rec*COL_GROUPS_MAX + 1]
   int2* col;         // [n_in*cap_in + n_rec*cap_rec]
   // the transfer-coefficient e-prop kernel with more than 128 instances:
-  // the gradient of instance chunks 1, 2, ... accumulates in arrays of its
-  // own, by slot (input rows, then recurrent rows), until the update or a
-  // fold adds them to G in chunk order; zero otherwise
-  float* gx;         // [ceil(B/128) - 1][n_in*cap_in + n_rec*cap_rec]
+  // each instance chunk's gradient accumulates by list position until a fold
+  // (before the update, or before G is read or written or rows move) adds
+  // the chunks to G in chunk order and clears them; zero otherwise
+  float* gx;         // [ceil(B/128)][n_in*cap_in + n_rec*cap_rec]
   int n_col;         // n_in*cap_in + n_rec*cap_rec
 };
 
@@ -141,6 +141,9 @@ struct EpropArgs {
   float* gx; int n_col;                  // ColumnView's per-chunk gradients (B > 128)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+// Add the per-chunk gradients (a.gx, B > 128) to G in chunk order and clear
+// them; reads the column view that the e-prop launches used.
+void launch_gx_fold(hipStream_t s, const EpropArgs& a);
 // Default steps per eligibility block (one e-prop launch) for batch B.
 int eprop_default_block(int B, uint32_t update_interval);
 // Default block lengths when automatic updates run every update_interval
@@ -166,14 +169,8 @@ struct UpdateArgs {
   // replayed launches: the bias corrections of update k = *adam_base + adam_off
   // come from adam_tab[2 min(k, adam_kmax)], [.. + 1] (inv_c1, inv_c2); null: the fields above
   const float* adam_tab; const uint32_t* adam_base; int adam_off, adam_kmax;
-  // per-chunk gradients of the transfer-coefficient e-prop kernel, added to
-  // G before the step and cleared: gx_n arrays of gx_stride slots (input
-  // rows, then recurrent rows); gx_n = 0 without them
-  float* gx; int64_t gx_stride; int gx_n;
 };
 void launch_update(hipStream_t s, const UpdateArgs& a);
-// Add the per-chunk gradients to G (chunk order) and clear them.
-void launch_gx_fold(hipStream_t s, const UpdateArgs& a);
 int update_blocks(const UpdateArgs& a);
 // work[g] = (network, block, blocks of that network)
 void launch_update_multi(hipStream_t s, const UpdateArgs* A, const int4* work, int n_work);
