@@ -532,14 +532,17 @@ void launch_fwd(hipStream_t s, const FwdArgs& a_in) {
 // goes into the ring [k][slot][b].  Labels outside 0..n_out-1 contribute no
 // target term.
 constexpr int RO_KMAX = 4;  // n_out <= 4 * WAVE
+// KMAX output chunks of 64 per lane (KMAX = 1 for n_out <= 64: fewer registers,
+// so a workgroup fits beside the e-prop launch's)
+template <int KMAX>
 __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx) {
   const int b = bx * 4 + wave_id(), lane = lane_id();
   if (b >= a.B) return;
   const int label = a.labels[b];
-  double y[RO_KMAX];
-  float bias[RO_KMAX];
+  double y[KMAX];
+  float bias[KMAX];
 #pragma unroll
-  for (int q = 0; q < RO_KMAX; ++q) {
+  for (int q = 0; q < KMAX; ++q) {
     const int k = q * WAVE + lane;
     y[q] = k < a.n_out ? a.Y[(int64_t)b * a.n_out + k] : 0.0;
     bias[q] = k < a.n_out ? a.bout[k] : 0.0f;
@@ -551,20 +554,20 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
   constexpr int RO_TC = 8;
   for (int t0 = 0; t0 < a.nsteps; t0 += RO_TC) {
     const int nt = min(RO_TC, a.nsteps - t0);
-    float uc[RO_TC][RO_KMAX];
+    float uc[RO_TC][KMAX];
 #pragma unroll
     for (int t = 0; t < RO_TC; ++t) {
       const int64_t row = ((int64_t)min(t0 + t, a.nsteps - 1) * a.B + b) * a.n_out;
 #pragma unroll
-      for (int q = 0; q < RO_KMAX; ++q) uc[t][q] = ld_global(a.u + row + min(q * WAVE + lane, a.n_out - 1));
+      for (int q = 0; q < KMAX; ++q) uc[t][q] = ld_global(a.u + row + min(q * WAVE + lane, a.n_out - 1));
     }
     // outputs after each step of the group (steps past the block leave y as it is)
-    float yf[RO_TC][RO_KMAX], m[RO_TC];
+    float yf[RO_TC][KMAX], m[RO_TC];
 #pragma unroll
     for (int t = 0; t < RO_TC; ++t) {
       m[t] = -INFINITY;
 #pragma unroll
-      for (int q = 0; q < RO_KMAX; ++q) {
+      for (int q = 0; q < KMAX; ++q) {
         if (t < nt && q * WAVE + lane < a.n_out) y[q] = a.alpha * y[q] + (double)uc[t][q] + (double)bias[q];
         yf[t][q] = (float)y[q];
         if (q * WAVE + lane < a.n_out) m[t] = fmaxf(m[t], yf[t][q]);
@@ -572,12 +575,12 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
     }
 #pragma unroll
     for (int t = 0; t < RO_TC; ++t) m[t] = wave_max(m[t]);
-    float ex[RO_TC][RO_KMAX], den[RO_TC];
+    float ex[RO_TC][KMAX], den[RO_TC];
 #pragma unroll
     for (int t = 0; t < RO_TC; ++t) {
       den[t] = 0.0f;
 #pragma unroll
-      for (int q = 0; q < RO_KMAX; ++q) {
+      for (int q = 0; q < KMAX; ++q) {
         ex[t][q] = expf(yf[t][q] - m[t]);
         if (q * WAVE + lane < a.n_out) den[t] += ex[t][q];
       }
@@ -588,7 +591,7 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
     for (int t = 0; t < RO_TC; ++t) {
       if (t >= nt) break;
 #pragma unroll
-      for (int q = 0; q < RO_KMAX; ++q) {
+      for (int q = 0; q < KMAX; ++q) {
         const int k = q * WAVE + lane;
         if (k < a.n_out) {
           const float d = ex[t][q] / den[t] - (k == label ? 1.0f : 0.0f);
@@ -598,12 +601,13 @@ __device__ __forceinline__ void readout_body(const ReadoutArgs& a, const int bx)
     }
   }
 #pragma unroll
-  for (int q = 0; q < RO_KMAX; ++q) {
+  for (int q = 0; q < KMAX; ++q) {
     const int k = q * WAVE + lane;
     if (k < a.n_out) a.Y[(int64_t)b * a.n_out + k] = y[q];
   }
 }
-__global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) { readout_body(a, blockIdx.x); }
+template <int KMAX>
+__global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) { readout_body<KMAX>(a, blockIdx.x); }
 
 // Learning signal L_j = sum_k W_out[k][j] delta_k (recurrent classifier
 // section), written straight into the ring [j][slot][b]: lanes over
@@ -611,11 +615,14 @@ __global__ void __launch_bounds__(256) k_readout(ReadoutArgs a) { readout_body(a
 // readout weights are staged in LDS.  blockIdx = (neuron tile, instance tile,
 // step).  A thread requests its weights and up to LS_KC deltas before using
 // any (rows and outputs past the ends are read again, clamped, and not used),
-// and the products are added in output order.
-constexpr int LS_KC = 32;
-__device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const int bx, const int by,
-                                                     const int bz) {
-  __shared__ float w[64][65];  // [k in chunk][j in tile]
+// and the products are added in output order.  The staged weights take
+// min(n_out, 64) rows of LDS (5.2 KB for 20 outputs), so a workgroup fits on
+// a CU beside three e-prop workgroups.
+constexpr int LS_KC = 16;
+constexpr int LS_LD = 65;  // LDS row pitch in floats
+inline size_t ls_lds_bytes(int n_out) { return (size_t)(n_out < 64 ? n_out : 64) * LS_LD * sizeof(float); }
+__device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const int bx, const int by, const int bz,
+                                                     float* w /* [min(n_out, 64)][LS_LD]: [k in chunk][j in tile] */) {
   const int lane = lane_id(), wv = wave_id();
   const int j0 = bx * 64, b = by * 64 + lane, tau = bz;
   const int jq = wv * 16;  // this wave's 16 neurons of the tile
@@ -639,7 +646,7 @@ __device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
       const int kk = wv + 4 * i;
-      w[kk][lane] = (kk < kn && j0 + lane < a.n_rec) ? wl[i] : 0.0f;
+      if (kk < kn) w[kk * LS_LD + lane] = j0 + lane < a.n_rec ? wl[i] : 0.0f;
     }
     __syncthreads();
     for (int kc = 0; kc < kn; kc += LS_KC) {
@@ -648,7 +655,7 @@ __device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const
       for (int i = 0; i < LS_KC; ++i) {
         if (kc + i >= kn) break;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] = fmaf(w[kc + i][jq + q], d[i], acc[q]);
+        for (int q = 0; q < 16; ++q) acc[q] = fmaf(w[(kc + i) * LS_LD + jq + q], d[i], acc[q]);
       }
     }
   }
@@ -660,7 +667,8 @@ __device__ __forceinline__ void learning_signal_body(const ReadoutArgs& a, const
   }
 }
 __global__ void __launch_bounds__(256) k_learning_signal(ReadoutArgs a) {
-  learning_signal_body(a, blockIdx.x, blockIdx.y, blockIdx.z);
+  extern __shared__ float ls_w[];
+  learning_signal_body(a, blockIdx.x, blockIdx.y, blockIdx.z, ls_w);
 }
 
 int readout_grid(const ReadoutArgs& a) { return (a.B + 3) / 4; }
@@ -672,45 +680,52 @@ void learning_signal_grid(const ReadoutArgs& a, int g[3]) {
 
 void launch_readout(hipStream_t s, const ReadoutArgs& a, bool learning_signal) {
   if (a.nsteps <= 0) return;
-  hipLaunchKernelGGL(k_readout, dim3(readout_grid(a)), dim3(256), 0, s, a);
+  if (a.n_out <= WAVE) hipLaunchKernelGGL(k_readout<1>, dim3(readout_grid(a)), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_readout<RO_KMAX>, dim3(readout_grid(a)), dim3(256), 0, s, a);
   if (learning_signal) {
     int g[3];
     learning_signal_grid(a, g);
-    hipLaunchKernelGGL(k_learning_signal, dim3(g[0], g[1], g[2]), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_learning_signal, dim3(g[0], g[1], g[2]), dim3(256), ls_lds_bytes(a.n_out), s, a);
   }
 }
 
 // Hand-off transpose: [step][B][n] -> [n][nslot][B] (slot slot0 + step) through
-// a 64 x 64 LDS tile, both sides coalesced; 32-bit words are moved unchanged.
-// blockIdx.z enumerates (array, step) pairs.  A thread's sixteen loads are all
-// issued before the first is used (past the array's edges the last row or
-// column is read again and not stored), so a workgroup waits for memory once.
+// a 32 (instances) x 64 (neurons) LDS tile, both sides coalesced; 32-bit words
+// are moved unchanged.  blockIdx.z enumerates (array, step) pairs.  A thread's
+// eight loads are all issued before the first is used (past the array's edges
+// the last row or column is read again and not stored), so a workgroup waits
+// for memory once.  The tile's 8.3 KB fit on a CU beside three e-prop
+// workgroups.
+constexpr int HO_TB = 32;  // instances per transpose tile
 __device__ __forceinline__ void handoff_body(const HandoffArrays& h, const int B, const int bx, const int by,
                                              const int bz) {
-  __shared__ uint32_t tile[64][65];
+  __shared__ uint32_t tile[HO_TB][65];
   int z = bz, arr = 0;
   while (arr + 1 < HANDOFF_ARRAYS && z >= h.steps[arr]) z -= h.steps[arr++];
   const int tau = z, n = h.n[arr];
-  const int n0 = bx * 64, b0 = by * 64;
+  const int n0 = bx * 64, b0 = by * HO_TB;
   if (n0 >= n || b0 >= B || tau >= h.steps[arr]) return;
   const uint32_t* src = h.src[arr] + (int64_t)tau * B * n;
   uint32_t* dst = h.dst[arr];
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
+  // loads: 64 neurons (lanes) x 4 rows of instances per pass
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   const int jl = min(n0 + tx, n - 1);
-  uint32_t v[16];
+  uint32_t v[8];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = ld_global(src + (int64_t)min(b0 + ty + 4 * i, B - 1) * n + jl);
+  for (int i = 0; i < 8; ++i) v[i] = ld_global(src + (int64_t)min(b0 + ty + 4 * i, B - 1) * n + jl);
 #pragma unroll
-  for (int i = 0; i < 16; ++i) tile[ty + 4 * i][tx] = v[i];
+  for (int i = 0; i < 8; ++i) tile[ty + 4 * i][tx] = v[i];
   __syncthreads();
-  const int b = b0 + tx;
+  // stores: 32 instances (lanes) x 8 neurons per pass
+  const int sx = threadIdx.x & 31, sy = threadIdx.x >> 5;
+  const int b = b0 + sx;
   if (b >= B) return;
   const int64_t col = (int64_t)h.slot0[arr] + tau, nslot = h.nslot[arr];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) v[i] = tile[tx][ty + 4 * i];
+  for (int i = 0; i < 8; ++i) v[i] = tile[sx][sy + 8 * i];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    const int j = n0 + ty + 4 * i;
+  for (int i = 0; i < 8; ++i) {
+    const int j = n0 + sy + 8 * i;
     if (j < n) dst[((int64_t)j * nslot + col) * B + b] = v[i];
   }
 }
@@ -730,13 +745,14 @@ __global__ void __launch_bounds__(256) k_readout_multi(const ReadoutArgs* __rest
                                                        const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
   const ReadoutArgs a = A[w.x];
-  readout_body(a, w.y);
+  readout_body<RO_KMAX>(a, w.y);
 }
 __global__ void __launch_bounds__(256) k_learning_signal_multi(const ReadoutArgs* __restrict__ A,
                                                                const int4* __restrict__ work) {
   const int4 w = work[blockIdx.x];
   const ReadoutArgs a = A[w.x];
-  learning_signal_body(a, w.y, w.z, w.w);
+  __shared__ float w_tile[64 * LS_LD];  // networks of any output count
+  learning_signal_body(a, w.y, w.z, w.w, w_tile);
 }
 
 void handoff_grid(const HandoffArrays& h, int B, int g[3]) {
@@ -746,7 +762,7 @@ void handoff_grid(const HandoffArrays& h, int B, int g[3]) {
     zs += h.steps[q];
   }
   g[0] = (nmax + 63) / 64;
-  g[1] = (B + 63) / 64;
+  g[1] = (B + HO_TB - 1) / HO_TB;
   g[2] = zs;
 }
 
