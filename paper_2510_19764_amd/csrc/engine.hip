@@ -225,7 +225,7 @@ struct rs_eprop {
 
 namespace {
 
-rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr) {
+rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr, bool interleave) {
   const size_t n = (size_t)P.n_pre * P.cap;
   TRY(ar.alloc(&P.len, (size_t)P.n_pre));
   TRY(ar.alloc(&P.ind, n));
@@ -233,8 +233,9 @@ rs_status alloc_proj(Arena& ar, ProjDev& P, int B, bool alif, bool deepr) {
   TRY(ar.alloc(&P.m, n));
   TRY(ar.alloc(&P.v, n));
   TRY(ar.alloc(&P.G, n));
-  TRY(ar.alloc(&P.ebar, n * B));
-  if (alif) TRY(ar.alloc(&P.eps, n * B));
+  P.erec = alif && interleave ? 2 * B : B;
+  TRY(ar.alloc(&P.ebar, n * P.erec));
+  if (alif && !interleave) TRY(ar.alloc(&P.eps, n * B));
   TRY(ar.alloc(&P.dormant, (size_t)P.n_pre));
   TRY(ar.alloc(&P.assigned, (size_t)P.n_pre));
   if (deepr) {
@@ -249,7 +250,7 @@ void zero_proj_state(hipStream_t s, const ProjDev& P, int B) {
   launch_fill_zero(s, P.m, n * 4);
   launch_fill_zero(s, P.v, n * 4);
   launch_fill_zero(s, P.G, n * 4);
-  launch_fill_zero(s, P.ebar, n * B * 4);
+  launch_fill_zero(s, P.ebar, n * P.erec * 4);
   if (P.eps) launch_fill_zero(s, P.eps, n * B * 4);
   launch_fill_zero(s, P.dormant, (size_t)P.n_pre * 4);
   launch_fill_zero(s, P.assigned, (size_t)P.n_pre * 4);
@@ -333,8 +334,9 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   };
   TRY(setup(n->in, prm->n_in, prm->n_rec, 0, 0, prm->p_in, prm->cap_in));
   TRY(setup(n->rec, prm->n_rec, prm->n_rec, 1, 1, prm->p_rec, prm->cap_rec));
-  TRY(alloc_proj(n->arena, n->in, B, prm->alif, prm->deepr_mask & 1));
-  TRY(alloc_proj(n->arena, n->rec, B, prm->alif, prm->deepr_mask & 2));
+  const bool il = eprop_interleaved(B, prm->alif != 0);
+  TRY(alloc_proj(n->arena, n->in, B, prm->alif, prm->deepr_mask & 1, il));
+  TRY(alloc_proj(n->arena, n->rec, B, prm->alif, prm->deepr_mask & 2, il));
   Arena& ar = n->arena;
   const size_t NR = prm->n_rec, NI = prm->n_in, K = prm->n_out;
   TRY(ar.alloc(&n->V, B * NR));
@@ -466,7 +468,7 @@ void reset_state(rs_eprop* n, hipStream_t s) {
   launch_fill_zero(s, n->zbar, B * NR * 4);
   for (ProjDev* P : {&n->in, &n->rec}) {
     const size_t m = (size_t)P->n_pre * P->cap * B * 4;
-    launch_fill_zero(s, P->ebar, m);
+    launch_fill_zero(s, P->ebar, (size_t)P->n_pre * P->cap * P->erec * 4);
     if (P->eps) launch_fill_zero(s, P->eps, m);
   }
 }
@@ -725,6 +727,7 @@ struct VarRef {
   void* ptr;
   size_t bytes;
   size_t rows = 0, pitch = 0;  // strided ring slot: rows of bytes/rows, pitch apart
+  int il = -1;                 // >= 0: float il of every pair of an interleaved array of 2 bytes/4 floats
 };
 
 bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
@@ -765,8 +768,18 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
     case RS_P_M: *r = {P.m, ns * 4}; return true;
     case RS_P_V: *r = {P.v, ns * 4}; return true;
     case RS_P_G: *r = {P.G, ns * 4}; return true;
-    case RS_P_EPS: *r = {P.eps, ns * B * 4}; return P.eps != nullptr;
-    case RS_P_EBAR: *r = {P.ebar, ns * B * 4}; return true;
+    case RS_P_EPS:
+      if ((size_t)P.erec == 2 * B) {  // the second float of each interleaved pair
+        *r = {P.ebar, ns * B * 4};
+        r->il = 1;
+        return true;
+      }
+      *r = {P.eps, ns * B * 4};
+      return P.eps != nullptr;
+    case RS_P_EBAR:
+      *r = {P.ebar, ns * B * 4};
+      if ((size_t)P.erec == 2 * B) r->il = 0;
+      return true;
     case RS_P_CONN: *r = {P.conn, (size_t)P.n_pre * P.words * 4}; return P.conn != nullptr;
     case RS_P_SIGN: *r = {P.sign, (size_t)P.n_pre * P.words * 4}; return P.sign != nullptr;
     case RS_P_DORMANT: *r = {P.dormant, (size_t)P.n_pre * 4}; return true;
@@ -906,6 +919,15 @@ rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
   if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
   if (var % 0x100 == RS_P_G && var >= 0x100) fold_gradients(n, n->stream);
+  if (r.il >= 0) {  // one float of each pair of the interleaved eligibility state
+    const size_t cnt = bytes / 4;
+    std::vector<float> both(2 * cnt);
+    HIP_OK(hipMemcpyAsync(both.data(), r.ptr, 2 * bytes, hipMemcpyDeviceToHost, n->stream));
+    HIP_OK(hipStreamSynchronize(n->stream));
+    float* out = (float*)host;
+    for (size_t k = 0; k < cnt; ++k) out[k] = both[2 * k + r.il];
+    return RS_OK;
+  }
   if (r.rows) {
     const size_t w = bytes / r.rows;
     HIP_OK(hipMemcpy2DAsync(host, w, r.ptr, r.pitch, w, r.rows, hipMemcpyDeviceToHost, n->stream));
@@ -949,6 +971,17 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
   // the chunks' parts go into G first: a new G replaces them too, and new
   // rows must not inherit them at slots the update no longer visits
   fold_gradients(n, n->stream);
+  if (r.il >= 0) {  // replace one float of each pair of the interleaved eligibility state
+    const size_t cnt = bytes / 4;
+    std::vector<float> both(2 * cnt);
+    HIP_OK(hipMemcpyAsync(both.data(), r.ptr, 2 * bytes, hipMemcpyDeviceToHost, n->stream));
+    HIP_OK(hipStreamSynchronize(n->stream));
+    const float* in = (const float*)host;
+    for (size_t k = 0; k < cnt; ++k) both[2 * k + r.il] = in[k];
+    HIP_OK(hipMemcpyAsync(r.ptr, both.data(), 2 * bytes, hipMemcpyHostToDevice, n->stream));
+    HIP_OK(hipStreamSynchronize(n->stream));
+    return RS_OK;
+  }
   HIP_OK(hipMemcpyAsync(r.ptr, host, bytes, hipMemcpyHostToDevice, n->stream));
   if (pj >= 0 && (f == RS_P_LEN || f == RS_P_IND)) rebuild_columns(n, n->stream);
   HIP_OK(hipStreamSynchronize(n->stream));
@@ -1944,7 +1977,7 @@ rs_status multi_build_tables(rs_multi* m) {
     zr.push_back({e->zbar, B * NR * 4});
     for (const ProjDev* P : {&e->in, &e->rec}) {
       const size_t bytes = (size_t)P->n_pre * P->cap * B * 4;
-      zr.push_back({P->ebar, bytes});
+      zr.push_back({P->ebar, (size_t)P->n_pre * P->cap * P->erec * 4});
       if (P->eps) zr.push_back({P->eps, bytes});
     }
   }

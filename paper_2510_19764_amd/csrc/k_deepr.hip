@@ -72,12 +72,12 @@ __device__ __forceinline__ void elim_body(const ProjDev& P, const int B, long lo
     P.G[d] = P.G[s];
   }
   if (P.ebar) {
+    const int R = P.erec;
     for (int q = 0; q < pairs; ++q) {
-      const int64_t d = (base + holes[q]) * B, s = (base + tail[q]) * B;
-      for (int c = lane; c < B; c += WAVE) {
-        P.ebar[d + c] = P.ebar[s + c];
-        if (P.eps) P.eps[d + c] = P.eps[s + c];
-      }
+      const int64_t d = base + holes[q], s = base + tail[q];
+      for (int c = lane; c < R; c += WAVE) P.ebar[d * R + c] = P.ebar[s * R + c];
+      if (P.eps)
+        for (int c = lane; c < B; c += WAVE) P.eps[d * B + c] = P.eps[s * B + c];
     }
   }
   if (lane == 0) {
@@ -222,12 +222,11 @@ __device__ __forceinline__ void form_body(const uint64_t seed, const ProjDev& P,
     P.G[base + k] = 0.0f;
   }
   if (P.ebar) {
+    const int R = P.erec;
     for (int k = 0; k < nf; ++k) {
-      const int64_t s = (base + k) * B;
-      for (int c = lane; c < B; c += WAVE) {
-        P.ebar[s + c] = 0.0f;
-        if (P.eps) P.eps[s + c] = 0.0f;
-      }
+      for (int c = lane; c < R; c += WAVE) P.ebar[(base + k) * R + c] = 0.0f;
+      if (P.eps)
+        for (int c = lane; c < B; c += WAVE) P.eps[(base + k) * B + c] = 0.0f;
     }
   }
   if (lane == 0) {

@@ -546,8 +546,15 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     s.n = n;
     const int i = s.fin ? r : r - a.n_in;
     const int64_t rec = (int64_t)slot * B + bi;
-    s.eb = __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.ebar : a.rec.ebar) + rec));
-    s.ep = ALIF ? __builtin_nontemporal_load((const tcv*)((s.fin ? a.in.eps : a.rec.eps) + rec)) : (tcv)0.f;
+    const float* el = s.fin ? a.in.ebar : a.rec.ebar;
+    if (ALIF) {  // ebar and eps of the lane's two instances, interleaved: one 16-byte record
+      const f4 v = __builtin_nontemporal_load((const f4*)(el + 2 * rec));
+      s.eb = (tcv){v.x, v.z};
+      s.ep = (tcv){v.y, v.w};
+    } else {
+      s.eb = __builtin_nontemporal_load((const tcv*)(el + rec));
+      s.ep = (tcv)0.f;
+    }
     s.pr = *(const tcv*)((s.fin ? a.x0 : a.z0) + (int64_t)i * B + bi);
     s.bits = *(const tcu*)((s.fin ? a.xbits : a.zbits) + (int64_t)i * B + bi);
   };
@@ -579,8 +586,9 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
     const int fin = __builtin_amdgcn_readfirstlane(s.fin), slot = __builtin_amdgcn_readfirstlane(s.slot);
     const int64_t rec = (int64_t)slot * B + bi;
     if (act) {
-      __builtin_nontemporal_store(eb, (tcv*)((fin ? a.in.ebar : a.rec.ebar) + rec));
-      if (ALIF) __builtin_nontemporal_store(ep, (tcv*)((fin ? a.in.eps : a.rec.eps) + rec));
+      float* el = fin ? a.in.ebar : a.rec.ebar;
+      if (ALIF) __builtin_nontemporal_store((f4){eb.x, ep.x, eb.y, ep.y}, (f4*)(el + 2 * rec));
+      else __builtin_nontemporal_store(eb, (tcv*)(el + rec));
     }
     const float part = wave_sum(act ? g.x + g.y : 0.f);
     gacc = lane == s.n ? part : gacc;
@@ -887,6 +895,8 @@ int eprop_default_block(int B, uint32_t update_interval) {
   const uint32_t n = (update_interval + TC_TB - 1) / TC_TB;
   return (int)((update_interval + n - 1) / n);
 }
+
+bool eprop_interleaved(int B, bool alif) { return alif && B % 4 == 0 && B >= TC_MIN_B; }
 
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;

@@ -67,6 +67,7 @@ extern "C" rs_status rs_deepr_rewire_noalloc(const rs_deepr_rows* r, uint64_t se
   P.G = r->G;
   P.eps = r->eps;
   P.ebar = r->ebar;
+  P.erec = (int)r->batch;  // the caller's ebar and eps are separate arrays
   P.conn = r->conn;
   P.sign = r->sign;
   P.dormant = (int*)base;                           // written for every row by the elimination

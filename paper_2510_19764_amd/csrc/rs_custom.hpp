@@ -124,11 +124,10 @@ __global__ void __launch_bounds__(WAVE) k_row_update(ProjDev P, Rule rule, uint6
   }
   if (P.ebar)
     for (int q = 0; q < pairs; ++q) {
-      const int64_t d = (base + holes[q]) * B, s = (base + tail[q]) * B;
-      for (int c = lane; c < B; c += WAVE) {
-        P.ebar[d + c] = P.ebar[s + c];
-        if (P.eps) P.eps[d + c] = P.eps[s + c];
-      }
+      const int64_t d = base + holes[q], s = base + tail[q];
+      for (int c = lane; c < P.erec; c += WAVE) P.ebar[d * P.erec + c] = P.ebar[s * P.erec + c];
+      if (P.eps)
+        for (int c = lane; c < B; c += WAVE) P.eps[d * B + c] = P.eps[s * B + c];
     }
   __syncthreads();
   // add_synapse: lane 0 runs the rule's appends
@@ -150,11 +149,10 @@ __global__ void __launch_bounds__(WAVE) k_row_update(ProjDev P, Rule rule, uint6
   }
   if (P.ebar)
     for (int k = 0; k < na; ++k) {
-      const int64_t s = (base + n2 + k) * B;
-      for (int c = lane; c < B; c += WAVE) {
-        P.ebar[s + c] = 0.0f;
-        if (P.eps) P.eps[s + c] = 0.0f;
-      }
+      const int64_t s = base + n2 + k;
+      for (int c = lane; c < P.erec; c += WAVE) P.ebar[s * P.erec + c] = 0.0f;
+      if (P.eps)
+        for (int c = lane; c < B; c += WAVE) P.eps[s * B + c] = 0.0f;
     }
   if (lane == 0) {
     P.len[r] = n2 + na;

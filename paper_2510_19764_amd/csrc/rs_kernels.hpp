@@ -14,8 +14,12 @@ struct ProjDev {
   float* m;          // Adam moments / gradient, may be null
   float* v;
   float* G;
-  float* eps;        // [n_pre*cap*B], null for LIF / untrained
-  float* ebar;       // [n_pre*cap*B], null if untrained
+  float* eps;        // [n_pre*cap*B], null for LIF / untrained / interleaved
+  float* ebar;       // [n_pre*cap*B], or [n_pre*cap*B][2] interleaved; null if untrained
+  // floats per slot in ebar: B, or 2B when ebar holds ebar and eps of each
+  // instance side by side (the transfer-coefficient kernel's ALIF layout, eps
+  // null); record moves copy erec floats of ebar (and B of eps if present)
+  int erec;
   uint32_t* conn;    // [n_pre*words] DEEP R connectivity bits, may be null
   uint32_t* sign;    // [n_pre*words] DEEP R sign bits, may be null
   int* dormant;      // [n_pre] eliminated per row by the last rewire
@@ -141,6 +145,9 @@ struct EpropArgs {
   float* gx; int n_col;                  // ColumnView's per-chunk gradients (B > 128)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+// Whether a network of batch B keeps ebar and eps interleaved (ALIF under the
+// transfer-coefficient kernel, which reads a synapse's state as one record).
+bool eprop_interleaved(int B, bool alif);
 // Add the per-chunk gradients (a.gx, B > 128) to G in chunk order and clear
 // them; reads the column view that the e-prop launches used.
 void launch_gx_fold(hipStream_t s, const EpropArgs& a);
