@@ -178,8 +178,11 @@ struct rs_eprop {
   // the join at each update covers them all.
   float *psiT = nullptr, *LT = nullptr, *deltaT = nullptr;
   // per segment: traces at the block start and the block's spike bits, [Q][n][B]
+  // each, or (tr_es = 2, the transfer-coefficient kernel) [Q][n][B][2] with a
+  // trace and its spike word side by side (xbitsT = x0T + 1 word, and so on)
   float *x0T = nullptr, *z0T = nullptr;
   uint32_t *xbitsT = nullptr, *zbitsT = nullptr;
+  int tr_es = 1;
   // the forward kernel's coalesced staging of a block, one per ring segment,
   // so that a block's transpose can run beside the next block's forward pass
   uint32_t *stg[HANDOFF_ARRAYS] = {};                 // psi [Q][K][B][NR]; x0, z0, xbits, zbits [Q][B][n]
@@ -361,10 +364,18 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
     n->Q = U ? (int)std::min<uint32_t>(std::max<uint32_t>(nb + 1, 2), RING_MAX) : 2;
   }
   const size_t QS = (size_t)n->Q;
-  TRY(ar.alloc(&n->x0T, QS * NI * B));
-  TRY(ar.alloc(&n->z0T, QS * NR * B));
-  TRY(ar.alloc(&n->xbitsT, QS * NI * B));
-  TRY(ar.alloc(&n->zbitsT, QS * NR * B));
+  if (eprop_tc_path((int)B)) {
+    n->tr_es = 2;
+    TRY(ar.alloc(&n->x0T, QS * NI * B * 2));
+    TRY(ar.alloc(&n->z0T, QS * NR * B * 2));
+    n->xbitsT = (uint32_t*)n->x0T + 1;
+    n->zbitsT = (uint32_t*)n->z0T + 1;
+  } else {
+    TRY(ar.alloc(&n->x0T, QS * NI * B));
+    TRY(ar.alloc(&n->z0T, QS * NR * B));
+    TRY(ar.alloc(&n->xbitsT, QS * NI * B));
+    TRY(ar.alloc(&n->zbitsT, QS * NR * B));
+  }
   n->nslot = n->Q * n->K;
   const size_t NS = (size_t)n->nslot;
   TRY(ar.alloc(&n->psiT, NR * NS * B));
@@ -441,10 +452,12 @@ rs_status create_impl(const rs_eprop_params* prm, void* stream, rs_eprop** out, 
   for (double* q : {n->V, n->A}) launch_fill_zero(s, q, B * NR * 8);
   launch_fill_zero(s, n->zbar, B * NR * 4);
   for (float* q : {n->psiT, n->LT}) launch_fill_zero(s, q, B * NR * NS * 4);
-  launch_fill_zero(s, n->x0T, QS * B * NI * 4);
-  launch_fill_zero(s, n->z0T, QS * B * NR * 4);
-  launch_fill_zero(s, n->xbitsT, QS * B * NI * 4);
-  launch_fill_zero(s, n->zbitsT, QS * B * NR * 4);
+  launch_fill_zero(s, n->x0T, QS * B * NI * 4 * n->tr_es);
+  launch_fill_zero(s, n->z0T, QS * B * NR * 4 * n->tr_es);
+  if (n->tr_es == 1) {
+    launch_fill_zero(s, n->xbitsT, QS * B * NI * 4);
+    launch_fill_zero(s, n->zbitsT, QS * B * NR * 4);
+  }
   launch_fill_zero(s, n->deltaT, B * K * NS * 4);
   launch_fill_zero(s, n->xbar, B * NI * 4);
   launch_fill_zero(s, n->Y, B * K * 8);
@@ -571,9 +584,10 @@ FwdArgs block_fwd_args(const rs_eprop* n, int h, uint64_t t0, int nsteps) {
 HandoffArrays block_handoff_args(const rs_eprop* n, int h, int nsteps) {
   HandoffArrays ho{};
   const size_t NI = n->p.n_in, NR = n->p.n_rec, B = n->B;
-  uint32_t* dst[HANDOFF_ARRAYS] = {(uint32_t*)n->psiT, (uint32_t*)(n->x0T + h * NI * B),
-                                   (uint32_t*)(n->z0T + h * NR * B), n->xbitsT + h * NI * B,
-                                   n->zbitsT + h * NR * B};
+  const size_t es = n->tr_es;
+  uint32_t* dst[HANDOFF_ARRAYS] = {(uint32_t*)n->psiT, (uint32_t*)(n->x0T + h * NI * B * es),
+                                   (uint32_t*)(n->z0T + h * NR * B * es), n->xbitsT + h * NI * B * es,
+                                   n->zbitsT + h * NR * B * es};
   const int dims[HANDOFF_ARRAYS] = {(int)NR, (int)NI, (int)NR, (int)NI, (int)NR};
   for (int q = 0; q < HANDOFF_ARRAYS; ++q) {
     ho.src[q] = stg_seg(n, q, h);
@@ -582,6 +596,7 @@ HandoffArrays block_handoff_args(const rs_eprop* n, int h, int nsteps) {
     ho.steps[q] = q == 0 ? nsteps : 1;  // psi per step into the ring, the rest once per block
     ho.slot0[q] = q == 0 ? h * n->K : 0;
     ho.nslot[q] = q == 0 ? n->nslot : 1;
+    ho.es[q] = q == 0 ? 1 : n->tr_es;
   }
   return ho;
 }
@@ -605,8 +620,10 @@ EpropArgs block_eprop_args(const rs_eprop* n, int h, int nsteps) {
   a.alpha = (float)n->alpha; a.rho = (float)n->rho; a.beta = (float)n->beta;
   a.one_m_rho = (float)(1.0 - n->rho);
   a.in = n->in; a.rec = n->rec;
-  a.x0 = n->x0T + h * NI * B; a.z0 = n->z0T + h * NR * B;
-  a.xbits = n->xbitsT + h * NI * B; a.zbits = n->zbitsT + h * NR * B;
+  const size_t es = n->tr_es;
+  a.x0 = n->x0T + h * NI * B * es; a.z0 = n->z0T + h * NR * B * es;
+  a.xbits = n->xbitsT + h * NI * B * es; a.zbits = n->zbitsT + h * NR * B * es;
+  a.tr_es = n->tr_es;
   a.tofs = 0;
   a.psiT = n->psiT; a.LT = n->LT; a.deltaT = n->deltaT;
   a.slot0 = h * n->K; a.nsteps = nsteps; a.nslot = n->nslot;
@@ -754,7 +771,14 @@ bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
       case RS_MB: *r = {n->Mb, K * 4}; return true;
       case RS_VB: *r = {n->Vb, K * 4}; return true;
       case RS_ZCOUNT: *r = {n->zcount, B * NR * 4}; return true;
-      case RS_ZBITS: *r = {n->zbitsT + (size_t)n->last_seg * NR * B, NR * B * 4}; return !for_write;
+      case RS_ZBITS:
+        if (n->tr_es == 2) {  // the second word of each (trace, spike word) pair
+          *r = {n->z0T + (size_t)n->last_seg * NR * B * 2, NR * B * 4};
+          r->il = 1;
+        } else {
+          *r = {n->zbitsT + (size_t)n->last_seg * NR * B, NR * B * 4};
+        }
+        return !for_write;
       default: return false;
     }
   }

@@ -154,8 +154,10 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
   const int B = a.B, T = a.nsteps;
   const bool wt = j < a.n_rec;
   const uint32_t step_bytes = (uint32_t)B * 4u, blk = (uint32_t)T * step_bytes;
-  const auto rz = buf_rsrc(a.z0 + (int64_t)(wt ? j : 0) * B, step_bytes);
-  const auto rb = buf_rsrc(a.zbits + (int64_t)(wt ? j : 0) * B, step_bytes);
+  // (trace, word) pairs: B % 4 == 0 there, four instances are two 16-byte loads
+  const bool pairs = a.tr_es == 2;
+  const auto rz = buf_rsrc(a.z0 + (int64_t)(wt ? j : 0) * B * (pairs ? 2 : 1), pairs ? 2 * step_bytes : step_bytes);
+  const auto rb = buf_rsrc(a.zbits + (int64_t)(wt ? j : 0) * B * (pairs ? 2 : 1), pairs ? 2 * step_bytes : step_bytes);
   const int ipl = B % 4 == 0 ? 4 : 1;  // instances per lane
   for (int k = 0; k < a.n_out; ++k) {
     const auto rd = buf_rsrc(a.deltaT + ring(a, k, 0), blk);
@@ -165,7 +167,11 @@ __device__ __forceinline__ void readout_grad(const EpropArgs& a, int j, int lane
       f4 z = {1.f, 1.f, 1.f, 1.f};
       v4u w = {0u, 0u, 0u, 0u};
       if (wt) {
-        if (ipl == 4) {
+        if (pairs) {
+          const f4 p0 = buf_ldv<4>(rz, 2 * off, 0), p1 = buf_ldv<4>(rz, 2 * off + 16u, 0);
+          z = (f4){p0.x, p0.z, p1.x, p1.z};
+          w = (v4u){__float_as_uint(p0.y), __float_as_uint(p0.w), __float_as_uint(p1.y), __float_as_uint(p1.w)};
+        } else if (ipl == 4) {
           z = buf_ldv<4>(rz, off, 0);
           w = __builtin_bit_cast(v4u, buf_ldv<4>(rb, off, 0));
         } else {
@@ -555,8 +561,10 @@ __global__ void __launch_bounds__(TC_NW * WAVE) k_eprop_tc(EpropArgs a) {
       s.eb = __builtin_nontemporal_load((const tcv*)(el + rec));
       s.ep = (tcv)0.f;
     }
-    s.pr = *(const tcv*)((s.fin ? a.x0 : a.z0) + (int64_t)i * B + bi);
-    s.bits = *(const tcu*)((s.fin ? a.xbits : a.zbits) + (int64_t)i * B + bi);
+    // the lane's two instances' block-start traces and spike words: one 16-byte (trace, word) pair record
+    const f4 tb = *(const f4*)((s.fin ? a.x0 : a.z0) + ((int64_t)i * B + bi) * 2);
+    s.pr = (tcv){tb.x, tb.z};
+    s.bits = (tcu){__float_as_uint(tb.y), __float_as_uint(tb.w)};
   };
   auto run = [&](const In& s) {
     tcv pr = s.pr;
@@ -896,7 +904,8 @@ int eprop_default_block(int B, uint32_t update_interval) {
   return (int)((update_interval + n - 1) / n);
 }
 
-bool eprop_interleaved(int B, bool alif) { return alif && B % 4 == 0 && B >= TC_MIN_B; }
+bool eprop_tc_path(int B) { return B % 4 == 0 && B >= TC_MIN_B; }
+bool eprop_interleaved(int B, bool alif) { return alif && eprop_tc_path(B); }
 
 void launch_eprop(hipStream_t s, const EpropArgs& a) {
   if (a.nsteps <= 0) return;

@@ -720,13 +720,13 @@ __device__ __forceinline__ void handoff_body(const HandoffArrays& h, const int B
   const int sx = threadIdx.x & 31, sy = threadIdx.x >> 5;
   const int b = b0 + sx;
   if (b >= B) return;
-  const int64_t col = (int64_t)h.slot0[arr] + tau, nslot = h.nslot[arr];
+  const int64_t col = (int64_t)h.slot0[arr] + tau, nslot = h.nslot[arr], es = h.es[arr];
 #pragma unroll
   for (int i = 0; i < 8; ++i) v[i] = tile[sx][sy + 8 * i];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
     const int j = n0 + sy + 8 * i;
-    if (j < n) dst[((int64_t)j * nslot + col) * B + b] = v[i];
+    if (j < n) dst[(((int64_t)j * nslot + col) * B + b) * es] = v[i];
   }
 }
 __global__ void __launch_bounds__(256) k_handoff_transpose(HandoffArrays h, int B) {

@@ -121,6 +121,7 @@ struct HandoffArrays {
   const uint32_t* src[HANDOFF_ARRAYS];
   uint32_t* dst[HANDOFF_ARRAYS];
   int n[HANDOFF_ARRAYS], steps[HANDOFF_ARRAYS], slot0[HANDOFF_ARRAYS], nslot[HANDOFF_ARRAYS];
+  int es[HANDOFF_ARRAYS];  // words between consecutive elements of dst: 1, or 2 in a pair array
 };
 void launch_handoff_transpose(hipStream_t s, const HandoffArrays& h, int B);
 void handoff_grid(const HandoffArrays& h, int B, int g[3]);
@@ -136,6 +137,7 @@ struct EpropArgs {
   // ([n][B]; bit t of a word = step t of the block)
   const float* x0; const float* z0;
   const uint32_t* xbits; const uint32_t* zbits;
+  int tr_es;                // 2: x0/xbits (z0/zbits) are one [n][B][2] array of (trace, word) pairs; else 1
   int tofs;                 // steps of the block before this launch's first step
   // ring [n][nslot][B]; this launch applies steps slot0 .. slot0+nsteps-1
   const float* psiT; const float* LT; const float* deltaT;
@@ -145,6 +147,9 @@ struct EpropArgs {
   float* gx; int n_col;                  // ColumnView's per-chunk gradients (B > 128)
 };
 void launch_eprop(hipStream_t s, const EpropArgs& a);
+// Whether a network of batch B runs the transfer-coefficient e-prop kernel,
+// which reads the block-start traces and spike words as (trace, word) pairs.
+bool eprop_tc_path(int B);
 // Whether a network of batch B keeps ebar and eps interleaved (ALIF under the
 // transfer-coefficient kernel, which reads a synapse's state as one record).
 bool eprop_interleaved(int B, bool alif);
