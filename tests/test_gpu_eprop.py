@@ -594,3 +594,55 @@ def test_lockstep_with_the_papers_alpha(name):
         compare_state(snap, N, cfg, trace_rtol=1.5e-5)
     assert resync <= 2
     print("worst error / bound:", {k: round(v, 3) for k, v in sorted(MARGINS.items())}, flush=True)
+
+
+def _train_net(cfg, steps):
+    rates = wl.poisson_rates(cfg.seed, cfg.n_in, 60.0)
+    raster = wl.poisson_raster(cfg.seed, rates, cfg.sample_steps, cfg.batch)
+    labels = (np.arange(cfg.batch) % cfg.n_out).astype(np.int32)
+    net = rb.EpropNet(cfg)
+    net.set_input(*gpu_input(raster, labels))
+    net.step(steps, rb.RS_LEARN)
+    return net
+
+
+def test_gradient_set_replaces_every_chunk():
+    """With more than 128 instances each instance chunk accumulates its part
+    of the gradient on its own until a fold adds the parts to G.  Writing G
+    replaces the whole gradient: a network whose G is written with another
+    network's (folded) G ends bit-identical to that network after 15 more
+    learning steps, and G reads back exactly as written."""
+    cfg = make_cfg(40, 64, 4, 256, True, p=0.3, seed=31, U=0, T=200)
+    a = _train_net(cfg, 15)
+    b = _train_net(cfg, 15)
+    for p in (0, 1):
+        g = a.get(rb.PROJ(p, rb.P_G))
+        assert np.abs(g).sum() > 0
+        b.set(rb.PROJ(p, rb.P_G), g)
+        assert np.array_equal(b.get(rb.PROJ(p, rb.P_G)), g)
+    a.step(15, rb.RS_LEARN)
+    b.step(15, rb.RS_LEARN)
+    for p in (0, 1):
+        assert np.array_equal(a.get(rb.PROJ(p, rb.P_G)), b.get(rb.PROJ(p, rb.P_G))), p
+    a.close()
+    b.close()
+
+
+def test_interleaved_eligibility_set_get():
+    """ALIF networks under the transfer-coefficient kernel keep ebar and eps
+    of an instance side by side in one array; each still reads and writes as
+    its own [n_pre][cap][batch] variable without touching the other."""
+    cfg = make_cfg(40, 64, 4, 64, True, p=0.3, seed=32, U=0, T=200)
+    net = _train_net(cfg, 12)
+    rng = np.random.default_rng(5)
+    for p in (0, 1):
+        eb, ep = net.get(rb.PROJ(p, rb.P_EBAR)), net.get(rb.PROJ(p, rb.P_EPS))
+        assert np.abs(eb).sum() > 0 and np.abs(ep).sum() > 0
+        r = rng.standard_normal(ep.shape).astype(np.float32)
+        net.set(rb.PROJ(p, rb.P_EPS), r)
+        assert np.array_equal(net.get(rb.PROJ(p, rb.P_EPS)), r)
+        assert np.array_equal(net.get(rb.PROJ(p, rb.P_EBAR)), eb)
+        net.set(rb.PROJ(p, rb.P_EBAR), r[::-1].copy())
+        assert np.array_equal(net.get(rb.PROJ(p, rb.P_EBAR)), r[::-1])
+        assert np.array_equal(net.get(rb.PROJ(p, rb.P_EPS)), r)
+    net.close()
