@@ -744,7 +744,7 @@ struct VarRef {
   void* ptr;
   size_t bytes;
   size_t rows = 0, pitch = 0;  // strided ring slot: rows of bytes/rows, pitch apart
-  int il = -1;                 // >= 0: float il of every pair of an interleaved array of 2 bytes/4 floats
+  int il = -1;                 // >= 0: word il of every pair of an interleaved array of 2 bytes/4 32-bit words
 };
 
 bool var_ref(rs_eprop* n, int32_t var, VarRef* r, bool for_write) {
@@ -943,12 +943,12 @@ rs_status rs_eprop_get(rs_eprop* n, int32_t var, void* host, size_t bytes) {
   if (!var_ref(n, var, &r, false)) return fail(RS_EINVAL, "unknown or absent variable 0x%x", var);
   if (bytes != r.bytes) return fail(RS_ECAPACITY, "variable 0x%x has %zu bytes, buffer %zu", var, r.bytes, bytes);
   if (var % 0x100 == RS_P_G && var >= 0x100) fold_gradients(n, n->stream);
-  if (r.il >= 0) {  // one float of each pair of the interleaved eligibility state
+  if (r.il >= 0) {  // one word of each pair: interleaved eligibility state, or the last block's spike words
     const size_t cnt = bytes / 4;
-    std::vector<float> both(2 * cnt);
+    std::vector<uint32_t> both(2 * cnt);
     HIP_OK(hipMemcpyAsync(both.data(), r.ptr, 2 * bytes, hipMemcpyDeviceToHost, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
-    float* out = (float*)host;
+    uint32_t* out = (uint32_t*)host;
     for (size_t k = 0; k < cnt; ++k) out[k] = both[2 * k + r.il];
     return RS_OK;
   }
@@ -995,12 +995,12 @@ rs_status rs_eprop_set(rs_eprop* n, int32_t var, const void* host, size_t bytes)
   // the chunks' parts go into G first: a new G replaces them too, and new
   // rows must not inherit them at slots the update no longer visits
   fold_gradients(n, n->stream);
-  if (r.il >= 0) {  // replace one float of each pair of the interleaved eligibility state
+  if (r.il >= 0) {  // replace one word of each pair of the interleaved eligibility state
     const size_t cnt = bytes / 4;
-    std::vector<float> both(2 * cnt);
+    std::vector<uint32_t> both(2 * cnt);
     HIP_OK(hipMemcpyAsync(both.data(), r.ptr, 2 * bytes, hipMemcpyDeviceToHost, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
-    const float* in = (const float*)host;
+    const uint32_t* in = (const uint32_t*)host;
     for (size_t k = 0; k < cnt; ++k) both[2 * k + r.il] = in[k];
     HIP_OK(hipMemcpyAsync(r.ptr, both.data(), 2 * bytes, hipMemcpyHostToDevice, n->stream));
     HIP_OK(hipStreamSynchronize(n->stream));
